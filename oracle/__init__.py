@@ -1,0 +1,23 @@
+"""CPU oracle for the thermoelastic PCG + smoothed-aggregation AMG path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import or call anything in this
+package; the product path (the HIP library and its Python binding) never
+does, and shares no code with it.
+
+Everything here is plain, slow and written to be checked by eye against the
+paper and the textbook methods it names, in float64:
+
+* ``fem``     -- Lagrange P1/P2 tetrahedral assembly of the thermoelastic
+                 weak form (Sec. 3, eq. wf_elastic with p_bc = 0), Dirichlet
+                 elimination, rigid-body near-nullspace.
+* ``amg``     -- smoothed-aggregation AMG (Sec. 2.1.3, Sec. 5.1): strength,
+                 greedy aggregation, tentative prolongator by QR, Lanczos
+                 eigenvalue estimate, prolongator smoothing, Galerkin
+                 product, Chebyshev smoother, V-cycle, coarse Cholesky.
+* ``krylov``  -- preconditioned and flexible conjugate gradients
+                 (Sec. 2.1.2), single and multiple right-hand sides.
+* ``mpnn``    -- message-passing network forward/backward for the learned
+                 initial guess.
+* ``rng``     -- splitmix64 counter generator (Steele, Lea & Flood 2014).
+"""

@@ -1,0 +1,318 @@
+"""Oracle: Lagrange P1/P2 tetrahedral assembly of the linear thermoelastic
+problem (test infrastructure only; see the package docstring).
+
+Problem (Sec. 3, eqs. elasticity_bvp and u-dbc, weak form wf_elastic with no
+boundary pressure): find u_h in [V_h]^3, u_h = u_bc on Gamma_D, with
+
+    a(u, v) = int lam div u div v + 2 mu eps(u):eps(v) dx
+            = int C:eps_T : grad v dx + int f.v dx,
+    eps_T   = alpha (T - T_ref) I,  so  C:eps_T = (3 lam + 2 mu) alpha (T - T_ref) I.
+
+Writing u = phi_b e_j and v = phi_a e_i gives the 3x3 coupling block of nodes
+a, b (component i of the test function, j of the trial function)
+
+    K[(a,i),(b,j)] = int lam d_i phi_a d_j phi_b + mu d_j phi_a d_i phi_b
+                         + mu delta_ij grad phi_a . grad phi_b,
+    b[(a,i)]       = (3 lam + 2 mu) alpha int (T_h - T_ref) d_i phi_a + int f_i phi_a.
+
+The isotropic stiffness tensor is read from (E, nu) through the Lame constants
+(the paper only names an elastic stiffness tensor).  T_h is the nodal
+interpolant of T in the same Lagrange space as u.  Every integral is exact:
+the integrands are polynomials in the barycentric coordinates, integrated with
+  int_K l0^a l1^b l2^c l3^d dx = a! b! c! d! 3! |K| / (a+b+c+d+3)!.
+"""
+from __future__ import annotations
+
+import functools
+from fractions import Fraction
+from math import factorial
+
+import numpy as np
+import scipy.sparse as sp
+
+# ---------------------------------------------------------------------------
+# Barycentric polynomial algebra (exact, rational)
+# ---------------------------------------------------------------------------
+
+EDGES = [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+
+
+def _poly_mul(p, q):
+    out = {}
+    for ep, cp in p.items():
+        for eq, cq in q.items():
+            e = tuple(a + b for a, b in zip(ep, eq))
+            out[e] = out.get(e, Fraction(0)) + cp * cq
+    return out
+
+
+def _poly_add(p, q, s=Fraction(1)):
+    out = dict(p)
+    for e, c in q.items():
+        out[e] = out.get(e, Fraction(0)) + s * c
+    return out
+
+
+def _lam(k, c=1):
+    e = [0, 0, 0, 0]
+    e[k] = 1
+    return {tuple(e): Fraction(c)}
+
+
+def _const(c):
+    return {(0, 0, 0, 0): Fraction(c)}
+
+
+def _integral_over_volume(p):
+    """(1/|K|) int_K p dx for p in barycentric monomials."""
+    tot = Fraction(0)
+    for (a, b, c, d), coef in p.items():
+        num = factorial(a) * factorial(b) * factorial(c) * factorial(d) * factorial(3)
+        tot += coef * Fraction(num, factorial(a + b + c + d + 3))
+    return tot
+
+
+def basis(degree):
+    """Lagrange basis on the tetrahedron in barycentric coordinates.
+    P1: phi_a = l_a.  P2: vertices l_a (2 l_a - 1), edges 4 l_a l_b in the
+    order (01, 02, 03, 12, 13, 23)."""
+    if degree == 1:
+        return [_lam(a) for a in range(4)]
+    phis = [_poly_add(_poly_mul(_lam(a, 2), _lam(a)), _lam(a), Fraction(-1)) for a in range(4)]
+    phis += [_poly_mul(_lam(a, 4), _lam(b)) for a, b in EDGES]
+    return phis
+
+
+def _d_dlam(p, k):
+    out = {}
+    for e, c in p.items():
+        if e[k] > 0:
+            e2 = list(e)
+            e2[k] -= 1
+            out[tuple(e2)] = out.get(tuple(e2), Fraction(0)) + c * e[k]
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def reference_tables(degree):
+    """Exact tables (as float64), all divided by |K|:
+    S[a,b,k,l] = int (dphi_a/dl_k)(dphi_b/dl_l);  W[c,a,k] = int phi_c dphi_a/dl_k;
+    M[a,c] = int phi_a phi_c."""
+    phis = basis(degree)
+    n = len(phis)
+    dphi = [[_d_dlam(p, k) for k in range(4)] for p in phis]
+    S = np.zeros((n, n, 4, 4))
+    W = np.zeros((n, n, 4))
+    M = np.zeros((n, n))
+    for a in range(n):
+        for b in range(n):
+            M[a, b] = float(_integral_over_volume(_poly_mul(phis[a], phis[b])))
+            for k in range(4):
+                W[a, b, k] = float(_integral_over_volume(_poly_mul(phis[a], dphi[b][k])))
+                for l in range(4):
+                    S[a, b, k, l] = float(_integral_over_volume(_poly_mul(dphi[a][k], dphi[b][l])))
+    return S, W, M
+
+
+def lame(E, nu):
+    """Lame constants of an isotropic material."""
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    return lam, mu
+
+
+# ---------------------------------------------------------------------------
+# Element geometry and element tensors
+# ---------------------------------------------------------------------------
+
+def cell_geometry(coords, cells):
+    """vol[C] = |det J|/6 and G[C,k,i] = d_i l_k for the affine map of each cell
+    (vertices are the first four cell nodes)."""
+    x = coords[cells[:, :4]]  # [C,4,3]
+    J = np.stack([x[:, 1] - x[:, 0], x[:, 2] - x[:, 0], x[:, 3] - x[:, 0]], axis=2)  # columns
+    det = np.linalg.det(J)
+    Jinv = np.linalg.inv(J)  # rows k = grad l_{k+1}
+    G = np.empty((cells.shape[0], 4, 3))
+    G[:, 1:, :] = Jinv
+    G[:, 0, :] = -Jinv.sum(axis=1)
+    return np.abs(det) / 6.0, G
+
+
+def element_stiffness(vol, G, lam, mu, degree):
+    """K_e[C, a, i, b, j] for the bilinear form above (exact integration)."""
+    S, _, _ = reference_tables(degree)
+    GG = np.einsum("cki,clj->cklij", G, G)           # G[k,i] G[l,j]
+    dots = np.einsum("ckm,clm->ckl", G, G)           # grad l_k . grad l_l
+    eye = np.eye(3)
+    kern = lam * GG + mu * GG.transpose(0, 1, 2, 4, 3) + mu * dots[:, :, :, None, None] * eye
+    # kern[c,k,l,i,j] = lam G_ki G_lj + mu G_kj G_li + mu delta_ij G_k.G_l
+    Ke = np.einsum("abkl,cklij->caibj", S, kern)
+    return vol[:, None, None, None, None] * Ke
+
+
+def element_load(vol, G, dT_cell, f_cell, lam, mu, alpha, degree):
+    """b_e[C, a, i]: thermal load plus consistent body-force load."""
+    _, W, M = reference_tables(degree)
+    c_alpha = (3.0 * lam + 2.0 * mu) * alpha
+    # sum_c dT_c int phi_c d_i phi_a = sum_c dT_c sum_k W[c,a,k] G[k,i]
+    be = c_alpha * np.einsum("cn,nak,cki->cai", dT_cell, W, G) * vol[:, None, None]
+    if f_cell is not None:
+        be = be + vol[:, None, None] * np.einsum("an,cni->cai", M, f_cell)
+    return be
+
+
+# ---------------------------------------------------------------------------
+# Global assembly into 3x3-block compressed rows
+# ---------------------------------------------------------------------------
+
+def sparsity(cells, n_nodes):
+    """Block pattern: I ~ J when both belong to one cell (closed star).
+    Returns (row_ptr[N+1], col_idx[nnzb]) with sorted columns."""
+    c = cells.astype(np.int64)
+    npe = c.shape[1]
+    I = np.repeat(c, npe, axis=1).ravel()
+    J = np.tile(c, (1, npe)).ravel()
+    keys = np.unique(I * n_nodes + J)
+    rows = keys // n_nodes
+    cols = keys % n_nodes
+    row_ptr = np.zeros(n_nodes + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n_nodes), out=row_ptr[1:])
+    return row_ptr, cols
+
+
+def assemble(coords, cells, degree, E, nu, alpha, T_ref, T, f=None, chunk=200_000):
+    """Unconstrained global stiffness (scipy BSR, 3x3 blocks) and load b[N,3]."""
+    n = coords.shape[0]
+    lam, mu = lame(E, nu)
+    row_ptr, cols = sparsity(cells, n)
+    keys = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr)) * n + cols
+    val = np.zeros((cols.size, 3, 3))
+    b = np.zeros((n, 3))
+    npe = cells.shape[1]
+    for s in range(0, cells.shape[0], chunk):
+        cc = cells[s:s + chunk].astype(np.int64)
+        vol, G = cell_geometry(coords, cc)
+        Ke = element_stiffness(vol, G, lam, mu, degree)  # [c,a,i,b,j]
+        dT = T[cc] - T_ref
+        fc = None if f is None else f[cc]
+        be = element_load(vol, G, dT, fc, lam, mu, alpha, degree)
+        I = np.repeat(cc, npe, axis=1)   # [c, a*npe+b] -> node a
+        J = np.tile(cc, (1, npe))
+        pos = np.searchsorted(keys, (I * n + J).ravel())
+        blocks = Ke.transpose(0, 1, 3, 2, 4).reshape(-1, 3, 3)  # [c*a*b, i, j]
+        np.add.at(val, pos, blocks)
+        np.add.at(b, cc.ravel(), be.reshape(-1, 3))
+    A = sp.bsr_matrix((val, cols, row_ptr), shape=(3 * n, 3 * n))
+    return A, b
+
+
+def assemble_rows(coords, cells, degree, E, nu, alpha, T_ref, T, rows, f=None):
+    """Block rows `rows` of the unconstrained system, computed from the cells
+    that touch them only (exact for those rows).  Returns a dict
+    row -> (cols[int], blocks[k,3,3], b_row[3])."""
+    rows = np.asarray(rows, dtype=np.int64)
+    touch = np.isin(cells, rows).any(axis=1)
+    sub = cells[touch].astype(np.int64)
+    lam, mu = lame(E, nu)
+    vol, G = cell_geometry(coords, sub)
+    Ke = element_stiffness(vol, G, lam, mu, degree)
+    be = element_load(vol, G, T[sub] - T_ref, None if f is None else f[sub], lam, mu, alpha, degree)
+    out = {}
+    npe = sub.shape[1]
+    for r in rows.tolist():
+        acc = {}
+        brow = np.zeros(3)
+        cs, as_ = np.nonzero(sub == r)
+        for c, a in zip(cs.tolist(), as_.tolist()):
+            brow += be[c, a]
+            for bb in range(npe):
+                J = int(sub[c, bb])
+                acc[J] = acc.get(J, 0.0) + Ke[c, a, :, bb, :]
+        cols = np.array(sorted(acc))
+        out[r] = (cols, np.array([acc[j] for j in cols]), brow)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Dirichlet conditions and near-nullspace
+# ---------------------------------------------------------------------------
+
+def apply_dirichlet(A, b, mask, u_bc=None):
+    """Symmetric elimination that keeps every DOF in the system: the lifting
+    b -= A[:, D] u_D, then rows and columns of constrained DOFs are zeroed,
+    their diagonal set to 1 and b_D = u_D.  Returns new (A, b[3N])."""
+    m = mask.reshape(-1).astype(bool)
+    bf = b.reshape(-1).astype(np.float64).copy()
+    uD = np.zeros_like(bf) if u_bc is None else np.where(m, u_bc.reshape(-1), 0.0)
+    bf = bf - A @ uD
+    bf[m] = uD[m]
+    A = A.copy()
+    nb = A.shape[0] // 3
+    rows = np.repeat(np.arange(nb), np.diff(A.indptr))
+    keep_r = (~m).reshape(nb, 3)[rows][:, :, None]
+    keep_c = (~m).reshape(nb, 3)[A.indices][:, None, :]
+    A.data = A.data * keep_r * keep_c
+    diag = np.nonzero(rows == A.indices)[0]
+    md = m.reshape(nb, 3)[rows[diag]]
+    for i in range(3):
+        A.data[diag, i, i] = np.where(md[:, i], 1.0, A.data[diag, i, i])
+    return A, bf
+
+
+def rigid_body_modes(coords, mask=None):
+    """B[3N, 6]: translations e_x, e_y, e_z and rotations about the node
+    centroid, (-(y-yc), x-xc, 0), (0, -(z-zc), y-yc), (z-zc, 0, -(x-xc));
+    rows of constrained DOFs set to zero."""
+    n = coords.shape[0]
+    c = coords - coords.mean(axis=0)
+    B = np.zeros((n, 3, 6))
+    B[:, 0, 0] = 1.0
+    B[:, 1, 1] = 1.0
+    B[:, 2, 2] = 1.0
+    B[:, 0, 3] = -c[:, 1]
+    B[:, 1, 3] = c[:, 0]
+    B[:, 1, 4] = -c[:, 2]
+    B[:, 2, 4] = c[:, 1]
+    B[:, 0, 5] = c[:, 2]
+    B[:, 2, 5] = -c[:, 0]
+    B = B.reshape(3 * n, 6)
+    if mask is not None:
+        B[mask.reshape(-1).astype(bool)] = 0.0
+    return B
+
+
+def assemble_problem(prob, u_bc=None):
+    """Convenience: assemble + Dirichlet for a meshgen.Problem.
+    Returns (A_dirichlet, b_dirichlet[3N], A_free, b_free[N,3])."""
+    m = prob.mesh
+    A0, b0 = assemble(m.coords, m.cells, m.degree, prob.E, prob.nu, prob.alpha, prob.T_ref, prob.T, prob.f)
+    A, b = apply_dirichlet(A0, b0, prob.mask, u_bc)
+    return A, b, A0, b0
+
+
+def cell_strain_stress(coords, cells, degree, u, E, nu, alpha, T_ref, T, points):
+    """Strain and stress at barycentric `points` [P,4] of every cell, for the
+    closed-form checks: eps = sym grad u_h, sigma = C:(eps - alpha dT_h I)."""
+    lam, mu = lame(E, nu)
+    vol, G = cell_geometry(coords, cells.astype(np.int64))
+    phis = basis(degree)
+    dphi = [[_d_dlam(p, k) for k in range(4)] for p in phis]
+
+    def ev(p, l):
+        return sum(float(c) * np.prod([l[i] ** e[i] for i in range(4)]) for e, c in p.items())
+
+    ue = u.reshape(-1, 3)[cells]  # [C, n, 3]
+    Te = T[cells] - T_ref
+    out_eps, out_sig = [], []
+    for l in points:
+        dv = np.array([[ev(dphi[a][k], l) for k in range(4)] for a in range(len(phis))])  # [n,4]
+        ph = np.array([ev(p, l) for p in phis])
+        grad_phi = np.einsum("ak,cki->cai", dv, G)  # [C,n,3]
+        gu = np.einsum("cai,caj->cij", ue, grad_phi)  # d_j u_i
+        eps = 0.5 * (gu + gu.transpose(0, 2, 1))
+        dT = Te @ ph
+        tr = np.trace(eps, axis1=1, axis2=2) - 3 * alpha * dT
+        sig = 2 * mu * (eps - alpha * dT[:, None, None] * np.eye(3)) + lam * tr[:, None, None] * np.eye(3)
+        out_eps.append(eps)
+        out_sig.append(sig)
+    return np.array(out_eps), np.array(out_sig)

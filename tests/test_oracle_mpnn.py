@@ -1,0 +1,99 @@
+"""Pins of the oracle's message-passing network: backward against central
+finite differences, the neighbour-mean adjoint identity, masking and a
+hand-computed forward on a 3-vertex graph."""
+import numpy as np
+
+import meshgen as mg
+from oracle import mpnn
+
+
+def _small():
+    m = mg.disc_mesh(3, 12, 2, 1)
+    rng = np.random.default_rng(1)
+    T = 300 + rng.uniform(0, 100, m.n_nodes)
+    mask = mg.disc_clamp_bore(m)
+    X = mpnn.features(m.coords, T, 300.0, None, mask)
+    ptr, nbr = mpnn.vertex_graph(m.cells, m.n_nodes)
+    ut = rng.normal(size=(m.n_nodes, 3)) * (1 - mask)
+    return m, X, ptr, nbr, mask, ut
+
+
+def test_vertex_graph_is_p1_pattern_without_diagonal():
+    m = mg.disc_mesh(80, 344, 11, 1)
+    ptr, nbr = mpnn.vertex_graph(m.cells, m.n_nodes)
+    assert nbr.size == 4_426_592  # = 4,760,960 blocks - 334,368 diagonal
+    rows = np.repeat(np.arange(m.n_nodes), np.diff(ptr))
+    assert not np.any(rows == nbr)
+
+
+def test_gradients_match_finite_differences():
+    m, X, ptr, nbr, mask, ut = _small()
+    p = mpnn.init_params(3)
+    # non-zero biases so every ReLU branch is exercised
+    rng = np.random.default_rng(9)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.normal(size=p[k].shape) * 0.1
+    assert mpnn.grad_check(p, X, ptr, nbr, mask, ut, n_probe=4) < 1e-6
+
+
+def test_neighbour_mean_adjoint():
+    m, X, ptr, nbr, mask, ut = _small()
+    rng = np.random.default_rng(2)
+    a = rng.normal(size=(m.n_nodes, 5))
+    b = rng.normal(size=(m.n_nodes, 5))
+    lhs = (mpnn._mean_nbr(ptr, nbr, a) * b).sum()
+    rhs = (a * mpnn._mean_nbr_T(ptr, nbr, b)).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_masked_outputs_are_zero_and_param_count():
+    m, X, ptr, nbr, mask, ut = _small()
+    p = mpnn.init_params(0)
+    y, _ = mpnn.forward(p, X, ptr, nbr, mask)
+    assert np.all(y[mask.astype(bool)] == 0)
+    n = sum(p[k].size for k in mpnn.PARAM_ORDER)
+    assert n == 10 * 64 + 64 + 4 * (3 * 64 * 64 + 64) + 64 * 3 + 3
+
+
+def test_forward_by_hand_three_vertices():
+    # path graph 0 - 1 - 2, F_IN inputs, tiny weights: recompute with loops
+    ptr = np.array([0, 1, 3, 4])
+    nbr = np.array([1, 0, 2, 1])
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(3, mpnn.F_IN))
+    p = mpnn.init_params(1)
+    mask = np.zeros((3, 3))
+    y, _ = mpnn.forward(p, X, ptr, nbr, mask)
+    h = np.maximum(X @ p["W_in"] + p["b_in"], 0)
+    for l in range(mpnn.L):
+        m = np.stack([h[1], 0.5 * (h[0] + h[2]), h[1]])
+        g = (h[0] + h[1] + h[2]) / 3
+        h = h + np.maximum(h @ p[f"W_s{l}"] + m @ p[f"W_n{l}"] + g @ p[f"W_g{l}"] + p[f"b{l}"], 0)
+    ref = h @ p["W_out"] + p["b_out"]
+    assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_adam_first_step_closed_form():
+    # bias-corrected first Adam step moves every weight by lr * sign(g)
+    p = {k: np.ones(2) for k in mpnn.PARAM_ORDER}
+    g = {k: np.array([3.0, -0.5]) for k in mpnn.PARAM_ORDER}
+    mpnn.adam_step(p, g, {}, lr=0.01)
+    for k in mpnn.PARAM_ORDER:
+        assert np.allclose(p[k], [0.99, 1.01], rtol=0, atol=1e-9)
+
+
+def test_grad_check_detects_a_planted_adjoint_mistake(monkeypatch):
+    # the classic mistake: transpose of the neighbour mean weighted by 1/deg_u
+    m, X, ptr, nbr, mask, ut = _small()
+    p = mpnn.init_params(3)
+
+    def wrong(ptr_, nbr_, gm):
+        deg = np.diff(ptr_)
+        rows = np.repeat(np.arange(gm.shape[0]), deg)
+        out = np.zeros_like(gm)
+        np.add.at(out, nbr_, gm[rows])
+        return out / np.maximum(deg, 1)[:, None]
+
+    monkeypatch.setattr(mpnn, "_mean_nbr_T", wrong)
+    assert mpnn.grad_check(p, X, ptr, nbr, mask, ut, n_probe=4) > 1e-3
