@@ -1,0 +1,248 @@
+/*
+ * te.h -- C ABI of the MI355X (gfx950) thermoelastic PCG + smoothed-aggregation
+ * AMG library.
+ *
+ * The library solves the linear thermoelastic problem of the paper's Sec. 3
+ * (eqs. elasticity_bvp, u-dbc and the weak form wf_elastic, without boundary
+ * pressure):  -div(C:(eps(u) - alpha (T - T_ref) I)) = f  on a tetrahedral
+ * mesh with Lagrange P1 or P2 elements (Sec. 3.1), by conjugate gradients
+ * preconditioned with smoothed-aggregation AMG using the rigid-body modes as
+ * near-nullspace and a Chebyshev smoother (Sec. 2.1.2, 2.1.3 and 5.1).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller unless the
+ *     comment says "host".  Arrays are dense, contiguous, row-major.
+ *   - Vector unknowns are node-major: DOF 3*i + c is component c of node i.
+ *   - All device work is enqueued on the caller's stream; calls return once
+ *     the work is enqueued unless stated otherwise (setup and solve
+ *     synchronise the stream because they need host-side decisions).
+ *   - Return codes: 0 OK, >0 completed with a warning, <0 error (see below).
+ *     te_last_error() gives a thread-local message for the last failure.
+ *   - Handles are not safe for concurrent use from several threads.
+ */
+#ifndef TE_H
+#define TE_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define TE_OK          0
+#define TE_ENOTCONV    1   /* maxit reached; result and report are valid     */
+#define TE_EINVAL    (-1)  /* bad argument (null pointer, size, option)      */
+#define TE_ENOMEM    (-2)  /* device or host allocation failed               */
+#define TE_EHIP      (-3)  /* a HIP runtime call failed                      */
+#define TE_EINDEF    (-4)  /* CG breakdown: (p,Ap) <= 0 or (r,z) <= 0         */
+#define TE_ENAN      (-5)  /* NaN or Inf in a residual                       */
+#define TE_ERANK     (-6)  /* aggregate near-nullspace block of rank < 6     */
+#define TE_ECHOL     (-7)  /* coarse Cholesky pivot <= 0                     */
+
+#define TE_PREC_FP64   0   /* everything in float64 (the reference method)   */
+#define TE_PREC_MIXED  1   /* float32 V-cycle inside float64 flexible CG     */
+
+/* Library version (major*10000 + minor*100 + patch). */
+int te_version(void);
+/* Thread-local text of the last error ("" if none). Host string, static. */
+const char *te_last_error(void);
+
+/* ---- inputs (Sec. 3.1: conforming Lagrange spaces on tetrahedra) ------- */
+typedef struct {
+    int64_t n_nodes;        /* N: vertices (P1) or vertices + edge nodes (P2) */
+    int64_t n_cells;        /* C                                               */
+    int32_t degree;         /* 1 or 2                                          */
+    const double *coords;   /* device [N][3]                                   */
+    const int32_t *cells;   /* device [C][4] (P1) or [C][10]: v0..v3 then the
+                               edge nodes e01,e02,e03,e12,e13,e23 (P2); every
+                               cell positively oriented, P2 edge nodes at the
+                               straight-edge midpoints (affine cells)          */
+} te_mesh;
+
+typedef struct {            /* isotropic material: C from (E, nu)             */
+    double E, nu;           /* Young's modulus, Poisson ratio                 */
+    double alpha;           /* thermal expansion coefficient alpha_L          */
+    double T_ref;           /* reference temperature of the thermal strain    */
+} te_material;
+
+/* 3x3-block compressed sparse rows (node-node coupling blocks). */
+typedef struct {
+    int64_t n_brows;        /* N                                              */
+    int64_t nnzb;           /* number of stored 3x3 blocks                    */
+    int64_t *row_ptr;       /* device [N+1]                                   */
+    int32_t *col_idx;       /* device [nnzb], ascending within a row          */
+    double *val;            /* device [nnzb][3][3], block row-major:
+                               val[k][i][j] couples component i of the row
+                               node with component j of the column node       */
+} te_bsr;
+
+/* ---- assembly (Sec. 2.3.3, weak form wf_elastic) ----------------------- */
+
+/* Block sparsity of the stiffness matrix: node I couples with node J when
+ * both belong to one cell (diagonal blocks included).
+ *   row_ptr: device [N+1], written (row_ptr[0] = 0).
+ *   nnzb_out: host, receives row_ptr[N].
+ * Synchronises `stream`.  Errors: TE_EINVAL (bad mesh, node index out of
+ * range, a node coupling to more than 192 nodes), TE_ENOMEM, TE_EHIP. */
+int fe_assemble_pattern(const te_mesh *mesh, int64_t *row_ptr, int64_t *nnzb_out, hipStream_t stream);
+
+/* Stiffness matrix and load vector of the thermoelastic weak form,
+ *   K[(a,i),(b,j)] = int lam d_i phi_a d_j phi_b + mu d_j phi_a d_i phi_b
+ *                        + mu delta_ij grad phi_a . grad phi_b
+ *   b[(a,i)]       = (3 lam + 2 mu) alpha int (T_h - T_ref) d_i phi_a + int f_i phi_a
+ * (T_h the nodal interpolant of T in the same space; exact integration),
+ * followed by Dirichlet elimination that keeps every DOF: b -= A[:,D] u_D,
+ * rows and columns of constrained DOFs zeroed, unit diagonal, b_D = u_D.
+ *   T: device [N]; f: device [N][3] or NULL (no body force);
+ *   dir_mask: device [N][3] uint8 (nonzero = constrained) or NULL;
+ *   u_bc: device [N][3] prescribed values or NULL (= 0);
+ *   A: row_ptr from fe_assemble_pattern, col_idx/val caller-allocated with
+ *      A->nnzb entries; both are overwritten.  b: device [3N], overwritten.
+ * Deterministic (gather-based, no atomics in the sums).  Errors: TE_EINVAL,
+ * TE_ENOMEM, TE_EHIP. */
+int fe_assemble_thermoelastic(const te_mesh *mesh, const te_material *mat, const double *T,
+                              const double *f, const uint8_t *dir_mask, const double *u_bc,
+                              te_bsr *A, double *b, hipStream_t stream);
+
+/* Load vector only (same b as above with u_bc = 0), for many load cases on
+ * one assembled matrix.  nrhs load cases: T device [nrhs][N], f device
+ * [nrhs][N][3] or NULL; b device [N][3][nrhs] (right-hand sides fastest). */
+int fe_assemble_load(const te_mesh *mesh, const te_material *mat, const double *T,
+                     const double *f, const uint8_t *dir_mask, int32_t nrhs,
+                     double *b, hipStream_t stream);
+
+/* ---- smoothed-aggregation AMG (Sec. 2.1.3, 5.1) ------------------------- */
+typedef struct amg_handle amg_handle;
+
+typedef struct {
+    double theta0;           /* strength threshold at level 0, halved per level (0.08) */
+    int32_t coarse_max;      /* stop coarsening at <= this many DOF (3000)            */
+    int32_t max_levels;      /* (10)                                                    */
+    int32_t lanczos_steps;   /* steps of the largest-eigenvalue estimate (20)         */
+    int32_t cheb_degree;     /* Chebyshev polynomial degree (2)                        */
+    double cheb_ratio;       /* interval [b/ratio, b] (10)                              */
+    double cheb_safety;      /* b = safety * lambda_hat (1.1)                           */
+    double max_coarse_ratio; /* stop if a coarse level keeps more than this share (0.8) */
+    int32_t build_fp32;      /* also keep float32 copies for TE_PREC_MIXED (1)         */
+    int32_t host_threads;    /* host threads for the setup (0 = all)                    */
+    int32_t max_nrhs;        /* largest nrhs a solve will use (1..64; 1)               */
+} amg_options;
+
+/* Fills the defaults listed above. */
+void amg_options_default(amg_options *opt);
+
+/* Builds the hierarchy for the Dirichlet-eliminated matrix A (3x3 blocks).
+ *   coords: device [N][3] (rigid-body modes about the node centroid);
+ *   dir_mask: device [N][3] or NULL: near-nullspace rows of constrained DOFs
+ *             are zeroed;
+ *   out: receives a library-owned handle (release with amg_destroy).
+ * The matrix values are copied; A may be freed afterwards.  Synchronises
+ * `stream`.  Errors: TE_EINVAL, TE_ENOMEM, TE_EHIP, TE_ERANK, TE_ECHOL. */
+int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask,
+              const amg_options *opt, amg_handle **out, hipStream_t stream);
+
+/* Test hook: as amg_setup, but the aggregate map of levels 0..n_levels_given-1
+ * is imposed instead of computed (host arrays agg[l][n_l], -1 = isolated,
+ * aggregate ids 0..n_agg-1 in creation order).  Used to drive the hierarchy
+ * from an external aggregation for component-level comparisons. */
+int amg_setup_with_aggregates(const te_bsr *A, const double *coords, const uint8_t *dir_mask,
+                              const amg_options *opt, const int32_t *const *agg,
+                              int32_t n_levels_given, amg_handle **out, hipStream_t stream);
+
+typedef struct {
+    int32_t n_levels;
+    int64_t n_dof[16];       /* DOF per level                                   */
+    int64_t nnzb[16];        /* stored blocks of A_l                            */
+    int32_t bs[16];          /* block size of A_l                               */
+    double lambda_hat[16];   /* largest-eigenvalue estimate of D^-1 A_l          */
+    int64_t p_nnzb[16];      /* stored blocks of P_l                            */
+    double setup_ms;         /* host wall time of the setup                      */
+    int64_t bytes_device;    /* device memory held by the handle                 */
+} amg_info;
+
+int amg_get_info(const amg_handle *h, amg_info *info);
+
+/* Host copy of the aggregate map of level l (n_l entries, natural order). */
+int amg_get_aggregates(const amg_handle *h, int32_t level, int32_t *agg_host);
+
+/* Host copy of A_l in natural (un-permuted) numbering:
+ * row_ptr [n_l+1], col [nnzb], val [nnzb][bs][bs]; pass NULL arrays to query
+ * sizes through *n_rows_out / *nnzb_out first. */
+int amg_get_level_matrix(const amg_handle *h, int32_t level, int64_t *n_rows_out, int64_t *nnzb_out,
+                         int64_t *row_ptr, int32_t *col, double *val);
+
+/* Component access in natural numbering of level l (device vectors, float64),
+ * for parity tests and diagnostics:
+ *   TE_OP_A       y = A_l x
+ *   TE_OP_P       y = P_l x        (x on level l+1)
+ *   TE_OP_R       y = P_l^T x      (y on level l+1)
+ *   TE_OP_SMOOTH  y = Chebyshev(A_l, g = x, x0 = y)   (y in: x0, out: result)
+ *   TE_OP_VCYCLE  y = V-cycle from level l applied to x
+ * `precision` selects the float64 or float32 operator copies. */
+#define TE_OP_A       0
+#define TE_OP_P       1
+#define TE_OP_R       2
+#define TE_OP_SMOOTH  3
+#define TE_OP_VCYCLE  4
+int amg_apply(amg_handle *h, int32_t level, int32_t op, int32_t precision,
+              const double *x, double *y, hipStream_t stream);
+
+/* ---- preconditioned conjugate gradients (Sec. 2.1.2) -------------------- */
+typedef struct {
+    double rtol;             /* stop at true |b - A u|_2 <= rtol |b|_2 (1e-8)           */
+    int32_t maxit;           /* (500)                                                   */
+    int32_t precision;       /* TE_PREC_FP64 or TE_PREC_MIXED                           */
+    int32_t max_replace;     /* residual replacements after a failed true check (3)     */
+    int32_t profile;         /* 1: time each kernel class with HIP events (0)           */
+} pcg_options;
+
+/* Kernel classes timed when pcg_options.profile = 1 (level 0 = mesh level):   */
+#define TE_K_AP        0   /* q = A_0 p with the (p,q) partial sums            */
+#define TE_K_PRE       1   /* level-0 pre-smoothing Chebyshev step            */
+#define TE_K_RESID     2   /* level-0 residual s = g - A_0 x                  */
+#define TE_K_RESTRICT  3   /* R_0 s                                           */
+#define TE_K_PROLONG   4   /* x += P_0 e                                      */
+#define TE_K_POSTINIT  5   /* level-0 post-smoothing start r = g - A_0 x      */
+#define TE_K_POST      6   /* level-0 post-smoothing Chebyshev step           */
+#define TE_K_COARSE    7   /* all work on levels >= 1 (incl. the dense solve) */
+#define TE_K_VECTOR    8   /* level-0 vector kernels (CG updates, dots)       */
+#define TE_K_COUNT     9
+
+void pcg_options_default(pcg_options *opt);
+
+typedef struct {
+    /* host arrays of nrhs entries each, filled if non-NULL */
+    int32_t *iters;          /* iterations (A p products) per right-hand side          */
+    int32_t *converged;      /* 1 if the true residual met rtol                         */
+    double *relres_true;     /* final |b - A u| / |b|                                  */
+    /* host array of (maxit + 1) * nrhs relative recurrence residuals, entry
+       [k * nrhs + j] after iteration k of column j (NaN after it stopped), or NULL */
+    double *history;
+    /* outputs */
+    int32_t max_iters;
+    double time_ms;          /* elapsed device time of the solve (HIP events)           */
+    double kernel_ms[TE_K_COUNT];       /* summed event time per class (profile = 1) */
+    int32_t kernel_launches[TE_K_COUNT];
+} pcg_report;
+
+/* Solves A U = B for nrhs right-hand sides (1..max_nrhs of the setup).
+ *   b: device [N][3][nrhs] (nrhs = 1: [3N]);
+ *   u: device [N][3][nrhs]; in: initial guess, out: solution.
+ *   rep: host, may be NULL.
+ * Each column runs its own CG recurrence (the columns share every sparse
+ * product); a converged column is frozen.  MIXED runs the V-cycle in float32
+ * and uses the flexible beta.  Synchronises `stream`.
+ * Returns TE_OK, TE_ENOTCONV (some column hit maxit), TE_EINDEF, TE_ENAN,
+ * TE_EINVAL, TE_EHIP. */
+int amg_pcg_solve(amg_handle *h, const double *b, double *u, int32_t nrhs,
+                  const pcg_options *opt, pcg_report *rep, hipStream_t stream);
+
+/* Releases everything the handle owns.  NULL is accepted. */
+int amg_destroy(amg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TE_H */

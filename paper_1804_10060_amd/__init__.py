@@ -1,0 +1,240 @@
+"""MI355X thermoelastic PCG + smoothed-aggregation AMG (Python binding).
+
+Thin marshalling layer over the C ABI of include/te.h: every computation runs
+in the HIP library libte_amd.so.  PyTorch supplies device memory and the
+stream.  Importing this package does not touch the GPU; the library is loaded
+on first use and a missing library raises (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+from . import _lib
+from ._lib import (TE_OP_A, TE_OP_P, TE_OP_R, TE_OP_SMOOTH, TE_OP_VCYCLE, TE_PREC_FP64, TE_PREC_MIXED, TeError,
+                   check, load)
+
+__all__ = ["assemble", "assemble_load", "AMG", "Matrix", "TeError", "load", "TE_PREC_FP64", "TE_PREC_MIXED",
+           "TE_OP_A", "TE_OP_P", "TE_OP_R", "TE_OP_SMOOTH", "TE_OP_VCYCLE"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="array"):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+@dataclasses.dataclass
+class Matrix:
+    """3x3-block compressed rows on the device (te_bsr)."""
+
+    row_ptr: object   # int64 [N+1]
+    col_idx: object   # int32 [nnzb]
+    val: object       # float64 [nnzb, 3, 3]
+
+    @property
+    def n(self):
+        return self.row_ptr.numel() - 1
+
+    @property
+    def nnzb(self):
+        return self.col_idx.numel()
+
+    def c(self):
+        return _lib.TeBsr(self.n, self.nnzb, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.val.data_ptr())
+
+
+def _mesh(coords, cells, degree):
+    torch = _torch()
+    npe = 4 if degree == 1 else 10
+    _dev(coords, torch.float64, (coords.shape[0], 3), "coords")
+    _dev(cells, torch.int32, (cells.shape[0], npe), "cells")
+    return _lib.TeMesh(coords.shape[0], cells.shape[0], degree, coords.data_ptr(), cells.data_ptr())
+
+
+def assemble(coords, cells, degree, E, nu, alpha, T_ref, T, f=None, mask=None, u_bc=None):
+    """fe_assemble_pattern + fe_assemble_thermoelastic.  Returns (Matrix, b[3N])."""
+    torch = _torch()
+    lib = load()
+    m = _mesh(coords, cells, degree)
+    n = coords.shape[0]
+    _dev(T, torch.float64, (n,), "T")
+    _dev(f, torch.float64, (n, 3), "f")
+    _dev(mask, torch.uint8, (n, 3), "mask")
+    _dev(u_bc, torch.float64, (n, 3), "u_bc")
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=coords.device)
+    nnzb = C.c_int64(0)
+    check(lib.fe_assemble_pattern(C.byref(m), _ptr(row_ptr), C.byref(nnzb), _stream()))
+    col = torch.empty(nnzb.value, dtype=torch.int32, device=coords.device)
+    val = torch.empty((nnzb.value, 3, 3), dtype=torch.float64, device=coords.device)
+    b = torch.empty(3 * n, dtype=torch.float64, device=coords.device)
+    A = Matrix(row_ptr, col, val)
+    mat = _lib.TeMaterial(E, nu, alpha, T_ref)
+    bsr = A.c()
+    check(lib.fe_assemble_thermoelastic(C.byref(m), C.byref(mat), _ptr(T), _ptr(f), _ptr(mask), _ptr(u_bc),
+                                        C.byref(bsr), _ptr(b), _stream()))
+    return A, b
+
+
+def assemble_load(coords, cells, degree, E, nu, alpha, T_ref, T, f=None, mask=None):
+    """fe_assemble_load for nrhs load cases: T [nrhs, N] -> b [N, 3, nrhs]."""
+    torch = _torch()
+    lib = load()
+    m = _mesh(coords, cells, degree)
+    n = coords.shape[0]
+    nrhs = T.shape[0]
+    _dev(T, torch.float64, (nrhs, n), "T")
+    _dev(f, torch.float64, (nrhs, n, 3), "f")
+    _dev(mask, torch.uint8, (n, 3), "mask")
+    b = torch.empty((n, 3, nrhs), dtype=torch.float64, device=coords.device)
+    mat = _lib.TeMaterial(E, nu, alpha, T_ref)
+    check(lib.fe_assemble_load(C.byref(m), C.byref(mat), _ptr(T), _ptr(f), _ptr(mask), nrhs, _ptr(b), _stream()))
+    return b
+
+
+@dataclasses.dataclass
+class SolveReport:
+    iters: list
+    converged: list
+    relres_true: list
+    history: object
+    max_iters: int
+    time_ms: float
+    code: int
+    kernel_ms: list
+    kernel_launches: list
+
+
+class AMG:
+    """amg_setup / amg_pcg_solve / amg_destroy."""
+
+    def __init__(self, A: Matrix, coords, mask=None, aggregates=None, **opts):
+        torch = _torch()
+        lib = load()
+        n = A.n
+        _dev(A.row_ptr, torch.int64, (n + 1,), "row_ptr")
+        _dev(A.col_idx, torch.int32, None, "col_idx")
+        _dev(A.val, torch.float64, (A.nnzb, 3, 3), "val")
+        _dev(coords, torch.float64, (n, 3), "coords")
+        _dev(mask, torch.uint8, (n, 3), "mask")
+        o = _lib.AmgOptions()
+        lib.amg_options_default(C.byref(o))
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown AMG option {k}")
+            setattr(o, k, v)
+        self.opts = o
+        self._h = C.c_void_p(0)
+        bsr = A.c()
+        if aggregates is None:
+            check(lib.amg_setup(C.byref(bsr), _ptr(coords), _ptr(mask), C.byref(o), C.byref(self._h), _stream()))
+        else:
+            import numpy as np
+            arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in aggregates]
+            ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+            check(lib.amg_setup_with_aggregates(C.byref(bsr), _ptr(coords), _ptr(mask), C.byref(o), ptrs,
+                                                len(arrs), C.byref(self._h), _stream()))
+        self.n = n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load().amg_destroy(h)
+            self._h = C.c_void_p(0)
+
+    def close(self):
+        self.__del__()
+
+    # ---- introspection --------------------------------------------------
+    def info(self):
+        i = _lib.AmgInfo()
+        check(load().amg_get_info(self._h, C.byref(i)))
+        L = i.n_levels
+        return {"n_levels": L, "n_dof": list(i.n_dof[:L]), "nnzb": list(i.nnzb[:L]), "bs": list(i.bs[:L]),
+                "lambda_hat": list(i.lambda_hat[:L]), "p_nnzb": list(i.p_nnzb[:L]), "setup_ms": i.setup_ms,
+                "bytes_device": i.bytes_device}
+
+    def aggregates(self, level):
+        import numpy as np
+        n = self.info()["n_dof"][level] // self.info()["bs"][level]
+        out = np.empty(n, np.int32)
+        check(load().amg_get_aggregates(self._h, level, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def level_matrix(self, level):
+        """(row_ptr, col, val[nnzb, bs, bs]) of A_level in natural numbering (host numpy)."""
+        import numpy as np
+        nr, nz = C.c_int64(0), C.c_int64(0)
+        lib = load()
+        check(lib.amg_get_level_matrix(self._h, level, C.byref(nr), C.byref(nz), None, None, None))
+        bs = self.info()["bs"][level]
+        rp = np.empty(nr.value + 1, np.int64)
+        col = np.empty(nz.value, np.int32)
+        val = np.empty((nz.value, bs, bs), np.float64)
+        check(lib.amg_get_level_matrix(self._h, level, C.byref(nr), C.byref(nz), C.c_void_p(rp.ctypes.data),
+                                       C.c_void_p(col.ctypes.data), C.c_void_p(val.ctypes.data)))
+        return rp, col, val
+
+    def apply(self, level, op, x, y=None, precision=TE_PREC_FP64):
+        torch = _torch()
+        _dev(x, torch.float64, None, "x")
+        if y is None:
+            info = self.info()
+            lv = level + 1 if op == TE_OP_R else level
+            y = torch.zeros(info["n_dof"][lv], dtype=torch.float64, device=x.device)
+        check(load().amg_apply(self._h, level, op, precision, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    # ---- solve ----------------------------------------------------------
+    def solve(self, b, u0=None, rtol=1e-8, maxit=500, precision="fp64", max_replace=3, history=False,
+              allow_notconv=False, profile=False):
+        """Returns (u, SolveReport).  b: [3N] or [N, 3, nrhs] float64 device tensor."""
+        torch = _torch()
+        import numpy as np
+        nrhs = 1 if b.dim() == 1 else b.shape[-1]
+        _dev(b, torch.float64, None, "b")
+        if b.numel() != 3 * self.n * nrhs:
+            raise ValueError("b has the wrong size")
+        u = torch.zeros_like(b) if u0 is None else _dev(u0, torch.float64, tuple(b.shape), "u0").clone()
+        o = _lib.PcgOptions()
+        load().pcg_options_default(C.byref(o))
+        o.rtol, o.maxit, o.max_replace, o.profile = rtol, maxit, max_replace, int(profile)
+        o.precision = {"fp64": TE_PREC_FP64, "mixed": TE_PREC_MIXED}[precision] if isinstance(precision, str) \
+            else precision
+        iters = np.zeros(nrhs, np.int32)
+        conv = np.zeros(nrhs, np.int32)
+        rel = np.zeros(nrhs, np.float64)
+        hist = np.zeros((maxit + 1) * nrhs, np.float64) if history else None
+        rep = _lib.PcgReport()
+        rep.iters, rep.converged, rep.relres_true = iters.ctypes.data, conv.ctypes.data, rel.ctypes.data
+        rep.history = hist.ctypes.data if hist is not None else None
+        code = load().amg_pcg_solve(self._h, _ptr(b), _ptr(u), nrhs, C.byref(o), C.byref(rep), _stream())
+        check(code, allow=(_lib.TE_OK, _lib.TE_ENOTCONV) if allow_notconv else (_lib.TE_OK,))
+        h = hist.reshape(maxit + 1, nrhs) if hist is not None else None
+        return u, SolveReport(iters.tolist(), conv.tolist(), rel.tolist(), h, rep.max_iters, rep.time_ms, code,
+                              list(rep.kernel_ms), list(rep.kernel_launches))

@@ -1,0 +1,113 @@
+"""ctypes declarations of the C ABI in include/te.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libte_amd.so")
+
+TE_OK, TE_ENOTCONV = 0, 1
+TE_EINVAL, TE_ENOMEM, TE_EHIP, TE_EINDEF, TE_ENAN, TE_ERANK, TE_ECHOL = -1, -2, -3, -4, -5, -6, -7
+TE_PREC_FP64, TE_PREC_MIXED = 0, 1
+TE_OP_A, TE_OP_P, TE_OP_R, TE_OP_SMOOTH, TE_OP_VCYCLE = 0, 1, 2, 3, 4
+KERNEL_CLASSES = ["Ap", "pre_smooth", "residual", "restrict", "prolong", "post_init", "post_smooth", "coarse_levels",
+                  "vector"]
+
+CODE_NAMES = {TE_ENOTCONV: "TE_ENOTCONV", TE_EINVAL: "TE_EINVAL", TE_ENOMEM: "TE_ENOMEM", TE_EHIP: "TE_EHIP",
+              TE_EINDEF: "TE_EINDEF", TE_ENAN: "TE_ENAN", TE_ERANK: "TE_ERANK", TE_ECHOL: "TE_ECHOL"}
+
+# exported names declared in include/te.h
+EXPORTS = ["te_version", "te_last_error", "fe_assemble_pattern", "fe_assemble_thermoelastic", "fe_assemble_load",
+           "amg_options_default", "amg_setup", "amg_setup_with_aggregates", "amg_get_info", "amg_get_aggregates",
+           "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_destroy"]
+
+
+class TeMesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_cells", C.c_int64), ("degree", C.c_int32),
+                ("coords", C.c_void_p), ("cells", C.c_void_p)]
+
+
+class TeMaterial(C.Structure):
+    _fields_ = [("E", C.c_double), ("nu", C.c_double), ("alpha", C.c_double), ("T_ref", C.c_double)]
+
+
+class TeBsr(C.Structure):
+    _fields_ = [("n_brows", C.c_int64), ("nnzb", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class AmgOptions(C.Structure):
+    _fields_ = [("theta0", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+                ("lanczos_steps", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
+                ("cheb_safety", C.c_double), ("max_coarse_ratio", C.c_double), ("build_fp32", C.c_int32),
+                ("host_threads", C.c_int32), ("max_nrhs", C.c_int32)]
+
+
+class AmgInfo(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_dof", C.c_int64 * 16), ("nnzb", C.c_int64 * 16),
+                ("bs", C.c_int32 * 16), ("lambda_hat", C.c_double * 16), ("p_nnzb", C.c_int64 * 16),
+                ("setup_ms", C.c_double), ("bytes_device", C.c_int64)]
+
+
+class PcgOptions(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("precision", C.c_int32), ("max_replace", C.c_int32),
+                ("profile", C.c_int32)]
+
+
+class PcgReport(C.Structure):
+    _fields_ = [("iters", C.c_void_p), ("converged", C.c_void_p), ("relres_true", C.c_void_p),
+                ("history", C.c_void_p), ("max_iters", C.c_int32), ("time_ms", C.c_double),
+                ("kernel_ms", C.c_double * 9), ("kernel_launches", C.c_int32 * 9)]
+
+
+_lib = None
+
+
+def load():
+    """Load libte_amd.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_1804_10060_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "te_version": ([], C.c_int),
+        "te_last_error": ([], C.c_char_p),
+        "fe_assemble_pattern": ([C.POINTER(TeMesh), vp, C.POINTER(i64), vp], C.c_int),
+        "fe_assemble_thermoelastic": ([C.POINTER(TeMesh), C.POINTER(TeMaterial), vp, vp, vp, vp, C.POINTER(TeBsr),
+                                       vp, vp], C.c_int),
+        "fe_assemble_load": ([C.POINTER(TeMesh), C.POINTER(TeMaterial), vp, vp, vp, i32, vp, vp], C.c_int),
+        "amg_options_default": ([C.POINTER(AmgOptions)], None),
+        "amg_setup": ([C.POINTER(TeBsr), vp, vp, C.POINTER(AmgOptions), C.POINTER(vp), vp], C.c_int),
+        "amg_setup_with_aggregates": ([C.POINTER(TeBsr), vp, vp, C.POINTER(AmgOptions), C.POINTER(vp), i32,
+                                       C.POINTER(vp), vp], C.c_int),
+        "amg_get_info": ([vp, C.POINTER(AmgInfo)], C.c_int),
+        "amg_get_aggregates": ([vp, i32, vp], C.c_int),
+        "amg_get_level_matrix": ([vp, i32, C.POINTER(i64), C.POINTER(i64), vp, vp, vp], C.c_int),
+        "amg_apply": ([vp, i32, i32, i32, vp, vp, vp], C.c_int),
+        "pcg_options_default": ([C.POINTER(PcgOptions)], None),
+        "amg_pcg_solve": ([vp, vp, vp, i32, C.POINTER(PcgOptions), C.POINTER(PcgReport), vp], C.c_int),
+        "amg_destroy": ([vp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class TeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{CODE_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(code, allow=(TE_OK,)):
+    if code in allow:
+        return code
+    msg = load().te_last_error().decode(errors="replace")
+    raise TeError(code, msg)

@@ -1,0 +1,1038 @@
+// Smoothed-aggregation AMG setup (Sec. 2.1.3 and 5.1 of the paper; the
+// method of Vanek, Mandel & Brezina 1996 with the rigid-body near-nullspace).
+//
+// Host part: strength of connection, greedy aggregation, tentative
+// prolongator by Householder QR, prolongator smoothing and the Galerkin
+// product (row-wise sparse products with per-thread accumulators), the dense
+// Cholesky factor and inverse of the coarsest level.  Device part: every
+// level operator is packed into the SELL-64 layout, and the largest
+// eigenvalue of D^-1 A is estimated with Lanczos on the GPU.
+//
+// Readings of what the paper leaves open (strength threshold 0.08 halved per
+// level, tie handling, QR sign, 20 Lanczos steps, coarse size 3000 DOF,
+// Chebyshev interval) are the library defaults of amg_options.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <thread>
+
+#include "te_amg.h"
+
+namespace te {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[1024] = "";
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+const char *last_error() { return g_err; }
+
+// ---------------------------------------------------------------------------
+// threads
+// ---------------------------------------------------------------------------
+static int g_threads = 0;
+static int n_threads() {
+    if (g_threads > 0) return g_threads;
+    unsigned h = std::thread::hardware_concurrency();
+    return h ? (int)std::min(h, 64u) : 4;
+}
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &fn) {
+    int nt = (int)std::min<int64_t>(n_threads(), std::max<int64_t>(1, n / 256));
+    if (nt <= 1) {
+        fn(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) {
+        int64_t lo = n * t / nt, hi = n * (t + 1) / nt;
+        th.emplace_back([=, &fn] { fn(lo, hi, t); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------
+// host block-sparse helpers
+// ---------------------------------------------------------------------------
+static void bsr_diag_points(const HBsr &A, std::vector<double> &d) {
+    const int b = A.br;
+    d.assign((size_t)A.nr * b, 0.0);
+    for (int64_t i = 0; i < A.nr; ++i)
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (A.col[k] == i)
+                for (int p = 0; p < b; ++p) d[i * b + p] = A.val[(size_t)k * b * b + p * b + p];
+}
+
+// C = A * B (block products, row-wise). Columns of each C row sorted.
+static HBsr bsr_mult(const HBsr &A, const HBsr &B) {
+    TE_REQUIRE(A.bc == B.br && A.nc == B.nr, TE_EINVAL, "bsr_mult shape mismatch");
+    const int br = A.br, bk = A.bc, bc = B.bc, bb = br * bc;
+    HBsr C;
+    C.br = br;
+    C.bc = bc;
+    C.nr = A.nr;
+    C.nc = B.nc;
+    const int nt = n_threads();
+    std::vector<std::vector<int32_t>> tcol(nt);
+    std::vector<std::vector<double>> tval(nt);
+    std::vector<int64_t> cnt(A.nr, 0);
+    std::vector<int64_t> chunk_lo(nt + 1, 0);
+    std::vector<int> used(nt, 0);
+    std::vector<int64_t> lo_of(nt, 0), hi_of(nt, 0);
+    parallel_for(A.nr, [&](int64_t lo, int64_t hi, int t) {
+        used[t] = 1;
+        lo_of[t] = lo;
+        hi_of[t] = hi;
+        std::vector<int32_t> marker(B.nc, -1);
+        std::vector<int32_t> cols;
+        std::vector<double> acc;
+        auto &oc = tcol[t];
+        auto &ov = tval[t];
+        for (int64_t i = lo; i < hi; ++i) {
+            cols.clear();
+            acc.clear();
+            for (int64_t ka = A.ptr[i]; ka < A.ptr[i + 1]; ++ka) {
+                const int32_t j = A.col[ka];
+                const double *a = &A.val[(size_t)ka * br * bk];
+                for (int64_t kb = B.ptr[j]; kb < B.ptr[j + 1]; ++kb) {
+                    const int32_t c = B.col[kb];
+                    int32_t slot = marker[c];
+                    if (slot < 0) {
+                        slot = (int32_t)cols.size();
+                        marker[c] = slot;
+                        cols.push_back(c);
+                        acc.resize(acc.size() + bb, 0.0);
+                    }
+                    const double *bv = &B.val[(size_t)kb * bk * bc];
+                    double *o = &acc[(size_t)slot * bb];
+                    for (int p = 0; p < br; ++p)
+                        for (int r = 0; r < bk; ++r) {
+                            const double av = a[p * bk + r];
+                            if (av == 0.0) continue;
+                            for (int q = 0; q < bc; ++q) o[p * bc + q] += av * bv[r * bc + q];
+                        }
+                }
+            }
+            // emit sorted by column
+            std::vector<int32_t> order(cols.size());
+            for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+            std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cols[x] < cols[y]; });
+            for (int32_t k : order) {
+                oc.push_back(cols[k]);
+                ov.insert(ov.end(), acc.begin() + (size_t)k * bb, acc.begin() + (size_t)(k + 1) * bb);
+            }
+            cnt[i] = (int64_t)cols.size();
+            for (int32_t c : cols) marker[c] = -1;
+        }
+    });
+    C.ptr.assign(A.nr + 1, 0);
+    for (int64_t i = 0; i < A.nr; ++i) C.ptr[i + 1] = C.ptr[i] + cnt[i];
+    C.col.resize(C.ptr[A.nr]);
+    C.val.resize((size_t)C.ptr[A.nr] * bb);
+    for (int t = 0; t < nt; ++t) {
+        if (!used[t] || lo_of[t] >= hi_of[t]) continue;
+        int64_t off = C.ptr[lo_of[t]];
+        std::copy(tcol[t].begin(), tcol[t].end(), C.col.begin() + off);
+        std::copy(tval[t].begin(), tval[t].end(), C.val.begin() + (size_t)off * bb);
+    }
+    return C;
+}
+
+static HBsr bsr_transpose(const HBsr &A) {
+    HBsr T;
+    T.br = A.bc;
+    T.bc = A.br;
+    T.nr = A.nc;
+    T.nc = A.nr;
+    const int bb = A.br * A.bc;
+    T.ptr.assign(T.nr + 1, 0);
+    for (int32_t c : A.col) T.ptr[c + 1]++;
+    for (int64_t i = 0; i < T.nr; ++i) T.ptr[i + 1] += T.ptr[i];
+    T.col.resize(A.col.size());
+    T.val.resize(A.val.size());
+    std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
+    for (int64_t i = 0; i < A.nr; ++i)
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            int64_t d = pos[A.col[k]]++;
+            T.col[d] = (int32_t)i;
+            const double *s = &A.val[(size_t)k * bb];
+            double *o = &T.val[(size_t)d * bb];
+            for (int p = 0; p < A.br; ++p)
+                for (int q = 0; q < A.bc; ++q) o[q * A.br + p] = s[p * A.bc + q];
+        }
+    return T;
+}
+
+// ---------------------------------------------------------------------------
+// strength and aggregation
+// ---------------------------------------------------------------------------
+struct Strength {
+    std::vector<double> s;  // per stored block (0 on the diagonal)
+};
+
+// Frobenius norms with the squares summed in row-major order (no fused
+// multiply-add: this file is compiled with -ffp-contract=off).
+static Strength strength_of(const HBsr &A) {
+    const int bb = A.br * A.bc;
+    std::vector<double> fro(A.col.size());
+    parallel_for(A.nnzb(), [&](int64_t lo, int64_t hi, int) {
+        for (int64_t k = lo; k < hi; ++k) {
+            double acc = 0.0;
+            const double *v = &A.val[(size_t)k * bb];
+            for (int e = 0; e < bb; ++e) {
+                double sq = v[e] * v[e];
+                acc = acc + sq;
+            }
+            fro[k] = std::sqrt(acc);
+        }
+    });
+    std::vector<double> dn(A.nr, 0.0);
+    for (int64_t i = 0; i < A.nr; ++i)
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (A.col[k] == i) dn[i] = fro[k];
+    Strength S;
+    S.s.resize(A.col.size());
+    parallel_for(A.nr, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                const int32_t j = A.col[k];
+                S.s[k] = (j == i) ? 0.0 : fro[k] / std::sqrt(dn[i] * dn[j]);
+            }
+    });
+    return S;
+}
+
+static const double kTieRtol = 1e-9;
+static const double kRankRtol = 1e-10;
+
+// agg[i] = aggregate id or -1 (isolated); returns the number of aggregates
+static int64_t greedy_aggregate(const HBsr &A, const Strength &S, double theta, std::vector<int32_t> &agg) {
+    const int64_t n = A.nr;
+    agg.assign(n, -1);
+    std::vector<uint8_t> has_strong(n, 0);
+    auto strong = [&](int64_t i, int64_t k) { return A.col[k] != i && S.s[k] >= theta; };
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (strong(i, k)) {
+                has_strong[i] = 1;
+                break;
+            }
+    int64_t na = 0;
+    // phase 1: a free node whose strong neighbours are all free roots a new aggregate
+    for (int64_t i = 0; i < n; ++i) {
+        if (!has_strong[i] || agg[i] >= 0) continue;
+        bool free = true;
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1] && free; ++k)
+            if (strong(i, k) && agg[A.col[k]] >= 0) free = false;
+        if (!free) continue;
+        agg[i] = (int32_t)na;
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+            if (strong(i, k)) agg[A.col[k]] = (int32_t)na;
+        ++na;
+    }
+    // phase 2: remaining nodes join the phase-1 aggregate of their strongest
+    // strong neighbour; near-equal strengths go to the smaller aggregate id
+    std::vector<int32_t> snap(agg);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!has_strong[i] || snap[i] >= 0) continue;
+        double bs = -1.0;
+        int32_t ba = -1;
+        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+            if (!strong(i, k)) continue;
+            const int32_t a = snap[A.col[k]];
+            if (a < 0) continue;
+            const double sv = S.s[k];
+            if (ba < 0 || sv > bs * (1.0 + kTieRtol)) {
+                bs = sv;
+                ba = a;
+            } else if (sv >= bs * (1.0 - kTieRtol) && a < ba) {
+                bs = sv;
+                ba = a;
+            }
+        }
+        TE_REQUIRE(ba >= 0, TE_EINVAL, "aggregation: node %lld has no aggregated strong neighbour", (long long)i);
+        agg[i] = ba;
+    }
+    return na;
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR of an m x k matrix (column-major), thin Q with diag(R) > 0
+// ---------------------------------------------------------------------------
+static bool qr_thin(int m, int k, std::vector<double> &M /* m x k col-major in, Q out */, double *R /* k x k */) {
+    if (m < k) return false;
+    std::vector<double> V((size_t)m * k, 0.0), beta(k, 0.0);
+    std::vector<double> W(M);
+    for (int j = 0; j < k; ++j) {
+        double nrm = 0.0;
+        for (int i = j; i < m; ++i) nrm += W[(size_t)j * m + i] * W[(size_t)j * m + i];
+        nrm = std::sqrt(nrm);
+        double x0 = W[(size_t)j * m + j];
+        double alpha = x0 >= 0 ? -nrm : nrm;
+        double *v = &V[(size_t)j * m];
+        for (int i = j; i < m; ++i) v[i] = W[(size_t)j * m + i];
+        v[j] -= alpha;
+        double vn = 0.0;
+        for (int i = j; i < m; ++i) vn += v[i] * v[i];
+        beta[j] = vn > 0 ? 2.0 / vn : 0.0;
+        for (int c = j; c < k; ++c) {
+            double t = 0.0;
+            for (int i = j; i < m; ++i) t += v[i] * W[(size_t)c * m + i];
+            t *= beta[j];
+            for (int i = j; i < m; ++i) W[(size_t)c * m + i] -= t * v[i];
+        }
+    }
+    for (int r = 0; r < k; ++r)
+        for (int c = 0; c < k; ++c) R[r * k + c] = (c >= r) ? W[(size_t)c * m + r] : 0.0;
+    // Q = H_0 ... H_{k-1} [I_k; 0]
+    for (int c = 0; c < k; ++c) {
+        double *q = &M[(size_t)c * m];
+        for (int i = 0; i < m; ++i) q[i] = (i == c) ? 1.0 : 0.0;
+        for (int j = k - 1; j >= 0; --j) {
+            const double *v = &V[(size_t)j * m];
+            double t = 0.0;
+            for (int i = j; i < m; ++i) t += v[i] * q[i];
+            t *= beta[j];
+            for (int i = j; i < m; ++i) q[i] -= t * v[i];
+        }
+    }
+    // positive diagonal of R
+    for (int r = 0; r < k; ++r)
+        if (R[r * k + r] < 0) {
+            for (int c = 0; c < k; ++c) R[r * k + c] = -R[r * k + c];
+            for (int i = 0; i < m; ++i) M[(size_t)r * m + i] = -M[(size_t)r * m + i];
+        }
+    return true;
+}
+
+static bool rank_ok(const double *R, int k) {
+    double mx = 0.0, mn = INFINITY;
+    for (int r = 0; r < k; ++r) {
+        double v = std::fabs(R[r * k + r]);
+        mx = std::max(mx, v);
+        mn = std::min(mn, v);
+    }
+    return mx > 0 && mn >= kRankRtol * mx;
+}
+
+struct Tentative {
+    int64_t nc = 0;
+    std::vector<int32_t> agg;   // compact ids, -1 isolated
+    std::vector<double> Q;      // [n][bs][k] (zero rows for isolated nodes)
+    std::vector<double> Bc;     // [nc][k][k]
+};
+
+// Nodes of an aggregate as a 'bs*|J| x k' column-major block of B.
+static void gather_B(const std::vector<int32_t> &nodes, const std::vector<double> &B, int bs, int k,
+                     std::vector<double> &M) {
+    const int m = (int)nodes.size() * bs;
+    M.assign((size_t)m * k, 0.0);
+    for (size_t a = 0; a < nodes.size(); ++a)
+        for (int p = 0; p < bs; ++p)
+            for (int c = 0; c < k; ++c) M[(size_t)c * m + a * bs + p] = B[((size_t)nodes[a] * bs + p) * k + c];
+}
+
+static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t> agg, int64_t na,
+                           const std::vector<double> &B, int bs, int k) {
+    const int64_t n = A.nr;
+    std::vector<std::vector<int32_t>> mem(na);
+    for (int64_t i = 0; i < n; ++i)
+        if (agg[i] >= 0) mem[agg[i]].push_back((int32_t)i);
+    std::vector<double> M, R((size_t)k * k);
+    int64_t a = 0;
+    while (a < na) {
+        auto &nodes = mem[a];
+        if (nodes.empty()) {
+            ++a;
+            continue;
+        }
+        gather_B(nodes, B, bs, k, M);
+        const int m = (int)nodes.size() * bs;
+        if (m >= k && qr_thin(m, k, M, R.data()) && rank_ok(R.data(), k)) {
+            ++a;
+            continue;
+        }
+        // merge into the neighbour aggregate with the largest summed strength
+        std::vector<std::pair<int32_t, double>> score;
+        for (int32_t i : nodes)
+            for (int64_t kk = A.ptr[i]; kk < A.ptr[i + 1]; ++kk) {
+                const int32_t c = A.col[kk];
+                if (c == i) continue;
+                const int32_t t = agg[c];
+                if (t < 0 || t == a) continue;
+                bool found = false;
+                for (auto &sc : score)
+                    if (sc.first == t) {
+                        sc.second += S.s[kk];
+                        found = true;
+                        break;
+                    }
+                if (!found) score.push_back({t, S.s[kk]});
+            }
+        TE_REQUIRE(!score.empty(), TE_ERANK, "aggregate %lld is rank deficient and has no neighbour", (long long)a);
+        int32_t best = score[0].first;
+        double bsv = score[0].second;
+        for (auto &sc : score)
+            if (sc.second > bsv || (sc.second == bsv && sc.first < best)) {
+                best = sc.first;
+                bsv = sc.second;
+            }
+        for (int32_t i : nodes) agg[i] = best;
+        auto &dst = mem[best];
+        dst.insert(dst.end(), nodes.begin(), nodes.end());
+        std::sort(dst.begin(), dst.end());
+        nodes.clear();
+        a = (best < a) ? best : a + 1;
+    }
+    Tentative T;
+    std::vector<int32_t> remap(na, -1);
+    for (int64_t x = 0; x < na; ++x)
+        if (!mem[x].empty()) remap[x] = (int32_t)T.nc++;
+    T.agg.assign(n, -1);
+    for (int64_t i = 0; i < n; ++i)
+        if (agg[i] >= 0) T.agg[i] = remap[agg[i]];
+    T.Q.assign((size_t)n * bs * k, 0.0);
+    T.Bc.assign((size_t)T.nc * k * k, 0.0);
+    std::vector<int64_t> live;
+    for (int64_t x = 0; x < na; ++x)
+        if (!mem[x].empty()) live.push_back(x);
+    parallel_for((int64_t)live.size(), [&](int64_t lo, int64_t hi, int) {
+        std::vector<double> Mt;
+        for (int64_t li = lo; li < hi; ++li) {
+            const auto &nodes = mem[live[li]];
+            const int m = (int)nodes.size() * bs;
+            gather_B(nodes, B, bs, k, Mt);
+            double *Rc = &T.Bc[(size_t)li * k * k];
+            qr_thin(m, k, Mt, Rc);
+            for (size_t aa = 0; aa < nodes.size(); ++aa)
+                for (int p = 0; p < bs; ++p)
+                    for (int c = 0; c < k; ++c)
+                        T.Q[((size_t)nodes[aa] * bs + p) * k + c] = Mt[(size_t)c * m + aa * bs + p];
+        }
+    });
+    return T;
+}
+
+// P = (I - omega D^-1 A) P_tent as a block matrix (bs x k blocks)
+static HBsr smoothed_P(const HBsr &A, const std::vector<double> &dpt, const Tentative &T, double omega, int k) {
+    const int bs = A.br;
+    HBsr P;
+    P.br = bs;
+    P.bc = k;
+    P.nr = A.nr;
+    P.nc = T.nc;
+    const int bb = bs * k;
+    const int nt = n_threads();
+    std::vector<std::vector<int32_t>> tcol(nt);
+    std::vector<std::vector<double>> tval(nt);
+    std::vector<int64_t> cnt(A.nr, 0), lo_of(nt, 0), hi_of(nt, 0);
+    std::vector<int> used(nt, 0);
+    parallel_for(A.nr, [&](int64_t lo, int64_t hi, int t) {
+        used[t] = 1;
+        lo_of[t] = lo;
+        hi_of[t] = hi;
+        std::vector<int32_t> cols;
+        std::vector<double> acc;
+        for (int64_t i = lo; i < hi; ++i) {
+            cols.clear();
+            acc.clear();
+            auto slot_of = [&](int32_t c) {
+                for (size_t s = 0; s < cols.size(); ++s)
+                    if (cols[s] == c) return (int)s;
+                cols.push_back(c);
+                acc.resize(acc.size() + bb, 0.0);
+                return (int)cols.size() - 1;
+            };
+            for (int64_t kk = A.ptr[i]; kk < A.ptr[i + 1]; ++kk) {
+                const int32_t j = A.col[kk];
+                if (T.agg[j] < 0) continue;
+                const int s = slot_of(T.agg[j]);
+                const double *a = &A.val[(size_t)kk * bs * bs];
+                const double *q = &T.Q[(size_t)j * bs * k];
+                double *o = &acc[(size_t)s * bb];
+                for (int p = 0; p < bs; ++p) {
+                    const double f = omega / dpt[i * bs + p];
+                    for (int r = 0; r < bs; ++r) {
+                        const double av = a[p * bs + r];
+                        if (av == 0.0) continue;
+                        for (int c = 0; c < k; ++c) o[p * k + c] -= f * av * q[r * k + c];
+                    }
+                }
+            }
+            if (T.agg[i] >= 0) {
+                const int s = slot_of(T.agg[i]);
+                const double *q = &T.Q[(size_t)i * bs * k];
+                double *o = &acc[(size_t)s * bb];
+                for (int e = 0; e < bb; ++e) o[e] += q[e];
+            }
+            std::vector<int32_t> order(cols.size());
+            for (size_t x = 0; x < order.size(); ++x) order[x] = (int32_t)x;
+            std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cols[x] < cols[y]; });
+            for (int32_t x : order) {
+                tcol[t].push_back(cols[x]);
+                tval[t].insert(tval[t].end(), acc.begin() + (size_t)x * bb, acc.begin() + (size_t)(x + 1) * bb);
+            }
+            cnt[i] = (int64_t)cols.size();
+        }
+    });
+    P.ptr.assign(A.nr + 1, 0);
+    for (int64_t i = 0; i < A.nr; ++i) P.ptr[i + 1] = P.ptr[i] + cnt[i];
+    P.col.resize(P.ptr[A.nr]);
+    P.val.resize((size_t)P.ptr[A.nr] * bb);
+    for (int t = 0; t < nt; ++t) {
+        if (!used[t] || lo_of[t] >= hi_of[t]) continue;
+        int64_t off = P.ptr[lo_of[t]];
+        std::copy(tcol[t].begin(), tcol[t].end(), P.col.begin() + off);
+        std::copy(tval[t].begin(), tval[t].end(), P.val.begin() + (size_t)off * bb);
+    }
+    return P;
+}
+
+// ---------------------------------------------------------------------------
+// SELL packing
+// ---------------------------------------------------------------------------
+std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_t window) {
+    const int64_t n = (int64_t)ptr.size() - 1;
+    std::vector<int32_t> ord(n);
+    for (int64_t i = 0; i < n; ++i) ord[i] = (int32_t)i;
+    for (int64_t w0 = 0; w0 < n; w0 += window) {
+        int64_t w1 = std::min(n, w0 + window);
+        std::stable_sort(ord.begin() + w0, ord.begin() + w1, [&](int32_t a, int32_t b) {
+            return (ptr[a + 1] - ptr[a]) > (ptr[b + 1] - ptr[b]);
+        });
+    }
+    return ord;
+}
+
+void build_sell(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map,
+                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s) {
+    const int br = M.br, bc = M.bc, bb = br * bc;
+    S.br = br;
+    S.bc = bc;
+    S.nrows = M.nr;
+    S.ncols = M.nc;
+    S.nnzb = M.nnzb();
+    S.nslices = (M.nr + SELL_C - 1) / SELL_C;
+    std::vector<int32_t> off(S.nslices + 1, 0), rowlen(S.nslices * SELL_C, 0);
+    for (int64_t sl = 0; sl < S.nslices; ++sl) {
+        int64_t w = 0;
+        for (int l = 0; l < SELL_C; ++l) {
+            int64_t r = sl * SELL_C + l;
+            if (r >= M.nr) break;
+            int64_t o = row_order[r];
+            int64_t len = M.ptr[o + 1] - M.ptr[o];
+            rowlen[r] = (int32_t)len;
+            w = std::max(w, len);
+        }
+        TE_REQUIRE((int64_t)off[sl] + w < INT32_MAX, TE_EINVAL, "matrix too large for the SELL offsets");
+        off[sl + 1] = off[sl] + (int32_t)w;
+    }
+    const int64_t padded = (int64_t)off[S.nslices] * SELL_C;
+    S.padded = padded;
+    std::vector<int32_t> col(padded, 0);
+    std::vector<double> val((size_t)padded * bb, 0.0);
+    parallel_for(S.nslices, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t sl = lo; sl < hi; ++sl) {
+            const int64_t o0 = off[sl], w = off[sl + 1] - off[sl];
+            for (int l = 0; l < SELL_C; ++l) {
+                const int64_t r = sl * SELL_C + l;
+                int32_t last = 0;
+                const int64_t len = r < M.nr ? rowlen[r] : 0;
+                const int64_t orow = r < M.nr ? row_order[r] : 0;
+                for (int64_t k = 0; k < w; ++k) {
+                    const int64_t e = (o0 + k) * SELL_C + l;
+                    if (k < len) {
+                        const int64_t src = M.ptr[orow] + k;
+                        last = col_map[M.col[src]];
+                        for (int x = 0; x < bb; ++x)
+                            val[((o0 + k) * bb + x) * SELL_C + l] = M.val[(size_t)src * bb + x];
+                    }
+                    col[e] = last;
+                }
+            }
+        }
+    });
+    upload(S.slice_off, off, s);
+    upload(S.rowlen, rowlen, s);
+    upload(S.col, col, s);
+    upload(S.val, val, s);
+    if (fp32) {
+        std::vector<float> v32(val.size());
+        for (size_t i = 0; i < val.size(); ++i) v32[i] = (float)val[i];
+        upload(S.val32, v32, s);
+    } else {
+        S.val32.release();
+    }
+    if (out_map) {
+        std::vector<int32_t> rm(S.nslices * SELL_C, -1);
+        for (int64_t r = 0; r < M.nr; ++r) rm[r] = (*out_map)[row_order[r]];
+        upload(S.rowmap, rm, s);
+    } else {
+        S.rowmap.release();
+    }
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos estimate of the largest eigenvalue of D^-1/2 A D^-1/2 (device)
+// ---------------------------------------------------------------------------
+static double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b) {
+    const int m = (int)a.size();
+    if (m == 1) return a[0];
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = 0; i < m; ++i) {
+        double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    // number of eigenvalues < x (Sturm sequence of the LDL^T pivots)
+    auto count_below = [&](double x) {
+        int c = 0;
+        double d = a[0] - x;
+        if (d < 0) ++c;
+        for (int i = 1; i < m; ++i) {
+            double dd = d == 0.0 ? 1e-300 : d;
+            d = (a[i] - x) - b[i - 1] * b[i - 1] / dd;
+            if (d < 0) ++c;
+        }
+        return c;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (count_below(mid) < m) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+static double dev_dot(const double *x, const double *y, int64_t n, DBuf<double> &part, DBuf<double> &res,
+                      hipStream_t s) {
+    dot_partials(x, y, n, 1, part.p, s);
+    reduce_partials(part.p, dot_nblocks(n), 1, res.p, s);
+    double h = 0.0;
+    TE_CHECK_HIP(hipMemcpyAsync(&h, res.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+static double lanczos_estimate(const Level &L, int steps, uint64_t seed, hipStream_t s) {
+    const int64_t n = L.n * L.bs;
+    DBuf<double> v(n), vp(n), w(n), t(n), dh(n), part(dot_nblocks(n) + 1), res(1);
+    std::vector<double> dhh(n);
+    for (int64_t i = 0; i < n; ++i) dhh[i] = 1.0 / std::sqrt(L.dstore[i]);
+    TE_CHECK_HIP(hipMemcpyAsync(dh.p, dhh.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+    lanczos_start(v.p, L.perm.p, L.n, L.bs, seed, s);
+    double nv = std::sqrt(dev_dot(v.p, v.p, n, part, res, s));
+    scal(v.p, 1.0 / nv, n, s);
+    TE_CHECK_HIP(hipMemsetAsync(vp.p, 0, n * sizeof(double), s));
+    std::vector<double> al, be;
+    double beta_prev = 0.0;
+    for (int j = 0; j < steps; ++j) {
+        scale_mul(v.p, dh.p, t.p, n, s);
+        sell_apply<double>(L.A, t.p, w.p, nullptr, 0, 1, s);
+        lanczos_w(w.p, dh.p, vp.p, beta_prev, n, s);
+        double a = dev_dot(w.p, v.p, n, part, res, s);
+        axpy<double>(w.p, v.p, -a, n, s);
+        double b = std::sqrt(dev_dot(w.p, w.p, n, part, res, s));
+        al.push_back(a);
+        if (j == steps - 1 || b <= 1e-12 * (std::fabs(a) + beta_prev)) break;
+        be.push_back(b);
+        std::swap(vp.p, v.p);  // v_prev <- v
+        // v <- w / b
+        TE_CHECK_HIP(hipMemcpyAsync(v.p, w.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        scal(v.p, 1.0 / b, n, s);
+        beta_prev = b;
+    }
+    be.resize(al.size() > 0 ? al.size() - 1 : 0);
+    return tridiag_max_eig(al, be);
+}
+
+// ---------------------------------------------------------------------------
+// dense coarse factor
+// ---------------------------------------------------------------------------
+static void dense_inverse_spd(std::vector<double> &Mat, int n) {
+    // Cholesky M = L L^T (lower, row-major), then inverse = L^-T L^-1
+    for (int j = 0; j < n; ++j) {
+        double d = Mat[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= Mat[(size_t)j * n + k] * Mat[(size_t)j * n + k];
+        TE_REQUIRE(d > 0, TE_ECHOL, "coarse Cholesky: pivot %d is %g", j, d);
+        d = std::sqrt(d);
+        Mat[(size_t)j * n + j] = d;
+        parallel_for(n - j - 1, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t ii = lo; ii < hi; ++ii) {
+                const int i = j + 1 + (int)ii;
+                double v = Mat[(size_t)i * n + j];
+                const double *ri = &Mat[(size_t)i * n];
+                const double *rj = &Mat[(size_t)j * n];
+                for (int k = 0; k < j; ++k) v -= ri[k] * rj[k];
+                Mat[(size_t)i * n + j] = v / d;
+            }
+        });
+    }
+    // Linv (lower), column by column in parallel
+    std::vector<double> Li((size_t)n * n, 0.0);
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t c = lo; c < hi; ++c) {
+            for (int i = (int)c; i < n; ++i) {
+                double v = (i == c) ? 1.0 : 0.0;
+                for (int k = (int)c; k < i; ++k) v -= Mat[(size_t)i * n + k] * Li[(size_t)k * n + c];
+                Li[(size_t)i * n + c] = v / Mat[(size_t)i * n + i];
+            }
+        }
+    });
+    // inv[i][j] = sum_k Li[k][i] Li[k][j], k >= max(i,j)
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int j = 0; j < n; ++j) {
+                double v = 0.0;
+                for (int k = std::max((int)i, j); k < n; ++k) v += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+                Mat[(size_t)i * n + j] = v;
+            }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// the setup
+// ---------------------------------------------------------------------------
+static void rigid_body_modes(const std::vector<double> &X, const std::vector<uint8_t> &mask, int64_t n,
+                             std::vector<double> &B) {
+    double c[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) c[k] += X[i * 3 + k];
+    for (int k = 0; k < 3; ++k) c[k] /= (double)n;
+    B.assign((size_t)n * 3 * 6, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = X[i * 3] - c[0], y = X[i * 3 + 1] - c[1], z = X[i * 3 + 2] - c[2];
+        double *b = &B[(size_t)i * 18];
+        b[0 * 6 + 0] = 1;
+        b[1 * 6 + 1] = 1;
+        b[2 * 6 + 2] = 1;
+        b[0 * 6 + 3] = -y;
+        b[1 * 6 + 3] = x;
+        b[1 * 6 + 4] = -z;
+        b[2 * 6 + 4] = y;
+        b[0 * 6 + 5] = z;
+        b[2 * 6 + 5] = -x;
+        if (!mask.empty())
+            for (int p = 0; p < 3; ++p)
+                if (mask[i * 3 + p])
+                    for (int q = 0; q < 6; ++q) b[p * 6 + q] = 0.0;
+    }
+}
+
+static void finish_level(Level &L, const amg_options &o, hipStream_t s) {
+    // storage order and operator
+    L.perm_h = window_sorted_order(L.Ah.ptr, 4096);
+    L.iperm_h.assign(L.n, 0);
+    for (int64_t i = 0; i < L.n; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
+    build_sell(L.A, L.Ah, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s);
+    upload(L.perm, L.perm_h, s);
+    std::vector<double> dnat;
+    bsr_diag_points(L.Ah, dnat);
+    L.dstore.assign((size_t)L.n * L.bs, 0.0);
+    std::vector<double> dinv((size_t)L.n * L.bs);
+    std::vector<float> dinv32((size_t)L.n * L.bs);
+    for (int64_t i = 0; i < L.n; ++i)
+        for (int p = 0; p < L.bs; ++p) {
+            double d = dnat[(size_t)L.perm_h[i] * L.bs + p];
+            TE_REQUIRE(d > 0, TE_EINVAL, "non-positive diagonal entry %g at level %d row %lld", d, L.index,
+                       (long long)L.perm_h[i]);
+            L.dstore[i * L.bs + p] = d;
+            dinv[i * L.bs + p] = 1.0 / d;
+            dinv32[i * L.bs + p] = (float)(1.0 / d);
+        }
+    upload(L.dinv, dinv, s);
+    if (o.build_fp32) upload(L.dinv32, dinv32, s);
+}
+
+static void set_cheb(Level &L, const amg_options &o) {
+    const double b = o.cheb_safety * L.lam, a = b / o.cheb_ratio;
+    L.theta = 0.5 * (b + a);
+    L.delta = 0.5 * (b - a);
+    const double sigma = L.theta / L.delta;
+    double rho = 1.0 / sigma;
+    L.c1.clear();
+    L.c2.clear();
+    for (int k = 0; k + 1 < o.cheb_degree; ++k) {
+        double rn = 1.0 / (2.0 * sigma - rho);
+        L.c1.push_back(rn * rho);
+        L.c2.push_back(2.0 * rn / L.delta);
+        rho = rn;
+    }
+}
+
+static void alloc_work(amg_handle *h, hipStream_t) {
+    const int m = h->opt.max_nrhs;
+    for (auto &L : h->L) {
+        const size_t n = (size_t)L.n * L.bs * m;
+        L.w64.g.alloc(n);
+        L.w64.x.alloc(n);
+        L.w64.r.alloc(n);
+        L.w64.d.alloc(n);
+        L.w64.d2.alloc(n);
+        L.w64.s.alloc(n);
+        if (h->opt.build_fp32) {
+            L.w32.g.alloc(n);
+            L.w32.x.alloc(n);
+            L.w32.r.alloc(n);
+            L.w32.d.alloc(n);
+            L.w32.d2.alloc(n);
+            L.w32.s.alloc(n);
+        }
+    }
+    const size_t n0 = (size_t)h->L[0].n * 3 * m;
+    h->u.alloc(n0);
+    h->r.alloc(n0);
+    h->r_old.alloc(n0);
+    h->z.alloc(n0);
+    h->p.alloc(n0);
+    h->q.alloc(n0);
+    h->t.alloc(n0);
+    h->b.alloc(n0);
+    int np = std::max<int>(dot_nblocks(h->L[0].n * 3), (int)((h->L[0].A.nslices + 3) / 4 + 8));
+    np = std::max<int>(np, (int)((h->L[0].n + 3) / 4 + 8));
+    h->partials.alloc((size_t)np * m * 2 + 64);
+    h->sums.alloc(4 * 64);
+    h->scal.alloc(cg_scalars_bytes());
+}
+
+int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt_in,
+               const int32_t *const *agg_given, int n_given, amg_handle **out, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    TE_REQUIRE(A && coords && out, TE_EINVAL, "NULL argument");
+    TE_REQUIRE(A->n_brows > 0 && A->row_ptr && A->col_idx && A->val, TE_EINVAL, "empty or NULL matrix");
+    amg_options o;
+    if (opt_in) o = *opt_in;
+    else amg_options_default(&o);
+    TE_REQUIRE(o.max_nrhs >= 1 && o.max_nrhs <= 64, TE_EINVAL, "max_nrhs must be in 1..64");
+    TE_REQUIRE(o.cheb_degree >= 1 && o.cheb_degree <= 8, TE_EINVAL, "cheb_degree must be in 1..8");
+    TE_REQUIRE(o.max_levels >= 1 && o.max_levels <= 16, TE_EINVAL, "max_levels must be in 1..16");
+    TE_REQUIRE(o.lanczos_steps >= 1, TE_EINVAL, "lanczos_steps must be >= 1");
+    g_threads = o.host_threads;
+    auto h = std::make_unique<amg_handle>();
+    h->opt = o;
+    const int64_t n = A->n_brows;
+    // host copies
+    Level L0;
+    L0.index = 0;
+    L0.bs = 3;
+    L0.n = n;
+    L0.Ah.br = L0.Ah.bc = 3;
+    L0.Ah.nr = L0.Ah.nc = n;
+    download(L0.Ah.ptr, A->row_ptr, (size_t)n + 1, s);
+    TE_REQUIRE(L0.Ah.ptr[0] == 0 && L0.Ah.ptr[n] == A->nnzb, TE_EINVAL, "row_ptr inconsistent with nnzb");
+    download(L0.Ah.col, A->col_idx, (size_t)A->nnzb, s);
+    for (int64_t i = 0; i < n; ++i) {
+        TE_REQUIRE(L0.Ah.ptr[i + 1] >= L0.Ah.ptr[i], TE_EINVAL, "row_ptr decreases at row %lld", (long long)i);
+        bool diag = false;
+        for (int64_t k = L0.Ah.ptr[i]; k < L0.Ah.ptr[i + 1]; ++k) {
+            const int32_t c = L0.Ah.col[k];
+            TE_REQUIRE(c >= 0 && c < n, TE_EINVAL, "column index %d out of range in row %lld", c, (long long)i);
+            diag = diag || c == i;
+        }
+        TE_REQUIRE(diag, TE_EINVAL, "row %lld has no diagonal block", (long long)i);
+    }
+    download(L0.Ah.val, A->val, (size_t)A->nnzb * 9, s);
+    std::vector<double> X;
+    download(X, coords, (size_t)n * 3, s);
+    std::vector<uint8_t> mask;
+    if (dir_mask) download(mask, dir_mask, (size_t)n * 3, s);
+    std::vector<double> B;
+    rigid_body_modes(X, mask, n, B);
+    const int k = 6;
+    const bool verbose = std::getenv("TE_VERBOSE") != nullptr;
+    auto note = [&](const char *what, int l, int64_t nn, int64_t nz) {
+        if (!verbose) return;
+        double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        std::fprintf(stderr, "[te setup %7.2fs] level %d: %s (n=%lld, nnzb=%lld)\n", t, l, what, (long long)nn,
+                     (long long)nz);
+        std::fflush(stderr);
+    };
+    h->L.push_back(std::move(L0));
+    for (int l = 0;; ++l) {
+        Level &L = h->L[l];
+        note("pack operator", l, L.n, L.Ah.nnzb());
+        finish_level(L, o, s);
+        const int64_t ndof = L.n * L.bs;
+        if (ndof <= o.coarse_max || l == o.max_levels - 1) break;
+        L.lam = lanczos_estimate(L, o.lanczos_steps, 0x5EEDull + (uint64_t)l, s);
+        set_cheb(L, o);
+        const double theta = o.theta0 * std::ldexp(1.0, -l);
+        Strength S = strength_of(L.Ah);
+        std::vector<int32_t> agg;
+        int64_t na;
+        if (agg_given && l < n_given) {
+            TE_REQUIRE(agg_given[l], TE_EINVAL, "aggregate map of level %d is NULL", l);
+            agg.assign(agg_given[l], agg_given[l] + L.n);
+            na = 0;
+            for (int32_t a : agg) {
+                TE_REQUIRE(a >= -1 && a < L.n, TE_EINVAL, "aggregate id %d out of range at level %d", a, l);
+                na = std::max<int64_t>(na, (int64_t)a + 1);
+            }
+        } else {
+            na = greedy_aggregate(L.Ah, S, theta, agg);
+        }
+        if (na == 0) break;
+        note("aggregated", l, na, 0);
+        Tentative T = tentative(L.Ah, S, agg, na, B, L.bs, k);
+        std::vector<double> dnat;
+        bsr_diag_points(L.Ah, dnat);
+        HBsr P = smoothed_P(L.Ah, dnat, T, 4.0 / (3.0 * L.lam), k);
+        note("smoothed P", l, P.nr, P.nnzb());
+        HBsr AP = bsr_mult(L.Ah, P);
+        note("A P", l, AP.nr, AP.nnzb());
+        HBsr R = bsr_transpose(P);
+        HBsr Ac = bsr_mult(R, AP);
+        note("Galerkin", l, Ac.nr, Ac.nnzb());
+        AP = HBsr();
+        if ((double)Ac.nr * k > o.max_coarse_ratio * (double)ndof) break;
+        L.agg = T.agg;
+        L.Ph = std::move(P);
+        L.Rh = std::move(R);
+        Level N;
+        N.index = l + 1;
+        N.bs = k;
+        N.n = Ac.nr;
+        N.Ah = std::move(Ac);
+        B = T.Bc;
+        h->L.push_back(std::move(N));
+    }
+    // transfer operators (need the next level's storage order)
+    for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+        Level &L = h->L[l];
+        Level &N = h->L[l + 1];
+        auto pord = window_sorted_order(L.Ph.ptr, 4096);
+        build_sell(L.P, L.Ph, pord, N.iperm_h, &L.iperm_h, o.build_fp32 != 0, s);
+        auto rord = window_sorted_order(L.Rh.ptr, 4096);
+        build_sell(L.R, L.Rh, rord, L.iperm_h, &N.iperm_h, o.build_fp32 != 0, s);
+    }
+    note("transfer operators packed", (int)h->L.size() - 1, 0, 0);
+    // coarsest level: dense inverse of (A + A^T)/2 in storage order
+    {
+        Level &C = h->L.back();
+        C.lam = 0.0;
+        const int64_t nc = C.n * C.bs;
+        TE_REQUIRE(nc <= 12000, TE_EINVAL, "coarsest level has %lld DOF, too many for the dense factor",
+                   (long long)nc);
+        std::vector<double> M((size_t)nc * nc, 0.0);
+        const int b = C.bs;
+        for (int64_t i = 0; i < C.n; ++i)
+            for (int64_t kk = C.Ah.ptr[i]; kk < C.Ah.ptr[i + 1]; ++kk) {
+                const int64_t j = C.Ah.col[kk];
+                const int64_t si = C.iperm_h[i], sj = C.iperm_h[j];
+                for (int p = 0; p < b; ++p)
+                    for (int q = 0; q < b; ++q) {
+                        double v = 0.5 * C.Ah.val[(size_t)kk * b * b + p * b + q];
+                        M[(size_t)(si * b + p) * nc + sj * b + q] += v;
+                        M[(size_t)(sj * b + q) * nc + si * b + p] += v;
+                    }
+            }
+        dense_inverse_spd(M, (int)nc);
+        upload(h->Ainv, M, s);
+        h->nc = (int)nc;
+    }
+    note("coarse factor", (int)h->L.size() - 1, h->nc, 0);
+    alloc_work(h.get(), s);
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h.release();
+    return TE_OK;
+}
+
+}  // namespace te
+
+using namespace te;
+
+extern "C" const char *te_last_error(void) { return te::last_error(); }
+extern "C" int te_version(void) { return 100; }
+
+extern "C" void amg_options_default(amg_options *o) {
+    if (!o) return;
+    o->theta0 = 0.08;
+    o->coarse_max = 3000;
+    o->max_levels = 10;
+    o->lanczos_steps = 20;
+    o->cheb_degree = 2;
+    o->cheb_ratio = 10.0;
+    o->cheb_safety = 1.1;
+    o->max_coarse_ratio = 0.8;
+    o->build_fp32 = 1;
+    o->host_threads = 0;
+    o->max_nrhs = 1;
+}
+
+extern "C" int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,
+                         amg_handle **out, hipStream_t stream) {
+    return guarded([&] { return setup_impl(A, coords, dir_mask, opt, nullptr, 0, out, stream); });
+}
+
+extern "C" int amg_setup_with_aggregates(const te_bsr *A, const double *coords, const uint8_t *dir_mask,
+                                         const amg_options *opt, const int32_t *const *agg, int32_t n_levels_given,
+                                         amg_handle **out, hipStream_t stream) {
+    return guarded([&] {
+        TE_REQUIRE(agg || n_levels_given == 0, TE_EINVAL, "agg is NULL");
+        return setup_impl(A, coords, dir_mask, opt, agg, n_levels_given, out, stream);
+    });
+}
+
+extern "C" int amg_destroy(amg_handle *h) {
+    delete h;
+    return TE_OK;
+}
+
+extern "C" int amg_get_info(const amg_handle *h, amg_info *info) {
+    return guarded([&] {
+        TE_REQUIRE(h && info, TE_EINVAL, "NULL argument");
+        std::memset(info, 0, sizeof *info);
+        info->n_levels = (int32_t)h->L.size();
+        int64_t bytes = h->Ainv.bytes();
+        for (size_t l = 0; l < h->L.size() && l < 16; ++l) {
+            const Level &L = h->L[l];
+            info->n_dof[l] = L.n * L.bs;
+            info->nnzb[l] = L.Ah.nnzb();
+            info->bs[l] = L.bs;
+            info->lambda_hat[l] = L.lam;
+            info->p_nnzb[l] = L.Ph.nnzb();
+            bytes += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() + L.perm.bytes();
+        }
+        info->setup_ms = h->setup_ms;
+        info->bytes_device = bytes;
+        return TE_OK;
+    });
+}
+
+extern "C" int amg_get_aggregates(const amg_handle *h, int32_t level, int32_t *agg_host) {
+    return guarded([&] {
+        TE_REQUIRE(h && agg_host, TE_EINVAL, "NULL argument");
+        TE_REQUIRE(level >= 0 && level + 1 < (int)h->L.size(), TE_EINVAL, "level %d has no aggregates", level);
+        std::copy(h->L[level].agg.begin(), h->L[level].agg.end(), agg_host);
+        return TE_OK;
+    });
+}
+
+extern "C" int amg_get_level_matrix(const amg_handle *h, int32_t level, int64_t *n_rows_out, int64_t *nnzb_out,
+                                    int64_t *row_ptr, int32_t *col, double *val) {
+    return guarded([&] {
+        TE_REQUIRE(h && n_rows_out && nnzb_out, TE_EINVAL, "NULL argument");
+        TE_REQUIRE(level >= 0 && level < (int)h->L.size(), TE_EINVAL, "bad level %d", level);
+        const HBsr &M = h->L[level].Ah;
+        *n_rows_out = M.nr;
+        *nnzb_out = M.nnzb();
+        if (row_ptr) std::copy(M.ptr.begin(), M.ptr.end(), row_ptr);
+        if (col) std::copy(M.col.begin(), M.col.end(), col);
+        if (val) std::copy(M.val.begin(), M.val.end(), val);
+        return TE_OK;
+    });
+}

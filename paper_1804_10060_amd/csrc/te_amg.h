@@ -1,0 +1,89 @@
+// Hierarchy data structures shared by the setup and the solve.
+#pragma once
+
+#include <functional>
+#include <memory>
+
+#include "te_internal.h"
+
+namespace te {
+
+template <typename T>
+struct Work {
+    DBuf<T> g, x, r, d, d2, s;
+};
+
+struct Level {
+    int index = 0;
+    int bs = 3;                    // block size (3 on the mesh level, 6 below)
+    int64_t n = 0;                 // block rows
+    HBsr Ah;                       // operator, natural numbering (host)
+    HBsr Ph, Rh;                   // transfer to the next level, natural numbering (host)
+    std::vector<int32_t> agg;      // aggregate of each node (natural), -1 isolated
+    std::vector<int32_t> perm_h;   // storage position -> natural index
+    std::vector<int32_t> iperm_h;  // natural index -> storage position
+    std::vector<double> dstore;    // point diagonal in storage order
+    Sell A, P, R;                  // device operators, storage numbering
+    DBuf<int32_t> perm;
+    DBuf<double> dinv;
+    DBuf<float> dinv32;
+    double lam = 0.0;              // largest-eigenvalue estimate of D^-1 A
+    double theta = 0.0, delta = 0.0;
+    std::vector<double> c1, c2;    // Chebyshev step coefficients
+    Work<double> w64;
+    Work<float> w32;
+};
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &fn);
+int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,
+               const int32_t *const *agg_given, int n_given, amg_handle **out, hipStream_t s);
+
+}  // namespace te
+
+namespace te {
+// Event pairs around kernel launches, one list per kernel class.
+struct Prof {
+    bool on = false;
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> ev[TE_K_COUNT];
+    int used[TE_K_COUNT] = {};
+    void reset(bool enable, hipStream_t st) {
+        on = enable;
+        s = st;
+        for (int c = 0; c < TE_K_COUNT; ++c) used[c] = 0;
+    }
+    void begin(int c) {
+        if (!on) return;
+        if ((int)ev[c].size() < 2 * (used[c] + 1)) {
+            hipEvent_t a, b;
+            TE_CHECK_HIP(hipEventCreate(&a));
+            TE_CHECK_HIP(hipEventCreate(&b));
+            ev[c].push_back(a);
+            ev[c].push_back(b);
+        }
+        TE_CHECK_HIP(hipEventRecord(ev[c][2 * used[c]], s));
+    }
+    void end(int c) {
+        if (!on) return;
+        TE_CHECK_HIP(hipEventRecord(ev[c][2 * used[c] + 1], s));
+        ++used[c];
+    }
+    ~Prof() {
+        for (auto &v : ev)
+            for (auto e : v) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace te
+
+struct amg_handle {
+    amg_options opt;
+    te::Prof prof;
+    std::vector<te::Level> L;
+    te::DBuf<double> Ainv;         // coarsest level: dense inverse, storage order
+    int nc = 0;
+    double setup_ms = 0.0;
+    // solve workspace (level-0 storage order, [n][3][nrhs])
+    te::DBuf<double> u, r, r_old, z, p, q, t, b;
+    te::DBuf<double> partials, sums;
+    te::DBuf<char> scal;
+};

@@ -1,0 +1,543 @@
+// Finite-element assembly of the thermoelastic system (weak form wf_elastic,
+// Sec. 3.1) into 3x3-block compressed rows, and Dirichlet elimination.
+//
+// Gather formulation: one thread owns one node row.  It walks the cells that
+// contain the node (ascending cell id, so the summation order is fixed and
+// the result deterministic), evaluates that node's rows of the element
+// tensors and adds them into its own blocks; nothing is scattered, so no
+// atomics touch the values.  Element integrals:
+//   stiffness  P1: constant gradients (one-point exact); P2: degree-2
+//              integrand, 4-point rule (a,b,b,b), a = (5+3 sqrt5)/20,
+//              b = (5-sqrt5)/20, weights 1/4 (exact for degree 2);
+//   thermal    P1: centroid rule (degree 1 exact); P2: degree-3 integrand,
+//              5-point rule with barycentric points (1/4,...) weight -4/5 and
+//              the permutations of (1/2,1/6,1/6,1/6) weight 9/20 (exact for
+//              degree 3);
+//   body force consistent mass: P1 |K|(1+delta_ac)/20; P2 the closed-form
+//              10-node mass matrix (|K|/420: 6/1 vertex-vertex, -4/-6
+//              vertex-edge, 32/16/8 edge-edge).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <numeric>
+
+#include "te_internal.h"
+
+namespace te {
+
+constexpr int ABLK = 64;
+constexpr int PCAP = 192;  // maximum distinct neighbours of one node
+
+__constant__ int c_edge[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+// ---------------------------------------------------------------------------
+// node -> (cell, local index) incidence
+// ---------------------------------------------------------------------------
+__global__ void k_check_cells(const int32_t *__restrict__ cells, int64_t n_entries, int64_t n_nodes,
+                              int32_t *__restrict__ bad) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_entries; t += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = cells[t];
+        if (v < 0 || v >= n_nodes) *bad = 1;
+    }
+}
+
+__global__ void k_inc_count(const int32_t *__restrict__ cells, int64_t n_entries, int32_t *__restrict__ cnt) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_entries; t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[cells[t]], 1);
+}
+
+__global__ void k_inc_fill(const int32_t *__restrict__ cells, int64_t n_entries, const int64_t *__restrict__ start,
+                           int32_t *__restrict__ fill, int64_t *__restrict__ inc) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n_entries; t += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = cells[t];
+        int32_t k = atomicAdd(&fill[v], 1);
+        inc[start[v] + k] = t;  // t = cell * npe + local
+    }
+}
+
+// per node: sort its incidence entries ascending (insertion sort, short lists)
+__global__ void k_inc_sort(const int64_t *__restrict__ start, int64_t *__restrict__ inc, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = start[i], hi = start[i + 1];
+        for (int64_t a = lo + 1; a < hi; ++a) {
+            int64_t v = inc[a];
+            int64_t b = a - 1;
+            while (b >= lo && inc[b] > v) {
+                inc[b + 1] = inc[b];
+                --b;
+            }
+            inc[b + 1] = v;
+        }
+    }
+}
+
+// Exclusive scan of int32 counts into int64 offsets (out[0] = 0, out[n] = total),
+// three phases with fixed-size blocks.
+__global__ void k_scan_block(const int32_t *__restrict__ in, int64_t *__restrict__ out, int64_t n,
+                             int64_t *__restrict__ block_sums) {
+    __shared__ int64_t s[1024];
+    int64_t base = (int64_t)blockIdx.x * 1024;
+    int64_t i = base + threadIdx.x;
+    s[threadIdx.x] = (i < n) ? (int64_t)in[i] : 0;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int64_t v = (threadIdx.x >= (unsigned)o) ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (i < n) out[i + 1] = s[threadIdx.x];  // inclusive -> shifted
+    if (threadIdx.x == 1023) block_sums[blockIdx.x] = s[1023];
+}
+__global__ void k_scan_add(int64_t *__restrict__ out, int64_t n, const int64_t *__restrict__ block_off) {
+    int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i < n) out[i + 1] += block_off[blockIdx.x];
+    if (i == 0) out[0] = 0;
+}
+
+static void scan_counts(const int32_t *cnt, int64_t *out, int64_t n, hipStream_t s) {
+    int64_t nb = (n + 1023) / 1024;
+    DBuf<int64_t> bs(std::max<int64_t>(nb, 1));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(1024), 0, s, cnt, out, n, bs.p);
+        TE_CHECK_HIP(hipGetLastError());
+    }
+    std::vector<int64_t> h;
+    download(h, bs.p, (size_t)nb, s);
+    std::vector<int64_t> off(nb, 0);
+    for (int64_t b = 1; b < nb; ++b) off[b] = off[b - 1] + h[b - 1];
+    DBuf<int64_t> doff;
+    upload(doff, off, s);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(1024), 0, s, out, n, doff.p);
+        TE_CHECK_HIP(hipGetLastError());
+    } else {
+        TE_CHECK_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+    }
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+struct Incidence {
+    DBuf<int64_t> start;  // [N+1]
+    DBuf<int64_t> inc;    // [C*npe] entries cell*npe + local, ascending per node
+};
+
+static void build_incidence(const te_mesh *m, int npe, Incidence &I, hipStream_t s) {
+    const int64_t n = m->n_nodes, ne = m->n_cells * (int64_t)npe;
+    DBuf<int32_t> bad(1);
+    TE_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    unsigned g = (unsigned)std::min<int64_t>((ne + 255) / 256 + 1, 1 << 20);
+    hipLaunchKernelGGL(k_check_cells, dim3(g), dim3(256), 0, s, m->cells, ne, n, bad.p);
+    TE_CHECK_HIP(hipGetLastError());
+    int32_t hb = 0;
+    TE_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    TE_REQUIRE(hb == 0, TE_EINVAL, "cells reference a node index outside [0, n_nodes)");
+    DBuf<int32_t> cnt(n);
+    TE_CHECK_HIP(hipMemsetAsync(cnt.p, 0, n * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_inc_count, dim3(g), dim3(256), 0, s, m->cells, ne, cnt.p);
+    TE_CHECK_HIP(hipGetLastError());
+    I.start.alloc(n + 1);
+    scan_counts(cnt.p, I.start.p, n, s);
+    TE_CHECK_HIP(hipMemsetAsync(cnt.p, 0, n * sizeof(int32_t), s));
+    I.inc.alloc(std::max<int64_t>(ne, 1));
+    hipLaunchKernelGGL(k_inc_fill, dim3(g), dim3(256), 0, s, m->cells, ne, I.start.p, cnt.p, I.inc.p);
+    TE_CHECK_HIP(hipGetLastError());
+    unsigned gn = (unsigned)std::min<int64_t>((n + 255) / 256 + 1, 1 << 20);
+    hipLaunchKernelGGL(k_inc_sort, dim3(gn), dim3(256), 0, s, I.start.p, I.inc.p, n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// sparsity pattern
+// ---------------------------------------------------------------------------
+// Sorted distinct neighbours of node i in an LDS list (thread-private slice).
+// mode 0: write count to cnt[i]; mode 1: write the list to col[row_ptr[i]..].
+__global__ void __launch_bounds__(ABLK) k_pattern(const int32_t *__restrict__ cells, int npe,
+                                                  const int64_t *__restrict__ start, const int64_t *__restrict__ inc,
+                                                  int64_t n, int mode, int32_t *__restrict__ cnt,
+                                                  const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col,
+                                                  int32_t *__restrict__ overflow) {
+    __shared__ int32_t lst[ABLK * PCAP];
+    int64_t i = (int64_t)blockIdx.x * ABLK + threadIdx.x;
+    if (i >= n) return;
+    int32_t *L = lst + threadIdx.x;  // strided by ABLK to spread banks
+    int len = 0;
+    bool over = false;
+    for (int64_t e = start[i]; e < start[i + 1] && !over; ++e) {
+        const int64_t cell = inc[e] / npe;
+        for (int b = 0; b < npe; ++b) {
+            int32_t v = cells[cell * npe + b];
+            // binary search for v in L[0..len)
+            int lo = 0, hi = len;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (L[mid * ABLK] < v) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < len && L[lo * ABLK] == v) continue;
+            if (len == PCAP) {
+                over = true;
+                break;
+            }
+            for (int k = len; k > lo; --k) L[k * ABLK] = L[(k - 1) * ABLK];
+            L[lo * ABLK] = v;
+            ++len;
+        }
+    }
+    if (over) {
+        *overflow = 1;
+        return;
+    }
+    if (mode == 0) {
+        cnt[i] = len;
+    } else {
+        // row_ptr comes from the caller: never write past its row
+        if (row_ptr[i + 1] - row_ptr[i] != len) {
+            *overflow = 2;
+            return;
+        }
+        int32_t *o = col + row_ptr[i];
+        for (int k = 0; k < len; ++k) o[k] = L[k * ABLK];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element integrals
+// ---------------------------------------------------------------------------
+struct Geo {
+    double G[4][3];  // gradient of barycentric coordinate k
+    double vol;
+};
+
+__device__ __forceinline__ Geo cell_geo(const double *__restrict__ X, const int32_t *__restrict__ cv) {
+    double x0[3], J[3][3];
+    for (int c = 0; c < 3; ++c) x0[c] = X[(int64_t)cv[0] * 3 + c];
+    for (int k = 0; k < 3; ++k)
+        for (int c = 0; c < 3; ++c) J[c][k] = X[(int64_t)cv[k + 1] * 3 + c] - x0[c];  // columns = edges
+    // inverse via cofactors: rows of J^-1 are the gradients of l1..l3
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    double id = 1.0 / det;
+    Geo g;
+    g.G[1][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    g.G[1][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    g.G[1][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    g.G[2][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    g.G[2][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    g.G[2][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    g.G[3][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    g.G[3][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    g.G[3][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    for (int c = 0; c < 3; ++c) g.G[0][c] = -(g.G[1][c] + g.G[2][c] + g.G[3][c]);
+    g.vol = fabs(det) / 6.0;
+    return g;
+}
+
+// gradient of the P2 basis function a at barycentric point l
+__device__ __forceinline__ void p2_grad(int a, const double l[4], const Geo &g, double out[3]) {
+    if (a < 4) {
+        double s = 4.0 * l[a] - 1.0;
+        for (int c = 0; c < 3; ++c) out[c] = s * g.G[a][c];
+    } else {
+        int i = c_edge[a - 4][0], j = c_edge[a - 4][1];
+        for (int c = 0; c < 3; ++c) out[c] = 4.0 * (l[j] * g.G[i][c] + l[i] * g.G[j][c]);
+    }
+}
+
+__device__ __forceinline__ double p2_val(int a, const double l[4]) {
+    if (a < 4) return l[a] * (2.0 * l[a] - 1.0);
+    return 4.0 * l[c_edge[a - 4][0]] * l[c_edge[a - 4][1]];
+}
+
+// closed-form P2 mass matrix times 420/|K|
+__device__ __forceinline__ double p2_mass420(int a, int c) {
+    if (a < 4 && c < 4) return a == c ? 6.0 : 1.0;
+    if (a >= 4 && c >= 4) {
+        if (a == c) return 32.0;
+        int i0 = c_edge[a - 4][0], i1 = c_edge[a - 4][1], j0 = c_edge[c - 4][0], j1 = c_edge[c - 4][1];
+        bool share = (i0 == j0) || (i0 == j1) || (i1 == j0) || (i1 == j1);
+        return share ? 16.0 : 8.0;
+    }
+    int v = a < 4 ? a : c, e = a < 4 ? c : a;
+    bool contains = (c_edge[e - 4][0] == v) || (c_edge[e - 4][1] == v);
+    return contains ? -4.0 : -6.0;
+}
+
+__device__ __forceinline__ int64_t find_col(const int32_t *__restrict__ cols, int64_t lo, int64_t hi, int32_t v) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (cols[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+struct AsmArgs {
+    const double *X;
+    const int32_t *cells;
+    int npe;
+    const int64_t *start;
+    const int64_t *inc;
+    int64_t n;
+    double lam, mu, calpha, T_ref;
+    const double *T;   // [nrhs][N]
+    const double *f;   // [nrhs][N][3] or null
+    const int64_t *row_ptr;
+    const int32_t *col;
+    double *val;       // null: load only
+    double *b;         // [N][3][nrhs]
+    int nrhs;
+};
+
+// Stiffness rows of node i (if val) and its load for right-hand side j.
+template <int DEG>
+__global__ void __launch_bounds__(ABLK) k_assemble(AsmArgs A, int j) {
+    const int64_t i = (int64_t)blockIdx.x * ABLK + threadIdx.x;
+    if (i >= A.n) return;
+    constexpr int NPE = DEG == 1 ? 4 : 10;
+    const int64_t r0 = A.row_ptr ? A.row_ptr[i] : 0, r1 = A.row_ptr ? A.row_ptr[i + 1] : 0;
+    const double *T = A.T + (int64_t)j * A.n;
+    const double *f = A.f ? A.f + (int64_t)j * A.n * 3 : nullptr;
+    double bi[3] = {0.0, 0.0, 0.0};
+    for (int64_t e = A.start[i]; e < A.start[i + 1]; ++e) {
+        const int64_t cell = A.inc[e] / NPE;
+        const int a = (int)(A.inc[e] % NPE);
+        const int32_t *cv = A.cells + cell * NPE;
+        const Geo g = cell_geo(A.X, cv);
+        double dT[NPE];
+        for (int c = 0; c < NPE; ++c) dT[c] = T[cv[c]] - A.T_ref;
+        if (DEG == 1) {
+            // thermal: (3 lam + 2 mu) alpha |K| mean(dT) grad l_a
+            double mT = 0.25 * (dT[0] + dT[1] + dT[2] + dT[3]);
+            for (int c = 0; c < 3; ++c) bi[c] += A.calpha * g.vol * mT * g.G[a][c];
+            if (f)
+                for (int c = 0; c < 4; ++c) {
+                    double m = g.vol * (c == a ? 2.0 : 1.0) / 20.0;
+                    for (int k = 0; k < 3; ++k) bi[k] += m * f[(int64_t)cv[c] * 3 + k];
+                }
+            if (A.val) {
+                const double *ga = g.G[a];
+                for (int bb = 0; bb < 4; ++bb) {
+                    const double *gb = g.G[bb];
+                    double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                    int64_t pos = find_col(A.col, r0, r1, cv[bb]);
+                    if (pos >= r1 || A.col[pos] != cv[bb]) continue;  // unreachable with a matching pattern
+                    double *blk = A.val + pos * 9;
+                    for (int p = 0; p < 3; ++p)
+                        for (int q = 0; q < 3; ++q)
+                            blk[p * 3 + q] += g.vol * (A.lam * ga[p] * gb[q] + A.mu * ga[q] * gb[p] +
+                                                       (p == q ? A.mu * dot : 0.0));
+                }
+            }
+        } else {
+            // thermal load, degree-3 exact 5-point rule
+            {
+                const double w5[5] = {-0.8, 0.45, 0.45, 0.45, 0.45};
+                for (int qp = 0; qp < 5; ++qp) {
+                    double l[4];
+                    if (qp == 0) {
+                        l[0] = l[1] = l[2] = l[3] = 0.25;
+                    } else {
+                        for (int k = 0; k < 4; ++k) l[k] = 1.0 / 6.0;
+                        l[qp - 1] = 0.5;
+                    }
+                    double Tq = 0.0;
+                    for (int c = 0; c < 10; ++c) Tq += dT[c] * p2_val(c, l);
+                    double gr[3];
+                    p2_grad(a, l, g, gr);
+                    for (int c = 0; c < 3; ++c) bi[c] += A.calpha * w5[qp] * g.vol * Tq * gr[c];
+                }
+            }
+            if (f)
+                for (int c = 0; c < 10; ++c) {
+                    double m = g.vol * p2_mass420(a, c) / 420.0;
+                    for (int k = 0; k < 3; ++k) bi[k] += m * f[(int64_t)cv[c] * 3 + k];
+                }
+            if (A.val) {
+                const double qa = 0.5854101966249685, qb = 0.1381966011250105;
+                double ga[4][3];
+                double lq[4][4];
+                for (int qp = 0; qp < 4; ++qp) {
+                    for (int k = 0; k < 4; ++k) lq[qp][k] = (k == qp) ? qa : qb;
+                    p2_grad(a, lq[qp], g, ga[qp]);
+                }
+                const double w = 0.25 * g.vol;
+                for (int bb = 0; bb < 10; ++bb) {
+                    double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                    for (int qp = 0; qp < 4; ++qp) {
+                        double gb[3];
+                        p2_grad(bb, lq[qp], g, gb);
+                        double dot = ga[qp][0] * gb[0] + ga[qp][1] * gb[1] + ga[qp][2] * gb[2];
+                        for (int p = 0; p < 3; ++p)
+                            for (int q = 0; q < 3; ++q)
+                                K[p * 3 + q] += A.lam * ga[qp][p] * gb[q] + A.mu * ga[qp][q] * gb[p] +
+                                                (p == q ? A.mu * dot : 0.0);
+                    }
+                    int64_t pos = find_col(A.col, r0, r1, cv[bb]);
+                    if (pos >= r1 || A.col[pos] != cv[bb]) continue;  // unreachable with a matching pattern
+                    double *blk = A.val + pos * 9;
+                    for (int k = 0; k < 9; ++k) blk[k] += w * K[k];
+                }
+            }
+        }
+    }
+    for (int c = 0; c < 3; ++c) A.b[(i * 3 + c) * A.nrhs + j] = bi[c];
+}
+
+// Dirichlet elimination, one thread per row.  Lifting with the unconstrained
+// values first, then rows/columns of constrained DOFs zeroed, unit diagonal,
+// b_D = u_D.
+__global__ void k_dirichlet(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                            double *__restrict__ val, double *__restrict__ b, const uint8_t *__restrict__ mask,
+                            const double *__restrict__ ubc) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        bool mi[3] = {mask[i * 3] != 0, mask[i * 3 + 1] != 0, mask[i * 3 + 2] != 0};
+        double bi[3] = {b[i * 3], b[i * 3 + 1], b[i * 3 + 2]};
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int64_t J = col[k];
+            double *blk = val + k * 9;
+            for (int q = 0; q < 3; ++q) {
+                if (!mask[J * 3 + q]) continue;
+                double u = ubc ? ubc[J * 3 + q] : 0.0;
+                for (int p = 0; p < 3; ++p) bi[p] -= blk[p * 3 + q] * u;
+            }
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q)
+                    if (mi[p] || mask[J * 3 + q]) blk[p * 3 + q] = (J == i && p == q) ? 1.0 : 0.0;
+        }
+        for (int p = 0; p < 3; ++p) b[i * 3 + p] = mi[p] ? (ubc ? ubc[i * 3 + p] : 0.0) : bi[p];
+    }
+}
+
+// load-only variant: constrained entries set to zero (u_bc = 0, no lifting needed)
+__global__ void k_zero_masked(int64_t n, int nrhs, double *__restrict__ b, const uint8_t *__restrict__ mask) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n * 3 * nrhs; t += (int64_t)gridDim.x * blockDim.x)
+        if (mask[t / nrhs]) b[t] = 0.0;
+}
+
+static void check_mesh(const te_mesh *m) {
+    TE_REQUIRE(m, TE_EINVAL, "mesh is NULL");
+    TE_REQUIRE(m->degree == 1 || m->degree == 2, TE_EINVAL, "degree must be 1 or 2 (got %d)", m->degree);
+    TE_REQUIRE(m->n_nodes > 0 && m->n_cells > 0, TE_EINVAL, "empty mesh");
+    TE_REQUIRE(m->n_nodes < (int64_t)INT32_MAX, TE_EINVAL, "too many nodes for 32-bit indices");
+    TE_REQUIRE(m->coords && m->cells, TE_EINVAL, "mesh arrays are NULL");
+}
+
+static void pattern_impl(const te_mesh *m, Incidence &I, int64_t *row_ptr, int32_t *col, hipStream_t s) {
+    const int npe = m->degree == 1 ? 4 : 10;
+    const int64_t n = m->n_nodes;
+    DBuf<int32_t> ovf(1);
+    TE_CHECK_HIP(hipMemsetAsync(ovf.p, 0, sizeof(int32_t), s));
+    unsigned g = (unsigned)((n + ABLK - 1) / ABLK);
+    if (!col) {
+        DBuf<int32_t> cnt(n);
+        hipLaunchKernelGGL(k_pattern, dim3(g), dim3(ABLK), 0, s, m->cells, npe, I.start.p, I.inc.p, n, 0, cnt.p,
+                           nullptr, nullptr, ovf.p);
+        TE_CHECK_HIP(hipGetLastError());
+        int32_t h = 0;
+        TE_CHECK_HIP(hipMemcpyAsync(&h, ovf.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+        TE_REQUIRE(h == 0, TE_EINVAL, "a node couples to more than %d nodes", PCAP);
+        scan_counts(cnt.p, row_ptr, n, s);
+    } else {
+        hipLaunchKernelGGL(k_pattern, dim3(g), dim3(ABLK), 0, s, m->cells, npe, I.start.p, I.inc.p, n, 1, nullptr,
+                           row_ptr, col, ovf.p);
+        TE_CHECK_HIP(hipGetLastError());
+        int32_t h = 0;
+        TE_CHECK_HIP(hipMemcpyAsync(&h, ovf.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+        TE_REQUIRE(h == 0, TE_EINVAL, h == 1 ? "a node couples to more than 192 nodes"
+                                             : "row_ptr does not match this mesh's sparsity pattern");
+    }
+}
+
+}  // namespace te
+
+using namespace te;
+
+extern "C" int fe_assemble_pattern(const te_mesh *mesh, int64_t *row_ptr, int64_t *nnzb_out, hipStream_t stream) {
+    return guarded([&]() -> int {
+        check_mesh(mesh);
+        TE_REQUIRE(row_ptr && nnzb_out, TE_EINVAL, "row_ptr / nnzb_out is NULL");
+        Incidence I;
+        build_incidence(mesh, mesh->degree == 1 ? 4 : 10, I, stream);
+        pattern_impl(mesh, I, row_ptr, nullptr, stream);
+        TE_CHECK_HIP(hipMemcpyAsync(nnzb_out, row_ptr + mesh->n_nodes, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        TE_CHECK_HIP(hipStreamSynchronize(stream));
+        return TE_OK;
+    });
+}
+
+static void material_consts(const te_material *mat, double &lam, double &mu, double &calpha) {
+    TE_REQUIRE(mat, TE_EINVAL, "material is NULL");
+    TE_REQUIRE(mat->E > 0 && mat->nu > -1.0 && mat->nu < 0.5, TE_EINVAL, "invalid E / nu");
+    lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
+    mu = mat->E / (2.0 * (1.0 + mat->nu));
+    calpha = (3.0 * lam + 2.0 * mu) * mat->alpha;
+}
+
+extern "C" int fe_assemble_thermoelastic(const te_mesh *mesh, const te_material *mat, const double *T,
+                                         const double *f, const uint8_t *dir_mask, const double *u_bc, te_bsr *A,
+                                         double *b, hipStream_t stream) {
+    return guarded([&]() -> int {
+        check_mesh(mesh);
+        TE_REQUIRE(T && b && A && A->row_ptr && A->col_idx && A->val, TE_EINVAL, "NULL array argument");
+        TE_REQUIRE(A->n_brows == mesh->n_nodes, TE_EINVAL, "A.n_brows != n_nodes");
+        double lam, mu, calpha;
+        material_consts(mat, lam, mu, calpha);
+        const int npe = mesh->degree == 1 ? 4 : 10;
+        Incidence I;
+        build_incidence(mesh, npe, I, stream);
+        int64_t nnzb = 0;
+        TE_CHECK_HIP(hipMemcpyAsync(&nnzb, A->row_ptr + mesh->n_nodes, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        TE_CHECK_HIP(hipStreamSynchronize(stream));
+        TE_REQUIRE(nnzb == A->nnzb, TE_EINVAL, "A.nnzb (%lld) != row_ptr[N] (%lld)", (long long)A->nnzb,
+                   (long long)nnzb);
+        pattern_impl(mesh, I, A->row_ptr, A->col_idx, stream);
+        TE_CHECK_HIP(hipMemsetAsync(A->val, 0, (size_t)nnzb * 9 * sizeof(double), stream));
+        AsmArgs a{mesh->coords, mesh->cells, npe, I.start.p, I.inc.p, mesh->n_nodes, lam, mu, calpha, mat->T_ref,
+                  T, f, A->row_ptr, A->col_idx, A->val, b, 1};
+        unsigned g = (unsigned)((mesh->n_nodes + ABLK - 1) / ABLK);
+        if (mesh->degree == 1) hipLaunchKernelGGL(k_assemble<1>, dim3(g), dim3(ABLK), 0, stream, a, 0);
+        else hipLaunchKernelGGL(k_assemble<2>, dim3(g), dim3(ABLK), 0, stream, a, 0);
+        TE_CHECK_HIP(hipGetLastError());
+        if (dir_mask) {
+            unsigned gd = (unsigned)std::min<int64_t>((mesh->n_nodes + 255) / 256, 1 << 20);
+            hipLaunchKernelGGL(k_dirichlet, dim3(gd), dim3(256), 0, stream, mesh->n_nodes, A->row_ptr, A->col_idx,
+                               A->val, b, dir_mask, u_bc);
+            TE_CHECK_HIP(hipGetLastError());
+        }
+        TE_CHECK_HIP(hipStreamSynchronize(stream));
+        return TE_OK;
+    });
+}
+
+extern "C" int fe_assemble_load(const te_mesh *mesh, const te_material *mat, const double *T, const double *f,
+                                const uint8_t *dir_mask, int32_t nrhs, double *b, hipStream_t stream) {
+    return guarded([&]() -> int {
+        check_mesh(mesh);
+        TE_REQUIRE(T && b, TE_EINVAL, "NULL array argument");
+        TE_REQUIRE(nrhs >= 1 && nrhs <= 64, TE_EINVAL, "nrhs must be in 1..64");
+        double lam, mu, calpha;
+        material_consts(mat, lam, mu, calpha);
+        const int npe = mesh->degree == 1 ? 4 : 10;
+        Incidence I;
+        build_incidence(mesh, npe, I, stream);
+        AsmArgs a{mesh->coords, mesh->cells, npe, I.start.p, I.inc.p, mesh->n_nodes, lam, mu, calpha, mat->T_ref,
+                  T, f, nullptr, nullptr, nullptr, b, nrhs};
+        unsigned g = (unsigned)((mesh->n_nodes + ABLK - 1) / ABLK);
+        for (int j = 0; j < nrhs; ++j) {
+            if (mesh->degree == 1) hipLaunchKernelGGL(k_assemble<1>, dim3(g), dim3(ABLK), 0, stream, a, j);
+            else hipLaunchKernelGGL(k_assemble<2>, dim3(g), dim3(ABLK), 0, stream, a, j);
+            TE_CHECK_HIP(hipGetLastError());
+        }
+        if (dir_mask) {
+            unsigned gd = (unsigned)std::min<int64_t>((mesh->n_nodes * 3 * nrhs + 255) / 256, 1 << 20);
+            hipLaunchKernelGGL(k_zero_masked, dim3(gd), dim3(256), 0, stream, mesh->n_nodes, nrhs, b, dir_mask);
+            TE_CHECK_HIP(hipGetLastError());
+        }
+        TE_CHECK_HIP(hipStreamSynchronize(stream));
+        return TE_OK;
+    });
+}

@@ -1,0 +1,202 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "te.h"
+
+namespace te {
+
+// ---- error handling ------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+struct Error {
+    int code;
+};
+
+#define TE_CHECK_HIP(expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            ::te::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                            __LINE__);                                                      \
+            throw ::te::Error{TE_EHIP};                                                     \
+        }                                                                                   \
+    } while (0)
+
+#define TE_REQUIRE(cond, code, ...)     \
+    do {                                \
+        if (!(cond)) {                  \
+            ::te::set_error(__VA_ARGS__); \
+            throw ::te::Error{code};    \
+        }                               \
+    } while (0)
+
+// Runs f() and converts library exceptions into return codes.
+template <class F>
+int guarded(F &&f) {
+    try {
+        clear_error();
+        return f();
+    } catch (const Error &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return TE_ENOMEM;
+    }
+}
+
+// ---- device memory -------------------------------------------------------
+// Owning device buffer (hipMalloc / hipFree).
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&p), count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            set_error("hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+            throw Error{TE_ENOMEM};
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+template <class T>
+void upload(DBuf<T> &d, const std::vector<T> &h, hipStream_t s) {
+    d.alloc(h.size());
+    if (!h.empty()) TE_CHECK_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+template <class T>
+void download(std::vector<T> &h, const T *d, size_t n, hipStream_t s) {
+    h.resize(n);
+    if (n) TE_CHECK_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+// ---- host block-sparse matrix (natural numbering) -------------------------
+struct HBsr {
+    int br = 0, bc = 0;
+    int64_t nr = 0, nc = 0;
+    std::vector<int64_t> ptr;   // [nr+1]
+    std::vector<int32_t> col;   // [nnzb]
+    std::vector<double> val;    // [nnzb][br][bc]
+    int64_t nnzb() const { return (int64_t)col.size(); }
+};
+
+// ---- SELL-64 block matrix on the device -----------------------------------
+// Rows are grouped into slices of 64; lane l of slice s holds row s*64+l of
+// the (permuted) row order.  Entry k of every lane of a slice is stored
+// contiguously across lanes:
+//   col[(off_s + k) * 64 + lane]
+//   val[((off_s + k) * br*bc + e) * 64 + lane]        e = i*bc + j
+// Padding entries carry a zero block and a valid column.
+constexpr int SELL_C = 64;
+
+struct Sell {
+    int br = 0, bc = 0;
+    int64_t nrows = 0;          // block rows
+    int64_t ncols = 0;          // block columns
+    int64_t nslices = 0;
+    int64_t nnzb = 0;           // real blocks (without padding)
+    int64_t padded = 0;         // stored entries per lane-column sum (= off_end*64)
+    DBuf<int32_t> slice_off;    // [nslices+1] in units of 64-wide entry columns
+    DBuf<int32_t> col;          // [padded]
+    DBuf<int32_t> rowlen;       // [nslices*64] entries of each row
+    DBuf<double> val;           // [padded * br*bc]
+    DBuf<float> val32;          // optional float32 copy
+    DBuf<int32_t> rowmap;       // [nslices*64] output row of each lane, -1 = none; empty = identity
+    size_t bytes() const {
+        return slice_off.bytes() + col.bytes() + rowlen.bytes() + val.bytes() + val32.bytes() + rowmap.bytes();
+    }
+};
+
+// Build a SELL matrix from a host block matrix.
+//   row_order[i] = row of M stored at position i (lane i%64 of slice i/64)
+//   col_map[c]   = column index used for column c of M
+//   out_map      = if non-null, position i writes output row (*out_map)[row_order[i]];
+//                  otherwise position i writes output row i
+void build_sell(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map,
+                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s);
+
+// Row order sorted by descending length inside windows of `window` rows.
+std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_t window);
+
+// ---- device-side CG scalars (one entry per right-hand side) ----------------
+struct CgScalars {
+    double rz[64], pq[64], alpha[64], beta[64], rr[64], bb[64], tr[64];
+    int32_t active[64];
+    int32_t flag[64];  // 1: (p,Ap) <= 0, 2: (r,z) <= 0, 3: NaN
+};
+
+// ---- kernel launchers (te_kernels.hip) ------------------------------------
+template <typename T>
+void sell_apply(const Sell &A, const T *x, T *y, const T *g, int mode, int nrhs, hipStream_t s);
+void sell_resid_norm(const Sell &A, const double *x, const double *g, double *y, int nrhs, double *partials,
+                     hipStream_t s);
+void sell_dot(const Sell &A, const double *p, double *q, int nrhs, double *partials, hipStream_t s);
+int sell_partials_count(const Sell &A, int nrhs);
+template <typename T>
+void cheb_init(const Sell &A, const T *x, const T *g, const T *dinv, T *r, T *d, double inv_theta, int nrhs,
+               hipStream_t s);
+template <typename T>
+void cheb_step(const Sell &A, const T *d, const T *rin, const T *dinv, T *rout, T *dout, T *x, double c1, double c2,
+               bool last, bool xzero, int nrhs, hipStream_t s);
+template <typename T>
+void jacobi_scale(const T *g, const T *dinv, T *d, double inv_theta, int64_t n, int nrhs, hipStream_t s);
+template <typename T>
+void axpy(T *y, const T *x, double a, int64_t n, hipStream_t s);
+void cast_f64_f32(const double *x, float *y, int64_t n, hipStream_t s);
+void cast_f32_f64(const float *x, double *y, int64_t n, hipStream_t s);
+void permute_gather(const double *src, double *dst, const int32_t *map, int64_t n_nodes, int bs, int nrhs,
+                    hipStream_t s);  // dst[i] = src[map[i]]
+void permute_scatter(const double *src, double *dst, const int32_t *map, int64_t n_nodes, int bs, int nrhs,
+                     hipStream_t s);  // dst[map[i]] = src[i]
+int dot_nblocks(int64_t n);
+void dot_partials(const double *a, const double *b, int64_t n, int nrhs, double *partials, hipStream_t s);
+void reduce_partials(const double *partials, int nparts, int nrhs, double *out, hipStream_t s);
+void reduce_pairs(const double *partials, int nparts, int nrhs, double *out, hipStream_t s);
+void cg_update(double *u, double *r, double *r_old, const double *p, const double *q, const double *alpha,
+               int64_t rows, int nrhs, double *partials, hipStream_t s);
+void dot_rz(const double *r, const double *z, const double *r_old, int64_t rows, int nrhs, double *partials,
+            hipStream_t s);
+void p_update(double *p, const double *z, const double *beta, int64_t n, int nrhs, hipStream_t s);
+void cg_alpha(void *S, const double *pq_sum, int nrhs, hipStream_t s);
+void cg_beta(void *S, const double *rzf, int nrhs, int flexible, hipStream_t s);
+void cg_rz0(void *S, const double *rzf, int nrhs, hipStream_t s);
+size_t cg_scalars_bytes();
+void copy_cols(double *r, const double *t, const int32_t *sel, int64_t n, int nrhs, hipStream_t s);
+template <typename T>
+void dense_mv(const double *Ainv, const T *x, T *y, int n, int nrhs, hipStream_t s);
+void lanczos_start(double *v, const int32_t *perm, int64_t n, int bs, uint64_t seed, hipStream_t s);
+void scale_mul(const double *x, const double *sc, double *y, int64_t n, hipStream_t s);
+void lanczos_w(double *w, const double *sc, const double *vprev, double beta, int64_t n, hipStream_t s);
+void scal(double *x, double a, int64_t n, hipStream_t s);
+
+}  // namespace te

@@ -1,0 +1,868 @@
+// Sparse and vector kernels of the PCG / V-cycle hot loop (gfx950, wave64).
+//
+// Every sparse product runs on the SELL-64 block layout of te_internal.h:
+// one lane per block row, 64 rows per wave, entry k of all 64 lanes stored
+// contiguously so each value plane is one fully coalesced 512-byte (float64)
+// load per wave.  Rows inside a slice are sorted by descending length, so the
+// per-lane length mask switches off whole cache lines of padding at the tail.
+// The x gathers hit L2: node numbering is lexicographic, and the block index
+// is remapped so that each XCD streams one contiguous range of slices and
+// keeps its own L2 window of x.
+//
+// Multi-RHS products (nrhs > 1, vectors laid out [row][comp][rhs]) use one
+// wave per block row with the right-hand sides on the lanes; the block values
+// are wave-uniform and come through the scalar cache.
+//
+// Epilogues fuse the vector work of the Chebyshev smoother (Saad, Alg. 12.1),
+// the residual of the V-cycle and the dot products of CG into the product.
+// All reductions are two-pass and deterministic: per-block partials in a
+// fixed order, then one block sums them in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "te_internal.h"
+
+namespace te {
+
+constexpr int WAVE = 64;
+constexpr int BLK = 256;   // 4 waves per workgroup
+constexpr int WPB = BLK / WAVE;
+
+// Consecutive logical blocks on one XCD: dispatch is round-robin over the 8
+// XCDs, so physical block b runs on XCD b % 8.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nb) {
+    int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, WAVE);
+    return v;
+}
+
+// Block-wide deterministic sum of one value per thread; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < WPB; ++i) t += lds[i];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Sparse-product kernel skeletons
+// ---------------------------------------------------------------------------
+template <typename VT>
+struct SellView {
+    const int32_t *__restrict__ slice_off;
+    const int32_t *__restrict__ col;
+    const int32_t *__restrict__ rowlen;
+    const VT *__restrict__ val;
+    const int32_t *__restrict__ rowmap;  // nullptr => identity
+    int64_t nrows;
+    int64_t nslices;
+};
+
+template <typename VT>
+SellView<VT> view(const Sell &S, const VT *val) {
+    return SellView<VT>{S.slice_off.p, S.col.p, S.rowlen.p, val, S.rowmap.p, S.nrows, S.nslices};
+}
+
+// Single right-hand side: lane = block row.  Epi::apply(row_out, acc, red)
+// consumes the BR accumulated entries and may add to `red` (block-reduced
+// into partials[logical block] when Epi::kReduce).
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
+__global__ void __launch_bounds__(BLK) k_sell1(SellView<VT> A, const XT *__restrict__ x, Epi epi,
+                                               double *__restrict__ partials) {
+    __shared__ double lds[WPB];
+    const int64_t nb = gridDim.x;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t slice = lb * WPB + threadIdx.x / WAVE;
+    double red = 0.0;
+    if (slice < A.nslices) {
+        const int64_t row = slice * WAVE + lane;
+        const int off = A.slice_off[slice];
+        const int w = A.slice_off[slice + 1] - off;
+        const int len = A.rowlen[row];
+        AT acc[BR];
+#pragma unroll
+        for (int i = 0; i < BR; ++i) acc[i] = AT(0);
+        const int32_t *cp = A.col + (int64_t)off * WAVE + lane;
+        const VT *vp = A.val + (int64_t)off * (BR * BC * WAVE) + lane;
+        for (int k = 0; k < w; ++k) {
+            if (k < len) {
+                const int64_t c = cp[(int64_t)k * WAVE];
+                AT xv[BC];
+#pragma unroll
+                for (int j = 0; j < BC; ++j) xv[j] = AT(x[c * BC + j]);
+                const VT *vk = vp + (int64_t)k * (BR * BC * WAVE);
+#pragma unroll
+                for (int i = 0; i < BR; ++i)
+#pragma unroll
+                    for (int j = 0; j < BC; ++j) acc[i] += AT(vk[(i * BC + j) * WAVE]) * xv[j];
+            }
+        }
+        if (row < A.nrows) {
+            const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+            epi.template apply<BR>(out, acc, red);
+        }
+    }
+    if (Epi::kReduce) {
+        double t = block_sum(red, lds);
+        if (threadIdx.x == 0) partials[lb] = t;
+    }
+}
+
+// Several right-hand sides: one wave per block row, lane = right-hand side.
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
+__global__ void __launch_bounds__(BLK) k_sellm(SellView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
+                                               double *__restrict__ partials) {
+    __shared__ double lds[BLK];
+    const int64_t nb = gridDim.x;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * WPB + threadIdx.x / WAVE));
+    double red = 0.0;
+    if (row < A.nrows) {
+        const int64_t slice = row / WAVE;
+        const int rl = (int)(row % WAVE);
+        const int off = A.slice_off[slice];
+        const int len = A.rowlen[row];
+        AT acc[BR];
+#pragma unroll
+        for (int i = 0; i < BR; ++i) acc[i] = AT(0);
+        if (lane < nrhs) {
+            for (int k = 0; k < len; ++k) {
+                const int64_t e = (int64_t)(off + k) * WAVE + rl;
+                const int64_t c = A.col[e];
+                const VT *vk = A.val + (int64_t)(off + k) * (BR * BC * WAVE) + rl;
+                AT xv[BC];
+#pragma unroll
+                for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
+#pragma unroll
+                for (int i = 0; i < BR; ++i)
+#pragma unroll
+                    for (int j = 0; j < BC; ++j) acc[i] += AT(vk[(i * BC + j) * WAVE]) * xv[j];
+            }
+            const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+            epi.template apply_m<BR>(out, lane, nrhs, acc, red);
+        }
+    }
+    if (Epi::kReduce) {
+        // per-column partial: sum over the waves of this block, fixed order
+        lds[threadIdx.x] = red;
+        __syncthreads();
+        if (threadIdx.x < WAVE && threadIdx.x < nrhs) {
+            double t = 0.0;
+            for (int w = 0; w < WPB; ++w) t += lds[w * WAVE + threadIdx.x];
+            partials[lb * nrhs + threadIdx.x] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues
+// ---------------------------------------------------------------------------
+template <typename T>
+struct EpiSet {  // y = A x
+    static constexpr bool kReduce = false;
+    T *y;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) y[r * BR + i] = T(acc[i]);
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) y[(r * BR + i) * m + j] = T(acc[i]);
+    }
+};
+
+template <typename T>
+struct EpiAdd {  // y += A x
+    static constexpr bool kReduce = false;
+    T *y;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) y[r * BR + i] = T(AT(y[r * BR + i]) + acc[i]);
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (r * BR + i) * m + j;
+            y[q] = T(AT(y[q]) + acc[i]);
+        }
+    }
+};
+
+template <typename T, bool NORM>
+struct EpiResid {  // y = g - A x  (optionally red += y^2)
+    static constexpr bool kReduce = NORM;
+    const T *g;
+    T *y;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            AT v = AT(g[r * BR + i]) - acc[i];
+            y[r * BR + i] = T(v);
+            if (NORM) red += double(v) * double(v);
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (r * BR + i) * m + j;
+            AT v = AT(g[q]) - acc[i];
+            y[q] = T(v);
+            if (NORM) red += double(v) * double(v);
+        }
+    }
+};
+
+struct EpiDot {  // q = A p, red += p.q   (float64 outer CG)
+    static constexpr bool kReduce = true;
+    const double *p;
+    double *q;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            q[r * BR + i] = acc[i];
+            red += p[r * BR + i] * double(acc[i]);
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t k = (r * BR + i) * m + j;
+            q[k] = acc[i];
+            red += p[k] * double(acc[i]);
+        }
+    }
+};
+
+// Post-smoothing start: r = g - A x, d = D^-1 r / theta.
+template <typename T>
+struct EpiChebInit {
+    static constexpr bool kReduce = false;
+    const T *g;
+    const T *dinv;
+    T *r;
+    T *d;
+    T inv_theta;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t row, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = row * BR + i;
+            T rv = T(AT(g[q]) - acc[i]);
+            r[q] = rv;
+            d[q] = dinv[q] * rv * inv_theta;
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (row * BR + i) * m + j;
+            T rv = T(AT(g[q]) - acc[i]);
+            r[q] = rv;
+            d[q] = dinv[row * BR + i] * rv * inv_theta;
+        }
+    }
+};
+
+// One Chebyshev step on the product acc = A d:
+//   r' = r - A d;  d' = c1 d + c2 D^-1 r';  x (+)= d  [+ d' on the last step]
+// `d` is the gathered vector of the product (own row read here); d' goes to a
+// different buffer.  XZERO: x starts from zero (pre-smoothing).
+template <typename T, bool LAST, bool XZERO>
+struct EpiChebStep {
+    static constexpr bool kReduce = false;
+    const T *rin;
+    const T *d;
+    const T *dinv;
+    T *rout;
+    T *dout;
+    T *x;
+    T c1, c2;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t row, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = row * BR + i;
+            T rn = T(AT(rin[q]) - acc[i]);
+            T dv = d[q];
+            T dn = c1 * dv + c2 * (dinv[q] * rn);
+            T xv = XZERO ? T(0) : x[q];
+            if (LAST) {
+                x[q] = xv + dv + dn;
+            } else {
+                rout[q] = rn;
+                dout[q] = dn;
+                x[q] = xv + dv;
+            }
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (row * BR + i) * m + j;
+            T rn = T(AT(rin[q]) - acc[i]);
+            T dv = d[q];
+            T dn = c1 * dv + c2 * (dinv[row * BR + i] * rn);
+            T xv = XZERO ? T(0) : x[q];
+            if (LAST) {
+                x[q] = xv + dv + dn;
+            } else {
+                rout[q] = rn;
+                dout[q] = dn;
+                x[q] = xv + dv;
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+static inline int64_t sell_grid(const Sell &A, int nrhs) {
+    if (nrhs == 1) return (A.nslices + WPB - 1) / WPB;
+    return (A.nrows + WPB - 1) / WPB;
+}
+
+int sell_partials_count(const Sell &A, int nrhs) { return (int)sell_grid(A, nrhs); }
+
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
+static void launch_t(const Sell &A, const VT *val, const XT *x, const Epi &epi, int nrhs, double *partials,
+                     hipStream_t s) {
+    int64_t g = sell_grid(A, nrhs);
+    if (g == 0) return;
+    if (nrhs == 1)
+        hipLaunchKernelGGL((k_sell1<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, view(A, val), x,
+                           epi, partials);
+    else
+        hipLaunchKernelGGL((k_sellm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, view(A, val), x,
+                           epi, nrhs, partials);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+template <typename T, class Epi>
+static void dispatch(const Sell &A, const T *x, const Epi &epi, int nrhs, double *partials, hipStream_t s) {
+    const T *val;
+    if constexpr (sizeof(T) == 4) {
+        TE_REQUIRE(A.val32.p, TE_EINVAL, "float32 operator copy not built");
+        val = A.val32.p;
+    } else {
+        val = A.val.p;
+    }
+    const int key = A.br * 10 + A.bc;
+    switch (key) {
+        case 33: launch_t<3, 3, T, T, T>(A, val, x, epi, nrhs, partials, s); break;
+        case 66: launch_t<6, 6, T, T, T>(A, val, x, epi, nrhs, partials, s); break;
+        case 36: launch_t<3, 6, T, T, T>(A, val, x, epi, nrhs, partials, s); break;
+        case 63: launch_t<6, 3, T, T, T>(A, val, x, epi, nrhs, partials, s); break;
+        case 11: launch_t<1, 1, T, T, T>(A, val, x, epi, nrhs, partials, s); break;
+        default: TE_REQUIRE(false, TE_EINVAL, "unsupported block shape %dx%d", A.br, A.bc);
+    }
+}
+
+template <typename T>
+void sell_apply(const Sell &A, const T *x, T *y, const T *g, int mode, int nrhs, hipStream_t s) {
+    if (mode == 0) dispatch(A, x, EpiSet<T>{y}, nrhs, nullptr, s);
+    else if (mode == 1) dispatch(A, x, EpiAdd<T>{y}, nrhs, nullptr, s);
+    else dispatch(A, x, EpiResid<T, false>{g, y}, nrhs, nullptr, s);
+}
+template void sell_apply<double>(const Sell &, const double *, double *, const double *, int, int, hipStream_t);
+template void sell_apply<float>(const Sell &, const float *, float *, const float *, int, int, hipStream_t);
+
+void sell_resid_norm(const Sell &A, const double *x, const double *g, double *y, int nrhs, double *partials,
+                     hipStream_t s) {
+    dispatch(A, x, EpiResid<double, true>{g, y}, nrhs, partials, s);
+}
+
+void sell_dot(const Sell &A, const double *p, double *q, int nrhs, double *partials, hipStream_t s) {
+    dispatch(A, p, EpiDot{p, q}, nrhs, partials, s);
+}
+
+template <typename T>
+void cheb_init(const Sell &A, const T *x, const T *g, const T *dinv, T *r, T *d, double inv_theta, int nrhs,
+               hipStream_t s) {
+    dispatch(A, x, EpiChebInit<T>{g, dinv, r, d, T(inv_theta)}, nrhs, nullptr, s);
+}
+template void cheb_init<double>(const Sell &, const double *, const double *, const double *, double *, double *,
+                                double, int, hipStream_t);
+template void cheb_init<float>(const Sell &, const float *, const float *, const float *, float *, float *, double,
+                               int, hipStream_t);
+
+template <typename T>
+void cheb_step(const Sell &A, const T *d, const T *rin, const T *dinv, T *rout, T *dout, T *x, double c1, double c2,
+               bool last, bool xzero, int nrhs, hipStream_t s) {
+    if (last && xzero)
+        dispatch(A, d, EpiChebStep<T, true, true>{rin, d, dinv, rout, dout, x, T(c1), T(c2)}, nrhs, nullptr, s);
+    else if (last)
+        dispatch(A, d, EpiChebStep<T, true, false>{rin, d, dinv, rout, dout, x, T(c1), T(c2)}, nrhs, nullptr, s);
+    else if (xzero)
+        dispatch(A, d, EpiChebStep<T, false, true>{rin, d, dinv, rout, dout, x, T(c1), T(c2)}, nrhs, nullptr, s);
+    else
+        dispatch(A, d, EpiChebStep<T, false, false>{rin, d, dinv, rout, dout, x, T(c1), T(c2)}, nrhs, nullptr, s);
+}
+template void cheb_step<double>(const Sell &, const double *, const double *, const double *, double *, double *,
+                                double *, double, double, bool, bool, int, hipStream_t);
+template void cheb_step<float>(const Sell &, const float *, const float *, const float *, float *, float *, float *,
+                               double, double, bool, bool, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Element-wise kernels
+// ---------------------------------------------------------------------------
+static inline unsigned egrid(int64_t n) {
+    int64_t g = (n + BLK - 1) / BLK;
+    if (g > (1 << 20)) g = 1 << 20;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// d = D^-1 g / theta  (pre-smoothing start, x0 = 0); rows*bs*nrhs entries
+template <typename T>
+__global__ void k_jacobi_scale(const T *__restrict__ g, const T *__restrict__ dinv, T *__restrict__ d, T inv_theta,
+                               int64_t n, int nrhs) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
+        d[i] = dinv[i / nrhs] * g[i] * inv_theta;
+}
+template <typename T>
+void jacobi_scale(const T *g, const T *dinv, T *d, double inv_theta, int64_t n, int nrhs, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_jacobi_scale<T>, dim3(egrid(n)), dim3(BLK), 0, s, g, dinv, d, T(inv_theta), n, nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+template void jacobi_scale<double>(const double *, const double *, double *, double, int64_t, int, hipStream_t);
+template void jacobi_scale<float>(const float *, const float *, float *, double, int64_t, int, hipStream_t);
+
+template <typename T>
+__global__ void k_axpy(T *__restrict__ y, const T *__restrict__ x, T a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) y[i] += a * x[i];
+}
+template <typename T>
+void axpy(T *y, const T *x, double a, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_axpy<T>, dim3(egrid(n)), dim3(BLK), 0, s, y, x, T(a), n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+template void axpy<double>(double *, const double *, double, int64_t, hipStream_t);
+template void axpy<float>(float *, const float *, double, int64_t, hipStream_t);
+
+template <typename A, typename B>
+__global__ void k_cast(const A *__restrict__ x, B *__restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) y[i] = B(x[i]);
+}
+void cast_f64_f32(const double *x, float *y, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(egrid(n)), dim3(BLK), 0, s, x, y, n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+void cast_f32_f64(const float *x, double *y, int64_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(egrid(n)), dim3(BLK), 0, s, x, y, n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// dst[i] = src[map[i]] per node (bs*nrhs contiguous values per node)
+__global__ void k_perm_gather(const double *__restrict__ src, double *__restrict__ dst, const int32_t *__restrict__ map,
+                              int64_t n, int per) {
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n * per; t += (int64_t)gridDim.x * BLK) {
+        int64_t i = t / per, k = t % per;
+        dst[t] = src[(int64_t)map[i] * per + k];
+    }
+}
+__global__ void k_perm_scatter(const double *__restrict__ src, double *__restrict__ dst,
+                               const int32_t *__restrict__ map, int64_t n, int per) {
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n * per; t += (int64_t)gridDim.x * BLK) {
+        int64_t i = t / per, k = t % per;
+        dst[(int64_t)map[i] * per + k] = src[t];
+    }
+}
+void permute_gather(const double *src, double *dst, const int32_t *map, int64_t n_nodes, int bs, int nrhs,
+                    hipStream_t s) {
+    if (n_nodes == 0) return;
+    hipLaunchKernelGGL(k_perm_gather, dim3(egrid(n_nodes * bs * nrhs)), dim3(BLK), 0, s, src, dst, map, n_nodes,
+                       bs * nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+void permute_scatter(const double *src, double *dst, const int32_t *map, int64_t n_nodes, int bs, int nrhs,
+                     hipStream_t s) {
+    if (n_nodes == 0) return;
+    hipLaunchKernelGGL(k_perm_scatter, dim3(egrid(n_nodes * bs * nrhs)), dim3(BLK), 0, s, src, dst, map, n_nodes,
+                       bs * nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic dot products (per right-hand side column)
+// ---------------------------------------------------------------------------
+constexpr int DOT_BLOCKS = 1024;
+
+int dot_nblocks(int64_t n) {
+    int64_t g = (n + BLK - 1) / BLK;
+    return (int)(g < 1 ? 1 : (g > DOT_BLOCKS ? DOT_BLOCKS : g));
+}
+
+// Single column: block b sums a contiguous chunk in a fixed order.
+__global__ void k_dot1(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+                       double *__restrict__ partials) {
+    __shared__ double lds[WPB];
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = (n + nb - 1) / nb;
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double t = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BLK) t += a[i] * b[i];
+    t = block_sum(t, lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// Several columns (layout [rows][nrhs]): lane = column, waves over rows.
+__global__ void k_dotm(const double *__restrict__ a, const double *__restrict__ b, int64_t rows, int nrhs,
+                       double *__restrict__ partials) {
+    __shared__ double lds[BLK];
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = (rows + nb - 1) / nb;
+    const int64_t lo = blockIdx.x * chunk, hi = min(rows, lo + chunk);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    double t = 0.0;
+    if (lane < nrhs)
+        for (int64_t i = lo + w; i < hi; i += WPB) t += a[i * nrhs + lane] * b[i * nrhs + lane];
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x < nrhs) {
+        double s = 0.0;
+        for (int k = 0; k < WPB; ++k) s += lds[k * WAVE + threadIdx.x];
+        partials[blockIdx.x * (int64_t)nrhs + threadIdx.x] = s;
+    }
+}
+
+void dot_partials(const double *a, const double *b, int64_t n, int nrhs, double *partials, hipStream_t s) {
+    int64_t rows = n / nrhs;
+    int nb = dot_nblocks(rows);
+    if (nrhs == 1)
+        hipLaunchKernelGGL(k_dot1, dim3(nb), dim3(BLK), 0, s, a, b, n, partials);
+    else
+        hipLaunchKernelGGL(k_dotm, dim3(nb), dim3(BLK), 0, s, a, b, rows, nrhs, partials);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// out[j] = sum_b partials[b*nrhs + j], fixed order (thread j, sequential b).
+__global__ void k_reduce_partials(const double *__restrict__ partials, int nparts, int nrhs, double *__restrict__ out) {
+    __shared__ double lds[BLK];
+    // each column j: threads split the parts in a fixed strided way, then tree
+    for (int j = 0; j < nrhs; ++j) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += BLK) t += partials[(int64_t)b * nrhs + j];
+        lds[threadIdx.x] = t;
+        __syncthreads();
+        for (int o = BLK / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[j] = lds[0];
+        __syncthreads();
+    }
+}
+void reduce_partials(const double *partials, int nparts, int nrhs, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(BLK), 0, s, partials, nparts, nrhs, out);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// CG vector updates (float64), per-column scalars on the device
+// ---------------------------------------------------------------------------
+// u += alpha_j p; r_old = r (if keep_old); r -= alpha_j q; red_j += r^2
+__global__ void k_cg_update(double *__restrict__ u, double *__restrict__ r, double *__restrict__ r_old,
+                            const double *__restrict__ p, const double *__restrict__ q, const double *__restrict__ alpha,
+                            int64_t rows, int nrhs, double *__restrict__ partials) {
+    __shared__ double lds[BLK];
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = (rows + nb - 1) / nb;
+    const int64_t lo = blockIdx.x * chunk, hi = min(rows, lo + chunk);
+    if (nrhs == 1) {
+        const double a = alpha[0];
+        double t = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += BLK) {
+            u[i] += a * p[i];
+            double rv = r[i];
+            if (r_old) r_old[i] = rv;
+            rv -= a * q[i];
+            r[i] = rv;
+            t += rv * rv;
+        }
+        t = block_sum(t, lds);
+        if (threadIdx.x == 0) partials[blockIdx.x] = t;
+        return;
+    }
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    double t = 0.0;
+    if (lane < nrhs) {
+        const double a = alpha[lane];
+        for (int64_t i = lo + w; i < hi; i += WPB) {
+            int64_t k = i * nrhs + lane;
+            u[k] += a * p[k];
+            double rv = r[k];
+            if (r_old) r_old[k] = rv;
+            rv -= a * q[k];
+            r[k] = rv;
+            t += rv * rv;
+        }
+    }
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x < nrhs) {
+        double s = 0.0;
+        for (int k = 0; k < WPB; ++k) s += lds[k * WAVE + threadIdx.x];
+        partials[blockIdx.x * (int64_t)nrhs + threadIdx.x] = s;
+    }
+}
+void cg_update(double *u, double *r, double *r_old, const double *p, const double *q, const double *alpha,
+               int64_t rows, int nrhs, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update, dim3(dot_nblocks(rows)), dim3(BLK), 0, s, u, r, r_old, p, q, alpha, rows, nrhs,
+                       partials);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// (r, z) and, for the flexible variant, (z, r - r_old) per column
+__global__ void k_dot_rz(const double *__restrict__ r, const double *__restrict__ z, const double *__restrict__ r_old,
+                         int64_t rows, int nrhs, double *__restrict__ partials) {
+    __shared__ double lds[2 * BLK];
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = (rows + nb - 1) / nb;
+    const int64_t lo = blockIdx.x * chunk, hi = min(rows, lo + chunk);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    double t = 0.0, f = 0.0;
+    if (nrhs == 1) {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += BLK) {
+            t += r[i] * z[i];
+            if (r_old) f += z[i] * (r[i] - r_old[i]);
+        }
+        double a = block_sum(t, lds);
+        double b = block_sum(f, lds + WPB);
+        if (threadIdx.x == 0) {
+            partials[2 * blockIdx.x] = a;
+            partials[2 * blockIdx.x + 1] = b;
+        }
+        return;
+    }
+    if (lane < nrhs)
+        for (int64_t i = lo + w; i < hi; i += WPB) {
+            int64_t k = i * nrhs + lane;
+            t += r[k] * z[k];
+            if (r_old) f += z[k] * (r[k] - r_old[k]);
+        }
+    lds[threadIdx.x] = t;
+    lds[BLK + threadIdx.x] = f;
+    __syncthreads();
+    if (threadIdx.x < nrhs) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < WPB; ++k) {
+            s1 += lds[k * WAVE + threadIdx.x];
+            s2 += lds[BLK + k * WAVE + threadIdx.x];
+        }
+        partials[(blockIdx.x * (int64_t)nrhs + threadIdx.x) * 2] = s1;
+        partials[(blockIdx.x * (int64_t)nrhs + threadIdx.x) * 2 + 1] = s2;
+    }
+}
+void dot_rz(const double *r, const double *z, const double *r_old, int64_t rows, int nrhs, double *partials,
+            hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_rz, dim3(dot_nblocks(rows)), dim3(BLK), 0, s, r, z, r_old, rows, nrhs, partials);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// p = z + beta_j p
+__global__ void k_p_update(double *__restrict__ p, const double *__restrict__ z, const double *__restrict__ beta,
+                           int64_t n, int nrhs) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
+        p[i] = z[i] + beta[i % nrhs] * p[i];
+}
+void p_update(double *p, const double *z, const double *beta, int64_t n, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_p_update, dim3(egrid(n)), dim3(BLK), 0, s, p, z, beta, n, nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// Scalar bookkeeping of the CG recurrence, one thread per column.
+//   alpha: pq from partials -> alpha = active ? rz/pq : 0 ; flag if pq <= 0
+//   beta:  rz_new (+ flexible term) -> beta; rz = rz_new; flag if rz_new <= 0
+__global__ void k_cg_alpha(CgScalars *S, const double *__restrict__ pq_sum, int nrhs) {
+    int j = threadIdx.x;
+    if (j >= nrhs) return;
+    double pq = pq_sum[j];
+    S->pq[j] = pq;
+    double a = 0.0;
+    if (S->active[j]) {
+        if (!(pq > 0.0)) {
+            S->flag[j] = (pq != pq) ? 3 : 1;
+        } else {
+            a = S->rz[j] / pq;
+        }
+    }
+    S->alpha[j] = a;
+}
+__global__ void k_cg_beta(CgScalars *S, const double *__restrict__ rzf, int nrhs, int flexible) {
+    int j = threadIdx.x;
+    if (j >= nrhs) return;
+    double rzn = rzf[2 * j], fl = rzf[2 * j + 1];
+    double b = 0.0;
+    if (S->active[j]) {
+        if (!(rzn > 0.0)) {
+            S->flag[j] = (rzn != rzn) ? 3 : 2;
+        } else {
+            b = flexible ? fl / S->rz[j] : rzn / S->rz[j];
+            S->rz[j] = rzn;
+        }
+    }
+    S->beta[j] = b;
+}
+__global__ void k_cg_rz0(CgScalars *S, const double *__restrict__ rzf, int nrhs) {
+    int j = threadIdx.x;
+    if (j >= nrhs) return;
+    double rzn = rzf[2 * j];
+    if (S->active[j] && !(rzn > 0.0)) S->flag[j] = (rzn != rzn) ? 3 : 2;
+    S->rz[j] = rzn;
+}
+// reduce interleaved (rz, flex) partial pairs
+__global__ void k_reduce_pairs(const double *__restrict__ partials, int nparts, int nrhs, double *__restrict__ out) {
+    __shared__ double lds[BLK];
+    for (int jj = 0; jj < 2 * nrhs; ++jj) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += BLK) t += partials[(int64_t)b * 2 * nrhs + jj];
+        lds[threadIdx.x] = t;
+        __syncthreads();
+        for (int o = BLK / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) lds[threadIdx.x] += lds[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[jj] = lds[0];
+        __syncthreads();
+    }
+}
+
+void cg_alpha(void *S, const double *pq_sum, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64), 0, s, (CgScalars *)S, pq_sum, nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+void cg_beta(void *S, const double *rzf, int nrhs, int flexible, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64), 0, s, (CgScalars *)S, rzf, nrhs, flexible);
+    TE_CHECK_HIP(hipGetLastError());
+}
+void cg_rz0(void *S, const double *rzf, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_rz0, dim3(1), dim3(64), 0, s, (CgScalars *)S, rzf, nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+void reduce_pairs(const double *partials, int nparts, int nrhs, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(BLK), 0, s, partials, nparts, nrhs, out);
+    TE_CHECK_HIP(hipGetLastError());
+}
+size_t cg_scalars_bytes() { return sizeof(CgScalars); }
+
+// Column select: r[:, j] = t[:, j] where sel[j] != 0
+__global__ void k_copy_cols(double *__restrict__ r, const double *__restrict__ t, const int32_t *__restrict__ sel,
+                            int64_t n, int nrhs) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
+        if (sel[i % nrhs]) r[i] = t[i];
+}
+void copy_cols(double *r, const double *t, const int32_t *sel, int64_t n, int nrhs, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_cols, dim3(egrid(n)), dim3(BLK), 0, s, r, t, sel, n, nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Dense coarse solve: y = Ainv x (Ainv symmetric n x n, float64)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(BLK) k_dense_mv(const double *__restrict__ Ainv, const T *__restrict__ x,
+                                                  T *__restrict__ y, int n, int nrhs) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * WPB + threadIdx.x / WAVE));
+    if (row >= n) return;
+    const double *a = Ainv + row * (int64_t)n;
+    if (nrhs == 1) {
+        double t = 0.0;
+        for (int j = lane; j < n; j += WAVE) t += a[j] * double(x[j]);
+        t = wave_sum(t);
+        if (lane == 0) y[row] = T(t);
+        return;
+    }
+    if (lane >= nrhs) return;
+    double t = 0.0;
+    for (int j = 0; j < n; ++j) t += a[j] * double(x[(int64_t)j * nrhs + lane]);
+    y[row * nrhs + lane] = T(t);
+}
+template <typename T>
+void dense_mv(const double *Ainv, const T *x, T *y, int n, int nrhs, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_dense_mv<T>, dim3((n + WPB - 1) / WPB), dim3(BLK), 0, s, Ainv, x, y, n, nrhs);
+    TE_CHECK_HIP(hipGetLastError());
+}
+template void dense_mv<double>(const double *, const double *, double *, int, int, hipStream_t);
+template void dense_mv<float>(const double *, const float *, float *, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Lanczos helpers (setup)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    // Steele, Lea & Flood 2014: one step of the generator on input x
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// v[new*bs + c] = U(splitmix64(seed ^ natural_dof)) - 0.5
+__global__ void k_lanczos_start(double *__restrict__ v, const int32_t *__restrict__ perm, int64_t n, int bs,
+                                uint64_t seed) {
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n * bs; t += (int64_t)gridDim.x * BLK) {
+        int64_t i = t / bs, c = t % bs;
+        uint64_t nat = (uint64_t)perm[i] * (uint64_t)bs + (uint64_t)c;
+        uint64_t z = splitmix64(seed ^ nat);
+        v[t] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+    }
+}
+void lanczos_start(double *v, const int32_t *perm, int64_t n, int bs, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_start, dim3(egrid(n * bs)), dim3(BLK), 0, s, v, perm, n, bs, seed);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// y = a*x + b*y element-wise, then helpers for D^{1/2} scaling
+__global__ void k_scale_mul(const double *__restrict__ x, const double *__restrict__ s, double *__restrict__ y,
+                            int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) y[i] = s[i] * x[i];
+}
+void scale_mul(const double *x, const double *sc, double *y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_mul, dim3(egrid(n)), dim3(BLK), 0, s, x, sc, y, n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+// w = sc * w - beta * vprev  (in place on w)
+__global__ void k_lanczos_w(double *__restrict__ w, const double *__restrict__ sc, const double *__restrict__ vprev,
+                            double beta, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
+        w[i] = sc[i] * w[i] - beta * vprev[i];
+}
+void lanczos_w(double *w, const double *sc, const double *vprev, double beta, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_lanczos_w, dim3(egrid(n)), dim3(BLK), 0, s, w, sc, vprev, beta, n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+__global__ void k_scal(double *__restrict__ x, double a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) x[i] *= a;
+}
+void scal(double *x, double a, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scal, dim3(egrid(n)), dim3(BLK), 0, s, x, a, n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace te

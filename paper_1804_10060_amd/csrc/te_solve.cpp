@@ -1,0 +1,443 @@
+// V-cycle and (flexible) preconditioned conjugate gradients on the device.
+//
+// CG follows the paper's solver (Sec. 2.1.2; Sec. 5.1: CG preconditioned by
+// smoothed-aggregation AMG with Chebyshev smoothing), in the form of Saad's
+// Algorithm 9.1.  For the float32 V-cycle the flexible beta of Notay (2000),
+// (z', r' - r)/(z, r), keeps CG convergent with a preconditioner that is not
+// an exact fixed linear operator.  Every column of a multi-RHS solve keeps its
+// own recurrence; the sparse products are shared.  The host reads back one
+// residual norm per column and iteration to decide convergence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "te_amg.h"
+
+namespace te {
+
+template <typename T>
+static Work<T> &work(Level &L);
+template <>
+Work<double> &work<double>(Level &L) {
+    return L.w64;
+}
+template <>
+Work<float> &work<float>(Level &L) {
+    return L.w32;
+}
+template <typename T>
+static const T *dinv_of(const Level &L);
+template <>
+const double *dinv_of<double>(const Level &L) {
+    return L.dinv.p;
+}
+template <>
+const float *dinv_of<float>(const Level &L) {
+    return L.dinv32.p;
+}
+
+// Chebyshev steps after the start d0 (and r0 = rin), accumulating into x.
+template <typename T>
+static void cheb_chain(Level &L, const T *rin, T *x, bool xzero, int degree, int m, hipStream_t s) {
+    Work<T> &W = work<T>(L);
+    const T *dinv = dinv_of<T>(L);
+    T *dc = W.d.p, *dn = W.d2.p;
+    if (degree == 1) {
+        if (xzero) TE_CHECK_HIP(hipMemcpyAsync(x, dc, (size_t)L.n * L.bs * m * sizeof(T), hipMemcpyDeviceToDevice, s));
+        else axpy<T>(x, dc, 1.0, L.n * L.bs * m, s);
+        return;
+    }
+    for (int k = 0; k + 1 < degree; ++k) {
+        const bool last = (k + 2 == degree);
+        cheb_step<T>(L.A, dc, rin, dinv, W.r.p, dn, x, L.c1[k], L.c2[k], last, xzero && k == 0, m, s);
+        rin = W.r.p;
+        std::swap(dc, dn);
+    }
+}
+
+// x = Chebyshev(g, x0 = x) (post-smoothing form, x0 arbitrary)
+template <typename T>
+static void smooth_from(amg_handle *h, Level &L, const T *g, T *x, int m, hipStream_t s) {
+    Work<T> &W = work<T>(L);
+    cheb_init<T>(L.A, x, g, dinv_of<T>(L), W.r.p, W.d.p, 1.0 / L.theta, m, s);
+    cheb_chain<T>(L, W.r.p, x, false, h->opt.cheb_degree, m, s);
+}
+
+template <typename T>
+void vcycle(amg_handle *h, int l, const T *g, T *x, int m, hipStream_t s) {
+    Level &L = h->L[l];
+    Prof *pf = (l == 0) ? &h->prof : nullptr;
+    auto B = [&](int c) { if (pf) pf->begin(c); };
+    auto E = [&](int c) { if (pf) pf->end(c); };
+    if (l + 1 == (int)h->L.size()) {
+        B(TE_K_COARSE);
+        dense_mv<T>(h->Ainv.p, g, x, h->nc, m, s);
+        E(TE_K_COARSE);
+        return;
+    }
+    Work<T> &W = work<T>(L);
+    const int64_t nv = L.n * L.bs * m;
+    const T *dinv = dinv_of<T>(L);
+    const int deg = h->opt.cheb_degree;
+    // pre-smoothing from x0 = 0: r0 = g, d0 = D^-1 g / theta
+    B(TE_K_VECTOR);
+    jacobi_scale<T>(g, dinv, W.d.p, 1.0 / L.theta, nv, m, s);
+    E(TE_K_VECTOR);
+    B(TE_K_PRE);
+    cheb_chain<T>(L, g, x, true, deg, m, s);
+    E(TE_K_PRE);
+    // residual, restriction, coarse correction, prolongation
+    B(TE_K_RESID);
+    sell_apply<T>(L.A, x, W.s.p, g, 2, m, s);
+    E(TE_K_RESID);
+    Level &N = h->L[l + 1];
+    Work<T> &WN = work<T>(N);
+    B(TE_K_RESTRICT);
+    sell_apply<T>(L.R, W.s.p, WN.g.p, nullptr, 0, m, s);
+    E(TE_K_RESTRICT);
+    B(TE_K_COARSE);
+    vcycle<T>(h, l + 1, WN.g.p, WN.x.p, m, s);
+    E(TE_K_COARSE);
+    B(TE_K_PROLONG);
+    sell_apply<T>(L.P, WN.x.p, x, nullptr, 1, m, s);
+    E(TE_K_PROLONG);
+    // post-smoothing from the corrected x
+    B(TE_K_POSTINIT);
+    cheb_init<T>(L.A, x, g, dinv, W.r.p, W.d.p, 1.0 / L.theta, m, s);
+    E(TE_K_POSTINIT);
+    B(TE_K_POST);
+    cheb_chain<T>(L, W.r.p, x, false, deg, m, s);
+    E(TE_K_POST);
+}
+
+// z = M^-1 r on level 0 (float64 in and out)
+static void precondition(amg_handle *h, const double *r, double *z, int m, bool mixed, hipStream_t s) {
+    Level &L0 = h->L[0];
+    const int64_t nv = L0.n * 3 * m;
+    if (!mixed) {
+        vcycle<double>(h, 0, r, z, m, s);
+        return;
+    }
+    h->prof.begin(TE_K_VECTOR);
+    cast_f64_f32(r, L0.w32.g.p, nv, s);
+    h->prof.end(TE_K_VECTOR);
+    vcycle<float>(h, 0, L0.w32.g.p, L0.w32.x.p, m, s);
+    h->prof.begin(TE_K_VECTOR);
+    cast_f32_f64(L0.w32.x.p, z, nv, s);
+    h->prof.end(TE_K_VECTOR);
+}
+
+struct HostScal {
+    std::vector<double> v;
+    std::vector<int32_t> f;
+};
+
+static void fetch(const double *dsum, int count, std::vector<double> &out, hipStream_t s) {
+    out.resize(count);
+    TE_CHECK_HIP(hipMemcpyAsync(out.data(), dsum, count * sizeof(double), hipMemcpyDeviceToHost, s));
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, const pcg_options *opt_in,
+                      pcg_report *rep, hipStream_t s) {
+    TE_REQUIRE(h && b_nat && u_nat, TE_EINVAL, "NULL argument");
+    TE_REQUIRE(m >= 1 && m <= h->opt.max_nrhs, TE_EINVAL, "nrhs %d outside 1..max_nrhs (%d)", m, h->opt.max_nrhs);
+    pcg_options o;
+    if (opt_in) o = *opt_in;
+    else pcg_options_default(&o);
+    TE_REQUIRE(o.rtol > 0 && o.maxit >= 0, TE_EINVAL, "bad rtol / maxit");
+    const bool mixed = o.precision == TE_PREC_MIXED;
+    TE_REQUIRE(o.precision == TE_PREC_FP64 || mixed, TE_EINVAL, "unknown precision %d", o.precision);
+    TE_REQUIRE(!mixed || h->opt.build_fp32, TE_EINVAL, "mixed precision needs build_fp32 at setup");
+    Level &L0 = h->L[0];
+    const int64_t n = L0.n, rows = n * 3, nv = rows * m;
+    CgScalars *S = reinterpret_cast<CgScalars *>(h->scal.p);
+    double *part = h->partials.p, *sums = h->sums.p;
+
+    h->prof.reset(o.profile != 0, s);
+    hipEvent_t e0, e1;
+    TE_CHECK_HIP(hipEventCreate(&e0));
+    TE_CHECK_HIP(hipEventCreate(&e1));
+    TE_CHECK_HIP(hipEventRecord(e0, s));
+
+    permute_gather(b_nat, h->b.p, L0.perm.p, n, 3, m, s);
+    permute_gather(u_nat, h->u.p, L0.perm.p, n, 3, m, s);
+    std::vector<double> bb, rr, tr;
+    dot_partials(h->b.p, h->b.p, nv, m, part, s);
+    reduce_partials(part, dot_nblocks(rows), m, sums, s);
+    fetch(sums, m, bb, s);
+    sell_resid_norm(L0.A, h->u.p, h->b.p, h->r.p, m, part, s);
+    reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+    fetch(sums, m, rr, s);
+
+    std::vector<int32_t> active(64, 0), flags(64, 0), iters(m, 0), conv(m, 0), replaced(m, 0);
+    std::vector<double> hist;
+    if (rep && rep->history) {
+        for (int k = 0; k <= o.maxit; ++k)
+            for (int j = 0; j < m; ++j) rep->history[(size_t)k * m + j] = NAN;
+    }
+    int n_active = 0;
+    std::vector<int32_t> zero_cols(64, 0);
+    bool any_zero = false;
+    for (int j = 0; j < m; ++j) {
+        const double rel = bb[j] > 0 ? std::sqrt(rr[j] / bb[j]) : 0.0;
+        if (rep && rep->history) rep->history[j] = rel;
+        TE_REQUIRE(std::isfinite(rr[j]) && std::isfinite(bb[j]), TE_ENAN, "NaN/Inf in the right-hand side or guess");
+        if (bb[j] == 0.0) {
+            conv[j] = 1;  // u = 0 is the solution
+            zero_cols[j] = 1;
+            any_zero = true;
+        } else if (rel <= o.rtol) {
+            conv[j] = 1;
+        } else {
+            active[j] = 1;
+            ++n_active;
+        }
+    }
+    if (any_zero) {  // b = 0 has the solution u = 0 whatever the guess
+        DBuf<int32_t> dsel(64);
+        TE_CHECK_HIP(hipMemcpyAsync(dsel.p, zero_cols.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        TE_CHECK_HIP(hipMemsetAsync(h->t.p, 0, nv * sizeof(double), s));
+        copy_cols(h->u.p, h->t.p, dsel.p, nv, m, s);
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    if (n_active) {
+        TE_CHECK_HIP(hipMemsetAsync(h->scal.p, 0, sizeof(CgScalars), s));
+        TE_CHECK_HIP(hipMemcpyAsync(S->active, active.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // zero-guess columns that are already converged stay untouched (alpha = 0)
+        precondition(h, h->r.p, h->z.p, m, mixed, s);
+        dot_rz(h->r.p, h->z.p, nullptr, rows, m, part, s);
+        reduce_pairs(part, dot_nblocks(rows), m, sums, s);
+        cg_rz0(S, sums, m, s);
+        TE_CHECK_HIP(hipMemcpyAsync(h->p.p, h->z.p, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+        TE_CHECK_HIP(hipMemcpyAsync(flags.data(), S->flag, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < m; ++j)
+            if (active[j] && flags[j]) {
+                TE_REQUIRE(flags[j] != 3, TE_ENAN, "NaN in (r,z) of column %d", j);
+                TE_REQUIRE(false, TE_EINDEF, "CG breakdown at start: (r,z) <= 0 in column %d", j);
+            }
+    }
+    int it = 0;
+    while (n_active > 0 && it < o.maxit) {
+        ++it;
+        h->prof.begin(TE_K_AP);
+        sell_dot(L0.A, h->p.p, h->q.p, m, part, s);
+        h->prof.end(TE_K_AP);
+        h->prof.begin(TE_K_VECTOR);
+        reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+        cg_alpha(S, sums, m, s);
+        cg_update(h->u.p, h->r.p, mixed ? h->r_old.p : nullptr, h->p.p, h->q.p, S->alpha, rows, m, part, s);
+        reduce_partials(part, dot_nblocks(rows), m, sums, s);
+        h->prof.end(TE_K_VECTOR);
+        TE_CHECK_HIP(hipMemcpyAsync(flags.data(), S->flag, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        fetch(sums, m, rr, s);
+        std::vector<int32_t> cand(m, 0);
+        bool any_cand = false;
+        for (int j = 0; j < m; ++j) {
+            if (!active[j]) continue;
+            if (flags[j] == 3 || !std::isfinite(rr[j])) TE_REQUIRE(false, TE_ENAN, "NaN in CG column %d", j);
+            if (flags[j]) TE_REQUIRE(false, TE_EINDEF, "CG breakdown in column %d at iteration %d: (p,Ap) <= 0", j, it);
+            iters[j] = it;
+            const double rel = std::sqrt(rr[j] / bb[j]);
+            if (rep && rep->history) rep->history[(size_t)it * m + j] = rel;
+            if (rel <= o.rtol) {
+                cand[j] = 1;
+                any_cand = true;
+            }
+        }
+        if (any_cand) {
+            sell_resid_norm(L0.A, h->u.p, h->b.p, h->t.p, m, part, s);
+            reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+            fetch(sums, m, tr, s);
+            std::vector<int32_t> repl(64, 0);
+            bool any_repl = false, changed = false;
+            for (int j = 0; j < m; ++j) {
+                if (!cand[j]) continue;
+                const double rel = std::sqrt(tr[j] / bb[j]);
+                if (rel <= o.rtol) {
+                    conv[j] = 1;
+                    active[j] = 0;
+                    --n_active;
+                    changed = true;
+                } else if (replaced[j] < o.max_replace) {
+                    ++replaced[j];
+                    repl[j] = 1;
+                    any_repl = true;
+                } else {
+                    active[j] = 0;
+                    --n_active;
+                    changed = true;
+                }
+            }
+            if (any_repl) {
+                DBuf<int32_t> dsel(64);
+                TE_CHECK_HIP(hipMemcpyAsync(dsel.p, repl.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+                copy_cols(h->r.p, h->t.p, dsel.p, nv, m, s);
+                TE_CHECK_HIP(hipStreamSynchronize(s));
+            }
+            if (changed)
+                TE_CHECK_HIP(hipMemcpyAsync(S->active, active.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        }
+        if (n_active == 0) break;
+        precondition(h, h->r.p, h->z.p, m, mixed, s);
+        h->prof.begin(TE_K_VECTOR);
+        dot_rz(h->r.p, h->z.p, mixed ? h->r_old.p : nullptr, rows, m, part, s);
+        reduce_pairs(part, dot_nblocks(rows), m, sums, s);
+        cg_beta(S, sums, m, mixed ? 1 : 0, s);
+        p_update(h->p.p, h->z.p, S->beta, nv, m, s);
+        h->prof.end(TE_K_VECTOR);
+    }
+    // final true residual of every column
+    sell_resid_norm(L0.A, h->u.p, h->b.p, h->t.p, m, part, s);
+    reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+    permute_scatter(h->u.p, u_nat, L0.perm.p, n, 3, m, s);
+    TE_CHECK_HIP(hipEventRecord(e1, s));
+    fetch(sums, m, tr, s);
+    float ms = 0.f;
+    TE_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    bool all_conv = true;
+    int maxit_seen = 0;
+    for (int j = 0; j < m; ++j) {
+        const double rel = bb[j] > 0 ? std::sqrt(tr[j] / bb[j]) : 0.0;
+        if (bb[j] > 0) conv[j] = conv[j] && rel <= o.rtol;
+        all_conv = all_conv && conv[j];
+        maxit_seen = std::max(maxit_seen, iters[j]);
+        if (rep) {
+            if (rep->iters) rep->iters[j] = iters[j];
+            if (rep->converged) rep->converged[j] = conv[j];
+            if (rep->relres_true) rep->relres_true[j] = rel;
+        }
+    }
+    if (rep) {
+        rep->max_iters = maxit_seen;
+        rep->time_ms = ms;
+        for (int c = 0; c < TE_K_COUNT; ++c) {
+            double t = 0.0;
+            for (int i = 0; i < h->prof.used[c]; ++i) {
+                float e = 0.f;
+                TE_CHECK_HIP(hipEventElapsedTime(&e, h->prof.ev[c][2 * i], h->prof.ev[c][2 * i + 1]));
+                t += e;
+            }
+            rep->kernel_ms[c] = t;
+            rep->kernel_launches[c] = h->prof.used[c];
+        }
+    }
+    h->prof.reset(false, s);
+    return all_conv ? TE_OK : TE_ENOTCONV;
+}
+
+// ---------------------------------------------------------------------------
+// component access for tests (natural numbering of the level)
+// ---------------------------------------------------------------------------
+static void to_f32(const double *x, DBuf<float> &y, int64_t n, hipStream_t s) {
+    y.alloc(n);
+    cast_f64_f32(x, y.p, n, s);
+}
+
+static int apply_impl(amg_handle *h, int l, int op, int prec, const double *x, double *y, hipStream_t s) {
+    TE_REQUIRE(h && x && y, TE_EINVAL, "NULL argument");
+    TE_REQUIRE(l >= 0 && l < (int)h->L.size(), TE_EINVAL, "bad level %d", l);
+    const bool f32 = prec == TE_PREC_MIXED;
+    TE_REQUIRE(!f32 || h->opt.build_fp32, TE_EINVAL, "float32 copies not built");
+    h->prof.reset(false, s);
+    Level &L = h->L[l];
+    const int64_t nl = L.n * L.bs;
+    const bool has_next = l + 1 < (int)h->L.size();
+    TE_REQUIRE(op == TE_OP_A || op == TE_OP_VCYCLE || has_next, TE_EINVAL, "level %d has no transfer/smoother", l);
+    Level *N = has_next ? &h->L[l + 1] : nullptr;
+    const int64_t nn = N ? N->n * N->bs : 0;
+    DBuf<double> xs, ys;
+    switch (op) {
+        case TE_OP_A:
+        case TE_OP_SMOOTH:
+        case TE_OP_VCYCLE: {
+            xs.alloc(nl);
+            ys.alloc(nl);
+            permute_gather(x, xs.p, L.perm.p, L.n, L.bs, 1, s);
+            if (op == TE_OP_SMOOTH) permute_gather(y, ys.p, L.perm.p, L.n, L.bs, 1, s);
+            if (!f32) {
+                if (op == TE_OP_A) sell_apply<double>(L.A, xs.p, ys.p, nullptr, 0, 1, s);
+                else if (op == TE_OP_SMOOTH) smooth_from<double>(h, L, xs.p, ys.p, 1, s);
+                else vcycle<double>(h, l, xs.p, ys.p, 1, s);
+            } else {
+                DBuf<float> x32, y32;
+                to_f32(xs.p, x32, nl, s);
+                y32.alloc(nl);
+                if (op == TE_OP_SMOOTH) cast_f64_f32(ys.p, y32.p, nl, s);
+                if (op == TE_OP_A) sell_apply<float>(L.A, x32.p, y32.p, nullptr, 0, 1, s);
+                else if (op == TE_OP_SMOOTH) smooth_from<float>(h, L, x32.p, y32.p, 1, s);
+                else vcycle<float>(h, l, x32.p, y32.p, 1, s);
+                cast_f32_f64(y32.p, ys.p, nl, s);
+                TE_CHECK_HIP(hipStreamSynchronize(s));
+            }
+            permute_scatter(ys.p, y, L.perm.p, L.n, L.bs, 1, s);
+            break;
+        }
+        case TE_OP_P: {
+            xs.alloc(nn);
+            ys.alloc(nl);
+            permute_gather(x, xs.p, N->perm.p, N->n, N->bs, 1, s);
+            TE_CHECK_HIP(hipMemsetAsync(ys.p, 0, nl * sizeof(double), s));
+            if (!f32) {
+                sell_apply<double>(L.P, xs.p, ys.p, nullptr, 1, 1, s);
+            } else {
+                DBuf<float> x32, y32(nl);
+                to_f32(xs.p, x32, nn, s);
+                TE_CHECK_HIP(hipMemsetAsync(y32.p, 0, nl * sizeof(float), s));
+                sell_apply<float>(L.P, x32.p, y32.p, nullptr, 1, 1, s);
+                cast_f32_f64(y32.p, ys.p, nl, s);
+                TE_CHECK_HIP(hipStreamSynchronize(s));
+            }
+            permute_scatter(ys.p, y, L.perm.p, L.n, L.bs, 1, s);
+            break;
+        }
+        case TE_OP_R: {
+            xs.alloc(nl);
+            ys.alloc(nn);
+            permute_gather(x, xs.p, L.perm.p, L.n, L.bs, 1, s);
+            if (!f32) {
+                sell_apply<double>(L.R, xs.p, ys.p, nullptr, 0, 1, s);
+            } else {
+                DBuf<float> x32, y32(nn);
+                to_f32(xs.p, x32, nl, s);
+                sell_apply<float>(L.R, x32.p, y32.p, nullptr, 0, 1, s);
+                cast_f32_f64(y32.p, ys.p, nn, s);
+                TE_CHECK_HIP(hipStreamSynchronize(s));
+            }
+            permute_scatter(ys.p, y, N->perm.p, N->n, N->bs, 1, s);
+            break;
+        }
+        default:
+            TE_REQUIRE(false, TE_EINVAL, "unknown op %d", op);
+    }
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    return TE_OK;
+}
+
+}  // namespace te
+
+using namespace te;
+
+extern "C" void pcg_options_default(pcg_options *o) {
+    if (!o) return;
+    o->rtol = 1e-8;
+    o->maxit = 500;
+    o->precision = TE_PREC_FP64;
+    o->max_replace = 3;
+    o->profile = 0;
+}
+
+extern "C" int amg_pcg_solve(amg_handle *h, const double *b, double *u, int32_t nrhs, const pcg_options *opt,
+                             pcg_report *rep, hipStream_t stream) {
+    return guarded([&] { return solve_impl(h, b, u, nrhs, opt, rep, stream); });
+}
+
+extern "C" int amg_apply(amg_handle *h, int32_t level, int32_t op, int32_t precision, const double *x, double *y,
+                         hipStream_t stream) {
+    return guarded([&] { return apply_impl(h, level, op, precision, x, y, stream); });
+}

@@ -1,0 +1,131 @@
+"""GPU smoothed-aggregation hierarchy and its components against the oracle.
+
+The hierarchy is built from the oracle's own matrix (uploaded), so both sides
+make the integer decisions (strength threshold, aggregation, rank check) on
+the same numbers: aggregates must agree exactly.  Level operators, transfer
+operators, smoother and V-cycle then agree to rounding.
+
+Tolerances (float64): a sparse product row with t terms differs between two
+correct summation orders by at most ~t * eps * (|A||x|)_i; with t <= 6*80 terms
+this is below 1e-13 relative to |A||x|, written as SPMV_TOL below.  Composite
+operators (smoothed P, Galerkin product, V-cycle) compound a few such steps
+and use 1e-11 relative to the operator scale."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import meshgen as mg
+from oracle import amg, fem
+from tests.gpu_util import dev, oracle_bsr_to_device, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+SPMV_TOL = 1e-13
+OP_TOL = 1e-11
+
+
+def _oracle_system(prob):
+    A, b, _, _ = fem.assemble_problem(prob)
+    B = fem.rigid_body_modes(prob.mesh.coords, prob.mask)
+    return A, b, B
+
+
+def _gpu_amg_from_oracle_matrix(prob, A, **opts):
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    say("amg_setup from oracle matrix", prob.name)
+    return te.AMG(oracle_bsr_to_device(A), dev(prob.mesh.coords, torch.float64), dev(prob.mask), **opts)
+
+
+@pytest.fixture(scope="module")
+def cube_case():
+    prob = mg.cube_problem(16, 1)
+    A, b, B = _oracle_system(prob)
+    levels = amg.setup(A, B)
+    h = _gpu_amg_from_oracle_matrix(prob, A)
+    return prob, A, b, B, levels, h
+
+
+@pytest.fixture(scope="module")
+def disc_case():
+    # P2 disc with three levels at a reduced coarse size
+    prob = mg.disc_problem(8, 34, 2, 2, seed=5)
+    A, b, B = _oracle_system(prob)
+    opt = amg.AMGOptions(coarse_max=400)
+    levels = amg.setup(A, B, opt)
+    h = _gpu_amg_from_oracle_matrix(prob, A, coarse_max=400)
+    return prob, A, b, B, levels, h
+
+
+@pytest.mark.parametrize("case", ["cube_case", "disc_case"])
+def test_hierarchy_matches_oracle(case, request):
+    prob, A, b, B, levels, h = request.getfixturevalue(case)
+    info = h.info()
+    assert info["n_levels"] == len(levels)
+    for l, lv in enumerate(levels):
+        assert info["n_dof"][l] == lv.A.shape[0]
+        if l + 1 < len(levels):
+            assert np.array_equal(h.aggregates(l), lv.agg), f"aggregates differ at level {l}"
+            assert abs(info["lambda_hat"][l] - lv.lam) <= 1e-10 * lv.lam
+        rp, col, val = h.level_matrix(l)
+        bs = lv.bs
+        G = sp.bsr_matrix((val, col, rp), shape=lv.A.shape).tocsr()
+        D = (G - lv.A.tocsr())
+        scale = np.abs(lv.A.data).max()
+        assert (abs(D).max() if D.nnz else 0.0) <= OP_TOL * scale, f"A_{l} differs"
+        assert bs == info["bs"][l]
+
+
+@pytest.mark.parametrize("case", ["cube_case", "disc_case"])
+def test_level_operators_and_transfers(case, request):
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob, A, b, B, levels, h = request.getfixturevalue(case)
+    rng = np.random.default_rng(1)
+    for l, lv in enumerate(levels):
+        x = rng.normal(size=lv.A.shape[0])
+        y = h.apply(l, te.TE_OP_A, dev(x, torch.float64)).cpu().numpy()
+        ref = lv.A @ x
+        bound = (abs(lv.A) @ np.abs(x))
+        assert np.all(np.abs(y - ref) <= SPMV_TOL * bound + 1e-300), f"A_{l} x"
+        if l + 1 < len(levels):
+            xc = rng.normal(size=lv.P.shape[1])
+            yp = h.apply(l, te.TE_OP_P, dev(xc, torch.float64)).cpu().numpy()
+            refp = lv.P @ xc
+            assert np.abs(yp - refp).max() <= OP_TOL * (abs(lv.P) @ np.abs(xc)).max(), f"P_{l}"
+            yr = h.apply(l, te.TE_OP_R, dev(x, torch.float64)).cpu().numpy()
+            refr = lv.R @ x
+            assert np.abs(yr - refr).max() <= OP_TOL * (abs(lv.R) @ np.abs(x)).max(), f"R_{l}"
+
+
+@pytest.mark.parametrize("case", ["cube_case", "disc_case"])
+def test_smoother_and_vcycle(case, request):
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob, A, b, B, levels, h = request.getfixturevalue(case)
+    rng = np.random.default_rng(2)
+    lv = levels[0]
+    g = rng.normal(size=A.shape[0])
+    x0 = rng.normal(size=A.shape[0])
+    y = h.apply(0, te.TE_OP_SMOOTH, dev(g, torch.float64), dev(x0, torch.float64)).cpu().numpy()
+    ref = amg.chebyshev(lv.A, lv.D, g, x0, lv.lam)
+    assert np.abs(y - ref).max() <= OP_TOL * np.abs(ref).max()
+    z = h.apply(0, te.TE_OP_VCYCLE, dev(g, torch.float64)).cpu().numpy()
+    zr = amg.vcycle(levels, g)
+    assert np.abs(z - zr).max() <= 1e-10 * np.abs(zr).max()
+    # float32 V-cycle: close to the float64 one at single-precision level
+    z32 = h.apply(0, te.TE_OP_VCYCLE, dev(g, torch.float64), precision=te.TE_PREC_MIXED).cpu().numpy()
+    assert np.abs(z32 - zr).max() <= 1e-3 * np.abs(zr).max()
+
+
+def test_imposed_aggregates_reproduce_hierarchy(disc_case):
+    """amg_setup_with_aggregates with the oracle's maps gives the same hierarchy."""
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob, A, b, B, levels, h = disc_case
+    aggs = [lv.agg for lv in levels[:-1]]
+    h2 = te.AMG(oracle_bsr_to_device(A), dev(prob.mesh.coords, torch.float64), dev(prob.mask), aggregates=aggs,
+                coarse_max=400)
+    assert h2.info()["n_dof"] == h.info()["n_dof"]
+    for l in range(len(levels) - 1):
+        assert np.array_equal(h2.aggregates(l), levels[l].agg)

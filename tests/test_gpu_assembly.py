@@ -1,0 +1,113 @@
+"""GPU assembly (fe_assemble_pattern / fe_assemble_thermoelastic /
+fe_assemble_load) against the oracle, element by element.
+
+Tolerance: each assembled entry is a sum of at most 24 element contributions
+(P2 vertex rows) of products of a few float64 terms, so the rounding of two
+correct implementations differs by a small multiple of eps * max|K|; the bar is
+1e-13 * max|A| (and 1e-13 * max|b| for the load), written in each test."""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from oracle import fem
+from tests.gpu_util import dev, gpu_assemble, matrix_to_host, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-13
+
+
+def _compare(prob, u_bc=None):
+    A, b, _ = gpu_assemble(prob, u_bc)
+    rp, col, val = matrix_to_host(A)
+    Ao, bo, _, _ = fem.assemble_problem(prob, u_bc)
+    assert np.array_equal(rp, Ao.indptr)
+    assert np.array_equal(col, Ao.indices)
+    scale = np.abs(Ao.data).max()
+    assert np.abs(val - Ao.data).max() <= TOL * scale
+    bg = b.cpu().numpy()
+    assert np.abs(bg - bo).max() <= TOL * max(np.abs(bo).max(), 1e-300)
+    return A, b
+
+
+def test_cube_p1_config_matches_oracle():
+    _compare(mg.cube_problem(16, 1))
+
+
+def test_disc_p2_several_tiles_ragged():
+    prob = mg.disc_problem(6, 26, 2, 2, seed=3)   # 4173 nodes: 66 slices, ragged tail
+    assert prob.mesh.n_nodes % 64 != 0
+    _compare(prob)
+
+
+def test_body_force_and_nonzero_dirichlet_p1_p2():
+    for deg, prob in [(1, mg.disc_problem(5, 20, 2, 1, seed=4)), (2, mg.cube_problem(3, 2))]:
+        rng = np.random.default_rng(deg)
+        n = prob.mesh.n_nodes
+        prob.f = rng.normal(size=(n, 3)) * 1e3
+        prob.mask = (rng.uniform(size=(n, 3)) < 0.2).astype(np.uint8)
+        u_bc = rng.normal(size=(n, 3)) * 1e-3
+        _compare(prob, u_bc)
+
+
+def test_load_only_multiple_cases():
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob = mg.disc_problem(5, 22, 2, 1, seed=0)
+    m = prob.mesh
+    Ts = np.stack([mg.disc_temperature_bumps(m, s) for s in (1000, 1001, 1002)])
+    rng = np.random.default_rng(2)
+    fs = rng.normal(size=(3, m.n_nodes, 3)) * 1e6
+    say("assemble_load nrhs=3")
+    b = te.assemble_load(dev(m.coords, torch.float64), dev(m.cells.astype(np.int32)), 1, prob.E, prob.nu,
+                         prob.alpha, prob.T_ref, dev(Ts, torch.float64), f=dev(fs, torch.float64),
+                         mask=dev(prob.mask)).cpu().numpy()
+    for j in range(3):
+        _, bo = fem.assemble(m.coords, m.cells, 1, prob.E, prob.nu, prob.alpha, prob.T_ref, Ts[j], fs[j])
+        bo[prob.mask.astype(bool)] = 0.0
+        assert np.abs(b[:, :, j] - bo).max() <= TOL * np.abs(bo).max()
+
+
+def test_invalid_mesh_rejected():
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    m = mg.cube_mesh(2, 1)
+    cells = m.cells.copy()
+    cells[3, 2] = m.n_nodes + 5  # out of range: the host check must reject it before assembly
+    with pytest.raises(te.TeError, match="TE_EINVAL"):
+        te.assemble(dev(m.coords, torch.float64), dev(cells), 1, 1.0, 0.3, 1e-3, 300.0,
+                    dev(np.full(m.n_nodes, 301.0), torch.float64))
+
+
+def test_full_size_disc_p2_sampled_rows():
+    """The 12,043,200-DOF disc at full size: sampled block rows (vertex, edge,
+    face, centre, bore and rim nodes) against the oracle, plus symmetry of the
+    sampled blocks and the row sums of the unconstrained operator."""
+    nr, nth, nz, deg = mg.DISC_P2_12M
+    prob = mg.disc_problem(nr, nth, nz, deg, seed=0)
+    m = prob.mesh
+    assert m.n_dof == 12_043_200
+    A, b, _ = gpu_assemble(prob)
+    assert A.nnzb == 112_293_376
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([rng.integers(0, m.n_nodes, 24), [0, 1, 12, 13, 25, 26, m.n_nodes - 1]]))
+    rp = A.row_ptr.cpu().numpy()
+    ref = fem.assemble_rows(m.coords, m.cells, deg, prob.E, prob.nu, prob.alpha, prob.T_ref, prob.T, rows)
+    mask = prob.mask.astype(bool)
+    for r in rows.tolist():
+        cols_o, blocks_o, b_o = ref[r]
+        lo, hi = int(rp[r]), int(rp[r + 1])
+        cols_g = A.col_idx[lo:hi].cpu().numpy()
+        blk_g = A.val[lo:hi].cpu().numpy()
+        assert np.array_equal(cols_g, cols_o)
+        # apply the Dirichlet elimination to the oracle row (u_bc = 0)
+        blocks_o = blocks_o.copy()
+        for k, c in enumerate(cols_o.tolist()):
+            for p in range(3):
+                for q in range(3):
+                    if mask[r, p] or mask[c, q]:
+                        blocks_o[k, p, q] = 1.0 if (c == r and p == q) else 0.0
+        b_o = np.where(mask[r], 0.0, b_o)
+        scale = np.abs(blocks_o).max()
+        assert np.abs(blk_g - blocks_o).max() <= TOL * scale
+        assert np.abs(b[3 * r:3 * r + 3].cpu().numpy() - b_o).max() <= TOL * max(np.abs(b_o).max(), 1.0)
