@@ -193,6 +193,19 @@ def main():
                                   "post_init": "k_sell1<3,3,double,double,double,EpiChebInit<double>>"}[dom],
                 "algo_bytes_per_launch": kernels[dom]["algo_bytes"]}
 
+    # HBM traffic of the dominant kernel from the committed counter runs,
+    # valid only while the kernel source is the one that was measured
+    tj = os.path.join(ROOT, "profiles", "disc_p2_12M_fp64_traffic.json")
+    if os.path.exists(tj) and (nr, nth, nz, deg) == (96, 416, 12, 2):
+        import hashlib
+        t = json.load(open(tj))
+        csrc = os.path.join(ROOT, "paper_1804_10060_amd", "csrc")
+        h = hashlib.sha256(open(os.path.join(csrc, "te_kernels.hip"), "rb").read() +
+                           open(os.path.join(csrc, "te_internal.h"), "rb").read()).hexdigest()
+        if h == t.get("kernel_source_sha256") and dom in t.get("per_launch", {}):
+            roofline["traffic"] = t["per_launch"][dom]["traffic_bytes"]
+            roofline["traffic_source"] = "profiles/disc_p2_12M_fp64_hbm_counters.md"
+
     forms = {}
     if not args.no_forms:
         u64 = u.clone()

@@ -242,6 +242,49 @@ int amg_pcg_solve(amg_handle *h, const double *b, double *u, int32_t nrhs,
 /* Releases everything the handle owns.  NULL is accepted. */
 int amg_destroy(amg_handle *h);
 
+/* ---- learned initial guess (message-passing network, float32) ---------
+ * The paper starts each transient elastic solve from the previous step's
+ * displacement (Sec. 5.3).  This network maps the load instead:
+ *   h0 = relu(X W_in + b_in);  4 layers of
+ *   h  = h + relu(h W_s + mean_{N(v)} h W_n + mean_V h W_g + b);
+ *   y  = (h W_out + b_out) * (1 - mask),  u0 = 1e-3 * y.
+ * Features X[v] = [(T-T_ref)/500, f/2e9 (3), mask (3), (x - centroid)/0.5 (3)].
+ * Parameters: one float array of mpnn_param_count() entries in the order
+ * W_in[10][64], b_in[64], per layer {W_s,W_n,W_g}[64][64], b[64],
+ * W_out[64][3], b_out[3] (weights [in][out]). */
+typedef struct mpnn_handle mpnn_handle;
+
+int64_t mpnn_param_count(void);
+
+/* Graph and workspace for a mesh of N vertices.  row_ptr/col_idx: the P1
+ * stiffness pattern (device, as produced by fe_assemble_pattern); its
+ * diagonal is dropped.  coords: device [N][3].  Synchronises `stream`. */
+int mpnn_create(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const double *coords,
+                mpnn_handle **out, hipStream_t stream);
+int mpnn_destroy(mpnn_handle *h);
+
+/* X [N][10] float from T [N], f [N][3] or NULL, mask [N][3] (device). */
+int mpnn_features(mpnn_handle *h, const double *T, double T_ref, const double *f, const uint8_t *mask,
+                  float *X, hipStream_t stream);
+
+/* y [N][3] = network output (may be NULL: kept inside the handle); the
+ * activations are kept for mpnn_backward. */
+int mpnn_forward(mpnn_handle *h, const float *params, const float *X, const uint8_t *mask, float *y,
+                 hipStream_t stream);
+
+/* Mean squared error of the last forward against target [N][3] (the
+ * displacement divided by 1e-3) into *loss (host, may be NULL) and its
+ * gradient with respect to every parameter into grad.  Synchronises. */
+int mpnn_backward(mpnn_handle *h, const float *params, const float *target, float *grad, double *loss,
+                  hipStream_t stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on n entries. */
+int mpnn_adam_step(int64_t n, float *params, const float *grad, float *m, float *v, int32_t step, float lr,
+                   float beta1, float beta2, float eps, hipStream_t stream);
+
+/* u0 [N][3] float64 = 1e-3 * y of the last forward. */
+int mpnn_guess(mpnn_handle *h, double *u0, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,8 +14,8 @@ from . import _lib
 from ._lib import (TE_OP_A, TE_OP_P, TE_OP_R, TE_OP_SMOOTH, TE_OP_VCYCLE, TE_PREC_FP64, TE_PREC_MIXED, TeError,
                    check, load)
 
-__all__ = ["assemble", "assemble_load", "AMG", "Matrix", "TeError", "load", "TE_PREC_FP64", "TE_PREC_MIXED",
-           "TE_OP_A", "TE_OP_P", "TE_OP_R", "TE_OP_SMOOTH", "TE_OP_VCYCLE"]
+__all__ = ["assemble", "assemble_load", "AMG", "MPNN", "Matrix", "TeError", "load", "TE_PREC_FP64",
+           "TE_PREC_MIXED", "TE_OP_A", "TE_OP_P", "TE_OP_R", "TE_OP_SMOOTH", "TE_OP_VCYCLE"]
 
 
 def _torch():
@@ -238,3 +238,61 @@ class AMG:
         h = hist.reshape(maxit + 1, nrhs) if hist is not None else None
         return u, SolveReport(iters.tolist(), conv.tolist(), rel.tolist(), h, rep.max_iters, rep.time_ms, code,
                               list(rep.kernel_ms), list(rep.kernel_launches))
+
+
+class MPNN:
+    """mpnn_create / features / forward / backward / Adam / guess (float32)."""
+
+    def __init__(self, A: Matrix, coords):
+        torch = _torch()
+        lib = load()
+        _dev(coords, torch.float64, (A.n, 3), "coords")
+        self.n = A.n
+        self.n_params = int(lib.mpnn_param_count())
+        self._h = C.c_void_p(0)
+        check(lib.mpnn_create(A.n, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(coords), C.byref(self._h), _stream()))
+        self.device = coords.device
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            load().mpnn_destroy(h)
+            self._h = C.c_void_p(0)
+
+    def features(self, T, T_ref, mask, f=None):
+        torch = _torch()
+        _dev(T, torch.float64, (self.n,), "T")
+        _dev(mask, torch.uint8, (self.n, 3), "mask")
+        _dev(f, torch.float64, (self.n, 3), "f")
+        X = torch.empty((self.n, 10), dtype=torch.float32, device=self.device)
+        check(load().mpnn_features(self._h, _ptr(T), T_ref, _ptr(f), _ptr(mask), _ptr(X), _stream()))
+        return X
+
+    def forward(self, params, X, mask):
+        torch = _torch()
+        _dev(params, torch.float32, (self.n_params,), "params")
+        _dev(X, torch.float32, (self.n, 10), "X")
+        _dev(mask, torch.uint8, (self.n, 3), "mask")
+        y = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
+        check(load().mpnn_forward(self._h, _ptr(params), _ptr(X), _ptr(mask), _ptr(y), _stream()))
+        return y
+
+    def backward(self, params, target):
+        """Gradient of the mean squared error of the last forward; returns (grad, loss)."""
+        torch = _torch()
+        _dev(target, torch.float32, (self.n, 3), "target")
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        loss = C.c_double(0.0)
+        check(load().mpnn_backward(self._h, _ptr(params), _ptr(target), _ptr(grad), C.byref(loss), _stream()))
+        return grad, loss.value
+
+    def adam_step(self, params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        check(load().mpnn_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, b1, b2,
+                                    eps, _stream()))
+
+    def guess(self):
+        """u0 [3N] float64 from the last forward."""
+        torch = _torch()
+        u0 = torch.empty(3 * self.n, dtype=torch.float64, device=self.device)
+        check(load().mpnn_guess(self._h, _ptr(u0), _stream()))
+        return u0

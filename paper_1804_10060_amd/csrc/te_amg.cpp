@@ -516,9 +516,66 @@ std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_
     return ord;
 }
 
+static void build_rowwave(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order,
+                          const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32,
+                          hipStream_t s) {
+    const int bb = M.br * M.bc;
+    S.format = FMT_ROWWAVE;
+    S.br = M.br;
+    S.bc = M.bc;
+    S.nrows = M.nr;
+    S.ncols = M.nc;
+    S.nnzb = M.nnzb();
+    S.nslices = 0;
+    S.padded = M.nnzb();
+    std::vector<int64_t> rptr(M.nr + 1, 0);
+    for (int64_t r = 0; r < M.nr; ++r) {
+        const int64_t o = row_order[r];
+        rptr[r + 1] = rptr[r] + (M.ptr[o + 1] - M.ptr[o]);
+    }
+    std::vector<int32_t> col(M.nnzb());
+    std::vector<double> val((size_t)M.nnzb() * bb);
+    parallel_for(M.nr, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t r = lo; r < hi; ++r) {
+            const int64_t o = row_order[r];
+            for (int64_t k = 0; k < M.ptr[o + 1] - M.ptr[o]; ++k) {
+                const int64_t src = M.ptr[o] + k, dst = rptr[r] + k;
+                col[dst] = col_map[M.col[src]];
+                std::copy(&M.val[(size_t)src * bb], &M.val[(size_t)(src + 1) * bb], &val[(size_t)dst * bb]);
+            }
+        }
+    });
+    upload(S.rptr, rptr, s);
+    upload(S.col, col, s);
+    upload(S.val, val, s);
+    S.slice_off.release();
+    S.rowlen.release();
+    if (fp32) {
+        std::vector<float> v32(val.size());
+        for (size_t i = 0; i < val.size(); ++i) v32[i] = (float)val[i];
+        upload(S.val32, v32, s);
+    } else {
+        S.val32.release();
+    }
+    if (out_map) {
+        std::vector<int32_t> rm(M.nr);
+        for (int64_t r = 0; r < M.nr; ++r) rm[r] = (*out_map)[row_order[r]];
+        upload(S.rowmap, rm, s);
+    } else {
+        S.rowmap.release();
+    }
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
 void build_sell(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map,
-                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s) {
+                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s, int format) {
+    if (format == FMT_ROWWAVE) {
+        build_rowwave(S, M, row_order, col_map, out_map, fp32, s);
+        return;
+    }
     const int br = M.br, bc = M.bc, bb = br * bc;
+    S.format = FMT_SELL;
+    S.rptr.release();
     S.br = br;
     S.bc = bc;
     S.nrows = M.nr;
@@ -732,12 +789,16 @@ static void rigid_body_modes(const std::vector<double> &X, const std::vector<uin
     }
 }
 
+// Lane-per-row SELL for operators with 3-row blocks (many short rows); one
+// wave per row for 6-row blocks (coarse operators, restrictions).
+static int fmt_for(const HBsr &M) { return M.br >= 6 ? FMT_ROWWAVE : FMT_SELL; }
+
 static void finish_level(Level &L, const amg_options &o, hipStream_t s) {
     // storage order and operator
     L.perm_h = window_sorted_order(L.Ah.ptr, 4096);
     L.iperm_h.assign(L.n, 0);
     for (int64_t i = 0; i < L.n; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
-    build_sell(L.A, L.Ah, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s);
+    build_sell(L.A, L.Ah, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.Ah));
     upload(L.perm, L.perm_h, s);
     std::vector<double> dnat;
     bsr_diag_points(L.Ah, dnat);
@@ -914,9 +975,9 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
         Level &L = h->L[l];
         Level &N = h->L[l + 1];
         auto pord = window_sorted_order(L.Ph.ptr, 4096);
-        build_sell(L.P, L.Ph, pord, N.iperm_h, &L.iperm_h, o.build_fp32 != 0, s);
-        auto rord = window_sorted_order(L.Rh.ptr, 4096);
-        build_sell(L.R, L.Rh, rord, L.iperm_h, &N.iperm_h, o.build_fp32 != 0, s);
+        build_sell(L.P, L.Ph, pord, N.iperm_h, &L.iperm_h, o.build_fp32 != 0, s, fmt_for(L.Ph));
+        // restriction rows in the coarse level's own order: contiguous output
+        build_sell(L.R, L.Rh, N.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.Rh));
     }
     note("transfer operators packed", (int)h->L.size() - 1, 0, 0);
     // coarsest level: dense inverse of (A + A^T)/2 in storage order

@@ -119,7 +119,15 @@ struct HBsr {
 // Padding entries carry a zero block and a valid column.
 constexpr int SELL_C = 64;
 
+// Second layout for operators whose rows are few and long (6-row blocks:
+// coarse operators and the restrictions): format 1 stores the blocks of a row
+// contiguously (val[k][br][bc], rptr[row]..rptr[row+1]) and one wave handles
+// one row, lane = (block slot, row of the block).
+constexpr int FMT_SELL = 0;
+constexpr int FMT_ROWWAVE = 1;
+
 struct Sell {
+    int format = FMT_SELL;
     int br = 0, bc = 0;
     int64_t nrows = 0;          // block rows
     int64_t ncols = 0;          // block columns
@@ -132,8 +140,10 @@ struct Sell {
     DBuf<double> val;           // [padded * br*bc]
     DBuf<float> val32;          // optional float32 copy
     DBuf<int32_t> rowmap;       // [nslices*64] output row of each lane, -1 = none; empty = identity
+    DBuf<int64_t> rptr;         // format 1: [nrows+1] block offset of each stored row
     size_t bytes() const {
-        return slice_off.bytes() + col.bytes() + rowlen.bytes() + val.bytes() + val32.bytes() + rowmap.bytes();
+        return slice_off.bytes() + col.bytes() + rowlen.bytes() + val.bytes() + val32.bytes() + rowmap.bytes() +
+               rptr.bytes();
     }
 };
 
@@ -143,7 +153,7 @@ struct Sell {
 //   out_map      = if non-null, position i writes output row (*out_map)[row_order[i]];
 //                  otherwise position i writes output row i
 void build_sell(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map,
-                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s);
+                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s, int format = FMT_SELL);
 
 // Row order sorted by descending length inside windows of `window` rows.
 std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_t window);

@@ -165,6 +165,106 @@ __global__ void __launch_bounds__(BLK) k_sellm(SellView<VT> A, const XT *__restr
     }
 }
 
+// One wave per stored row (format 1).  Lane = (block slot, row of the block):
+// with NB = 64 / BR slots, a wave consumes NB consecutive blocks per step,
+// i.e. one contiguous run of NB*BR*BC values, each lane reading the BC
+// contiguous values of one block row.  The BR row sums are then combined in
+// LDS in a fixed order and lane 0 runs the epilogue.
+template <typename VT>
+struct RowView {
+    const int64_t *__restrict__ rptr;
+    const int32_t *__restrict__ col;
+    const VT *__restrict__ val;
+    const int32_t *__restrict__ rowmap;
+    int64_t nrows;
+};
+
+template <typename VT>
+RowView<VT> rview(const Sell &S, const VT *val) {
+    return RowView<VT>{S.rptr.p, S.col.p, val, S.rowmap.p, S.nrows};
+}
+
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
+__global__ void __launch_bounds__(BLK) k_roww(RowView<VT> A, const XT *__restrict__ x, Epi epi,
+                                              double *__restrict__ partials) {
+    __shared__ AT lds[BLK];
+    __shared__ double rlds[WPB];
+    constexpr int NB = WAVE / BR;
+    const int64_t nb = gridDim.x;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int64_t row = lb * WPB + w;
+    const int slot = lane / BR, i = lane % BR;
+    AT acc = AT(0);
+    if (row < A.nrows && slot < NB) {
+        const int64_t hi = A.rptr[row + 1];
+        for (int64_t k = A.rptr[row] + slot; k < hi; k += NB) {
+            const int64_t c = A.col[k];
+            const VT *v = A.val + k * (BR * BC) + i * BC;
+#pragma unroll
+            for (int j = 0; j < BC; ++j) acc += AT(v[j]) * AT(x[c * BC + j]);
+        }
+    }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    double red = 0.0;
+    if (lane == 0 && row < A.nrows) {
+        AT r[BR];
+#pragma unroll
+        for (int q = 0; q < BR; ++q) {
+            AT t = AT(0);
+            for (int sl = 0; sl < NB; ++sl) t += lds[w * WAVE + sl * BR + q];
+            r[q] = t;
+        }
+        const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+        epi.template apply<BR>(out, r, red);
+    }
+    if (Epi::kReduce) {
+        double t = block_sum(red, rlds);
+        if (threadIdx.x == 0) partials[lb] = t;
+    }
+}
+
+// Format 1 with several right-hand sides: one wave per row, lane = RHS.
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
+__global__ void __launch_bounds__(BLK) k_rowwm(RowView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
+                                               double *__restrict__ partials) {
+    __shared__ double lds[BLK];
+    const int64_t nb = gridDim.x;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * WPB + threadIdx.x / WAVE));
+    double red = 0.0;
+    if (row < A.nrows && lane < nrhs) {
+        AT acc[BR];
+#pragma unroll
+        for (int i = 0; i < BR; ++i) acc[i] = AT(0);
+        const int64_t hi = A.rptr[row + 1];
+        for (int64_t k = A.rptr[row]; k < hi; ++k) {
+            const int64_t c = A.col[k];
+            const VT *v = A.val + k * (BR * BC);
+            AT xv[BC];
+#pragma unroll
+            for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
+#pragma unroll
+            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                for (int j = 0; j < BC; ++j) acc[i] += AT(v[i * BC + j]) * xv[j];
+        }
+        const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+        epi.template apply_m<BR>(out, lane, nrhs, acc, red);
+    }
+    if (Epi::kReduce) {
+        lds[threadIdx.x] = red;
+        __syncthreads();
+        if (threadIdx.x < WAVE && threadIdx.x < nrhs) {
+            double t = 0.0;
+            for (int w = 0; w < WPB; ++w) t += lds[w * WAVE + threadIdx.x];
+            partials[lb * nrhs + threadIdx.x] = t;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Epilogues
 // ---------------------------------------------------------------------------
@@ -339,7 +439,7 @@ struct EpiChebStep {
 // Launch helpers
 // ---------------------------------------------------------------------------
 static inline int64_t sell_grid(const Sell &A, int nrhs) {
-    if (nrhs == 1) return (A.nslices + WPB - 1) / WPB;
+    if (nrhs == 1 && A.format == FMT_SELL) return (A.nslices + WPB - 1) / WPB;
     return (A.nrows + WPB - 1) / WPB;
 }
 
@@ -350,12 +450,20 @@ static void launch_t(const Sell &A, const VT *val, const XT *x, const Epi &epi, 
                      hipStream_t s) {
     int64_t g = sell_grid(A, nrhs);
     if (g == 0) return;
-    if (nrhs == 1)
+    if (A.format == FMT_ROWWAVE) {
+        if (nrhs == 1)
+            hipLaunchKernelGGL((k_roww<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, rview(A, val),
+                               x, epi, partials);
+        else
+            hipLaunchKernelGGL((k_rowwm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s,
+                               rview(A, val), x, epi, nrhs, partials);
+    } else if (nrhs == 1) {
         hipLaunchKernelGGL((k_sell1<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, view(A, val), x,
                            epi, partials);
-    else
+    } else {
         hipLaunchKernelGGL((k_sellm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, view(A, val), x,
                            epi, nrhs, partials);
+    }
     TE_CHECK_HIP(hipGetLastError());
 }
 

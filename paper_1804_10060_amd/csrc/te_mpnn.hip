@@ -1,0 +1,537 @@
+// Message-passing network for the learned initial displacement guess:
+// forward, backward (hand-written adjoints) and Adam, float32, on the vertex
+// graph of a P1 mesh.  The paper starts each transient solve from the previous
+// step's displacement (Sec. 5.3); here the starting guess comes from the load.
+//
+//   h0   = relu(X W_in + b_in)                               X: [N, 10]
+//   for l < 4:  m = mean_{u in N(v)} h_u;  g = mean_v h_v
+//               h = h + relu(h W_s + m W_n + g W_g + b)
+//   y    = (h W_out + b_out) * (1 - mask)                    [N, 3]
+//
+// Layouts: activations [N][64] row-major; parameters one float array in the
+// order W_in[10][64], b_in[64], per layer {W_s, W_n, W_g}[64][64], b[64],
+// W_out[64][3], b_out[3] (weights [in][out]).
+//
+// Vertex kernels run one wave per vertex with the 64 channels on the lanes
+// (the neighbour gather is then a coalesced 256-byte row read); weight
+// gradients X^T Y are blocked reductions over vertices with per-block partial
+// tiles summed in a fixed order (deterministic, no atomics).  The graph is
+// symmetric, so the adjoint of the neighbour mean is again a gather:
+// d h_u = sum_{v in N(u)} d m_v / deg_v.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <memory>
+
+#include "te_internal.h"
+
+namespace te {
+
+constexpr int MH = 64, ML = 4, MF = 10, MO = 3;
+constexpr int64_t OFF_WIN = 0, OFF_BIN = MF * MH;
+constexpr int64_t LAYER0 = OFF_BIN + MH;
+constexpr int64_t LAYER_SZ = 3 * MH * MH + MH;
+constexpr int64_t OFF_WOUT = LAYER0 + ML * LAYER_SZ;
+constexpr int64_t OFF_BOUT = OFF_WOUT + MH * MO;
+constexpr int64_t NPARAM = OFF_BOUT + MO;
+constexpr float S_T = 500.f, S_F = 2.0e9f, S_X = 0.5f;
+constexpr double S_U = 1.0e-3;
+constexpr int MB = 256, MW = MB / 64;
+constexpr int RED_BLOCKS = 512;
+
+__host__ __device__ constexpr int64_t off_ws(int l) { return LAYER0 + l * LAYER_SZ; }
+__host__ __device__ constexpr int64_t off_wn(int l) { return LAYER0 + l * LAYER_SZ + MH * MH; }
+__host__ __device__ constexpr int64_t off_wg(int l) { return LAYER0 + l * LAYER_SZ + 2 * MH * MH; }
+__host__ __device__ constexpr int64_t off_b(int l) { return LAYER0 + l * LAYER_SZ + 3 * MH * MH; }
+
+static inline unsigned vgrid(int64_t n) {
+    int64_t g = (n + MW - 1) / MW;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+// features: X[v] = [dT/S_T, f/S_F, mask, xc/S_X]
+__global__ void k_features(int64_t n, const double *__restrict__ xc, const double *__restrict__ T, double T_ref,
+                           const double *__restrict__ f, const uint8_t *__restrict__ mask, float *__restrict__ X) {
+    for (int64_t v = blockIdx.x * (int64_t)MB + threadIdx.x; v < n; v += (int64_t)gridDim.x * MB) {
+        float *o = X + v * MF;
+        o[0] = float((T[v] - T_ref) / S_T);
+        for (int c = 0; c < 3; ++c) {
+            o[1 + c] = f ? float(f[v * 3 + c] / S_F) : 0.f;
+            o[4 + c] = mask[v * 3 + c] ? 1.f : 0.f;
+            o[7 + c] = float(xc[v * 3 + c] / S_X);
+        }
+    }
+}
+
+// h0 = relu(X W_in + b_in): one wave per vertex, lane = channel
+__global__ void __launch_bounds__(MB) k_in(int64_t n, const float *__restrict__ P, const float *__restrict__ X,
+                                           float *__restrict__ h0) {
+    const int c = threadIdx.x & 63;
+    for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
+        float a = P[OFF_BIN + c];
+        for (int k = 0; k < MF; ++k) a += X[v * MF + k] * P[OFF_WIN + k * MH + c];
+        h0[v * MH + c] = a > 0.f ? a : 0.f;
+    }
+}
+
+// column sums of an [n][64] array: partials[block][64]
+__global__ void __launch_bounds__(MB) k_colsum(int64_t n, const float *__restrict__ H, double *__restrict__ part) {
+    __shared__ double lds[MB];
+    const int c = threadIdx.x & 63, w = threadIdx.x / 64;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double t = 0.0;
+    for (int64_t v = lo + w; v < hi; v += MW) t += H[v * MH + c];
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int k = 0; k < MW; ++k) s += lds[k * 64 + threadIdx.x];
+        part[blockIdx.x * 64 + threadIdx.x] = s;
+    }
+}
+
+// g = colsum/n (from partials), gw = g W_g + b (forward) ; one block of 64
+__global__ void k_global(int nparts, const double *__restrict__ part, int64_t n, const float *__restrict__ P, int l,
+                         float *__restrict__ g, float *__restrict__ gw) {
+    __shared__ float gs[64];
+    const int c = threadIdx.x;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[b * 64 + c];
+    gs[c] = float(s / double(n));
+    g[c] = gs[c];
+    __syncthreads();
+    float a = P[off_b(l) + c];
+    for (int k = 0; k < MH; ++k) a += gs[k] * P[off_wg(l) + k * MH + c];
+    gw[c] = a;
+}
+
+// one message-passing layer: m = mean of neighbours, a = h W_s + m W_n + gw,
+// h' = h + relu(a); stores m and a for the backward pass
+__global__ void __launch_bounds__(MB) k_mp_fwd(int64_t n, const int64_t *__restrict__ gp, const int32_t *__restrict__ gi,
+                                               const float *__restrict__ P, int l, const float *__restrict__ gw,
+                                               const float *__restrict__ h, float *__restrict__ m,
+                                               float *__restrict__ a, float *__restrict__ hn) {
+    __shared__ float Ws[MH * MH], Wn[MH * MH];
+    for (int t = threadIdx.x; t < MH * MH; t += MB) {
+        Ws[t] = P[off_ws(l) + t];
+        Wn[t] = P[off_wn(l) + t];
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 63;
+    const float gwc = gw[c];
+    for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
+        const int64_t lo = gp[v], hi = gp[v + 1];
+        float s = 0.f;
+        for (int64_t e = lo; e < hi; ++e) s += h[(int64_t)gi[e] * MH + c];
+        const float mv = hi > lo ? s / float(hi - lo) : 0.f;
+        const float hv = h[v * MH + c];
+        float acc = gwc;
+        for (int k = 0; k < MH; ++k) {
+            acc += __shfl(hv, k, 64) * Ws[k * MH + c];
+            acc += __shfl(mv, k, 64) * Wn[k * MH + c];
+        }
+        m[v * MH + c] = mv;
+        a[v * MH + c] = acc;
+        hn[v * MH + c] = hv + (acc > 0.f ? acc : 0.f);
+    }
+}
+
+// y = (h W_out + b_out) * keep ; if target: loss and gy = 2 (y - t)/(3n) * keep,
+// gh = gy W_out^T ; per-block partial loss
+__global__ void __launch_bounds__(MB) k_out(int64_t n, const float *__restrict__ P, const float *__restrict__ h,
+                                            const uint8_t *__restrict__ mask, float *__restrict__ y,
+                                            const float *__restrict__ target, float *__restrict__ gy,
+                                            float *__restrict__ gh, double *__restrict__ lpart) {
+    __shared__ double lds[MW];
+    const int c = threadIdx.x & 63, w = threadIdx.x / 64;
+    double lsum = 0.0;
+    const float inv = 2.f / float(3 * n);
+    for (int64_t v = blockIdx.x * (int64_t)MW + w; v < n; v += (int64_t)gridDim.x * MW) {
+        const float hv = h[v * MH + c];
+        float yv[MO];
+        for (int j = 0; j < MO; ++j) {
+            float t = hv * P[OFF_WOUT + c * MO + j];
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+            const float keep = mask[v * 3 + j] ? 0.f : 1.f;
+            yv[j] = (t + P[OFF_BOUT + j]) * keep;
+        }
+        if (c < MO) y[v * MO + c] = c == 0 ? yv[0] : (c == 1 ? yv[1] : yv[2]);
+        if (target) {
+            float g[MO];
+            for (int j = 0; j < MO; ++j) {
+                const float keep = mask[v * 3 + j] ? 0.f : 1.f;
+                const float d = yv[j] - target[v * MO + j];
+                if (c == 0) lsum += double(d) * double(d);
+                g[j] = inv * d * keep;
+            }
+            if (c < MO) gy[v * MO + c] = c == 0 ? g[0] : (c == 1 ? g[1] : g[2]);
+            float ghc = 0.f;
+            for (int j = 0; j < MO; ++j) ghc += g[j] * P[OFF_WOUT + c * MO + j];
+            gh[v * MH + c] = ghc;
+        }
+    }
+    if (target) {
+        if (c == 0) lds[w] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int k = 0; k < MW; ++k) t += lds[k];
+            lpart[blockIdx.x] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+// ga = gh * (a > 0); gmd = (ga W_n^T) / deg
+__global__ void __launch_bounds__(MB) k_mp_bwd1(int64_t n, const int64_t *__restrict__ gp, const float *__restrict__ P,
+                                                int l, const float *__restrict__ gh, const float *__restrict__ a,
+                                                float *__restrict__ ga, float *__restrict__ gmd) {
+    __shared__ float Wn[MH * MH];
+    for (int t = threadIdx.x; t < MH * MH; t += MB) Wn[t] = P[off_wn(l) + t];
+    __syncthreads();
+    const int c = threadIdx.x & 63;
+    for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
+        const float g = a[v * MH + c] > 0.f ? gh[v * MH + c] : 0.f;
+        ga[v * MH + c] = g;
+        float t = 0.f;
+        for (int k = 0; k < MH; ++k) t += __shfl(g, k, 64) * Wn[c * MH + k];
+        const int64_t deg = gp[v + 1] - gp[v];
+        gmd[v * MH + c] = deg > 0 ? t / float(deg) : 0.f;
+    }
+}
+
+// gh_prev = gh + ga W_s^T + sum_{u in N(v)} gmd_u + gg / n
+__global__ void __launch_bounds__(MB) k_mp_bwd2(int64_t n, const int64_t *__restrict__ gp, const int32_t *__restrict__ gi,
+                                                const float *__restrict__ P, int l, const float *__restrict__ ga,
+                                                const float *__restrict__ gmd, const float *__restrict__ gg,
+                                                float *__restrict__ gh) {
+    __shared__ float Ws[MH * MH];
+    for (int t = threadIdx.x; t < MH * MH; t += MB) Ws[t] = P[off_ws(l) + t];
+    __syncthreads();
+    const int c = threadIdx.x & 63;
+    const float ggc = gg[c] / float(n);
+    for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
+        const float g = ga[v * MH + c];
+        float t = gh[v * MH + c] + ggc;
+        for (int k = 0; k < MH; ++k) t += __shfl(g, k, 64) * Ws[c * MH + k];
+        for (int64_t e = gp[v]; e < gp[v + 1]; ++e) t += gmd[(int64_t)gi[e] * MH + c];
+        gh[v * MH + c] = t;
+    }
+}
+
+// ga_in = gh * (h0 > 0)
+__global__ void k_relu_mask(int64_t n, const float *__restrict__ h0, const float *__restrict__ gh,
+                            float *__restrict__ ga) {
+    for (int64_t t = blockIdx.x * (int64_t)MB + threadIdx.x; t < n * MH; t += (int64_t)gridDim.x * MB)
+        ga[t] = h0[t] > 0.f ? gh[t] : 0.f;
+}
+
+// partial X^T Y over a chunk of vertices: X [n][KX], Y [n][KY]; block partial
+// tile [KX][KY] (thread t owns entries t, t+256, ...)
+template <int KX, int KY>
+__global__ void __launch_bounds__(MB) k_xty(int64_t n, const float *__restrict__ X, const float *__restrict__ Y,
+                                            float *__restrict__ part) {
+    constexpr int ROWS = 32;
+    __shared__ float xs[ROWS * KX], ys[ROWS * KY];
+    constexpr int PER = (KX * KY + MB - 1) / MB;
+    float acc[PER];
+    for (int q = 0; q < PER; ++q) acc[q] = 0.f;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    for (int64_t r0 = lo; r0 < hi; r0 += ROWS) {
+        const int rows = (int)min<int64_t>(ROWS, hi - r0);
+        for (int t = threadIdx.x; t < ROWS * KX; t += MB) xs[t] = (t / KX) < rows ? X[(r0 + t / KX) * KX + t % KX] : 0.f;
+        for (int t = threadIdx.x; t < ROWS * KY; t += MB) ys[t] = (t / KY) < rows ? Y[(r0 + t / KY) * KY + t % KY] : 0.f;
+        __syncthreads();
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + q * MB;
+            if (e < KX * KY) {
+                const int i = e / KY, j = e % KY;
+                float s = 0.f;
+                for (int r = 0; r < rows; ++r) s += xs[r * KX + i] * ys[r * KY + j];
+                acc[q] += s;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * MB;
+        if (e < KX * KY) part[blockIdx.x * (int64_t)(KX * KY) + e] = acc[q];
+    }
+}
+
+// out[e] (+)= sum_b part[b][e], fixed order in double
+__global__ void k_sum_parts(int nparts, int nel, const float *__restrict__ part, float *__restrict__ out) {
+    for (int e = blockIdx.x * MB + threadIdx.x; e < nel; e += gridDim.x * MB) {
+        double s = 0.0;
+        for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * nel + e];
+        out[e] = float(s);
+    }
+}
+
+// layer scalars: gb = colsum(ga); gW_g = g^T gb (outer product); gg = gb W_g^T
+__global__ void k_layer_small(int nparts, const double *__restrict__ part, const float *__restrict__ g,
+                              const float *__restrict__ P, int l, float *__restrict__ grad, float *__restrict__ gg) {
+    __shared__ float gb[64];
+    const int c = threadIdx.x;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[b * 64 + c];
+    gb[c] = float(s);
+    grad[off_b(l) + c] = gb[c];
+    __syncthreads();
+    for (int k = 0; k < MH; ++k) grad[off_wg(l) + k * MH + c] = g[k] * gb[c];
+    float t = 0.f;
+    for (int k = 0; k < MH; ++k) t += gb[k] * P[off_wg(l) + c * MH + k];
+    gg[c] = t;
+}
+
+// b grads from partial colsums of widths <= 64
+__global__ void k_colsum_out(int nparts, const double *__restrict__ part, int width, float *__restrict__ out) {
+    const int c = threadIdx.x;
+    if (c >= width) return;
+    double s = 0.0;
+    for (int b = 0; b < nparts; ++b) s += part[b * 64 + c];
+    out[c] = float(s);
+}
+
+// column sums of an [n][3] array into partials[block][64] (first 3 used)
+__global__ void __launch_bounds__(MB) k_colsum3(int64_t n, const float *__restrict__ Y, double *__restrict__ part) {
+    __shared__ double lds[MB * 3];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double t[3] = {0, 0, 0};
+    for (int64_t v = lo + threadIdx.x; v < hi; v += MB)
+        for (int j = 0; j < 3; ++j) t[j] += Y[v * 3 + j];
+    for (int j = 0; j < 3; ++j) lds[threadIdx.x * 3 + j] = t[j];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int k = 0; k < MB; ++k) s += lds[k * 3 + threadIdx.x];
+        part[blockIdx.x * 64 + threadIdx.x] = s;
+    }
+}
+
+// Adam (Kingma & Ba 2015) with bias correction
+__global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (int64_t i = blockIdx.x * (int64_t)MB + threadIdx.x; i < n; i += (int64_t)gridDim.x * MB) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+__global__ void k_guess(int64_t n, const float *__restrict__ y, double *__restrict__ u0) {
+    for (int64_t t = blockIdx.x * (int64_t)MB + threadIdx.x; t < n * 3; t += (int64_t)gridDim.x * MB)
+        u0[t] = S_U * double(y[t]);
+}
+
+// vertex graph = stiffness pattern without the diagonal
+__global__ void k_graph_count(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                              int32_t *__restrict__ cnt) {
+    for (int64_t v = blockIdx.x * (int64_t)MB + threadIdx.x; v < n; v += (int64_t)gridDim.x * MB) {
+        int c = 0;
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e) c += ci[e] != v;
+        cnt[v] = c;
+    }
+}
+__global__ void k_graph_fill(int64_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                             const int64_t *__restrict__ gp, int32_t *__restrict__ gi) {
+    for (int64_t v = blockIdx.x * (int64_t)MB + threadIdx.x; v < n; v += (int64_t)gridDim.x * MB) {
+        int64_t o = gp[v];
+        for (int64_t e = rp[v]; e < rp[v + 1]; ++e)
+            if (ci[e] != v) gi[o++] = ci[e];
+    }
+}
+
+}  // namespace te
+
+// ---------------------------------------------------------------------------
+// handle and C ABI
+// ---------------------------------------------------------------------------
+struct mpnn_handle {
+    int64_t n = 0;
+    te::DBuf<int64_t> gp;
+    te::DBuf<int32_t> gi;
+    te::DBuf<double> xc;  // centred coordinates
+    te::DBuf<float> h[te::ML + 1], m[te::ML], a[te::ML], g[te::ML], gw;
+    te::DBuf<float> y, gy, gh, ga, gmd, gg, part;
+    te::DBuf<double> dpart;
+    te::DBuf<float> X;     // last forward input (borrowed copy)
+    te::DBuf<uint8_t> mask;
+    bool have_forward = false;
+};
+
+using namespace te;
+
+extern "C" int64_t mpnn_param_count(void) { return NPARAM; }
+
+extern "C" int mpnn_create(int64_t n, const int64_t *row_ptr, const int32_t *col_idx, const double *coords,
+                           mpnn_handle **out, hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(n > 0 && row_ptr && col_idx && coords && out, TE_EINVAL, "bad argument");
+        auto H = std::make_unique<mpnn_handle>();
+        H->n = n;
+        DBuf<int32_t> cnt(n);
+        const unsigned g = (unsigned)std::min<int64_t>((n + MB - 1) / MB, 65536);
+        hipLaunchKernelGGL(k_graph_count, dim3(g), dim3(MB), 0, s, n, row_ptr, col_idx, cnt.p);
+        TE_CHECK_HIP(hipGetLastError());
+        std::vector<int32_t> hc;
+        download(hc, cnt.p, n, s);
+        std::vector<int64_t> gp(n + 1, 0);
+        for (int64_t v = 0; v < n; ++v) gp[v + 1] = gp[v] + hc[v];
+        upload(H->gp, gp, s);
+        H->gi.alloc(std::max<int64_t>(gp[n], 1));
+        hipLaunchKernelGGL(k_graph_fill, dim3(g), dim3(MB), 0, s, n, row_ptr, col_idx, H->gp.p, H->gi.p);
+        TE_CHECK_HIP(hipGetLastError());
+        std::vector<double> X;
+        download(X, coords, n * 3, s);
+        double c[3] = {0, 0, 0};
+        for (int64_t v = 0; v < n; ++v)
+            for (int k = 0; k < 3; ++k) c[k] += X[v * 3 + k];
+        for (int k = 0; k < 3; ++k) c[k] /= double(n);
+        for (int64_t v = 0; v < n; ++v)
+            for (int k = 0; k < 3; ++k) X[v * 3 + k] -= c[k];
+        upload(H->xc, X, s);
+        for (int l = 0; l <= ML; ++l) H->h[l].alloc(n * MH);
+        for (int l = 0; l < ML; ++l) {
+            H->m[l].alloc(n * MH);
+            H->a[l].alloc(n * MH);
+            H->g[l].alloc(MH);
+        }
+        H->gw.alloc(MH);
+        H->y.alloc(n * MO);
+        H->gy.alloc(n * MO);
+        H->gh.alloc(n * MH);
+        H->ga.alloc(n * MH);
+        H->gmd.alloc(n * MH);
+        H->gg.alloc(MH);
+        H->part.alloc((size_t)RED_BLOCKS * MH * MH);
+        H->dpart.alloc((size_t)RED_BLOCKS * 64);
+        H->X.alloc(n * MF);
+        H->mask.alloc(n * 3);
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+        *out = H.release();
+        return TE_OK;
+    });
+}
+
+extern "C" int mpnn_destroy(mpnn_handle *h) {
+    delete h;
+    return TE_OK;
+}
+
+extern "C" int mpnn_features(mpnn_handle *H, const double *T, double T_ref, const double *f, const uint8_t *mask,
+                             float *X, hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(H && T && mask && X, TE_EINVAL, "bad argument");
+        const unsigned g = (unsigned)std::min<int64_t>((H->n + MB - 1) / MB, 65536);
+        hipLaunchKernelGGL(k_features, dim3(g), dim3(MB), 0, s, H->n, H->xc.p, T, T_ref, f, mask, X);
+        TE_CHECK_HIP(hipGetLastError());
+        return TE_OK;
+    });
+}
+
+static int nparts_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + 255) / 256)); }
+
+extern "C" int mpnn_forward(mpnn_handle *H, const float *P, const float *X, const uint8_t *mask, float *y,
+                            hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(H && P && X && mask, TE_EINVAL, "bad argument");
+        const int64_t n = H->n;
+        TE_CHECK_HIP(hipMemcpyAsync(H->X.p, X, n * MF * sizeof(float), hipMemcpyDeviceToDevice, s));
+        TE_CHECK_HIP(hipMemcpyAsync(H->mask.p, mask, n * 3, hipMemcpyDeviceToDevice, s));
+        const int np = nparts_for(n);
+        hipLaunchKernelGGL(k_in, dim3(vgrid(n)), dim3(MB), 0, s, n, P, X, H->h[0].p);
+        for (int l = 0; l < ML; ++l) {
+            hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->dpart.p);
+            hipLaunchKernelGGL(k_global, dim3(1), dim3(64), 0, s, np, H->dpart.p, n, P, l, H->g[l].p, H->gw.p);
+            hipLaunchKernelGGL(k_mp_fwd, dim3(vgrid(n)), dim3(MB), 0, s, n, H->gp.p, H->gi.p, P, l, H->gw.p,
+                               H->h[l].p, H->m[l].p, H->a[l].p, H->h[l + 1].p);
+        }
+        hipLaunchKernelGGL(k_out, dim3(vgrid(n)), dim3(MB), 0, s, n, P, H->h[ML].p, mask, y ? y : H->y.p,
+                           (const float *)nullptr, (float *)nullptr, (float *)nullptr, (double *)nullptr);
+        TE_CHECK_HIP(hipGetLastError());
+        if (y && y != H->y.p) TE_CHECK_HIP(hipMemcpyAsync(H->y.p, y, n * MO * sizeof(float), hipMemcpyDeviceToDevice, s));
+        H->have_forward = true;
+        return TE_OK;
+    });
+}
+
+// Loss of the last forward against target (scaled displacement [N][3]) and
+// gradients of every parameter into grad[NPARAM].
+extern "C" int mpnn_backward(mpnn_handle *H, const float *P, const float *target, float *grad, double *loss,
+                             hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(H && P && target && grad, TE_EINVAL, "bad argument");
+        TE_REQUIRE(H->have_forward, TE_EINVAL, "mpnn_backward needs a preceding mpnn_forward");
+        const int64_t n = H->n;
+        const int np = nparts_for(n);
+        const unsigned vg = vgrid(n);
+        hipLaunchKernelGGL(k_out, dim3(np), dim3(MB), 0, s, n, P, H->h[ML].p, H->mask.p, H->y.p, target, H->gy.p,
+                           H->gh.p, H->dpart.p);
+        TE_CHECK_HIP(hipGetLastError());
+        std::vector<double> lp;
+        download(lp, H->dpart.p, np, s);
+        double L = 0.0;
+        for (double v : lp) L += v;
+        if (loss) *loss = L / double(3 * n);
+        // output layer
+        hipLaunchKernelGGL((k_xty<MH, MO>), dim3(np), dim3(MB), 0, s, n, H->h[ML].p, H->gy.p, H->part.p);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(MB), 0, s, np, MH * MO, H->part.p, grad + OFF_WOUT);
+        hipLaunchKernelGGL(k_colsum3, dim3(np), dim3(MB), 0, s, n, H->gy.p, H->dpart.p);
+        hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MO, grad + OFF_BOUT);
+        for (int l = ML - 1; l >= 0; --l) {
+            hipLaunchKernelGGL(k_mp_bwd1, dim3(vg), dim3(MB), 0, s, n, H->gp.p, P, l, H->gh.p, H->a[l].p, H->ga.p,
+                               H->gmd.p);
+            hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->ga.p, H->part.p);
+            hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_ws(l));
+            hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->m[l].p, H->ga.p, H->part.p);
+            hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_wn(l));
+            hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->ga.p, H->dpart.p);
+            hipLaunchKernelGGL(k_layer_small, dim3(1), dim3(64), 0, s, np, H->dpart.p, H->g[l].p, P, l, grad, H->gg.p);
+            hipLaunchKernelGGL(k_mp_bwd2, dim3(vg), dim3(MB), 0, s, n, H->gp.p, H->gi.p, P, l, H->ga.p, H->gmd.p,
+                               H->gg.p, H->gh.p);
+        }
+        hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<int64_t>((n * MH + MB - 1) / MB, 65536)), dim3(MB), 0,
+                           s, n, H->h[0].p, H->gh.p, H->ga.p);
+        hipLaunchKernelGGL((k_xty<MF, MH>), dim3(np), dim3(MB), 0, s, n, H->X.p, H->ga.p, H->part.p);
+        hipLaunchKernelGGL(k_sum_parts, dim3(4), dim3(MB), 0, s, np, MF * MH, H->part.p, grad + OFF_WIN);
+        hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->ga.p, H->dpart.p);
+        hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MH, grad + OFF_BIN);
+        TE_CHECK_HIP(hipGetLastError());
+        return TE_OK;
+    });
+}
+
+extern "C" int mpnn_adam_step(int64_t n, float *p, const float *g, float *m, float *v, int32_t step, float lr,
+                              float b1, float b2, float eps, hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(n > 0 && p && g && m && v && step >= 1, TE_EINVAL, "bad argument");
+        const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+        const unsigned gr = (unsigned)std::min<int64_t>((n + MB - 1) / MB, 65536);
+        hipLaunchKernelGGL(k_adam, dim3(gr), dim3(MB), 0, s, n, p, g, m, v, lr, b1, b2, eps, c1, c2);
+        TE_CHECK_HIP(hipGetLastError());
+        return TE_OK;
+    });
+}
+
+// u0 = S_U * y of the last forward (float64 [N][3])
+extern "C" int mpnn_guess(mpnn_handle *H, double *u0, hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(H && u0 && H->have_forward, TE_EINVAL, "bad argument or no forward pass");
+        const unsigned g = (unsigned)std::min<int64_t>((H->n * 3 + MB - 1) / MB, 65536);
+        hipLaunchKernelGGL(k_guess, dim3(g), dim3(MB), 0, s, H->n, H->y.p, u0);
+        TE_CHECK_HIP(hipGetLastError());
+        return TE_OK;
+    });
+}
