@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--grid", default="96,416,12,2", help="disc nr,ntheta,nz,degree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision solve")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch configurations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build targets a single MI355X); --gpus {args.gpus} is not "
@@ -146,6 +147,13 @@ def main():
     info = h.info()
     log(f"setup {t_setup:.1f}s levels {info['n_dof']}")
 
+    tune_report, t_tune = "", 0.0
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        tune_report = h.autotune()
+        t_tune = time.perf_counter() - t0
+        log(f"autotune {t_tune:.2f}s\n" + tune_report)
+
     for w in range(args.warmup):
         u, rep = h.solve(b)
         log(f"warmup {w}: {rep.iters[0]} it, {rep.time_ms:.1f} ms, relres {rep.relres_true[0]:.2e}")
@@ -200,9 +208,9 @@ def main():
         import hashlib
         t = json.load(open(tj))
         csrc = os.path.join(ROOT, "paper_1804_10060_amd", "csrc")
-        h = hashlib.sha256(open(os.path.join(csrc, "te_kernels.hip"), "rb").read() +
-                           open(os.path.join(csrc, "te_internal.h"), "rb").read()).hexdigest()
-        if h == t.get("kernel_source_sha256") and dom in t.get("per_launch", {}):
+        digest = hashlib.sha256(open(os.path.join(csrc, "te_kernels.hip"), "rb").read() +
+                                open(os.path.join(csrc, "te_internal.h"), "rb").read()).hexdigest()
+        if digest == t.get("kernel_source_sha256") and dom in t.get("per_launch", {}):
             roofline["traffic"] = t["per_launch"][dom]["traffic_bytes"]
             roofline["traffic_source"] = "profiles/disc_p2_12M_fp64_hbm_counters.md"
 
@@ -233,9 +241,11 @@ def main():
         "time_solve_ms": round(ms_per_step, 2),
         "time_assembly_ms": round(t_asm * 1e3, 2),
         "time_setup_ms": round(t_setup * 1e3, 1),
+        "time_autotune_ms": round(t_tune * 1e3, 1),
         "dof_per_s_with_setup": m.n_dof / (t_asm + t_setup + ms_per_step * 1e-3),
         "roofline": roofline,
         "kernels": kernels,
+        "autotune": [ln for ln in tune_report.splitlines() if ln.strip()],
         "copy_probe_GBps": round(copy_gbs, 1),
         "forms": forms,
         "cpu_baseline": cpu,

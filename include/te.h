@@ -239,6 +239,39 @@ typedef struct {
 int amg_pcg_solve(amg_handle *h, const double *b, double *u, int32_t nrhs,
                   const pcg_options *opt, pcg_report *rep, hipStream_t stream);
 
+/* Solves n independent systems at once, system i with its own hierarchy
+ * h[i] (from amg_setup; same Chebyshev degree), right-hand side b[i] and
+ * guess/solution u[i] (device [3 N_i] each, float64 only).  Every phase of
+ * the CG iteration is one persistent launch over a queue of (mesh, level,
+ * row-tile) work, and one iteration is captured once as a HIP graph and
+ * replayed; each system keeps its own CG recurrence and stop test, so system
+ * i gets the standalone amg_pcg_solve of b[i] (up to the summation order of
+ * reductions).  rep: host array of n reports (nrhs = 1 each) or NULL;
+ * time_ms is the elapsed time of the whole batch.  The handles' solve
+ * workspaces are used, so they must not be in use elsewhere meanwhile.
+ * Returns TE_OK, TE_ENOTCONV, TE_EINDEF, TE_ENAN, TE_EINVAL, TE_EHIP. */
+int amg_pcg_solve_multi(amg_handle **h, int32_t n, const double *const *b, double *const *u,
+                        const pcg_options *opt, pcg_report *rep, hipStream_t stream);
+
+/* Initial-guess scaling for CG: u0 <- gamma u0 with
+ * gamma = (b, u0) / (u0, A u0), the multiple of the guess of least energy
+ * (smallest A-norm error along u0); gamma = 0, i.e. the zero guess, when
+ * (b, u0) <= 0 or (u0, A u0) <= 0.  b, u0: device [3N]; *gamma: host or NULL.
+ * Synchronises `stream`. */
+int amg_energy_scale(amg_handle *h, const double *b, double *u0, double *gamma, hipStream_t stream);
+
+/* Autotuner: for every level operator (A_l, P_l, R_l; float64 and, if built,
+ * float32) times the launch configurations (waves per workgroup 2/4/8,
+ * slices or rows per wave 1/2/4, XCD-contiguous block order on/off,
+ * non-temporal matrix loads on/off; median of 5 launches) and keeps the
+ * fastest in the handle.  cache_path (host string, may be NULL): if
+ * use_cache, choices already stored there for the same operator class
+ * (layout, block shape, dtype, row-count octave, blocks per row) are applied
+ * without timing; the merged choices are written back.  report (host, may be
+ * NULL): a text summary, truncated to report_len bytes.  Synchronises. */
+int te_autotune(amg_handle *h, const char *cache_path, int32_t use_cache, char *report, int64_t report_len,
+                hipStream_t stream);
+
 /* Releases everything the handle owns.  NULL is accepted. */
 int amg_destroy(amg_handle *h);
 
@@ -277,6 +310,17 @@ int mpnn_forward(mpnn_handle *h, const float *params, const float *X, const uint
  * gradient with respect to every parameter into grad.  Synchronises. */
 int mpnn_backward(mpnn_handle *h, const float *params, const float *target, float *grad, double *loss,
                   hipStream_t stream);
+
+/* Gradients of any loss of the last forward given dL/dy (device float
+ * [N][3]; entries of constrained DOFs are ignored) into grad. */
+int mpnn_backward_from(mpnn_handle *h, const float *params, const float *gy, float *grad, hipStream_t stream);
+
+/* Energy-norm loss of the last forward's guess, the quantity CG reduces:
+ * loss = e^T A e / t^T A t with e = 1e-3 (y - target), t = 1e-3 target and A
+ * the level-0 operator of `amg` (same mesh); gy [N][3] = dloss/dy (device
+ * float).  *loss host, may be NULL.  Uses amg's solve workspace; synchronises. */
+int mpnn_energy_grad(mpnn_handle *h, amg_handle *amg, const float *target, float *gy, double *loss,
+                     hipStream_t stream);
 
 /* One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on n entries. */
 int mpnn_adam_step(int64_t n, float *params, const float *grad, float *m, float *v, int32_t step, float lr,

@@ -125,8 +125,24 @@ def loss(y, u_true_scaled):
 
 def backward(p, X, ptr, nbr, cache, y, u_true_scaled):
     """Gradients of the mean-squared loss with respect to every parameter."""
-    n = X.shape[0]
     gy = 2.0 * (y - u_true_scaled) / y.size
+    return backward_from(p, X, ptr, nbr, cache, gy)
+
+
+def energy_loss(y, u_true_scaled, A, keep):
+    """Relative energy error of the guess S_U y: e^T A e / (t^T A t) with
+    e = S_U (y - t) and t = u_true_scaled (A: assembled operator on [3N]);
+    returns (loss, dL/dy)."""
+    e = (S_U * (y - u_true_scaled) * keep).reshape(-1)
+    t = (S_U * u_true_scaled).reshape(-1)
+    Ae = A @ e
+    E = float(t @ (A @ t))
+    return float(e @ Ae) / E, (2.0 * S_U * Ae.reshape(y.shape) * keep) / E
+
+
+def backward_from(p, X, ptr, nbr, cache, gy):
+    """Gradients of a loss with dL/dy = gy with respect to every parameter."""
+    n = X.shape[0]
     gy = gy * cache["keep"]
     hs = cache["hs"]
     g = {}

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (TE_OP_A, TE_OP_P, TE_OP_R, TE_OP_SMOOTH, TE_OP_VCYCLE, TE_PREC_FP64, TE_PREC_MIXED, TeError,
                    check, load)
 
-__all__ = ["assemble", "assemble_load", "AMG", "MPNN", "Matrix", "TeError", "load", "TE_PREC_FP64",
+__all__ = ["assemble", "assemble_load", "AMG", "MPNN", "solve_multi", "Matrix", "TeError", "load", "TE_PREC_FP64",
            "TE_PREC_MIXED", "TE_OP_A", "TE_OP_P", "TE_OP_R", "TE_OP_SMOOTH", "TE_OP_VCYCLE"]
 
 
@@ -210,6 +210,22 @@ class AMG:
         check(load().amg_apply(self._h, level, op, precision, _ptr(x), _ptr(y), _stream()))
         return y
 
+    def autotune(self, cache_path=None, use_cache=True):
+        """te_autotune: choose each operator's launch configuration; returns the text report."""
+        buf = C.create_string_buffer(1 << 16)
+        p = cache_path.encode() if cache_path else None
+        check(load().te_autotune(self._h, p, int(use_cache), buf, len(buf), _stream()))
+        return buf.value.decode()
+
+    def energy_scale(self, b, u0):
+        """u0 <- gamma u0, gamma = (b,u0)/(u0,A u0) (0 if the guess cannot beat zero); returns gamma."""
+        torch = _torch()
+        _dev(b, torch.float64, None, "b")
+        _dev(u0, torch.float64, tuple(b.shape), "u0")
+        g = C.c_double(0.0)
+        check(load().amg_energy_scale(self._h, _ptr(b), _ptr(u0), C.byref(g), _stream()))
+        return g.value
+
     # ---- solve ----------------------------------------------------------
     def solve(self, b, u0=None, rtol=1e-8, maxit=500, precision="fp64", max_replace=3, history=False,
               allow_notconv=False, profile=False):
@@ -238,6 +254,32 @@ class AMG:
         h = hist.reshape(maxit + 1, nrhs) if hist is not None else None
         return u, SolveReport(iters.tolist(), conv.tolist(), rel.tolist(), h, rep.max_iters, rep.time_ms, code,
                               list(rep.kernel_ms), list(rep.kernel_launches))
+
+
+def solve_multi(amgs, bs, u0s=None, rtol=1e-8, maxit=500, max_replace=3):
+    """amg_pcg_solve_multi over several AMG handles.  Returns (us, reports)."""
+    import numpy as np
+    torch = _torch()
+    n = len(amgs)
+    us = [torch.zeros_like(b) if u0s is None else u0.clone() for b, u0 in zip(bs, u0s or [None] * n)]
+    o = _lib.PcgOptions()
+    load().pcg_options_default(C.byref(o))
+    o.rtol, o.maxit, o.max_replace = rtol, maxit, max_replace
+    H = (C.c_void_p * n)(*[a._h.value for a in amgs])
+    B = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    U = (C.c_void_p * n)(*[u.data_ptr() for u in us])
+    iters = np.zeros(n, np.int32)
+    conv = np.zeros(n, np.int32)
+    rel = np.zeros(n, np.float64)
+    reps = (_lib.PcgReport * n)()
+    for i in range(n):
+        reps[i].iters = iters.ctypes.data + 4 * i
+        reps[i].converged = conv.ctypes.data + 4 * i
+        reps[i].relres_true = rel.ctypes.data + 8 * i
+    code = load().amg_pcg_solve_multi(H, n, B, U, C.byref(o), reps, _stream())
+    check(code, allow=(_lib.TE_OK, _lib.TE_ENOTCONV))
+    return us, {"iters": iters.tolist(), "converged": conv.tolist(), "relres_true": rel.tolist(),
+                "time_ms": reps[0].time_ms, "code": code}
 
 
 class MPNN:
@@ -285,6 +327,23 @@ class MPNN:
         loss = C.c_double(0.0)
         check(load().mpnn_backward(self._h, _ptr(params), _ptr(target), _ptr(grad), C.byref(loss), _stream()))
         return grad, loss.value
+
+    def backward_from(self, params, gy):
+        """Gradient of a loss with dL/dy = gy (float [N, 3]) of the last forward."""
+        torch = _torch()
+        _dev(gy, torch.float32, (self.n, 3), "gy")
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        check(load().mpnn_backward_from(self._h, _ptr(params), _ptr(gy), _ptr(grad), _stream()))
+        return grad
+
+    def energy_grad(self, amg, target):
+        """(gy, loss): relative energy error of the last forward's guess and its dL/dy."""
+        torch = _torch()
+        _dev(target, torch.float32, (self.n, 3), "target")
+        gy = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
+        loss = C.c_double(0.0)
+        check(load().mpnn_energy_grad(self._h, amg._h, _ptr(target), _ptr(gy), C.byref(loss), _stream()))
+        return gy, loss.value
 
     def adam_step(self, params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         check(load().mpnn_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, b1, b2,

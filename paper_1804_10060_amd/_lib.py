@@ -20,8 +20,8 @@ CODE_NAMES = {TE_ENOTCONV: "TE_ENOTCONV", TE_EINVAL: "TE_EINVAL", TE_ENOMEM: "TE
 # exported names declared in include/te.h
 EXPORTS = ["te_version", "te_last_error", "fe_assemble_pattern", "fe_assemble_thermoelastic", "fe_assemble_load",
            "amg_options_default", "amg_setup", "amg_setup_with_aggregates", "amg_get_info", "amg_get_aggregates",
-           "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_destroy",
-           "mpnn_param_count", "mpnn_create", "mpnn_destroy", "mpnn_features", "mpnn_forward", "mpnn_backward",
+           "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_pcg_solve_multi", "amg_energy_scale", "te_autotune", "amg_destroy",
+           "mpnn_param_count", "mpnn_create", "mpnn_destroy", "mpnn_features", "mpnn_forward", "mpnn_backward", "mpnn_backward_from", "mpnn_energy_grad",
            "mpnn_adam_step", "mpnn_guess"]
 
 
@@ -92,6 +92,10 @@ def load():
         "amg_apply": ([vp, i32, i32, i32, vp, vp, vp], C.c_int),
         "pcg_options_default": ([C.POINTER(PcgOptions)], None),
         "amg_pcg_solve": ([vp, vp, vp, i32, C.POINTER(PcgOptions), C.POINTER(PcgReport), vp], C.c_int),
+        "amg_pcg_solve_multi": ([C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(PcgOptions),
+                                 C.POINTER(PcgReport), vp], C.c_int),
+        "amg_energy_scale": ([vp, vp, vp, C.POINTER(C.c_double), vp], C.c_int),
+        "te_autotune": ([vp, C.c_char_p, i32, C.c_char_p, i64, vp], C.c_int),
         "amg_destroy": ([vp], C.c_int),
         "mpnn_param_count": ([], i64),
         "mpnn_create": ([i64, vp, vp, vp, C.POINTER(vp), vp], C.c_int),
@@ -99,6 +103,8 @@ def load():
         "mpnn_features": ([vp, vp, C.c_double, vp, vp, vp, vp], C.c_int),
         "mpnn_forward": ([vp, vp, vp, vp, vp, vp], C.c_int),
         "mpnn_backward": ([vp, vp, vp, vp, C.POINTER(C.c_double), vp], C.c_int),
+        "mpnn_backward_from": ([vp, vp, vp, vp, vp], C.c_int),
+        "mpnn_energy_grad": ([vp, vp, vp, vp, C.POINTER(C.c_double), vp], C.c_int),
         "mpnn_adam_step": ([i64, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp], C.c_int),
         "mpnn_guess": ([vp, vp, vp], C.c_int),
     }

@@ -44,8 +44,14 @@ const char *last_error() { return g_err; }
 // threads
 // ---------------------------------------------------------------------------
 static int g_threads = 0;
+// host_threads if set, else OMP_NUM_THREADS (the process's CPU share), else
+// the hardware thread count, at most 64
 static int n_threads() {
     if (g_threads > 0) return g_threads;
+    if (const char *e = std::getenv("OMP_NUM_THREADS")) {
+        const int v = std::atoi(e);
+        if (v > 0) return std::min(v, 64);
+    }
     unsigned h = std::thread::hardware_concurrency();
     return h ? (int)std::min(h, 64u) : 4;
 }
@@ -862,7 +868,9 @@ static void alloc_work(amg_handle *h, hipStream_t) {
     h->q.alloc(n0);
     h->t.alloc(n0);
     h->b.alloc(n0);
-    int np = std::max<int>(dot_nblocks(h->L[0].n * 3), (int)((h->L[0].A.nslices + 3) / 4 + 8));
+    // partial sums of the level-0 products: at most one per slice (any launch
+    // configuration) or one per 4 rows (several right-hand sides)
+    int np = std::max<int>(dot_nblocks(h->L[0].n * 3), (int)(h->L[0].A.nslices + 8));
     np = std::max<int>(np, (int)((h->L[0].n + 3) / 4 + 8));
     h->partials.alloc((size_t)np * m * 2 + 64);
     h->sums.alloc(4 * 64);

@@ -1,0 +1,336 @@
+// Device-side building blocks shared by the sparse kernels: launch shape,
+// the XCD-contiguous block order, deterministic reductions, the two operator
+// layouts (SELL-64 lane-per-row and one-wave-per-row) with their row bodies,
+// and the fused epilogues.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "te_internal.h"
+
+namespace te {
+
+constexpr int WAVE = 64;
+constexpr int BLK = 256;   // 4 waves per workgroup
+constexpr int WPB = BLK / WAVE;
+
+// Consecutive logical blocks on one XCD: dispatch is round-robin over the 8
+// XCDs, so physical block b runs on XCD b % 8.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nb) {
+    int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, WAVE);
+    return v;
+}
+
+// Block-wide deterministic sum of one value per thread; result valid in
+// thread 0.  lds must hold blockDim.x / 64 doubles (at most 16).
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < nw; ++i) t += lds[i];
+    __syncthreads();
+    return t;
+}
+
+// value loads of the streamed operator: optionally non-temporal, so the
+// single-use matrix stream does not displace the reused x vector in the caches
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_val(const T *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// ---------------------------------------------------------------------------
+// Sparse-product kernel skeletons
+// ---------------------------------------------------------------------------
+template <typename VT>
+struct SellView {
+    const int32_t *__restrict__ slice_off;
+    const int32_t *__restrict__ col;
+    const int32_t *__restrict__ rowlen;
+    const VT *__restrict__ val;
+    const int32_t *__restrict__ rowmap;  // nullptr => identity
+    int64_t nrows;
+    int64_t nslices;
+};
+
+template <typename VT>
+inline SellView<VT> view(const Sell &S, const VT *val) {
+    return SellView<VT>{S.slice_off.p, S.col.p, S.rowlen.p, val, S.rowmap.p, S.nrows, S.nslices};
+}
+
+// Single right-hand side: lane = block row.  Epi::apply(row_out, acc, red)
+// consumes the BR accumulated entries and may add to `red` (block-reduced
+// into partials[logical block] when Epi::kReduce).
+template <int BR, int BC, typename VT, typename XT, typename AT, bool NT>
+__device__ __forceinline__ void sell1_entry(const int32_t *__restrict__ cp, const VT *__restrict__ vp, int k,
+                                            const XT *__restrict__ x, AT *acc) {
+    const int64_t c = cp[(int64_t)k * WAVE];
+    AT xv[BC];
+#pragma unroll
+    for (int j = 0; j < BC; ++j) xv[j] = AT(x[c * BC + j]);
+    const VT *vk = vp + (int64_t)k * (BR * BC * WAVE);
+#pragma unroll
+    for (int i = 0; i < BR; ++i)
+#pragma unroll
+        for (int j = 0; j < BC; ++j) acc[i] += AT(ld_val<NT>(&vk[(i * BC + j) * WAVE])) * xv[j];
+}
+
+// One slice, lane = row.  Rows of a slice are sorted by descending length,
+// so lane 63 holds the shortest: entries below that length are taken by all
+// lanes without a mask, two at a time (loads of both issued together), and
+// only the ragged tail is masked per lane.
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT = false>
+__device__ __forceinline__ void sell1_body(const SellView<VT> &A, const XT *__restrict__ x, const Epi &epi,
+                                           int64_t slice, int lane, double &red) {
+    const int64_t row = slice * WAVE + lane;
+    const int off = A.slice_off[slice];
+    const int w = A.slice_off[slice + 1] - off;
+    const int len = A.rowlen[row];
+    const int kmin = __builtin_amdgcn_readlane(len, WAVE - 1);
+    AT acc[BR];
+#pragma unroll
+    for (int i = 0; i < BR; ++i) acc[i] = AT(0);
+    const int32_t *cp = A.col + (int64_t)off * WAVE + lane;
+    const VT *vp = A.val + (int64_t)off * (BR * BC * WAVE) + lane;
+    int k = 0;
+    for (; k + 1 < kmin; k += 2) {
+        sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k, x, acc);
+        sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k + 1, x, acc);
+    }
+    for (; k < w; ++k)
+        if (k < len) sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k, x, acc);
+    if (row < A.nrows) {
+        const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+        epi.template apply<BR>(out, acc, red);
+    }
+}
+
+// One wave per stored row (format 1).  Lane = (block slot, row of the block):
+// with NB = 64 / BR slots, a wave consumes NB consecutive blocks per step,
+// i.e. one contiguous run of NB*BR*BC values, each lane reading the BC
+// contiguous values of one block row.  The BR row sums are then combined in
+// LDS in a fixed order and lane 0 runs the epilogue.
+template <typename VT>
+struct RowView {
+    const int64_t *__restrict__ rptr;
+    const int32_t *__restrict__ col;
+    const VT *__restrict__ val;
+    const int32_t *__restrict__ rowmap;
+    int64_t nrows;
+};
+
+template <typename VT>
+inline RowView<VT> rview(const Sell &S, const VT *val) {
+    return RowView<VT>{S.rptr.p, S.col.p, val, S.rowmap.p, S.nrows};
+}
+
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT = false>
+__device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__restrict__ x, const Epi &epi, int64_t row,
+                                          int lane, double &red) {
+    constexpr int NB = WAVE / BR;
+    const int slot = lane / BR, i = lane % BR;
+    AT acc = AT(0);
+    if (slot < NB) {
+        const int64_t hi = A.rptr[row + 1];
+        for (int64_t k = A.rptr[row] + slot; k < hi; k += NB) {
+            const int64_t c = A.col[k];
+            const VT *v = A.val + k * (BR * BC) + i * BC;
+#pragma unroll
+            for (int j = 0; j < BC; ++j) acc += AT(ld_val<NT>(&v[j])) * AT(x[c * BC + j]);
+        }
+    }
+    // row sums: every lane takes part in the cross-lane reads, lane 0 keeps them
+    AT r[BR];
+#pragma unroll
+    for (int q = 0; q < BR; ++q) {
+        AT t = AT(0);
+        for (int sl = 0; sl < NB; ++sl) t += __shfl(acc, sl * BR + q, WAVE);
+        r[q] = t;
+    }
+    if (lane == 0) {
+        const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+        epi.template apply<BR>(out, r, red);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues
+// ---------------------------------------------------------------------------
+template <typename T>
+struct EpiSet {  // y = A x
+    static constexpr bool kReduce = false;
+    T *y;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) y[r * BR + i] = T(acc[i]);
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) y[(r * BR + i) * m + j] = T(acc[i]);
+    }
+};
+
+template <typename T>
+struct EpiAdd {  // y += A x
+    static constexpr bool kReduce = false;
+    T *y;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) y[r * BR + i] = T(AT(y[r * BR + i]) + acc[i]);
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (r * BR + i) * m + j;
+            y[q] = T(AT(y[q]) + acc[i]);
+        }
+    }
+};
+
+template <typename T, bool NORM>
+struct EpiResid {  // y = g - A x  (optionally red += y^2)
+    static constexpr bool kReduce = NORM;
+    const T *g;
+    T *y;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            AT v = AT(g[r * BR + i]) - acc[i];
+            y[r * BR + i] = T(v);
+            if (NORM) red += double(v) * double(v);
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (r * BR + i) * m + j;
+            AT v = AT(g[q]) - acc[i];
+            y[q] = T(v);
+            if (NORM) red += double(v) * double(v);
+        }
+    }
+};
+
+struct EpiDot {  // q = A p, red += p.q   (float64 outer CG)
+    static constexpr bool kReduce = true;
+    const double *p;
+    double *q;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            q[r * BR + i] = acc[i];
+            red += p[r * BR + i] * double(acc[i]);
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t k = (r * BR + i) * m + j;
+            q[k] = acc[i];
+            red += p[k] * double(acc[i]);
+        }
+    }
+};
+
+// Post-smoothing start: r = g - A x, d = D^-1 r / theta.
+template <typename T>
+struct EpiChebInit {
+    static constexpr bool kReduce = false;
+    const T *g;
+    const T *dinv;
+    T *r;
+    T *d;
+    T inv_theta;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t row, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = row * BR + i;
+            T rv = T(AT(g[q]) - acc[i]);
+            r[q] = rv;
+            d[q] = dinv[q] * rv * inv_theta;
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (row * BR + i) * m + j;
+            T rv = T(AT(g[q]) - acc[i]);
+            r[q] = rv;
+            d[q] = dinv[row * BR + i] * rv * inv_theta;
+        }
+    }
+};
+
+// One Chebyshev step on the product acc = A d:
+//   r' = r - A d;  d' = c1 d + c2 D^-1 r';  x (+)= d  [+ d' on the last step]
+// `d` is the gathered vector of the product (own row read here); d' goes to a
+// different buffer.  XZERO: x starts from zero (pre-smoothing).
+template <typename T, bool LAST, bool XZERO>
+struct EpiChebStep {
+    static constexpr bool kReduce = false;
+    const T *rin;
+    const T *d;
+    const T *dinv;
+    T *rout;
+    T *dout;
+    T *x;
+    T c1, c2;
+    template <int BR, typename AT>
+    __device__ void apply(int64_t row, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = row * BR + i;
+            T rn = T(AT(rin[q]) - acc[i]);
+            T dv = d[q];
+            T dn = c1 * dv + c2 * (dinv[q] * rn);
+            T xv = XZERO ? T(0) : x[q];
+            if (LAST) {
+                x[q] = xv + dv + dn;
+            } else {
+                rout[q] = rn;
+                dout[q] = dn;
+                x[q] = xv + dv;
+            }
+        }
+    }
+    template <int BR, typename AT>
+    __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            int64_t q = (row * BR + i) * m + j;
+            T rn = T(AT(rin[q]) - acc[i]);
+            T dv = d[q];
+            T dn = c1 * dv + c2 * (dinv[row * BR + i] * rn);
+            T xv = XZERO ? T(0) : x[q];
+            if (LAST) {
+                x[q] = xv + dv + dn;
+            } else {
+                rout[q] = rn;
+                dout[q] = dn;
+                x[q] = xv + dv;
+            }
+        }
+    }
+};
+
+}  // namespace te

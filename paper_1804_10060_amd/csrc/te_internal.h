@@ -126,7 +126,15 @@ constexpr int SELL_C = 64;
 constexpr int FMT_SELL = 0;
 constexpr int FMT_ROWWAVE = 1;
 
+// Launch configuration of one operator, chosen by the autotuner:
+// waves per workgroup, slices (or rows) per wave, XCD-contiguous block order,
+// non-temporal loads of the matrix values.
+struct Tune {
+    int wpb = 4, spw = 1, remap = 1, nt = 0;
+};
+
 struct Sell {
+    Tune tune64, tune32;
     int format = FMT_SELL;
     int br = 0, bc = 0;
     int64_t nrows = 0;          // block rows

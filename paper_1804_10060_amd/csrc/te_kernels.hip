@@ -19,99 +19,23 @@
 // fixed order, then one block sums them in a fixed order.
 #include <hip/hip_runtime.h>
 
-#include "te_internal.h"
+#include "te_dev.h"
 
 namespace te {
-
-constexpr int WAVE = 64;
-constexpr int BLK = 256;   // 4 waves per workgroup
-constexpr int WPB = BLK / WAVE;
-
-// Consecutive logical blocks on one XCD: dispatch is round-robin over the 8
-// XCDs, so physical block b runs on XCD b % 8.
-__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nb) {
-    int64_t q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, WAVE);
-    return v;
-}
-
-// Block-wide deterministic sum of one value per thread; result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double *lds) {
-    v = wave_sum(v);
-    int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    if (lane == 0) lds[w] = v;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int i = 0; i < WPB; ++i) t += lds[i];
-    __syncthreads();
-    return t;
-}
-
-// ---------------------------------------------------------------------------
-// Sparse-product kernel skeletons
-// ---------------------------------------------------------------------------
-template <typename VT>
-struct SellView {
-    const int32_t *__restrict__ slice_off;
-    const int32_t *__restrict__ col;
-    const int32_t *__restrict__ rowlen;
-    const VT *__restrict__ val;
-    const int32_t *__restrict__ rowmap;  // nullptr => identity
-    int64_t nrows;
-    int64_t nslices;
-};
-
-template <typename VT>
-SellView<VT> view(const Sell &S, const VT *val) {
-    return SellView<VT>{S.slice_off.p, S.col.p, S.rowlen.p, val, S.rowmap.p, S.nrows, S.nslices};
-}
-
-// Single right-hand side: lane = block row.  Epi::apply(row_out, acc, red)
-// consumes the BR accumulated entries and may add to `red` (block-reduced
-// into partials[logical block] when Epi::kReduce).
-template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
-__global__ void __launch_bounds__(BLK) k_sell1(SellView<VT> A, const XT *__restrict__ x, Epi epi,
-                                               double *__restrict__ partials) {
-    __shared__ double lds[WPB];
+// Single right-hand side, lane per row: each wave handles `spw` consecutive
+// slices, a workgroup blockDim/64 waves (both chosen by the autotuner);
+// `remap` turns the XCD-contiguous block order on.
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT>
+__global__ void __launch_bounds__(512) k_sell1(SellView<VT> A, const XT *__restrict__ x, Epi epi,
+                                               double *__restrict__ partials, int spw, int remap) {
+    __shared__ double lds[16];
     const int64_t nb = gridDim.x;
-    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
+    const int64_t lb = remap ? xcd_logical_block(blockIdx.x, nb) : (int64_t)blockIdx.x;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t slice = lb * WPB + threadIdx.x / WAVE;
+    const int64_t w0 = (lb * (blockDim.x / WAVE) + threadIdx.x / WAVE) * spw;
     double red = 0.0;
-    if (slice < A.nslices) {
-        const int64_t row = slice * WAVE + lane;
-        const int off = A.slice_off[slice];
-        const int w = A.slice_off[slice + 1] - off;
-        const int len = A.rowlen[row];
-        AT acc[BR];
-#pragma unroll
-        for (int i = 0; i < BR; ++i) acc[i] = AT(0);
-        const int32_t *cp = A.col + (int64_t)off * WAVE + lane;
-        const VT *vp = A.val + (int64_t)off * (BR * BC * WAVE) + lane;
-        for (int k = 0; k < w; ++k) {
-            if (k < len) {
-                const int64_t c = cp[(int64_t)k * WAVE];
-                AT xv[BC];
-#pragma unroll
-                for (int j = 0; j < BC; ++j) xv[j] = AT(x[c * BC + j]);
-                const VT *vk = vp + (int64_t)k * (BR * BC * WAVE);
-#pragma unroll
-                for (int i = 0; i < BR; ++i)
-#pragma unroll
-                    for (int j = 0; j < BC; ++j) acc[i] += AT(vk[(i * BC + j) * WAVE]) * xv[j];
-            }
-        }
-        if (row < A.nrows) {
-            const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
-            epi.template apply<BR>(out, acc, red);
-        }
-    }
+    for (int u = 0; u < spw; ++u)
+        if (w0 + u < A.nslices) sell1_body<BR, BC, VT, XT, AT, Epi, NT>(A, x, epi, w0 + u, lane, red);
     if (Epi::kReduce) {
         double t = block_sum(red, lds);
         if (threadIdx.x == 0) partials[lb] = t;
@@ -165,60 +89,17 @@ __global__ void __launch_bounds__(BLK) k_sellm(SellView<VT> A, const XT *__restr
     }
 }
 
-// One wave per stored row (format 1).  Lane = (block slot, row of the block):
-// with NB = 64 / BR slots, a wave consumes NB consecutive blocks per step,
-// i.e. one contiguous run of NB*BR*BC values, each lane reading the BC
-// contiguous values of one block row.  The BR row sums are then combined in
-// LDS in a fixed order and lane 0 runs the epilogue.
-template <typename VT>
-struct RowView {
-    const int64_t *__restrict__ rptr;
-    const int32_t *__restrict__ col;
-    const VT *__restrict__ val;
-    const int32_t *__restrict__ rowmap;
-    int64_t nrows;
-};
-
-template <typename VT>
-RowView<VT> rview(const Sell &S, const VT *val) {
-    return RowView<VT>{S.rptr.p, S.col.p, val, S.rowmap.p, S.nrows};
-}
-
-template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
-__global__ void __launch_bounds__(BLK) k_roww(RowView<VT> A, const XT *__restrict__ x, Epi epi,
-                                              double *__restrict__ partials) {
-    __shared__ AT lds[BLK];
-    __shared__ double rlds[WPB];
-    constexpr int NB = WAVE / BR;
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT>
+__global__ void __launch_bounds__(512) k_roww(RowView<VT> A, const XT *__restrict__ x, Epi epi,
+                                              double *__restrict__ partials, int spw, int remap) {
+    __shared__ double rlds[16];
     const int64_t nb = gridDim.x;
-    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    const int64_t row = lb * WPB + w;
-    const int slot = lane / BR, i = lane % BR;
-    AT acc = AT(0);
-    if (row < A.nrows && slot < NB) {
-        const int64_t hi = A.rptr[row + 1];
-        for (int64_t k = A.rptr[row] + slot; k < hi; k += NB) {
-            const int64_t c = A.col[k];
-            const VT *v = A.val + k * (BR * BC) + i * BC;
-#pragma unroll
-            for (int j = 0; j < BC; ++j) acc += AT(v[j]) * AT(x[c * BC + j]);
-        }
-    }
-    lds[threadIdx.x] = acc;
-    __syncthreads();
+    const int64_t lb = remap ? xcd_logical_block(blockIdx.x, nb) : (int64_t)blockIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t w0 = (lb * (blockDim.x / WAVE) + threadIdx.x / WAVE) * spw;
     double red = 0.0;
-    if (lane == 0 && row < A.nrows) {
-        AT r[BR];
-#pragma unroll
-        for (int q = 0; q < BR; ++q) {
-            AT t = AT(0);
-            for (int sl = 0; sl < NB; ++sl) t += lds[w * WAVE + sl * BR + q];
-            r[q] = t;
-        }
-        const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
-        epi.template apply<BR>(out, r, red);
-    }
+    for (int u = 0; u < spw; ++u)
+        if (w0 + u < A.nrows) roww_body<BR, BC, VT, XT, AT, Epi, NT>(A, x, epi, w0 + u, lane, red);
     if (Epi::kReduce) {
         double t = block_sum(red, rlds);
         if (threadIdx.x == 0) partials[lb] = t;
@@ -266,203 +147,53 @@ __global__ void __launch_bounds__(BLK) k_rowwm(RowView<VT> A, const XT *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Epilogues
-// ---------------------------------------------------------------------------
-template <typename T>
-struct EpiSet {  // y = A x
-    static constexpr bool kReduce = false;
-    T *y;
-    template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) y[r * BR + i] = T(acc[i]);
-    }
-    template <int BR, typename AT>
-    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) y[(r * BR + i) * m + j] = T(acc[i]);
-    }
-};
-
-template <typename T>
-struct EpiAdd {  // y += A x
-    static constexpr bool kReduce = false;
-    T *y;
-    template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) y[r * BR + i] = T(AT(y[r * BR + i]) + acc[i]);
-    }
-    template <int BR, typename AT>
-    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            int64_t q = (r * BR + i) * m + j;
-            y[q] = T(AT(y[q]) + acc[i]);
-        }
-    }
-};
-
-template <typename T, bool NORM>
-struct EpiResid {  // y = g - A x  (optionally red += y^2)
-    static constexpr bool kReduce = NORM;
-    const T *g;
-    T *y;
-    template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &red) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            AT v = AT(g[r * BR + i]) - acc[i];
-            y[r * BR + i] = T(v);
-            if (NORM) red += double(v) * double(v);
-        }
-    }
-    template <int BR, typename AT>
-    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            int64_t q = (r * BR + i) * m + j;
-            AT v = AT(g[q]) - acc[i];
-            y[q] = T(v);
-            if (NORM) red += double(v) * double(v);
-        }
-    }
-};
-
-struct EpiDot {  // q = A p, red += p.q   (float64 outer CG)
-    static constexpr bool kReduce = true;
-    const double *p;
-    double *q;
-    template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &red) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            q[r * BR + i] = acc[i];
-            red += p[r * BR + i] * double(acc[i]);
-        }
-    }
-    template <int BR, typename AT>
-    __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            int64_t k = (r * BR + i) * m + j;
-            q[k] = acc[i];
-            red += p[k] * double(acc[i]);
-        }
-    }
-};
-
-// Post-smoothing start: r = g - A x, d = D^-1 r / theta.
-template <typename T>
-struct EpiChebInit {
-    static constexpr bool kReduce = false;
-    const T *g;
-    const T *dinv;
-    T *r;
-    T *d;
-    T inv_theta;
-    template <int BR, typename AT>
-    __device__ void apply(int64_t row, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            int64_t q = row * BR + i;
-            T rv = T(AT(g[q]) - acc[i]);
-            r[q] = rv;
-            d[q] = dinv[q] * rv * inv_theta;
-        }
-    }
-    template <int BR, typename AT>
-    __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            int64_t q = (row * BR + i) * m + j;
-            T rv = T(AT(g[q]) - acc[i]);
-            r[q] = rv;
-            d[q] = dinv[row * BR + i] * rv * inv_theta;
-        }
-    }
-};
-
-// One Chebyshev step on the product acc = A d:
-//   r' = r - A d;  d' = c1 d + c2 D^-1 r';  x (+)= d  [+ d' on the last step]
-// `d` is the gathered vector of the product (own row read here); d' goes to a
-// different buffer.  XZERO: x starts from zero (pre-smoothing).
-template <typename T, bool LAST, bool XZERO>
-struct EpiChebStep {
-    static constexpr bool kReduce = false;
-    const T *rin;
-    const T *d;
-    const T *dinv;
-    T *rout;
-    T *dout;
-    T *x;
-    T c1, c2;
-    template <int BR, typename AT>
-    __device__ void apply(int64_t row, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            int64_t q = row * BR + i;
-            T rn = T(AT(rin[q]) - acc[i]);
-            T dv = d[q];
-            T dn = c1 * dv + c2 * (dinv[q] * rn);
-            T xv = XZERO ? T(0) : x[q];
-            if (LAST) {
-                x[q] = xv + dv + dn;
-            } else {
-                rout[q] = rn;
-                dout[q] = dn;
-                x[q] = xv + dv;
-            }
-        }
-    }
-    template <int BR, typename AT>
-    __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
-#pragma unroll
-        for (int i = 0; i < BR; ++i) {
-            int64_t q = (row * BR + i) * m + j;
-            T rn = T(AT(rin[q]) - acc[i]);
-            T dv = d[q];
-            T dn = c1 * dv + c2 * (dinv[row * BR + i] * rn);
-            T xv = XZERO ? T(0) : x[q];
-            if (LAST) {
-                x[q] = xv + dv + dn;
-            } else {
-                rout[q] = rn;
-                dout[q] = dn;
-                x[q] = xv + dv;
-            }
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
 // Launch helpers
 // ---------------------------------------------------------------------------
-static inline int64_t sell_grid(const Sell &A, int nrhs) {
-    if (nrhs == 1 && A.format == FMT_SELL) return (A.nslices + WPB - 1) / WPB;
+template <typename T>
+static inline const Tune &tune_of(const Sell &A) {
+    return sizeof(T) == 4 ? A.tune32 : A.tune64;
+}
+
+static inline int64_t sell_grid(const Sell &A, int nrhs, const Tune &t) {
+    if (nrhs == 1) {
+        const int64_t units = A.format == FMT_SELL ? A.nslices : A.nrows;
+        const int64_t per = (int64_t)t.wpb * t.spw;
+        return (units + per - 1) / per;
+    }
     return (A.nrows + WPB - 1) / WPB;
 }
 
-int sell_partials_count(const Sell &A, int nrhs) { return (int)sell_grid(A, nrhs); }
+int sell_partials_count(const Sell &A, int nrhs) { return (int)sell_grid(A, nrhs, A.tune64); }
 
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
 static void launch_t(const Sell &A, const VT *val, const XT *x, const Epi &epi, int nrhs, double *partials,
                      hipStream_t s) {
-    int64_t g = sell_grid(A, nrhs);
+    const Tune &t = tune_of<VT>(A);
+    int64_t g = sell_grid(A, nrhs, t);
     if (g == 0) return;
-    if (A.format == FMT_ROWWAVE) {
-        if (nrhs == 1)
-            hipLaunchKernelGGL((k_roww<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, rview(A, val),
-                               x, epi, partials);
-        else
-            hipLaunchKernelGGL((k_rowwm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s,
-                               rview(A, val), x, epi, nrhs, partials);
-    } else if (nrhs == 1) {
-        hipLaunchKernelGGL((k_sell1<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, view(A, val), x,
-                           epi, partials);
+    const dim3 blk(nrhs == 1 ? 64 * t.wpb : BLK);
+    if (nrhs == 1) {
+        if (A.format == FMT_ROWWAVE) {
+            if (t.nt)
+                hipLaunchKernelGGL((k_roww<BR, BC, VT, XT, AT, Epi, true>), dim3((unsigned)g), blk, 0, s,
+                                   rview(A, val), x, epi, partials, t.spw, t.remap);
+            else
+                hipLaunchKernelGGL((k_roww<BR, BC, VT, XT, AT, Epi, false>), dim3((unsigned)g), blk, 0, s,
+                                   rview(A, val), x, epi, partials, t.spw, t.remap);
+        } else {
+            if (t.nt)
+                hipLaunchKernelGGL((k_sell1<BR, BC, VT, XT, AT, Epi, true>), dim3((unsigned)g), blk, 0, s,
+                                   view(A, val), x, epi, partials, t.spw, t.remap);
+            else
+                hipLaunchKernelGGL((k_sell1<BR, BC, VT, XT, AT, Epi, false>), dim3((unsigned)g), blk, 0, s,
+                                   view(A, val), x, epi, partials, t.spw, t.remap);
+        }
+    } else if (A.format == FMT_ROWWAVE) {
+        hipLaunchKernelGGL((k_rowwm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), blk, 0, s, rview(A, val), x, epi,
+                           nrhs, partials);
     } else {
-        hipLaunchKernelGGL((k_sellm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), dim3(BLK), 0, s, view(A, val), x,
-                           epi, nrhs, partials);
+        hipLaunchKernelGGL((k_sellm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), blk, 0, s, view(A, val), x, epi,
+                           nrhs, partials);
     }
     TE_CHECK_HIP(hipGetLastError());
 }
@@ -974,3 +705,4 @@ void scal(double *x, double a, int64_t n, hipStream_t s) {
 }
 
 }  // namespace te
+

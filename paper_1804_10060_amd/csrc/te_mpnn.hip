@@ -23,6 +23,7 @@
 #include <cmath>
 #include <memory>
 
+#include "te_amg.h"
 #include "te_internal.h"
 
 namespace te {
@@ -317,6 +318,37 @@ __global__ void __launch_bounds__(MB) k_colsum3(int64_t n, const float *__restri
     }
 }
 
+// gh = (gy * keep) W_out^T, gy_masked stored
+__global__ void __launch_bounds__(MB) k_gy_to_gh(int64_t n, const float *__restrict__ P, const uint8_t *__restrict__ mask,
+                                                 const float *__restrict__ gy_in, float *__restrict__ gy,
+                                                 float *__restrict__ gh) {
+    const int c = threadIdx.x & 63;
+    for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
+        float g[MO];
+        for (int j = 0; j < MO; ++j) g[j] = mask[v * 3 + j] ? 0.f : gy_in[v * MO + j];
+        if (c < MO) gy[v * MO + c] = c == 0 ? g[0] : (c == 1 ? g[1] : g[2]);
+        float t = 0.f;
+        for (int j = 0; j < MO; ++j) t += g[j] * P[OFF_WOUT + c * MO + j];
+        gh[v * MH + c] = t;
+    }
+}
+
+// e = S_U (y - t) * keep, u_t = S_U t  (float64, natural order)
+__global__ void k_energy_err(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
+                             const uint8_t *__restrict__ mask, double *__restrict__ e, double *__restrict__ ut) {
+    for (int64_t i = blockIdx.x * (int64_t)MB + threadIdx.x; i < n * 3; i += (int64_t)gridDim.x * MB) {
+        const double keep = mask[i] ? 0.0 : 1.0;
+        e[i] = S_U * (double(y[i]) - double(t[i])) * keep;
+        ut[i] = S_U * double(t[i]);
+    }
+}
+// gy = 2 S_U keep * Ae / E (float)
+__global__ void k_energy_gy(int64_t n, const double *__restrict__ Ae, const uint8_t *__restrict__ mask, double scale,
+                            float *__restrict__ gy) {
+    for (int64_t i = blockIdx.x * (int64_t)MB + threadIdx.x; i < n * 3; i += (int64_t)gridDim.x * MB)
+        gy[i] = mask[i] ? 0.f : float(scale * Ae[i]);
+}
+
 // Adam (Kingma & Ba 2015) with bias correction
 __global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
                        float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
@@ -467,6 +499,36 @@ extern "C" int mpnn_forward(mpnn_handle *H, const float *P, const float *X, cons
     });
 }
 
+static void backward_tail(mpnn_handle *H, const float *P, float *grad, hipStream_t s) {
+    const int64_t n = H->n;
+    const int np = nparts_for(n);
+    const unsigned vg = vgrid(n);
+    // output layer (gy and gh are in the handle)
+    hipLaunchKernelGGL((k_xty<MH, MO>), dim3(np), dim3(MB), 0, s, n, H->h[ML].p, H->gy.p, H->part.p);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(MB), 0, s, np, MH * MO, H->part.p, grad + OFF_WOUT);
+    hipLaunchKernelGGL(k_colsum3, dim3(np), dim3(MB), 0, s, n, H->gy.p, H->dpart.p);
+    hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MO, grad + OFF_BOUT);
+    for (int l = ML - 1; l >= 0; --l) {
+        hipLaunchKernelGGL(k_mp_bwd1, dim3(vg), dim3(MB), 0, s, n, H->gp.p, P, l, H->gh.p, H->a[l].p, H->ga.p,
+                           H->gmd.p);
+        hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->ga.p, H->part.p);
+        hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_ws(l));
+        hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->m[l].p, H->ga.p, H->part.p);
+        hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_wn(l));
+        hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->ga.p, H->dpart.p);
+        hipLaunchKernelGGL(k_layer_small, dim3(1), dim3(64), 0, s, np, H->dpart.p, H->g[l].p, P, l, grad, H->gg.p);
+        hipLaunchKernelGGL(k_mp_bwd2, dim3(vg), dim3(MB), 0, s, n, H->gp.p, H->gi.p, P, l, H->ga.p, H->gmd.p,
+                           H->gg.p, H->gh.p);
+    }
+    hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<int64_t>((n * MH + MB - 1) / MB, 65536)), dim3(MB), 0, s,
+                       n, H->h[0].p, H->gh.p, H->ga.p);
+    hipLaunchKernelGGL((k_xty<MF, MH>), dim3(np), dim3(MB), 0, s, n, H->X.p, H->ga.p, H->part.p);
+    hipLaunchKernelGGL(k_sum_parts, dim3(4), dim3(MB), 0, s, np, MF * MH, H->part.p, grad + OFF_WIN);
+    hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->ga.p, H->dpart.p);
+    hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MH, grad + OFF_BIN);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
 // Loss of the last forward against target (scaled displacement [N][3]) and
 // gradients of every parameter into grad[NPARAM].
 extern "C" int mpnn_backward(mpnn_handle *H, const float *P, const float *target, float *grad, double *loss,
@@ -476,7 +538,6 @@ extern "C" int mpnn_backward(mpnn_handle *H, const float *P, const float *target
         TE_REQUIRE(H->have_forward, TE_EINVAL, "mpnn_backward needs a preceding mpnn_forward");
         const int64_t n = H->n;
         const int np = nparts_for(n);
-        const unsigned vg = vgrid(n);
         hipLaunchKernelGGL(k_out, dim3(np), dim3(MB), 0, s, n, P, H->h[ML].p, H->mask.p, H->y.p, target, H->gy.p,
                            H->gh.p, H->dpart.p);
         TE_CHECK_HIP(hipGetLastError());
@@ -485,29 +546,52 @@ extern "C" int mpnn_backward(mpnn_handle *H, const float *P, const float *target
         double L = 0.0;
         for (double v : lp) L += v;
         if (loss) *loss = L / double(3 * n);
-        // output layer
-        hipLaunchKernelGGL((k_xty<MH, MO>), dim3(np), dim3(MB), 0, s, n, H->h[ML].p, H->gy.p, H->part.p);
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(MB), 0, s, np, MH * MO, H->part.p, grad + OFF_WOUT);
-        hipLaunchKernelGGL(k_colsum3, dim3(np), dim3(MB), 0, s, n, H->gy.p, H->dpart.p);
-        hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MO, grad + OFF_BOUT);
-        for (int l = ML - 1; l >= 0; --l) {
-            hipLaunchKernelGGL(k_mp_bwd1, dim3(vg), dim3(MB), 0, s, n, H->gp.p, P, l, H->gh.p, H->a[l].p, H->ga.p,
-                               H->gmd.p);
-            hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->ga.p, H->part.p);
-            hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_ws(l));
-            hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->m[l].p, H->ga.p, H->part.p);
-            hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_wn(l));
-            hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->ga.p, H->dpart.p);
-            hipLaunchKernelGGL(k_layer_small, dim3(1), dim3(64), 0, s, np, H->dpart.p, H->g[l].p, P, l, grad, H->gg.p);
-            hipLaunchKernelGGL(k_mp_bwd2, dim3(vg), dim3(MB), 0, s, n, H->gp.p, H->gi.p, P, l, H->ga.p, H->gmd.p,
-                               H->gg.p, H->gh.p);
-        }
-        hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<int64_t>((n * MH + MB - 1) / MB, 65536)), dim3(MB), 0,
-                           s, n, H->h[0].p, H->gh.p, H->ga.p);
-        hipLaunchKernelGGL((k_xty<MF, MH>), dim3(np), dim3(MB), 0, s, n, H->X.p, H->ga.p, H->part.p);
-        hipLaunchKernelGGL(k_sum_parts, dim3(4), dim3(MB), 0, s, np, MF * MH, H->part.p, grad + OFF_WIN);
-        hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->ga.p, H->dpart.p);
-        hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MH, grad + OFF_BIN);
+        backward_tail(H, P, grad, s);
+        return TE_OK;
+    });
+}
+
+// Gradients of a loss given dL/dy of the last forward (float [N][3]).
+extern "C" int mpnn_backward_from(mpnn_handle *H, const float *P, const float *gy, float *grad, hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(H && P && gy && grad, TE_EINVAL, "bad argument");
+        TE_REQUIRE(H->have_forward, TE_EINVAL, "mpnn_backward_from needs a preceding mpnn_forward");
+        hipLaunchKernelGGL(k_gy_to_gh, dim3(vgrid(H->n)), dim3(MB), 0, s, H->n, P, H->mask.p, gy, H->gy.p, H->gh.p);
+        TE_CHECK_HIP(hipGetLastError());
+        backward_tail(H, P, grad, s);
+        return TE_OK;
+    });
+}
+
+// Relative energy error of the last forward's guess, loss = e^T A e / t^T A t
+// with e = S_U (y - t), t = S_U target (A = level-0 operator of the AMG
+// handle), and gy = dloss/dy.  Uses the AMG handle's solve workspace.
+extern "C" int mpnn_energy_grad(mpnn_handle *H, amg_handle *A, const float *target, float *gy, double *loss,
+                                hipStream_t s) {
+    return guarded([&] {
+        TE_REQUIRE(H && A && target && gy, TE_EINVAL, "bad argument");
+        TE_REQUIRE(H->have_forward, TE_EINVAL, "mpnn_energy_grad needs a preceding mpnn_forward");
+        Level &L0 = A->L[0];
+        TE_REQUIRE(L0.n == H->n, TE_EINVAL, "AMG and MPNN sizes differ");
+        const int64_t n = H->n, nv = 3 * n;
+        const unsigned g = (unsigned)std::min<int64_t>((nv + MB - 1) / MB, 65536);
+        // natural-order e and u_t in the AMG's z / p buffers, storage order in t / u
+        hipLaunchKernelGGL(k_energy_err, dim3(g), dim3(MB), 0, s, n, H->y.p, target, H->mask.p, A->z.p, A->p.p);
+        permute_gather(A->z.p, A->t.p, L0.perm.p, n, 3, 1, s);
+        permute_gather(A->p.p, A->u.p, L0.perm.p, n, 3, 1, s);
+        sell_apply<double>(L0.A, A->t.p, A->q.p, nullptr, 0, 1, s);   // A e
+        sell_apply<double>(L0.A, A->u.p, A->r.p, nullptr, 0, 1, s);   // A u_t
+        double *part = A->partials.p, *sums = A->sums.p;
+        dot_partials(A->t.p, A->q.p, nv, 1, part, s);
+        reduce_partials(part, dot_nblocks(nv), 1, sums, s);
+        dot_partials(A->u.p, A->r.p, nv, 1, part, s);
+        reduce_partials(part, dot_nblocks(nv), 1, sums + 1, s);
+        std::vector<double> v;
+        download(v, sums, 2, s);
+        TE_REQUIRE(v[1] > 0, TE_EINVAL, "target has no energy");
+        if (loss) *loss = v[0] / v[1];
+        permute_scatter(A->q.p, A->z.p, L0.perm.p, n, 3, 1, s);
+        hipLaunchKernelGGL(k_energy_gy, dim3(g), dim3(MB), 0, s, n, A->z.p, H->mask.p, 2.0 * S_U / v[1], gy);
         TE_CHECK_HIP(hipGetLastError());
         return TE_OK;
     });

@@ -419,9 +419,40 @@ static int apply_impl(amg_handle *h, int l, int op, int prec, const double *x, d
     return TE_OK;
 }
 
+// u0 <- gamma u0 with gamma = (b, u0) / (u0, A u0): the multiple of the guess
+// with the lowest energy 1/2 u^T A u - b^T u, i.e. the smallest A-norm error
+// along the guess; gamma = 0 (the zero guess) when the guess cannot beat zero.
+static int energy_scale_impl(amg_handle *h, const double *b_nat, double *u_nat, double *gamma_out, hipStream_t s) {
+    TE_REQUIRE(h && b_nat && u_nat, TE_EINVAL, "NULL argument");
+    Level &L0 = h->L[0];
+    const int64_t n = L0.n, nv = n * 3;
+    permute_gather(b_nat, h->b.p, L0.perm.p, n, 3, 1, s);
+    permute_gather(u_nat, h->t.p, L0.perm.p, n, 3, 1, s);
+    sell_apply<double>(L0.A, h->t.p, h->q.p, nullptr, 0, 1, s);
+    double *part = h->partials.p, *sums = h->sums.p;
+    dot_partials(h->b.p, h->t.p, nv, 1, part, s);
+    reduce_partials(part, dot_nblocks(nv), 1, sums, s);
+    dot_partials(h->t.p, h->q.p, nv, 1, part, s);
+    reduce_partials(part, dot_nblocks(nv), 1, sums + 1, s);
+    std::vector<double> v;
+    fetch(sums, 2, v, s);
+    const double bu = v[0], uau = v[1];
+    TE_REQUIRE(std::isfinite(bu) && std::isfinite(uau), TE_ENAN, "NaN/Inf in the guess");
+    const double gamma = (uau > 0.0 && bu > 0.0) ? bu / uau : 0.0;
+    if (gamma == 0.0) TE_CHECK_HIP(hipMemsetAsync(u_nat, 0, nv * sizeof(double), s));
+    else scal(u_nat, gamma, nv, s);
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    if (gamma_out) *gamma_out = gamma;
+    return TE_OK;
+}
+
 }  // namespace te
 
 using namespace te;
+
+extern "C" int amg_energy_scale(amg_handle *h, const double *b, double *u0, double *gamma, hipStream_t stream) {
+    return guarded([&] { return energy_scale_impl(h, b, u0, gamma, stream); });
+}
 
 extern "C" void pcg_options_default(pcg_options *o) {
     if (!o) return;

@@ -1,0 +1,163 @@
+"""Measurements of the batched and learned forms against plain float64 PCG-AMG
+on the same GPU, at the same true relative residual 1e-8.
+
+    python -m paper_1804_10060_amd.forms [block|multi|learned|all] [--quick]
+
+Prints one JSON object.  Workloads (seeded, synthetic):
+  block   : 64 thermal load cases (4-16 Gaussian bumps, U[0,500] K) on the
+            P1 disc 104x452x13 (1,993,320 DOF): one 64-column solve vs 64
+            single-column solves;
+  multi   : 32 P1 discs with DOF log-uniform in [1e4, 5e5]: one multi-mesh
+            solve (persistent launches, graph replay) vs 32 separate solves;
+  learned : P1 disc 80x344x11 (1,003,104 DOF); 2000 training and 200
+            held-out load fields solved by the library, the network trained
+            by the library's kernels, then held-out solves from the learned
+            guess vs from zero.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+import meshgen as mg
+
+
+def log(*a):
+    print("[forms]", *a, file=sys.stderr, flush=True)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def block_form(quick=False):
+    import paper_1804_10060_amd as te
+    from paper_1804_10060_amd import learned
+    torch = _torch()
+    grid = (26, 113, 3) if quick else mg.DISC_P1_2M[:3]
+    k = 16 if quick else 64
+    pr = learned.Problem(*grid, max_nrhs=64)
+    seeds = list(range(1000, 1000 + k))
+    T = torch.from_numpy(np.stack([mg.disc_temperature_bumps(pr.mesh, s) for s in seeds])).to(pr.dev)
+    fv = torch.zeros((k, 3), dtype=torch.float64, device=pr.dev)
+    B = pr.loads(T, fv)
+    log(f"block: {pr.mesh.n_dof} DOF, {k} load cases")
+    pr.amg.solve(B[:, :, :2].contiguous())  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, rep = pr.amg.solve(B)
+    torch.cuda.synchronize()
+    t_block = time.perf_counter() - t0
+    singles, diffs, its = 0.0, [], []
+    for j in range(k):
+        bj = B[:, :, j].reshape(-1).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uj, rj = pr.amg.solve(bj)
+        torch.cuda.synchronize()
+        singles += time.perf_counter() - t0
+        its.append(rj.iters[0])
+        diffs.append(float((U[:, :, j].reshape(-1) - uj).norm() / uj.norm()))
+    out = {"workload": f"P1 disc {grid[0]}x{grid[1]}x{grid[2]}, {pr.mesh.n_dof} DOF, {k} bump load cases",
+           "n_dof": pr.mesh.n_dof, "nrhs": k, "block_s": t_block, "singles_s": singles,
+           "speedup": singles / t_block, "block_iters_max": max(rep.iters), "single_iters_mean": float(np.mean(its)),
+           "all_converged": bool(all(rep.converged)), "max_relres_true": max(rep.relres_true),
+           "max_rel_diff_vs_single": max(diffs),
+           "dof_rhs_per_s_block": pr.mesh.n_dof * k / t_block, "dof_rhs_per_s_single": pr.mesh.n_dof * k / singles}
+    log(json.dumps(out))
+    return out
+
+
+def multi_form(quick=False):
+    import paper_1804_10060_amd as te
+    torch = _torch()
+    sizes = mg.multi_mesh_sizes(8 if quick else 32, lo=1e4, hi=(5e4 if quick else 5e5))
+    hs, bs = [], []
+    ndof = 0
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    for (nr, nth, nz, seed) in sizes:
+        prob = mg.disc_problem(nr, nth, nz, 1, seed=0)
+        prob.T = mg.disc_temperature_bumps(prob.mesh, seed)
+        m = prob.mesh
+        c = torch.from_numpy(m.coords).to(dev)
+        A, b = te.assemble(c, torch.from_numpy(m.cells).to(dev), 1, prob.E, prob.nu, prob.alpha, prob.T_ref,
+                           torch.from_numpy(prob.T).to(dev), mask=torch.from_numpy(prob.mask).to(dev))
+        hs.append(te.AMG(A, c, torch.from_numpy(prob.mask).to(dev)))
+        bs.append(b)
+        ndof += m.n_dof
+    log(f"multi: {len(hs)} meshes, {ndof} DOF total, setup {time.perf_counter() - t0:.1f}s")
+    te.solve_multi(hs[:2], bs[:2])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, rep = te.solve_multi(hs, bs)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t0
+    seq, diffs, its = 0.0, [], []
+    for h, b, u in zip(hs, bs, us):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u1, r1 = h.solve(b)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+        its.append(r1.iters[0])
+        diffs.append(float((u - u1).norm() / u1.norm()))
+    out = {"workload": f"{len(hs)} P1 discs, DOF log-uniform, {ndof} DOF total",
+           "meshes": len(hs), "total_dof": ndof, "dof_per_mesh": [3 * int(h.info()['n_dof'][0] // 3) for h in hs],
+           "multi_s": t_multi, "sequential_s": seq, "speedup": seq / t_multi,
+           "iters_multi": rep["iters"], "iters_single": its, "all_converged": bool(all(rep["converged"])),
+           "max_relres_true": max(rep["relres_true"]), "max_rel_diff_vs_single": max(diffs)}
+    log(json.dumps({k: v for k, v in out.items() if k not in ("dof_per_mesh",)}))
+    return out
+
+
+def learned_form(quick=False):
+    from paper_1804_10060_amd import learned
+    grid = (16, 68, 3) if quick else mg.DISC_P1_1M[:3]
+    n_train, n_test = (192, 16) if quick else (2000, 200)
+    epochs = 24 if quick else 12
+    pr = learned.Problem(*grid, max_nrhs=64)
+    t0 = time.perf_counter()
+    train = pr.generate(list(range(10000, 10000 + n_train)), log=log)
+    test = pr.generate(list(range(20000, 20000 + n_test)), log=log)
+    t_gen = time.perf_counter() - t0
+    params, hist, t_train = pr.train(train, epochs=epochs, lr=2e-3, log=log)
+    res = pr.evaluate(params, test)
+    iz = [r["iters_zero"] for r in res]
+    ig = [r["iters_guess"] for r in res]
+    out = {"workload": f"P1 disc {grid[0]}x{grid[1]}x{grid[2]}, {pr.mesh.n_dof} DOF; {n_train} train / {n_test} "
+                       f"held-out load fields", "n_dof": pr.mesh.n_dof, "train": n_train, "test": n_test,
+           "epochs": epochs, "data_generation_s": t_gen, "training_s": t_train, "loss_first": hist[0],
+           "loss_last": hist[-1], "iters_zero_mean": float(np.mean(iz)), "iters_guess_mean": float(np.mean(ig)),
+           "ms_zero_mean": float(np.mean([r["ms_zero"] for r in res])),
+           "ms_guess_mean": float(np.mean([r["ms_guess"] for r in res])),
+           "guess_used_fraction": float(np.mean([r["guess_used"] for r in res])),
+           "rel_err_scaled_guess_mean": float(np.mean([r["rel_err0"] for r in res])),
+           "max_relres_true_guess": max(r["relres_true_guess"] for r in res),
+           "max_rel_diff_vs_zero_start": max(r["rel_diff"] for r in res)}
+    log(json.dumps(out))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", nargs="?", default="all", choices=["block", "multi", "learned", "all"])
+    ap.add_argument("--quick", action="store_true")
+    a = ap.parse_args()
+    out = {}
+    if a.which in ("block", "all"):
+        out["block_rhs"] = block_form(a.quick)
+    if a.which in ("multi", "all"):
+        out["multi_mesh"] = multi_form(a.quick)
+    if a.which in ("learned", "all"):
+        out["learned_guess"] = learned_form(a.quick)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -2,9 +2,10 @@
 batched solver, training with the library's MPNN kernels (float32 forward,
 backward and Adam on the GPU), and evaluation against the zero guess.
 
-The network only proposes u0; the solve still runs to the same true relative
-residual, and a guess whose residual is not below |b| is replaced by zero, so
-accuracy never depends on the network.
+The network only proposes u0; it is scaled to its energy-optimal multiple
+(amg_energy_scale, which falls back to the zero guess when the guess cannot
+beat zero in the energy norm), and the solve still runs to the same true
+relative residual, so accuracy never depends on the network.
 """
 from __future__ import annotations
 
@@ -113,7 +114,9 @@ class Problem:
             f = f_vec[None, :].expand(self.mesh.n_nodes, 3).contiguous()
         return self.net.features(T_row.contiguous(), self.prob.T_ref, self.mask, f)
 
-    def train(self, data: Dataset, epochs=8, lr=1e-3, seed=0, log=print):
+    def train(self, data: Dataset, epochs=8, lr=1e-3, seed=0, log=print, loss="energy"):
+        """Adam on the relative energy error of the guess (the quantity CG
+        reduces; loss="energy") or on the mean squared error (loss="mse")."""
         import torch
         params = torch.from_numpy(init_params(seed)).to(self.dev)
         m1 = torch.zeros_like(params)
@@ -128,11 +131,15 @@ class Problem:
             for i in rng.permutation(S).tolist():
                 X = self.features(data.T[i], data.f[i])
                 self.net.forward(params, X, self.mask)
-                g, loss = self.net.backward(params, data.U[i])
+                if loss == "energy":
+                    gy, lv = self.net.energy_grad(self.amg, data.U[i])
+                    g = self.net.backward_from(params, gy)
+                else:
+                    g, lv = self.net.backward(params, data.U[i])
                 step += 1
-                lr_t = lr * (0.5 ** (ep // 3))
+                lr_t = lr * (0.5 ** (ep // max(1, epochs // 4)))
                 self.net.adam_step(params, g, m1, v1, step, lr=lr_t)
-                tot += loss
+                tot += lv
             hist.append(tot / S)
             log(f"  epoch {ep}: mean loss {tot / S:.4e}")
         torch.cuda.synchronize()
@@ -144,21 +151,23 @@ class Problem:
         return self.net.guess()
 
     def evaluate(self, params, data: Dataset, log=print):
-        """Per test case: iterations and solve time from the learned guess (with
-        the zero fallback) and from zero, both to true relres 1e-8 in float64."""
+        """Per test case: iterations and solve time from the scaled learned guess
+        and from zero, both to true relres 1e-8 in float64."""
         import torch
         res = []
         for i in range(data.T.shape[0]):
             b = self.loads(data.T[i:i + 1].contiguous(), data.f[i:i + 1].contiguous()).reshape(-1).contiguous()
             u0 = self.guess(params, data.T[i], data.f[i])
-            # fallback: the guess must reduce the residual below |b|
+            # energy-optimal multiple of the guess; gamma = 0 falls back to zero
+            gamma = self.amg.energy_scale(b, u0)
             r0 = float(torch.linalg.norm(b - self.apply_A(u0)))
-            used = r0 < float(torch.linalg.norm(b))
             uz, rz = self.amg.solve(b)
-            ug, rg = self.amg.solve(b, u0=u0 if used else None)
+            ug, rg = self.amg.solve(b, u0=u0)
             err = float(torch.linalg.norm(ug - uz) / torch.linalg.norm(uz))
+            e0 = float(torch.linalg.norm(u0 - uz) / torch.linalg.norm(uz))
             res.append({"iters_zero": rz.iters[0], "iters_guess": rg.iters[0], "ms_zero": rz.time_ms,
-                        "ms_guess": rg.time_ms, "guess_used": bool(used), "relres0": r0 / float(torch.linalg.norm(b)),
+                        "ms_guess": rg.time_ms, "gamma": gamma, "guess_used": gamma > 0,
+                        "relres0": r0 / float(torch.linalg.norm(b)), "rel_err0": e0,
                         "relres_true_guess": rg.relres_true[0], "rel_diff": err})
         return res
 

@@ -1,0 +1,41 @@
+"""Autotuner: every candidate launch configuration computes the same rows,
+so tuned operators reproduce the untuned products bit for bit, the tuned
+solve matches, and the choices survive a round trip through the cache file."""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from tests.gpu_util import dev, gpu_assemble, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob = mg.disc_problem(10, 40, 3, 2, seed=2)
+    A, b, d = gpu_assemble(prob)
+    h = te.AMG(A, d["coords"], d["mask"], coarse_max=400)
+    info = h.info()
+    rng = np.random.default_rng(0)
+    xs = [dev(rng.normal(size=n), torch.float64) for n in info["n_dof"]]
+    before = [h.apply(l, te.TE_OP_A, xs[l]).cpu().numpy() for l in range(info["n_levels"])]
+    before32 = h.apply(0, te.TE_OP_A, xs[0], precision=te.TE_PREC_MIXED).cpu().numpy()
+    u0, r0 = h.solve(b)
+    cache = str(tmp_path / "tune.json")
+    rep = h.autotune(cache)
+    say(rep)
+    assert "best" in rep
+    after = [h.apply(l, te.TE_OP_A, xs[l]).cpu().numpy() for l in range(info["n_levels"])]
+    for a, c in zip(before, after):
+        assert np.array_equal(a, c)
+    assert np.array_equal(before32, h.apply(0, te.TE_OP_A, xs[0], precision=te.TE_PREC_MIXED).cpu().numpy())
+    u1, r1 = h.solve(b)
+    assert abs(r1.iters[0] - r0.iters[0]) <= 1
+    assert float(((u1 - u0).norm() / u0.norm()).cpu()) <= 1e-10
+    h2 = te.AMG(A, d["coords"], d["mask"], coarse_max=400)
+    rep2 = h2.autotune(cache)
+    assert "best" not in rep2 and "cached" in rep2
+    u2, r2 = h2.solve(b)
+    assert r2.iters[0] == r1.iters[0]
+    assert float(((u2 - u1).norm() / u1.norm()).cpu()) == 0.0

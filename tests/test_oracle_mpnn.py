@@ -5,6 +5,7 @@ import numpy as np
 
 import meshgen as mg
 from oracle import mpnn
+from oracle import mpnn as om
 
 
 def _small():
@@ -97,3 +98,27 @@ def test_grad_check_detects_a_planted_adjoint_mistake(monkeypatch):
 
     monkeypatch.setattr(mpnn, "_mean_nbr_T", wrong)
     assert mpnn.grad_check(p, X, ptr, nbr, mask, ut, n_probe=4) > 1e-3
+
+
+def test_energy_loss_gradient_finite_differences():
+    from oracle import fem
+    prob = mg.disc_problem(3, 12, 2, 1, seed=0)
+    A, b, _, _ = fem.assemble_problem(prob)
+    rng = np.random.default_rng(3)
+    n = prob.mesh.n_nodes
+    keep = 1.0 - prob.mask
+    t = rng.normal(size=(n, 3)) * keep
+    y = rng.normal(size=(n, 3))
+    L, g = om.energy_loss(y, t, A, keep)
+    for _ in range(6):
+        i, j = rng.integers(n), rng.integers(3)
+        h = 1e-6
+        y2 = y.copy()
+        y2[i, j] += h
+        Lp, _ = om.energy_loss(y2, t, A, keep)
+        y2[i, j] -= 2 * h
+        Lm, _ = om.energy_loss(y2, t, A, keep)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g[i, j]) <= 1e-6 * max(abs(fd), 1e-8) + 1e-10
+    # the exact solution has zero loss
+    assert om.energy_loss(t, t, A, keep)[0] == 0.0
