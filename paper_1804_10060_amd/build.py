@@ -24,8 +24,9 @@ ARCH = os.environ.get("TE_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function",
           "-Wno-unused-variable", "-Wno-unused-result"]
-# Host-side setup arithmetic without fused multiply-add contraction, so the
-# strength-of-connection values are the plainly rounded expressions.
+# Host-side setup arithmetic (aggregate QR, coarse factor) without fused
+# multiply-add contraction: plainly rounded expressions, as in the reference
+# arithmetic of the tests.
 PER_FILE = {"te_amg.cpp": ["-ffp-contract=off"]}
 
 

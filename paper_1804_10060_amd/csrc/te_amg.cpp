@@ -1,12 +1,14 @@
 // Smoothed-aggregation AMG setup (Sec. 2.1.3 and 5.1 of the paper; the
 // method of Vanek, Mandel & Brezina 1996 with the rigid-body near-nullspace).
 //
-// Host part: strength of connection, greedy aggregation, tentative
-// prolongator by Householder QR, prolongator smoothing and the Galerkin
-// product (row-wise sparse products with per-thread accumulators), the dense
-// Cholesky factor and inverse of the coarsest level.  Device part: every
-// level operator is packed into the SELL-64 layout, and the largest
-// eigenvalue of D^-1 A is estimated with Lanczos on the GPU.
+// Host part: the greedy aggregation, the tentative prolongator by
+// Householder QR per aggregate, the storage order of every level and the
+// dense Cholesky factor and inverse of the coarsest level.  Device part
+// (te_setup_gpu.hip and te_kernels.hip): strength of connection, prolongator
+// smoothing, the products A P and P^T (A P), the transpose, the packing into
+// the solver layouts and the Lanczos estimate of the largest eigenvalue of
+// D^-1 A.  Matrix values never leave the device, except those of the
+// coarsest level.
 //
 // Readings of what the paper leaves open (strength threshold 0.08 halved per
 // level, tie handling, QR sign, 20 Lanczos steps, coarse size 3000 DOF,
@@ -24,6 +26,7 @@
 #include <thread>
 
 #include "te_amg.h"
+#include "te_setup_gpu.h"
 
 namespace te {
 
@@ -70,155 +73,11 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &f
 }
 
 // ---------------------------------------------------------------------------
-// host block-sparse helpers
-// ---------------------------------------------------------------------------
-static void bsr_diag_points(const HBsr &A, std::vector<double> &d) {
-    const int b = A.br;
-    d.assign((size_t)A.nr * b, 0.0);
-    for (int64_t i = 0; i < A.nr; ++i)
-        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-            if (A.col[k] == i)
-                for (int p = 0; p < b; ++p) d[i * b + p] = A.val[(size_t)k * b * b + p * b + p];
-}
-
-// C = A * B (block products, row-wise). Columns of each C row sorted.
-static HBsr bsr_mult(const HBsr &A, const HBsr &B) {
-    TE_REQUIRE(A.bc == B.br && A.nc == B.nr, TE_EINVAL, "bsr_mult shape mismatch");
-    const int br = A.br, bk = A.bc, bc = B.bc, bb = br * bc;
-    HBsr C;
-    C.br = br;
-    C.bc = bc;
-    C.nr = A.nr;
-    C.nc = B.nc;
-    const int nt = n_threads();
-    std::vector<std::vector<int32_t>> tcol(nt);
-    std::vector<std::vector<double>> tval(nt);
-    std::vector<int64_t> cnt(A.nr, 0);
-    std::vector<int64_t> chunk_lo(nt + 1, 0);
-    std::vector<int> used(nt, 0);
-    std::vector<int64_t> lo_of(nt, 0), hi_of(nt, 0);
-    parallel_for(A.nr, [&](int64_t lo, int64_t hi, int t) {
-        used[t] = 1;
-        lo_of[t] = lo;
-        hi_of[t] = hi;
-        std::vector<int32_t> marker(B.nc, -1);
-        std::vector<int32_t> cols;
-        std::vector<double> acc;
-        auto &oc = tcol[t];
-        auto &ov = tval[t];
-        for (int64_t i = lo; i < hi; ++i) {
-            cols.clear();
-            acc.clear();
-            for (int64_t ka = A.ptr[i]; ka < A.ptr[i + 1]; ++ka) {
-                const int32_t j = A.col[ka];
-                const double *a = &A.val[(size_t)ka * br * bk];
-                for (int64_t kb = B.ptr[j]; kb < B.ptr[j + 1]; ++kb) {
-                    const int32_t c = B.col[kb];
-                    int32_t slot = marker[c];
-                    if (slot < 0) {
-                        slot = (int32_t)cols.size();
-                        marker[c] = slot;
-                        cols.push_back(c);
-                        acc.resize(acc.size() + bb, 0.0);
-                    }
-                    const double *bv = &B.val[(size_t)kb * bk * bc];
-                    double *o = &acc[(size_t)slot * bb];
-                    for (int p = 0; p < br; ++p)
-                        for (int r = 0; r < bk; ++r) {
-                            const double av = a[p * bk + r];
-                            if (av == 0.0) continue;
-                            for (int q = 0; q < bc; ++q) o[p * bc + q] += av * bv[r * bc + q];
-                        }
-                }
-            }
-            // emit sorted by column
-            std::vector<int32_t> order(cols.size());
-            for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
-            std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cols[x] < cols[y]; });
-            for (int32_t k : order) {
-                oc.push_back(cols[k]);
-                ov.insert(ov.end(), acc.begin() + (size_t)k * bb, acc.begin() + (size_t)(k + 1) * bb);
-            }
-            cnt[i] = (int64_t)cols.size();
-            for (int32_t c : cols) marker[c] = -1;
-        }
-    });
-    C.ptr.assign(A.nr + 1, 0);
-    for (int64_t i = 0; i < A.nr; ++i) C.ptr[i + 1] = C.ptr[i] + cnt[i];
-    C.col.resize(C.ptr[A.nr]);
-    C.val.resize((size_t)C.ptr[A.nr] * bb);
-    for (int t = 0; t < nt; ++t) {
-        if (!used[t] || lo_of[t] >= hi_of[t]) continue;
-        int64_t off = C.ptr[lo_of[t]];
-        std::copy(tcol[t].begin(), tcol[t].end(), C.col.begin() + off);
-        std::copy(tval[t].begin(), tval[t].end(), C.val.begin() + (size_t)off * bb);
-    }
-    return C;
-}
-
-static HBsr bsr_transpose(const HBsr &A) {
-    HBsr T;
-    T.br = A.bc;
-    T.bc = A.br;
-    T.nr = A.nc;
-    T.nc = A.nr;
-    const int bb = A.br * A.bc;
-    T.ptr.assign(T.nr + 1, 0);
-    for (int32_t c : A.col) T.ptr[c + 1]++;
-    for (int64_t i = 0; i < T.nr; ++i) T.ptr[i + 1] += T.ptr[i];
-    T.col.resize(A.col.size());
-    T.val.resize(A.val.size());
-    std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
-    for (int64_t i = 0; i < A.nr; ++i)
-        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-            int64_t d = pos[A.col[k]]++;
-            T.col[d] = (int32_t)i;
-            const double *s = &A.val[(size_t)k * bb];
-            double *o = &T.val[(size_t)d * bb];
-            for (int p = 0; p < A.br; ++p)
-                for (int q = 0; q < A.bc; ++q) o[q * A.br + p] = s[p * A.bc + q];
-        }
-    return T;
-}
-
-// ---------------------------------------------------------------------------
 // strength and aggregation
 // ---------------------------------------------------------------------------
 struct Strength {
     std::vector<double> s;  // per stored block (0 on the diagonal)
 };
-
-// Frobenius norms with the squares summed in row-major order (no fused
-// multiply-add: this file is compiled with -ffp-contract=off).
-static Strength strength_of(const HBsr &A) {
-    const int bb = A.br * A.bc;
-    std::vector<double> fro(A.col.size());
-    parallel_for(A.nnzb(), [&](int64_t lo, int64_t hi, int) {
-        for (int64_t k = lo; k < hi; ++k) {
-            double acc = 0.0;
-            const double *v = &A.val[(size_t)k * bb];
-            for (int e = 0; e < bb; ++e) {
-                double sq = v[e] * v[e];
-                acc = acc + sq;
-            }
-            fro[k] = std::sqrt(acc);
-        }
-    });
-    std::vector<double> dn(A.nr, 0.0);
-    for (int64_t i = 0; i < A.nr; ++i)
-        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-            if (A.col[k] == i) dn[i] = fro[k];
-    Strength S;
-    S.s.resize(A.col.size());
-    parallel_for(A.nr, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t i = lo; i < hi; ++i)
-            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-                const int32_t j = A.col[k];
-                S.s[k] = (j == i) ? 0.0 : fro[k] / std::sqrt(dn[i] * dn[j]);
-            }
-    });
-    return S;
-}
 
 static const double kTieRtol = 1e-9;
 static const double kRankRtol = 1e-10;
@@ -431,81 +290,6 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
     return T;
 }
 
-// P = (I - omega D^-1 A) P_tent as a block matrix (bs x k blocks)
-static HBsr smoothed_P(const HBsr &A, const std::vector<double> &dpt, const Tentative &T, double omega, int k) {
-    const int bs = A.br;
-    HBsr P;
-    P.br = bs;
-    P.bc = k;
-    P.nr = A.nr;
-    P.nc = T.nc;
-    const int bb = bs * k;
-    const int nt = n_threads();
-    std::vector<std::vector<int32_t>> tcol(nt);
-    std::vector<std::vector<double>> tval(nt);
-    std::vector<int64_t> cnt(A.nr, 0), lo_of(nt, 0), hi_of(nt, 0);
-    std::vector<int> used(nt, 0);
-    parallel_for(A.nr, [&](int64_t lo, int64_t hi, int t) {
-        used[t] = 1;
-        lo_of[t] = lo;
-        hi_of[t] = hi;
-        std::vector<int32_t> cols;
-        std::vector<double> acc;
-        for (int64_t i = lo; i < hi; ++i) {
-            cols.clear();
-            acc.clear();
-            auto slot_of = [&](int32_t c) {
-                for (size_t s = 0; s < cols.size(); ++s)
-                    if (cols[s] == c) return (int)s;
-                cols.push_back(c);
-                acc.resize(acc.size() + bb, 0.0);
-                return (int)cols.size() - 1;
-            };
-            for (int64_t kk = A.ptr[i]; kk < A.ptr[i + 1]; ++kk) {
-                const int32_t j = A.col[kk];
-                if (T.agg[j] < 0) continue;
-                const int s = slot_of(T.agg[j]);
-                const double *a = &A.val[(size_t)kk * bs * bs];
-                const double *q = &T.Q[(size_t)j * bs * k];
-                double *o = &acc[(size_t)s * bb];
-                for (int p = 0; p < bs; ++p) {
-                    const double f = omega / dpt[i * bs + p];
-                    for (int r = 0; r < bs; ++r) {
-                        const double av = a[p * bs + r];
-                        if (av == 0.0) continue;
-                        for (int c = 0; c < k; ++c) o[p * k + c] -= f * av * q[r * k + c];
-                    }
-                }
-            }
-            if (T.agg[i] >= 0) {
-                const int s = slot_of(T.agg[i]);
-                const double *q = &T.Q[(size_t)i * bs * k];
-                double *o = &acc[(size_t)s * bb];
-                for (int e = 0; e < bb; ++e) o[e] += q[e];
-            }
-            std::vector<int32_t> order(cols.size());
-            for (size_t x = 0; x < order.size(); ++x) order[x] = (int32_t)x;
-            std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cols[x] < cols[y]; });
-            for (int32_t x : order) {
-                tcol[t].push_back(cols[x]);
-                tval[t].insert(tval[t].end(), acc.begin() + (size_t)x * bb, acc.begin() + (size_t)(x + 1) * bb);
-            }
-            cnt[i] = (int64_t)cols.size();
-        }
-    });
-    P.ptr.assign(A.nr + 1, 0);
-    for (int64_t i = 0; i < A.nr; ++i) P.ptr[i + 1] = P.ptr[i] + cnt[i];
-    P.col.resize(P.ptr[A.nr]);
-    P.val.resize((size_t)P.ptr[A.nr] * bb);
-    for (int t = 0; t < nt; ++t) {
-        if (!used[t] || lo_of[t] >= hi_of[t]) continue;
-        int64_t off = P.ptr[lo_of[t]];
-        std::copy(tcol[t].begin(), tcol[t].end(), P.col.begin() + off);
-        std::copy(tval[t].begin(), tval[t].end(), P.val.begin() + (size_t)off * bb);
-    }
-    return P;
-}
-
 // ---------------------------------------------------------------------------
 // SELL packing
 // ---------------------------------------------------------------------------
@@ -520,132 +304,6 @@ std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_
         });
     }
     return ord;
-}
-
-static void build_rowwave(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order,
-                          const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32,
-                          hipStream_t s) {
-    const int bb = M.br * M.bc;
-    S.format = FMT_ROWWAVE;
-    S.br = M.br;
-    S.bc = M.bc;
-    S.nrows = M.nr;
-    S.ncols = M.nc;
-    S.nnzb = M.nnzb();
-    S.nslices = 0;
-    S.padded = M.nnzb();
-    std::vector<int64_t> rptr(M.nr + 1, 0);
-    for (int64_t r = 0; r < M.nr; ++r) {
-        const int64_t o = row_order[r];
-        rptr[r + 1] = rptr[r] + (M.ptr[o + 1] - M.ptr[o]);
-    }
-    std::vector<int32_t> col(M.nnzb());
-    std::vector<double> val((size_t)M.nnzb() * bb);
-    parallel_for(M.nr, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t r = lo; r < hi; ++r) {
-            const int64_t o = row_order[r];
-            for (int64_t k = 0; k < M.ptr[o + 1] - M.ptr[o]; ++k) {
-                const int64_t src = M.ptr[o] + k, dst = rptr[r] + k;
-                col[dst] = col_map[M.col[src]];
-                std::copy(&M.val[(size_t)src * bb], &M.val[(size_t)(src + 1) * bb], &val[(size_t)dst * bb]);
-            }
-        }
-    });
-    upload(S.rptr, rptr, s);
-    upload(S.col, col, s);
-    upload(S.val, val, s);
-    S.slice_off.release();
-    S.rowlen.release();
-    if (fp32) {
-        std::vector<float> v32(val.size());
-        for (size_t i = 0; i < val.size(); ++i) v32[i] = (float)val[i];
-        upload(S.val32, v32, s);
-    } else {
-        S.val32.release();
-    }
-    if (out_map) {
-        std::vector<int32_t> rm(M.nr);
-        for (int64_t r = 0; r < M.nr; ++r) rm[r] = (*out_map)[row_order[r]];
-        upload(S.rowmap, rm, s);
-    } else {
-        S.rowmap.release();
-    }
-    TE_CHECK_HIP(hipStreamSynchronize(s));
-}
-
-void build_sell(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map,
-                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s, int format) {
-    if (format == FMT_ROWWAVE) {
-        build_rowwave(S, M, row_order, col_map, out_map, fp32, s);
-        return;
-    }
-    const int br = M.br, bc = M.bc, bb = br * bc;
-    S.format = FMT_SELL;
-    S.rptr.release();
-    S.br = br;
-    S.bc = bc;
-    S.nrows = M.nr;
-    S.ncols = M.nc;
-    S.nnzb = M.nnzb();
-    S.nslices = (M.nr + SELL_C - 1) / SELL_C;
-    std::vector<int32_t> off(S.nslices + 1, 0), rowlen(S.nslices * SELL_C, 0);
-    for (int64_t sl = 0; sl < S.nslices; ++sl) {
-        int64_t w = 0;
-        for (int l = 0; l < SELL_C; ++l) {
-            int64_t r = sl * SELL_C + l;
-            if (r >= M.nr) break;
-            int64_t o = row_order[r];
-            int64_t len = M.ptr[o + 1] - M.ptr[o];
-            rowlen[r] = (int32_t)len;
-            w = std::max(w, len);
-        }
-        TE_REQUIRE((int64_t)off[sl] + w < INT32_MAX, TE_EINVAL, "matrix too large for the SELL offsets");
-        off[sl + 1] = off[sl] + (int32_t)w;
-    }
-    const int64_t padded = (int64_t)off[S.nslices] * SELL_C;
-    S.padded = padded;
-    std::vector<int32_t> col(padded, 0);
-    std::vector<double> val((size_t)padded * bb, 0.0);
-    parallel_for(S.nslices, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t sl = lo; sl < hi; ++sl) {
-            const int64_t o0 = off[sl], w = off[sl + 1] - off[sl];
-            for (int l = 0; l < SELL_C; ++l) {
-                const int64_t r = sl * SELL_C + l;
-                int32_t last = 0;
-                const int64_t len = r < M.nr ? rowlen[r] : 0;
-                const int64_t orow = r < M.nr ? row_order[r] : 0;
-                for (int64_t k = 0; k < w; ++k) {
-                    const int64_t e = (o0 + k) * SELL_C + l;
-                    if (k < len) {
-                        const int64_t src = M.ptr[orow] + k;
-                        last = col_map[M.col[src]];
-                        for (int x = 0; x < bb; ++x)
-                            val[((o0 + k) * bb + x) * SELL_C + l] = M.val[(size_t)src * bb + x];
-                    }
-                    col[e] = last;
-                }
-            }
-        }
-    });
-    upload(S.slice_off, off, s);
-    upload(S.rowlen, rowlen, s);
-    upload(S.col, col, s);
-    upload(S.val, val, s);
-    if (fp32) {
-        std::vector<float> v32(val.size());
-        for (size_t i = 0; i < val.size(); ++i) v32[i] = (float)val[i];
-        upload(S.val32, v32, s);
-    } else {
-        S.val32.release();
-    }
-    if (out_map) {
-        std::vector<int32_t> rm(S.nslices * SELL_C, -1);
-        for (int64_t r = 0; r < M.nr; ++r) rm[r] = (*out_map)[row_order[r]];
-        upload(S.rowmap, rm, s);
-    } else {
-        S.rowmap.release();
-    }
-    TE_CHECK_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------------------
@@ -797,31 +455,38 @@ static void rigid_body_modes(const std::vector<double> &X, const std::vector<uin
 
 // Lane-per-row SELL for operators with 3-row blocks (many short rows); one
 // wave per row for 6-row blocks (coarse operators, restrictions).
-static int fmt_for(const HBsr &M) { return M.br >= 6 ? FMT_ROWWAVE : FMT_SELL; }
+static int fmt_for(int br) { return br >= 6 ? FMT_ROWWAVE : FMT_SELL; }
 
-static void finish_level(Level &L, const amg_options &o, hipStream_t s) {
-    // storage order and operator
+// Storage order, packed operator and point diagonal of a level; dnat gets
+// the diagonal in natural numbering (device) for the prolongator smoothing.
+static void finish_level(Level &L, const DBsr &D, const amg_options &o, DBuf<double> &dnat, hipStream_t s) {
     L.perm_h = window_sorted_order(L.Ah.ptr, 4096);
     L.iperm_h.assign(L.n, 0);
     for (int64_t i = 0; i < L.n; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
-    build_sell(L.A, L.Ah, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.Ah));
+    dev_pack(L.A, D, L.Ah.ptr, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.bs));
     upload(L.perm, L.perm_h, s);
-    std::vector<double> dnat;
-    bsr_diag_points(L.Ah, dnat);
+    dev_diag(D, dnat, s);
+    std::vector<double> dh;
+    download(dh, dnat.p, (size_t)L.n * L.bs, s);
+    for (int64_t i = 0; i < L.n; ++i)
+        for (int p = 0; p < L.bs; ++p)
+            TE_REQUIRE(dh[(size_t)i * L.bs + p] > 0, TE_EINVAL, "non-positive diagonal entry %g at level %d row %lld",
+                       dh[(size_t)i * L.bs + p], L.index, (long long)i);
     L.dstore.assign((size_t)L.n * L.bs, 0.0);
     std::vector<double> dinv((size_t)L.n * L.bs);
     std::vector<float> dinv32((size_t)L.n * L.bs);
-    for (int64_t i = 0; i < L.n; ++i)
-        for (int p = 0; p < L.bs; ++p) {
-            double d = dnat[(size_t)L.perm_h[i] * L.bs + p];
-            TE_REQUIRE(d > 0, TE_EINVAL, "non-positive diagonal entry %g at level %d row %lld", d, L.index,
-                       (long long)L.perm_h[i]);
-            L.dstore[i * L.bs + p] = d;
-            dinv[i * L.bs + p] = 1.0 / d;
-            dinv32[i * L.bs + p] = (float)(1.0 / d);
-        }
+    parallel_for(L.n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int p = 0; p < L.bs; ++p) {
+                const double d = dh[(size_t)L.perm_h[i] * L.bs + p];
+                L.dstore[i * L.bs + p] = d;
+                dinv[i * L.bs + p] = 1.0 / d;
+                dinv32[i * L.bs + p] = (float)(1.0 / d);
+            }
+    });
     upload(L.dinv, dinv, s);
     if (o.build_fp32) upload(L.dinv32, dinv32, s);
+    TE_CHECK_HIP(hipStreamSynchronize(s));
 }
 
 static void set_cheb(Level &L, const amg_options &o) {
@@ -893,34 +558,6 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     auto h = std::make_unique<amg_handle>();
     h->opt = o;
     const int64_t n = A->n_brows;
-    // host copies
-    Level L0;
-    L0.index = 0;
-    L0.bs = 3;
-    L0.n = n;
-    L0.Ah.br = L0.Ah.bc = 3;
-    L0.Ah.nr = L0.Ah.nc = n;
-    download(L0.Ah.ptr, A->row_ptr, (size_t)n + 1, s);
-    TE_REQUIRE(L0.Ah.ptr[0] == 0 && L0.Ah.ptr[n] == A->nnzb, TE_EINVAL, "row_ptr inconsistent with nnzb");
-    download(L0.Ah.col, A->col_idx, (size_t)A->nnzb, s);
-    for (int64_t i = 0; i < n; ++i) {
-        TE_REQUIRE(L0.Ah.ptr[i + 1] >= L0.Ah.ptr[i], TE_EINVAL, "row_ptr decreases at row %lld", (long long)i);
-        bool diag = false;
-        for (int64_t k = L0.Ah.ptr[i]; k < L0.Ah.ptr[i + 1]; ++k) {
-            const int32_t c = L0.Ah.col[k];
-            TE_REQUIRE(c >= 0 && c < n, TE_EINVAL, "column index %d out of range in row %lld", c, (long long)i);
-            diag = diag || c == i;
-        }
-        TE_REQUIRE(diag, TE_EINVAL, "row %lld has no diagonal block", (long long)i);
-    }
-    download(L0.Ah.val, A->val, (size_t)A->nnzb * 9, s);
-    std::vector<double> X;
-    download(X, coords, (size_t)n * 3, s);
-    std::vector<uint8_t> mask;
-    if (dir_mask) download(mask, dir_mask, (size_t)n * 3, s);
-    std::vector<double> B;
-    rigid_body_modes(X, mask, n, B);
-    const int k = 6;
     const bool verbose = std::getenv("TE_VERBOSE") != nullptr;
     auto note = [&](const char *what, int l, int64_t nn, int64_t nz) {
         if (!verbose) return;
@@ -929,72 +566,154 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                      (long long)nz);
         std::fflush(stderr);
     };
+    // level 0: the pattern on the host (aggregation, storage order), the
+    // values stay in the caller's device arrays
+    Level L0;
+    L0.index = 0;
+    L0.bs = 3;
+    L0.n = n;
+    L0.Ah.br = L0.Ah.bc = 3;
+    L0.Ah.nr = L0.Ah.nc = n;
+    download(L0.Ah.ptr, A->row_ptr, (size_t)n + 1, s);
+    TE_REQUIRE(L0.Ah.ptr[0] == 0 && L0.Ah.ptr[n] == A->nnzb, TE_EINVAL, "row_ptr inconsistent with nnzb");
+    for (int64_t i = 0; i < n; ++i)
+        TE_REQUIRE(L0.Ah.ptr[i + 1] >= L0.Ah.ptr[i], TE_EINVAL, "row_ptr decreases at row %lld", (long long)i);
+    download(L0.Ah.col, A->col_idx, (size_t)A->nnzb, s);
+    {
+        std::atomic<int64_t> bad{INT64_MAX};
+        parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t i = lo; i < hi; ++i) {
+                bool diag = false, ok = true;
+                for (int64_t k = L0.Ah.ptr[i]; k < L0.Ah.ptr[i + 1]; ++k) {
+                    const int32_t c = L0.Ah.col[k];
+                    ok = ok && c >= 0 && c < n;
+                    diag = diag || c == i;
+                }
+                if (!ok || !diag) {
+                    int64_t cur = bad.load();
+                    while (i < cur && !bad.compare_exchange_weak(cur, i)) {
+                    }
+                    break;
+                }
+            }
+        });
+        const int64_t i = bad.load();
+        TE_REQUIRE(i == INT64_MAX, TE_EINVAL, "row %lld has a column index out of range or no diagonal block",
+                   (long long)i);
+    }
+    DBsr D0;  // view of the caller's matrix
+    D0.br = D0.bc = 3;
+    D0.nr = D0.nc = n;
+    D0.nnzb = A->nnzb;
+    D0.ptr = A->row_ptr;
+    D0.col = A->col_idx;
+    D0.val = A->val;
+    std::vector<double> X;
+    download(X, coords, (size_t)n * 3, s);
+    std::vector<uint8_t> mask;
+    if (dir_mask) download(mask, dir_mask, (size_t)n * 3, s);
+    std::vector<double> B;
+    rigid_body_modes(X, mask, n, B);
+    const int k = 6;
     h->L.push_back(std::move(L0));
+    DBsr owned;               // operator of the current level below the mesh level
+    const DBsr *cur = &D0;    // natural-numbering operator of the current level
+    DBsr Pn, Rn;              // transfers of the previous level, waiting for this level's storage order
+    std::vector<int64_t> Pn_ptr, Rn_ptr;
+    bool pending = false;
     for (int l = 0;; ++l) {
         Level &L = h->L[l];
         note("pack operator", l, L.n, L.Ah.nnzb());
-        finish_level(L, o, s);
-        const int64_t ndof = L.n * L.bs;
-        if (ndof <= o.coarse_max || l == o.max_levels - 1) break;
-        L.lam = lanczos_estimate(L, o.lanczos_steps, 0x5EEDull + (uint64_t)l, s);
-        set_cheb(L, o);
-        const double theta = o.theta0 * std::ldexp(1.0, -l);
-        Strength S = strength_of(L.Ah);
-        std::vector<int32_t> agg;
-        int64_t na;
-        if (agg_given && l < n_given) {
-            TE_REQUIRE(agg_given[l], TE_EINVAL, "aggregate map of level %d is NULL", l);
-            agg.assign(agg_given[l], agg_given[l] + L.n);
-            na = 0;
-            for (int32_t a : agg) {
-                TE_REQUIRE(a >= -1 && a < L.n, TE_EINVAL, "aggregate id %d out of range at level %d", a, l);
-                na = std::max<int64_t>(na, (int64_t)a + 1);
-            }
-        } else {
-            na = greedy_aggregate(L.Ah, S, theta, agg);
+        DBuf<double> dnat;
+        finish_level(L, *cur, o, dnat, s);
+        if (pending) {
+            Level &U = h->L[l - 1];
+            const auto pord = window_sorted_order(Pn_ptr, 4096);
+            dev_pack(U.P, Pn, Pn_ptr, pord, L.iperm_h, &U.iperm_h, o.build_fp32 != 0, s, fmt_for(Pn.br));
+            // restriction rows in this level's own storage order: contiguous output
+            dev_pack(U.R, Rn, Rn_ptr, L.perm_h, U.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(Rn.br));
+            Pn.release();
+            Rn.release();
+            pending = false;
+            note("transfer operators packed", l - 1, 0, 0);
         }
-        if (na == 0) break;
-        note("aggregated", l, na, 0);
-        Tentative T = tentative(L.Ah, S, agg, na, B, L.bs, k);
-        std::vector<double> dnat;
-        bsr_diag_points(L.Ah, dnat);
-        HBsr P = smoothed_P(L.Ah, dnat, T, 4.0 / (3.0 * L.lam), k);
-        note("smoothed P", l, P.nr, P.nnzb());
-        HBsr AP = bsr_mult(L.Ah, P);
-        note("A P", l, AP.nr, AP.nnzb());
-        HBsr R = bsr_transpose(P);
-        HBsr Ac = bsr_mult(R, AP);
-        note("Galerkin", l, Ac.nr, Ac.nnzb());
-        AP = HBsr();
-        if ((double)Ac.nr * k > o.max_coarse_ratio * (double)ndof) break;
-        L.agg = T.agg;
-        L.Ph = std::move(P);
-        L.Rh = std::move(R);
-        Level N;
-        N.index = l + 1;
-        N.bs = k;
-        N.n = Ac.nr;
-        N.Ah = std::move(Ac);
-        B = T.Bc;
-        h->L.push_back(std::move(N));
+        const int64_t ndof = L.n * L.bs;
+        bool coarsest = ndof <= o.coarse_max || l == o.max_levels - 1;
+        if (!coarsest) {
+            L.lam = lanczos_estimate(L, o.lanczos_steps, 0x5EEDull + (uint64_t)l, s);
+            set_cheb(L, o);
+            const double theta = o.theta0 * std::ldexp(1.0, -l);
+            Strength S;
+            {
+                DBuf<double> ds;
+                dev_strength(*cur, ds, s);
+                download(S.s, ds.p, (size_t)cur->nnzb, s);
+            }
+            std::vector<int32_t> agg;
+            int64_t na;
+            if (agg_given && l < n_given) {
+                TE_REQUIRE(agg_given[l], TE_EINVAL, "aggregate map of level %d is NULL", l);
+                agg.assign(agg_given[l], agg_given[l] + L.n);
+                na = 0;
+                for (int32_t a : agg) {
+                    TE_REQUIRE(a >= -1 && a < L.n, TE_EINVAL, "aggregate id %d out of range at level %d", a, l);
+                    na = std::max<int64_t>(na, (int64_t)a + 1);
+                }
+            } else {
+                na = greedy_aggregate(L.Ah, S, theta, agg);
+            }
+            coarsest = na == 0;
+            if (!coarsest) {
+                note("aggregated", l, na, 0);
+                Tentative T = tentative(L.Ah, S, agg, na, B, L.bs, k);
+                S = Strength();
+                DBuf<int32_t> dagg;
+                DBuf<double> dQ;
+                upload(dagg, T.agg, s);
+                upload(dQ, T.Q, s);
+                DBsr P, AP, R, Ac;
+                dev_smoothed_p(*cur, dagg, T.nc, dQ, dnat, 4.0 / (3.0 * L.lam), P, s);
+                note("smoothed P", l, P.nr, P.nnzb);
+                dev_mult(*cur, P, AP, s);
+                note("A P", l, AP.nr, AP.nnzb);
+                dev_transpose(P, R, s);
+                dev_mult(R, AP, Ac, s);
+                note("Galerkin", l, Ac.nr, Ac.nnzb);
+                AP.release();
+                coarsest = (double)Ac.nr * k > o.max_coarse_ratio * (double)ndof;
+                if (!coarsest) {
+                    L.agg = T.agg;
+                    L.p_nnzb = P.nnzb;
+                    Level N;
+                    N.index = l + 1;
+                    N.bs = k;
+                    N.n = Ac.nr;
+                    dev_pattern_to_host(Ac, N.Ah, s);
+                    B = std::move(T.Bc);
+                    download(Pn_ptr, P.ptr, (size_t)P.nr + 1, s);
+                    download(Rn_ptr, R.ptr, (size_t)R.nr + 1, s);
+                    Pn = std::move(P);
+                    Rn = std::move(R);
+                    pending = true;
+                    owned = std::move(Ac);  // releases this level's operator (already packed)
+                    cur = &owned;
+                    h->L.push_back(std::move(N));
+                    continue;
+                }
+            }
+        }
+        // this level is the coarsest: its values on the host for the dense factor
+        TE_REQUIRE(ndof <= 12000, TE_EINVAL, "coarsest level has %lld DOF, too many for the dense factor",
+                   (long long)ndof);
+        dev_to_host(*cur, L.Ah, s);
+        break;
     }
-    // transfer operators (need the next level's storage order)
-    for (size_t l = 0; l + 1 < h->L.size(); ++l) {
-        Level &L = h->L[l];
-        Level &N = h->L[l + 1];
-        auto pord = window_sorted_order(L.Ph.ptr, 4096);
-        build_sell(L.P, L.Ph, pord, N.iperm_h, &L.iperm_h, o.build_fp32 != 0, s, fmt_for(L.Ph));
-        // restriction rows in the coarse level's own order: contiguous output
-        build_sell(L.R, L.Rh, N.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.Rh));
-    }
-    note("transfer operators packed", (int)h->L.size() - 1, 0, 0);
+    owned.release();
     // coarsest level: dense inverse of (A + A^T)/2 in storage order
     {
         Level &C = h->L.back();
         C.lam = 0.0;
         const int64_t nc = C.n * C.bs;
-        TE_REQUIRE(nc <= 12000, TE_EINVAL, "coarsest level has %lld DOF, too many for the dense factor",
-                   (long long)nc);
         std::vector<double> M((size_t)nc * nc, 0.0);
         const int b = C.bs;
         for (int64_t i = 0; i < C.n; ++i)
@@ -1018,6 +737,36 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = h.release();
     return TE_OK;
+}
+
+// Values of A_l in natural numbering from the packed operator: storage row r
+// holds natural row perm[r] with its blocks in the natural order.
+static void unpack_values(const Level &L, std::vector<double> &val) {
+    const Sell &S = L.A;
+    const int bb = S.br * S.bc;
+    hipStream_t s = nullptr;
+    std::vector<double> sv;
+    download(sv, S.val.p, S.val.n, s);
+    val.assign((size_t)L.Ah.nnzb() * bb, 0.0);
+    if (S.format == FMT_ROWWAVE) {
+        std::vector<int64_t> rptr;
+        download(rptr, S.rptr.p, (size_t)S.nrows + 1, s);
+        for (int64_t r = 0; r < S.nrows; ++r) {
+            const int64_t o = L.perm_h[r], d0 = L.Ah.ptr[o];
+            for (int64_t k = 0; k < rptr[r + 1] - rptr[r]; ++k)
+                for (int x = 0; x < bb; ++x) val[(size_t)(d0 + k) * bb + x] = sv[(size_t)(rptr[r] + k) * bb + x];
+        }
+    } else {
+        std::vector<int32_t> off;
+        download(off, S.slice_off.p, (size_t)S.nslices + 1, s);
+        for (int64_t r = 0; r < S.nrows; ++r) {
+            const int64_t o = L.perm_h[r], d0 = L.Ah.ptr[o], len = L.Ah.ptr[o + 1] - d0;
+            const int64_t sl = r / SELL_C, ln = r % SELL_C;
+            for (int64_t k = 0; k < len; ++k)
+                for (int x = 0; x < bb; ++x)
+                    val[(size_t)(d0 + k) * bb + x] = sv[(size_t)(((int64_t)off[sl] + k) * bb + x) * SELL_C + ln];
+        }
+    }
 }
 
 }  // namespace te
@@ -1073,7 +822,7 @@ extern "C" int amg_get_info(const amg_handle *h, amg_info *info) {
             info->nnzb[l] = L.Ah.nnzb();
             info->bs[l] = L.bs;
             info->lambda_hat[l] = L.lam;
-            info->p_nnzb[l] = L.Ph.nnzb();
+            info->p_nnzb[l] = L.p_nnzb;
             bytes += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() + L.perm.bytes();
         }
         info->setup_ms = h->setup_ms;
@@ -1096,12 +845,17 @@ extern "C" int amg_get_level_matrix(const amg_handle *h, int32_t level, int64_t 
     return guarded([&] {
         TE_REQUIRE(h && n_rows_out && nnzb_out, TE_EINVAL, "NULL argument");
         TE_REQUIRE(level >= 0 && level < (int)h->L.size(), TE_EINVAL, "bad level %d", level);
-        const HBsr &M = h->L[level].Ah;
+        const Level &L = h->L[level];
+        const HBsr &M = L.Ah;
         *n_rows_out = M.nr;
         *nnzb_out = M.nnzb();
         if (row_ptr) std::copy(M.ptr.begin(), M.ptr.end(), row_ptr);
         if (col) std::copy(M.col.begin(), M.col.end(), col);
-        if (val) std::copy(M.val.begin(), M.val.end(), val);
+        if (val) {
+            std::vector<double> v;
+            unpack_values(L, v);
+            std::copy(v.begin(), v.end(), val);
+        }
         return TE_OK;
     });
 }

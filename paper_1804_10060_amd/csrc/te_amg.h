@@ -17,8 +17,8 @@ struct Level {
     int index = 0;
     int bs = 3;                    // block size (3 on the mesh level, 6 below)
     int64_t n = 0;                 // block rows
-    HBsr Ah;                       // operator, natural numbering (host)
-    HBsr Ph, Rh;                   // transfer to the next level, natural numbering (host)
+    HBsr Ah;                       // pattern in natural numbering (host; values only on the coarsest level)
+    int64_t p_nnzb = 0;            // stored blocks of the prolongator to the next level
     std::vector<int32_t> agg;      // aggregate of each node (natural), -1 isolated
     std::vector<int32_t> perm_h;   // storage position -> natural index
     std::vector<int32_t> iperm_h;  // natural index -> storage position

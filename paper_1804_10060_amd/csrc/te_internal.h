@@ -155,14 +155,6 @@ struct Sell {
     }
 };
 
-// Build a SELL matrix from a host block matrix.
-//   row_order[i] = row of M stored at position i (lane i%64 of slice i/64)
-//   col_map[c]   = column index used for column c of M
-//   out_map      = if non-null, position i writes output row (*out_map)[row_order[i]];
-//                  otherwise position i writes output row i
-void build_sell(Sell &S, const HBsr &M, const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map,
-                const std::vector<int32_t> *out_map, bool fp32, hipStream_t s, int format = FMT_SELL);
-
 // Row order sorted by descending length inside windows of `window` rows.
 std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_t window);
 

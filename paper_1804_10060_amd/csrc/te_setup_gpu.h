@@ -1,0 +1,69 @@
+// Block compressed-row matrices on the device and the sparse products of the
+// smoothed-aggregation setup that run on them (te_setup_gpu.hip).
+#pragma once
+
+#include "te_internal.h"
+
+namespace te {
+
+// Natural numbering, sorted columns per row, blocks row-major [nnzb][br][bc].
+// The pointers either refer to the owned buffers or, for a caller's matrix,
+// to memory the library does not own.
+struct DBsr {
+    int br = 0, bc = 0;
+    int64_t nr = 0, nc = 0, nnzb = 0;
+    const int64_t *ptr = nullptr;
+    const int32_t *col = nullptr;
+    const double *val = nullptr;
+    DBuf<int64_t> ptr_own;
+    DBuf<int32_t> col_own;
+    DBuf<double> val_own;
+    void bind() {
+        ptr = ptr_own.p;
+        col = col_own.p;
+        val = val_own.p;
+    }
+    void release() {
+        ptr_own.release();
+        col_own.release();
+        val_own.release();
+        ptr = nullptr;
+        col = nullptr;
+        val = nullptr;
+        nnzb = 0;
+    }
+};
+
+// s[k] = |A_k|_F / sqrt(|A_ii|_F |A_jj|_F) for the off-diagonal block k = (i, j),
+// 0 on the diagonal; squares and sums rounded separately (no contraction).
+void dev_strength(const DBsr &A, DBuf<double> &s, hipStream_t st);
+
+// Point diagonal of A in natural numbering: d[i*br + p] = A_ii[p][p].
+void dev_diag(const DBsr &A, DBuf<double> &d, hipStream_t st);
+
+// P = (I - omega D^-1 A) P_tent with P_tent given by the aggregate of each
+// node (agg, -1 = none) and the orthonormal rows Q [n][br][6].
+void dev_smoothed_p(const DBsr &A, const DBuf<int32_t> &agg, int64_t nagg, const DBuf<double> &Q,
+                    const DBuf<double> &d, double omega, DBsr &P, hipStream_t s);
+
+// C = A B with the blocks summed in the order of A's row, then B's row.
+void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s);
+
+// T = A^T (blocks transposed; rows of each column in ascending order).
+void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s);
+
+// Pack M into a solver layout (SELL-64 or one wave per row).  hptr is M's
+// row pointer on the host.
+//   row_order[i] = row of M stored at position i (lane i%64 of slice i/64)
+//   col_map[c]   = column index stored for column c of M
+//   out_map      = if non-null, position i writes output row (*out_map)[row_order[i]];
+//                  otherwise position i writes output row i
+void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &row_order,
+              const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32, hipStream_t s,
+              int format);
+
+// Host copies of the pattern or of the whole matrix.
+void dev_pattern_to_host(const DBsr &M, HBsr &H, hipStream_t s);
+void dev_to_host(const DBsr &M, HBsr &H, hipStream_t s);
+
+}  // namespace te

@@ -1,0 +1,639 @@
+// Device-side products of the smoothed-aggregation setup (Sec. 2.1.3):
+// strength of connection, the smoothed prolongator P = (I - w D^-1 A) P_tent,
+// the product A P, the transpose R = P^T and the Galerkin product R (A P),
+// all on block compressed rows, and the packing of an operator into the
+// solver layouts.  The greedy aggregation and the per-aggregate QR stay on
+// the host: both are sequential by definition.
+//
+// Sparse products take two passes.  Symbolic: one wave per output row puts
+// the candidate columns into an open-addressing hash set in LDS, counts them,
+// and (second call) writes them sorted by rank.  Numeric: one wave per output
+// row maps column -> slot through the same kind of LDS table; lane e owns
+// entry e of every output block, and the contributions are added in the order
+// of A's row, then B's row.  Every output value is thus summed by one lane in
+// a fixed order: the result does not depend on the launch or on timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "te_setup_gpu.h"
+
+namespace te {
+
+namespace {
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
+
+template <int TB>
+__device__ __forceinline__ uint32_t hslot(int32_t c) {
+    return ((uint32_t)c * 2654435761u) >> (32 - ilog2(TB));
+}
+
+// Insert c into the set (tab: TB slots, -1 = empty).  New keys are appended
+// to lst.  Returns false when the table is full.
+template <int TB>
+__device__ __forceinline__ bool set_insert(int32_t *tab, int32_t *lst, int32_t *num, int32_t c) {
+    uint32_t h = hslot<TB>(c);
+    for (int probe = 0; probe < TB; ++probe) {
+        const int32_t old = atomicCAS(&tab[h], -1, c);
+        if (old == -1) {
+            const int32_t at = atomicAdd(num, 1);
+            if (at < TB) lst[at] = c;
+            return true;
+        }
+        if (old == c) return true;
+        h = (h + 1) & (TB - 1);
+    }
+    return false;
+}
+
+// flag bits: 1 row set overflowed the table, 2 pattern/count mismatch,
+//            4 row longer than the numeric table, 8 column missing from the pattern
+template <int TB, bool AGG>
+__global__ void __launch_bounds__(64) k_sym(int64_t n, const int64_t *__restrict__ aptr,
+                                            const int32_t *__restrict__ acol, const int64_t *__restrict__ bptr,
+                                            const int32_t *__restrict__ bcol, const int32_t *__restrict__ agg,
+                                            int32_t *__restrict__ cnt, const int64_t *__restrict__ cptr,
+                                            int32_t *__restrict__ ccol, int32_t *__restrict__ flag) {
+    __shared__ int32_t tab[TB];
+    __shared__ int32_t lst[TB];
+    __shared__ int32_t num;
+    const int lane = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        for (int t = lane; t < TB; t += 64) tab[t] = -1;
+        if (lane == 0) num = 0;
+        __syncthreads();
+        bool ok = true;
+        if (AGG) {
+            // columns of P's row i: the aggregates of the nodes of A's row i
+            for (int64_t ka = aptr[i] + lane; ka < aptr[i + 1]; ka += 64) {
+                const int32_t c = agg[acol[ka]];
+                if (c >= 0) ok = set_insert<TB>(tab, lst, &num, c) && ok;
+            }
+        } else {
+            for (int64_t ka = aptr[i]; ka < aptr[i + 1]; ++ka) {
+                const int32_t j = acol[ka];
+                for (int64_t kb = bptr[j] + lane; kb < bptr[j + 1]; kb += 64)
+                    ok = set_insert<TB>(tab, lst, &num, bcol[kb]) && ok;
+            }
+        }
+        if (!ok) atomicOr(flag, 1);
+        __syncthreads();
+        const int m = min(num, TB);
+        if (cptr == nullptr) {
+            if (lane == 0) cnt[i] = m;
+        } else {
+            const int64_t c0 = cptr[i];
+            if (cptr[i + 1] - c0 != (int64_t)m) {
+                if (lane == 0) atomicOr(flag, 2);
+            } else {
+                for (int x = lane; x < m; x += 64) {
+                    const int32_t key = lst[x];
+                    int r = 0;
+                    for (int y = 0; y < m; ++y) r += lst[y] < key ? 1 : 0;
+                    ccol[c0 + r] = key;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int BR, int BK, int BC, int TB>
+__global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict__ aptr,
+                                            const int32_t *__restrict__ acol, const double *__restrict__ aval,
+                                            const int64_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
+                                            const double *__restrict__ bval, const int64_t *__restrict__ cptr,
+                                            const int32_t *__restrict__ ccol, double *__restrict__ cval,
+                                            int32_t *__restrict__ flag) {
+    constexpr int BB = BR * BC;
+    static_assert(BB <= 64, "output block larger than a wave");
+    __shared__ int32_t key[TB];
+    __shared__ int32_t slot[TB];
+    const int lane = threadIdx.x;
+    const bool on = lane < BB;
+    const int p = on ? lane / BC : 0, q = on ? lane % BC : 0;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t c0 = cptr[i];
+        const int m = (int)(cptr[i + 1] - c0);
+        if (2 * m > TB) {  // uniform over the block
+            if (lane == 0) atomicOr(flag, 4);
+            continue;
+        }
+        for (int t = lane; t < TB; t += 64) key[t] = -1;
+        __syncthreads();
+        for (int x = lane; x < m; x += 64) {
+            const int32_t c = ccol[c0 + x];
+            uint32_t h = hslot<TB>(c);
+            for (int probe = 0; probe < TB; ++probe) {
+                if (atomicCAS(&key[h], -1, c) == -1) {
+                    slot[h] = x;
+                    break;
+                }
+                h = (h + 1) & (TB - 1);
+            }
+        }
+        for (int64_t t = lane; t < (int64_t)m * BB; t += 64) cval[c0 * BB + t] = 0.0;
+        __syncthreads();
+        for (int64_t ka = aptr[i]; ka < aptr[i + 1]; ++ka) {
+            const int32_t j = acol[ka];
+            double ar[BK];
+            const double *a = aval + ka * (BR * BK) + p * BK;
+#pragma unroll
+            for (int r = 0; r < BK; ++r) ar[r] = on ? a[r] : 0.0;
+            for (int64_t kb = bptr[j]; kb < bptr[j + 1]; ++kb) {
+                const int32_t c = bcol[kb];
+                uint32_t h = hslot<TB>(c);
+                int probe = 0;
+                while (probe < TB && key[h] != c) {
+                    h = (h + 1) & (TB - 1);
+                    ++probe;
+                }
+                if (probe == TB) {
+                    if (lane == 0) atomicOr(flag, 8);
+                    continue;
+                }
+                if (on) {
+                    const double *b = bval + kb * (BK * BC) + q;
+                    double t = 0.0;
+#pragma unroll
+                    for (int r = 0; r < BK; ++r) t += ar[r] * b[r * BC];
+                    cval[(c0 + slot[h]) * BB + lane] += t;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- strength of connection and diagonal -----------------------------------------
+__global__ void k_fro(int64_t nnzb, int bb, const double *__restrict__ val, double *__restrict__ fro) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnzb; k += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int e = 0; e < bb; ++e) {
+            const double v = val[k * bb + e];
+            acc = __dadd_rn(acc, __dmul_rn(v, v));
+        }
+        fro[k] = __dsqrt_rn(acc);
+    }
+}
+__global__ void k_diag_fro(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ fro, double *__restrict__ dn) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double d = 0.0;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+            if (col[k] == i) d = fro[k];
+        dn[i] = d;
+    }
+}
+__global__ void k_strength(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                           const double *__restrict__ dn, double *__restrict__ s /* in: fro, out: strength */) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            s[k] = (j == i) ? 0.0 : __ddiv_rn(s[k], __dsqrt_rn(__dmul_rn(dn[i], dn[j])));
+        }
+}
+__global__ void k_diag_points(int64_t n, int b, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                              const double *__restrict__ val, double *__restrict__ d) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        for (int p = 0; p < b; ++p) d[i * b + p] = 0.0;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+            if (col[k] == i)
+                for (int p = 0; p < b; ++p) d[i * b + p] = val[k * b * b + p * b + p];
+    }
+}
+
+// ---- smoothed prolongator, numeric ---------------------------------------------------
+// P_iJ = [agg i = J] Q_i - w D_i^-1 sum_{j in row i, agg j = J} A_ij Q_j   (BS x 6 blocks);
+// one thread per row, terms in the order of A's row, the tentative part last
+template <int BS>
+__global__ void k_p_numeric(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ val, const int32_t *__restrict__ agg,
+                            const double *__restrict__ Q, const double *__restrict__ d, double omega,
+                            const int64_t *__restrict__ pptr, const int32_t *__restrict__ pcol,
+                            double *__restrict__ pval, int32_t *__restrict__ flag) {
+    constexpr int K = 6;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p0 = pptr[i], p1 = pptr[i + 1];
+        for (int64_t e = p0 * BS * K; e < p1 * BS * K; ++e) pval[e] = 0.0;
+        auto find = [&](int32_t a) -> int64_t {
+            int64_t lo = p0, hi = p1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (pcol[mid] < a) lo = mid + 1;
+                else hi = mid;
+            }
+            return (lo < p1 && pcol[lo] == a) ? lo : -1;
+        };
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            const int32_t a = agg[j];
+            if (a < 0) continue;
+            const int64_t at = find(a);
+            if (at < 0) {
+                atomicOr(flag, 8);
+                continue;
+            }
+            double *o = pval + at * BS * K;
+            const double *av = val + k * BS * BS;
+            const double *qv = Q + (int64_t)j * BS * K;
+            for (int pp = 0; pp < BS; ++pp) {
+                const double f = omega / d[i * BS + pp];
+                for (int r = 0; r < BS; ++r) {
+                    const double ar = av[pp * BS + r];
+                    if (ar == 0.0) continue;
+                    for (int c = 0; c < K; ++c) o[pp * K + c] -= f * ar * qv[r * K + c];
+                }
+            }
+        }
+        const int32_t ai = agg[i];
+        if (ai >= 0) {
+            const int64_t at = find(ai);
+            if (at < 0) {
+                atomicOr(flag, 8);
+                continue;
+            }
+            double *o = pval + at * BS * K;
+            const double *qv = Q + i * BS * K;
+            for (int e = 0; e < BS * K; ++e) o[e] += qv[e];
+        }
+    }
+}
+
+// ---- transpose --------------------------------------------------------------------------
+__global__ void k_t_count(int64_t nnzb, const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnzb; k += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[col[k]], 1);
+}
+// every stored block k of A goes to a free place of its column's segment;
+// the segments are then sorted by k, i.e. by row of A
+__global__ void k_t_place(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                          const int64_t *__restrict__ tptr, int32_t *__restrict__ fill, int64_t *__restrict__ src,
+                          int32_t *__restrict__ row) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t c = col[k];
+            const int32_t at = atomicAdd(&fill[c], 1);
+            src[tptr[c] + at] = k;
+            row[k] = (int32_t)i;
+        }
+}
+__global__ void k_t_sort(int64_t n, const int64_t *__restrict__ tptr, int64_t *__restrict__ src) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lo = tptr[r], hi = tptr[r + 1];
+        for (int64_t a = lo + 1; a < hi; ++a) {
+            const int64_t v = src[a];
+            int64_t b = a - 1;
+            while (b >= lo && src[b] > v) {
+                src[b + 1] = src[b];
+                --b;
+            }
+            src[b + 1] = v;
+        }
+    }
+}
+template <int BR, int BC>
+__global__ void k_t_fill(int64_t tn, const int64_t *__restrict__ src, const int32_t *__restrict__ row,
+                         const double *__restrict__ val, int32_t *__restrict__ tcol, double *__restrict__ tval) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tn; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = src[t];
+        tcol[t] = row[k];
+        for (int p = 0; p < BR; ++p)
+            for (int q = 0; q < BC; ++q) tval[t * BR * BC + q * BR + p] = val[k * BR * BC + p * BC + q];
+    }
+}
+
+// ---- packing into the solver layouts ----------------------------------------------------
+// SELL-64: storage position r (slice r/64, lane r%64) holds row order[r]
+__global__ void k_pack_sell(int64_t nr, int bb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ val, const int32_t *__restrict__ order,
+                            const int32_t *__restrict__ colmap, const int32_t *__restrict__ slice_off,
+                            int64_t nslices, int32_t *__restrict__ scol, double *__restrict__ sval,
+                            float *__restrict__ sval32) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nslices * 64;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sl = r / 64, l = r % 64;
+        const int64_t o0 = slice_off[sl], w = slice_off[sl + 1] - o0;
+        const bool real = r < nr;
+        const int64_t o = real ? order[r] : 0;
+        const int64_t s0 = real ? ptr[o] : 0;
+        const int64_t len = real ? ptr[o + 1] - s0 : 0;
+        int32_t last = 0;
+        for (int64_t k = 0; k < w; ++k) {
+            if (k < len) last = colmap[col[s0 + k]];
+            scol[(o0 + k) * 64 + l] = last;
+            for (int x = 0; x < bb; ++x) {
+                const double v = k < len ? val[(s0 + k) * bb + x] : 0.0;
+                const int64_t e = ((o0 + k) * bb + x) * 64 + l;
+                sval[e] = v;
+                if (sval32) sval32[e] = (float)v;
+            }
+        }
+    }
+}
+// one wave per row: storage row r holds row order[r], blocks contiguous
+__global__ void k_pack_rows(int64_t nr, int bb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ val, const int32_t *__restrict__ order,
+                            const int32_t *__restrict__ colmap, const int64_t *__restrict__ rptr,
+                            int32_t *__restrict__ rcol, double *__restrict__ rval, float *__restrict__ rval32) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nr; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = order[r];
+        const int64_t s0 = ptr[o], len = ptr[o + 1] - s0, d0 = rptr[r];
+        for (int64_t k = 0; k < len; ++k) {
+            rcol[d0 + k] = colmap[col[s0 + k]];
+            for (int x = 0; x < bb; ++x) {
+                const double v = val[(s0 + k) * bb + x];
+                rval[(d0 + k) * bb + x] = v;
+                if (rval32) rval32[(d0 + k) * bb + x] = (float)v;
+            }
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t n, int b = 256) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + b - 1) / b, 1 << 16));
+}
+inline unsigned wave_grid(int64_t rows) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, 1 << 17)); }
+
+int32_t read_flag(const DBuf<int32_t> &f, hipStream_t s) {
+    int32_t h = 0;
+    TE_CHECK_HIP(hipMemcpyAsync(&h, f.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// counts -> row pointer (host scan); returns the largest count
+int64_t counts_to_ptr(const DBuf<int32_t> &cnt, int64_t n, DBuf<int64_t> &ptr, int64_t &total, hipStream_t s) {
+    std::vector<int32_t> h;
+    download(h, cnt.p, (size_t)n, s);
+    std::vector<int64_t> p(n + 1, 0);
+    int64_t mx = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        p[i + 1] = p[i] + h[i];
+        mx = std::max<int64_t>(mx, h[i]);
+    }
+    total = p[n];
+    upload(ptr, p, s);
+    return mx;
+}
+
+template <bool AGG>
+void launch_sym(int tb, const DBsr &A, const int64_t *bptr, const int32_t *bcol, const int32_t *agg, int32_t *cnt,
+                const int64_t *cptr, int32_t *ccol, int32_t *flag, hipStream_t s) {
+    const dim3 g(wave_grid(A.nr)), b(64);
+#define TE_SYM(TBV)                                                                                                  \
+    case TBV:                                                                                                        \
+        hipLaunchKernelGGL((k_sym<TBV, AGG>), g, b, 0, s, A.nr, A.ptr, A.col, bptr, bcol, agg, cnt, cptr, ccol, flag); \
+        break;
+    switch (tb) {
+        TE_SYM(64)
+        TE_SYM(128)
+        TE_SYM(256)
+        TE_SYM(512)
+        TE_SYM(1024)
+        TE_SYM(2048)
+        TE_SYM(4096)
+        default: TE_REQUIRE(false, TE_EINVAL, "bad table size %d", tb);
+    }
+#undef TE_SYM
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+// smallest table with load factor <= 1/2 for rows of `cols` blocks
+int table_for(int64_t cols) {
+    int tb = 64;
+    while (tb < 2 * cols && tb < 4096) tb *= 2;
+    return tb;
+}
+
+// symbolic product into C's own row pointer and columns; returns the longest row
+template <bool AGG>
+int64_t symbolic(const DBsr &A, const int64_t *bptr, const int32_t *bcol, const int32_t *agg, int first_tb, DBsr &C,
+                 hipStream_t s) {
+    const int64_t n = A.nr;
+    DBuf<int32_t> cnt(std::max<int64_t>(n, 1)), flag(1);
+    int tb = first_tb;
+    for (;;) {
+        TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+        launch_sym<AGG>(tb, A, bptr, bcol, agg, cnt.p, nullptr, nullptr, flag.p, s);
+        if (read_flag(flag, s) == 0) break;
+        TE_REQUIRE(tb < 4096, TE_ENOMEM, "sparse product row with more than 4096 blocks");
+        tb = std::min(4096, tb * 4);
+    }
+    const int64_t mx = counts_to_ptr(cnt, n, C.ptr_own, C.nnzb, s);
+    C.col_own.alloc(std::max<int64_t>(C.nnzb, 1));
+    C.bind();
+    TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    launch_sym<AGG>(table_for(mx), A, bptr, bcol, agg, nullptr, C.ptr, C.col_own.p, flag.p, s);
+    TE_REQUIRE(read_flag(flag, s) == 0, TE_EHIP, "sparse product pattern pass disagrees with its count pass");
+    return mx;
+}
+
+template <int BR, int BK, int BC>
+void launch_num(int tb, const DBsr &A, const DBsr &B, DBsr &C, int32_t *flag, hipStream_t s) {
+    const dim3 g(wave_grid(A.nr)), b(64);
+#define TE_NUM(TBV)                                                                                              \
+    case TBV:                                                                                                    \
+        hipLaunchKernelGGL((k_num<BR, BK, BC, TBV>), g, b, 0, s, A.nr, A.ptr, A.col, A.val, B.ptr, B.col, B.val, \
+                           C.ptr, C.col, C.val_own.p, flag);                                                     \
+        break;
+    switch (tb) {
+        TE_NUM(64)
+        TE_NUM(128)
+        TE_NUM(256)
+        TE_NUM(512)
+        TE_NUM(1024)
+        TE_NUM(2048)
+        TE_NUM(4096)
+        default: TE_REQUIRE(false, TE_EINVAL, "bad table size %d", tb);
+    }
+#undef TE_NUM
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host entry points
+// ---------------------------------------------------------------------------
+void dev_strength(const DBsr &A, DBuf<double> &s, hipStream_t st) {
+    TE_REQUIRE(A.br == A.bc, TE_EINVAL, "strength of a non-square block matrix");
+    s.alloc(std::max<int64_t>(A.nnzb, 1));
+    DBuf<double> dn(std::max<int64_t>(A.nr, 1));
+    hipLaunchKernelGGL(k_fro, dim3(grid_for(A.nnzb)), dim3(256), 0, st, A.nnzb, A.br * A.bc, A.val, s.p);
+    hipLaunchKernelGGL(k_diag_fro, dim3(grid_for(A.nr)), dim3(256), 0, st, A.nr, A.ptr, A.col, s.p, dn.p);
+    hipLaunchKernelGGL(k_strength, dim3(grid_for(A.nr)), dim3(256), 0, st, A.nr, A.ptr, A.col, dn.p, s.p);
+    TE_CHECK_HIP(hipGetLastError());
+    TE_CHECK_HIP(hipStreamSynchronize(st));
+}
+
+void dev_diag(const DBsr &A, DBuf<double> &d, hipStream_t st) {
+    TE_REQUIRE(A.br == A.bc, TE_EINVAL, "diagonal of a non-square block matrix");
+    d.alloc((size_t)std::max<int64_t>(A.nr, 1) * A.br);
+    hipLaunchKernelGGL(k_diag_points, dim3(grid_for(A.nr)), dim3(256), 0, st, A.nr, A.br, A.ptr, A.col, A.val, d.p);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+void dev_smoothed_p(const DBsr &A, const DBuf<int32_t> &agg, int64_t nagg, const DBuf<double> &Q,
+                    const DBuf<double> &d, double omega, DBsr &P, hipStream_t s) {
+    TE_REQUIRE(A.br == 3 || A.br == 6, TE_EINVAL, "unsupported block size %d", A.br);
+    P.release();
+    P.br = A.br;
+    P.bc = 6;
+    P.nr = A.nr;
+    P.nc = nagg;
+    symbolic<true>(A, nullptr, nullptr, agg.p, 64, P, s);
+    P.val_own.alloc(std::max<int64_t>(P.nnzb * P.br * P.bc, 1));
+    P.bind();
+    DBuf<int32_t> flag(1);
+    TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    if (A.br == 3)
+        hipLaunchKernelGGL(k_p_numeric<3>, dim3(grid_for(A.nr)), dim3(256), 0, s, A.nr, A.ptr, A.col, A.val, agg.p,
+                           Q.p, d.p, omega, P.ptr, P.col, P.val_own.p, flag.p);
+    else
+        hipLaunchKernelGGL(k_p_numeric<6>, dim3(grid_for(A.nr)), dim3(256), 0, s, A.nr, A.ptr, A.col, A.val, agg.p,
+                           Q.p, d.p, omega, P.ptr, P.col, P.val_own.p, flag.p);
+    TE_CHECK_HIP(hipGetLastError());
+    TE_REQUIRE(read_flag(flag, s) == 0, TE_EHIP, "prolongator pattern misses a column");
+}
+
+void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s) {
+    TE_REQUIRE(A.bc == B.br && A.nc == B.nr, TE_EINVAL, "product shape mismatch");
+    C.release();
+    C.br = A.br;
+    C.bc = B.bc;
+    C.nr = A.nr;
+    C.nc = B.nc;
+    const int64_t mx = symbolic<false>(A, B.ptr, B.col, nullptr, C.br == 3 ? 128 : 512, C, s);
+    C.val_own.alloc(std::max<int64_t>(C.nnzb * C.br * C.bc, 1));
+    C.bind();
+    const int tb = table_for(mx);
+    TE_REQUIRE(2 * mx <= tb, TE_ENOMEM, "sparse product row with %lld blocks is too long", (long long)mx);
+    DBuf<int32_t> flag(1);
+    TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    const int key = A.br * 100 + A.bc * 10 + B.bc;
+    if (key == 336) launch_num<3, 3, 6>(tb, A, B, C, flag.p, s);
+    else if (key == 636) launch_num<6, 3, 6>(tb, A, B, C, flag.p, s);
+    else if (key == 666) launch_num<6, 6, 6>(tb, A, B, C, flag.p, s);
+    else TE_REQUIRE(false, TE_EINVAL, "unsupported product block shapes %dx%d * %dx%d", A.br, A.bc, B.br, B.bc);
+    TE_REQUIRE(read_flag(flag, s) == 0, TE_EHIP, "sparse product numeric pass found an inconsistent pattern");
+}
+
+void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s) {
+    T.release();
+    T.br = A.bc;
+    T.bc = A.br;
+    T.nr = A.nc;
+    T.nc = A.nr;
+    const int64_t nt = std::max<int64_t>(T.nr, 1);
+    DBuf<int32_t> cnt(nt), fill(nt), row(std::max<int64_t>(A.nnzb, 1));
+    TE_CHECK_HIP(hipMemsetAsync(cnt.p, 0, nt * sizeof(int32_t), s));
+    TE_CHECK_HIP(hipMemsetAsync(fill.p, 0, nt * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_t_count, dim3(grid_for(A.nnzb)), dim3(256), 0, s, A.nnzb, A.col, cnt.p);
+    TE_CHECK_HIP(hipGetLastError());
+    counts_to_ptr(cnt, T.nr, T.ptr_own, T.nnzb, s);
+    TE_REQUIRE(T.nnzb == A.nnzb, TE_EINVAL, "transpose: column index out of range");
+    DBuf<int64_t> src(std::max<int64_t>(A.nnzb, 1));
+    T.col_own.alloc(std::max<int64_t>(T.nnzb, 1));
+    T.val_own.alloc(std::max<int64_t>(T.nnzb * T.br * T.bc, 1));
+    T.bind();
+    hipLaunchKernelGGL(k_t_place, dim3(grid_for(A.nr)), dim3(256), 0, s, A.nr, A.ptr, A.col, T.ptr, fill.p, src.p,
+                       row.p);
+    hipLaunchKernelGGL(k_t_sort, dim3(grid_for(T.nr)), dim3(256), 0, s, T.nr, T.ptr, src.p);
+    if (A.br == 3 && A.bc == 6)
+        hipLaunchKernelGGL((k_t_fill<3, 6>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, src.p, row.p, A.val,
+                           T.col_own.p, T.val_own.p);
+    else if (A.br == 6 && A.bc == 6)
+        hipLaunchKernelGGL((k_t_fill<6, 6>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, src.p, row.p, A.val,
+                           T.col_own.p, T.val_own.p);
+    else
+        TE_REQUIRE(false, TE_EINVAL, "unsupported transpose block shape %dx%d", A.br, A.bc);
+    TE_CHECK_HIP(hipGetLastError());
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &row_order,
+              const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32, hipStream_t s,
+              int format) {
+    TE_REQUIRE((int64_t)hptr.size() == M.nr + 1 && (int64_t)row_order.size() == M.nr &&
+                   (int64_t)col_map.size() == M.nc && hptr[M.nr] == M.nnzb,
+               TE_EINVAL, "pack: inconsistent sizes");
+    const int bb = M.br * M.bc;
+    DBuf<int32_t> dorder, dmap;
+    upload(dorder, row_order, s);
+    upload(dmap, col_map, s);
+    S.format = format;
+    S.br = M.br;
+    S.bc = M.bc;
+    S.nrows = M.nr;
+    S.ncols = M.nc;
+    S.nnzb = M.nnzb;
+    if (format == FMT_ROWWAVE) {
+        S.nslices = 0;
+        S.padded = M.nnzb;
+        std::vector<int64_t> rptr(M.nr + 1, 0);
+        for (int64_t r = 0; r < M.nr; ++r) rptr[r + 1] = rptr[r] + (hptr[row_order[r] + 1] - hptr[row_order[r]]);
+        upload(S.rptr, rptr, s);
+        S.col.alloc(std::max<int64_t>(M.nnzb, 1));
+        S.val.alloc(std::max<int64_t>(M.nnzb * bb, 1));
+        if (fp32) S.val32.alloc(std::max<int64_t>(M.nnzb * bb, 1));
+        else S.val32.release();
+        hipLaunchKernelGGL(k_pack_rows, dim3(grid_for(M.nr)), dim3(256), 0, s, M.nr, bb, M.ptr, M.col, M.val, dorder.p,
+                           dmap.p, S.rptr.p, S.col.p, S.val.p, fp32 ? S.val32.p : nullptr);
+        S.slice_off.release();
+        S.rowlen.release();
+    } else {
+        S.rptr.release();
+        S.nslices = (M.nr + SELL_C - 1) / SELL_C;
+        std::vector<int32_t> off(S.nslices + 1, 0), rowlen(S.nslices * SELL_C, 0);
+        for (int64_t sl = 0; sl < S.nslices; ++sl) {
+            int64_t w = 0;
+            for (int l = 0; l < SELL_C; ++l) {
+                const int64_t r = sl * SELL_C + l;
+                if (r >= M.nr) break;
+                const int64_t len = hptr[row_order[r] + 1] - hptr[row_order[r]];
+                rowlen[r] = (int32_t)len;
+                w = std::max(w, len);
+            }
+            TE_REQUIRE((int64_t)off[sl] + w < INT32_MAX, TE_EINVAL, "matrix too large for the SELL offsets");
+            off[sl + 1] = off[sl] + (int32_t)w;
+        }
+        S.padded = (int64_t)off[S.nslices] * SELL_C;
+        upload(S.slice_off, off, s);
+        upload(S.rowlen, rowlen, s);
+        S.col.alloc(std::max<int64_t>(S.padded, 1));
+        S.val.alloc(std::max<int64_t>(S.padded * bb, 1));
+        if (fp32) S.val32.alloc(std::max<int64_t>(S.padded * bb, 1));
+        else S.val32.release();
+        hipLaunchKernelGGL(k_pack_sell, dim3(grid_for(S.nslices * 64)), dim3(256), 0, s, M.nr, bb, M.ptr, M.col,
+                           M.val, dorder.p, dmap.p, S.slice_off.p, S.nslices, S.col.p, S.val.p,
+                           fp32 ? S.val32.p : nullptr);
+    }
+    TE_CHECK_HIP(hipGetLastError());
+    if (out_map) {
+        std::vector<int32_t> rm(format == FMT_ROWWAVE ? M.nr : S.nslices * SELL_C, -1);
+        for (int64_t r = 0; r < M.nr; ++r) rm[r] = (*out_map)[row_order[r]];
+        upload(S.rowmap, rm, s);
+    } else {
+        S.rowmap.release();
+    }
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void dev_pattern_to_host(const DBsr &M, HBsr &H, hipStream_t s) {
+    H.br = M.br;
+    H.bc = M.bc;
+    H.nr = M.nr;
+    H.nc = M.nc;
+    download(H.ptr, M.ptr, (size_t)M.nr + 1, s);
+    download(H.col, M.col, (size_t)M.nnzb, s);
+    H.val.clear();
+}
+
+void dev_to_host(const DBsr &M, HBsr &H, hipStream_t s) {
+    dev_pattern_to_host(M, H, s);
+    download(H.val, M.val, (size_t)M.nnzb * M.br * M.bc, s);
+}
+
+}  // namespace te
