@@ -208,8 +208,8 @@ def main():
         import hashlib
         t = json.load(open(tj))
         csrc = os.path.join(ROOT, "paper_1804_10060_amd", "csrc")
-        digest = hashlib.sha256(open(os.path.join(csrc, "te_kernels.hip"), "rb").read() +
-                                open(os.path.join(csrc, "te_internal.h"), "rb").read()).hexdigest()
+        digest = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                         for f in ("te_dev.h", "te_kernels.hip", "te_internal.h"))).hexdigest()
         if digest == t.get("kernel_source_sha256") and dom in t.get("per_launch", {}):
             roofline["traffic"] = t["per_launch"][dom]["traffic_bytes"]
             roofline["traffic_source"] = "profiles/disc_p2_12M_fp64_hbm_counters.md"

@@ -163,7 +163,9 @@ class AMG:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        # at interpreter exit the module globals may already be gone; the
+        # process end releases the device memory then
+        if h is not None and h.value and load is not None:
             load().amg_destroy(h)
             self._h = C.c_void_p(0)
 
@@ -297,7 +299,9 @@ class MPNN:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        # at interpreter exit the module globals may already be gone; the
+        # process end releases the device memory then
+        if h is not None and h.value and load is not None:
             load().mpnn_destroy(h)
             self._h = C.c_void_p(0)
 

@@ -86,50 +86,59 @@ static const double kRankRtol = 1e-10;
 static int64_t greedy_aggregate(const HBsr &A, const Strength &S, double theta, std::vector<int32_t> &agg) {
     const int64_t n = A.nr;
     agg.assign(n, -1);
-    std::vector<uint8_t> has_strong(n, 0);
-    auto strong = [&](int64_t i, int64_t k) { return A.col[k] != i && S.s[k] >= theta; };
-    for (int64_t i = 0; i < n; ++i)
-        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-            if (strong(i, k)) {
-                has_strong[i] = 1;
-                break;
-            }
+    // strong[k]: off-diagonal block k at or above the threshold
+    std::vector<uint8_t> strong(A.col.size(), 0), has_strong(n, 0);
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+                if (A.col[k] != i && S.s[k] >= theta) {
+                    strong[k] = 1;
+                    has_strong[i] = 1;
+                }
+    });
     int64_t na = 0;
-    // phase 1: a free node whose strong neighbours are all free roots a new aggregate
+    // phase 1 (sequential by definition): a free node whose strong neighbours
+    // are all free roots a new aggregate
     for (int64_t i = 0; i < n; ++i) {
         if (!has_strong[i] || agg[i] >= 0) continue;
         bool free = true;
         for (int64_t k = A.ptr[i]; k < A.ptr[i + 1] && free; ++k)
-            if (strong(i, k) && agg[A.col[k]] >= 0) free = false;
+            if (strong[k] && agg[A.col[k]] >= 0) free = false;
         if (!free) continue;
         agg[i] = (int32_t)na;
         for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-            if (strong(i, k)) agg[A.col[k]] = (int32_t)na;
+            if (strong[k]) agg[A.col[k]] = (int32_t)na;
         ++na;
     }
-    // phase 2: remaining nodes join the phase-1 aggregate of their strongest
-    // strong neighbour; near-equal strengths go to the smaller aggregate id
-    std::vector<int32_t> snap(agg);
-    for (int64_t i = 0; i < n; ++i) {
-        if (!has_strong[i] || snap[i] >= 0) continue;
-        double bs = -1.0;
-        int32_t ba = -1;
-        for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-            if (!strong(i, k)) continue;
-            const int32_t a = snap[A.col[k]];
-            if (a < 0) continue;
-            const double sv = S.s[k];
-            if (ba < 0 || sv > bs * (1.0 + kTieRtol)) {
-                bs = sv;
-                ba = a;
-            } else if (sv >= bs * (1.0 - kTieRtol) && a < ba) {
-                bs = sv;
-                ba = a;
+    // phase 2 (independent per node): remaining nodes join the phase-1
+    // aggregate of their strongest strong neighbour; near-equal strengths go
+    // to the smaller aggregate id
+    const std::vector<int32_t> snap(agg);
+    std::atomic<int64_t> orphan{-1};
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i) {
+            if (!has_strong[i] || snap[i] >= 0) continue;
+            double bs = -1.0;
+            int32_t ba = -1;
+            for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+                if (!strong[k]) continue;
+                const int32_t a = snap[A.col[k]];
+                if (a < 0) continue;
+                const double sv = S.s[k];
+                if (ba < 0 || sv > bs * (1.0 + kTieRtol)) {
+                    bs = sv;
+                    ba = a;
+                } else if (sv >= bs * (1.0 - kTieRtol) && a < ba) {
+                    bs = sv;
+                    ba = a;
+                }
             }
+            if (ba < 0) orphan.store(i);
+            agg[i] = ba;
         }
-        TE_REQUIRE(ba >= 0, TE_EINVAL, "aggregation: node %lld has no aggregated strong neighbour", (long long)i);
-        agg[i] = ba;
-    }
+    });
+    TE_REQUIRE(orphan.load() < 0, TE_EINVAL, "aggregation: node %lld has no aggregated strong neighbour",
+               (long long)orphan.load());
     return na;
 }
 
@@ -215,7 +224,21 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
     std::vector<std::vector<int32_t>> mem(na);
     for (int64_t i = 0; i < n; ++i)
         if (agg[i] >= 0) mem[agg[i]].push_back((int32_t)i);
-    std::vector<double> M, R((size_t)k * k);
+    // full rank of every aggregate's block of B, checked in parallel; an
+    // aggregate that receives merged nodes is checked again when visited
+    auto full_rank = [&](const std::vector<int32_t> &nodes, std::vector<double> &M) {
+        std::vector<double> R((size_t)k * k);
+        gather_B(nodes, B, bs, k, M);
+        const int m = (int)nodes.size() * bs;
+        return m >= k && qr_thin(m, k, M, R.data()) && rank_ok(R.data(), k);
+    };
+    std::vector<uint8_t> ok(na, 0), current(na, 1);
+    parallel_for(na, [&](int64_t lo, int64_t hi, int) {
+        std::vector<double> Mt;
+        for (int64_t x = lo; x < hi; ++x)
+            if (!mem[x].empty()) ok[x] = full_rank(mem[x], Mt) ? 1 : 0;
+    });
+    std::vector<double> M;
     int64_t a = 0;
     while (a < na) {
         auto &nodes = mem[a];
@@ -223,9 +246,7 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
             ++a;
             continue;
         }
-        gather_B(nodes, B, bs, k, M);
-        const int m = (int)nodes.size() * bs;
-        if (m >= k && qr_thin(m, k, M, R.data()) && rank_ok(R.data(), k)) {
+        if (current[a] ? ok[a] != 0 : full_rank(nodes, M)) {
             ++a;
             continue;
         }
@@ -255,6 +276,7 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
                 bsv = sc.second;
             }
         for (int32_t i : nodes) agg[i] = best;
+        current[best] = 0;
         auto &dst = mem[best];
         dst.insert(dst.end(), nodes.begin(), nodes.end());
         std::sort(dst.begin(), dst.end());
@@ -293,16 +315,23 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
 // ---------------------------------------------------------------------------
 // SELL packing
 // ---------------------------------------------------------------------------
+// Rows sorted by descending length inside windows of `window` rows (ties in
+// natural order), so the 64 rows of a slice have nearly equal lengths while
+// x stays local to the window.
 std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_t window) {
     const int64_t n = (int64_t)ptr.size() - 1;
     std::vector<int32_t> ord(n);
     for (int64_t i = 0; i < n; ++i) ord[i] = (int32_t)i;
-    for (int64_t w0 = 0; w0 < n; w0 += window) {
-        int64_t w1 = std::min(n, w0 + window);
-        std::stable_sort(ord.begin() + w0, ord.begin() + w1, [&](int32_t a, int32_t b) {
-            return (ptr[a + 1] - ptr[a]) > (ptr[b + 1] - ptr[b]);
-        });
-    }
+    const int64_t nw = (n + window - 1) / window;
+    parallel_for(nw, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t wi = lo; wi < hi; ++wi) {
+            const int64_t w0 = wi * window, w1 = std::min(n, w0 + window);
+            std::sort(ord.begin() + w0, ord.begin() + w1, [&](int32_t a, int32_t b) {
+                const int64_t la = ptr[a + 1] - ptr[a], lb = ptr[b + 1] - ptr[b];
+                return la != lb ? la > lb : a < b;
+            });
+        }
+    });
     return ord;
 }
 
@@ -626,6 +655,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
         note("pack operator", l, L.n, L.Ah.nnzb());
         DBuf<double> dnat;
         finish_level(L, *cur, o, dnat, s);
+        note("operator packed", l, L.n, L.Ah.nnzb());
         if (pending) {
             Level &U = h->L[l - 1];
             const auto pord = window_sorted_order(Pn_ptr, 4096);
@@ -642,6 +672,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
         if (!coarsest) {
             L.lam = lanczos_estimate(L, o.lanczos_steps, 0x5EEDull + (uint64_t)l, s);
             set_cheb(L, o);
+            note("eigenvalue estimate", l, L.n, 0);
             const double theta = o.theta0 * std::ldexp(1.0, -l);
             Strength S;
             {
@@ -649,6 +680,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                 dev_strength(*cur, ds, s);
                 download(S.s, ds.p, (size_t)cur->nnzb, s);
             }
+            note("strength", l, L.n, cur->nnzb);
             std::vector<int32_t> agg;
             int64_t na;
             if (agg_given && l < n_given) {
@@ -667,6 +699,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                 note("aggregated", l, na, 0);
                 Tentative T = tentative(L.Ah, S, agg, na, B, L.bs, k);
                 S = Strength();
+                note("tentative prolongator", l, T.nc, 0);
                 DBuf<int32_t> dagg;
                 DBuf<double> dQ;
                 upload(dagg, T.agg, s);

@@ -72,9 +72,8 @@ inline SellView<VT> view(const Sell &S, const VT *val) {
 // consumes the BR accumulated entries and may add to `red` (block-reduced
 // into partials[logical block] when Epi::kReduce).
 template <int BR, int BC, typename VT, typename XT, typename AT, bool NT>
-__device__ __forceinline__ void sell1_entry(const int32_t *__restrict__ cp, const VT *__restrict__ vp, int k,
-                                            const XT *__restrict__ x, AT *acc) {
-    const int64_t c = cp[(int64_t)k * WAVE];
+__device__ __forceinline__ void sell1_entry_c(int64_t c, const VT *__restrict__ vp, int k, const XT *__restrict__ x,
+                                              AT *acc) {
     AT xv[BC];
 #pragma unroll
     for (int j = 0; j < BC; ++j) xv[j] = AT(x[c * BC + j]);
@@ -83,6 +82,12 @@ __device__ __forceinline__ void sell1_entry(const int32_t *__restrict__ cp, cons
     for (int i = 0; i < BR; ++i)
 #pragma unroll
         for (int j = 0; j < BC; ++j) acc[i] += AT(ld_val<NT>(&vk[(i * BC + j) * WAVE])) * xv[j];
+}
+
+template <int BR, int BC, typename VT, typename XT, typename AT, bool NT>
+__device__ __forceinline__ void sell1_entry(const int32_t *__restrict__ cp, const VT *__restrict__ vp, int k,
+                                            const XT *__restrict__ x, AT *acc) {
+    sell1_entry_c<BR, BC, VT, XT, AT, NT>(cp[(int64_t)k * WAVE], vp, k, x, acc);
 }
 
 // One slice, lane = row.  Rows of a slice are sorted by descending length,
@@ -118,8 +123,9 @@ __device__ __forceinline__ void sell1_body(const SellView<VT> &A, const XT *__re
 // One wave per stored row (format 1).  Lane = (block slot, row of the block):
 // with NB = 64 / BR slots, a wave consumes NB consecutive blocks per step,
 // i.e. one contiguous run of NB*BR*BC values, each lane reading the BC
-// contiguous values of one block row.  The BR row sums are then combined in
-// LDS in a fixed order and lane 0 runs the epilogue.
+// contiguous values of one block row.  The partial sums go through the
+// wave's 64-entry LDS buffer; lane q < BR adds the NB slots of row q in slot
+// order and runs the epilogue for that entry.
 template <typename VT>
 struct RowView {
     const int64_t *__restrict__ rptr;
@@ -134,33 +140,42 @@ inline RowView<VT> rview(const Sell &S, const VT *val) {
     return RowView<VT>{S.rptr.p, S.col.p, val, S.rowmap.p, S.nrows};
 }
 
+// LDS written by some lanes of a wave and read by others: order the two
+// inside the wave (no workgroup barrier; waves of a group are independent)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT = false>
 __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__restrict__ x, const Epi &epi, int64_t row,
-                                          int lane, double &red) {
+                                          int lane, double &red, AT *__restrict__ wbuf) {
     constexpr int NB = WAVE / BR;
     const int slot = lane / BR, i = lane % BR;
     AT acc = AT(0);
     if (slot < NB) {
         const int64_t hi = A.rptr[row + 1];
-        for (int64_t k = A.rptr[row] + slot; k < hi; k += NB) {
-            const int64_t c = A.col[k];
+        int64_t k = A.rptr[row] + slot;
+        int64_t c = k < hi ? A.col[k] : 0;
+        for (; k < hi; k += NB) {
+            const int64_t cn = k + NB < hi ? A.col[k + NB] : 0;  // next step's column, one step ahead
             const VT *v = A.val + k * (BR * BC) + i * BC;
 #pragma unroll
             for (int j = 0; j < BC; ++j) acc += AT(ld_val<NT>(&v[j])) * AT(x[c * BC + j]);
+            c = cn;
         }
     }
-    // row sums: every lane takes part in the cross-lane reads, lane 0 keeps them
-    AT r[BR];
+    wbuf[lane] = acc;
+    wave_lds_sync();
+    if (lane < BR) {
+        AT t[1] = {AT(0)};
 #pragma unroll
-    for (int q = 0; q < BR; ++q) {
-        AT t = AT(0);
-        for (int sl = 0; sl < NB; ++sl) t += __shfl(acc, sl * BR + q, WAVE);
-        r[q] = t;
-    }
-    if (lane == 0) {
+        for (int sl = 0; sl < NB; ++sl) t[0] += wbuf[sl * BR + lane];
         const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
-        epi.template apply<BR>(out, r, red);
+        epi.template apply<1>(out * BR + lane, t, red);
     }
+    wave_lds_sync();  // the next row's writes after these reads
 }
 
 // ---------------------------------------------------------------------------

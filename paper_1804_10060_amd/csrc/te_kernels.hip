@@ -93,13 +93,15 @@ template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool
 __global__ void __launch_bounds__(512) k_roww(RowView<VT> A, const XT *__restrict__ x, Epi epi,
                                               double *__restrict__ partials, int spw, int remap) {
     __shared__ double rlds[16];
+    __shared__ AT wb[512];
     const int64_t nb = gridDim.x;
     const int64_t lb = remap ? xcd_logical_block(blockIdx.x, nb) : (int64_t)blockIdx.x;
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t w0 = (lb * (blockDim.x / WAVE) + threadIdx.x / WAVE) * spw;
+    AT *wbuf = wb + (threadIdx.x / WAVE) * WAVE;
     double red = 0.0;
     for (int u = 0; u < spw; ++u)
-        if (w0 + u < A.nrows) roww_body<BR, BC, VT, XT, AT, Epi, NT>(A, x, epi, w0 + u, lane, red);
+        if (w0 + u < A.nrows) roww_body<BR, BC, VT, XT, AT, Epi, NT>(A, x, epi, w0 + u, lane, red, wbuf);
     if (Epi::kReduce) {
         double t = block_sum(red, rlds);
         if (threadIdx.x == 0) partials[lb] = t;

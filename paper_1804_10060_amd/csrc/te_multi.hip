@@ -269,7 +269,6 @@ void build_phases(MultiState &M, hipStream_t s) {
             // post-smoothing: same operators, rin = r after the init, never x = 0
             std::vector<GItem<double, EpiChebStep<double, true, false>>> q_l;
             std::vector<GItem<double, EpiChebStep<double, false, false>>> q_n;
-            int idx = 0;
             for (int m = 0; m < M.n; ++m) {
                 amg_handle *h = M.H[m];
                 if (l + 1 >= (int)h->L.size()) continue;
@@ -280,7 +279,6 @@ void build_phases(MultiState &M, hipStream_t s) {
                 double *dn = (k % 2 == 0) ? W.d2.p : W.d.p;
                 if (last) q_l.push_back(gitem(L.A, dc, EpiChebStep<double, true, false>{W.r.p, dc, L.dinv.p, W.r.p, dn, x, L.c1[k], L.c2[k]}, m));
                 else q_n.push_back(gitem(L.A, dc, EpiChebStep<double, false, false>{W.r.p, dc, L.dinv.p, W.r.p, dn, x, L.c1[k], L.c2[k]}, m));
-                ++idx;
             }
             Phase &Pq = M.post_steps[l][k];
             Pq.kind = 0; Pq.br = bs; Pq.bc = bs;

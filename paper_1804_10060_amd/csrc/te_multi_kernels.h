@@ -25,6 +25,7 @@ __global__ void __launch_bounds__(BLK) k_group(const GItem<T, Epi> *__restrict__
                                                const int64_t *__restrict__ tile0, int nitems,
                                                const int32_t *__restrict__ active, double *__restrict__ partials) {
     __shared__ double lds[WPB];
+    __shared__ T wb[BLK];
     const int64_t ntiles = tile0[nitems];
     const int64_t nb = gridDim.x, lb = xcd_logical_block(blockIdx.x, nb);
     const int64_t t_lo = ntiles * lb / nb, t_hi = ntiles * (lb + 1) / nb;
@@ -48,7 +49,9 @@ __global__ void __launch_bounds__(BLK) k_group(const GItem<T, Epi> *__restrict__
             if (G.fmt == FMT_SELL) {
                 if (unit < G.sv.nslices) sell1_body<BR, BC, T, T, T, Epi>(G.sv, G.x, G.epi, unit, lane, red);
             } else {
-                if (unit < G.rv.nrows) roww_body<BR, BC, T, T, T, Epi>(G.rv, G.x, G.epi, unit, lane, red);
+                if (unit < G.rv.nrows)
+                    roww_body<BR, BC, T, T, T, Epi>(G.rv, G.x, G.epi, unit, lane, red,
+                                                    wb + (threadIdx.x / WAVE) * WAVE);
             }
         }
         if (Epi::kReduce) {

@@ -79,6 +79,21 @@ def test_invalid_mesh_rejected():
                     dev(np.full(m.n_nodes, 301.0), torch.float64))
 
 
+def _load_magnitudes(m, prob, deg, rows):
+    """Per sampled row: sum over the touching cells of |element load entry|
+    (oracle element loads), the scale of the rounding of any summation order."""
+    touch = np.isin(m.cells, rows).any(axis=1)
+    sub = m.cells[touch].astype(np.int64)
+    lam, mu = fem.lame(prob.E, prob.nu)
+    vol, G = fem.cell_geometry(m.coords, sub)
+    be = fem.element_load(vol, G, prob.T[sub] - prob.T_ref, None, lam, mu, prob.alpha, deg)
+    out = {}
+    for r in rows.tolist():
+        cs, as_ = np.nonzero(sub == r)
+        out[r] = np.abs(be[cs, as_]).sum(axis=0)
+    return out
+
+
 @pytest.mark.timeout(900)
 def test_full_size_disc_p2_sampled_rows():
     """The 12,043,200-DOF disc at full size, assembled as the benchmark does:
@@ -95,6 +110,7 @@ def test_full_size_disc_p2_sampled_rows():
     rows = np.unique(np.concatenate([rng.integers(0, m.n_nodes, 24), [0, 1, 12, 13, 25, 26, m.n_nodes - 1]]))
     rp = A.row_ptr.cpu().numpy()
     ref = fem.assemble_rows(m.coords, m.cells, deg, prob.E, prob.nu, prob.alpha, prob.T_ref, prob.T, rows)
+    mag = _load_magnitudes(m, prob, deg, rows)
     mask = prob.mask.astype(bool)
     for r in rows.tolist():
         cols_o, blocks_o, b_o = ref[r]
@@ -112,4 +128,8 @@ def test_full_size_disc_p2_sampled_rows():
         b_o = np.where(mask[r], 0.0, b_o)
         scale = np.abs(blocks_o).max()
         assert np.abs(blk_g - blocks_o).max() <= TOL * scale
-        assert np.abs(b[3 * r:3 * r + 3].cpu().numpy() - b_o).max() <= TOL * max(np.abs(b_o).max(), 1.0)
+        # the thermal load of an interior node is a sum of large element terms
+        # that nearly cancel (for uniform dT it is exactly zero), so the bar is
+        # relative to the sum of the terms' magnitudes, not to the result
+        bound = np.where(mask[r], 0.0, TOL * mag[r]) + 1e-300
+        assert np.all(np.abs(b[3 * r:3 * r + 3].cpu().numpy() - b_o) <= bound)
