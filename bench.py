@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configurations")
+    ap.add_argument("--coarse-sym", type=int, default=0, choices=(0, 1),
+                    help="store the coarse operators by their upper triangle (amg_options.coarse_sym)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the build targets a single MI355X); --gpus {args.gpus} is not "
@@ -141,7 +143,7 @@ def main():
     log(f"assembly {t_asm * 1e3:.1f} ms, nnzb {A.nnzb}")
     log("AMG setup")
     ts = time.perf_counter()
-    h = te.AMG(A, coords, mask)
+    h = te.AMG(A, coords, mask, coarse_sym=args.coarse_sym)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - ts
     info = h.info()

@@ -492,7 +492,8 @@ static void finish_level(Level &L, const DBsr &D, const amg_options &o, DBuf<dou
     L.perm_h = window_sorted_order(L.Ah.ptr, 4096);
     L.iperm_h.assign(L.n, 0);
     for (int64_t i = 0; i < L.n; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
-    dev_pack(L.A, D, L.Ah.ptr, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.bs));
+    dev_pack(L.A, D, L.Ah.ptr, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.bs),
+             (o.coarse_sym && L.bs == 6) ? &L.Ah.col : nullptr);
     upload(L.perm, L.perm_h, s);
     dev_diag(D, dnat, s);
     std::vector<double> dh;
@@ -781,7 +782,32 @@ static void unpack_values(const Level &L, std::vector<double> &val) {
     std::vector<double> sv;
     download(sv, S.val.p, S.val.n, s);
     val.assign((size_t)L.Ah.nnzb() * bb, 0.0);
-    if (S.format == FMT_ROWWAVE) {
+    if (S.format == FMT_ROWWAVE && S.sym()) {
+        // blocks on/above the diagonal in the row's natural order, the others
+        // as the transposes of their mirrors, in the same order
+        std::vector<int64_t> rptr, lptr;
+        std::vector<int32_t> lidx;
+        download(rptr, S.rptr.p, (size_t)S.nrows + 1, s);
+        download(lptr, S.lptr.p, (size_t)S.nrows + 1, s);
+        download(lidx, S.lidx.p, (size_t)lptr[S.nrows], s);
+        const int b = S.br;
+        for (int64_t r = 0; r < S.nrows; ++r) {
+            const int64_t o = L.perm_h[r];
+            int64_t u = rptr[r], l = lptr[r];
+            for (int64_t k = L.Ah.ptr[o]; k < L.Ah.ptr[o + 1]; ++k) {
+                double *dst = &val[(size_t)k * bb];
+                if (L.iperm_h[L.Ah.col[k]] >= r) {
+                    std::copy(&sv[(size_t)u * bb], &sv[(size_t)(u + 1) * bb], dst);
+                    ++u;
+                } else {
+                    const double *m = &sv[(size_t)lidx[l] * bb];
+                    for (int p = 0; p < b; ++p)
+                        for (int q = 0; q < b; ++q) dst[p * b + q] = m[q * b + p];
+                    ++l;
+                }
+            }
+        }
+    } else if (S.format == FMT_ROWWAVE) {
         std::vector<int64_t> rptr;
         download(rptr, S.rptr.p, (size_t)S.nrows + 1, s);
         for (int64_t r = 0; r < S.nrows; ++r) {
@@ -822,6 +848,7 @@ extern "C" void amg_options_default(amg_options *o) {
     o->build_fp32 = 1;
     o->host_threads = 0;
     o->max_nrhs = 1;
+    o->coarse_sym = 0;
 }
 
 extern "C" int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,

@@ -133,11 +133,14 @@ struct RowView {
     const VT *__restrict__ val;
     const int32_t *__restrict__ rowmap;
     int64_t nrows;
+    const int64_t *__restrict__ lptr;  // symmetric storage: blocks below the diagonal (else null)
+    const int32_t *__restrict__ lcol;
+    const int32_t *__restrict__ lidx;
 };
 
 template <typename VT>
 inline RowView<VT> rview(const Sell &S, const VT *val) {
-    return RowView<VT>{S.rptr.p, S.col.p, val, S.rowmap.p, S.nrows};
+    return RowView<VT>{S.rptr.p, S.col.p, val, S.rowmap.p, S.nrows, S.lptr.p, S.lcol.p, S.lidx.p};
 }
 
 // LDS written by some lanes of a wave and read by others: order the two
@@ -164,6 +167,18 @@ __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__rest
 #pragma unroll
             for (int j = 0; j < BC; ++j) acc += AT(ld_val<NT>(&v[j])) * AT(x[c * BC + j]);
             c = cn;
+        }
+        if constexpr (BR == BC) {
+            if (A.lptr) {
+                // row i of a block below the diagonal = column i of its stored mirror
+                const int64_t lhi = A.lptr[row + 1];
+                for (int64_t q = A.lptr[row] + slot; q < lhi; q += NB) {
+                    const int64_t cl = A.lcol[q];
+                    const VT *v = A.val + (int64_t)A.lidx[q] * (BR * BC) + i;
+#pragma unroll
+                    for (int j = 0; j < BC; ++j) acc += AT(v[j * BC]) * AT(x[cl * BC + j]);
+                }
+            }
         }
     }
     wbuf[lane] = acc;

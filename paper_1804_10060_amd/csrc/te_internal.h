@@ -149,9 +149,17 @@ struct Sell {
     DBuf<float> val32;          // optional float32 copy
     DBuf<int32_t> rowmap;       // [nslices*64] output row of each lane, -1 = none; empty = identity
     DBuf<int64_t> rptr;         // format 1: [nrows+1] block offset of each stored row
+    // Format 1, symmetric operator: rptr/col/val hold only the blocks on or
+    // above the diagonal (storage numbering); the blocks below it are read
+    // transposed from their mirror: row r's lower blocks are
+    // lptr[r]..lptr[r+1], column lcol[k], mirror block lidx[k] of val.
+    DBuf<int64_t> lptr;
+    DBuf<int32_t> lcol;
+    DBuf<int32_t> lidx;
+    bool sym() const { return lptr.p != nullptr; }
     size_t bytes() const {
         return slice_off.bytes() + col.bytes() + rowlen.bytes() + val.bytes() + val32.bytes() + rowmap.bytes() +
-               rptr.bytes();
+               rptr.bytes() + lptr.bytes() + lcol.bytes() + lidx.bytes();
     }
 };
 

@@ -134,6 +134,22 @@ __global__ void __launch_bounds__(BLK) k_rowwm(RowView<VT> A, const XT *__restri
 #pragma unroll
                 for (int j = 0; j < BC; ++j) acc[i] += AT(v[i * BC + j]) * xv[j];
         }
+        if constexpr (BR == BC) {
+            if (A.lptr) {
+                const int64_t lhi = A.lptr[row + 1];
+                for (int64_t q = A.lptr[row]; q < lhi; ++q) {
+                    const int64_t c = A.lcol[q];
+                    const VT *v = A.val + (int64_t)A.lidx[q] * (BR * BC);
+                    AT xv[BC];
+#pragma unroll
+                    for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
+#pragma unroll
+                    for (int i = 0; i < BR; ++i)
+#pragma unroll
+                        for (int j = 0; j < BC; ++j) acc[i] += AT(v[j * BC + i]) * xv[j];
+                }
+            }
+        }
         const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
         epi.template apply_m<BR>(out, lane, nrhs, acc, red);
     }

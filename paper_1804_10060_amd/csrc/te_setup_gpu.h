@@ -58,9 +58,12 @@ void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s);
 //   col_map[c]   = column index stored for column c of M
 //   out_map      = if non-null, position i writes output row (*out_map)[row_order[i]];
 //                  otherwise position i writes output row i
+//   sym_cols     = if non-null (the host columns of M), a square M in the
+//                  one-wave-per-row format keeps only its blocks on and above
+//                  the diagonal when its pattern is symmetric
 void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &row_order,
               const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32, hipStream_t s,
-              int format);
+              int format, const std::vector<int32_t> *sym_cols = nullptr);
 
 // Host copies of the pattern or of the whole matrix.
 void dev_pattern_to_host(const DBsr &M, HBsr &H, hipStream_t s);

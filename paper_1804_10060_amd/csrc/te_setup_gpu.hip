@@ -15,7 +15,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
+#include "te_amg.h"
 #include "te_setup_gpu.h"
 
 namespace te {
@@ -351,6 +353,17 @@ __global__ void k_pack_rows(int64_t nr, int bb, const int64_t *__restrict__ ptr,
     }
 }
 
+// symmetric storage: upper slot u takes block src[u] of the natural matrix
+__global__ void k_pack_upper(int64_t nup, int bb, const int64_t *__restrict__ src, const double *__restrict__ val,
+                             double *__restrict__ rval, float *__restrict__ rval32) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nup * bb; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = t / bb, x = t % bb;
+        const double v = val[src[u] * bb + x];
+        rval[t] = v;
+        if (rval32) rval32[t] = (float)v;
+    }
+}
+
 inline unsigned grid_for(int64_t n, int b = 256) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + b - 1) / b, 1 << 16));
 }
@@ -553,9 +566,116 @@ void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s) {
     TE_CHECK_HIP(hipStreamSynchronize(s));
 }
 
+// Symmetric one-wave-per-row layout of a square M (storage row r holds row
+// row_order[r], storage column cs = col_map[c]): blocks with cs >= r stay,
+// each block with cs < r becomes a reference to its mirror.  Returns false
+// (and leaves S alone) when the pattern is not symmetric.
+static bool pack_rows_sym(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &hcol,
+                          const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map, bool fp32,
+                          hipStream_t s) {
+    const int64_t n = M.nr;
+    if (M.nr != M.nc || M.br != M.bc || (int64_t)hcol.size() != M.nnzb) return false;
+    for (int64_t r = 0; r < n; ++r)
+        if (col_map[row_order[r]] != r) return false;  // rows and columns in the same numbering
+    std::vector<int64_t> ucnt(n), lcnt(n);
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t r = lo; r < hi; ++r) {
+            const int64_t o = row_order[r];
+            int64_t u = 0;
+            for (int64_t k = hptr[o]; k < hptr[o + 1]; ++k) u += col_map[hcol[k]] >= r ? 1 : 0;
+            ucnt[r] = u;
+            lcnt[r] = hptr[o + 1] - hptr[o] - u;
+        }
+    });
+    std::vector<int64_t> rptr(n + 1, 0), lptr(n + 1, 0);
+    for (int64_t r = 0; r < n; ++r) {
+        rptr[r + 1] = rptr[r] + ucnt[r];
+        lptr[r + 1] = lptr[r] + lcnt[r];
+    }
+    const int64_t nup = rptr[n], nlow = lptr[n];
+    if (nup >= INT32_MAX) return false;
+    std::vector<int64_t> upos(M.nnzb, -1), usrc(nup);
+    std::vector<int32_t> ucol(nup), lcol(nlow), lidx(nlow);
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t r = lo; r < hi; ++r) {
+            const int64_t o = row_order[r];
+            int64_t u = rptr[r];
+            for (int64_t k = hptr[o]; k < hptr[o + 1]; ++k) {
+                const int32_t cs = col_map[hcol[k]];
+                if (cs >= r) {
+                    upos[k] = u;
+                    usrc[u] = k;
+                    ucol[u] = cs;
+                    ++u;
+                }
+            }
+        }
+    });
+    std::atomic<bool> bad{false};
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t r = lo; r < hi; ++r) {
+            const int64_t o = row_order[r];
+            int64_t l = lptr[r];
+            for (int64_t k = hptr[o]; k < hptr[o + 1]; ++k) {
+                const int32_t cs = col_map[hcol[k]];
+                if (cs >= r) continue;
+                // the mirror block (row hcol[k], column o) in its sorted row
+                const int64_t j = hcol[k];
+                const auto b0 = hcol.begin() + hptr[j], b1 = hcol.begin() + hptr[j + 1];
+                const auto it = std::lower_bound(b0, b1, (int32_t)o);
+                if (it == b1 || *it != (int32_t)o || upos[it - hcol.begin()] < 0) {
+                    bad = true;
+                    return;
+                }
+                lcol[l] = cs;
+                lidx[l] = (int32_t)upos[it - hcol.begin()];
+                ++l;
+            }
+        }
+    });
+    if (bad) return false;
+    const int bb = M.br * M.bc;
+    S.format = FMT_ROWWAVE;
+    S.br = M.br;
+    S.bc = M.bc;
+    S.nrows = n;
+    S.ncols = n;
+    S.nnzb = nup;
+    S.nslices = 0;
+    S.padded = nup;
+    upload(S.rptr, rptr, s);
+    upload(S.col, ucol, s);
+    upload(S.lptr, lptr, s);
+    upload(S.lcol, lcol, s);
+    upload(S.lidx, lidx, s);
+    if (nlow == 0) {  // keep the symmetric marker valid for an operator without lower blocks
+        S.lcol.alloc(1);
+        S.lidx.alloc(1);
+    }
+    DBuf<int64_t> dsrc;
+    upload(dsrc, usrc, s);
+    S.val.alloc(std::max<int64_t>(nup * bb, 1));
+    if (fp32) S.val32.alloc(std::max<int64_t>(nup * bb, 1));
+    else S.val32.release();
+    hipLaunchKernelGGL(k_pack_upper, dim3(grid_for(nup * bb)), dim3(256), 0, s, nup, bb, dsrc.p, M.val, S.val.p,
+                       fp32 ? S.val32.p : nullptr);
+    TE_CHECK_HIP(hipGetLastError());
+    S.slice_off.release();
+    S.rowlen.release();
+    S.rowmap.release();
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    return true;
+}
+
 void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &row_order,
               const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32, hipStream_t s,
-              int format) {
+              int format, const std::vector<int32_t> *sym_cols) {
+    S.lptr.release();
+    S.lcol.release();
+    S.lidx.release();
+    if (sym_cols && format == FMT_ROWWAVE && !out_map &&
+        pack_rows_sym(S, M, hptr, *sym_cols, row_order, col_map, fp32, s))
+        return;
     TE_REQUIRE((int64_t)hptr.size() == M.nr + 1 && (int64_t)row_order.size() == M.nr &&
                    (int64_t)col_map.size() == M.nc && hptr[M.nr] == M.nnzb,
                TE_EINVAL, "pack: inconsistent sizes");

@@ -24,8 +24,9 @@ std::string key_of(const Sell &A, const char *dtype) {
     const double per_row = A.nrows ? (double)A.nnzb / (double)A.nrows : 0.0;
     const int rbucket = A.nrows > 0 ? (int)std::floor(std::log2((double)A.nrows)) : 0;
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%s-%dx%d-%s-rows2^%d-bpr%d", A.format == FMT_SELL ? "sell" : "roww", A.br, A.bc,
-                  dtype, rbucket, (int)std::lround(per_row));
+    std::snprintf(buf, sizeof buf, "%s-%dx%d-%s-rows2^%d-bpr%d",
+                  A.format == FMT_SELL ? "sell" : (A.sym() ? "rsym" : "roww"), A.br, A.bc, dtype, rbucket,
+                  (int)std::lround(per_row));
     return buf;
 }
 
@@ -92,7 +93,7 @@ void tune_one(Sell &A, Tune &slot, const char *dtype, const T *x, T *y, std::map
     }
     Tune best;
     float best_t = INFINITY, def_t = 0.f;
-    for (int wpb : {2, 4, 8})
+    for (int wpb : {1, 2, 4, 8})
         for (int spw : {1, 2, 4})
             for (int remap : {0, 1})
                 for (int nt : {0, 1}) {

@@ -129,3 +129,35 @@ def test_imposed_aggregates_reproduce_hierarchy(disc_case):
     assert h2.info()["n_dof"] == h.info()["n_dof"]
     for l in range(len(levels) - 1):
         assert np.array_equal(h2.aggregates(l), levels[l].agg)
+
+
+def test_coarse_symmetric_storage_matches_full(disc_case):
+    """Coarse operators stored by their blocks on/above the diagonal
+    (coarse_sym = 1) against the full storage of the same hierarchy: level
+    matrices agree to the rounding asymmetry of the Galerkin product, products
+    and V-cycles to SPMV_TOL / 1e-10, and the solve takes the same iterations."""
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob, A, b, B, levels, hf = disc_case
+    h = _gpu_amg_from_oracle_matrix(prob, A, coarse_max=400, coarse_sym=1)
+    assert h.opts.coarse_sym == 1 and hf.opts.coarse_sym == 0 and hf.info()["n_dof"] == h.info()["n_dof"]
+    rng = np.random.default_rng(5)
+    for l in range(1, h.info()["n_levels"]):
+        rp, col, val = h.level_matrix(l)
+        rpf, colf, valf = hf.level_matrix(l)
+        assert np.array_equal(rp, rpf) and np.array_equal(col, colf)
+        assert np.abs(val - valf).max() <= 1e-13 * np.abs(valf).max(), f"A_{l} values"
+        G = sp.bsr_matrix((valf, colf, rpf)).tocsr()
+        x = rng.normal(size=G.shape[0])
+        y = h.apply(l, te.TE_OP_A, dev(x, torch.float64)).cpu().numpy()
+        yf = hf.apply(l, te.TE_OP_A, dev(x, torch.float64)).cpu().numpy()
+        bound = abs(G) @ np.abs(x)
+        assert np.all(np.abs(y - yf) <= 2 * SPMV_TOL * bound + 1e-300), f"A_{l} x"
+    g = rng.normal(size=A.shape[0])
+    z = h.apply(0, te.TE_OP_VCYCLE, dev(g, torch.float64)).cpu().numpy()
+    zf = hf.apply(0, te.TE_OP_VCYCLE, dev(g, torch.float64)).cpu().numpy()
+    assert np.abs(z - zf).max() <= 1e-10 * np.abs(zf).max()
+    u, rep = h.solve(dev(b, torch.float64))
+    uf, repf = hf.solve(dev(b, torch.float64))
+    assert rep.iters == repf.iters
+    assert float((u - uf).norm() / uf.norm()) <= 1e-8
