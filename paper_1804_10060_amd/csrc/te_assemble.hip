@@ -1,11 +1,12 @@
 // Finite-element assembly of the thermoelastic system (weak form wf_elastic,
 // Sec. 3.1) into 3x3-block compressed rows, and Dirichlet elimination.
 //
-// Gather formulation: one thread owns one node row.  It walks the cells that
-// contain the node (ascending cell id, so the summation order is fixed and
-// the result deterministic), evaluates that node's rows of the element
-// tensors and adds them into its own blocks; nothing is scattered, so no
-// atomics touch the values.  Element integrals:
+// Gather formulation, nothing is scattered: the stiffness rows of a node are
+// built by one wave that walks the cells containing the node (ascending cell
+// id, so the summation order is fixed and the result deterministic): the
+// element blocks of a chunk of cells go through LDS and each lane adds them
+// to the row blocks it owns, which are written once.  The load vector takes
+// one thread per node.  Element integrals:
 //   stiffness  P1: constant gradients (one-point exact); P2: degree-2
 //              integrand, 4-point rule (a,b,b,b), a = (5+3 sqrt5)/20,
 //              b = (5-sqrt5)/20, weights 1/4 (exact for degree 2);
@@ -234,20 +235,32 @@ __device__ __forceinline__ Geo cell_geo(const double *__restrict__ X, const int3
     return g;
 }
 
-// gradient of the P2 basis function a at barycentric point l
-__device__ __forceinline__ void p2_grad(int a, const double l[4], const Geo &g, double out[3]) {
+// Element tables are indexed by runtime node numbers; to keep them out of
+// private (scratch) memory, the barycentric values are selected from
+// registers and the gradients are read from LDS (G: [4][3] row-major).
+__device__ __forceinline__ double sel4(double v0, double v1, double v2, double v3, int k) {
+    return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
+}
+
+// gradient of the P2 basis function a at the barycentric point (l0..l3)
+__device__ __forceinline__ void p2_grad(int a, double l0, double l1, double l2, double l3, const double *G,
+                                        double out[3]) {
     if (a < 4) {
-        double s = 4.0 * l[a] - 1.0;
-        for (int c = 0; c < 3; ++c) out[c] = s * g.G[a][c];
+        const double s = 4.0 * sel4(l0, l1, l2, l3, a) - 1.0;
+        for (int c = 0; c < 3; ++c) out[c] = s * G[a * 3 + c];
     } else {
-        int i = c_edge[a - 4][0], j = c_edge[a - 4][1];
-        for (int c = 0; c < 3; ++c) out[c] = 4.0 * (l[j] * g.G[i][c] + l[i] * g.G[j][c]);
+        const int i = c_edge[a - 4][0], j = c_edge[a - 4][1];
+        const double li = sel4(l0, l1, l2, l3, i), lj = sel4(l0, l1, l2, l3, j);
+        for (int c = 0; c < 3; ++c) out[c] = 4.0 * (lj * G[i * 3 + c] + li * G[j * 3 + c]);
     }
 }
 
-__device__ __forceinline__ double p2_val(int a, const double l[4]) {
-    if (a < 4) return l[a] * (2.0 * l[a] - 1.0);
-    return 4.0 * l[c_edge[a - 4][0]] * l[c_edge[a - 4][1]];
+__device__ __forceinline__ double p2_val(int a, double l0, double l1, double l2, double l3) {
+    if (a < 4) {
+        const double la = sel4(l0, l1, l2, l3, a);
+        return la * (2.0 * la - 1.0);
+    }
+    return 4.0 * sel4(l0, l1, l2, l3, c_edge[a - 4][0]) * sel4(l0, l1, l2, l3, c_edge[a - 4][1]);
 }
 
 // closed-form P2 mass matrix times 420/|K|
@@ -264,15 +277,6 @@ __device__ __forceinline__ double p2_mass420(int a, int c) {
     return contains ? -4.0 : -6.0;
 }
 
-__device__ __forceinline__ int64_t find_col(const int32_t *__restrict__ cols, int64_t lo, int64_t hi, int32_t v) {
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (cols[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 struct AsmArgs {
     const double *X;
     const int32_t *cells;
@@ -285,67 +289,55 @@ struct AsmArgs {
     const double *f;   // [nrhs][N][3] or null
     const int64_t *row_ptr;
     const int32_t *col;
-    double *val;       // null: load only
+    double *val;       // stiffness values (k_stiff)
     double *b;         // [N][3][nrhs]
     int nrhs;
 };
 
-// Stiffness rows of node i (if val) and its load for right-hand side j.
+// Load of node i for right-hand side j (thermal strain and body force).
 template <int DEG>
 __global__ void __launch_bounds__(ABLK) k_assemble(AsmArgs A, int j) {
     const int64_t i = (int64_t)blockIdx.x * ABLK + threadIdx.x;
     if (i >= A.n) return;
     constexpr int NPE = DEG == 1 ? 4 : 10;
-    const int64_t r0 = A.row_ptr ? A.row_ptr[i] : 0, r1 = A.row_ptr ? A.row_ptr[i + 1] : 0;
     const double *T = A.T + (int64_t)j * A.n;
     const double *f = A.f ? A.f + (int64_t)j * A.n * 3 : nullptr;
+    __shared__ double s_g[ABLK][12];
+    double *G = s_g[threadIdx.x];  // this thread's gradients, addressable without scratch
     double bi[3] = {0.0, 0.0, 0.0};
     for (int64_t e = A.start[i]; e < A.start[i + 1]; ++e) {
         const int64_t cell = A.inc[e] / NPE;
         const int a = (int)(A.inc[e] % NPE);
         const int32_t *cv = A.cells + cell * NPE;
         const Geo g = cell_geo(A.X, cv);
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) G[k * 3 + c] = g.G[k][c];
         double dT[NPE];
         for (int c = 0; c < NPE; ++c) dT[c] = T[cv[c]] - A.T_ref;
         if (DEG == 1) {
             // thermal: (3 lam + 2 mu) alpha |K| mean(dT) grad l_a
             double mT = 0.25 * (dT[0] + dT[1] + dT[2] + dT[3]);
-            for (int c = 0; c < 3; ++c) bi[c] += A.calpha * g.vol * mT * g.G[a][c];
+            for (int c = 0; c < 3; ++c) bi[c] += A.calpha * g.vol * mT * G[a * 3 + c];
             if (f)
                 for (int c = 0; c < 4; ++c) {
                     double m = g.vol * (c == a ? 2.0 : 1.0) / 20.0;
                     for (int k = 0; k < 3; ++k) bi[k] += m * f[(int64_t)cv[c] * 3 + k];
                 }
-            if (A.val) {
-                const double *ga = g.G[a];
-                for (int bb = 0; bb < 4; ++bb) {
-                    const double *gb = g.G[bb];
-                    double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
-                    int64_t pos = find_col(A.col, r0, r1, cv[bb]);
-                    if (pos >= r1 || A.col[pos] != cv[bb]) continue;  // unreachable with a matching pattern
-                    double *blk = A.val + pos * 9;
-                    for (int p = 0; p < 3; ++p)
-                        for (int q = 0; q < 3; ++q)
-                            blk[p * 3 + q] += g.vol * (A.lam * ga[p] * gb[q] + A.mu * ga[q] * gb[p] +
-                                                       (p == q ? A.mu * dot : 0.0));
-                }
-            }
         } else {
             // thermal load, degree-3 exact 5-point rule
             {
                 const double w5[5] = {-0.8, 0.45, 0.45, 0.45, 0.45};
                 for (int qp = 0; qp < 5; ++qp) {
-                    double l[4];
-                    if (qp == 0) {
-                        l[0] = l[1] = l[2] = l[3] = 0.25;
-                    } else {
-                        for (int k = 0; k < 4; ++k) l[k] = 1.0 / 6.0;
-                        l[qp - 1] = 0.5;
-                    }
+                    // (1/4,1/4,1/4,1/4), then the permutations of (1/2,1/6,1/6,1/6)
+                    const double l0 = qp == 0 ? 0.25 : (qp == 1 ? 0.5 : 1.0 / 6.0);
+                    const double l1 = qp == 0 ? 0.25 : (qp == 2 ? 0.5 : 1.0 / 6.0);
+                    const double l2 = qp == 0 ? 0.25 : (qp == 3 ? 0.5 : 1.0 / 6.0);
+                    const double l3 = qp == 0 ? 0.25 : (qp == 4 ? 0.5 : 1.0 / 6.0);
                     double Tq = 0.0;
-                    for (int c = 0; c < 10; ++c) Tq += dT[c] * p2_val(c, l);
+#pragma unroll
+                    for (int c = 0; c < 10; ++c) Tq += dT[c] * p2_val(c, l0, l1, l2, l3);
                     double gr[3];
-                    p2_grad(a, l, g, gr);
+                    p2_grad(a, l0, l1, l2, l3, G, gr);
                     for (int c = 0; c < 3; ++c) bi[c] += A.calpha * w5[qp] * g.vol * Tq * gr[c];
                 }
             }
@@ -354,35 +346,121 @@ __global__ void __launch_bounds__(ABLK) k_assemble(AsmArgs A, int j) {
                     double m = g.vol * p2_mass420(a, c) / 420.0;
                     for (int k = 0; k < 3; ++k) bi[k] += m * f[(int64_t)cv[c] * 3 + k];
                 }
-            if (A.val) {
-                const double qa = 0.5854101966249685, qb = 0.1381966011250105;
-                double ga[4][3];
-                double lq[4][4];
-                for (int qp = 0; qp < 4; ++qp) {
-                    for (int k = 0; k < 4; ++k) lq[qp][k] = (k == qp) ? qa : qb;
-                    p2_grad(a, lq[qp], g, ga[qp]);
-                }
-                const double w = 0.25 * g.vol;
-                for (int bb = 0; bb < 10; ++bb) {
-                    double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-                    for (int qp = 0; qp < 4; ++qp) {
-                        double gb[3];
-                        p2_grad(bb, lq[qp], g, gb);
-                        double dot = ga[qp][0] * gb[0] + ga[qp][1] * gb[1] + ga[qp][2] * gb[2];
-                        for (int p = 0; p < 3; ++p)
-                            for (int q = 0; q < 3; ++q)
-                                K[p * 3 + q] += A.lam * ga[qp][p] * gb[q] + A.mu * ga[qp][q] * gb[p] +
-                                                (p == q ? A.mu * dot : 0.0);
-                    }
-                    int64_t pos = find_col(A.col, r0, r1, cv[bb]);
-                    if (pos >= r1 || A.col[pos] != cv[bb]) continue;  // unreachable with a matching pattern
-                    double *blk = A.val + pos * 9;
-                    for (int k = 0; k < 9; ++k) blk[k] += w * K[k];
-                }
-            }
         }
     }
     for (int c = 0; c < 3; ++c) A.b[(i * 3 + c) * A.nrhs + j] = bi[c];
+}
+
+// Stiffness rows, one wave per node row.  The row's incident cells are taken
+// in chunks of SCH: lanes compute the chunk's cell geometries, then the
+// element blocks K_e[a][b] of all (cell, b) pairs with the position of block
+// b in the row; lane q owns blocks q, q + 64, q + 128 of the row (at most
+// PCAP) and adds the chunk's blocks to them in cell order.
+constexpr int SCH = 16;
+
+template <int DEG>
+__global__ void __launch_bounds__(64) k_stiff(AsmArgs A) {
+    constexpr int NPE = DEG == 1 ? 4 : 10;
+    static_assert(NPE % 2 == 0, "cell entries are read in pairs");
+    __shared__ double s_geo[SCH][13];  // gradients of the 4 barycentric coordinates, volume
+    __shared__ int32_t s_cv[SCH][NPE];
+    __shared__ int32_t s_a[SCH];
+    __shared__ double s_k[SCH * NPE][9];
+    __shared__ __align__(8) int32_t s_pos[SCH * NPE];  // NPE is even: a cell's entries read as int2
+    __shared__ int32_t s_col[PCAP];                    // the row's columns, searched in LDS
+    const int lane = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < A.n; i += gridDim.x) {
+        const int64_t r0 = A.row_ptr[i], r1 = A.row_ptr[i + 1];
+        const int len = (int)(r1 - r0);
+        for (int t = lane; t < len; t += 64) s_col[t] = A.col[r0 + t];
+        double acc[3][9];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc[q][k] = 0.0;
+        const int64_t e0 = A.start[i], e1 = A.start[i + 1];
+        for (int64_t cb = e0; cb < e1; cb += SCH) {
+            const int nc = (int)((e1 - cb) < SCH ? (e1 - cb) : SCH);
+            if (lane < nc) {
+                const int64_t ent = A.inc[cb + lane];
+                const int32_t *cv = A.cells + (ent / NPE) * NPE;
+                s_a[lane] = (int)(ent % NPE);
+                for (int b = 0; b < NPE; ++b) s_cv[lane][b] = cv[b];
+                const Geo g = cell_geo(A.X, cv);
+                for (int k = 0; k < 4; ++k)
+                    for (int c = 0; c < 3; ++c) s_geo[lane][k * 3 + c] = g.G[k][c];
+                s_geo[lane][12] = g.vol;
+            }
+            __syncthreads();
+            for (int t = lane; t < nc * NPE; t += 64) {
+                const int c = t / NPE, bb = t % NPE, a = s_a[c];
+                const double *G = s_geo[c];
+                const double vol = s_geo[c][12];
+                double K[9];
+                if (DEG == 1) {
+                    const double *ga = G + a * 3, *gb = G + bb * 3;
+                    const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                    for (int p = 0; p < 3; ++p)
+                        for (int q = 0; q < 3; ++q)
+                            K[p * 3 + q] =
+                                vol * (A.lam * ga[p] * gb[q] + A.mu * ga[q] * gb[p] + (p == q ? A.mu * dot : 0.0));
+                } else {
+                    // degree-2 integrand: 4-point rule (a,b,b,b), weights |K|/4
+                    const double qa = 0.5854101966249685, qb = 0.1381966011250105;
+                    for (int k = 0; k < 9; ++k) K[k] = 0.0;
+                    for (int qp = 0; qp < 4; ++qp) {
+                        const double l0 = qp == 0 ? qa : qb, l1 = qp == 1 ? qa : qb, l2 = qp == 2 ? qa : qb,
+                                     l3 = qp == 3 ? qa : qb;
+                        double ga[3], gb[3];
+                        p2_grad(a, l0, l1, l2, l3, G, ga);
+                        p2_grad(bb, l0, l1, l2, l3, G, gb);
+                        const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+                        for (int p = 0; p < 3; ++p)
+                            for (int q = 0; q < 3; ++q)
+                                K[p * 3 + q] += A.lam * ga[p] * gb[q] + A.mu * ga[q] * gb[p] + (p == q ? A.mu * dot : 0.0);
+                    }
+                    const double w = 0.25 * vol;
+                    for (int k = 0; k < 9; ++k) K[k] *= w;
+                }
+                const int32_t v = s_cv[c][bb];
+                int lo = 0, hi = len;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_col[mid] < v) lo = mid + 1;
+                    else hi = mid;
+                }
+                s_pos[t] = (lo < len && s_col[lo] == v) ? lo : -1;  // -1 unreachable with a matching pattern
+                for (int k = 0; k < 9; ++k) s_k[t][k] = K[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int blk = lane + 64 * q;
+                if (blk < len)
+                    for (int c = 0; c < nc; ++c) {  // cells ascending; a cell meets a block at most once
+                        const int2 *pp = reinterpret_cast<const int2 *>(&s_pos[c * NPE]);
+                        int hit = -1;
+#pragma unroll
+                        for (int h = 0; h < NPE / 2; ++h) {
+                            const int2 v = pp[h];
+                            hit = v.x == blk ? 2 * h : hit;
+                            hit = v.y == blk ? 2 * h + 1 : hit;
+                        }
+                        if (hit >= 0)
+#pragma unroll
+                            for (int k = 0; k < 9; ++k) acc[q][k] += s_k[c * NPE + hit][k];
+                    }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int blk = lane + 64 * q;
+            if (blk < len)
+#pragma unroll
+                for (int k = 0; k < 9; ++k) A.val[(r0 + blk) * 9 + k] = acc[q][k];
+        }
+    }
 }
 
 // Dirichlet elimination, one thread per row.  Lifting with the unconstrained
@@ -495,9 +573,12 @@ extern "C" int fe_assemble_thermoelastic(const te_mesh *mesh, const te_material 
         TE_REQUIRE(nnzb == A->nnzb, TE_EINVAL, "A.nnzb (%lld) != row_ptr[N] (%lld)", (long long)A->nnzb,
                    (long long)nnzb);
         pattern_impl(mesh, I, A->row_ptr, A->col_idx, stream);
-        TE_CHECK_HIP(hipMemsetAsync(A->val, 0, (size_t)nnzb * 9 * sizeof(double), stream));
         AsmArgs a{mesh->coords, mesh->cells, npe, I.start.p, I.inc.p, mesh->n_nodes, lam, mu, calpha, mat->T_ref,
                   T, f, A->row_ptr, A->col_idx, A->val, b, 1};
+        const unsigned gs = (unsigned)std::min<int64_t>(mesh->n_nodes, 1 << 18);
+        if (mesh->degree == 1) hipLaunchKernelGGL(k_stiff<1>, dim3(gs), dim3(64), 0, stream, a);
+        else hipLaunchKernelGGL(k_stiff<2>, dim3(gs), dim3(64), 0, stream, a);
+        TE_CHECK_HIP(hipGetLastError());
         unsigned g = (unsigned)((mesh->n_nodes + ABLK - 1) / ABLK);
         if (mesh->degree == 1) hipLaunchKernelGGL(k_assemble<1>, dim3(g), dim3(ABLK), 0, stream, a, 0);
         else hipLaunchKernelGGL(k_assemble<2>, dim3(g), dim3(ABLK), 0, stream, a, 0);
