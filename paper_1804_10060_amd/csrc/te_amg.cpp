@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <thread>
 
 #include "te_amg.h"
@@ -42,6 +43,66 @@ void set_error(const char *fmt, ...) {
 }
 void clear_error() { g_err[0] = 0; }
 const char *last_error() { return g_err; }
+
+// ---------------------------------------------------------------------------
+// host <-> device copies through pinned staging
+// ---------------------------------------------------------------------------
+static constexpr size_t kStage = (size_t)32 << 20;  // bytes per staging half
+static std::mutex g_stage_mu;
+static char *g_stage = nullptr;  // 2 x kStage pinned bytes, kept until the process ends
+
+static char *stage_buffer() {
+    if (!g_stage) {
+        void *p = nullptr;
+        TE_CHECK_HIP(hipHostMalloc(&p, 2 * kStage, hipHostMallocDefault));
+        g_stage = static_cast<char *>(p);
+    }
+    return g_stage;
+}
+
+void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes < ((size_t)4 << 20)) {
+        TE_CHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    char *st = stage_buffer();
+    const char *in = static_cast<const char *>(src);
+    char *out = static_cast<char *>(dst);
+    int half = 0;
+    for (size_t off = 0; off < bytes; off += kStage, half ^= 1) {
+        const size_t n = std::min(kStage, bytes - off);
+        char *buf = st + half * kStage;
+        std::memcpy(buf, in + off, n);  // overlaps the DMA of the previous chunk (other half)
+        TE_CHECK_HIP(hipStreamSynchronize(s));  // that DMA is done: its half may be refilled next
+        TE_CHECK_HIP(hipMemcpyAsync(out + off, buf, n, hipMemcpyHostToDevice, s));
+    }
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes < ((size_t)4 << 20)) {
+        TE_CHECK_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    char *st = stage_buffer();
+    const char *in = static_cast<const char *>(src);
+    char *out = static_cast<char *>(dst);
+    size_t prev_off = 0, prev_n = 0;
+    int half = 0;
+    for (size_t off = 0; off < bytes; off += kStage, half ^= 1) {
+        const size_t n = std::min(kStage, bytes - off);
+        TE_CHECK_HIP(hipMemcpyAsync(st + half * kStage, in + off, n, hipMemcpyDeviceToHost, s));
+        if (prev_n) std::memcpy(out + prev_off, st + (half ^ 1) * kStage, prev_n);  // overlaps this DMA
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+        prev_off = off;
+        prev_n = n;
+    }
+    std::memcpy(out + prev_off, st + (half ^ 1) * kStage, prev_n);
+}
 
 // ---------------------------------------------------------------------------
 // threads
@@ -209,11 +270,11 @@ struct Tentative {
 };
 
 // Nodes of an aggregate as a 'bs*|J| x k' column-major block of B.
-static void gather_B(const std::vector<int32_t> &nodes, const std::vector<double> &B, int bs, int k,
+static void gather_B(const int32_t *nodes, size_t cnt, const std::vector<double> &B, int bs, int k,
                      std::vector<double> &M) {
-    const int m = (int)nodes.size() * bs;
+    const int m = (int)cnt * bs;
     M.assign((size_t)m * k, 0.0);
-    for (size_t a = 0; a < nodes.size(); ++a)
+    for (size_t a = 0; a < cnt; ++a)
         for (int p = 0; p < bs; ++p)
             for (int c = 0; c < k; ++c) M[(size_t)c * m + a * bs + p] = B[((size_t)nodes[a] * bs + p) * k + c];
 }
@@ -221,38 +282,73 @@ static void gather_B(const std::vector<int32_t> &nodes, const std::vector<double
 static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t> agg, int64_t na,
                            const std::vector<double> &B, int bs, int k) {
     const int64_t n = A.nr;
-    std::vector<std::vector<int32_t>> mem(na);
+    // members of each aggregate, ascending (counting sort by aggregate id);
+    // aggregates whose membership changes by a merge get an explicit list
+    std::vector<int64_t> off(na + 1, 0);
     for (int64_t i = 0; i < n; ++i)
-        if (agg[i] >= 0) mem[agg[i]].push_back((int32_t)i);
-    // full rank of every aggregate's block of B, checked in parallel; an
-    // aggregate that receives merged nodes is checked again when visited
-    auto full_rank = [&](const std::vector<int32_t> &nodes, std::vector<double> &M) {
-        std::vector<double> R((size_t)k * k);
-        gather_B(nodes, B, bs, k, M);
-        const int m = (int)nodes.size() * bs;
-        return m >= k && qr_thin(m, k, M, R.data()) && rank_ok(R.data(), k);
+        if (agg[i] >= 0) ++off[agg[i] + 1];
+    for (int64_t x = 0; x < na; ++x) off[x + 1] += off[x];
+    std::vector<int32_t> mem(off[na]);
+    {
+        std::vector<int64_t> fill(off.begin(), off.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            if (agg[i] >= 0) mem[fill[agg[i]]++] = (int32_t)i;
+    }
+    std::vector<uint8_t> changed(na, 0);
+    std::vector<std::vector<int32_t>> moved(na);  // lists of the changed aggregates
+    auto members = [&](int64_t x, const int32_t *&p, size_t &cnt) {
+        if (changed[x]) {
+            p = moved[x].data();
+            cnt = moved[x].size();
+        } else {
+            p = mem.data() + off[x];
+            cnt = (size_t)(off[x + 1] - off[x]);
+        }
     };
-    std::vector<uint8_t> ok(na, 0), current(na, 1);
+    Tentative T;
+    T.Q.assign((size_t)n * bs * k, 0.0);
+    std::vector<double> Rall((size_t)na * k * k, 0.0);
+    // thin QR of an aggregate's block of B: Q rows of its nodes, R; full rank?
+    auto factor = [&](int64_t x, std::vector<double> &M) {
+        const int32_t *nodes;
+        size_t cnt;
+        members(x, nodes, cnt);
+        const int m = (int)cnt * bs;
+        gather_B(nodes, cnt, B, bs, k, M);
+        double *R = &Rall[(size_t)x * k * k];
+        if (m < k || !qr_thin(m, k, M, R) || !rank_ok(R, k)) return false;
+        for (size_t aa = 0; aa < cnt; ++aa)
+            for (int p = 0; p < bs; ++p)
+                for (int c = 0; c < k; ++c)
+                    T.Q[((size_t)nodes[aa] * bs + p) * k + c] = M[(size_t)c * m + aa * bs + p];
+        return true;
+    };
+    std::vector<uint8_t> ok(na, 0);
     parallel_for(na, [&](int64_t lo, int64_t hi, int) {
         std::vector<double> Mt;
         for (int64_t x = lo; x < hi; ++x)
-            if (!mem[x].empty()) ok[x] = full_rank(mem[x], Mt) ? 1 : 0;
+            if (off[x + 1] > off[x]) ok[x] = factor(x, Mt) ? 1 : 0;
     });
+    // rank-deficient aggregates merge into the neighbour aggregate with the
+    // largest summed strength (ties: smaller id); a grown aggregate is
+    // factored again when visited
     std::vector<double> M;
     int64_t a = 0;
     while (a < na) {
-        auto &nodes = mem[a];
-        if (nodes.empty()) {
+        const int32_t *nodes;
+        size_t cnt;
+        members(a, nodes, cnt);
+        if (cnt == 0) {
             ++a;
             continue;
         }
-        if (current[a] ? ok[a] != 0 : full_rank(nodes, M)) {
+        if (changed[a] ? factor(a, M) : ok[a] != 0) {
             ++a;
             continue;
         }
-        // merge into the neighbour aggregate with the largest summed strength
         std::vector<std::pair<int32_t, double>> score;
-        for (int32_t i : nodes)
+        for (size_t u = 0; u < cnt; ++u) {
+            const int32_t i = nodes[u];
             for (int64_t kk = A.ptr[i]; kk < A.ptr[i + 1]; ++kk) {
                 const int32_t c = A.col[kk];
                 if (c == i) continue;
@@ -267,6 +363,7 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
                     }
                 if (!found) score.push_back({t, S.s[kk]});
             }
+        }
         TE_REQUIRE(!score.empty(), TE_ERANK, "aggregate %lld is rank deficient and has no neighbour", (long long)a);
         int32_t best = score[0].first;
         double bsv = score[0].second;
@@ -275,40 +372,36 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
                 best = sc.first;
                 bsv = sc.second;
             }
-        for (int32_t i : nodes) agg[i] = best;
-        current[best] = 0;
-        auto &dst = mem[best];
-        dst.insert(dst.end(), nodes.begin(), nodes.end());
-        std::sort(dst.begin(), dst.end());
-        nodes.clear();
+        std::vector<int32_t> merged;
+        {
+            const int32_t *bn;
+            size_t bc;
+            members(best, bn, bc);
+            merged.assign(bn, bn + bc);
+        }
+        merged.insert(merged.end(), nodes, nodes + cnt);
+        std::sort(merged.begin(), merged.end());
+        for (size_t u = 0; u < cnt; ++u) agg[nodes[u]] = best;
+        moved[best] = std::move(merged);
+        changed[best] = 1;
+        moved[a].clear();
+        changed[a] = 1;
         a = (best < a) ? best : a + 1;
     }
-    Tentative T;
     std::vector<int32_t> remap(na, -1);
-    for (int64_t x = 0; x < na; ++x)
-        if (!mem[x].empty()) remap[x] = (int32_t)T.nc++;
+    for (int64_t x = 0; x < na; ++x) {
+        const int32_t *nodes;
+        size_t cnt;
+        members(x, nodes, cnt);
+        if (cnt) remap[x] = (int32_t)T.nc++;
+    }
     T.agg.assign(n, -1);
     for (int64_t i = 0; i < n; ++i)
         if (agg[i] >= 0) T.agg[i] = remap[agg[i]];
-    T.Q.assign((size_t)n * bs * k, 0.0);
     T.Bc.assign((size_t)T.nc * k * k, 0.0);
-    std::vector<int64_t> live;
     for (int64_t x = 0; x < na; ++x)
-        if (!mem[x].empty()) live.push_back(x);
-    parallel_for((int64_t)live.size(), [&](int64_t lo, int64_t hi, int) {
-        std::vector<double> Mt;
-        for (int64_t li = lo; li < hi; ++li) {
-            const auto &nodes = mem[live[li]];
-            const int m = (int)nodes.size() * bs;
-            gather_B(nodes, B, bs, k, Mt);
-            double *Rc = &T.Bc[(size_t)li * k * k];
-            qr_thin(m, k, Mt, Rc);
-            for (size_t aa = 0; aa < nodes.size(); ++aa)
-                for (int p = 0; p < bs; ++p)
-                    for (int c = 0; c < k; ++c)
-                        T.Q[((size_t)nodes[aa] * bs + p) * k + c] = Mt[(size_t)c * m + aa * bs + p];
-        }
-    });
+        if (remap[x] >= 0)
+            std::copy(&Rall[(size_t)x * k * k], &Rall[(size_t)(x + 1) * k * k], &T.Bc[(size_t)remap[x] * k * k]);
     return T;
 }
 

@@ -87,17 +87,24 @@ struct DBuf {
     size_t bytes() const { return n * sizeof(T); }
 };
 
+// Copies between pageable host memory and the device.  Transfers of a few MB
+// and more go through a process-wide pinned staging buffer in chunks (the
+// DMA of one chunk overlaps the host copy of the next), which runs at the
+// pinned rate instead of the pageable one.  Both return with the copy done.
+void copy_h2d(void *dst, const void *src, size_t bytes, hipStream_t s);
+void copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t s);
+
 template <class T>
 void upload(DBuf<T> &d, const std::vector<T> &h, hipStream_t s) {
     d.alloc(h.size());
-    if (!h.empty()) TE_CHECK_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (!h.empty()) copy_h2d(d.p, h.data(), h.size() * sizeof(T), s);
 }
 
 template <class T>
 void download(std::vector<T> &h, const T *d, size_t n, hipStream_t s) {
     h.resize(n);
-    if (n) TE_CHECK_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
-    TE_CHECK_HIP(hipStreamSynchronize(s));
+    if (n) copy_d2h(h.data(), d, n * sizeof(T), s);
+    else TE_CHECK_HIP(hipStreamSynchronize(s));
 }
 
 // ---- host block-sparse matrix (natural numbering) -------------------------

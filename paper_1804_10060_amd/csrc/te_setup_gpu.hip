@@ -101,24 +101,29 @@ __global__ void __launch_bounds__(64) k_sym(int64_t n, const int64_t *__restrict
     }
 }
 
-template <int BR, int BK, int BC, int TB>
+// Numeric pass.  For each block k_a of A's row, the lanes first look up the
+// output slots of the whole B row k_a points to (lane l: entry l), then walk
+// that B row in order, the slot passed by a lane shuffle.  LACC: the row's
+// output blocks are accumulated in dynamic LDS (mcap blocks), else in place.
+template <int BR, int BK, int BC, int TB, bool LACC>
 __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict__ aptr,
                                             const int32_t *__restrict__ acol, const double *__restrict__ aval,
                                             const int64_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
                                             const double *__restrict__ bval, const int64_t *__restrict__ cptr,
                                             const int32_t *__restrict__ ccol, double *__restrict__ cval,
-                                            int32_t *__restrict__ flag) {
+                                            int32_t *__restrict__ flag, int mcap) {
     constexpr int BB = BR * BC;
     static_assert(BB <= 64, "output block larger than a wave");
     __shared__ int32_t key[TB];
     __shared__ int32_t slot[TB];
+    extern __shared__ double s_acc[];  // LACC: [mcap][BB]
     const int lane = threadIdx.x;
     const bool on = lane < BB;
     const int p = on ? lane / BC : 0, q = on ? lane % BC : 0;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int64_t c0 = cptr[i];
         const int m = (int)(cptr[i + 1] - c0);
-        if (2 * m > TB) {  // uniform over the block
+        if (2 * m > TB || (LACC && m > mcap)) {  // uniform over the block
             if (lane == 0) atomicOr(flag, 4);
             continue;
         }
@@ -135,7 +140,8 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                 h = (h + 1) & (TB - 1);
             }
         }
-        for (int64_t t = lane; t < (int64_t)m * BB; t += 64) cval[c0 * BB + t] = 0.0;
+        double *acc = LACC ? s_acc : cval + c0 * BB;
+        for (int64_t t = lane; t < (int64_t)m * BB; t += 64) acc[t] = 0.0;
         __syncthreads();
         for (int64_t ka = aptr[i]; ka < aptr[i + 1]; ++ka) {
             const int32_t j = acol[ka];
@@ -143,27 +149,39 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
             const double *a = aval + ka * (BR * BK) + p * BK;
 #pragma unroll
             for (int r = 0; r < BK; ++r) ar[r] = on ? a[r] : 0.0;
-            for (int64_t kb = bptr[j]; kb < bptr[j + 1]; ++kb) {
-                const int32_t c = bcol[kb];
-                uint32_t h = hslot<TB>(c);
-                int probe = 0;
-                while (probe < TB && key[h] != c) {
-                    h = (h + 1) & (TB - 1);
-                    ++probe;
+            const int64_t b0 = bptr[j], b1 = bptr[j + 1];
+            for (int64_t kb0 = b0; kb0 < b1; kb0 += 64) {
+                const int nb = (int)((b1 - kb0) < 64 ? (b1 - kb0) : 64);
+                int my = -1;
+                if (lane < nb) {
+                    const int32_t c = bcol[kb0 + lane];
+                    uint32_t h = hslot<TB>(c);
+                    int probe = 0;
+                    while (probe < TB && key[h] != c) {
+                        h = (h + 1) & (TB - 1);
+                        ++probe;
+                    }
+                    my = probe < TB ? slot[h] : -1;
                 }
-                if (probe == TB) {
+                if (__any(lane < nb && my < 0)) {
                     if (lane == 0) atomicOr(flag, 8);
                     continue;
                 }
-                if (on) {
-                    const double *b = bval + kb * (BK * BC) + q;
-                    double t = 0.0;
+                for (int u = 0; u < nb; ++u) {
+                    const int sl = __shfl(my, u);
+                    if (on) {
+                        const double *b = bval + (kb0 + u) * (BK * BC) + q;
+                        double t = 0.0;
 #pragma unroll
-                    for (int r = 0; r < BK; ++r) t += ar[r] * b[r * BC];
-                    cval[(c0 + slot[h]) * BB + lane] += t;
+                        for (int r = 0; r < BK; ++r) t += ar[r] * b[r * BC];
+                        acc[sl * BB + lane] += t;
+                    }
                 }
             }
         }
+        __syncthreads();
+        if (LACC)
+            for (int64_t t = lane; t < (int64_t)m * BB; t += 64) cval[c0 * BB + t] = s_acc[t];
         __syncthreads();
     }
 }
@@ -263,6 +281,81 @@ __global__ void k_p_numeric(int64_t n, const int64_t *__restrict__ ptr, const in
     }
 }
 
+// The same with one wave per row: lane (p, c) owns entry (p, c) of every
+// block of the row and accumulates in LDS, in the same order as above (A's row,
+// then the rows of the block, the tentative part last).  Dynamic LDS: mcap
+// blocks of BS x 6 values, then mcap column indices.
+template <int BS>
+__global__ void __launch_bounds__(64) k_p_wave(int64_t n, const int64_t *__restrict__ ptr,
+                                               const int32_t *__restrict__ col, const double *__restrict__ val,
+                                               const int32_t *__restrict__ agg, const double *__restrict__ Q,
+                                               const double *__restrict__ d, double omega,
+                                               const int64_t *__restrict__ pptr, const int32_t *__restrict__ pcol,
+                                               double *__restrict__ pval, int32_t *__restrict__ flag, int mcap) {
+    constexpr int K = 6, BB = BS * K;
+    static_assert(BB <= 64, "block larger than a wave");
+    extern __shared__ double s_dyn[];
+    double *s_acc = s_dyn;
+    int32_t *s_pc = reinterpret_cast<int32_t *>(s_dyn + (size_t)mcap * BB);
+    const int lane = threadIdx.x;
+    const bool on = lane < BB;
+    const int p = on ? lane / K : 0, c = on ? lane % K : 0;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t p0 = pptr[i];
+        const int m = (int)(pptr[i + 1] - p0);
+        if (m > mcap) {  // uniform; cannot happen with mcap = the longest row
+            if (lane == 0) atomicOr(flag, 4);
+            continue;
+        }
+        for (int t = lane; t < m * BB; t += 64) s_acc[t] = 0.0;
+        for (int t = lane; t < m; t += 64) s_pc[t] = pcol[p0 + t];
+        __syncthreads();
+        auto find = [&](int32_t a) -> int {
+            int lo = 0, hi = m;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pc[mid] < a) lo = mid + 1;
+                else hi = mid;
+            }
+            return (lo < m && s_pc[lo] == a) ? lo : -1;
+        };
+        const double f = on ? omega / d[i * BS + p] : 0.0;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            const int32_t a = agg[j];
+            if (a < 0) continue;
+            const int at = find(a);
+            if (at < 0) {
+                if (lane == 0) atomicOr(flag, 8);
+                continue;
+            }
+            if (on) {
+                const double *av = val + k * BS * BS + p * BS;
+                const double *qv = Q + (int64_t)j * BS * K + c;
+                double o = s_acc[at * BB + lane];
+                for (int r = 0; r < BS; ++r) {
+                    const double ar = av[r];
+                    if (ar == 0.0) continue;
+                    o -= f * ar * qv[r * K];
+                }
+                s_acc[at * BB + lane] = o;
+            }
+        }
+        const int32_t ai = agg[i];
+        if (ai >= 0) {
+            const int at = find(ai);
+            if (at < 0) {
+                if (lane == 0) atomicOr(flag, 8);
+            } else if (on) {
+                s_acc[at * BB + lane] += Q[i * BS * K + lane];
+            }
+        }
+        __syncthreads();
+        for (int t = lane; t < m * BB; t += 64) pval[p0 * BB + t] = s_acc[t];
+        __syncthreads();
+    }
+}
+
 // ---- transpose --------------------------------------------------------------------------
 __global__ void k_t_count(int64_t nnzb, const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnzb; k += (int64_t)gridDim.x * blockDim.x)
@@ -281,18 +374,30 @@ __global__ void k_t_place(int64_t n, const int64_t *__restrict__ ptr, const int3
             row[k] = (int32_t)i;
         }
 }
-__global__ void k_t_sort(int64_t n, const int64_t *__restrict__ tptr, int64_t *__restrict__ src) {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t lo = tptr[r], hi = tptr[r + 1];
-        for (int64_t a = lo + 1; a < hi; ++a) {
-            const int64_t v = src[a];
-            int64_t b = a - 1;
-            while (b >= lo && src[b] > v) {
-                src[b + 1] = src[b];
-                --b;
-            }
-            src[b + 1] = v;
+// Segment r of src (the blocks of column r, placed in arbitrary order) in
+// ascending order: one wave per segment, each element's rank is the number of
+// smaller elements (the values are distinct block indices).  Segments longer
+// than TSEG are ranked from global memory.
+constexpr int TSEG = 1024;
+__global__ void __launch_bounds__(64) k_t_rank(int64_t n, const int64_t *__restrict__ tptr,
+                                               const int64_t *__restrict__ src, int64_t *__restrict__ dst) {
+    __shared__ int64_t sv[TSEG];
+    const int lane = threadIdx.x;
+    for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+        const int64_t lo = tptr[r];
+        const int L = (int)(tptr[r + 1] - lo);
+        const bool in_lds = L <= TSEG;
+        const int64_t *v = in_lds ? sv : src + lo;
+        if (in_lds)
+            for (int t = lane; t < L; t += 64) sv[t] = src[lo + t];
+        __syncthreads();
+        for (int t = lane; t < L; t += 64) {
+            const int64_t x = v[t];
+            int rank = 0;
+            for (int y = 0; y < L; ++y) rank += v[y] < x ? 1 : 0;
+            dst[lo + rank] = x;
         }
+        __syncthreads();
     }
 }
 template <int BR, int BC>
@@ -335,20 +440,20 @@ __global__ void k_pack_sell(int64_t nr, int bb, const int64_t *__restrict__ ptr,
     }
 }
 // one wave per row: storage row r holds row order[r], blocks contiguous
-__global__ void k_pack_rows(int64_t nr, int bb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                            const double *__restrict__ val, const int32_t *__restrict__ order,
-                            const int32_t *__restrict__ colmap, const int64_t *__restrict__ rptr,
-                            int32_t *__restrict__ rcol, double *__restrict__ rval, float *__restrict__ rval32) {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nr; r += (int64_t)gridDim.x * blockDim.x) {
+__global__ void __launch_bounds__(64) k_pack_rows(int64_t nr, int bb, const int64_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  const int32_t *__restrict__ order, const int32_t *__restrict__ colmap,
+                                                  const int64_t *__restrict__ rptr, int32_t *__restrict__ rcol,
+                                                  double *__restrict__ rval, float *__restrict__ rval32) {
+    const int lane = threadIdx.x;
+    for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
         const int64_t o = order[r];
         const int64_t s0 = ptr[o], len = ptr[o + 1] - s0, d0 = rptr[r];
-        for (int64_t k = 0; k < len; ++k) {
-            rcol[d0 + k] = colmap[col[s0 + k]];
-            for (int x = 0; x < bb; ++x) {
-                const double v = val[(s0 + k) * bb + x];
-                rval[(d0 + k) * bb + x] = v;
-                if (rval32) rval32[(d0 + k) * bb + x] = (float)v;
-            }
+        for (int64_t k = lane; k < len; k += 64) rcol[d0 + k] = colmap[col[s0 + k]];
+        for (int64_t t = lane; t < len * bb; t += 64) {
+            const double v = val[s0 * bb + t];
+            rval[d0 * bb + t] = v;
+            if (rval32) rval32[d0 * bb + t] = (float)v;
         }
     }
 }
@@ -444,12 +549,20 @@ int64_t symbolic(const DBsr &A, const int64_t *bptr, const int32_t *bcol, const 
 }
 
 template <int BR, int BK, int BC>
-void launch_num(int tb, const DBsr &A, const DBsr &B, DBsr &C, int32_t *flag, hipStream_t s) {
+void launch_num(int tb, int64_t mx, const DBsr &A, const DBsr &B, DBsr &C, int32_t *flag, hipStream_t s) {
     const dim3 g(wave_grid(A.nr)), b(64);
-#define TE_NUM(TBV)                                                                                              \
-    case TBV:                                                                                                    \
-        hipLaunchKernelGGL((k_num<BR, BK, BC, TBV>), g, b, 0, s, A.nr, A.ptr, A.col, A.val, B.ptr, B.col, B.val, \
-                           C.ptr, C.col, C.val_own.p, flag);                                                     \
+    // LDS accumulation while a row's blocks fit in 32 KB (several waves per CU)
+    const size_t lds = (size_t)std::max<int64_t>(mx, 1) * BR * BC * sizeof(double);
+    const bool lacc = lds <= ((size_t)32 << 10);
+    const int mcap = (int)std::max<int64_t>(mx, 1);
+#define TE_NUM(TBV)                                                                                                \
+    case TBV:                                                                                                      \
+        if (lacc)                                                                                                  \
+            hipLaunchKernelGGL((k_num<BR, BK, BC, TBV, true>), g, b, lds, s, A.nr, A.ptr, A.col, A.val, B.ptr,     \
+                               B.col, B.val, C.ptr, C.col, C.val_own.p, flag, mcap);                               \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_num<BR, BK, BC, TBV, false>), g, b, 0, s, A.nr, A.ptr, A.col, A.val, B.ptr,      \
+                               B.col, B.val, C.ptr, C.col, C.val_own.p, flag, mcap);                               \
         break;
     switch (tb) {
         TE_NUM(64)
@@ -496,12 +609,21 @@ void dev_smoothed_p(const DBsr &A, const DBuf<int32_t> &agg, int64_t nagg, const
     P.bc = 6;
     P.nr = A.nr;
     P.nc = nagg;
-    symbolic<true>(A, nullptr, nullptr, agg.p, 64, P, s);
+    const int64_t mx = symbolic<true>(A, nullptr, nullptr, agg.p, 64, P, s);
     P.val_own.alloc(std::max<int64_t>(P.nnzb * P.br * P.bc, 1));
     P.bind();
     DBuf<int32_t> flag(1);
     TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
-    if (A.br == 3)
+    const size_t lds = (size_t)std::max<int64_t>(mx, 1) * (P.br * 6 * sizeof(double) + sizeof(int32_t));
+    if (lds <= (size_t)48 << 10) {
+        const int mcap = (int)std::max<int64_t>(mx, 1);
+        if (A.br == 3)
+            hipLaunchKernelGGL(k_p_wave<3>, dim3(wave_grid(A.nr)), dim3(64), lds, s, A.nr, A.ptr, A.col, A.val, agg.p,
+                               Q.p, d.p, omega, P.ptr, P.col, P.val_own.p, flag.p, mcap);
+        else
+            hipLaunchKernelGGL(k_p_wave<6>, dim3(wave_grid(A.nr)), dim3(64), lds, s, A.nr, A.ptr, A.col, A.val, agg.p,
+                               Q.p, d.p, omega, P.ptr, P.col, P.val_own.p, flag.p, mcap);
+    } else if (A.br == 3)
         hipLaunchKernelGGL(k_p_numeric<3>, dim3(grid_for(A.nr)), dim3(256), 0, s, A.nr, A.ptr, A.col, A.val, agg.p,
                            Q.p, d.p, omega, P.ptr, P.col, P.val_own.p, flag.p);
     else
@@ -526,9 +648,9 @@ void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s) {
     DBuf<int32_t> flag(1);
     TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
     const int key = A.br * 100 + A.bc * 10 + B.bc;
-    if (key == 336) launch_num<3, 3, 6>(tb, A, B, C, flag.p, s);
-    else if (key == 636) launch_num<6, 3, 6>(tb, A, B, C, flag.p, s);
-    else if (key == 666) launch_num<6, 6, 6>(tb, A, B, C, flag.p, s);
+    if (key == 336) launch_num<3, 3, 6>(tb, mx, A, B, C, flag.p, s);
+    else if (key == 636) launch_num<6, 3, 6>(tb, mx, A, B, C, flag.p, s);
+    else if (key == 666) launch_num<6, 6, 6>(tb, mx, A, B, C, flag.p, s);
     else TE_REQUIRE(false, TE_EINVAL, "unsupported product block shapes %dx%d * %dx%d", A.br, A.bc, B.br, B.bc);
     TE_REQUIRE(read_flag(flag, s) == 0, TE_EHIP, "sparse product numeric pass found an inconsistent pattern");
 }
@@ -553,12 +675,13 @@ void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s) {
     T.bind();
     hipLaunchKernelGGL(k_t_place, dim3(grid_for(A.nr)), dim3(256), 0, s, A.nr, A.ptr, A.col, T.ptr, fill.p, src.p,
                        row.p);
-    hipLaunchKernelGGL(k_t_sort, dim3(grid_for(T.nr)), dim3(256), 0, s, T.nr, T.ptr, src.p);
+    DBuf<int64_t> srt(std::max<int64_t>(A.nnzb, 1));
+    hipLaunchKernelGGL(k_t_rank, dim3(wave_grid(T.nr)), dim3(64), 0, s, T.nr, T.ptr, src.p, srt.p);
     if (A.br == 3 && A.bc == 6)
-        hipLaunchKernelGGL((k_t_fill<3, 6>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, src.p, row.p, A.val,
+        hipLaunchKernelGGL((k_t_fill<3, 6>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, srt.p, row.p, A.val,
                            T.col_own.p, T.val_own.p);
     else if (A.br == 6 && A.bc == 6)
-        hipLaunchKernelGGL((k_t_fill<6, 6>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, src.p, row.p, A.val,
+        hipLaunchKernelGGL((k_t_fill<6, 6>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, srt.p, row.p, A.val,
                            T.col_own.p, T.val_own.p);
     else
         TE_REQUIRE(false, TE_EINVAL, "unsupported transpose block shape %dx%d", A.br, A.bc);
@@ -699,8 +822,8 @@ void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const st
         S.val.alloc(std::max<int64_t>(M.nnzb * bb, 1));
         if (fp32) S.val32.alloc(std::max<int64_t>(M.nnzb * bb, 1));
         else S.val32.release();
-        hipLaunchKernelGGL(k_pack_rows, dim3(grid_for(M.nr)), dim3(256), 0, s, M.nr, bb, M.ptr, M.col, M.val, dorder.p,
-                           dmap.p, S.rptr.p, S.col.p, S.val.p, fp32 ? S.val32.p : nullptr);
+        hipLaunchKernelGGL(k_pack_rows, dim3(wave_grid(M.nr)), dim3(64), 0, s, M.nr, bb, M.ptr, M.col, M.val,
+                           dorder.p, dmap.p, S.rptr.p, S.col.p, S.val.p, fp32 ? S.val32.p : nullptr);
         S.slice_off.release();
         S.rowlen.release();
     } else {
