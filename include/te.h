@@ -141,6 +141,11 @@ void amg_options_default(amg_options *opt);
  *   dir_mask: device [N][3] or NULL: near-nullspace rows of constrained DOFs
  *             are zeroed;
  *   out: receives a library-owned handle (release with amg_destroy).
+ * Strength of connection, prolongator smoothing, the products A P and
+ * P^T (A P) and the packing into the solver layouts run on the device; the
+ * greedy aggregation, the per-aggregate QR and the coarsest factor on the
+ * host (host_threads threads).  Only the pattern, the strength values and the
+ * tentative prolongator cross to the host and back.
  * The matrix values are copied; A may be freed afterwards.  Synchronises
  * `stream`.  Errors: TE_EINVAL, TE_ENOMEM, TE_EHIP, TE_ERANK, TE_ECHOL. */
 int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask,

@@ -167,14 +167,30 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                     if (lane == 0) atomicOr(flag, 8);
                     continue;
                 }
-                for (int u = 0; u < nb; ++u) {
-                    const int sl = __shfl(my, u);
-                    if (on) {
-                        const double *b = bval + (kb0 + u) * (BK * BC) + q;
-                        double t = 0.0;
+                // the slots of one B row are distinct: batches of UB updates
+                // load their accumulators together, then store them
+                constexpr int UB = 8;
+                for (int u0 = 0; u0 < nb; u0 += UB) {
+                    int sl[UB];
+                    double t[UB], old[UB];
 #pragma unroll
-                        for (int r = 0; r < BK; ++r) t += ar[r] * b[r * BC];
-                        acc[sl * BB + lane] += t;
+                    for (int uu = 0; uu < UB; ++uu) {
+                        const int u = u0 + uu < nb ? u0 + uu : nb - 1;
+                        sl[uu] = __shfl(my, u);
+                        t[uu] = 0.0;
+                        if (on && u0 + uu < nb) {
+                            const double *b = bval + (kb0 + u) * (BK * BC) + q;
+#pragma unroll
+                            for (int r = 0; r < BK; ++r) t[uu] += ar[r] * b[r * BC];
+                        }
+                    }
+                    if (on) {
+#pragma unroll
+                        for (int uu = 0; uu < UB; ++uu)
+                            if (u0 + uu < nb) old[uu] = acc[sl[uu] * BB + lane];
+#pragma unroll
+                        for (int uu = 0; uu < UB; ++uu)
+                            if (u0 + uu < nb) acc[sl[uu] * BB + lane] = old[uu] + t[uu];
                     }
                 }
             }

@@ -146,8 +146,9 @@ def test_error_paths_forced_from_host():
 def test_full_size_disc_p2_fp64_and_mixed():
     """The 12,043,200-DOF P2 disc: both precisions reach the true relative
     residual 1e-8; the residual is recomputed on the host from the assembled
-    system with scipy (not by the library), and the two solutions agree to the
-    accuracy the residual bound allows."""
+    system with scipy (not by the library), the two solutions agree to the
+    accuracy the residual bound allows, and sampled rows of the oracle's own
+    assembly confirm the float64 solution."""
     import scipy.sparse as sp
     import paper_1804_10060_amd as te
     nr, nth, nz, deg = mg.DISC_P2_12M
@@ -166,3 +167,27 @@ def test_full_size_disc_p2_fp64_and_mixed():
         assert np.linalg.norm(bh - M @ u) <= 1.0000001e-8 * np.linalg.norm(bh)
     a, c = u64.cpu().numpy(), u32.cpu().numpy()
     assert np.linalg.norm(a - c) <= 1e-5 * np.linalg.norm(a)
+    # the float64 solution against the oracle's own rows (assembled by the
+    # oracle from the cells that touch them, Dirichlet elimination applied):
+    # every row of b - A u is bounded by the 2-norm bound 1e-8 ||b||, plus the
+    # rounding of the two assemblies (1e-13 of the row's |A||u| and |b|)
+    from oracle import fem
+    m = prob.mesh
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([rng.integers(0, m.n_nodes, 24), [0, 1, m.n_nodes - 1]]))
+    ref = fem.assemble_rows(m.coords, m.cells, deg, prob.E, prob.nu, prob.alpha, prob.T_ref, prob.T, rows)
+    mask = prob.mask.astype(bool)
+    u3 = a.reshape(-1, 3)
+    bnorm = np.linalg.norm(bh)
+    for r in rows.tolist():
+        cols_o, blocks_o, b_o = ref[r]
+        blocks_o = blocks_o.copy()
+        for k, cc in enumerate(cols_o.tolist()):
+            for p in range(3):
+                for q in range(3):
+                    if mask[r, p] or mask[cc, q]:
+                        blocks_o[k, p, q] = 1.0 if (cc == r and p == q) else 0.0
+        b_o = np.where(mask[r], 0.0, b_o)
+        Au = np.einsum("kpq,kq->p", blocks_o, u3[cols_o])
+        scale = np.einsum("kpq,kq->p", np.abs(blocks_o), np.abs(u3[cols_o])) + np.abs(b_o)
+        assert np.all(np.abs(b_o - Au) <= 1e-8 * bnorm + 1e-13 * scale), f"row {r}"
