@@ -39,7 +39,7 @@ extern "C" {
 #define TE_EINDEF    (-4)  /* CG breakdown: (p,Ap) <= 0 or (r,z) <= 0         */
 #define TE_ENAN      (-5)  /* NaN or Inf in a residual                       */
 #define TE_ERANK     (-6)  /* aggregate near-nullspace block of rank < 6     */
-#define TE_ECHOL     (-7)  /* coarse Cholesky pivot <= 0                     */
+#define TE_ECHOL     (-7)  /* coarsest-level pivot <= 0 (not SPD)            */
 
 #define TE_PREC_FP64   0   /* everything in float64 (the reference method)   */
 #define TE_PREC_MIXED  1   /* float32 V-cycle inside float64 flexible CG     */

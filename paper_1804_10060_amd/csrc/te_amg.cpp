@@ -2,12 +2,11 @@
 // method of Vanek, Mandel & Brezina 1996 with the rigid-body near-nullspace).
 //
 // Host part: the greedy aggregation, the tentative prolongator by
-// Householder QR per aggregate, the storage order of every level and the
-// dense Cholesky factor and inverse of the coarsest level.  Device part
-// (te_setup_gpu.hip and te_kernels.hip): strength of connection, prolongator
-// smoothing, the products A P and P^T (A P), the transpose, the packing into
-// the solver layouts and the Lanczos estimate of the largest eigenvalue of
-// D^-1 A.  Matrix values never leave the device, except those of the
+// Householder QR per aggregate and the storage order of every level.  Device
+// part (te_setup_gpu.hip and te_kernels.hip): strength of connection,
+// prolongator smoothing, the products A P and P^T (A P), the transpose, the
+// packing into the solver layouts, the Lanczos estimate of the largest
+// eigenvalue of D^-1 A and the dense inverse of the coarsest level.  Matrix values never leave the device, except those of the
 // coarsest level.
 //
 // Readings of what the paper leaves open (strength threshold 0.08 halved per
@@ -502,49 +501,6 @@ static double lanczos_estimate(const Level &L, int steps, uint64_t seed, hipStre
     return tridiag_max_eig(al, be);
 }
 
-// ---------------------------------------------------------------------------
-// dense coarse factor
-// ---------------------------------------------------------------------------
-static void dense_inverse_spd(std::vector<double> &Mat, int n) {
-    // Cholesky M = L L^T (lower, row-major), then inverse = L^-T L^-1
-    for (int j = 0; j < n; ++j) {
-        double d = Mat[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k) d -= Mat[(size_t)j * n + k] * Mat[(size_t)j * n + k];
-        TE_REQUIRE(d > 0, TE_ECHOL, "coarse Cholesky: pivot %d is %g", j, d);
-        d = std::sqrt(d);
-        Mat[(size_t)j * n + j] = d;
-        parallel_for(n - j - 1, [&](int64_t lo, int64_t hi, int) {
-            for (int64_t ii = lo; ii < hi; ++ii) {
-                const int i = j + 1 + (int)ii;
-                double v = Mat[(size_t)i * n + j];
-                const double *ri = &Mat[(size_t)i * n];
-                const double *rj = &Mat[(size_t)j * n];
-                for (int k = 0; k < j; ++k) v -= ri[k] * rj[k];
-                Mat[(size_t)i * n + j] = v / d;
-            }
-        });
-    }
-    // Linv (lower), column by column in parallel
-    std::vector<double> Li((size_t)n * n, 0.0);
-    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t c = lo; c < hi; ++c) {
-            for (int i = (int)c; i < n; ++i) {
-                double v = (i == c) ? 1.0 : 0.0;
-                for (int k = (int)c; k < i; ++k) v -= Mat[(size_t)i * n + k] * Li[(size_t)k * n + c];
-                Li[(size_t)i * n + c] = v / Mat[(size_t)i * n + i];
-            }
-        }
-    });
-    // inv[i][j] = sum_k Li[k][i] Li[k][j], k >= max(i,j)
-    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t i = lo; i < hi; ++i)
-            for (int j = 0; j < n; ++j) {
-                double v = 0.0;
-                for (int k = std::max((int)i, j); k < n; ++k) v += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
-                Mat[(size_t)i * n + j] = v;
-            }
-    });
-}
 
 // ---------------------------------------------------------------------------
 // the setup
@@ -854,8 +810,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                         M[(size_t)(sj * b + q) * nc + si * b + p] += v;
                     }
             }
-        dense_inverse_spd(M, (int)nc);
-        upload(h->Ainv, M, s);
+        dev_dense_inverse_spd(M, (int)nc, h->Ainv, s);
         h->nc = (int)nc;
     }
     note("coarse factor", (int)h->L.size() - 1, h->nc, 0);

@@ -65,6 +65,11 @@ void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const st
               const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32, hipStream_t s,
               int format, const std::vector<int32_t> *sym_cols = nullptr);
 
+// inv = M^-1 for a symmetric positive definite n x n matrix M (host,
+// row-major), computed on the device by n symmetric sweeps; TE_ECHOL if a
+// pivot is not positive.
+void dev_dense_inverse_spd(const std::vector<double> &M, int n, DBuf<double> &inv, hipStream_t s);
+
 // Host copies of the pattern or of the whole matrix.
 void dev_pattern_to_host(const DBsr &M, HBsr &H, hipStream_t s);
 void dev_to_host(const DBsr &M, HBsr &H, hipStream_t s);

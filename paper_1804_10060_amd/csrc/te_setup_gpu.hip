@@ -116,6 +116,7 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
     static_assert(BB <= 64, "output block larger than a wave");
     __shared__ int32_t key[TB];
     __shared__ int32_t slot[TB];
+    __shared__ int64_t s_b0[64], s_b1[64];
     extern __shared__ double s_acc[];  // LACC: [mcap][BB]
     const int lane = threadIdx.x;
     const bool on = lane < BB;
@@ -143,57 +144,69 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
         double *acc = LACC ? s_acc : cval + c0 * BB;
         for (int64_t t = lane; t < (int64_t)m * BB; t += 64) acc[t] = 0.0;
         __syncthreads();
-        for (int64_t ka = aptr[i]; ka < aptr[i + 1]; ++ka) {
-            const int32_t j = acol[ka];
-            double ar[BK];
-            const double *a = aval + ka * (BR * BK) + p * BK;
+        const int64_t a0 = aptr[i], a1 = aptr[i + 1];
+        for (int64_t kc = a0; kc < a1; kc += 64) {
+            // B-row bounds of the next (up to) 64 blocks of A's row, fetched by the lanes at once
+            const int na = (int)((a1 - kc) < 64 ? (a1 - kc) : 64);
+            if (lane < na) {
+                const int32_t jj = acol[kc + lane];
+                s_b0[lane] = bptr[jj];
+                s_b1[lane] = bptr[jj + 1];
+            }
+            __syncthreads();
+            for (int ua = 0; ua < na; ++ua) {
+                const int64_t ka = kc + ua;
+                double ar[BK];
+                const double *a = aval + ka * (BR * BK) + p * BK;
 #pragma unroll
-            for (int r = 0; r < BK; ++r) ar[r] = on ? a[r] : 0.0;
-            const int64_t b0 = bptr[j], b1 = bptr[j + 1];
-            for (int64_t kb0 = b0; kb0 < b1; kb0 += 64) {
-                const int nb = (int)((b1 - kb0) < 64 ? (b1 - kb0) : 64);
-                int my = -1;
-                if (lane < nb) {
-                    const int32_t c = bcol[kb0 + lane];
-                    uint32_t h = hslot<TB>(c);
-                    int probe = 0;
-                    while (probe < TB && key[h] != c) {
-                        h = (h + 1) & (TB - 1);
-                        ++probe;
-                    }
-                    my = probe < TB ? slot[h] : -1;
-                }
-                if (__any(lane < nb && my < 0)) {
-                    if (lane == 0) atomicOr(flag, 8);
-                    continue;
-                }
-                // the slots of one B row are distinct: batches of UB updates
-                // load their accumulators together, then store them
-                constexpr int UB = 8;
-                for (int u0 = 0; u0 < nb; u0 += UB) {
-                    int sl[UB];
-                    double t[UB], old[UB];
-#pragma unroll
-                    for (int uu = 0; uu < UB; ++uu) {
-                        const int u = u0 + uu < nb ? u0 + uu : nb - 1;
-                        sl[uu] = __shfl(my, u);
-                        t[uu] = 0.0;
-                        if (on && u0 + uu < nb) {
-                            const double *b = bval + (kb0 + u) * (BK * BC) + q;
-#pragma unroll
-                            for (int r = 0; r < BK; ++r) t[uu] += ar[r] * b[r * BC];
+                for (int r = 0; r < BK; ++r) ar[r] = on ? a[r] : 0.0;
+                const int64_t b0 = s_b0[ua], b1 = s_b1[ua];
+                for (int64_t kb0 = b0; kb0 < b1; kb0 += 64) {
+                    const int nb = (int)((b1 - kb0) < 64 ? (b1 - kb0) : 64);
+                    int my = -1;
+                    if (lane < nb) {
+                        const int32_t c = bcol[kb0 + lane];
+                        uint32_t h = hslot<TB>(c);
+                        int probe = 0;
+                        while (probe < TB && key[h] != c) {
+                            h = (h + 1) & (TB - 1);
+                            ++probe;
                         }
+                        my = probe < TB ? slot[h] : -1;
                     }
-                    if (on) {
+                    if (__any(lane < nb && my < 0)) {
+                        if (lane == 0) atomicOr(flag, 8);
+                        continue;
+                    }
+                    // the slots of one B row are distinct: batches of UB updates
+                    // load their accumulators together, then store them
+                    constexpr int UB = 8;
+                    for (int u0 = 0; u0 < nb; u0 += UB) {
+                        int sl[UB];
+                        double t[UB], old[UB];
 #pragma unroll
-                        for (int uu = 0; uu < UB; ++uu)
-                            if (u0 + uu < nb) old[uu] = acc[sl[uu] * BB + lane];
+                        for (int uu = 0; uu < UB; ++uu) {
+                            const int u = u0 + uu < nb ? u0 + uu : nb - 1;
+                            sl[uu] = __shfl(my, u);
+                            t[uu] = 0.0;
+                            if (on && u0 + uu < nb) {
+                                const double *b = bval + (kb0 + u) * (BK * BC) + q;
 #pragma unroll
-                        for (int uu = 0; uu < UB; ++uu)
-                            if (u0 + uu < nb) acc[sl[uu] * BB + lane] = old[uu] + t[uu];
+                                for (int r = 0; r < BK; ++r) t[uu] += ar[r] * b[r * BC];
+                            }
+                        }
+                        if (on) {
+#pragma unroll
+                            for (int uu = 0; uu < UB; ++uu)
+                                if (u0 + uu < nb) old[uu] = acc[sl[uu] * BB + lane];
+#pragma unroll
+                            for (int uu = 0; uu < UB; ++uu)
+                                if (u0 + uu < nb) acc[sl[uu] * BB + lane] = old[uu] + t[uu];
+                        }
                     }
                 }
             }
+            __syncthreads();  // s_b0 / s_b1 are refilled for the next 64 blocks
         }
         __syncthreads();
         if (LACC)
@@ -483,6 +496,37 @@ __global__ void k_pack_upper(int64_t nup, int bb, const int64_t *__restrict__ sr
         rval[t] = v;
         if (rval32) rval32[t] = (float)v;
     }
+}
+
+// ---- dense inverse of the coarsest operator ----------------------------------------------
+// Symmetric sweep operator on pivot j (Goodnight 1979): with d = a_jj,
+//   a_jj <- -1/d,  a_ij <- a_ij/d,  a_jk <- a_jk/d,  a_ik <- a_ik - a_ij a_jk/d  (i, k != j);
+// after sweeping every pivot the matrix holds -A^-1.  On a symmetric positive
+// definite matrix each pivot is a Schur complement entry, hence positive;
+// a pivot <= 0 (or NaN) is reported.  Reads `in`, writes `out` (ping-pong).
+__global__ void k_sweep(int n, int j, const double *__restrict__ in, double *__restrict__ out,
+                        int32_t *__restrict__ bad) {
+    const double d = in[(int64_t)j * n + j];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double ajk = in[(int64_t)j * n + k];
+    for (int i = blockIdx.y; i < n; i += gridDim.y) {
+        const int64_t t = (int64_t)i * n + k;
+        double v;
+        if (i == j && k == j) {
+            v = -1.0 / d;
+            if (!(d > 0.0)) *bad = 1;
+        } else if (i == j || k == j) {
+            v = in[t] / d;
+        } else {
+            v = in[t] - in[(int64_t)i * n + j] * ajk / d;
+        }
+        out[t] = v;
+    }
+}
+__global__ void k_negate(int64_t nn, const double *__restrict__ in, double *__restrict__ out) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nn; t += (int64_t)gridDim.x * blockDim.x)
+        out[t] = -in[t];
 }
 
 inline unsigned grid_for(int64_t n, int b = 256) {
@@ -877,6 +921,28 @@ void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const st
     } else {
         S.rowmap.release();
     }
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void dev_dense_inverse_spd(const std::vector<double> &M, int n, DBuf<double> &inv, hipStream_t s) {
+    const int64_t nn = (int64_t)n * n;
+    TE_REQUIRE((int64_t)M.size() == nn && n > 0, TE_EINVAL, "dense inverse: bad size");
+    DBuf<double> a, b;
+    upload(a, M, s);
+    b.alloc(nn);
+    DBuf<int32_t> bad(1);
+    TE_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    const unsigned g = grid_for(nn);
+    const dim3 gs((n + 255) / 256, std::min(n, 4096));
+    for (int j = 0; j < n; ++j) {
+        hipLaunchKernelGGL(k_sweep, gs, dim3(256), 0, s, n, j, a.p, b.p, bad.p);
+        std::swap(a.p, b.p);
+    }
+    TE_CHECK_HIP(hipGetLastError());
+    TE_REQUIRE(read_flag(bad, s) == 0, TE_ECHOL, "coarse factor: a pivot of the coarsest operator is not positive");
+    inv.alloc(nn);
+    hipLaunchKernelGGL(k_negate, dim3(g), dim3(256), 0, s, nn, a.p, inv.p);
+    TE_CHECK_HIP(hipGetLastError());
     TE_CHECK_HIP(hipStreamSynchronize(s));
 }
 

@@ -72,3 +72,38 @@ def test_multi_mesh_matches_oracle_and_zero_rhs():
         err = np.linalg.norm(us[i].cpu().numpy() - res.u) / np.linalg.norm(res.u)
         say(f"oracle mesh {i}: iters multi {rep['iters'][i]} oracle {res.iters} diff {err:.1e}")
         assert err <= 1e-8
+
+
+def test_symmetric_coarse_storage_in_block_and_multi_mesh_solves():
+    """coarse_sym = 1 takes the lower-block paths of the several-RHS product
+    and of the grouped multi-mesh kernels: both give the solves of the full
+    storage to rounding (same iteration counts +-1, 1e-10 / 1e-6 relative)."""
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    probs = [mg.disc_problem(6, 26, 2, 1, seed=4), mg.disc_problem(10, 40, 2, 1, seed=5)]
+    hs_s, hs_f, bs = [], [], []
+    for i, p in enumerate(probs):
+        p.T = mg.disc_temperature_bumps(p.mesh, 3000 + i)
+        A, b, d = gpu_assemble(p)
+        hs_s.append(te.AMG(A, d["coords"], d["mask"], coarse_max=400, coarse_sym=1, max_nrhs=4))
+        hs_f.append(te.AMG(A, d["coords"], d["mask"], coarse_max=400, coarse_sym=0, max_nrhs=4))
+        bs.append(b)
+    assert min(h.info()["n_levels"] for h in hs_s) >= 2
+
+    def close(a, b, it_a, it_b):
+        assert abs(it_a - it_b) <= 1
+        tol = 1e-10 if it_a == it_b else 1e-6
+        assert float(((a - b).norm() / b.norm()).cpu()) <= tol
+
+    # several right-hand sides: b, 2b, -b on mesh 0
+    B = torch.stack([bs[0], 2 * bs[0], -bs[0]], dim=-1).reshape(-1, 3, 3).contiguous()
+    Us, rs = hs_s[0].solve(B)
+    Uf, rf = hs_f[0].solve(B)
+    for j in range(3):
+        close(Us[:, :, j], Uf[:, :, j], rs.iters[j], rf.iters[j])
+    # both meshes in one multi-mesh solve
+    us, reps = te.solve_multi(hs_s, bs)
+    uf, repf = te.solve_multi(hs_f, bs)
+    assert all(reps["converged"]) and all(repf["converged"])
+    for i in range(2):
+        close(us[i], uf[i], reps["iters"][i], repf["iters"][i])
