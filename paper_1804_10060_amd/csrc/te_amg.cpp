@@ -871,7 +871,8 @@ static void unpack_values(const Level &L, std::vector<double> &val) {
             const int64_t sl = r / SELL_C, ln = r % SELL_C;
             for (int64_t k = 0; k < len; ++k)
                 for (int x = 0; x < bb; ++x)
-                    val[(size_t)(d0 + k) * bb + x] = sv[(size_t)(((int64_t)off[sl] + k) * bb + x) * SELL_C + ln];
+                    val[(size_t)(d0 + k) * bb + x] =
+                        sv[(size_t)(((int64_t)off[sl] + k) * bb * SELL_C + sell_val_off<sell_vw<double>()>(x, bb, (int)ln))];
         }
     }
 }

@@ -71,23 +71,44 @@ inline SellView<VT> view(const Sell &S, const VT *val) {
 // Single right-hand side: lane = block row.  Epi::apply(row_out, acc, red)
 // consumes the BR accumulated entries and may add to `red` (block-reduced
 // into partials[logical block] when Epi::kReduce).
+// The BR*BC values of one lane's block at slot k (layout of sell_val_off):
+// 16-byte loads for the groups, single loads for the remainder.
+template <int BR, int BC, typename VT, bool NT>
+__device__ __forceinline__ void sell1_block(const VT *__restrict__ vp, int k, int lane, VT *v) {
+    constexpr int E = BR * BC, VW = sell_vw<VT>(), G = E / VW;
+    typedef VT vec_t __attribute__((ext_vector_type(VW)));
+    const VT *vk = vp + (int64_t)k * (E * WAVE);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const vec_t *q = reinterpret_cast<const vec_t *>(vk + (int64_t)(g * WAVE + lane) * VW);
+        vec_t t;
+        if constexpr (NT) t = __builtin_nontemporal_load(q);
+        else t = *q;
+#pragma unroll
+        for (int u = 0; u < VW; ++u) v[g * VW + u] = t[u];
+    }
+#pragma unroll
+    for (int e = G * VW; e < E; ++e) v[e] = ld_val<NT>(&vk[(int64_t)G * VW * WAVE + (e - G * VW) * WAVE + lane]);
+}
+
 template <int BR, int BC, typename VT, typename XT, typename AT, bool NT>
-__device__ __forceinline__ void sell1_entry_c(int64_t c, const VT *__restrict__ vp, int k, const XT *__restrict__ x,
-                                              AT *acc) {
+__device__ __forceinline__ void sell1_entry_c(int64_t c, const VT *__restrict__ vp, int k, int lane,
+                                              const XT *__restrict__ x, AT *acc) {
     AT xv[BC];
 #pragma unroll
     for (int j = 0; j < BC; ++j) xv[j] = AT(x[c * BC + j]);
-    const VT *vk = vp + (int64_t)k * (BR * BC * WAVE);
+    VT v[BR * BC];
+    sell1_block<BR, BC, VT, NT>(vp, k, lane, v);
 #pragma unroll
     for (int i = 0; i < BR; ++i)
 #pragma unroll
-        for (int j = 0; j < BC; ++j) acc[i] += AT(ld_val<NT>(&vk[(i * BC + j) * WAVE])) * xv[j];
+        for (int j = 0; j < BC; ++j) acc[i] += AT(v[i * BC + j]) * xv[j];
 }
 
 template <int BR, int BC, typename VT, typename XT, typename AT, bool NT>
 __device__ __forceinline__ void sell1_entry(const int32_t *__restrict__ cp, const VT *__restrict__ vp, int k,
-                                            const XT *__restrict__ x, AT *acc) {
-    sell1_entry_c<BR, BC, VT, XT, AT, NT>(cp[(int64_t)k * WAVE], vp, k, x, acc);
+                                            int lane, const XT *__restrict__ x, AT *acc) {
+    sell1_entry_c<BR, BC, VT, XT, AT, NT>(cp[(int64_t)k * WAVE], vp, k, lane, x, acc);
 }
 
 // One slice, lane = row.  Rows of a slice are sorted by descending length,
@@ -106,14 +127,14 @@ __device__ __forceinline__ void sell1_body(const SellView<VT> &A, const XT *__re
 #pragma unroll
     for (int i = 0; i < BR; ++i) acc[i] = AT(0);
     const int32_t *cp = A.col + (int64_t)off * WAVE + lane;
-    const VT *vp = A.val + (int64_t)off * (BR * BC * WAVE) + lane;
+    const VT *vp = A.val + (int64_t)off * (BR * BC * WAVE);
     int k = 0;
     for (; k + 1 < kmin; k += 2) {
-        sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k, x, acc);
-        sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k + 1, x, acc);
+        sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k, lane, x, acc);
+        sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k + 1, lane, x, acc);
     }
     for (; k < w; ++k)
-        if (k < len) sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k, x, acc);
+        if (k < len) sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k, lane, x, acc);
     if (row < A.nrows) {
         const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
         epi.template apply<BR>(out, acc, red);

@@ -122,9 +122,23 @@ struct HBsr {
 // the (permuted) row order.  Entry k of every lane of a slice is stored
 // contiguously across lanes:
 //   col[(off_s + k) * 64 + lane]
-//   val[((off_s + k) * br*bc + e) * 64 + lane]        e = i*bc + j
-// Padding entries carry a zero block and a valid column.
+//   val[(off_s + k) * br*bc * 64 + sell_val_off<VW>(e, br*bc, lane)]   e = i*bc + j
+// The E = br*bc values of a block go in groups of VW = 16 / sizeof(value)
+// consecutive entries, one 16-byte piece per lane, the pieces of the 64
+// lanes contiguous; the E % VW remaining entries take one plane of 64 values
+// each.  A lane thus reads its block with 16-byte loads.  Padding entries
+// carry a zero block and a valid column.
 constexpr int SELL_C = 64;
+
+template <int VW>
+__host__ __device__ __forceinline__ constexpr int64_t sell_val_off(int e, int E, int lane) {
+    return e < E / VW * VW ? ((int64_t)(e / VW) * SELL_C + lane) * VW + e % VW
+                           : (int64_t)(E / VW * VW) * SELL_C + (int64_t)(e - E / VW * VW) * SELL_C + lane;
+}
+template <typename VT>
+constexpr int sell_vw() {
+    return 16 / (int)sizeof(VT);
+}
 
 // Second layout for operators whose rows are few and long (6-row blocks:
 // coarse operators and the restrictions): format 1 stores the blocks of a row

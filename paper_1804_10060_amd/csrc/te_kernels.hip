@@ -64,14 +64,15 @@ __global__ void __launch_bounds__(BLK) k_sellm(SellView<VT> A, const XT *__restr
             for (int k = 0; k < len; ++k) {
                 const int64_t e = (int64_t)(off + k) * WAVE + rl;
                 const int64_t c = A.col[e];
-                const VT *vk = A.val + (int64_t)(off + k) * (BR * BC * WAVE) + rl;
+                const VT *vk = A.val + (int64_t)(off + k) * (BR * BC * WAVE);
                 AT xv[BC];
 #pragma unroll
                 for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
 #pragma unroll
                 for (int i = 0; i < BR; ++i)
 #pragma unroll
-                    for (int j = 0; j < BC; ++j) acc[i] += AT(vk[(i * BC + j) * WAVE]) * xv[j];
+                    for (int j = 0; j < BC; ++j)
+                        acc[i] += AT(vk[sell_val_off<sell_vw<VT>()>(i * BC + j, BR * BC, rl)]) * xv[j];
             }
             const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
             epi.template apply_m<BR>(out, lane, nrhs, acc, red);

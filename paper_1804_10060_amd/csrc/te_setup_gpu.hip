@@ -461,9 +461,9 @@ __global__ void k_pack_sell(int64_t nr, int bb, const int64_t *__restrict__ ptr,
             scol[(o0 + k) * 64 + l] = last;
             for (int x = 0; x < bb; ++x) {
                 const double v = k < len ? val[(s0 + k) * bb + x] : 0.0;
-                const int64_t e = ((o0 + k) * bb + x) * 64 + l;
-                sval[e] = v;
-                if (sval32) sval32[e] = (float)v;
+                const int64_t e0 = (o0 + k) * bb * 64;
+                sval[e0 + sell_val_off<sell_vw<double>()>(x, bb, (int)l)] = v;
+                if (sval32) sval32[e0 + sell_val_off<sell_vw<float>()>(x, bb, (int)l)] = (float)v;
             }
         }
     }
