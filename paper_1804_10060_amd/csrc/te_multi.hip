@@ -52,7 +52,7 @@ void upload_items(Phase &P, const std::vector<Item> &items, const std::vector<in
 
 inline int64_t tiles_of(const Sell &A) {
     const int64_t units = A.format == FMT_SELL ? A.nslices : A.nrows;
-    return (units + WPB - 1) / WPB;
+    return (units + GW - 1) / GW;
 }
 
 template <class Epi>
@@ -151,7 +151,8 @@ void run(const Phase &P, const int32_t *active, double *partials, hipStream_t s)
 }
 
 void reduce(const Phase &P, int nv, double *partials, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_group_reduce, dim3(1), dim3(64), 0, s, partials, P.tile0.p, P.nitems, P.mesh_of.p, nv, out);
+    hipLaunchKernelGGL(k_group_reduce, dim3(P.nitems, nv), dim3(WAVE), 0, s, partials, P.tile0.p, P.mesh_of.p, nv,
+                       out);
     TE_CHECK_HIP(hipGetLastError());
 }
 

@@ -10,6 +10,11 @@
 
 namespace te {
 
+// Waves per workgroup of the grouped sparse products: one, so a tile is one
+// slice (lane-per-row items) or one row (one-wave-per-row items).
+constexpr int GW = 1;
+constexpr int GBLK = GW * WAVE;
+
 template <typename T, class Epi>
 struct GItem {
     SellView<T> sv;
@@ -21,11 +26,11 @@ struct GItem {
 };
 
 template <int BR, int BC, typename T, class Epi>
-__global__ void __launch_bounds__(BLK) k_group(const GItem<T, Epi> *__restrict__ items,
-                                               const int64_t *__restrict__ tile0, int nitems,
-                                               const int32_t *__restrict__ active, double *__restrict__ partials) {
-    __shared__ double lds[WPB];
-    __shared__ T wb[BLK];
+__global__ void __launch_bounds__(GBLK) k_group(const GItem<T, Epi> *__restrict__ items,
+                                                const int64_t *__restrict__ tile0, int nitems,
+                                                const int32_t *__restrict__ active, double *__restrict__ partials) {
+    __shared__ double lds[GW];
+    __shared__ T wb[GBLK];
     const int64_t ntiles = tile0[nitems];
     const int64_t nb = gridDim.x, lb = xcd_logical_block(blockIdx.x, nb);
     const int64_t t_lo = ntiles * lb / nb, t_hi = ntiles * (lb + 1) / nb;
@@ -43,11 +48,12 @@ __global__ void __launch_bounds__(BLK) k_group(const GItem<T, Epi> *__restrict__
     for (int64_t t = t_lo; t < t_hi; ++t) {
         while (it + 1 < nitems && tile0[it + 1] <= t) ++it;
         const GItem<T, Epi> &G = items[it];
-        const int64_t unit = (t - tile0[it]) * WPB + threadIdx.x / WAVE;
+        const int64_t unit = (t - tile0[it]) * GW + threadIdx.x / WAVE;
         double red = 0.0;
         if (active == nullptr || active[G.mesh]) {
             if (G.fmt == FMT_SELL) {
-                if (unit < G.sv.nslices) sell1_body<BR, BC, T, T, T, Epi>(G.sv, G.x, G.epi, unit, lane, red);
+                // the operator values are read once per product: non-temporal loads
+                if (unit < G.sv.nslices) sell1_body<BR, BC, T, T, T, Epi, true>(G.sv, G.x, G.epi, unit, lane, red);
             } else {
                 if (unit < G.rv.nrows)
                     roww_body<BR, BC, T, T, T, Epi>(G.rv, G.x, G.epi, unit, lane, red,
@@ -137,15 +143,17 @@ __global__ void __launch_bounds__(BLK) k_group_vec(const VItem *__restrict__ ite
     }
 }
 
-// per-item sums of tile partials (fixed order), out[mesh * nv + v]
-__global__ void k_group_reduce(const double *__restrict__ partials, const int64_t *__restrict__ tile0, int nitems,
-                               const int32_t *__restrict__ mesh_of, int nv, double *__restrict__ out) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nitems; i += gridDim.x * blockDim.x)
-        for (int v = 0; v < nv; ++v) {
-            double s = 0.0;
-            for (int64_t t = tile0[i]; t < tile0[i + 1]; ++t) s += partials[t * nv + v];
-            out[mesh_of[i] * nv + v] = s;
-        }
+// per-item sums of tile partials, out[mesh * nv + v]: one wave per (item, v),
+// lane l adds tiles l, l+64, ... in order, then a fixed shuffle tree
+__global__ void __launch_bounds__(WAVE) k_group_reduce(const double *__restrict__ partials,
+                                                       const int64_t *__restrict__ tile0,
+                                                       const int32_t *__restrict__ mesh_of, int nv,
+                                                       double *__restrict__ out) {
+    const int i = blockIdx.x, v = blockIdx.y, lane = threadIdx.x;
+    double s = 0.0;
+    for (int64_t t = tile0[i] + lane; t < tile0[i + 1]; t += WAVE) s += partials[t * nv + v];
+    s = wave_sum(s);
+    if (lane == 0) out[mesh_of[i] * nv + v] = s;
 }
 
 // dense coarse solves of several meshes: y = Ainv x, one wave per row
@@ -233,12 +241,24 @@ __global__ void k_multi_beta(MultiScal S, const int32_t *__restrict__ mask, cons
 // ---- launchers -------------------------------------------------------------
 constexpr int GROUP_GRID = 2048;
 
+// Workgroups of a kernel resident on the whole device at once (the grid of a
+// persistent launch); queried once per kernel.
+template <class K>
+int64_t resident_groups(K kernel, int threads) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    TE_CHECK_HIP(hipGetDevice(&dev));
+    TE_CHECK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    TE_CHECK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+    return std::max<int64_t>(1, (int64_t)ncu * std::max(per_cu, 1));
+}
+
 template <int BR, int BC, class Epi>
 void group_launch(const void *items, const int64_t *tile0, int nitems, int64_t ntiles, const int32_t *active,
                   double *partials, hipStream_t s) {
     if (nitems == 0 || ntiles == 0) return;
-    const unsigned g = (unsigned)std::min<int64_t>(ntiles, GROUP_GRID);
-    hipLaunchKernelGGL((k_group<BR, BC, double, Epi>), dim3(g), dim3(BLK), 0, s,
+    static const int64_t cap = resident_groups(k_group<BR, BC, double, Epi>, GBLK);
+    const unsigned g = (unsigned)std::min<int64_t>(ntiles, cap);
+    hipLaunchKernelGGL((k_group<BR, BC, double, Epi>), dim3(g), dim3(GBLK), 0, s,
                        (const GItem<double, Epi> *)items, tile0, nitems, active, partials);
     TE_CHECK_HIP(hipGetLastError());
 }
