@@ -123,6 +123,10 @@ __device__ __forceinline__ void sell1_body(const SellView<VT> &A, const XT *__re
     const int w = A.slice_off[slice + 1] - off;
     const int len = A.rowlen[row];
     const int kmin = __builtin_amdgcn_readlane(len, WAVE - 1);
+    const bool real = row < A.nrows;
+    const int64_t out = real ? (A.rowmap ? (int64_t)A.rowmap[row] : row) : 0;
+    typename Epi::template Pre<BR> pre{};
+    if (real) pre = epi.template load<BR>(out);
     AT acc[BR];
 #pragma unroll
     for (int i = 0; i < BR; ++i) acc[i] = AT(0);
@@ -135,10 +139,7 @@ __device__ __forceinline__ void sell1_body(const SellView<VT> &A, const XT *__re
     }
     for (; k < w; ++k)
         if (k < len) sell1_entry<BR, BC, VT, XT, AT, NT>(cp, vp, k, lane, x, acc);
-    if (row < A.nrows) {
-        const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
-        epi.template apply<BR>(out, acc, red);
-    }
+    if (real) epi.template apply<BR>(out, acc, red, pre);
 }
 
 // One wave per stored row (format 1).  Lane = (block slot, row of the block):
@@ -217,14 +218,29 @@ __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__rest
 // ---------------------------------------------------------------------------
 // Epilogues
 // ---------------------------------------------------------------------------
+// Each epilogue reads its per-row vector inputs with load<BR>(row) and
+// finishes the row with apply<BR>(row, acc, red, pre).  The lane-per-row
+// product issues load before its entry loop, so those reads are in flight
+// while the operator streams instead of after it; apply(row, acc, red) does
+// both at the end.  Inputs that are only streamed are read non-temporally.
 template <typename T>
 struct EpiSet {  // y = A x
     static constexpr bool kReduce = false;
     T *y;
+    template <int BR>
+    struct Pre {};
+    template <int BR>
+    __device__ Pre<BR> load(int64_t) const {
+        return {};
+    }
     template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &) const {
+    __device__ void apply(int64_t r, AT *acc, double &, const Pre<BR> &) const {
 #pragma unroll
         for (int i = 0; i < BR; ++i) y[r * BR + i] = T(acc[i]);
+    }
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+        apply<BR>(r, acc, red, load<BR>(r));
     }
     template <int BR, typename AT>
     __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
@@ -237,10 +253,22 @@ template <typename T>
 struct EpiAdd {  // y += A x
     static constexpr bool kReduce = false;
     T *y;
+    // y is read after the entry loop: reading it early measured slower in the
+    // prolongation (3x6 blocks)
+    template <int BR>
+    struct Pre {};
+    template <int BR>
+    __device__ Pre<BR> load(int64_t) const {
+        return {};
+    }
     template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &) const {
+    __device__ void apply(int64_t r, AT *acc, double &, const Pre<BR> &) const {
 #pragma unroll
         for (int i = 0; i < BR; ++i) y[r * BR + i] = T(AT(y[r * BR + i]) + acc[i]);
+    }
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+        apply<BR>(r, acc, red, load<BR>(r));
     }
     template <int BR, typename AT>
     __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &) const {
@@ -257,14 +285,29 @@ struct EpiResid {  // y = g - A x  (optionally red += y^2)
     static constexpr bool kReduce = NORM;
     const T *g;
     T *y;
+    template <int BR>
+    struct Pre {
+        T g[BR];
+    };
+    template <int BR>
+    __device__ Pre<BR> load(int64_t r) const {
+        Pre<BR> p;
+#pragma unroll
+        for (int i = 0; i < BR; ++i) p.g[i] = ld_val<true>(&g[r * BR + i]);
+        return p;
+    }
     template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &red) const {
+    __device__ void apply(int64_t r, AT *acc, double &red, const Pre<BR> &p) const {
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
-            AT v = AT(g[r * BR + i]) - acc[i];
+            AT v = AT(p.g[i]) - acc[i];
             y[r * BR + i] = T(v);
             if (NORM) red += double(v) * double(v);
         }
+    }
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+        apply<BR>(r, acc, red, load<BR>(r));
     }
     template <int BR, typename AT>
     __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
@@ -282,13 +325,28 @@ struct EpiDot {  // q = A p, red += p.q   (float64 outer CG)
     static constexpr bool kReduce = true;
     const double *p;
     double *q;
+    template <int BR>
+    struct Pre {
+        double p[BR];
+    };
+    template <int BR>
+    __device__ Pre<BR> load(int64_t r) const {
+        Pre<BR> v;
+#pragma unroll
+        for (int i = 0; i < BR; ++i) v.p[i] = p[r * BR + i];
+        return v;
+    }
     template <int BR, typename AT>
-    __device__ void apply(int64_t r, AT *acc, double &red) const {
+    __device__ void apply(int64_t r, AT *acc, double &red, const Pre<BR> &v) const {
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             q[r * BR + i] = acc[i];
-            red += p[r * BR + i] * double(acc[i]);
+            red += v.p[i] * double(acc[i]);
         }
+    }
+    template <int BR, typename AT>
+    __device__ void apply(int64_t r, AT *acc, double &red) const {
+        apply<BR>(r, acc, red, load<BR>(r));
     }
     template <int BR, typename AT>
     __device__ void apply_m(int64_t r, int j, int m, AT *acc, double &red) const {
@@ -310,15 +368,33 @@ struct EpiChebInit {
     T *r;
     T *d;
     T inv_theta;
+    template <int BR>
+    struct Pre {
+        T g[BR], v[BR];
+    };
+    template <int BR>
+    __device__ Pre<BR> load(int64_t row) const {
+        Pre<BR> p;
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            p.g[i] = ld_val<true>(&g[row * BR + i]);
+            p.v[i] = ld_val<true>(&dinv[row * BR + i]);
+        }
+        return p;
+    }
     template <int BR, typename AT>
-    __device__ void apply(int64_t row, AT *acc, double &) const {
+    __device__ void apply(int64_t row, AT *acc, double &, const Pre<BR> &p) const {
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             int64_t q = row * BR + i;
-            T rv = T(AT(g[q]) - acc[i]);
+            T rv = T(AT(p.g[i]) - acc[i]);
             r[q] = rv;
-            d[q] = dinv[q] * rv * inv_theta;
+            d[q] = p.v[i] * rv * inv_theta;
         }
+    }
+    template <int BR, typename AT>
+    __device__ void apply(int64_t row, AT *acc, double &red) const {
+        apply<BR>(row, acc, red, load<BR>(row));
     }
     template <int BR, typename AT>
     __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
@@ -346,15 +422,32 @@ struct EpiChebStep {
     T *dout;
     T *x;
     T c1, c2;
+    template <int BR>
+    struct Pre {
+        T r[BR], d[BR], v[BR], x[BR];
+    };
+    template <int BR>
+    __device__ Pre<BR> load(int64_t row) const {
+        Pre<BR> p;
+#pragma unroll
+        for (int i = 0; i < BR; ++i) {
+            const int64_t q = row * BR + i;
+            p.r[i] = ld_val<true>(&rin[q]);
+            p.d[i] = d[q];
+            p.v[i] = ld_val<true>(&dinv[q]);
+            p.x[i] = XZERO ? T(0) : ld_val<true>(&x[q]);
+        }
+        return p;
+    }
     template <int BR, typename AT>
-    __device__ void apply(int64_t row, AT *acc, double &) const {
+    __device__ void apply(int64_t row, AT *acc, double &, const Pre<BR> &p) const {
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             int64_t q = row * BR + i;
-            T rn = T(AT(rin[q]) - acc[i]);
-            T dv = d[q];
-            T dn = c1 * dv + c2 * (dinv[q] * rn);
-            T xv = XZERO ? T(0) : x[q];
+            T rn = T(AT(p.r[i]) - acc[i]);
+            T dv = p.d[i];
+            T dn = c1 * dv + c2 * (p.v[i] * rn);
+            T xv = p.x[i];
             if (LAST) {
                 x[q] = xv + dv + dn;
             } else {
@@ -363,6 +456,10 @@ struct EpiChebStep {
                 x[q] = xv + dv;
             }
         }
+    }
+    template <int BR, typename AT>
+    __device__ void apply(int64_t row, AT *acc, double &red) const {
+        apply<BR>(row, acc, red, load<BR>(row));
     }
     template <int BR, typename AT>
     __device__ void apply_m(int64_t row, int j, int m, AT *acc, double &) const {
