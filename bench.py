@@ -92,7 +92,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision solve")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configurations")
-    ap.add_argument("--coarse-sym", type=int, default=0, choices=(0, 1),
+    ap.add_argument("--coarse-sym", type=int, default=1, choices=(0, 1),
                     help="store the coarse operators by their upper triangle (amg_options.coarse_sym)")
     args = ap.parse_args()
     if args.gpus != 1:

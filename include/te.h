@@ -128,9 +128,10 @@ typedef struct {
     int32_t build_fp32;      /* also keep float32 copies for TE_PREC_MIXED (1)         */
     int32_t host_threads;    /* host threads for the setup (0 = all)                    */
     int32_t max_nrhs;        /* largest nrhs a solve will use (1..64; 1)               */
-    int32_t coarse_sym;      /* store the coarse operators (6x6 blocks) by the blocks on
-                                and above the diagonal, the others read transposed from
-                                their mirror; only for a symmetric pattern (0)          */
+    int32_t coarse_sym;      /* store the float64 coarse operators (6x6 blocks) by the
+                                blocks on and above the diagonal, the others read
+                                transposed from their mirror (symmetric pattern only;
+                                float32 copies keep full storage) (1)                   */
 } amg_options;
 
 /* Fills the defaults listed above. */

@@ -543,6 +543,13 @@ static void finish_level(Level &L, const DBsr &D, const amg_options &o, DBuf<dou
     for (int64_t i = 0; i < L.n; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
     dev_pack(L.A, D, L.Ah.ptr, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.bs),
              (o.coarse_sym && L.bs == 6) ? &L.Ah.col : nullptr);
+    if (L.A.sym() && o.build_fp32) {
+        // the float32 V-cycle keeps full storage: its halved value stream does
+        // not pay for the gathered mirror blocks
+        dev_pack(L.A32, D, L.Ah.ptr, L.perm_h, L.iperm_h, nullptr, true, s, fmt_for(L.bs));
+        L.A32.val.release();
+        L.A.val32.release();
+    }
     upload(L.perm, L.perm_h, s);
     dev_diag(D, dnat, s);
     std::vector<double> dh;
@@ -897,7 +904,7 @@ extern "C" void amg_options_default(amg_options *o) {
     o->build_fp32 = 1;
     o->host_threads = 0;
     o->max_nrhs = 1;
-    o->coarse_sym = 0;
+    o->coarse_sym = 1;
 }
 
 extern "C" int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,
@@ -932,7 +939,8 @@ extern "C" int amg_get_info(const amg_handle *h, amg_info *info) {
             info->bs[l] = L.bs;
             info->lambda_hat[l] = L.lam;
             info->p_nnzb[l] = L.p_nnzb;
-            bytes += L.A.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() + L.perm.bytes();
+            bytes += L.A.bytes() + L.A32.bytes() + L.P.bytes() + L.R.bytes() + L.dinv.bytes() + L.dinv32.bytes() +
+                     L.perm.bytes();
         }
         info->setup_ms = h->setup_ms;
         info->bytes_device = bytes;

@@ -24,6 +24,7 @@ struct Level {
     std::vector<int32_t> iperm_h;  // natural index -> storage position
     std::vector<double> dstore;    // point diagonal in storage order
     Sell A, P, R;                  // device operators, storage numbering
+    Sell A32;                      // float32 operator in full storage when A keeps only its upper blocks
     DBuf<int32_t> perm;
     DBuf<double> dinv;
     DBuf<float> dinv32;
@@ -33,6 +34,14 @@ struct Level {
     Work<double> w64;
     Work<float> w32;
 };
+
+// The level operator a precision runs on: float32 work uses the full-storage
+// copy where the float64 operator is stored by its upper blocks.
+template <typename T>
+inline Sell &level_op(Level &L) {
+    if constexpr (sizeof(T) == 4) return L.A32.nrows ? L.A32 : L.A;
+    else return L.A;
+}
 
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &fn);
 int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,

@@ -51,7 +51,7 @@ static void cheb_chain(Level &L, const T *rin, T *x, bool xzero, int degree, int
     }
     for (int k = 0; k + 1 < degree; ++k) {
         const bool last = (k + 2 == degree);
-        cheb_step<T>(L.A, dc, rin, dinv, W.r.p, dn, x, L.c1[k], L.c2[k], last, xzero && k == 0, m, s);
+        cheb_step<T>(level_op<T>(L), dc, rin, dinv, W.r.p, dn, x, L.c1[k], L.c2[k], last, xzero && k == 0, m, s);
         rin = W.r.p;
         std::swap(dc, dn);
     }
@@ -61,7 +61,7 @@ static void cheb_chain(Level &L, const T *rin, T *x, bool xzero, int degree, int
 template <typename T>
 static void smooth_from(amg_handle *h, Level &L, const T *g, T *x, int m, hipStream_t s) {
     Work<T> &W = work<T>(L);
-    cheb_init<T>(L.A, x, g, dinv_of<T>(L), W.r.p, W.d.p, 1.0 / L.theta, m, s);
+    cheb_init<T>(level_op<T>(L), x, g, dinv_of<T>(L), W.r.p, W.d.p, 1.0 / L.theta, m, s);
     cheb_chain<T>(L, W.r.p, x, false, h->opt.cheb_degree, m, s);
 }
 
@@ -90,7 +90,7 @@ void vcycle(amg_handle *h, int l, const T *g, T *x, int m, hipStream_t s) {
     E(TE_K_PRE);
     // residual, restriction, coarse correction, prolongation
     B(TE_K_RESID);
-    sell_apply<T>(L.A, x, W.s.p, g, 2, m, s);
+    sell_apply<T>(level_op<T>(L), x, W.s.p, g, 2, m, s);
     E(TE_K_RESID);
     Level &N = h->L[l + 1];
     Work<T> &WN = work<T>(N);
@@ -105,7 +105,7 @@ void vcycle(amg_handle *h, int l, const T *g, T *x, int m, hipStream_t s) {
     E(TE_K_PROLONG);
     // post-smoothing from the corrected x
     B(TE_K_POSTINIT);
-    cheb_init<T>(L.A, x, g, dinv, W.r.p, W.d.p, 1.0 / L.theta, m, s);
+    cheb_init<T>(level_op<T>(L), x, g, dinv, W.r.p, W.d.p, 1.0 / L.theta, m, s);
     E(TE_K_POSTINIT);
     B(TE_K_POST);
     cheb_chain<T>(L, W.r.p, x, false, deg, m, s);
@@ -369,7 +369,7 @@ static int apply_impl(amg_handle *h, int l, int op, int prec, const double *x, d
                 to_f32(xs.p, x32, nl, s);
                 y32.alloc(nl);
                 if (op == TE_OP_SMOOTH) cast_f64_f32(ys.p, y32.p, nl, s);
-                if (op == TE_OP_A) sell_apply<float>(L.A, x32.p, y32.p, nullptr, 0, 1, s);
+                if (op == TE_OP_A) sell_apply<float>(level_op<float>(L), x32.p, y32.p, nullptr, 0, 1, s);
                 else if (op == TE_OP_SMOOTH) smooth_from<float>(h, L, x32.p, y32.p, 1, s);
                 else vcycle<float>(h, l, x32.p, y32.p, 1, s);
                 cast_f32_f64(y32.p, ys.p, nl, s);

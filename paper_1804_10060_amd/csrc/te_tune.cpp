@@ -131,7 +131,8 @@ int autotune_impl(amg_handle *h, const char *cache_path, int32_t use_cache, char
             tune_one<double>(L.R, L.R.tune64, "f64", L.w64.s.p, N.w64.g.p, cache, use_cache, s, e0, e1, rep);
         }
         if (h->opt.build_fp32) {
-            tune_one<float>(L.A, L.A.tune32, "f32", L.w32.d.p, L.w32.s.p, cache, use_cache, s, e0, e1, rep);
+            tune_one<float>(level_op<float>(L), level_op<float>(L).tune32, "f32", L.w32.d.p, L.w32.s.p, cache,
+                            use_cache, s, e0, e1, rep);
             if (next) {
                 Level &N = h->L[l + 1];
                 tune_one<float>(L.P, L.P.tune32, "f32", N.w32.x.p, L.w32.s.p, cache, use_cache, s, e0, e1, rep);

@@ -133,13 +133,14 @@ def test_imposed_aggregates_reproduce_hierarchy(disc_case):
 
 def test_coarse_symmetric_storage_matches_full(disc_case):
     """Coarse operators stored by their blocks on/above the diagonal
-    (coarse_sym = 1) against the full storage of the same hierarchy: level
-    matrices agree to the rounding asymmetry of the Galerkin product, products
-    and V-cycles to SPMV_TOL / 1e-10, and the solve takes the same iterations."""
+    (coarse_sym = 1, the default) against the full storage of the same
+    hierarchy: level matrices agree to the rounding asymmetry of the Galerkin
+    product, products and V-cycles to SPMV_TOL / 1e-10, and the solve takes
+    the same iterations."""
     import paper_1804_10060_amd as te
     torch = torch_cuda()
-    prob, A, b, B, levels, hf = disc_case
-    h = _gpu_amg_from_oracle_matrix(prob, A, coarse_max=400, coarse_sym=1)
+    prob, A, b, B, levels, h = disc_case
+    hf = _gpu_amg_from_oracle_matrix(prob, A, coarse_max=400, coarse_sym=0)
     assert h.opts.coarse_sym == 1 and hf.opts.coarse_sym == 0 and hf.info()["n_dof"] == h.info()["n_dof"]
     rng = np.random.default_rng(5)
     for l in range(1, h.info()["n_levels"]):
@@ -153,6 +154,11 @@ def test_coarse_symmetric_storage_matches_full(disc_case):
         yf = hf.apply(l, te.TE_OP_A, dev(x, torch.float64)).cpu().numpy()
         bound = abs(G) @ np.abs(x)
         assert np.all(np.abs(y - yf) <= 2 * SPMV_TOL * bound + 1e-300), f"A_{l} x"
+        # float32 work runs on a full-storage copy: the same float32 product
+        x32 = dev(x, torch.float64)
+        y32 = h.apply(l, te.TE_OP_A, x32, precision=te.TE_PREC_MIXED).cpu().numpy()
+        yf32 = hf.apply(l, te.TE_OP_A, x32, precision=te.TE_PREC_MIXED).cpu().numpy()
+        assert np.array_equal(y32, yf32), f"float32 A_{l} x"
     g = rng.normal(size=A.shape[0])
     z = h.apply(0, te.TE_OP_VCYCLE, dev(g, torch.float64)).cpu().numpy()
     zf = hf.apply(0, te.TE_OP_VCYCLE, dev(g, torch.float64)).cpu().numpy()
@@ -161,3 +167,10 @@ def test_coarse_symmetric_storage_matches_full(disc_case):
     uf, repf = hf.solve(dev(b, torch.float64))
     assert rep.iters == repf.iters
     assert float((u - uf).norm() / uf.norm()) <= 1e-8
+    # the float32 V-cycle runs on full storage in both hierarchies (its
+    # Chebyshev intervals come from float64 Lanczos runs, whose summation
+    # orders differ, hence not bit for bit)
+    um, repm = h.solve(dev(b, torch.float64), precision="mixed")
+    umf, repmf = hf.solve(dev(b, torch.float64), precision="mixed")
+    assert repm.iters == repmf.iters and repm.converged == [1]
+    assert float((um - umf).norm() / umf.norm()) <= 1e-8
