@@ -84,9 +84,35 @@ struct Prof {
 };
 }  // namespace te
 
+namespace te {
+// Executable graphs of the preconditioner of a solve, one per (precision,
+// number of right-hand sides); launch configurations are baked in, so the
+// autotuner clears them.  Captured on a stream of their own (the caller's
+// may be the null stream, which cannot be captured) and launched on the
+// caller's.
+struct GraphSet {
+    std::vector<std::pair<int, hipGraphExec_t>> g;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t find(int key) const {
+        for (const auto &e : g)
+            if (e.first == key) return e.second;
+        return nullptr;
+    }
+    void clear() {
+        for (auto &e : g) (void)hipGraphExecDestroy(e.second);
+        g.clear();
+    }
+    ~GraphSet() {
+        clear();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+}  // namespace te
+
 struct amg_handle {
     amg_options opt;
     te::Prof prof;
+    te::GraphSet vgraphs;
     std::vector<te::Level> L;
     te::DBuf<double> Ainv;         // coarsest level: dense inverse, storage order
     int nc = 0;

@@ -113,7 +113,7 @@ void vcycle(amg_handle *h, int l, const T *g, T *x, int m, hipStream_t s) {
 }
 
 // z = M^-1 r on level 0 (float64 in and out)
-static void precondition(amg_handle *h, const double *r, double *z, int m, bool mixed, hipStream_t s) {
+static void precondition_body(amg_handle *h, const double *r, double *z, int m, bool mixed, hipStream_t s) {
     Level &L0 = h->L[0];
     const int64_t nv = L0.n * 3 * m;
     if (!mixed) {
@@ -127,6 +127,38 @@ static void precondition(amg_handle *h, const double *r, double *z, int m, bool 
     h->prof.begin(TE_K_VECTOR);
     cast_f32_f64(L0.w32.x.p, z, nv, s);
     h->prof.end(TE_K_VECTOR);
+}
+
+// The preconditioner of a solve (r and z are the handle's own vectors) is a
+// fixed sequence of launches: captured once per (precision, nrhs) as a HIP
+// graph and replayed, which removes the host launch cost of its many small
+// kernels on small meshes.  Profiled solves launch the kernels directly.
+static void precondition(amg_handle *h, const double *r, double *z, int m, bool mixed, hipStream_t s) {
+    if (h->prof.on) {
+        precondition_body(h, r, z, m, mixed, s);
+        return;
+    }
+    const int key = (mixed ? 1000 : 0) + m;
+    hipGraphExec_t x = h->vgraphs.find(key);
+    if (!x) {
+        if (!h->vgraphs.cap) TE_CHECK_HIP(hipStreamCreateWithFlags(&h->vgraphs.cap, hipStreamNonBlocking));
+        hipStream_t c = h->vgraphs.cap;
+        hipGraph_t g = nullptr;
+        TE_CHECK_HIP(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+        try {
+            precondition_body(h, r, z, m, mixed, c);
+        } catch (...) {
+            (void)hipStreamEndCapture(c, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        TE_CHECK_HIP(hipStreamEndCapture(c, &g));
+        const hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        TE_CHECK_HIP(e);
+        h->vgraphs.g.emplace_back(key, x);
+    }
+    TE_CHECK_HIP(hipGraphLaunch(x, s));
 }
 
 struct HostScal {

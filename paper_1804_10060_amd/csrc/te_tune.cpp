@@ -116,6 +116,7 @@ void tune_one(Sell &A, Tune &slot, const char *dtype, const T *x, T *y, std::map
 int autotune_impl(amg_handle *h, const char *cache_path, int32_t use_cache, char *report_out, int64_t report_len,
                   hipStream_t s) {
     TE_REQUIRE(h, TE_EINVAL, "NULL handle");
+    h->vgraphs.clear();  // their launches use the configurations about to change
     auto cache = read_cache(use_cache ? cache_path : nullptr);
     hipEvent_t e0, e1;
     TE_CHECK_HIP(hipEventCreate(&e0));

@@ -98,6 +98,34 @@ def test_multiple_rhs_equal_single_solves():
         assert np.linalg.norm(U[:, :, j].reshape(-1) - uj) <= tol * np.linalg.norm(uj)
 
 
+def test_graph_replayed_preconditioner_equals_direct_launches():
+    """The preconditioner of a solve is captured once per (precision, nrhs)
+    and replayed; a profiled solve launches the same kernels directly.
+    Repeated solves on one handle (other work between them) must agree bit for
+    bit with the direct ones, in float64, mixed precision and with several
+    right-hand sides; a retune drops the graphs, and the recaptured ones agree
+    with direct launches under the new configuration (which may group the
+    CG dot partial sums differently, hence its own reference)."""
+    torch = torch_cuda()
+    prob = mg.disc_problem(8, 34, 2, 2, seed=5)
+    import paper_1804_10060_amd as te
+    A, b, d = gpu_assemble(prob)
+    h = te.AMG(A, d["coords"], d["mask"], coarse_max=400, max_nrhs=3)
+    B = torch.stack([b, 2.0 * b, torch.roll(b, 3)], dim=1).reshape(-1, 3, 3).contiguous()
+    for tuned in (False, True):
+        if tuned:
+            h.autotune(use_cache=False)
+        for precision in ("fp64", "mixed"):
+            ref, rref = h.solve(b, precision=precision, profile=True)
+            refm, rrefm = h.solve(B, precision=precision, profile=True)
+            for k in range(2):
+                u, rep = h.solve(b, precision=precision)
+                assert rep.iters == rref.iters and torch.equal(u, ref), (tuned, precision, k)
+                um, repm = h.solve(B, precision=precision)
+                assert repm.iters == rrefm.iters and torch.equal(um, refm), (tuned, precision, k)
+    say("graph replays equal direct launches")
+
+
 def test_edge_cases_zero_rhs_exact_guess_single_level():
     import paper_1804_10060_amd as te
     torch = torch_cuda()
