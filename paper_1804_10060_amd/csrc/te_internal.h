@@ -219,6 +219,9 @@ void permute_scatter(const double *src, double *dst, const int32_t *map, int64_t
                      hipStream_t s);  // dst[map[i]] = src[i]
 int dot_nblocks(int64_t n);
 void dot_partials(const double *a, const double *b, int64_t n, int nrhs, double *partials, hipStream_t s);
+// out[j] = sum over b of partials[b*nrhs + j], in a fixed order.  Above 4096
+// parts the sum takes two passes whose chunk sums are written after the
+// input: the buffer must then hold (nparts + min(1024, nparts/64)) * nrhs.
 void reduce_partials(const double *partials, int nparts, int nrhs, double *out, hipStream_t s);
 void reduce_pairs(const double *partials, int nparts, int nrhs, double *out, hipStream_t s);
 void cg_update(double *u, double *r, double *r_old, const double *p, const double *q, const double *alpha,

@@ -15,9 +15,12 @@
 //
 // Epilogues fuse the vector work of the Chebyshev smoother (Saad, Alg. 12.1),
 // the residual of the V-cycle and the dot products of CG into the product.
-// All reductions are two-pass and deterministic: per-block partials in a
-// fixed order, then one block sums them in a fixed order.
+// All reductions are deterministic: per-block partials in a fixed order,
+// then summed in a fixed order (by one workgroup, or, for large partial
+// tables, by fixed chunks and then the chunk sums).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "te_dev.h"
 
@@ -435,7 +438,51 @@ __global__ void k_reduce_partials(const double *__restrict__ partials, int npart
         __syncthreads();
     }
 }
+// Many partials (one per workgroup of a sparse product): two passes.  Pass 1:
+// workgroup g sums rows [g*chunk, (g+1)*chunk) of the [nparts][ncols] table,
+// thread (row offset, column) with coalesced reads, then the row offsets in
+// order; pass 2: one thread per column adds the G chunk sums in order.
+constexpr int REDUCE_ONE_PASS = 4096;
+__global__ void __launch_bounds__(BLK) k_reduce_cols1(const double *__restrict__ partials, int nparts, int ncols,
+                                                      int chunk, double *__restrict__ out2) {
+    __shared__ double lds[BLK];
+    const int R = BLK / ncols;  // rows per pass
+    const int r = threadIdx.x / ncols, c = threadIdx.x % ncols;
+    const int lo = blockIdx.x * chunk, hi = min(nparts, lo + chunk);
+    double t = 0.0;
+    if (r < R)
+        for (int b = lo + r; b < hi; b += R) t += partials[(int64_t)b * ncols + c];
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    if ((int)threadIdx.x < ncols) {
+        double u = 0.0;
+        for (int k = 0; k < R; ++k) u += lds[k * ncols + threadIdx.x];
+        out2[(int64_t)blockIdx.x * ncols + threadIdx.x] = u;
+    }
+}
+__global__ void __launch_bounds__(BLK) k_reduce_cols2(const double *__restrict__ out2, int G, int ncols,
+                                                      double *__restrict__ out) {
+    for (int c = threadIdx.x; c < ncols; c += BLK) {
+        double u = 0.0;
+        for (int g = 0; g < G; ++g) u += out2[(int64_t)g * ncols + c];
+        out[c] = u;
+    }
+}
+static void reduce_cols(const double *partials, int nparts, int ncols, double *out, hipStream_t s) {
+    TE_REQUIRE(ncols >= 1 && ncols <= BLK, TE_EINVAL, "reduction over %d columns", ncols);
+    const int G = std::min(1024, std::max(1, nparts / 64));
+    const int chunk = (nparts + G - 1) / G;
+    double *out2 = const_cast<double *>(partials) + (int64_t)nparts * ncols;
+    hipLaunchKernelGGL(k_reduce_cols1, dim3(G), dim3(BLK), 0, s, partials, nparts, ncols, chunk, out2);
+    hipLaunchKernelGGL(k_reduce_cols2, dim3(1), dim3(BLK), 0, s, out2, G, ncols, out);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
 void reduce_partials(const double *partials, int nparts, int nrhs, double *out, hipStream_t s) {
+    if (nparts > REDUCE_ONE_PASS) {
+        reduce_cols(partials, nparts, nrhs, out, s);
+        return;
+    }
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(BLK), 0, s, partials, nparts, nrhs, out);
     TE_CHECK_HIP(hipGetLastError());
 }
@@ -623,6 +670,10 @@ void cg_rz0(void *S, const double *rzf, int nrhs, hipStream_t s) {
     TE_CHECK_HIP(hipGetLastError());
 }
 void reduce_pairs(const double *partials, int nparts, int nrhs, double *out, hipStream_t s) {
+    if (nparts > REDUCE_ONE_PASS) {
+        reduce_cols(partials, nparts, 2 * nrhs, out, s);
+        return;
+    }
     hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(BLK), 0, s, partials, nparts, nrhs, out);
     TE_CHECK_HIP(hipGetLastError());
 }
