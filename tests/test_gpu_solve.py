@@ -70,10 +70,14 @@ def test_mixed_precision_reaches_fp64_accuracy():
     assert rep.iters[0] <= res.iters + 3
 
 
-def test_multiple_rhs_equal_single_solves():
+@pytest.mark.parametrize("grid", [(6, 26, 2), (40, 120, 3)])
+def test_multiple_rhs_equal_single_solves(grid):
+    """Each column of a block solve against its single solve.  The larger
+    disc (19,680 nodes) has more than 4096 partial sums per column in its
+    products, so the two-pass reduction of the partial tables is used."""
     import paper_1804_10060_amd as te
     torch = torch_cuda()
-    prob = mg.disc_problem(6, 26, 2, 1, seed=1)
+    prob = mg.disc_problem(*grid, 1, seed=1)
     m = prob.mesh
     Ts = np.stack([mg.disc_temperature_bumps(m, s) for s in range(1000, 1005)])
     d_coords = dev(m.coords, torch.float64)
