@@ -381,16 +381,25 @@ int multi_impl(amg_handle **hs, int n, const double *const *b, double *const *u,
     for (int m = 0; m < n; ++m)
         for (size_t l = 1; l < hs[m]->L.size(); ++l)
             TE_REQUIRE(hs[m]->L[l].bs == 6, TE_EINVAL, "unexpected coarse block size");
-    hipStream_t s;
-    TE_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    // private stream and events; on every exit, errors included, the
+    // caller's stream is made to wait for the private stream's work before
+    // both are released
     struct StreamGuard {
-        hipStream_t s;
-        ~StreamGuard() { (void)hipStreamDestroy(s); }
-    } sg{s};
-    hipEvent_t ev0, ev1, evj;
-    TE_CHECK_HIP(hipEventCreate(&ev0));
-    TE_CHECK_HIP(hipEventCreate(&ev1));
-    TE_CHECK_HIP(hipEventCreateWithFlags(&evj, hipEventDisableTiming));
+        hipStream_t user, s = nullptr;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr, evj = nullptr;
+        ~StreamGuard() {
+            if (s && evj && hipEventRecord(evj, s) == hipSuccess) (void)hipStreamWaitEvent(user, evj, 0);
+            for (hipEvent_t e : {ev0, ev1, evj})
+                if (e) (void)hipEventDestroy(e);
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } sg{user};
+    TE_CHECK_HIP(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+    TE_CHECK_HIP(hipEventCreate(&sg.ev0));
+    TE_CHECK_HIP(hipEventCreate(&sg.ev1));
+    TE_CHECK_HIP(hipEventCreateWithFlags(&sg.evj, hipEventDisableTiming));
+    hipStream_t s = sg.s;
+    hipEvent_t ev0 = sg.ev0, ev1 = sg.ev1, evj = sg.evj;
     TE_CHECK_HIP(hipEventRecord(evj, user));
     TE_CHECK_HIP(hipStreamWaitEvent(s, evj, 0));
     TE_CHECK_HIP(hipEventRecord(ev0, s));
@@ -552,11 +561,6 @@ int multi_impl(amg_handle **hs, int n, const double *const *b, double *const *u,
     TE_CHECK_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     TE_CHECK_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    TE_CHECK_HIP(hipEventRecord(evj, s));
-    TE_CHECK_HIP(hipStreamWaitEvent(user, evj, 0));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    (void)hipEventDestroy(evj);
     bool all = true;
     for (int m = 0; m < n; ++m) {
         const double rel = bbh[m] > 0 ? std::sqrt(trh[m] / bbh[m]) : 0.0;

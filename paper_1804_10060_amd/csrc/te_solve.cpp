@@ -189,9 +189,16 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
     double *part = h->partials.p, *sums = h->sums.p;
 
     h->prof.reset(o.profile != 0, s);
-    hipEvent_t e0, e1;
-    TE_CHECK_HIP(hipEventCreate(&e0));
-    TE_CHECK_HIP(hipEventCreate(&e1));
+    struct Events {  // released on every exit, errors included
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    TE_CHECK_HIP(hipEventCreate(&ev.a));
+    TE_CHECK_HIP(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     TE_CHECK_HIP(hipEventRecord(e0, s));
 
     permute_gather(b_nat, h->b.p, L0.perm.p, n, 3, m, s);
@@ -330,8 +337,6 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
     fetch(sums, m, tr, s);
     float ms = 0.f;
     TE_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     bool all_conv = true;
     int maxit_seen = 0;
     for (int j = 0; j < m; ++j) {

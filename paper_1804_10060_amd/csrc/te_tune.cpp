@@ -118,9 +118,16 @@ int autotune_impl(amg_handle *h, const char *cache_path, int32_t use_cache, char
     TE_REQUIRE(h, TE_EINVAL, "NULL handle");
     h->vgraphs.clear();  // their launches use the configurations about to change
     auto cache = read_cache(use_cache ? cache_path : nullptr);
-    hipEvent_t e0, e1;
-    TE_CHECK_HIP(hipEventCreate(&e0));
-    TE_CHECK_HIP(hipEventCreate(&e1));
+    struct Events {  // released on every exit, errors included
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    TE_CHECK_HIP(hipEventCreate(&ev.a));
+    TE_CHECK_HIP(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     std::string rep;
     for (size_t l = 0; l < h->L.size(); ++l) {
         Level &L = h->L[l];
@@ -141,8 +148,6 @@ int autotune_impl(amg_handle *h, const char *cache_path, int32_t use_cache, char
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     // the work vectors held timing garbage: nothing reads them before writing
     if (cache_path) write_cache(cache_path, cache);
     if (report_out && report_len > 0) {
