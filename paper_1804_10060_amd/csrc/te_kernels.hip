@@ -63,20 +63,28 @@ __global__ void __launch_bounds__(BLK) k_sellm(SellView<VT> A, const XT *__restr
         AT acc[BR];
 #pragma unroll
         for (int i = 0; i < BR; ++i) acc[i] = AT(0);
-        if (lane < nrhs) {
-            for (int k = 0; k < len; ++k) {
-                const int64_t e = (int64_t)(off + k) * WAVE + rl;
-                const int64_t c = A.col[e];
-                const VT *vk = A.val + (int64_t)(off + k) * (BR * BC * WAVE);
-                AT xv[BC];
+        // up to 64 column indices of the row in one load (lane u holds entry
+        // k0 + u, every lane active), then taken one by one with readlane: the
+        // x loads of an entry depend on no load of its own
+        for (int k0 = 0; k0 < len; k0 += WAVE) {
+            const int cnt = min(WAVE, len - k0);
+            const int cl = k0 + lane < len ? A.col[(int64_t)(off + k0 + lane) * WAVE + rl] : 0;
+            if (lane < nrhs) {
+                for (int u = 0; u < cnt; ++u) {
+                    const int64_t c = __builtin_amdgcn_readlane(cl, u);
+                    const VT *vk = A.val + (int64_t)(off + k0 + u) * (BR * BC * WAVE);
+                    AT xv[BC];
 #pragma unroll
-                for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
+                    for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
 #pragma unroll
-                for (int i = 0; i < BR; ++i)
+                    for (int i = 0; i < BR; ++i)
 #pragma unroll
-                    for (int j = 0; j < BC; ++j)
-                        acc[i] += AT(vk[sell_val_off<sell_vw<VT>()>(i * BC + j, BR * BC, rl)]) * xv[j];
+                        for (int j = 0; j < BC; ++j)
+                            acc[i] += AT(vk[sell_val_off<sell_vw<VT>()>(i * BC + j, BR * BC, rl)]) * xv[j];
+                }
             }
+        }
+        if (lane < nrhs) {
             const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
             epi.template apply_m<BR>(out, lane, nrhs, acc, red);
         }
@@ -122,40 +130,56 @@ __global__ void __launch_bounds__(BLK) k_rowwm(RowView<VT> A, const XT *__restri
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * WPB + threadIdx.x / WAVE));
     double red = 0.0;
-    if (row < A.nrows && lane < nrhs) {
+    if (row < A.nrows) {
         AT acc[BR];
 #pragma unroll
         for (int i = 0; i < BR; ++i) acc[i] = AT(0);
-        const int64_t hi = A.rptr[row + 1];
-        for (int64_t k = A.rptr[row]; k < hi; ++k) {
-            const int64_t c = A.col[k];
-            const VT *v = A.val + k * (BR * BC);
-            AT xv[BC];
-#pragma unroll
-            for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
-#pragma unroll
-            for (int i = 0; i < BR; ++i)
-#pragma unroll
-                for (int j = 0; j < BC; ++j) acc[i] += AT(v[i * BC + j]) * xv[j];
-        }
-        if constexpr (BR == BC) {
-            if (A.lptr) {
-                const int64_t lhi = A.lptr[row + 1];
-                for (int64_t q = A.lptr[row]; q < lhi; ++q) {
-                    const int64_t c = A.lcol[q];
-                    const VT *v = A.val + (int64_t)A.lidx[q] * (BR * BC);
+        // column indices 64 at a time (every lane active), taken with readlane
+        const int64_t lo = A.rptr[row], hi = A.rptr[row + 1];
+        for (int64_t k0 = lo; k0 < hi; k0 += WAVE) {
+            const int cnt = (int)min((int64_t)WAVE, hi - k0);
+            const int cl = k0 + lane < hi ? A.col[k0 + lane] : 0;
+            if (lane < nrhs) {
+                for (int u = 0; u < cnt; ++u) {
+                    const int64_t c = __builtin_amdgcn_readlane(cl, u);
+                    const VT *v = A.val + (k0 + u) * (BR * BC);
                     AT xv[BC];
 #pragma unroll
                     for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
 #pragma unroll
                     for (int i = 0; i < BR; ++i)
 #pragma unroll
-                        for (int j = 0; j < BC; ++j) acc[i] += AT(v[j * BC + i]) * xv[j];
+                        for (int j = 0; j < BC; ++j) acc[i] += AT(v[i * BC + j]) * xv[j];
                 }
             }
         }
-        const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
-        epi.template apply_m<BR>(out, lane, nrhs, acc, red);
+        if constexpr (BR == BC) {
+            if (A.lptr) {
+                const int64_t llo = A.lptr[row], lhi = A.lptr[row + 1];
+                for (int64_t q0 = llo; q0 < lhi; q0 += WAVE) {
+                    const int cnt = (int)min((int64_t)WAVE, lhi - q0);
+                    const int cl = q0 + lane < lhi ? A.lcol[q0 + lane] : 0;
+                    const int il = q0 + lane < lhi ? A.lidx[q0 + lane] : 0;
+                    if (lane < nrhs) {
+                        for (int u = 0; u < cnt; ++u) {
+                            const int64_t c = __builtin_amdgcn_readlane(cl, u);
+                            const VT *v = A.val + (int64_t)__builtin_amdgcn_readlane(il, u) * (BR * BC);
+                            AT xv[BC];
+#pragma unroll
+                            for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
+#pragma unroll
+                            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                                for (int j = 0; j < BC; ++j) acc[i] += AT(v[j * BC + i]) * xv[j];
+                        }
+                    }
+                }
+            }
+        }
+        if (lane < nrhs) {
+            const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+            epi.template apply_m<BR>(out, lane, nrhs, acc, red);
+        }
     }
     if (Epi::kReduce) {
         lds[threadIdx.x] = red;
