@@ -244,6 +244,103 @@ def random_unit(rng, n):
 
 
 # ---------------------------------------------------------------------------
+# Boundary faces, material regions and boundary pressure
+# ---------------------------------------------------------------------------
+# A face opposite each local vertex of a tetrahedron (local vertex triples).
+_TET_FACES = [(1, 2, 3), (0, 3, 2), (0, 1, 3), (0, 2, 1)]
+# Edge nodes of a P2 face in the order 01, 02, 12 of the face's vertices.
+_FACE_EDGES = [(0, 1), (0, 2), (1, 2)]
+
+
+def boundary_faces(mesh: Mesh, select=None) -> np.ndarray:
+    """Triangles that belong to exactly one cell, ordered so that
+    (x1 - x0) x (x2 - x0) points out of that cell: [F][3] vertex ids (P1), or
+    [F][6] with the edge nodes 01, 02, 12 of that vertex order (P2), sorted
+    by their vertex triple.  `select(centroids [F][3]) -> bool[F]` keeps a
+    subset."""
+    cells = mesh.cells.astype(np.int64)
+    tri = np.array(_TET_FACES)
+    verts = cells[:, tri]                                  # [C,4,3] local triple -> global ids
+    key = np.sort(verts, axis=2).reshape(-1, 3)
+    _, inv, cnt = np.unique(key, axis=0, return_inverse=True, return_counts=True)
+    once = np.nonzero(cnt[inv.ravel()] == 1)[0]
+    c_of, f_of = once // 4, once % 4
+    v = verts[c_of, f_of]                                  # [F,3]
+    x = mesh.coords[v]
+    nrm = np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0])
+    opp = mesh.coords[cells[c_of, f_of]]                   # local vertex f is opposite face f
+    flip = np.einsum("fi,fi->f", nrm, x.mean(axis=1) - opp) < 0
+    v[flip] = v[flip][:, [0, 2, 1]]
+    if mesh.degree == 2:
+        # edge node of global vertices (a, b) in cell c: its local edge index
+        loc = np.argmax(cells[c_of][:, None, :4] == v[:, :, None], axis=2)  # [F,3] local vertex of each face vertex
+        edge_ids = {e: i for i, e in enumerate(_EDGES)}
+        mids = np.empty((v.shape[0], 3), np.int64)
+        for k, (a, b) in enumerate(_FACE_EDGES):
+            la, lb = loc[:, a], loc[:, b]
+            lo, hi = np.minimum(la, lb), np.maximum(la, lb)
+            e = np.array([edge_ids[(int(p), int(q))] for p, q in zip(lo, hi)], dtype=np.int64)
+            mids[:, k] = cells[c_of, 4 + e]
+        v = np.concatenate([v, mids], axis=1)
+    order = np.lexsort(np.sort(v[:, :3], axis=1).T[::-1])
+    v = v[order]
+    if select is not None:
+        v = v[np.asarray(select(mesh.coords[v[:, :3]].mean(axis=1)), dtype=bool)]
+    return np.ascontiguousarray(v.astype(np.int32))
+
+
+@dataclasses.dataclass
+class Materials:
+    """Temperature tables [n_materials][n_points] (T ascending) of E, nu and
+    alpha_L, and the material of every cell."""
+    T: np.ndarray
+    E: np.ndarray
+    nu: np.ndarray
+    alpha: np.ndarray
+    cell_material: np.ndarray
+
+
+def turbine_material_tables():
+    """Three illustrative metals sampled at 250..1000 K (the paper shows
+    normalised temperature curves only): stiffness falling and expansion and
+    Poisson ratio rising with temperature."""
+    Tp = np.linspace(250.0, 1000.0, 6)
+    s = (Tp - 250.0) / 750.0
+    rows = []
+    for E0, a0, dE, da in ((205e9, 1.15e-5, 0.28, 0.38), (195e9, 1.30e-5, 0.22, 0.30), (215e9, 1.05e-5, 0.33, 0.45)):
+        rows.append((E0 * (1.0 - dE * s * (1.0 + 0.4 * s)), np.full_like(s, 0.0) + 0.29 + 0.03 * s,
+                     a0 * (1.0 + da * s * (1.0 - 0.2 * s))))
+    E = np.array([r[0] for r in rows])
+    nu = np.array([r[1] for r in rows])
+    alpha = np.array([r[2] for r in rows])
+    return np.tile(Tp, (3, 1)), E, nu, alpha
+
+
+def disc_materials(mesh: Mesh, geom: DiscGeom = DiscGeom()) -> Materials:
+    """Hub, web and rim of the disc as three materials by the radius of the
+    cell centroid (radial thirds)."""
+    c = mesh.coords[mesh.cells[:, :4].astype(np.int64)].mean(axis=1)
+    r = np.hypot(c[:, 0], c[:, 1])
+    t = (r - geom.r_in) / (geom.r_out - geom.r_in)
+    cm = np.minimum(2, (3.0 * t).astype(np.int64)).astype(np.int32)
+    Tp, E, nu, alpha = turbine_material_tables()
+    return Materials(Tp, E, nu, alpha, np.ascontiguousarray(cm))
+
+
+def disc_pressure_faces(mesh: Mesh, p_rim: float = 4.0e7, p_top: float = -5.0e6, geom: DiscGeom = DiscGeom()):
+    """Boundary pressure of the disc: traction p_rim n on the outer rim (blade
+    pull, outward) and p_top n on the upper face (gas pressure, compressive).
+    Returns (faces, p)."""
+    faces = boundary_faces(mesh)
+    x = mesh.coords[faces[:, :3].astype(np.int64)]
+    rim = np.all(np.hypot(x[..., 0], x[..., 1]) > geom.r_out * (1 - 1e-6), axis=1)
+    top = np.all(x[..., 2] > geom.thickness * (1 - 1e-9), axis=1)
+    keep = rim | top
+    p = np.where(rim, p_rim, p_top)[keep]
+    return np.ascontiguousarray(faces[keep]), np.ascontiguousarray(p.astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
 # Named workloads
 # ---------------------------------------------------------------------------
 

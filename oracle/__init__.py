@@ -9,8 +9,10 @@ Everything here is plain, slow and written to be checked by eye against the
 paper and the textbook methods it names, in float64:
 
 * ``fem``     -- Lagrange P1/P2 tetrahedral assembly of the thermoelastic
-                 weak form (Sec. 3, eq. wf_elastic with p_bc = 0), Dirichlet
-                 elimination, rigid-body near-nullspace.
+                 weak form (Sec. 3, eq. wf_elastic), one material or
+                 temperature-dependent tables per material with the boundary
+                 pressure term, Dirichlet elimination, rigid-body
+                 near-nullspace.
 * ``amg``     -- smoothed-aggregation AMG (Sec. 2.1.3, Sec. 5.1): strength,
                  greedy aggregation, tentative prolongator by QR, Lanczos
                  eigenvalue estimate, prolongator smoothing, Galerkin

@@ -1,8 +1,9 @@
 """Oracle: Lagrange P1/P2 tetrahedral assembly of the linear thermoelastic
 problem (test infrastructure only; see the package docstring).
 
-Problem (Sec. 3, eqs. elasticity_bvp and u-dbc, weak form wf_elastic with no
-boundary pressure): find u_h in [V_h]^3, u_h = u_bc on Gamma_D, with
+Problem (Sec. 3, eqs. elasticity_bvp and u-dbc, weak form wf_elastic; the
+boundary pressure term and temperature-dependent materials are in their own
+section below): find u_h in [V_h]^3, u_h = u_bc on Gamma_D, with
 
     a(u, v) = int lam div u div v + 2 mu eps(u):eps(v) dx
             = int C:eps_T : grad v dx + int f.v dx,
@@ -23,6 +24,7 @@ the integrands are polynomials in the barycentric coordinates, integrated with
 """
 from __future__ import annotations
 
+import dataclasses
 import functools
 from fractions import Fraction
 from math import factorial
@@ -139,11 +141,14 @@ def cell_geometry(coords, cells):
 
 
 def element_stiffness(vol, G, lam, mu, degree):
-    """K_e[C, a, i, b, j] for the bilinear form above (exact integration)."""
+    """K_e[C, a, i, b, j] for the bilinear form above (exact integration);
+    lam and mu are scalars or per-cell arrays."""
     S, _, _ = reference_tables(degree)
     GG = np.einsum("cki,clj->cklij", G, G)           # G[k,i] G[l,j]
     dots = np.einsum("ckm,clm->ckl", G, G)           # grad l_k . grad l_l
     eye = np.eye(3)
+    lam = np.reshape(lam, (-1, 1, 1, 1, 1))
+    mu = np.reshape(mu, (-1, 1, 1, 1, 1))
     kern = lam * GG + mu * GG.transpose(0, 1, 2, 4, 3) + mu * dots[:, :, :, None, None] * eye
     # kern[c,k,l,i,j] = lam G_ki G_lj + mu G_kj G_li + mu delta_ij G_k.G_l
     Ke = np.einsum("abkl,cklij->caibj", S, kern)
@@ -151,9 +156,10 @@ def element_stiffness(vol, G, lam, mu, degree):
 
 
 def element_load(vol, G, dT_cell, f_cell, lam, mu, alpha, degree):
-    """b_e[C, a, i]: thermal load plus consistent body-force load."""
+    """b_e[C, a, i]: thermal load plus consistent body-force load; lam, mu and
+    alpha are scalars or per-cell arrays."""
     _, W, M = reference_tables(degree)
-    c_alpha = (3.0 * lam + 2.0 * mu) * alpha
+    c_alpha = np.reshape((3.0 * np.asarray(lam) + 2.0 * np.asarray(mu)) * np.asarray(alpha), (-1, 1, 1))
     # sum_c dT_c int phi_c d_i phi_a = sum_c dT_c sum_k W[c,a,k] G[k,i]
     be = c_alpha * np.einsum("cn,nak,cki->cai", dT_cell, W, G) * vol[:, None, None]
     if f_cell is not None:
@@ -181,9 +187,17 @@ def sparsity(cells, n_nodes):
 
 
 def assemble(coords, cells, degree, E, nu, alpha, T_ref, T, f=None, chunk=200_000):
-    """Unconstrained global stiffness (scipy BSR, 3x3 blocks) and load b[N,3]."""
+    """Unconstrained global stiffness (scipy BSR, 3x3 blocks) and load b[N,3]
+    of one material (E, nu, alpha scalars) or of per-cell coefficients
+    (arrays over the cells)."""
     n = coords.shape[0]
-    lam, mu = lame(E, nu)
+    lam, mu = lame(np.asarray(E, dtype=np.float64), np.asarray(nu, dtype=np.float64))
+    alpha = np.asarray(alpha, dtype=np.float64)
+    per_cell = lam.ndim > 0
+
+    def part(v, s0, s1):
+        return v[s0:s1] if per_cell else v
+
     row_ptr, cols = sparsity(cells, n)
     keys = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr)) * n + cols
     val = np.zeros((cols.size, 3, 3))
@@ -192,10 +206,12 @@ def assemble(coords, cells, degree, E, nu, alpha, T_ref, T, f=None, chunk=200_00
     for s in range(0, cells.shape[0], chunk):
         cc = cells[s:s + chunk].astype(np.int64)
         vol, G = cell_geometry(coords, cc)
-        Ke = element_stiffness(vol, G, lam, mu, degree)  # [c,a,i,b,j]
+        s1 = s + cc.shape[0]
+        Ke = element_stiffness(vol, G, part(lam, s, s1), part(mu, s, s1), degree)  # [c,a,i,b,j]
         dT = T[cc] - T_ref
         fc = None if f is None else f[cc]
-        be = element_load(vol, G, dT, fc, lam, mu, alpha, degree)
+        be = element_load(vol, G, dT, fc, part(lam, s, s1), part(mu, s, s1),
+                          alpha[s:s1] if per_cell else alpha, degree)
         I = np.repeat(cc, npe, axis=1)   # [c, a*npe+b] -> node a
         J = np.tile(cc, (1, npe))
         pos = np.searchsorted(keys, (I * n + J).ravel())
@@ -231,6 +247,120 @@ def assemble_rows(coords, cells, degree, E, nu, alpha, T_ref, T, rows, f=None):
         cols = np.array(sorted(acc))
         out[r] = (cols, np.array([acc[j] for j in cols]), brow)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Temperature-dependent materials and boundary pressure
+# ---------------------------------------------------------------------------
+# Sec. 3 lets the stiffness tensor C and alpha_L depend on temperature and
+# the weak form wf_elastic carries the boundary term - int p_bc n . v ds on
+# Gamma_N (traction sigma n = p_bc n); Sec. 4.1 shows normalised
+# temperature tables for several materials.  Readings: each material gives
+# E, nu and alpha_L as piecewise-linear tables in T, constant beyond their
+# ends; a cell takes the values of its material at the mean of T_h over the
+# cell (so C and alpha_L are constant per cell); p_bc is constant on each
+# boundary triangle.
+
+@dataclasses.dataclass
+class MaterialTables:
+    """T[m, k] ascending sample temperatures of material m, and E, nu, alpha
+    at those temperatures (all [n_materials, n_points])."""
+    T: np.ndarray
+    E: np.ndarray
+    nu: np.ndarray
+    alpha: np.ndarray
+
+
+def cell_mean(T, cells, degree):
+    """Mean of the Lagrange interpolant T_h over each cell:
+    sum_c T_c (1/|K|) int phi_c, with int phi_c = sum_a int phi_a phi_c
+    (the basis sums to one)."""
+    _, _, M = reference_tables(degree)
+    return T[cells] @ M.sum(axis=0)
+
+
+def cell_coefficients(T, cells, degree, cell_material, tables: MaterialTables):
+    """Per-cell (E, nu, alpha) of each cell's material at its mean temperature."""
+    Tm = cell_mean(T, cells, degree)
+    E = np.empty(cells.shape[0])
+    nu = np.empty_like(E)
+    alpha = np.empty_like(E)
+    for m in np.unique(cell_material).tolist():
+        sel = cell_material == m
+        E[sel] = np.interp(Tm[sel], tables.T[m], tables.E[m])
+        nu[sel] = np.interp(Tm[sel], tables.T[m], tables.nu[m])
+        alpha[sel] = np.interp(Tm[sel], tables.T[m], tables.alpha[m])
+    return E, nu, alpha
+
+
+FACE_EDGES = [(0, 1), (0, 2), (1, 2)]
+
+
+@functools.lru_cache(maxsize=None)
+def face_basis_integrals(degree):
+    """(1/|F|) int_F phi_a ds for the Lagrange basis on a triangle in
+    barycentric coordinates (P1: l_a; P2: vertices l_a (2 l_a - 1), then
+    4 l_a l_b on the edges 01, 02, 12), from
+    int_F l0^a l1^b l2^c ds = a! b! c! 2! |F| / (a+b+c+2)!."""
+    def lam(k, c=1):
+        e = [0, 0, 0]
+        e[k] = 1
+        return {tuple(e): Fraction(c)}
+
+    def mul(p, q):
+        out = {}
+        for ep, cp in p.items():
+            for eq, cq in q.items():
+                e = tuple(a + b for a, b in zip(ep, eq))
+                out[e] = out.get(e, Fraction(0)) + cp * cq
+        return out
+
+    if degree == 1:
+        phis = [lam(a) for a in range(3)]
+    else:
+        phis = []
+        for a in range(3):
+            q = mul(lam(a, 2), lam(a))
+            q[(0, 0, 0)] = Fraction(0)
+            e = [0, 0, 0]
+            e[a] = 1
+            q[tuple(e)] = q.get(tuple(e), Fraction(0)) - 1
+            phis.append(q)
+        phis += [mul(lam(a, 4), lam(b)) for a, b in FACE_EDGES]
+    out = []
+    for p in phis:
+        tot = Fraction(0)
+        for (a, b, c), coef in p.items():
+            tot += coef * Fraction(factorial(a) * factorial(b) * factorial(c) * 2, factorial(a + b + c + 2))
+        out.append(float(tot))
+    return np.array(out)
+
+
+def pressure_load(coords, faces, degree, p):
+    """b[N, 3] of the boundary term int_F p n . v ds summed over the faces
+    (traction p n; faces [F, 3] (P1) or [F, 6] (P2: vertices, then the edge
+    nodes 01, 02, 12); n = (x1 - x0) x (x2 - x0) / |.|, outward for faces
+    ordered counterclockwise seen from outside)."""
+    faces = np.asarray(faces, dtype=np.int64)
+    x = coords[faces[:, :3]]
+    nv = np.cross(x[:, 1] - x[:, 0], x[:, 2] - x[:, 0])
+    two_area = np.linalg.norm(nv, axis=1)
+    n = nv / two_area[:, None]
+    w = face_basis_integrals(degree)
+    contrib = (np.asarray(p, dtype=np.float64) * 0.5 * two_area)[:, None, None] * w[None, :, None] * n[:, None, :]
+    b = np.zeros((coords.shape[0], 3))
+    np.add.at(b, faces.ravel(), contrib.reshape(-1, 3))
+    return b
+
+
+def assemble_materials(coords, cells, degree, cell_material, tables, T_ref, T, f=None, faces=None, face_p=None):
+    """Unconstrained system with per-cell temperature-dependent coefficients
+    and the boundary pressure load: (A, b[N, 3])."""
+    E, nu, alpha = cell_coefficients(T, np.asarray(cells, dtype=np.int64), degree, np.asarray(cell_material), tables)
+    A, b = assemble(coords, cells, degree, E, nu, alpha, T_ref, T, f)
+    if faces is not None and len(faces):
+        b = b + pressure_load(coords, faces, degree, face_p)
+    return A, b
 
 
 # ---------------------------------------------------------------------------
