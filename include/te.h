@@ -106,6 +106,47 @@ int fe_assemble_thermoelastic(const te_mesh *mesh, const te_material *mat, const
                               const double *f, const uint8_t *dir_mask, const double *u_bc,
                               te_bsr *A, double *b, hipStream_t stream);
 
+/* Temperature-dependent isotropic materials (Sec. 3: C and alpha_L depend on
+ * T; Sec. 4.1 shows such tables for several materials).  Material m gives E,
+ * nu and alpha_L at n_points temperatures T[m][k] (strictly ascending); values
+ * between samples are linear in T, beyond the first and last sample constant.
+ * All arrays are host arrays [n_materials][n_points], read during the call. */
+typedef struct {
+    int32_t n_materials;
+    int32_t n_points;
+    const double *T;
+    const double *E;        /* > 0                                            */
+    const double *nu;       /* in (-1, 0.5)                                   */
+    const double *alpha;
+    double T_ref;           /* reference temperature of the thermal strain    */
+} te_material_tables;
+
+/* Boundary pressure of eq. wf_elastic: traction p_bc n on Gamma_N, p_bc
+ * constant on each boundary triangle.  faces: device [n_faces][3] vertex
+ * ids (P1) or [n_faces][6]: the three vertices, then the edge nodes 01, 02,
+ * 12 of that vertex order (P2); n = (x1 - x0) x (x2 - x0) / |.| must point
+ * out of the body.  p: device [n_faces]. */
+typedef struct {
+    int64_t n_faces;
+    const int32_t *faces;
+    const double *p;
+} te_pressure;
+
+/* fe_assemble_thermoelastic with per-cell coefficients and the boundary
+ * pressure: cell c takes the values of material cell_material[c] (device
+ * [C], 0..n_materials-1) at the mean of T_h over the cell, so lam, mu and
+ * alpha_L are constant per cell; b gains int_F p_bc n . phi_a ds on every
+ * pressure face (exact: |F|/3 per node for P1; 0 at the vertices and |F|/3
+ * at the edge nodes for P2), before the Dirichlet elimination.  pressure may
+ * be NULL (or hold no faces).  Other arguments, layouts and the elimination
+ * as in fe_assemble_thermoelastic.  Deterministic.  Errors: TE_EINVAL (bad
+ * tables, a material id or face node out of range), TE_ENOMEM, TE_EHIP. */
+int fe_assemble_thermoelastic_materials(const te_mesh *mesh, const te_material_tables *mat,
+                                        const int32_t *cell_material, const double *T,
+                                        const double *f, const te_pressure *pressure,
+                                        const uint8_t *dir_mask, const double *u_bc, te_bsr *A,
+                                        double *b, hipStream_t stream);
+
 /* Load vector only (same b as above with u_bc = 0), for many load cases on
  * one assembled matrix.  nrhs load cases: T device [nrhs][N], f device
  * [nrhs][N][3] or NULL; b device [N][3][nrhs] (right-hand sides fastest). */

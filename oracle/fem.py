@@ -363,6 +363,41 @@ def assemble_materials(coords, cells, degree, cell_material, tables, T_ref, T, f
     return A, b
 
 
+def assemble_rows_materials(coords, cells, degree, cell_material, tables, T_ref, T, rows, f=None, faces=None,
+                            face_p=None):
+    """Block rows `rows` of the unconstrained multi-material system with the
+    boundary pressure, from the cells and faces that touch them only.
+    Returns a dict row -> (cols[int], blocks[k,3,3], b_row[3])."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cells = np.asarray(cells, dtype=np.int64)
+    touch = np.isin(cells, rows).any(axis=1)
+    sub = cells[touch]
+    E, nu, alpha = cell_coefficients(T, sub, degree, np.asarray(cell_material)[touch], tables)
+    lam, mu = lame(E, nu)
+    vol, G = cell_geometry(coords, sub)
+    Ke = element_stiffness(vol, G, lam, mu, degree)
+    be = element_load(vol, G, T[sub] - T_ref, None if f is None else f[sub], lam, mu, alpha, degree)
+    bp = None
+    if faces is not None and len(faces):
+        faces = np.asarray(faces, dtype=np.int64)
+        ft = np.isin(faces, rows).any(axis=1)
+        bp = pressure_load(coords, faces[ft], degree, np.asarray(face_p)[ft])
+    out = {}
+    npe = sub.shape[1]
+    for r in rows.tolist():
+        acc = {}
+        brow = np.zeros(3) if bp is None else bp[r].copy()
+        cs, as_ = np.nonzero(sub == r)
+        for c, a in zip(cs.tolist(), as_.tolist()):
+            brow += be[c, a]
+            for bb in range(npe):
+                J = int(sub[c, bb])
+                acc[J] = acc.get(J, 0.0) + Ke[c, a, :, bb, :]
+        cols = np.array(sorted(acc))
+        out[r] = (cols, np.array([acc[j] for j in cols]), brow)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Dirichlet conditions and near-nullspace
 # ---------------------------------------------------------------------------

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import (TE_OP_A, TE_OP_P, TE_OP_R, TE_OP_SMOOTH, TE_OP_VCYCLE, TE_PREC_FP64, TE_PREC_MIXED, TeError,
                    check, load)
 
-__all__ = ["assemble", "assemble_load", "AMG", "MPNN", "solve_multi", "Matrix", "TeError", "load", "TE_PREC_FP64",
+__all__ = ["assemble", "assemble_load", "assemble_materials", "AMG", "MPNN", "solve_multi", "Matrix", "TeError", "load", "TE_PREC_FP64",
            "TE_PREC_MIXED", "TE_OP_A", "TE_OP_P", "TE_OP_R", "TE_OP_SMOOTH", "TE_OP_VCYCLE"]
 
 
@@ -98,6 +98,45 @@ def assemble(coords, cells, degree, E, nu, alpha, T_ref, T, f=None, mask=None, u
     bsr = A.c()
     check(lib.fe_assemble_thermoelastic(C.byref(m), C.byref(mat), _ptr(T), _ptr(f), _ptr(mask), _ptr(u_bc),
                                         C.byref(bsr), _ptr(b), _stream()))
+    return A, b
+
+
+def assemble_materials(coords, cells, degree, tables, cell_material, T_ref, T, f=None, faces=None, face_p=None,
+                       mask=None, u_bc=None):
+    """fe_assemble_pattern + fe_assemble_thermoelastic_materials.
+    tables: (T, E, nu, alpha) host arrays [n_materials][n_points];
+    cell_material: int32 [C]; faces/face_p: boundary pressure (int32 [F][3|6],
+    float64 [F]) or None.  Returns (Matrix, b[3N])."""
+    import numpy as np
+    torch = _torch()
+    lib = load()
+    m = _mesh(coords, cells, degree)
+    n = coords.shape[0]
+    _dev(T, torch.float64, (n,), "T")
+    _dev(cell_material, torch.int32, (cells.shape[0],), "cell_material")
+    _dev(f, torch.float64, (n, 3), "f")
+    _dev(mask, torch.uint8, (n, 3), "mask")
+    _dev(u_bc, torch.float64, (n, 3), "u_bc")
+    tab = [np.ascontiguousarray(a, dtype=np.float64) for a in tables]
+    if tab[0].ndim != 2 or any(a.shape != tab[0].shape for a in tab):
+        raise ValueError("tables must be four [n_materials][n_points] arrays")
+    mt = _lib.TeMaterialTables(tab[0].shape[0], tab[0].shape[1], *[a.ctypes.data for a in tab], T_ref)
+    pr = None
+    if faces is not None and faces.shape[0] > 0:
+        _dev(faces, torch.int32, (faces.shape[0], 3 if degree == 1 else 6), "faces")
+        _dev(face_p, torch.float64, (faces.shape[0],), "face_p")
+        pr = _lib.TePressure(faces.shape[0], faces.data_ptr(), face_p.data_ptr())
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=coords.device)
+    nnzb = C.c_int64(0)
+    check(lib.fe_assemble_pattern(C.byref(m), _ptr(row_ptr), C.byref(nnzb), _stream()))
+    col = torch.empty(nnzb.value, dtype=torch.int32, device=coords.device)
+    val = torch.empty((nnzb.value, 3, 3), dtype=torch.float64, device=coords.device)
+    b = torch.empty(3 * n, dtype=torch.float64, device=coords.device)
+    A = Matrix(row_ptr, col, val)
+    bsr = A.c()
+    check(lib.fe_assemble_thermoelastic_materials(C.byref(m), C.byref(mt), _ptr(cell_material), _ptr(T), _ptr(f),
+                                                  C.byref(pr) if pr is not None else None, _ptr(mask), _ptr(u_bc),
+                                                  C.byref(bsr), _ptr(b), _stream()))
     return A, b
 
 

@@ -19,6 +19,7 @@ CODE_NAMES = {TE_ENOTCONV: "TE_ENOTCONV", TE_EINVAL: "TE_EINVAL", TE_ENOMEM: "TE
 
 # exported names declared in include/te.h
 EXPORTS = ["te_version", "te_last_error", "fe_assemble_pattern", "fe_assemble_thermoelastic", "fe_assemble_load",
+           "fe_assemble_thermoelastic_materials",
            "amg_options_default", "amg_setup", "amg_setup_with_aggregates", "amg_get_info", "amg_get_aggregates",
            "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_pcg_solve_multi", "amg_energy_scale", "te_autotune", "amg_destroy",
            "mpnn_param_count", "mpnn_create", "mpnn_destroy", "mpnn_features", "mpnn_forward", "mpnn_backward", "mpnn_backward_from", "mpnn_energy_grad",
@@ -32,6 +33,15 @@ class TeMesh(C.Structure):
 
 class TeMaterial(C.Structure):
     _fields_ = [("E", C.c_double), ("nu", C.c_double), ("alpha", C.c_double), ("T_ref", C.c_double)]
+
+
+class TeMaterialTables(C.Structure):
+    _fields_ = [("n_materials", C.c_int32), ("n_points", C.c_int32), ("T", C.c_void_p), ("E", C.c_void_p),
+                ("nu", C.c_void_p), ("alpha", C.c_void_p), ("T_ref", C.c_double)]
+
+
+class TePressure(C.Structure):
+    _fields_ = [("n_faces", C.c_int64), ("faces", C.c_void_p), ("p", C.c_void_p)]
 
 
 class TeBsr(C.Structure):
@@ -82,6 +92,8 @@ def load():
         "fe_assemble_thermoelastic": ([C.POINTER(TeMesh), C.POINTER(TeMaterial), vp, vp, vp, vp, C.POINTER(TeBsr),
                                        vp, vp], C.c_int),
         "fe_assemble_load": ([C.POINTER(TeMesh), C.POINTER(TeMaterial), vp, vp, vp, i32, vp, vp], C.c_int),
+        "fe_assemble_thermoelastic_materials": ([C.POINTER(TeMesh), C.POINTER(TeMaterialTables), vp, vp, vp,
+                                                 C.POINTER(TePressure), vp, vp, C.POINTER(TeBsr), vp, vp], C.c_int),
         "amg_options_default": ([C.POINTER(AmgOptions)], None),
         "amg_setup": ([C.POINTER(TeBsr), vp, vp, C.POINTER(AmgOptions), C.POINTER(vp), vp], C.c_int),
         "amg_setup_with_aggregates": ([C.POINTER(TeBsr), vp, vp, C.POINTER(AmgOptions), C.POINTER(vp), i32,

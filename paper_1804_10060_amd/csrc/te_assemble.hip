@@ -285,6 +285,7 @@ struct AsmArgs {
     const int64_t *inc;
     int64_t n;
     double lam, mu, calpha, T_ref;
+    const double *coef;  // per cell (lam, mu, (3 lam + 2 mu) alpha) [C][3], or null: the scalars above
     const double *T;   // [nrhs][N]
     const double *f;   // [nrhs][N][3] or null
     const int64_t *row_ptr;
@@ -310,6 +311,7 @@ __global__ void __launch_bounds__(ABLK) k_assemble(AsmArgs A, int j) {
         const int a = (int)(A.inc[e] % NPE);
         const int32_t *cv = A.cells + cell * NPE;
         const Geo g = cell_geo(A.X, cv);
+        const double calpha = A.coef ? A.coef[cell * 3 + 2] : A.calpha;
         for (int k = 0; k < 4; ++k)
             for (int c = 0; c < 3; ++c) G[k * 3 + c] = g.G[k][c];
         double dT[NPE];
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(ABLK) k_assemble(AsmArgs A, int j) {
         if (DEG == 1) {
             // thermal: (3 lam + 2 mu) alpha |K| mean(dT) grad l_a
             double mT = 0.25 * (dT[0] + dT[1] + dT[2] + dT[3]);
-            for (int c = 0; c < 3; ++c) bi[c] += A.calpha * g.vol * mT * G[a * 3 + c];
+            for (int c = 0; c < 3; ++c) bi[c] += calpha * g.vol * mT * G[a * 3 + c];
             if (f)
                 for (int c = 0; c < 4; ++c) {
                     double m = g.vol * (c == a ? 2.0 : 1.0) / 20.0;
@@ -338,7 +340,7 @@ __global__ void __launch_bounds__(ABLK) k_assemble(AsmArgs A, int j) {
                     for (int c = 0; c < 10; ++c) Tq += dT[c] * p2_val(c, l0, l1, l2, l3);
                     double gr[3];
                     p2_grad(a, l0, l1, l2, l3, G, gr);
-                    for (int c = 0; c < 3; ++c) bi[c] += A.calpha * w5[qp] * g.vol * Tq * gr[c];
+                    for (int c = 0; c < 3; ++c) bi[c] += calpha * w5[qp] * g.vol * Tq * gr[c];
                 }
             }
             if (f)
@@ -362,7 +364,7 @@ template <int DEG>
 __global__ void __launch_bounds__(64) k_stiff(AsmArgs A) {
     constexpr int NPE = DEG == 1 ? 4 : 10;
     static_assert(NPE % 2 == 0, "cell entries are read in pairs");
-    __shared__ double s_geo[SCH][13];  // gradients of the 4 barycentric coordinates, volume
+    __shared__ double s_geo[SCH][15];  // gradients of the 4 barycentric coordinates, volume, lam, mu
     __shared__ int32_t s_cv[SCH][NPE];
     __shared__ int32_t s_a[SCH];
     __shared__ double s_k[SCH * NPE][9];
@@ -390,12 +392,14 @@ __global__ void __launch_bounds__(64) k_stiff(AsmArgs A) {
                 for (int k = 0; k < 4; ++k)
                     for (int c = 0; c < 3; ++c) s_geo[lane][k * 3 + c] = g.G[k][c];
                 s_geo[lane][12] = g.vol;
+                s_geo[lane][13] = A.coef ? A.coef[(ent / NPE) * 3] : A.lam;
+                s_geo[lane][14] = A.coef ? A.coef[(ent / NPE) * 3 + 1] : A.mu;
             }
             __syncthreads();
             for (int t = lane; t < nc * NPE; t += 64) {
                 const int c = t / NPE, bb = t % NPE, a = s_a[c];
                 const double *G = s_geo[c];
-                const double vol = s_geo[c][12];
+                const double vol = s_geo[c][12], lam = s_geo[c][13], mu = s_geo[c][14];
                 double K[9];
                 if (DEG == 1) {
                     const double *ga = G + a * 3, *gb = G + bb * 3;
@@ -403,7 +407,7 @@ __global__ void __launch_bounds__(64) k_stiff(AsmArgs A) {
                     for (int p = 0; p < 3; ++p)
                         for (int q = 0; q < 3; ++q)
                             K[p * 3 + q] =
-                                vol * (A.lam * ga[p] * gb[q] + A.mu * ga[q] * gb[p] + (p == q ? A.mu * dot : 0.0));
+                                vol * (lam * ga[p] * gb[q] + mu * ga[q] * gb[p] + (p == q ? mu * dot : 0.0));
                 } else {
                     // degree-2 integrand: 4-point rule (a,b,b,b), weights |K|/4
                     const double qa = 0.5854101966249685, qb = 0.1381966011250105;
@@ -417,7 +421,7 @@ __global__ void __launch_bounds__(64) k_stiff(AsmArgs A) {
                         const double dot = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
                         for (int p = 0; p < 3; ++p)
                             for (int q = 0; q < 3; ++q)
-                                K[p * 3 + q] += A.lam * ga[p] * gb[q] + A.mu * ga[q] * gb[p] + (p == q ? A.mu * dot : 0.0);
+                                K[p * 3 + q] += lam * ga[p] * gb[q] + mu * ga[q] * gb[p] + (p == q ? mu * dot : 0.0);
                     }
                     const double w = 0.25 * vol;
                     for (int k = 0; k < 9; ++k) K[k] *= w;
@@ -492,6 +496,86 @@ __global__ void k_dirichlet(int64_t n, const int64_t *__restrict__ row_ptr, cons
 __global__ void k_zero_masked(int64_t n, int nrhs, double *__restrict__ b, const uint8_t *__restrict__ mask) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n * 3 * nrhs; t += (int64_t)gridDim.x * blockDim.x)
         if (mask[t / nrhs]) b[t] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Temperature-dependent materials and boundary pressure
+// ---------------------------------------------------------------------------
+// Value of one table (n samples at temperatures Tt, ascending) at Tm: linear
+// between samples, constant beyond the ends.
+__device__ __forceinline__ double table_at(const double *Tt, const double *v, int n, double Tm) {
+    if (n == 1 || Tm <= Tt[0]) return v[0];
+    if (Tm >= Tt[n - 1]) return v[n - 1];
+    int k = 0;
+    while (k + 2 < n && Tm >= Tt[k + 1]) ++k;
+    const double slope = (v[k + 1] - v[k]) / (Tt[k + 1] - Tt[k]);
+    return slope * (Tm - Tt[k]) + v[k];
+}
+
+// Per cell: mean of T_h over the cell (P1: vertex average; P2: -1/20 of each
+// vertex value plus 1/5 of each edge value, the exact cell integrals of the
+// basis), the material's E, nu, alpha there, and (lam, mu, (3 lam + 2 mu) alpha).
+// tab = [T | E | nu | alpha], each [nmat][npts].
+template <int DEG>
+__global__ void k_cell_coef(int64_t nc, const int32_t *__restrict__ cells, const double *__restrict__ T,
+                            const int32_t *__restrict__ cmat, int nmat, int npts, const double *__restrict__ tab,
+                            double *__restrict__ coef, int32_t *__restrict__ bad) {
+    constexpr int NPE = DEG == 1 ? 4 : 10;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t *cv = cells + c * NPE;
+        double Tm;
+        if (DEG == 1) {
+            Tm = 0.25 * (T[cv[0]] + T[cv[1]] + T[cv[2]] + T[cv[3]]);
+        } else {
+            double sv = 0.0, se = 0.0;
+            for (int k = 0; k < 4; ++k) sv += T[cv[k]];
+            for (int k = 4; k < 10; ++k) se += T[cv[k]];
+            Tm = -0.05 * sv + 0.2 * se;
+        }
+        int m = cmat[c];
+        if (m < 0 || m >= nmat) {
+            *bad = 1;
+            m = 0;
+        }
+        const int64_t so = (int64_t)nmat * npts, mo = (int64_t)m * npts;
+        const double *Tt = tab + mo;
+        const double E = table_at(Tt, tab + so + mo, npts, Tm);
+        const double nu = table_at(Tt, tab + 2 * so + mo, npts, Tm);
+        const double al = table_at(Tt, tab + 3 * so + mo, npts, Tm);
+        const double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        const double mu = E / (2.0 * (1.0 + nu));
+        coef[c * 3] = lam;
+        coef[c * 3 + 1] = mu;
+        coef[c * 3 + 2] = (3.0 * lam + 2.0 * mu) * al;
+    }
+}
+
+// Pressure load, one thread per node: b_i += p_f |F| w_a n_f over the node's
+// (face, local node) entries in face order (w_a = 1/3 for P1 nodes and P2
+// edge nodes; P2 vertices have none).
+__global__ void k_pressure(int64_t n, const int64_t *__restrict__ ptr, const int64_t *__restrict__ ent, int npf,
+                           const int32_t *__restrict__ faces, const double *__restrict__ p,
+                           const double *__restrict__ X, double *__restrict__ b) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (ptr[i] == ptr[i + 1]) continue;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+            const int64_t f = ent[e] / npf;
+            const int32_t *fv = faces + f * npf;
+            double x0[3], d1[3], d2[3];
+            for (int k = 0; k < 3; ++k) {
+                x0[k] = X[(int64_t)fv[0] * 3 + k];
+                d1[k] = X[(int64_t)fv[1] * 3 + k] - x0[k];
+                d2[k] = X[(int64_t)fv[2] * 3 + k] - x0[k];
+            }
+            const double nv[3] = {d1[1] * d2[2] - d1[2] * d2[1], d1[2] * d2[0] - d1[0] * d2[2],
+                                  d1[0] * d2[1] - d1[1] * d2[0]};
+            // p |F| / 3 * n = p * |nv| / 2 / 3 * nv / |nv| = p nv / 6
+            const double s = p[f] / 6.0;
+            for (int k = 0; k < 3; ++k) acc[k] += s * nv[k];
+        }
+        for (int k = 0; k < 3; ++k) b[i * 3 + k] += acc[k];
+    }
 }
 
 static void check_mesh(const te_mesh *m) {
@@ -574,7 +658,7 @@ extern "C" int fe_assemble_thermoelastic(const te_mesh *mesh, const te_material 
                    (long long)nnzb);
         pattern_impl(mesh, I, A->row_ptr, A->col_idx, stream);
         AsmArgs a{mesh->coords, mesh->cells, npe, I.start.p, I.inc.p, mesh->n_nodes, lam, mu, calpha, mat->T_ref,
-                  T, f, A->row_ptr, A->col_idx, A->val, b, 1};
+                  nullptr, T, f, A->row_ptr, A->col_idx, A->val, b, 1};
         const unsigned gs = (unsigned)std::min<int64_t>(mesh->n_nodes, 1 << 18);
         if (mesh->degree == 1) hipLaunchKernelGGL(k_stiff<1>, dim3(gs), dim3(64), 0, stream, a);
         else hipLaunchKernelGGL(k_stiff<2>, dim3(gs), dim3(64), 0, stream, a);
@@ -606,7 +690,7 @@ extern "C" int fe_assemble_load(const te_mesh *mesh, const te_material *mat, con
         Incidence I;
         build_incidence(mesh, npe, I, stream);
         AsmArgs a{mesh->coords, mesh->cells, npe, I.start.p, I.inc.p, mesh->n_nodes, lam, mu, calpha, mat->T_ref,
-                  T, f, nullptr, nullptr, nullptr, b, nrhs};
+                  nullptr, T, f, nullptr, nullptr, nullptr, b, nrhs};
         unsigned g = (unsigned)((mesh->n_nodes + ABLK - 1) / ABLK);
         for (int j = 0; j < nrhs; ++j) {
             if (mesh->degree == 1) hipLaunchKernelGGL(k_assemble<1>, dim3(g), dim3(ABLK), 0, stream, a, j);
@@ -616,6 +700,106 @@ extern "C" int fe_assemble_load(const te_mesh *mesh, const te_material *mat, con
         if (dir_mask) {
             unsigned gd = (unsigned)std::min<int64_t>((mesh->n_nodes * 3 * nrhs + 255) / 256, 1 << 20);
             hipLaunchKernelGGL(k_zero_masked, dim3(gd), dim3(256), 0, stream, mesh->n_nodes, nrhs, b, dir_mask);
+            TE_CHECK_HIP(hipGetLastError());
+        }
+        TE_CHECK_HIP(hipStreamSynchronize(stream));
+        return TE_OK;
+    });
+}
+
+extern "C" int fe_assemble_thermoelastic_materials(const te_mesh *mesh, const te_material_tables *mat,
+                                                   const int32_t *cell_material, const double *T, const double *f,
+                                                   const te_pressure *pressure, const uint8_t *dir_mask,
+                                                   const double *u_bc, te_bsr *A, double *b, hipStream_t stream) {
+    return guarded([&]() -> int {
+        check_mesh(mesh);
+        TE_REQUIRE(mat && cell_material && T && b && A && A->row_ptr && A->col_idx && A->val, TE_EINVAL,
+                   "NULL argument");
+        TE_REQUIRE(A->n_brows == mesh->n_nodes, TE_EINVAL, "A.n_brows != n_nodes");
+        const int nm = mat->n_materials, np = mat->n_points;
+        TE_REQUIRE(nm >= 1 && np >= 1 && mat->T && mat->E && mat->nu && mat->alpha, TE_EINVAL,
+                   "material tables are empty or NULL");
+        std::vector<double> tab((size_t)4 * nm * np);
+        for (int m = 0; m < nm; ++m)
+            for (int k = 0; k < np; ++k) {
+                const size_t q = (size_t)m * np + k, so = (size_t)nm * np;
+                const double Tk = mat->T[q], E = mat->E[q], nu = mat->nu[q];
+                TE_REQUIRE(k == 0 || Tk > mat->T[q - 1], TE_EINVAL, "material %d: temperatures not ascending", m);
+                TE_REQUIRE(E > 0 && nu > -1.0 && nu < 0.5, TE_EINVAL, "material %d: invalid E / nu at sample %d", m, k);
+                tab[q] = Tk;
+                tab[so + q] = E;
+                tab[2 * so + q] = nu;
+                tab[3 * so + q] = mat->alpha[q];
+            }
+        const int npe = mesh->degree == 1 ? 4 : 10;
+        const int64_t nc = mesh->n_cells, n = mesh->n_nodes;
+        // node -> cell incidence first: it rejects node ids outside the mesh
+        // before any kernel reads through them
+        Incidence I;
+        build_incidence(mesh, npe, I, stream);
+        DBuf<double> dtab, coef(nc * 3);
+        upload(dtab, tab, stream);
+        DBuf<int32_t> bad(1);
+        TE_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), stream));
+        const unsigned gc = (unsigned)std::min<int64_t>((nc + 255) / 256, 1 << 20);
+        if (mesh->degree == 1)
+            hipLaunchKernelGGL(k_cell_coef<1>, dim3(gc), dim3(256), 0, stream, nc, mesh->cells, T, cell_material, nm,
+                               np, dtab.p, coef.p, bad.p);
+        else
+            hipLaunchKernelGGL(k_cell_coef<2>, dim3(gc), dim3(256), 0, stream, nc, mesh->cells, T, cell_material, nm,
+                               np, dtab.p, coef.p, bad.p);
+        TE_CHECK_HIP(hipGetLastError());
+        int32_t hb = 0;
+        TE_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        int64_t nnzb = 0;
+        TE_CHECK_HIP(hipMemcpyAsync(&nnzb, A->row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+        TE_CHECK_HIP(hipStreamSynchronize(stream));
+        TE_REQUIRE(hb == 0, TE_EINVAL, "a cell material id is outside 0..%d", nm - 1);
+        TE_REQUIRE(nnzb == A->nnzb, TE_EINVAL, "A.nnzb (%lld) != row_ptr[N] (%lld)", (long long)A->nnzb,
+                   (long long)nnzb);
+        // node -> (face, local node) entries of the pressure faces, in face order
+        const bool has_p = pressure && pressure->n_faces > 0;
+        DBuf<int64_t> pptr, pent;
+        const int npf = mesh->degree == 1 ? 3 : 6;
+        if (has_p) {
+            TE_REQUIRE(pressure->faces && pressure->p, TE_EINVAL, "pressure faces / values are NULL");
+            std::vector<int32_t> fh;
+            download(fh, pressure->faces, (size_t)pressure->n_faces * npf, stream);
+            std::vector<int64_t> cnt(n + 1, 0);
+            const int a0 = mesh->degree == 1 ? 0 : 3;  // P2 vertices carry no pressure load
+            for (int64_t q = 0; q < (int64_t)fh.size(); ++q) {
+                TE_REQUIRE(fh[q] >= 0 && fh[q] < n, TE_EINVAL, "pressure face %lld has a node outside the mesh",
+                           (long long)(q / npf));
+                if (q % npf >= a0) ++cnt[fh[q] + 1];
+            }
+            for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+            std::vector<int64_t> ent(cnt[n]), fill(cnt.begin(), cnt.end() - 1);
+            for (int64_t q = 0; q < (int64_t)fh.size(); ++q)
+                if (q % npf >= a0) ent[fill[fh[q]]++] = q;
+            upload(pptr, cnt, stream);
+            upload(pent, ent, stream);
+        }
+        pattern_impl(mesh, I, A->row_ptr, A->col_idx, stream);
+        AsmArgs a{mesh->coords, mesh->cells, npe, I.start.p, I.inc.p, n, 0.0, 0.0, 0.0, mat->T_ref,
+                  coef.p, T, f, A->row_ptr, A->col_idx, A->val, b, 1};
+        const unsigned gs = (unsigned)std::min<int64_t>(n, 1 << 18);
+        if (mesh->degree == 1) hipLaunchKernelGGL(k_stiff<1>, dim3(gs), dim3(64), 0, stream, a);
+        else hipLaunchKernelGGL(k_stiff<2>, dim3(gs), dim3(64), 0, stream, a);
+        TE_CHECK_HIP(hipGetLastError());
+        const unsigned g = (unsigned)((n + ABLK - 1) / ABLK);
+        if (mesh->degree == 1) hipLaunchKernelGGL(k_assemble<1>, dim3(g), dim3(ABLK), 0, stream, a, 0);
+        else hipLaunchKernelGGL(k_assemble<2>, dim3(g), dim3(ABLK), 0, stream, a, 0);
+        TE_CHECK_HIP(hipGetLastError());
+        if (has_p) {
+            const unsigned gp = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20);
+            hipLaunchKernelGGL(k_pressure, dim3(gp), dim3(256), 0, stream, n, pptr.p, pent.p, npf, pressure->faces,
+                               pressure->p, mesh->coords, b);
+            TE_CHECK_HIP(hipGetLastError());
+        }
+        if (dir_mask) {
+            const unsigned gd = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 20);
+            hipLaunchKernelGGL(k_dirichlet, dim3(gd), dim3(256), 0, stream, n, A->row_ptr, A->col_idx, A->val, b,
+                               dir_mask, u_bc);
             TE_CHECK_HIP(hipGetLastError());
         }
         TE_CHECK_HIP(hipStreamSynchronize(stream));

@@ -43,7 +43,8 @@ def test_library_exports_every_declared_symbol():
         assert re.search(rf"\sT {name}$", out, flags=re.M), name
 
 
-STRUCTS = {"te_mesh": "TeMesh", "te_material": "TeMaterial", "te_bsr": "TeBsr", "amg_options": "AmgOptions",
+STRUCTS = {"te_mesh": "TeMesh", "te_material": "TeMaterial", "te_material_tables": "TeMaterialTables",
+           "te_pressure": "TePressure", "te_bsr": "TeBsr", "amg_options": "AmgOptions",
            "amg_info": "AmgInfo", "pcg_options": "PcgOptions", "pcg_report": "PcgReport"}
 
 

@@ -162,3 +162,22 @@ def test_tables_clamp_beyond_their_ends():
         E, nu, a = fem.cell_coefficients(np.full(m.n_nodes, Tv), m.cells.astype(np.int64), 1,
                                          np.zeros(m.n_cells, np.int32), tab)
         assert np.allclose(E, Ee) and np.allclose(a, ae) and np.allclose(nu, 0.25)
+
+
+def test_sampled_rows_equal_the_full_assembly():
+    m = mg.disc_mesh(3, 12, 2, 2)
+    mat = mg.disc_materials(m)
+    tab = fem.MaterialTables(mat.T, mat.E, mat.nu, mat.alpha)
+    T = mg.disc_temperature_ramp(m, 1)
+    faces, p = mg.disc_pressure_faces(m)
+    A, b = fem.assemble_materials(m.coords, m.cells, 2, mat.cell_material, tab, 300.0, T, faces=faces, face_p=p)
+    A = A.tocsr()
+    rows = np.array([0, 5, m.n_nodes // 2, m.n_nodes - 1] + list(np.unique(faces[:4, 3:].ravel())))
+    got = fem.assemble_rows_materials(m.coords, m.cells, 2, mat.cell_material, tab, 300.0, T, rows, faces=faces,
+                                      face_p=p)
+    for r in rows.tolist():
+        cols, blocks, brow = got[r]
+        for k, c in enumerate(cols.tolist()):
+            ref = A[3 * r:3 * r + 3, 3 * c:3 * c + 3].toarray()
+            assert np.allclose(blocks[k], ref, rtol=0, atol=1e-12 * abs(A).max())
+        assert np.allclose(brow, b[r], rtol=0, atol=1e-12 * np.abs(b).max())
