@@ -1,7 +1,7 @@
 """Measurements of the batched and learned forms against plain float64 PCG-AMG
 on the same GPU, at the same true relative residual 1e-8.
 
-    python -m paper_1804_10060_amd.forms [block|multi|learned|all] [--quick]
+    python -m paper_1804_10060_amd.forms [block|multi|learned|materials|all] [--quick]
 
 Prints one JSON object.  Workloads (seeded, synthetic):
   block   : 64 thermal load cases (4-16 Gaussian bumps, U[0,500] K) on the
@@ -12,7 +12,10 @@ Prints one JSON object.  Workloads (seeded, synthetic):
   learned : P1 disc 80x344x11 (1,003,104 DOF); 2000 training and 200
             held-out load fields solved by the library, the network trained
             by the library's kernels, then held-out solves from the learned
-            guess vs from zero.
+            guess vs from zero;
+  materials: P2 disc 96x416x12 (12,043,200 DOF) with hub, web and rim
+            materials (temperature tables) and rim/top pressure: assembly
+            against the one-material assembly, and the solve.
 """
 from __future__ import annotations
 
@@ -144,9 +147,54 @@ def learned_form(quick=False):
     return out
 
 
+def materials_form(quick=False):
+    """The disc with hub, web and rim materials (temperature tables) and the
+    rim and top pressures against the one-material disc: assembly and solve."""
+    import paper_1804_10060_amd as te
+    torch = _torch()
+    grid = (24, 104, 3, 2) if quick else mg.DISC_P2_12M
+    prob = mg.disc_problem(*grid, seed=0)
+    m = prob.mesh
+    dev = torch.device("cuda:0")
+    c = torch.from_numpy(m.coords).to(dev)
+    cl = torch.from_numpy(m.cells.astype(np.int32)).to(dev)
+    T = torch.from_numpy(prob.T).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    mat = mg.disc_materials(m)
+    faces, p = mg.disc_pressure_faces(m)
+    cm = torch.from_numpy(mat.cell_material).to(dev)
+    fd = torch.from_numpy(faces).to(dev)
+    pd = torch.from_numpy(p).to(dev)
+
+    def timed(fn, reps=3):
+        out = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) / reps
+
+    (A1, b1), t_plain = timed(lambda: te.assemble(c, cl, grid[3], prob.E, prob.nu, prob.alpha, prob.T_ref, T,
+                                                  mask=mask))
+    (A, b), t_mat = timed(lambda: te.assemble_materials(c, cl, grid[3], (mat.T, mat.E, mat.nu, mat.alpha), cm,
+                                                        prob.T_ref, T, faces=fd, face_p=pd, mask=mask))
+    del A1, b1
+    h = te.AMG(A, c, mask)
+    h.solve(b)
+    u, rep = h.solve(b)
+    out = {"workload": f"P2 disc {grid[0]}x{grid[1]}x{grid[2]}, {m.n_dof} DOF, 3 materials (hub, web, rim; "
+                       f"E, nu, alpha_L tables 250-1000 K), pressure on {len(faces)} rim/top faces",
+           "n_dof": m.n_dof, "assembly_one_material_ms": t_plain * 1e3, "assembly_materials_ms": t_mat * 1e3,
+           "solve_ms": rep.time_ms, "iters": rep.iters[0], "relres_true": rep.relres_true[0],
+           "dof_per_s": m.n_dof / (rep.time_ms * 1e-3)}
+    log(json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", nargs="?", default="all", choices=["block", "multi", "learned", "all"])
+    ap.add_argument("which", nargs="?", default="all", choices=["block", "multi", "learned", "materials", "all"])
     ap.add_argument("--quick", action="store_true")
     a = ap.parse_args()
     out = {}
@@ -156,6 +204,8 @@ def main():
         out["multi_mesh"] = multi_form(a.quick)
     if a.which in ("learned", "all"):
         out["learned_guess"] = learned_form(a.quick)
+    if a.which in ("materials", "all"):
+        out["materials"] = materials_form(a.quick)
     print(json.dumps(out), flush=True)
 
 
