@@ -100,3 +100,88 @@ def pcg_multi(A, Bm, M=None, U0=None, **kw):
     for j in range(Bm.shape[1]):
         res.append(pcg(A, Bm[:, j], M, None if U0 is None else U0[:, j], **kw))
     return res
+
+
+@dataclasses.dataclass
+class BlockResult:
+    U: np.ndarray
+    iters: int
+    converged: list
+    relres_true: list
+    ranks: list
+
+
+def _orth(W, drop_tol):
+    """Orthonormal basis of the columns of W from the eigen-decomposition of
+    W^T W; directions whose singular value is below drop_tol times the
+    largest are dropped."""
+    G = W.T @ W
+    lam, V = np.linalg.eigh(0.5 * (G + G.T))
+    if lam[-1] <= 0.0:
+        return W[:, :0]
+    keep = lam > (drop_tol ** 2) * lam[-1]
+    return W @ (V[:, keep] / np.sqrt(lam[keep]))
+
+
+def block_pcg(A, B, M=None, U0=None, rtol=1e-8, maxit=500, max_replace=3, drop_tol=1e-6):
+    """Block preconditioned CG over the columns of B [n, m] (O'Leary, Linear
+    Algebra Appl. 29, 1980): one Krylov space shared by all columns,
+
+        R = B - A X;  Z = M^-1 R;  P = orth(Z)
+        repeat:  Q = A P;  alpha = (P^T Q)^-1 (P^T R);  X += P alpha;  R -= Q alpha
+                 stop test;  Z = M^-1 R;  beta = -(P^T Q)^-1 (Q^T Z);  P = orth(Z + P beta)
+
+    with the search block orthonormalised every step and its numerically
+    dependent directions dropped, which keeps P^T A P invertible when columns
+    converge or become dependent (the breakdown-free form of Ji and Li, 2017;
+    Dubrulle, ETNA 12, 2001).  The rank test is on the singular values of the
+    block relative to the largest (drop_tol; computed from the Gram matrix,
+    whose rounding puts numerically dependent directions near sqrt(eps), so
+    the default is 1e-6).  M: callable on one column (applied per column).
+    Stop test per column as in pcg(): the recurrence residual triggers a true
+    residual check of every column once all columns pass."""
+    mat = A if callable(A) else (lambda x: A @ x)
+    prec = M if M is not None else (lambda r: r.copy())
+    n, m = B.shape
+    bnorm = np.linalg.norm(B, axis=0)
+    X = np.zeros_like(B) if U0 is None else U0.astype(np.float64).copy()
+
+    def matb(Y):
+        return np.stack([mat(Y[:, j]) for j in range(Y.shape[1])], axis=1) if Y.shape[1] else Y.copy()
+
+    def precb(Y):
+        return np.stack([prec(Y[:, j]) for j in range(Y.shape[1])], axis=1)
+
+    def rel(Rm):
+        return np.where(bnorm > 0, np.linalg.norm(Rm, axis=0) / np.where(bnorm > 0, bnorm, 1.0), 0.0)
+
+    R = B - matb(X)
+    ranks = []
+    it = 0
+    replaced = 0
+    if np.all(rel(R) <= rtol):
+        return BlockResult(X, 0, [True] * m, rel(R).tolist(), ranks)
+    Z = precb(R)
+    P = _orth(Z, drop_tol)
+    while it < maxit and P.shape[1] > 0:
+        ranks.append(P.shape[1])
+        Q = matb(P)
+        PQ = P.T @ Q
+        alpha = np.linalg.solve(PQ, P.T @ R)
+        X = X + P @ alpha
+        R = R - Q @ alpha
+        it += 1
+        if np.all(rel(R) <= rtol):
+            Rt = B - matb(X)
+            rt = rel(Rt)
+            if np.all(rt <= rtol):
+                return BlockResult(X, it, [True] * m, rt.tolist(), ranks)
+            if replaced >= max_replace:
+                return BlockResult(X, it, (rt <= rtol).tolist(), rt.tolist(), ranks)
+            replaced += 1
+            R = Rt
+        Z = precb(R)
+        beta = -np.linalg.solve(PQ, Q.T @ Z)
+        P = _orth(Z + P @ beta, drop_tol)
+    rt = rel(B - matb(X))
+    return BlockResult(X, it, (rt <= rtol).tolist(), rt.tolist(), ranks)

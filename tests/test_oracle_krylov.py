@@ -123,3 +123,78 @@ def test_underestimated_eigenvalue_breaks_cg():
     except krylov.Breakdown:
         failed = True
     assert failed
+
+
+# ---------------------------------------------------------------------------
+# block CG (O'Leary 1980) with orthonormalised search blocks
+# ---------------------------------------------------------------------------
+
+def _laplace1d(n):
+    import scipy.sparse as sp
+    return sp.diags([-np.ones(n - 1), 2.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+
+
+def test_block_cg_with_one_column_is_cg():
+    """m = 1: the search block is the normalised CG direction, so the
+    iterates are those of CG."""
+    A = _laplace1d(60)
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=60)
+    M = lambda r: r / 2.0
+    res = krylov.pcg(A, b, M, rtol=1e-10)
+    blk = krylov.block_pcg(A, b[:, None], M, rtol=1e-10)
+    assert blk.iters == res.iters
+    assert np.abs(blk.U[:, 0] - res.u).max() <= 1e-10 * np.abs(res.u).max()
+
+
+def test_block_cg_terminates_in_n_over_m_steps():
+    """Finite termination: with m right-hand sides the shared Krylov space of
+    an n x n SPD matrix is exhausted after ceil(n / m) steps."""
+    n, m = 48, 8
+    A = _laplace1d(n)
+    rng = np.random.default_rng(5)
+    B = rng.normal(size=(n, m))
+    blk = krylov.block_pcg(A, B, rtol=1e-11, maxit=n // m)
+    assert blk.iters <= n // m and all(blk.converged)
+    X = np.linalg.solve(A.toarray(), B)
+    assert np.abs(blk.U - X).max() <= 1e-9 * np.abs(X).max()
+
+
+def test_block_cg_drops_dependent_directions():
+    """Dependent right-hand sides (a multiple, a sum, a zero column) make the
+    first block rank deficient: the dependent directions are dropped and every
+    column is still solved."""
+    A = _laplace1d(40)
+    rng = np.random.default_rng(7)
+    b0, b1 = rng.normal(size=40), rng.normal(size=40)
+    B = np.stack([b0, 2.0 * b0, b0 + b1, b1, np.zeros(40)], axis=1)
+    blk = krylov.block_pcg(A, B, lambda r: r / 2.0, rtol=1e-10)
+    assert blk.ranks[0] == 2 and all(blk.converged)
+    X = np.linalg.solve(A.toarray(), B)
+    assert np.abs(blk.U - X).max() <= 1e-8 * np.abs(X).max()
+
+
+def test_block_cg_with_amg_solves_the_disc_load_cases():
+    """Twelve bump load cases on a small P1 disc with the oracle's AMG: every
+    column meets the true residual, agrees with its direct solve to the
+    accuracy the residual allows, and the shared Krylov space needs fewer
+    steps than the slowest single solve."""
+    prob = mg.disc_problem(8, 34, 2, 1, seed=0)
+    m = prob.mesh
+    A0, _ = fem.assemble(m.coords, m.cells, 1, prob.E, prob.nu, prob.alpha, prob.T_ref, prob.T)
+    cols = []
+    for s in range(1000, 1012):
+        _, b = fem.assemble(m.coords, m.cells, 1, prob.E, prob.nu, prob.alpha, prob.T_ref,
+                            mg.disc_temperature_bumps(m, s))
+        cols.append(fem.apply_dirichlet(A0, b, prob.mask)[1])
+    A, _ = fem.apply_dirichlet(A0, cols[0], prob.mask)
+    B = np.stack(cols, axis=1)
+    opt = amg.AMGOptions(coarse_max=300)
+    levels = amg.setup(A, fem.rigid_body_modes(m.coords, prob.mask), opt)
+    M = lambda r: amg.vcycle(levels, r, opt=opt)
+    blk = krylov.block_pcg(A, B, M)
+    assert all(blk.converged) and max(blk.relres_true) <= 1e-8
+    X = spla.spsolve(A.tocsc(), B)
+    assert np.abs(blk.U - X).max() <= 1e-6 * np.abs(X).max()
+    single = max(krylov.pcg(A, B[:, j], M).iters for j in range(B.shape[1]))
+    assert blk.iters < single
