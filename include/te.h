@@ -246,6 +246,8 @@ typedef struct {
     int32_t precision;       /* TE_PREC_FP64 or TE_PREC_MIXED                           */
     int32_t max_replace;     /* residual replacements after a failed true check (3)     */
     int32_t profile;         /* 1: time each kernel class with HIP events (0)           */
+    int32_t block;           /* 1: block CG over the columns when nrhs > 1, float64
+                                only (0; see amg_pcg_solve)                             */
 } pcg_options;
 
 /* Kernel classes timed when pcg_options.profile = 1 (level 0 = mesh level):   */
@@ -283,7 +285,16 @@ typedef struct {
  *   rep: host, may be NULL.
  * Each column runs its own CG recurrence (the columns share every sparse
  * product); a converged column is frozen.  MIXED runs the V-cycle in float32
- * and uses the flexible beta.  Synchronises `stream`.
+ * and uses the flexible beta.
+ * With opt->block = 1 and nrhs > 1 the columns instead share one block
+ * Krylov space (block CG, O'Leary 1980, with the search block orthonormalised
+ * each step and numerically dependent directions dropped): every column takes
+ * the same number of iterations, usually fewer than its own CG, and the stop
+ * test waits for all of them; iters[j] is that common count, history is NaN,
+ * the per-kernel profile is not kept, and the setup's solve workspace for
+ * nrhs columns plus small buffers allocated per call are used.  Block CG
+ * with MIXED is TE_EINVAL; a block P^T A P that is not positive definite is
+ * TE_EINDEF.  Synchronises `stream`.
  * Returns TE_OK, TE_ENOTCONV (some column hit maxit), TE_EINDEF, TE_ENAN,
  * TE_EINVAL, TE_EHIP. */
 int amg_pcg_solve(amg_handle *h, const double *b, double *u, int32_t nrhs,

@@ -188,6 +188,7 @@ class AMG:
                 raise TypeError(f"unknown AMG option {k}")
             setattr(o, k, v)
         self.opts = o
+        self._cd = load()  # kept for __del__, which can run after module teardown
         self._h = C.c_void_p(0)
         bsr = A.c()
         if aggregates is None:
@@ -201,11 +202,9 @@ class AMG:
         self.n = n
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        # at interpreter exit the module globals may already be gone; the
-        # process end releases the device memory then
-        if h is not None and h.value and load is not None:
-            load().amg_destroy(h)
+        h, lib = getattr(self, "_h", None), getattr(self, "_cd", None)
+        if h is not None and h.value and lib is not None:
+            lib.amg_destroy(h)
             self._h = C.c_void_p(0)
 
     def close(self):
@@ -269,8 +268,9 @@ class AMG:
 
     # ---- solve ----------------------------------------------------------
     def solve(self, b, u0=None, rtol=1e-8, maxit=500, precision="fp64", max_replace=3, history=False,
-              allow_notconv=False, profile=False):
-        """Returns (u, SolveReport).  b: [3N] or [N, 3, nrhs] float64 device tensor."""
+              allow_notconv=False, profile=False, block=False):
+        """Returns (u, SolveReport).  b: [3N] or [N, 3, nrhs] float64 device tensor.
+        block: one block CG over the nrhs columns instead of nrhs CG recurrences."""
         torch = _torch()
         import numpy as np
         nrhs = 1 if b.dim() == 1 else b.shape[-1]
@@ -280,7 +280,7 @@ class AMG:
         u = torch.zeros_like(b) if u0 is None else _dev(u0, torch.float64, tuple(b.shape), "u0").clone()
         o = _lib.PcgOptions()
         load().pcg_options_default(C.byref(o))
-        o.rtol, o.maxit, o.max_replace, o.profile = rtol, maxit, max_replace, int(profile)
+        o.rtol, o.maxit, o.max_replace, o.profile, o.block = rtol, maxit, max_replace, int(profile), int(block)
         o.precision = {"fp64": TE_PREC_FP64, "mixed": TE_PREC_MIXED}[precision] if isinstance(precision, str) \
             else precision
         iters = np.zeros(nrhs, np.int32)
@@ -332,16 +332,15 @@ class MPNN:
         _dev(coords, torch.float64, (A.n, 3), "coords")
         self.n = A.n
         self.n_params = int(lib.mpnn_param_count())
+        self._cd = lib  # kept for __del__, which can run after module teardown
         self._h = C.c_void_p(0)
         check(lib.mpnn_create(A.n, _ptr(A.row_ptr), _ptr(A.col_idx), _ptr(coords), C.byref(self._h), _stream()))
         self.device = coords.device
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        # at interpreter exit the module globals may already be gone; the
-        # process end releases the device memory then
-        if h is not None and h.value and load is not None:
-            load().mpnn_destroy(h)
+        h, lib = getattr(self, "_h", None), getattr(self, "_cd", None)
+        if h is not None and h.value and lib is not None:
+            lib.mpnn_destroy(h)
             self._h = C.c_void_p(0)
 
     def features(self, T, T_ref, mask, f=None):

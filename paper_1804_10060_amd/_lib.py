@@ -64,7 +64,7 @@ class AmgInfo(C.Structure):
 
 class PcgOptions(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxit", C.c_int32), ("precision", C.c_int32), ("max_replace", C.c_int32),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("block", C.c_int32)]
 
 
 class PcgReport(C.Structure):

@@ -223,6 +223,21 @@ void dot_partials(const double *a, const double *b, int64_t n, int nrhs, double 
 // parts the sum takes two passes whose chunk sums are written after the
 // input: the buffer must then hold (nparts + min(1024, nparts/64)) * nrhs.
 void reduce_partials(const double *partials, int nparts, int nrhs, double *out, hipStream_t s);
+
+// Block CG kernels (te_block.hip); block vectors [rows][m], m <= 64, small
+// matrices 64 x 64 row-major (entries beyond m or the block rank are zero).
+//   block_gram: out[p] = mats[li[p]]^T mats[ri[p]] for p < npair (npair,
+//     nmat <= 3); partials: block_gram_nblocks() * npair * 4096 doubles.
+//   block_xr:   X += P alpha, R -= Q alpha; partials[b * m + j] = partial
+//     sums of R_j^2 over block_xr_nblocks(rows) workgroups.
+//   block_p:    P <- Z T1 + P T2 (in place).
+int block_gram_nblocks();
+int block_xr_nblocks(int64_t rows);
+void block_gram(const double *const *mats, int nmat, const int *li, const int *ri, int npair, int64_t rows, int m,
+                double *partials, double *out, hipStream_t s);
+void block_xr(int64_t rows, int m, const double *alpha, const double *P, const double *Q, double *X, double *R,
+              double *partials, hipStream_t s);
+void block_p(int64_t rows, int m, const double *T1, const double *T2, const double *Z, double *P, hipStream_t s);
 void reduce_pairs(const double *partials, int nparts, int nrhs, double *out, hipStream_t s);
 void cg_update(double *u, double *r, double *r_old, const double *p, const double *q, const double *alpha,
                int64_t rows, int nrhs, double *partials, hipStream_t s);

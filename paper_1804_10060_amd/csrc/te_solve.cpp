@@ -172,6 +172,288 @@ static void fetch(const double *dsum, int count, std::vector<double> &out, hipSt
     TE_CHECK_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------------------
+// Block CG (O'Leary, Linear Algebra Appl. 29, 1980) over the columns
+// ---------------------------------------------------------------------------
+// One Krylov space shared by the m columns, with the search block
+// orthonormalised every step and its numerically dependent directions
+// dropped (the breakdown-free form of Ji and Li 2017; Dubrulle 2001):
+//   R = B - A X;  Z = M^-1 R;  P = orth(Z)
+//   repeat:  Q = A P;  alpha = (P^T Q)^-1 (P^T R);  X += P alpha;  R -= Q alpha
+//            stop test;  Z = M^-1 R;  beta = -(P^T Q)^-1 (Q^T Z);  P = orth(Z + P beta)
+// The m x m algebra runs on the host in float64.  orth uses a pivoted
+// Cholesky factor of the Gram matrix (W^T W = Pi L L^T Pi^T, P = W Pi L^-T),
+// dropping directions whose remaining pivot is below (1e-6)^2 of the largest
+// diagonal; P^T R, P^T Q, P^T P, P^T Z, Q^T Z, Z^T Z come from two fused
+// passes over the block vectors, and W^T W = Z^T Z + beta^T P^T Z +
+// Z^T P beta + beta^T P^T P beta is formed from them.
+namespace {
+constexpr int BM = 64;
+
+struct Small {  // 64 x 64 row-major, zero-padded
+    std::vector<double> a = std::vector<double>(BM * BM, 0.0);
+    double &operator()(int i, int j) { return a[(size_t)i * BM + j]; }
+    double operator()(int i, int j) const { return a[(size_t)i * BM + j]; }
+};
+
+// X = G^-1 Y for the leading r x r block of an SPD G (Cholesky); false if G
+// is not positive definite there.  Y, X: r x m.
+bool chol_solve(const Small &G, int r, const Small &Y, int m, Small &X) {
+    std::vector<double> L((size_t)r * r, 0.0);
+    for (int j = 0; j < r; ++j) {
+        double d = G(j, j);
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * r + k] * L[(size_t)j * r + k];
+        if (!(d > 0.0)) return false;
+        L[(size_t)j * r + j] = std::sqrt(d);
+        for (int i = j + 1; i < r; ++i) {
+            double v = G(i, j);
+            for (int k = 0; k < j; ++k) v -= L[(size_t)i * r + k] * L[(size_t)j * r + k];
+            L[(size_t)i * r + j] = v / L[(size_t)j * r + j];
+        }
+    }
+    X = Small();
+    for (int c = 0; c < m; ++c) {
+        std::vector<double> y(r);
+        for (int i = 0; i < r; ++i) {
+            double v = Y(i, c);
+            for (int k = 0; k < i; ++k) v -= L[(size_t)i * r + k] * y[k];
+            y[i] = v / L[(size_t)i * r + i];
+        }
+        for (int i = r - 1; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < r; ++k) v -= L[(size_t)k * r + i] * X(k, c);
+            X(i, c) = v / L[(size_t)i * r + i];
+        }
+    }
+    return true;
+}
+
+// T (m x rank) with (W T)^T (W T) = I from the Gram matrix G = W^T W.
+int orth_transform(const Small &G, int m, double drop_tol, Small &T) {
+    Small A = G;
+    std::vector<int> perm(m);
+    for (int i = 0; i < m; ++i) perm[i] = i;
+    double d0 = 0.0;
+    for (int i = 0; i < m; ++i) d0 = std::max(d0, A(i, i));
+    Small L;
+    int rank = 0;
+    for (int k = 0; k < m && d0 > 0.0; ++k) {
+        int q = k;
+        for (int i = k + 1; i < m; ++i)
+            if (A(i, i) > A(q, q)) q = i;
+        if (!(A(q, q) > drop_tol * drop_tol * d0)) break;
+        if (q != k) {
+            std::swap(perm[k], perm[q]);
+            for (int j = 0; j < m; ++j) std::swap(A.a[(size_t)k * BM + j], A.a[(size_t)q * BM + j]);
+            for (int i = 0; i < m; ++i) std::swap(A.a[(size_t)i * BM + k], A.a[(size_t)i * BM + q]);
+            for (int j = 0; j < k; ++j) std::swap(L.a[(size_t)k * BM + j], L.a[(size_t)q * BM + j]);
+        }
+        const double lkk = std::sqrt(A(k, k));
+        L(k, k) = lkk;
+        for (int i = k + 1; i < m; ++i) L(i, k) = A(i, k) / lkk;
+        for (int i = k + 1; i < m; ++i)
+            for (int j = k + 1; j <= i; ++j) {
+                A(i, j) -= L(i, k) * L(j, k);
+                A(j, i) = A(i, j);
+            }
+        ++rank;
+    }
+    // T = Pi[:, :rank] L_r^-T: solve L_r^T Y = I (upper triangular) column by column
+    T = Small();
+    for (int c = 0; c < rank; ++c) {
+        std::vector<double> y(rank, 0.0);
+        for (int i = rank - 1; i >= 0; --i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int k = i + 1; k < rank; ++k) v -= L(k, i) * y[k];
+            y[i] = v / L(i, i);
+        }
+        for (int i = 0; i < rank; ++i) T(perm[i], c) = y[i];
+    }
+    return rank;
+}
+
+Small matmul(const Small &A, const Small &B, int n, int k, int m) {  // (n x k)(k x m)
+    Small C;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < m; ++j) {
+            double v = 0.0;
+            for (int l = 0; l < k; ++l) v += A(i, l) * B(l, j);
+            C(i, j) = v;
+        }
+    return C;
+}
+}  // namespace
+
+static int block_solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, const pcg_options &o,
+                            pcg_report *rep, hipStream_t s) {
+    TE_REQUIRE(o.precision == TE_PREC_FP64, TE_EINVAL, "block CG runs in float64");
+    const double drop_tol = 1e-6;
+    Level &L0 = h->L[0];
+    const int64_t n = L0.n, rows = n * 3, nv = rows * m;
+    double *part = h->partials.p, *sums = h->sums.p;
+    h->prof.reset(false, s);
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    TE_CHECK_HIP(hipEventCreate(&ev.a));
+    TE_CHECK_HIP(hipEventCreate(&ev.b));
+    TE_CHECK_HIP(hipEventRecord(ev.a, s));
+    double *X = h->u.p, *R = h->r.p, *Z = h->z.p, *P = h->p.p, *Q = h->q.p, *B = h->b.p, *Tt = h->t.p;
+    permute_gather(b_nat, B, L0.perm.p, n, 3, m, s);
+    permute_gather(u_nat, X, L0.perm.p, n, 3, m, s);
+    DBuf<double> gpart((size_t)block_gram_nblocks() * 3 * BM * BM), gout(3 * BM * BM), smalls(2 * BM * BM);
+    const int nxr = block_xr_nblocks(rows);
+    DBuf<double> xpart((size_t)(nxr + 1024) * m);
+    std::vector<double> bb, rr, tr;
+    dot_partials(B, B, nv, m, part, s);
+    reduce_partials(part, dot_nblocks(rows), m, sums, s);
+    fetch(sums, m, bb, s);
+    auto rel_of = [&](const std::vector<double> &v, std::vector<double> &out) {
+        out.resize(m);
+        bool all = true;
+        for (int j = 0; j < m; ++j) {
+            TE_REQUIRE(std::isfinite(v[j]), TE_ENAN, "NaN in block CG column %d", j);
+            out[j] = bb[j] > 0 ? std::sqrt(v[j] / bb[j]) : 0.0;
+            all = all && out[j] <= o.rtol;
+        }
+        return all;
+    };
+    auto gram = [&](std::initializer_list<const double *> mats, std::initializer_list<std::pair<int, int>> pairs,
+                    std::vector<Small> &res) {
+        const double *mv[3];
+        int li[3], ri[3], k = 0;
+        for (const double *p : mats) mv[k++] = p;
+        const int nmat = k;
+        k = 0;
+        for (auto pr : pairs) {
+            li[k] = pr.first;
+            ri[k] = pr.second;
+            ++k;
+        }
+        block_gram(mv, nmat, li, ri, k, rows, m, gpart.p, gout.p, s);
+        std::vector<double> hbuf;
+        fetch(gout.p, k * BM * BM, hbuf, s);
+        res.assign(k, Small());
+        for (int p = 0; p < k; ++p) std::copy(hbuf.begin() + (size_t)p * BM * BM, hbuf.begin() + (size_t)(p + 1) * BM * BM,
+                                              res[p].a.begin());
+    };
+    auto put_small = [&](const Small &A0, const Small &A1) {
+        std::vector<double> hbuf(2 * BM * BM);
+        std::copy(A0.a.begin(), A0.a.end(), hbuf.begin());
+        std::copy(A1.a.begin(), A1.a.end(), hbuf.begin() + BM * BM);
+        TE_CHECK_HIP(hipMemcpyAsync(smalls.p, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        TE_CHECK_HIP(hipStreamSynchronize(s));
+    };
+    // R = B - A X
+    sell_resid_norm(L0.A, X, B, R, m, part, s);
+    reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+    fetch(sums, m, rr, s);
+    std::vector<double> rel;
+    bool done = rel_of(rr, rel);
+    int it = 0, replaced = 0, rank = 0;
+    std::vector<Small> g1, g2;
+    if (!done) {
+        precondition(h, R, Z, m, false, s);
+        gram({Z}, {{0, 0}}, g2);
+        Small T;
+        rank = orth_transform(g2[0], m, drop_tol, T);
+        TE_CHECK_HIP(hipMemsetAsync(P, 0, nv * sizeof(double), s));
+        put_small(T, Small());
+        block_p(rows, m, smalls.p, smalls.p + BM * BM, Z, P, s);
+    }
+    bool conv = done;
+    while (!done && rank > 0 && it < o.maxit) {
+        sell_apply<double>(L0.A, P, Q, nullptr, 0, m, s);
+        gram({P, Q, R}, {{0, 1}, {0, 2}, {0, 0}}, g1);  // P^T Q, P^T R, P^T P
+        Small alpha;
+        TE_REQUIRE(chol_solve(g1[0], rank, g1[1], m, alpha), TE_EINDEF, "block CG breakdown: P^T A P is not SPD");
+        put_small(alpha, Small());
+        block_xr(rows, m, smalls.p, P, Q, X, R, xpart.p, s);
+        reduce_partials(xpart.p, nxr, m, sums, s);
+        fetch(sums, m, rr, s);
+        ++it;
+        if (rel_of(rr, rel)) {
+            sell_resid_norm(L0.A, X, B, Tt, m, part, s);
+            reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+            fetch(sums, m, tr, s);
+            if (rel_of(tr, rel)) {
+                conv = true;
+                break;
+            }
+            if (replaced >= o.max_replace) break;
+            ++replaced;
+            TE_CHECK_HIP(hipMemcpyAsync(R, Tt, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        precondition(h, R, Z, m, false, s);
+        gram({P, Q, Z}, {{0, 2}, {1, 2}, {2, 2}}, g2);  // P^T Z, Q^T Z, Z^T Z
+        Small beta;
+        TE_REQUIRE(chol_solve(g1[0], rank, g2[1], m, beta), TE_EINDEF, "block CG breakdown: P^T A P is not SPD");
+        for (double &v : beta.a) v = -v;
+        // W^T W with W = Z + P beta
+        Small G = g2[2];
+        const Small btPZ = [&] {  // beta^T (P^T Z)
+            Small c;
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) {
+                    double v = 0.0;
+                    for (int l = 0; l < rank; ++l) v += beta(l, i) * g2[0](l, j);
+                    c(i, j) = v;
+                }
+            return c;
+        }();
+        const Small PPb = matmul(g1[2], beta, rank, rank, m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                double v = 0.0;
+                for (int l = 0; l < rank; ++l) v += beta(l, i) * PPb(l, j);
+                G(i, j) += btPZ(i, j) + btPZ(j, i) + v;
+            }
+        Small T;
+        const int nr = orth_transform(G, m, drop_tol, T);
+        const Small T2 = matmul(beta, T, rank, m, nr);  // P_new = Z T + P (beta T)
+        put_small(T, T2);
+        block_p(rows, m, smalls.p, smalls.p + BM * BM, Z, P, s);
+        rank = nr;
+    }
+    if (!conv) {  // final true residual of every column
+        sell_resid_norm(L0.A, X, B, Tt, m, part, s);
+        reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+        fetch(sums, m, tr, s);
+        rel_of(tr, rel);
+    }
+    permute_scatter(X, u_nat, L0.perm.p, n, 3, m, s);
+    TE_CHECK_HIP(hipEventRecord(ev.b, s));
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    TE_CHECK_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+    bool all = true;
+    for (int j = 0; j < m; ++j) {
+        const bool cj = rel[j] <= o.rtol;
+        all = all && cj;
+        if (rep) {
+            if (rep->iters) rep->iters[j] = it;
+            if (rep->converged) rep->converged[j] = cj;
+            if (rep->relres_true) rep->relres_true[j] = rel[j];
+        }
+    }
+    if (rep) {
+        if (rep->history)
+            for (int k = 0; k <= o.maxit; ++k)
+                for (int j = 0; j < m; ++j) rep->history[(size_t)k * m + j] = NAN;
+        rep->max_iters = it;
+        rep->time_ms = ms;
+        for (int c = 0; c < TE_K_COUNT; ++c) {
+            rep->kernel_ms[c] = 0.0;
+            rep->kernel_launches[c] = 0;
+        }
+    }
+    return all ? TE_OK : TE_ENOTCONV;
+}
+
 static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, const pcg_options *opt_in,
                       pcg_report *rep, hipStream_t s) {
     TE_REQUIRE(h && b_nat && u_nat, TE_EINVAL, "NULL argument");
@@ -183,6 +465,7 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
     const bool mixed = o.precision == TE_PREC_MIXED;
     TE_REQUIRE(o.precision == TE_PREC_FP64 || mixed, TE_EINVAL, "unknown precision %d", o.precision);
     TE_REQUIRE(!mixed || h->opt.build_fp32, TE_EINVAL, "mixed precision needs build_fp32 at setup");
+    if (o.block && m > 1) return block_solve_impl(h, b_nat, u_nat, m, o, rep, s);
     Level &L0 = h->L[0];
     const int64_t n = L0.n, rows = n * 3, nv = rows * m;
     CgScalars *S = reinterpret_cast<CgScalars *>(h->scal.p);
@@ -498,6 +781,7 @@ extern "C" void pcg_options_default(pcg_options *o) {
     o->precision = TE_PREC_FP64;
     o->max_replace = 3;
     o->profile = 0;
+    o->block = 0;
 }
 
 extern "C" int amg_pcg_solve(amg_handle *h, const double *b, double *u, int32_t nrhs, const pcg_options *opt,

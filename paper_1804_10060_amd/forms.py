@@ -56,6 +56,13 @@ def block_form(quick=False):
     U, rep = pr.amg.solve(B)
     torch.cuda.synchronize()
     t_block = time.perf_counter() - t0
+    # block CG: one Krylov space over the k columns
+    pr.amg.solve(B[:, :, :2].contiguous(), block=True)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ub, repb = pr.amg.solve(B, block=True)
+    torch.cuda.synchronize()
+    t_bcg = time.perf_counter() - t0
     singles, diffs, its = 0.0, [], []
     for j in range(k):
         bj = B[:, :, j].reshape(-1).contiguous()
@@ -71,6 +78,10 @@ def block_form(quick=False):
            "speedup": singles / t_block, "block_iters_max": max(rep.iters), "single_iters_mean": float(np.mean(its)),
            "all_converged": bool(all(rep.converged)), "max_relres_true": max(rep.relres_true),
            "max_rel_diff_vs_single": max(diffs),
+           "block_cg_s": t_bcg, "block_cg_iters": repb.iters[0], "block_cg_speedup": singles / t_bcg,
+           "block_cg_all_converged": bool(all(repb.converged)), "block_cg_max_relres_true": max(repb.relres_true),
+           "block_cg_max_rel_diff_vs_single": float(max((Ub[:, :, j] - U[:, :, j]).norm() / U[:, :, j].norm()
+                                                        for j in range(k))),
            "dof_rhs_per_s_block": pr.mesh.n_dof * k / t_block, "dof_rhs_per_s_single": pr.mesh.n_dof * k / singles}
     log(json.dumps(out))
     return out
