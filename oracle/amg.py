@@ -18,6 +18,15 @@ is silent the following readings are taken (each is a parameter):
               a relative 1e-9 counting as equal and then the smaller aggregate
               id winning.  Nodes with no strong neighbour (e.g. clamped) are
               isolated and left out of every aggregate.
+* parallel aggregation (option "mis2"): the phase-1 roots are the maximal
+              distance-2 independent set of the strong graph (made symmetric)
+              chosen by fixed priorities in parallel rounds (Luby's rounds
+              with fixed keys; Bell, Dalton & Olson 2012 use them for
+              aggregation).  With fixed keys the rounds select exactly the
+              set the sequential phase 1 selects when it visits the nodes in
+              descending key order (Blelloch, Fineman & Shun 2012).  Key of
+              node I on level l: (splitmix64((0xA66 + l) ^ I) >> 33, I).
+              Aggregates are numbered by ascending root; phase 2 as above.
 * tentative P: per aggregate (nodes ascending) the thin QR B_J = Q_J R_J with
               diag(R_J) > 0; rank deficiency (min |R_kk| < 1e-10 max |R_kk|)
               merges the aggregate into its neighbour aggregate of largest
@@ -43,7 +52,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from .rng import uniform01_vec
+from .rng import splitmix64_vec, uniform01_vec
 
 TIE_RTOL = 1e-9
 RANK_RTOL = 1e-10
@@ -59,6 +68,7 @@ class AMGOptions:
     cheb_ratio: float = 10.0     # a = b / cheb_ratio
     cheb_safety: float = 1.1     # b = cheb_safety * lambda_hat
     max_coarse_ratio: float = 0.8
+    aggregation: str = "greedy"  # or "mis2"
 
 
 class RankError(RuntimeError):
@@ -115,7 +125,15 @@ def aggregate(A: sp.bsr_matrix, theta: float):
             agg[i] = n_agg
             agg[nb] = n_agg
             n_agg += 1
-    # phase 2: attach the rest to the strongest neighbour's phase-1 aggregate
+    return _attach_rest(agg, nbrs), n_agg, (rows, cols, s)
+
+
+def _attach_rest(agg, nbrs):
+    """Phase 2: every node with strong neighbours that is not in a phase-1
+    aggregate joins the phase-1 aggregate of its strongest aggregated
+    neighbour (relative ties within TIE_RTOL: the smaller aggregate id)."""
+    n = agg.shape[0]
+    agg = agg.copy()
     snap = agg.copy()
     for i in range(n):
         nb, sv = nbrs[i]
@@ -132,7 +150,83 @@ def aggregate(A: sp.bsr_matrix, theta: float):
                 best_s, best_a = sj, a
         assert best_a >= 0, "non-isolated node with no aggregated strong neighbour"
         agg[i] = best_a
-    return agg, n_agg, (rows, cols, s)
+    return agg
+
+
+MIS_SEED = 0xA66
+IN, UNDECIDED, OUT = 2, 1, 0
+
+
+def mis_keys(n, seed):
+    """Fixed priority key of each node: (splitmix64(seed ^ I) >> 33, I) packed
+    as prio * 2^30 + I (I < 2^30)."""
+    assert n < (1 << 30)
+    prio = (splitmix64_vec(seed, n) >> np.uint64(33)).astype(np.int64)
+    return prio * (1 << 30) + np.arange(n, dtype=np.int64)
+
+
+def symmetric_strong(A: sp.bsr_matrix, theta: float):
+    """Per stored block: strong if s_IJ >= theta or s_JI >= theta (I != J).
+    The two agree for a symmetric A up to rounding; taking both makes the
+    strong graph symmetric by construction.  Returns (flag, (rows, cols, s))."""
+    rows, cols, s = strength(A)
+    own = (s >= theta) & (rows != cols)
+    n = A.shape[0] // A.blocksize[0]
+    key = rows * n + cols
+    order = np.argsort(key)
+    tkey = cols * n + rows
+    tpos = order[np.searchsorted(key[order], tkey)]   # entry k = (I, J) -> position of (J, I)
+    assert np.array_equal(key[tpos], tkey), "pattern not symmetric"
+    return own | own[tpos], (rows, cols, s)
+
+
+def mis2_rounds(n, rows, cols, flag, keys):
+    """Distance-2 maximal independent set of the graph given by the flagged
+    entries, by rounds: key*(I) = (state, key) with IN > UNDECIDED > OUT;
+    m1(I) = max of key* over I and its neighbours, m2(I) = max of m1 over I
+    and its neighbours (= over all nodes within distance 2).  An undecided
+    node whose m2 is its own key* joins the set; an undecided node whose m2
+    belongs to a member is excluded.  Returns (in_set bool[n], rounds)."""
+    r, c = rows[flag], cols[flag]
+    has = np.zeros(n, bool)
+    has[r] = True
+    state = np.where(has, UNDECIDED, OUT).astype(np.int64)
+    rounds = 0
+    while np.any(state == UNDECIDED):
+        k = state * (1 << 61) + keys
+        m1 = k.copy()
+        np.maximum.at(m1, r, k[c])
+        m2 = m1.copy()
+        np.maximum.at(m2, r, m1[c])
+        und = state == UNDECIDED
+        join = und & (m2 == k)
+        drop = und & ((m2 >> 61) == IN)
+        state[join] = IN
+        state[drop] = OUT
+        rounds += 1
+    return state == IN, rounds
+
+
+def aggregate_mis2(A: sp.bsr_matrix, theta: float, seed: int):
+    """Parallel aggregation: phase-1 roots by mis2_rounds on the symmetric
+    strong graph, aggregates numbered by ascending root, phase-1 aggregate =
+    root and its strong neighbours, then phase 2 (_attach_rest).
+    Returns (agg, n_agg, (rows, cols, s))."""
+    n = A.shape[0] // A.blocksize[0]
+    flag, sinfo = symmetric_strong(A, theta)
+    rows, cols, s = sinfo
+    roots, _ = mis2_rounds(n, rows, cols, flag, mis_keys(n, seed))
+    agg = np.full(n, -1, np.int64)
+    ids = np.cumsum(roots) - 1
+    agg[roots] = ids[roots]
+    sel = flag & roots[rows]
+    hits = np.bincount(cols[sel], minlength=n)
+    assert hits.max(initial=0) <= 1 and not np.any(roots[cols[sel]]), "phase-1 aggregates overlap"
+    agg[cols[sel]] = ids[rows[sel]]
+    ptr = A.indptr
+    nbrs = [(cols[ptr[i]:ptr[i + 1]][flag[ptr[i]:ptr[i + 1]]], s[ptr[i]:ptr[i + 1]][flag[ptr[i]:ptr[i + 1]]])
+            for i in range(n)]
+    return _attach_rest(agg, nbrs), int(roots.sum()), sinfo
 
 
 # ---------------------------------------------------------------------------
@@ -298,6 +392,8 @@ def setup(A: sp.bsr_matrix, B: np.ndarray, opt: AMGOptions = AMGOptions(), aggre
             _, _, sinfo = aggregate(Al, theta)
             agg = np.asarray(aggregates[l], np.int64)
             n_agg = int(agg.max()) + 1 if agg.size and agg.max() >= 0 else 0
+        elif opt.aggregation == "mis2":
+            agg, n_agg, sinfo = aggregate_mis2(Al, theta, MIS_SEED + l)
         else:
             agg, n_agg, sinfo = aggregate(Al, theta)
         if n_agg == 0:

@@ -32,12 +32,16 @@ def uniform01(seed: int, n: int) -> np.ndarray:
     return out
 
 
-def uniform01_vec(seed: int, n: int) -> np.ndarray:
-    """Same values as `uniform01`, vectorised with wrapping uint64 arithmetic."""
+def splitmix64_vec(seed: int, n: int) -> np.ndarray:
+    """splitmix64(seed ^ i) for i < n as uint64 (wrapping arithmetic)."""
     with np.errstate(over="ignore"):
         z = np.bitwise_xor(np.uint64(seed), np.arange(n, dtype=np.uint64))
         z = z + np.uint64(0x9E3779B97F4A7C15)
         z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
         z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        z = z ^ (z >> np.uint64(31))
-    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform01_vec(seed: int, n: int) -> np.ndarray:
+    """Same values as `uniform01`, vectorised with wrapping uint64 arithmetic."""
+    return (splitmix64_vec(seed, n) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
