@@ -157,6 +157,24 @@ int fe_assemble_load(const te_mesh *mesh, const te_material *mat, const double *
 /* ---- smoothed-aggregation AMG (Sec. 2.1.3, 5.1) ------------------------- */
 typedef struct amg_handle amg_handle;
 
+/* Aggregation of each level (the rule is a reading: Sec. 5.1 names the
+ * library the paper uses and its defaults, not the rule; that library
+ * aggregates by maximal independent sets):
+ *   TE_AGG_GREEDY  sequential greedy in node order on the host (phase 1: a
+ *                  free node whose strong neighbours are all free roots an
+ *                  aggregate of them; phase 2: the rest join the aggregate of
+ *                  their strongest aggregated neighbour);
+ *   TE_AGG_MIS2    on the device: the phase-1 roots are the maximal
+ *                  distance-2 independent set of the (symmetrised) strong
+ *                  graph chosen in parallel rounds by the fixed keys
+ *                  (splitmix64((0xA66 + level) ^ node) >> 33, node), which is
+ *                  the set the sequential phase 1 picks when it visits nodes
+ *                  by descending key; aggregates numbered by ascending root;
+ *                  phase 2 as above.  No strength values cross to the host
+ *                  unless an aggregate is rank deficient. */
+#define TE_AGG_GREEDY 0
+#define TE_AGG_MIS2   1
+
 typedef struct {
     double theta0;           /* strength threshold at level 0, halved per level (0.08) */
     int32_t coarse_max;      /* stop coarsening at <= this many DOF (3000)            */
@@ -173,6 +191,7 @@ typedef struct {
                                 blocks on and above the diagonal, the others read
                                 transposed from their mirror (symmetric pattern only;
                                 float32 copies keep full storage) (1)                   */
+    int32_t aggregation;     /* TE_AGG_MIS2 (default) or TE_AGG_GREEDY                   */
 } amg_options;
 
 /* Fills the defaults listed above. */

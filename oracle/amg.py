@@ -11,16 +11,18 @@ is silent the following readings are taken (each is a parameter):
 * strength:   s_IJ = |A_IJ|_F / sqrt(|A_II|_F |A_JJ|_F), strong if I != J and
               s_IJ >= theta_l, theta_l = theta_0 2^-l, theta_0 = 0.08; the
               Frobenius sums run over block entries in row-major order.
-* aggregation: greedy, sequential in node order.  Phase 1 makes a new
+* aggregation: two phases.  The greedy rule (option "greedy") is
+              sequential in node order.  Phase 1 makes a new
               aggregate of I and its strong neighbours when all of them are
               free; phase 2 attaches each remaining node to the aggregate (of
               a phase-1 snapshot) of its strongest neighbour, strengths within
               a relative 1e-9 counting as equal and then the smaller aggregate
               id winning.  Nodes with no strong neighbour (e.g. clamped) are
               isolated and left out of every aggregate.
-* parallel aggregation (option "mis2"): the phase-1 roots are the maximal
-              distance-2 independent set of the strong graph (made symmetric)
-              chosen by fixed priorities in parallel rounds (Luby's rounds
+* parallel aggregation (option "mis2", the default): the phase-1 roots
+              are the maximal distance-2 independent set of the strong graph
+              (made symmetric) chosen by fixed priorities in parallel rounds
+              (Luby's rounds
               with fixed keys; Bell, Dalton & Olson 2012 use them for
               aggregation).  With fixed keys the rounds select exactly the
               set the sequential phase 1 selects when it visits the nodes in
@@ -68,7 +70,7 @@ class AMGOptions:
     cheb_ratio: float = 10.0     # a = b / cheb_ratio
     cheb_safety: float = 1.1     # b = cheb_safety * lambda_hat
     max_coarse_ratio: float = 0.8
-    aggregation: str = "greedy"  # or "mis2"
+    aggregation: str = "mis2"  # or "greedy"
 
 
 class RankError(RuntimeError):
@@ -375,7 +377,7 @@ class Level:
 
 def setup(A: sp.bsr_matrix, B: np.ndarray, opt: AMGOptions = AMGOptions(), aggregates=None):
     """Build the hierarchy.  `aggregates` optionally fixes the aggregate map of
-    each level (list of int arrays); otherwise the greedy rule is used."""
+    each level (list of int arrays); otherwise opt.aggregation's rule is used."""
     levels = []
     bs = A.blocksize[0]
     Al, Bl = A, B

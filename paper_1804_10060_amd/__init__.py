@@ -186,6 +186,8 @@ class AMG:
         for k, v in opts.items():
             if not hasattr(o, k):
                 raise TypeError(f"unknown AMG option {k}")
+            if k == "aggregation" and isinstance(v, str):
+                v = {"greedy": _lib.TE_AGG_GREEDY, "mis2": _lib.TE_AGG_MIS2}[v]
             setattr(o, k, v)
         self.opts = o
         self._cd = load()  # kept for __del__, which can run after module teardown

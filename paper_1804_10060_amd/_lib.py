@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libte_amd.so")
 TE_OK, TE_ENOTCONV = 0, 1
 TE_EINVAL, TE_ENOMEM, TE_EHIP, TE_EINDEF, TE_ENAN, TE_ERANK, TE_ECHOL = -1, -2, -3, -4, -5, -6, -7
 TE_PREC_FP64, TE_PREC_MIXED = 0, 1
+TE_AGG_GREEDY, TE_AGG_MIS2 = 0, 1
 TE_OP_A, TE_OP_P, TE_OP_R, TE_OP_SMOOTH, TE_OP_VCYCLE = 0, 1, 2, 3, 4
 KERNEL_CLASSES = ["Ap", "pre_smooth", "residual", "restrict", "prolong", "post_init", "post_smooth", "coarse_levels",
                   "vector"]
@@ -53,7 +54,8 @@ class AmgOptions(C.Structure):
     _fields_ = [("theta0", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("lanczos_steps", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("cheb_safety", C.c_double), ("max_coarse_ratio", C.c_double), ("build_fp32", C.c_int32),
-                ("host_threads", C.c_int32), ("max_nrhs", C.c_int32), ("coarse_sym", C.c_int32)]
+                ("host_threads", C.c_int32), ("max_nrhs", C.c_int32), ("coarse_sym", C.c_int32),
+                ("aggregation", C.c_int32)]
 
 
 class AmgInfo(C.Structure):

@@ -140,6 +140,7 @@ struct Strength {
 };
 
 static const double kTieRtol = 1e-9;
+static const uint64_t kMisSeed = 0xA66;  // key stream of level l: kMisSeed + l
 static const double kRankRtol = 1e-10;
 
 // agg[i] = aggregate id or -1 (isolated); returns the number of aggregates
@@ -278,8 +279,10 @@ static void gather_B(const int32_t *nodes, size_t cnt, const std::vector<double>
             for (int c = 0; c < k; ++c) M[(size_t)c * m + a * bs + p] = B[((size_t)nodes[a] * bs + p) * k + c];
 }
 
-static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t> agg, int64_t na,
-                           const std::vector<double> &B, int bs, int k) {
+// strength(): the per-block strengths, fetched only if an aggregate is rank
+// deficient and has to be merged
+static Tentative tentative(const HBsr &A, const std::function<const Strength &()> &strength,
+                           std::vector<int32_t> agg, int64_t na, const std::vector<double> &B, int bs, int k) {
     const int64_t n = A.nr;
     // members of each aggregate, ascending (counting sort by aggregate id);
     // aggregates whose membership changes by a merge get an explicit list
@@ -346,6 +349,7 @@ static Tentative tentative(const HBsr &A, const Strength &S, std::vector<int32_t
             continue;
         }
         std::vector<std::pair<int32_t, double>> score;
+        const Strength &S = strength();
         for (size_t u = 0; u < cnt; ++u) {
             const int32_t i = nodes[u];
             for (int64_t kk = A.ptr[i]; kk < A.ptr[i + 1]; ++kk) {
@@ -640,6 +644,8 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     TE_REQUIRE(o.cheb_degree >= 1 && o.cheb_degree <= 8, TE_EINVAL, "cheb_degree must be in 1..8");
     TE_REQUIRE(o.max_levels >= 1 && o.max_levels <= 16, TE_EINVAL, "max_levels must be in 1..16");
     TE_REQUIRE(o.lanczos_steps >= 1, TE_EINVAL, "lanczos_steps must be >= 1");
+    TE_REQUIRE(o.aggregation == TE_AGG_GREEDY || o.aggregation == TE_AGG_MIS2, TE_EINVAL,
+               "aggregation must be TE_AGG_GREEDY or TE_AGG_MIS2");
     g_threads = o.host_threads;
     auto h = std::make_unique<amg_handle>();
     h->opt = o;
@@ -731,12 +737,15 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
             set_cheb(L, o);
             note("eigenvalue estimate", l, L.n, 0);
             const double theta = o.theta0 * std::ldexp(1.0, -l);
+            const bool par = o.aggregation == TE_AGG_MIS2 && !(agg_given && l < n_given);
             Strength S;
-            {
-                DBuf<double> ds;
-                dev_strength(*cur, ds, s);
-                download(S.s, ds.p, (size_t)cur->nnzb, s);
-            }
+            DBuf<double> ds;
+            dev_strength(*cur, ds, s);
+            if (!par) download(S.s, ds.p, (size_t)cur->nnzb, s);
+            auto strength = [&]() -> const Strength & {
+                if (S.s.empty() && cur->nnzb) download(S.s, ds.p, (size_t)cur->nnzb, s);
+                return S;
+            };
             note("strength", l, L.n, cur->nnzb);
             std::vector<int32_t> agg;
             int64_t na;
@@ -748,14 +757,17 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                     TE_REQUIRE(a >= -1 && a < L.n, TE_EINVAL, "aggregate id %d out of range at level %d", a, l);
                     na = std::max<int64_t>(na, (int64_t)a + 1);
                 }
+            } else if (par) {
+                na = dev_aggregate_mis2(*cur, ds, theta, kMisSeed + (uint64_t)l, kTieRtol, agg, s);
             } else {
                 na = greedy_aggregate(L.Ah, S, theta, agg);
             }
             coarsest = na == 0;
             if (!coarsest) {
                 note("aggregated", l, na, 0);
-                Tentative T = tentative(L.Ah, S, agg, na, B, L.bs, k);
+                Tentative T = tentative(L.Ah, strength, agg, na, B, L.bs, k);
                 S = Strength();
+                ds.release();
                 note("tentative prolongator", l, T.nc, 0);
                 DBuf<int32_t> dagg;
                 DBuf<double> dQ;
@@ -905,6 +917,7 @@ extern "C" void amg_options_default(amg_options *o) {
     o->host_threads = 0;
     o->max_nrhs = 1;
     o->coarse_sym = 1;
+    o->aggregation = TE_AGG_MIS2;
 }
 
 extern "C" int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,

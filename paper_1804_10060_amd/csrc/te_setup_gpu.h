@@ -70,6 +70,18 @@ void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const st
 // pivot is not positive.
 void dev_dense_inverse_spd(const std::vector<double> &M, int n, DBuf<double> &inv, hipStream_t s);
 
+// Parallel aggregation of a level (square A with a symmetric pattern, s from
+// dev_strength): the strong graph made symmetric (block k = (i, j) strong if
+// s_ij or s_ji >= theta, i != j); phase-1 roots = the maximal distance-2
+// independent set chosen by fixed keys (splitmix64(seed ^ i) >> 33, i) in
+// parallel rounds; aggregates numbered by ascending root; phase-1 aggregate
+// = root and its strong neighbours; phase 2 joins each remaining node with a
+// strong neighbour to its strongest neighbour's phase-1 aggregate (relative
+// ties within tie_rtol: the smaller id).  agg: host [n], -1 for isolated
+// nodes; returns the number of aggregates.
+int64_t dev_aggregate_mis2(const DBsr &A, const DBuf<double> &s, double theta, uint64_t seed, double tie_rtol,
+                           std::vector<int32_t> &agg, hipStream_t st);
+
 // Host copies of the pattern or of the whole matrix.
 void dev_pattern_to_host(const DBsr &M, HBsr &H, hipStream_t s);
 void dev_to_host(const DBsr &M, HBsr &H, hipStream_t s);

@@ -946,6 +946,179 @@ void dev_dense_inverse_spd(const std::vector<double> &M, int n, DBuf<double> &in
     TE_CHECK_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------------------
+// Parallel (MIS-2) aggregation
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kKeyState = int64_t(1) << 61;  // key* = state * 2^61 + prio * 2^30 + i
+constexpr int8_t kOut = 0, kUndecided = 1, kIn = 2;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {  // splitmix64 (Steele, Lea & Flood 2014)
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// flag[k] = 1 for block k = (i, j), i != j, with s_ij >= theta, and for its
+// mirror (j, i) (binary search in the sorted row j).
+__global__ void k_strong_sym(int64_t nr, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                             const double *__restrict__ s, double theta, uint8_t *__restrict__ flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nr; i += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t j = col[k];
+            if (j == i || !(s[k] >= theta)) continue;
+            flag[k] = 1;
+            int64_t lo = ptr[j], hi = ptr[j + 1];
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < ptr[j + 1] && col[lo] == i) flag[lo] = 1;
+        }
+}
+
+// pk[i] = prio(i) * 2^30 + i; state = undecided if row i has a strong block
+__global__ void k_mis_init(int64_t nr, const int64_t *__restrict__ ptr, const uint8_t *__restrict__ flag,
+                           uint64_t seed, int64_t *__restrict__ pk, int8_t *__restrict__ state) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nr; i += (int64_t)gridDim.x * blockDim.x) {
+        pk[i] = (int64_t)(mix64(seed ^ (uint64_t)i) >> 33) * (int64_t(1) << 30) + i;
+        bool has = false;
+        for (int64_t k = ptr[i]; k < ptr[i + 1] && !has; ++k) has = flag[k] != 0;
+        state[i] = has ? kUndecided : kOut;
+    }
+}
+
+// out[i] = max(own, max over strong neighbours j of val(j)), val from the
+// current state and keys (first pass) or from the previous pass's output
+template <bool FIRST>
+__global__ void k_mis_max(int64_t nr, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                          const uint8_t *__restrict__ flag, const int8_t *__restrict__ state,
+                          const int64_t *__restrict__ pk, const int64_t *__restrict__ in, int64_t *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nr; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t m = FIRST ? state[i] * kKeyState + pk[i] : in[i];
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            if (!flag[k]) continue;
+            const int32_t j = col[k];
+            const int64_t v = FIRST ? state[j] * kKeyState + pk[j] : in[j];
+            m = v > m ? v : m;
+        }
+        out[i] = m;
+    }
+}
+
+// undecided i joins if the distance-2 maximum is its own key*, is excluded if
+// that maximum belongs to a member; counts the nodes still undecided
+__global__ void k_mis_step(int64_t nr, const int64_t *__restrict__ pk, const int64_t *__restrict__ m2,
+                           int8_t *__restrict__ state, int32_t *__restrict__ left) {
+    int32_t c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nr; i += (int64_t)gridDim.x * blockDim.x) {
+        if (state[i] != kUndecided) continue;
+        const int64_t own = kUndecided * kKeyState + pk[i];
+        if (m2[i] == own) state[i] = kIn;
+        else if (m2[i] / kKeyState == kIn) state[i] = kOut;
+        else ++c;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(left, c);
+}
+
+// phase 1: a root's id, or the id of the (unique) root among the strong
+// neighbours, else -1
+__global__ void k_agg_phase1(int64_t nr, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                             const uint8_t *__restrict__ flag, const int8_t *__restrict__ state,
+                             const int32_t *__restrict__ rid, int32_t *__restrict__ agg1) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nr; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t a = -1;
+        if (state[i] == kIn) a = rid[i];
+        else
+            for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+                if (flag[k] && state[col[k]] == kIn) {
+                    a = rid[col[k]];
+                    break;
+                }
+        agg1[i] = a;
+    }
+}
+
+// phase 2 over the phase-1 snapshot agg1, neighbours in stored order
+__global__ void k_agg_phase2(int64_t nr, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                             const uint8_t *__restrict__ flag, const double *__restrict__ s, double tie_rtol,
+                             const int32_t *__restrict__ agg1, int32_t *__restrict__ agg, int32_t *__restrict__ orphan) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nr; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t ba = agg1[i];
+        if (ba < 0) {
+            bool has = false;
+            double bs = -1.0;
+            for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+                if (!flag[k]) continue;
+                has = true;
+                const int32_t a = agg1[col[k]];
+                if (a < 0) continue;
+                const double sv = s[k];
+                if (ba < 0 || sv > bs * (1.0 + tie_rtol)) {
+                    bs = sv;
+                    ba = a;
+                } else if (sv >= bs * (1.0 - tie_rtol) && a < ba) {
+                    bs = sv;
+                    ba = a;
+                }
+            }
+            if (has && ba < 0) atomicMax(orphan, 1);
+        }
+        agg[i] = ba;
+    }
+}
+}  // namespace
+
+int64_t dev_aggregate_mis2(const DBsr &A, const DBuf<double> &s, double theta, uint64_t seed, double tie_rtol,
+                           std::vector<int32_t> &agg, hipStream_t st) {
+    TE_REQUIRE(A.nr == A.nc && A.nr < (int64_t(1) << 30), TE_EINVAL, "parallel aggregation: %lld rows",
+               (long long)A.nr);
+    const int64_t n = A.nr;
+    agg.assign(n, -1);
+    if (n == 0) return 0;
+    const unsigned g = grid_for(n);
+    DBuf<uint8_t> flag(std::max<int64_t>(A.nnzb, 1));
+    DBuf<int8_t> state(n);
+    DBuf<int64_t> pk(n), m1(n), m2(n);
+    DBuf<int32_t> left(1), rid(n), agg1(n), dagg(n), orphan(1);
+    TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, std::max<int64_t>(A.nnzb, 1), st));
+    TE_CHECK_HIP(hipMemsetAsync(orphan.p, 0, sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_strong_sym, dim3(g), dim3(256), 0, st, n, A.ptr, A.col, s.p, theta, flag.p);
+    hipLaunchKernelGGL(k_mis_init, dim3(g), dim3(256), 0, st, n, A.ptr, flag.p, seed, pk.p, state.p);
+    TE_CHECK_HIP(hipGetLastError());
+    // every round selects at least the undecided node of largest key, so at
+    // most n rounds; in practice a few tens
+    for (int64_t round = 0;; ++round) {
+        TE_REQUIRE(round <= n, TE_EINVAL, "parallel aggregation did not finish");
+        TE_CHECK_HIP(hipMemsetAsync(left.p, 0, sizeof(int32_t), st));
+        hipLaunchKernelGGL((k_mis_max<true>), dim3(g), dim3(256), 0, st, n, A.ptr, A.col, flag.p, state.p, pk.p,
+                           nullptr, m1.p);
+        hipLaunchKernelGGL((k_mis_max<false>), dim3(g), dim3(256), 0, st, n, A.ptr, A.col, flag.p, state.p, pk.p,
+                           m1.p, m2.p);
+        hipLaunchKernelGGL(k_mis_step, dim3(g), dim3(256), 0, st, n, pk.p, m2.p, state.p, left.p);
+        TE_CHECK_HIP(hipGetLastError());
+        if (read_flag(left, st) == 0) break;
+    }
+    // aggregate ids by ascending root
+    std::vector<int8_t> hs;
+    download(hs, state.p, (size_t)n, st);
+    std::vector<int32_t> hr(n, -1);
+    int64_t na = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (hs[i] == kIn) hr[i] = (int32_t)na++;
+    upload(rid, hr, st);
+    hipLaunchKernelGGL(k_agg_phase1, dim3(g), dim3(256), 0, st, n, A.ptr, A.col, flag.p, state.p, rid.p, agg1.p);
+    hipLaunchKernelGGL(k_agg_phase2, dim3(g), dim3(256), 0, st, n, A.ptr, A.col, flag.p, s.p, tie_rtol, agg1.p,
+                       dagg.p, orphan.p);
+    TE_CHECK_HIP(hipGetLastError());
+    TE_REQUIRE(read_flag(orphan, st) == 0, TE_EINVAL, "aggregation: a node has no aggregated strong neighbour");
+    download(agg, dagg.p, (size_t)n, st);
+    return na;
+}
+
 void dev_pattern_to_host(const DBsr &M, HBsr &H, hipStream_t s) {
     H.br = M.br;
     H.bc = M.bc;

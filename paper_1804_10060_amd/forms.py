@@ -1,12 +1,12 @@
 """Measurements of the batched and learned forms against plain float64 PCG-AMG
 on the same GPU, at the same true relative residual 1e-8.
 
-    python -m paper_1804_10060_amd.forms [block|multi|learned|materials|all] [--quick]
+    python -m paper_1804_10060_amd.forms [block|multi|learned|materials|aggregation|all] [--quick]
 
 Prints one JSON object.  Workloads (seeded, synthetic):
   block   : 64 thermal load cases (4-16 Gaussian bumps, U[0,500] K) on the
-            P1 disc 104x452x13 (1,993,320 DOF): one 64-column solve vs 64
-            single-column solves;
+            P1 disc 104x452x13 (1,993,320 DOF): one 64-column solve (64 CG
+            recurrences, and block CG) vs 64 single-column solves;
   multi   : 32 P1 discs with DOF log-uniform in [1e4, 5e5]: one multi-mesh
             solve (persistent launches, graph replay) vs 32 separate solves;
   learned : P1 disc 80x344x11 (1,003,104 DOF); 2000 training and 200
@@ -15,7 +15,9 @@ Prints one JSON object.  Workloads (seeded, synthetic):
             guess vs from zero;
   materials: P2 disc 96x416x12 (12,043,200 DOF) with hub, web and rim
             materials (temperature tables) and rim/top pressure: assembly
-            against the one-material assembly, and the solve.
+            against the one-material assembly, and the solve;
+  aggregation: P2 disc 96x416x12: AMG setup and solve with the device MIS-2
+            aggregation against the host greedy aggregation.
 """
 from __future__ import annotations
 
@@ -203,9 +205,42 @@ def materials_form(quick=False):
     return out
 
 
+def aggregation_form(quick=False):
+    """AMG setup and float64 solve with the host greedy aggregation and with
+    the device MIS-2 aggregation, on the same assembled system."""
+    import paper_1804_10060_amd as te
+    torch = _torch()
+    grid = (24, 104, 3, 2) if quick else mg.DISC_P2_12M
+    prob = mg.disc_problem(*grid, seed=0)
+    m = prob.mesh
+    dev = torch.device("cuda:0")
+    c = torch.from_numpy(m.coords).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    A, b = te.assemble(c, torch.from_numpy(m.cells.astype(np.int32)).to(dev), grid[3], prob.E, prob.nu, prob.alpha,
+                       prob.T_ref, torch.from_numpy(prob.T).to(dev), mask=mask)
+    out = {"workload": f"P2 disc {grid[0]}x{grid[1]}x{grid[2]}, {m.n_dof} DOF", "n_dof": m.n_dof}
+    te.AMG(A, c, mask, aggregation="mis2").close()  # warm-up of the setup kernels
+    for mode in ("greedy", "mis2"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = te.AMG(A, c, mask, aggregation=mode)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        info = h.info()
+        h.solve(b)
+        u, rep = h.solve(b)
+        out[mode] = {"setup_s": t_setup, "levels_dof": info["n_dof"], "solve_ms": rep.time_ms,
+                     "iters": rep.iters[0], "relres_true": rep.relres_true[0],
+                     "setup_plus_solve_s": t_setup + rep.time_ms * 1e-3}
+        h.close()
+    log(json.dumps(out))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", nargs="?", default="all", choices=["block", "multi", "learned", "materials", "all"])
+    ap.add_argument("which", nargs="?", default="all", choices=["block", "multi", "learned", "materials", "aggregation",
+                                                               "all"])
     ap.add_argument("--quick", action="store_true")
     a = ap.parse_args()
     out = {}
@@ -217,6 +252,8 @@ def main():
         out["learned_guess"] = learned_form(a.quick)
     if a.which in ("materials", "all"):
         out["materials"] = materials_form(a.quick)
+    if a.which in ("aggregation", "all"):
+        out["aggregation"] = aggregation_form(a.quick)
     print(json.dumps(out), flush=True)
 
 
