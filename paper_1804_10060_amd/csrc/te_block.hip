@@ -66,8 +66,10 @@ __global__ void __launch_bounds__(384) k_gram(GramArgs g) {
     const int64_t step = 4 * GU;
     const int64_t chunk = ((g.rows + gridDim.x - 1) / gridDim.x + step - 1) / step * step;
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(g.rows, lo + chunk);
-    for (int64_t r0 = lo; r0 < hi; r0 += step) {
-        double a[GU][2], b[GU][4];
+    // fragments of one batch of GU 4-row steps; the next batch is loaded
+    // while the current one goes through the matrix cores
+    double a[GU][2], b[GU][4];
+    auto load = [&](int64_t r0) {
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int64_t row = r0 + 4 * u + kr;
@@ -83,13 +85,25 @@ __global__ void __launch_bounds__(384) k_gram(GramArgs g) {
                 b[u][c] = (ok && col < m) ? R[row * m + col] : 0.0;
             }
         }
+    };
+    if (lo < hi) load(lo);
+    for (int64_t r0 = lo; r0 < hi; r0 += step) {
+        double ca[GU][2], cb[GU][4];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) ca[u][t] = a[u][t];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cb[u][c] = b[u][c];
+        }
+        if (r0 + step < hi) load(r0 + step);
 #pragma unroll
         for (int u = 0; u < GU; ++u)
 #pragma unroll
             for (int t = 0; t < 2; ++t)
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if (tj[t] && c * 16 < m) acc[t][c] = mfma(a[u][t], b[u][c], acc[t][c]);
+                    if (tj[t] && c * 16 < m) acc[t][c] = mfma(ca[u][t], cb[u][c], acc[t][c]);
     }
     double *out = g.partials + ((int64_t)blockIdx.x * g.npair + p) * GM * GM;
 #pragma unroll
@@ -141,18 +155,27 @@ __global__ void __launch_bounds__(UBLK) k_block_xr(int64_t rows, int m, const do
         d4 dx[4], dr[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) dx[c] = dr[c] = d4{0.0, 0.0, 0.0, 0.0};
+        // all fragments of the 16 rows first (loads in flight together), then
+        // the matrix-core steps
         const int64_t ra = r0 + kc;
-        for (int s = 0; s < nk; ++s) {
+        double pa[GM / 4], qa[GM / 4];
+#pragma unroll
+        for (int s = 0; s < GM / 4; ++s) {
             const int k = 4 * s + kr;
             const bool ok = ra < rows && k < m;
-            const double pa = ok ? P[ra * m + k] : 0.0;
-            const double qa = ok ? Q[ra * m + k] : 0.0;
+            pa[s] = ok ? P[ra * m + k] : 0.0;
+            qa[s] = ok ? Q[ra * m + k] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < GM / 4; ++s) {
+            if (s >= nk) break;
+            const int k = 4 * s + kr;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 if (c < nc) {
                     const double bv = s_a[k * GM + c * 16 + kc];
-                    dx[c] = mfma(pa, bv, dx[c]);
-                    dr[c] = mfma(qa, bv, dr[c]);
+                    dx[c] = mfma(pa[s], bv, dx[c]);
+                    dr[c] = mfma(qa[s], bv, dr[c]);
                 }
         }
 #pragma unroll
@@ -200,16 +223,23 @@ __global__ void __launch_bounds__(UBLK) k_block_p(int64_t rows, int m, const dou
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
         const int64_t ra = r0 + kc;
-        for (int s = 0; s < nk; ++s) {
+        double za[GM / 4], pa[GM / 4];
+#pragma unroll
+        for (int s = 0; s < GM / 4; ++s) {
             const int k = 4 * s + kr;
             const bool ok = ra < rows && k < m;
-            const double za = ok ? Z[ra * m + k] : 0.0;
-            const double pa = ok ? P[ra * m + k] : 0.0;
+            za[s] = ok ? Z[ra * m + k] : 0.0;
+            pa[s] = ok ? P[ra * m + k] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < GM / 4; ++s) {
+            if (s >= nk) break;
+            const int k = 4 * s + kr;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 if (c < nc) {
-                    acc[c] = mfma(za, s_1[k * GM + c * 16 + kc], acc[c]);
-                    acc[c] = mfma(pa, s_2[k * GM + c * 16 + kc], acc[c]);
+                    acc[c] = mfma(za[s], s_1[k * GM + c * 16 + kc], acc[c]);
+                    acc[c] = mfma(pa[s], s_2[k * GM + c * 16 + kc], acc[c]);
                 }
         }
 #pragma unroll

@@ -31,6 +31,13 @@ import numpy as np
 import meshgen as mg
 
 
+# The P1 discs (block, multi-mesh and learned forms) use the greedy
+# aggregation: with their index-ordered structured nodes it gives regular
+# aggregates that precondition better than the default MIS-2 rule (17 against
+# 23 iterations on the 2M-DOF disc); on the P2 discs the MIS-2 rule is better.
+P1_AGGREGATION = "greedy"
+
+
 def log(*a):
     print("[forms]", *a, file=sys.stderr, flush=True)
 
@@ -46,7 +53,7 @@ def block_form(quick=False):
     torch = _torch()
     grid = (26, 113, 3) if quick else mg.DISC_P1_2M[:3]
     k = 16 if quick else 64
-    pr = learned.Problem(*grid, max_nrhs=64)
+    pr = learned.Problem(*grid, max_nrhs=64, aggregation=P1_AGGREGATION)
     seeds = list(range(1000, 1000 + k))
     T = torch.from_numpy(np.stack([mg.disc_temperature_bumps(pr.mesh, s) for s in seeds])).to(pr.dev)
     fv = torch.zeros((k, 3), dtype=torch.float64, device=pr.dev)
@@ -104,7 +111,7 @@ def multi_form(quick=False):
         c = torch.from_numpy(m.coords).to(dev)
         A, b = te.assemble(c, torch.from_numpy(m.cells).to(dev), 1, prob.E, prob.nu, prob.alpha, prob.T_ref,
                            torch.from_numpy(prob.T).to(dev), mask=torch.from_numpy(prob.mask).to(dev))
-        hs.append(te.AMG(A, c, torch.from_numpy(prob.mask).to(dev)))
+        hs.append(te.AMG(A, c, torch.from_numpy(prob.mask).to(dev), aggregation=P1_AGGREGATION))
         bs.append(b)
         ndof += m.n_dof
     log(f"multi: {len(hs)} meshes, {ndof} DOF total, setup {time.perf_counter() - t0:.1f}s")
@@ -137,7 +144,7 @@ def learned_form(quick=False):
     grid = (16, 68, 3) if quick else mg.DISC_P1_1M[:3]
     n_train, n_test = (192, 16) if quick else (2000, 200)
     epochs = 24 if quick else 12
-    pr = learned.Problem(*grid, max_nrhs=64)
+    pr = learned.Problem(*grid, max_nrhs=64, aggregation=P1_AGGREGATION)
     t0 = time.perf_counter()
     train = pr.generate(list(range(10000, 10000 + n_train)), log=log)
     test = pr.generate(list(range(20000, 20000 + n_test)), log=log)

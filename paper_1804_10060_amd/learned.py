@@ -51,7 +51,7 @@ class Dataset:
 class Problem:
     """One P1 disc, its assembled operator, AMG hierarchy and MPNN graph."""
 
-    def __init__(self, nr, nth, nz, max_nrhs=64, device="cuda:0"):
+    def __init__(self, nr, nth, nz, max_nrhs=64, device="cuda:0", aggregation="mis2"):
         import torch
         self.prob = mg.disc_problem(nr, nth, nz, 1, seed=0)
         m = self.prob.mesh
@@ -64,7 +64,7 @@ class Problem:
         T0 = torch.full((m.n_nodes,), self.prob.T_ref, dtype=torch.float64, device=dev)
         self.A, _ = assemble(self.coords, self.cells, 1, self.prob.E, self.prob.nu, self.prob.alpha,
                              self.prob.T_ref, T0, mask=self.mask)
-        self.amg = AMG(self.A, self.coords, self.mask, max_nrhs=max_nrhs)
+        self.amg = AMG(self.A, self.coords, self.mask, max_nrhs=max_nrhs, aggregation=aggregation)
         self.net = MPNN(self.A, self.coords)
 
     def fields(self, seeds):
