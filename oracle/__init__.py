@@ -14,12 +14,14 @@ paper and the textbook methods it names, in float64:
                  pressure term, Dirichlet elimination, rigid-body
                  near-nullspace.
 * ``amg``     -- smoothed-aggregation AMG (Sec. 2.1.3, Sec. 5.1): strength,
-                 greedy aggregation, tentative prolongator by QR, Lanczos
+                 MIS-2 or greedy aggregation, tentative prolongator by QR, Lanczos
                  eigenvalue estimate, prolongator smoothing, Galerkin
                  product, Chebyshev smoother, V-cycle, coarse Cholesky.
 * ``krylov``  -- preconditioned and flexible conjugate gradients
                  (Sec. 2.1.2), single and multiple right-hand sides.
 * ``mpnn``    -- message-passing network forward/backward for the learned
                  initial guess.
+* ``transient`` -- the time-step control of eq. dt_spec around the elastic
+                 solve of a transient run (Sec. 3.4, Sec. 5.3).
 * ``rng``     -- splitmix64 counter generator (Steele, Lea & Flood 2014).
 """
