@@ -352,6 +352,33 @@ int amg_energy_scale(amg_handle *h, const double *b, double *u0, double *gamma, 
 int te_autotune(amg_handle *h, const char *cache_path, int32_t use_cache, char *report, int64_t report_len,
                 hipStream_t stream);
 
+/* ---- transient runs (Sec. 3.4, Sec. 5.3) -------------------------------- */
+
+/* Preconditioner reuse across time steps (Sec. 5.3: the elastic
+ * preconditioner of the first step serves the later ones).  From this call
+ * on, the CG products and residuals of amg_pcg_solve and amg_energy_scale use
+ * A, while the V-cycle (level-0 smoother included) keeps the matrices the
+ * hierarchy was built from.  A: device arrays as for amg_setup, with the same
+ * block pattern as the setup matrix (checked: block rows, block count and a
+ * 64-bit hash of row pointers and columns); its values are copied into
+ * library storage, so A may be freed afterwards.  A = NULL goes back to the
+ * setup matrix.  amg_pcg_solve_multi rejects a handle with such an operator.
+ * Synchronises `stream`.  Returns TE_OK, TE_EINVAL (NULL handle, different
+ * pattern), TE_ENOMEM, TE_EHIP. */
+int amg_set_operator(amg_handle *h, const te_bsr *A, hipStream_t stream);
+
+/* Time-step control of eq. dt_spec.  For a step of length dt that took the
+ * temperature from T_old to T_new (device [n] each):
+ *   dT = max_i |T_new[i] - T_old[i]|  (reduced on the device; exact);
+ *   dT <= dT_max: *accept = 1, *dt_next = eps * dT_max / dT * dt
+ *                 (2 dt when dT = 0, where the formula has no value);
+ *   dT >  dT_max: *accept = 0, *dt_next = dt / 2 (repeat the step).
+ * Outputs are host pointers; max_change may be NULL.  Needs dt > 0,
+ * dT_max > 0, 0 < eps <= 1.  Synchronises `stream`.  Returns TE_OK,
+ * TE_EINVAL, TE_ENAN (a NaN in either field), TE_EHIP. */
+int te_timestep(const double *T_new, const double *T_old, int64_t n, double dt, double dT_max, double eps,
+                double *dt_next, int32_t *accept, double *max_change, hipStream_t stream);
+
 /* Releases everything the handle owns.  NULL is accepted. */
 int amg_destroy(amg_handle *h);
 

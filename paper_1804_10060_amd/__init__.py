@@ -268,6 +268,15 @@ class AMG:
         check(load().amg_energy_scale(self._h, _ptr(b), _ptr(u0), C.byref(g), _stream()))
         return g.value
 
+    def set_operator(self, A=None):
+        """amg_set_operator: CG products with A (same pattern as the setup
+        matrix) while the hierarchy stays; None goes back to the setup matrix."""
+        if A is None:
+            check(load().amg_set_operator(self._h, None, _stream()))
+            return
+        bsr = A.c()
+        check(load().amg_set_operator(self._h, C.byref(bsr), _stream()))
+
     # ---- solve ----------------------------------------------------------
     def solve(self, b, u0=None, rtol=1e-8, maxit=500, precision="fp64", max_replace=3, history=False,
               allow_notconv=False, profile=False, block=False):
@@ -297,6 +306,18 @@ class AMG:
         h = hist.reshape(maxit + 1, nrhs) if hist is not None else None
         return u, SolveReport(iters.tolist(), conv.tolist(), rel.tolist(), h, rep.max_iters, rep.time_ms, code,
                               list(rep.kernel_ms), list(rep.kernel_launches))
+
+
+def timestep(T_new, T_old, dt, dT_max=10.0, eps=0.9):
+    """te_timestep (eq. dt_spec): returns (accept, dt_next, max_change) for a
+    step of length dt from T_old to T_new (float64 device tensors, same size)."""
+    torch = _torch()
+    _dev(T_new, torch.float64, None, "T_new")
+    _dev(T_old, torch.float64, tuple(T_new.shape), "T_old")
+    dn, acc, mc = C.c_double(0.0), C.c_int32(0), C.c_double(0.0)
+    check(load().te_timestep(_ptr(T_new), _ptr(T_old), T_new.numel(), float(dt), float(dT_max), float(eps),
+                             C.byref(dn), C.byref(acc), C.byref(mc), _stream()))
+    return bool(acc.value), dn.value, mc.value
 
 
 def solve_multi(amgs, bs, u0s=None, rtol=1e-8, maxit=500, max_replace=3):

@@ -693,6 +693,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
         TE_REQUIRE(i == INT64_MAX, TE_EINVAL, "row %lld has a column index out of range or no diagonal block",
                    (long long)i);
     }
+    h->pattern_hash = dev_pattern_hash(A->row_ptr, A->col_idx, n, s);
     DBsr D0;  // view of the caller's matrix
     D0.br = D0.bc = 3;
     D0.nr = D0.nc = n;
@@ -932,6 +933,42 @@ extern "C" int amg_setup_with_aggregates(const te_bsr *A, const double *coords, 
         TE_REQUIRE(agg || n_levels_given == 0, TE_EINVAL, "agg is NULL");
         return setup_impl(A, coords, dir_mask, opt, agg, n_levels_given, out, stream);
     });
+}
+
+// The matrix of the CG products from now on: same pattern as the setup
+// matrix, new values, packed in the level-0 storage order; the hierarchy
+// (level-0 smoother included) stays the one built at setup.
+static int set_operator_impl(amg_handle *h, const te_bsr *A, hipStream_t s) {
+    TE_REQUIRE(h, TE_EINVAL, "handle is NULL");
+    if (!A) {
+        h->Aop = Sell();
+        h->has_op = false;
+        return TE_OK;
+    }
+    Level &L0 = h->L[0];
+    TE_REQUIRE(A->row_ptr && A->col_idx && A->val, TE_EINVAL, "NULL matrix array");
+    TE_REQUIRE(A->n_brows == L0.n && A->nnzb == L0.Ah.nnzb(), TE_EINVAL,
+               "operator has %lld block rows and %lld blocks, the setup matrix %lld and %lld", (long long)A->n_brows,
+               (long long)A->nnzb, (long long)L0.n, (long long)L0.Ah.nnzb());
+    TE_REQUIRE(dev_pattern_hash(A->row_ptr, A->col_idx, A->n_brows, s) == h->pattern_hash, TE_EINVAL,
+               "operator pattern differs from the setup matrix's");
+    DBsr D;
+    D.br = D.bc = 3;
+    D.nr = D.nc = A->n_brows;
+    D.nnzb = A->nnzb;
+    D.ptr = A->row_ptr;
+    D.col = A->col_idx;
+    D.val = A->val;
+    Sell S;
+    dev_pack(S, D, L0.Ah.ptr, L0.perm_h, L0.iperm_h, nullptr, false, s, FMT_SELL);
+    h->Aop = std::move(S);
+    h->has_op = true;
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    return TE_OK;
+}
+
+extern "C" int amg_set_operator(amg_handle *h, const te_bsr *A, hipStream_t stream) {
+    return guarded([&] { return set_operator_impl(h, A, stream); });
 }
 
 extern "C" int amg_destroy(amg_handle *h) {

@@ -117,8 +117,24 @@ struct amg_handle {
     te::DBuf<double> Ainv;         // coarsest level: dense inverse, storage order
     int nc = 0;
     double setup_ms = 0.0;
+    // the matrix of the CG products when it is not the one the hierarchy was
+    // built for (amg_set_operator): same pattern, level-0 storage order
+    te::Sell Aop;
+    bool has_op = false;
+    uint64_t pattern_hash = 0;     // of the setup matrix's row pointers and columns
     // solve workspace (level-0 storage order, [n][3][nrhs])
     te::DBuf<double> u, r, r_old, z, p, q, t, b;
     te::DBuf<double> partials, sums;
     te::DBuf<char> scal;
 };
+
+namespace te {
+// The operator of the CG products (the setup matrix, or the one set by
+// amg_set_operator), with the tuned launch configuration of the setup matrix.
+inline Sell &cg_operator(amg_handle *h) {
+    if (!h->has_op) return h->L[0].A;
+    h->Aop.tune64 = h->L[0].A.tune64;
+    h->Aop.tune32 = h->L[0].A.tune32;
+    return h->Aop;
+}
+}  // namespace te

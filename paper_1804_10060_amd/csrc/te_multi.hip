@@ -374,6 +374,8 @@ int multi_impl(amg_handle **hs, int n, const double *const *b, double *const *u,
     M.deg = hs[0]->opt.cheb_degree;
     for (int m = 0; m < n; ++m) {
         TE_REQUIRE(hs[m] && b[m] && u[m], TE_EINVAL, "NULL handle or vector %d", m);
+        TE_REQUIRE(!hs[m]->has_op, TE_EINVAL, "handle %d has an operator set by amg_set_operator, which the "
+                   "multi-mesh solve does not take", m);
         TE_REQUIRE(hs[m]->opt.cheb_degree == M.deg && M.deg >= 2, TE_EINVAL,
                    "all meshes need the same Chebyshev degree >= 2");
         M.Lmax = std::max<int>(M.Lmax, (int)hs[m]->L.size());

@@ -82,6 +82,9 @@ void dev_dense_inverse_spd(const std::vector<double> &M, int n, DBuf<double> &in
 int64_t dev_aggregate_mis2(const DBsr &A, const DBuf<double> &s, double theta, uint64_t seed, double tie_rtol,
                            std::vector<int32_t> &agg, hipStream_t st);
 
+// Order-independent 64-bit hash of a block pattern (row pointers and columns).
+uint64_t dev_pattern_hash(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st);
+
 // Host copies of the pattern or of the whole matrix.
 void dev_pattern_to_host(const DBsr &M, HBsr &H, hipStream_t s);
 void dev_to_host(const DBsr &M, HBsr &H, hipStream_t s);

@@ -1072,6 +1072,32 @@ __global__ void k_agg_phase2(int64_t nr, const int64_t *__restrict__ ptr, const 
 }
 }  // namespace
 
+namespace {
+// sum over stored blocks of mix64(row * 2^32 + column), per row the row
+// length mixed in as well; wave sums then one 64-bit atomic per wave
+__global__ void k_pattern_hash(const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, int64_t n,
+                               unsigned long long *__restrict__ out) {
+    unsigned long long h = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        h += mix64(0xC0FFEEull ^ ((uint64_t)i << 32) ^ (uint64_t)(ptr[i + 1] - ptr[i]));
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) h += mix64(((uint64_t)i << 32) | (uint32_t)col[k]);
+    }
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_down(h, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, h);
+}
+}  // namespace
+
+uint64_t dev_pattern_hash(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st) {
+    DBuf<unsigned long long> d(1);
+    TE_CHECK_HIP(hipMemsetAsync(d.p, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_pattern_hash, dim3(grid_for(n)), dim3(256), 0, st, ptr, col, n, d.p);
+    TE_CHECK_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    TE_CHECK_HIP(hipMemcpyAsync(&h, d.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    TE_CHECK_HIP(hipStreamSynchronize(st));
+    return (uint64_t)h;
+}
+
 int64_t dev_aggregate_mis2(const DBsr &A, const DBuf<double> &s, double theta, uint64_t seed, double tie_rtol,
                            std::vector<int32_t> &agg, hipStream_t st) {
     TE_REQUIRE(A.nr == A.nc && A.nr < (int64_t(1) << 30), TE_EINVAL, "parallel aggregation: %lld rows",

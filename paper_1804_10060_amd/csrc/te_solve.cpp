@@ -349,8 +349,8 @@ static int block_solve_impl(amg_handle *h, const double *b_nat, double *u_nat, i
         TE_CHECK_HIP(hipStreamSynchronize(s));
     };
     // R = B - A X
-    sell_resid_norm(L0.A, X, B, R, m, part, s);
-    reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+    sell_resid_norm(cg_operator(h), X, B, R, m, part, s);
+    reduce_partials(part, sell_partials_count(cg_operator(h), m), m, sums, s);
     fetch(sums, m, rr, s);
     std::vector<double> rel;
     bool done = rel_of(rr, rel);
@@ -367,7 +367,7 @@ static int block_solve_impl(amg_handle *h, const double *b_nat, double *u_nat, i
     }
     bool conv = done;
     while (!done && rank > 0 && it < o.maxit) {
-        sell_apply<double>(L0.A, P, Q, nullptr, 0, m, s);
+        sell_apply<double>(cg_operator(h), P, Q, nullptr, 0, m, s);
         gram({P, Q, R}, {{0, 1}, {0, 2}, {0, 0}}, g1);  // P^T Q, P^T R, P^T P
         Small alpha;
         TE_REQUIRE(chol_solve(g1[0], rank, g1[1], m, alpha), TE_EINDEF, "block CG breakdown: P^T A P is not SPD");
@@ -377,8 +377,8 @@ static int block_solve_impl(amg_handle *h, const double *b_nat, double *u_nat, i
         fetch(sums, m, rr, s);
         ++it;
         if (rel_of(rr, rel)) {
-            sell_resid_norm(L0.A, X, B, Tt, m, part, s);
-            reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+            sell_resid_norm(cg_operator(h), X, B, Tt, m, part, s);
+            reduce_partials(part, sell_partials_count(cg_operator(h), m), m, sums, s);
             fetch(sums, m, tr, s);
             if (rel_of(tr, rel)) {
                 conv = true;
@@ -420,8 +420,8 @@ static int block_solve_impl(amg_handle *h, const double *b_nat, double *u_nat, i
         rank = nr;
     }
     if (!conv) {  // final true residual of every column
-        sell_resid_norm(L0.A, X, B, Tt, m, part, s);
-        reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+        sell_resid_norm(cg_operator(h), X, B, Tt, m, part, s);
+        reduce_partials(part, sell_partials_count(cg_operator(h), m), m, sums, s);
         fetch(sums, m, tr, s);
         rel_of(tr, rel);
     }
@@ -490,8 +490,8 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
     dot_partials(h->b.p, h->b.p, nv, m, part, s);
     reduce_partials(part, dot_nblocks(rows), m, sums, s);
     fetch(sums, m, bb, s);
-    sell_resid_norm(L0.A, h->u.p, h->b.p, h->r.p, m, part, s);
-    reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+    sell_resid_norm(cg_operator(h), h->u.p, h->b.p, h->r.p, m, part, s);
+    reduce_partials(part, sell_partials_count(cg_operator(h), m), m, sums, s);
     fetch(sums, m, rr, s);
 
     std::vector<int32_t> active(64, 0), flags(64, 0), iters(m, 0), conv(m, 0), replaced(m, 0);
@@ -546,10 +546,10 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
     while (n_active > 0 && it < o.maxit) {
         ++it;
         h->prof.begin(TE_K_AP);
-        sell_dot(L0.A, h->p.p, h->q.p, m, part, s);
+        sell_dot(cg_operator(h), h->p.p, h->q.p, m, part, s);
         h->prof.end(TE_K_AP);
         h->prof.begin(TE_K_VECTOR);
-        reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+        reduce_partials(part, sell_partials_count(cg_operator(h), m), m, sums, s);
         cg_alpha(S, sums, m, s);
         cg_update(h->u.p, h->r.p, mixed ? h->r_old.p : nullptr, h->p.p, h->q.p, S->alpha, rows, m, part, s);
         reduce_partials(part, dot_nblocks(rows), m, sums, s);
@@ -571,8 +571,8 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
             }
         }
         if (any_cand) {
-            sell_resid_norm(L0.A, h->u.p, h->b.p, h->t.p, m, part, s);
-            reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+            sell_resid_norm(cg_operator(h), h->u.p, h->b.p, h->t.p, m, part, s);
+            reduce_partials(part, sell_partials_count(cg_operator(h), m), m, sums, s);
             fetch(sums, m, tr, s);
             std::vector<int32_t> repl(64, 0);
             bool any_repl = false, changed = false;
@@ -613,8 +613,8 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
         h->prof.end(TE_K_VECTOR);
     }
     // final true residual of every column
-    sell_resid_norm(L0.A, h->u.p, h->b.p, h->t.p, m, part, s);
-    reduce_partials(part, sell_partials_count(L0.A, m), m, sums, s);
+    sell_resid_norm(cg_operator(h), h->u.p, h->b.p, h->t.p, m, part, s);
+    reduce_partials(part, sell_partials_count(cg_operator(h), m), m, sums, s);
     permute_scatter(h->u.p, u_nat, L0.perm.p, n, 3, m, s);
     TE_CHECK_HIP(hipEventRecord(e1, s));
     fetch(sums, m, tr, s);
@@ -748,7 +748,7 @@ static int energy_scale_impl(amg_handle *h, const double *b_nat, double *u_nat, 
     const int64_t n = L0.n, nv = n * 3;
     permute_gather(b_nat, h->b.p, L0.perm.p, n, 3, 1, s);
     permute_gather(u_nat, h->t.p, L0.perm.p, n, 3, 1, s);
-    sell_apply<double>(L0.A, h->t.p, h->q.p, nullptr, 0, 1, s);
+    sell_apply<double>(cg_operator(h), h->t.p, h->q.p, nullptr, 0, 1, s);
     double *part = h->partials.p, *sums = h->sums.p;
     dot_partials(h->b.p, h->t.p, nv, 1, part, s);
     reduce_partials(part, dot_nblocks(nv), 1, sums, s);

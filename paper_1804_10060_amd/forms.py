@@ -1,7 +1,7 @@
 """Measurements of the batched and learned forms against plain float64 PCG-AMG
 on the same GPU, at the same true relative residual 1e-8.
 
-    python -m paper_1804_10060_amd.forms [block|multi|learned|materials|aggregation|all] [--quick]
+    python -m paper_1804_10060_amd.forms [block|multi|learned|materials|aggregation|transient|all] [--quick]
 
 Prints one JSON object.  Workloads (seeded, synthetic):
   block   : 64 thermal load cases (4-16 Gaussian bumps, U[0,500] K) on the
@@ -17,11 +17,17 @@ Prints one JSON object.  Workloads (seeded, synthetic):
             materials (temperature tables) and rim/top pressure: assembly
             against the one-material assembly, and the solve;
   aggregation: P2 disc 96x416x12: AMG setup and solve with the device MIS-2
-            aggregation against the host greedy aggregation.
+            aggregation against the host greedy aggregation;
+  transient: P2 disc 96x416x12 with the three materials and pressure, heated
+            from 293 K toward its operating field (time constant 600 s), 16
+            steps of eq. dt_spec (dT_max 10 K, eps 0.9): the hierarchy of the
+            first step reused with the previous displacement as guess,
+            against a new hierarchy and a zero guess at sampled steps.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import sys
 import time
@@ -244,10 +250,63 @@ def aggregation_form(quick=False):
     return out
 
 
+def transient_form(quick=False):
+    """Elastic steps along a heating history with the first step's hierarchy
+    reused (amg_set_operator, previous displacement as guess), against a new
+    hierarchy per step from a zero guess at sampled steps."""
+    import math
+    import paper_1804_10060_amd as te
+    from paper_1804_10060_amd import transient
+    torch = _torch()
+    grid = (24, 104, 3, 2) if quick else mg.DISC_P2_12M
+    nsteps = 6 if quick else 16
+    prob = mg.disc_problem(*grid, seed=0)
+    m = prob.mesh
+    dev = torch.device("cuda:0")
+    mat = mg.disc_materials(m)
+    faces, p = mg.disc_pressure_faces(m)
+    c = torch.from_numpy(m.coords).to(dev)
+    cl = torch.from_numpy(m.cells.astype(np.int32)).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    cm = torch.from_numpy(mat.cell_material).to(dev)
+    tables = (mat.T, mat.E, mat.nu, mat.alpha)
+    Top = torch.from_numpy(prob.T).to(dev)
+    tau, T0 = 600.0, 293.0
+
+    def T_of_t(t):
+        return (T0 + (Top - T0) * (1.0 - math.exp(-t / tau))).contiguous()
+
+    run = transient.ElasticTransient(c, cl, grid[3], tables, cm, prob.T_ref, mask,
+                                     faces=torch.from_numpy(faces).to(dev), face_p=torch.from_numpy(p).to(dev))
+    recs = run.run(T_of_t, 0.0, 1e9, 1.0, dT_max=10.0, eps=0.9, max_steps=nsteps)
+    run.close()
+    # sampled steps again with a new hierarchy each and a zero guess
+    fresh = {}
+    for k in sorted({1, nsteps // 2, nsteps}):
+        r = transient.ElasticTransient(c, cl, grid[3], tables, cm, prob.T_ref, mask,
+                                       faces=torch.from_numpy(faces).to(dev), face_p=torch.from_numpy(p).to(dev))
+        u, rep, built, ta, to, ts = r.solve_at(T_of_t(recs[k].t))
+        fresh[k] = {"iters": rep.iters[0], "assemble_ms": ta, "setup_ms": to, "solve_ms": ts}
+        r.close()
+    steps = [dataclasses.asdict(s) for s in recs]
+    later = recs[1:]
+    reuse_ms = [s.assemble_ms + s.operator_ms + s.solve_ms for s in later]
+    fresh_ms = [v["assemble_ms"] + v["setup_ms"] + v["solve_ms"] for v in fresh.values()]
+    out = {"workload": f"P2 disc {grid[0]}x{grid[1]}x{grid[2]}, {m.n_dof} DOF, 3 materials + pressure, heating "
+                       f"293 K -> operating field (tau {tau:.0f} s), dT_max 10 K, eps 0.9",
+           "n_dof": m.n_dof, "steps": steps,
+           "reuse_step_ms_mean": float(np.mean(reuse_ms)), "reuse_iters_mean": float(np.mean([s.iters for s in later])),
+           "fresh_sampled": fresh, "fresh_step_ms_mean": float(np.mean(fresh_ms)),
+           "all_converged": bool(all(s.relres_true <= 1e-8 for s in recs)),
+           "rejected_total": int(sum(s.rejected for s in recs))}
+    log(json.dumps({k: v for k, v in out.items() if k != "steps"}))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", nargs="?", default="all", choices=["block", "multi", "learned", "materials", "aggregation",
-                                                               "all"])
+                                                               "transient", "all"])
     ap.add_argument("--quick", action="store_true")
     a = ap.parse_args()
     out = {}
@@ -261,6 +320,8 @@ def main():
         out["materials"] = materials_form(a.quick)
     if a.which in ("aggregation", "all"):
         out["aggregation"] = aggregation_form(a.quick)
+    if a.which in ("transient", "all"):
+        out["transient"] = transient_form(a.quick)
     print(json.dumps(out), flush=True)
 
 
