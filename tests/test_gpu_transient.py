@@ -128,9 +128,9 @@ def test_timestep_matches_oracle_exactly():
 
 def test_driver_follows_the_oracle_step_sequence():
     """Five steps of a heating history on a P2 disc with three materials and
-    pressure, first step 40 s (halved until its change is within 10 K): the same accepted times and
-    lengths as the oracle, and every displacement solves its step's system as
-    the oracle assembles it."""
+    pressure, the first attempt 40 s long (halved until its change is within
+    10 K): the same accepted times and lengths as the oracle, and every
+    displacement solves its step's system as the oracle assembles it."""
     from paper_1804_10060_amd import transient as gt
     torch = torch_cuda()
     prob = mg.disc_problem(6, 26, 2, 2, seed=2)
