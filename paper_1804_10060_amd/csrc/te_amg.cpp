@@ -505,35 +505,9 @@ static double lanczos_estimate(const Level &L, int steps, uint64_t seed, hipStre
     return tridiag_max_eig(al, be);
 }
 
-
 // ---------------------------------------------------------------------------
 // the setup
 // ---------------------------------------------------------------------------
-static void rigid_body_modes(const std::vector<double> &X, const std::vector<uint8_t> &mask, int64_t n,
-                             std::vector<double> &B) {
-    double c[3] = {0, 0, 0};
-    for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < 3; ++k) c[k] += X[i * 3 + k];
-    for (int k = 0; k < 3; ++k) c[k] /= (double)n;
-    B.assign((size_t)n * 3 * 6, 0.0);
-    for (int64_t i = 0; i < n; ++i) {
-        const double x = X[i * 3] - c[0], y = X[i * 3 + 1] - c[1], z = X[i * 3 + 2] - c[2];
-        double *b = &B[(size_t)i * 18];
-        b[0 * 6 + 0] = 1;
-        b[1 * 6 + 1] = 1;
-        b[2 * 6 + 2] = 1;
-        b[0 * 6 + 3] = -y;
-        b[1 * 6 + 3] = x;
-        b[1 * 6 + 4] = -z;
-        b[2 * 6 + 4] = y;
-        b[0 * 6 + 5] = z;
-        b[2 * 6 + 5] = -x;
-        if (!mask.empty())
-            for (int p = 0; p < 3; ++p)
-                if (mask[i * 3 + p])
-                    for (int q = 0; q < 6; ++q) b[p * 6 + q] = 0.0;
-    }
-}
 
 // Lane-per-row SELL for operators with 3-row blocks (many short rows); one
 // wave per row for 6-row blocks (coarse operators, restrictions).
@@ -701,12 +675,20 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     D0.ptr = A->row_ptr;
     D0.col = A->col_idx;
     D0.val = A->val;
-    std::vector<double> X;
-    download(X, coords, (size_t)n * 3, s);
-    std::vector<uint8_t> mask;
-    if (dir_mask) download(mask, dir_mask, (size_t)n * 3, s);
+    // near-nullspace of the current level on the device (level 0: the rigid-body
+    // modes about the node centroid); a host copy is made only when the
+    // tentative prolongator has to take the host path
+    DBuf<double> dB;
+    {
+        std::vector<double> X;
+        download(X, coords, (size_t)n * 3, s);
+        double c[3] = {0, 0, 0};
+        for (int64_t i = 0; i < n; ++i)
+            for (int q = 0; q < 3; ++q) c[q] += X[i * 3 + q];
+        for (int q = 0; q < 3; ++q) c[q] /= (double)n;
+        dev_rigid_body_modes(coords, dir_mask, n, c, dB, s);
+    }
     std::vector<double> B;
-    rigid_body_modes(X, mask, n, B);
     const int k = 6;
     h->L.push_back(std::move(L0));
     DBsr owned;               // operator of the current level below the mesh level
@@ -766,14 +748,36 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
             coarsest = na == 0;
             if (!coarsest) {
                 note("aggregated", l, na, 0);
-                Tentative T = tentative(L.Ah, strength, agg, na, B, L.bs, k);
+                // per-aggregate QR on the device; the host path (which can merge a
+                // rank-deficient aggregate into a neighbour) when that fails
+                Tentative T;
+                DBuf<double> dQ, dBc;
+                bool on_device;
+                {
+                    std::vector<int64_t> off(na + 1, 0);
+                    for (int64_t i = 0; i < L.n; ++i)
+                        if (agg[i] >= 0) ++off[agg[i] + 1];
+                    for (int64_t x = 0; x < na; ++x) off[x + 1] += off[x];
+                    std::vector<int32_t> mem(off[na]);
+                    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+                    for (int64_t i = 0; i < L.n; ++i)
+                        if (agg[i] >= 0) mem[fill[agg[i]]++] = (int32_t)i;
+                    on_device = dev_tentative(off, mem, dB, L.n, L.bs, kRankRtol, dQ, dBc, s);
+                }
+                if (on_device) {
+                    T.nc = na;
+                    T.agg = std::move(agg);
+                } else {
+                    if (B.empty()) download(B, dB.p, (size_t)L.n * L.bs * k, s);
+                    T = tentative(L.Ah, strength, agg, na, B, L.bs, k);
+                    upload(dQ, T.Q, s);
+                    upload(dBc, T.Bc, s);
+                }
                 S = Strength();
                 ds.release();
-                note("tentative prolongator", l, T.nc, 0);
+                note(on_device ? "tentative prolongator (device)" : "tentative prolongator (host)", l, T.nc, 0);
                 DBuf<int32_t> dagg;
-                DBuf<double> dQ;
                 upload(dagg, T.agg, s);
-                upload(dQ, T.Q, s);
                 DBsr P, AP, R, Ac;
                 dev_smoothed_p(*cur, dagg, T.nc, dQ, dnat, 4.0 / (3.0 * L.lam), P, s);
                 note("smoothed P", l, P.nr, P.nnzb);
@@ -792,7 +796,8 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                     N.bs = k;
                     N.n = Ac.nr;
                     dev_pattern_to_host(Ac, N.Ah, s);
-                    B = std::move(T.Bc);
+                    dB = std::move(dBc);
+                    B.clear();
                     download(Pn_ptr, P.ptr, (size_t)P.nr + 1, s);
                     download(Rn_ptr, R.ptr, (size_t)R.nr + 1, s);
                     Pn = std::move(P);

@@ -82,6 +82,21 @@ void dev_dense_inverse_spd(const std::vector<double> &M, int n, DBuf<double> &in
 int64_t dev_aggregate_mis2(const DBsr &A, const DBuf<double> &s, double theta, uint64_t seed, double tie_rtol,
                            std::vector<int32_t> &agg, hipStream_t st);
 
+// Level-0 near-nullspace on the device: the six rigid-body modes about the
+// point c, B [n][3][6] (translations x, y, z, then rotations about z, x, y),
+// rows of constrained DOFs (mask, may be NULL) zero.
+void dev_rigid_body_modes(const double *coords, const uint8_t *mask, int64_t n, const double c[3], DBuf<double> &B,
+                          hipStream_t st);
+
+// Tentative prolongator on the device: for each aggregate (members ascending,
+// given by the host as off/mem), the thin Householder QR of its rows of B
+// [n][bs][6] with diag(R) > 0; Q [n][bs][6] (zero rows for nodes in no
+// aggregate) and Bc [na][6][6] = R.  Returns false, leaving the outputs
+// unspecified, if an aggregate is rank deficient (min |R_kk| < rank_rtol
+// max |R_kk|) or has more than 640 rows: the caller then takes the host path.
+bool dev_tentative(const std::vector<int64_t> &off, const std::vector<int32_t> &mem, const DBuf<double> &B,
+                   int64_t n, int bs, double rank_rtol, DBuf<double> &Q, DBuf<double> &Bc, hipStream_t st);
+
 // Order-independent 64-bit hash of a block pattern (row pointers and columns).
 uint64_t dev_pattern_hash(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st);
 

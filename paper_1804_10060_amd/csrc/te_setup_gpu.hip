@@ -1073,6 +1073,111 @@ __global__ void k_agg_phase2(int64_t nr, const int64_t *__restrict__ ptr, const 
 }  // namespace
 
 namespace {
+__global__ void k_rbm(const double *__restrict__ X, const uint8_t *__restrict__ mask, int64_t n, double cx, double cy,
+                      double cz, double *__restrict__ B) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double x = X[i * 3] - cx, y = X[i * 3 + 1] - cy, z = X[i * 3 + 2] - cz;
+        const double b[18] = {1, 0, 0, -y, 0, z,    // row x
+                              0, 1, 0, x, -z, 0,    // row y
+                              0, 0, 1, 0, y, -x};   // row z
+        for (int p = 0; p < 3; ++p) {
+            const bool fixed = mask && mask[i * 3 + p];
+            for (int q = 0; q < 6; ++q) B[(i * 3 + p) * 6 + q] = fixed ? 0.0 : b[p * 6 + q];
+        }
+    }
+}
+
+constexpr int kTentK = 6;
+constexpr int kTentMaxRows = 640;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wave per aggregate: its m = bs * |J| rows of B in LDS (W, column-major
+// with leading dimension ld), Householder vectors in V.  The same steps as a
+// textbook thin QR: for each column j the reflector v = w - alpha e_j with
+// alpha = -sign(w_j) |w|, beta = 2 / v.v, applied to columns j..5; then
+// Q = H_0 ... H_5 [I; 0], and the signs flipped so that diag(R) > 0.
+__global__ void __launch_bounds__(64) k_tent_qr(const int64_t *__restrict__ off, const int32_t *__restrict__ mem,
+                                                const double *__restrict__ B, int bs, int ld, double rank_rtol,
+                                                double *__restrict__ Q, double *__restrict__ Bc,
+                                                int32_t *__restrict__ bad) {
+    extern __shared__ double sh[];
+    constexpr int K = kTentK;
+    double *W = sh, *V = sh + K * ld;
+    const int x = blockIdx.x, lane = threadIdx.x;
+    const int64_t o0 = off[x];
+    const int m = (int)(off[x + 1] - o0) * bs;
+    if (m < K || m > ld) {  // uniform over the wave
+        if (lane == 0) atomicOr(bad, 1);
+        return;
+    }
+    for (int i = lane; i < m; i += 64) {
+        const int64_t node = mem[o0 + i / bs];
+        const int p = i % bs;
+        for (int c = 0; c < K; ++c) W[c * ld + i] = B[(node * bs + p) * K + c];
+    }
+    __syncthreads();
+    double beta[K];
+    for (int j = 0; j < K; ++j) {
+        double t = 0.0;
+        for (int i = j + lane; i < m; i += 64) t += W[j * ld + i] * W[j * ld + i];
+        const double nrm = sqrt(wave_sum(t));
+        const double alpha = W[j * ld + j] >= 0 ? -nrm : nrm;
+        for (int i = lane; i < m; i += 64) V[j * ld + i] = (i >= j) ? W[j * ld + i] - (i == j ? alpha : 0.0) : 0.0;
+        __syncthreads();
+        t = 0.0;
+        for (int i = j + lane; i < m; i += 64) t += V[j * ld + i] * V[j * ld + i];
+        const double vn = wave_sum(t);
+        beta[j] = vn > 0 ? 2.0 / vn : 0.0;
+        for (int c = j; c < K; ++c) {
+            t = 0.0;
+            for (int i = j + lane; i < m; i += 64) t += V[j * ld + i] * W[c * ld + i];
+            const double f = wave_sum(t) * beta[j];
+            __syncthreads();
+            for (int i = j + lane; i < m; i += 64) W[c * ld + i] -= f * V[j * ld + i];
+            __syncthreads();
+        }
+    }
+    double R[K][K];
+    for (int r = 0; r < K; ++r)
+        for (int c = 0; c < K; ++c) R[r][c] = (c >= r) ? W[c * ld + r] : 0.0;
+    __syncthreads();
+    for (int c = 0; c < K; ++c) {
+        for (int i = lane; i < m; i += 64) W[c * ld + i] = (i == c) ? 1.0 : 0.0;
+        __syncthreads();
+        for (int j = K - 1; j >= 0; --j) {
+            double t = 0.0;
+            for (int i = j + lane; i < m; i += 64) t += V[j * ld + i] * W[c * ld + i];
+            const double f = wave_sum(t) * beta[j];
+            __syncthreads();
+            for (int i = j + lane; i < m; i += 64) W[c * ld + i] -= f * V[j * ld + i];
+            __syncthreads();
+        }
+    }
+    double mx = 0.0, mn = INFINITY, sg[K];
+    for (int r = 0; r < K; ++r) {
+        sg[r] = R[r][r] < 0 ? -1.0 : 1.0;
+        mx = fmax(mx, fabs(R[r][r]));
+        mn = fmin(mn, fabs(R[r][r]));
+    }
+    if (!(mx > 0 && mn >= rank_rtol * mx)) {
+        if (lane == 0) atomicOr(bad, 1);
+        return;
+    }
+    for (int i = lane; i < m; i += 64) {
+        const int64_t node = mem[o0 + i / bs];
+        const int p = i % bs;
+        for (int c = 0; c < K; ++c) Q[(node * bs + p) * K + c] = sg[c] * W[c * ld + i];
+    }
+    if (lane < K * K) {
+        const int r = lane / K, c = lane % K;
+        Bc[(int64_t)x * K * K + lane] = sg[r] * R[r][c];
+    }
+}
+
 // sum over stored blocks of mix64(row * 2^32 + column), per row the row
 // length mixed in as well; wave sums then one 64-bit atomic per wave
 __global__ void k_pattern_hash(const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, int64_t n,
@@ -1086,6 +1191,36 @@ __global__ void k_pattern_hash(const int64_t *__restrict__ ptr, const int32_t *_
     if ((threadIdx.x & 63) == 0) atomicAdd(out, h);
 }
 }  // namespace
+
+void dev_rigid_body_modes(const double *coords, const uint8_t *mask, int64_t n, const double c[3], DBuf<double> &B,
+                          hipStream_t st) {
+    B.alloc(std::max<int64_t>(n * 18, 1));
+    hipLaunchKernelGGL(k_rbm, dim3(grid_for(n)), dim3(256), 0, st, coords, mask, n, c[0], c[1], c[2], B.p);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
+bool dev_tentative(const std::vector<int64_t> &off, const std::vector<int32_t> &mem, const DBuf<double> &B,
+                   int64_t n, int bs, double rank_rtol, DBuf<double> &Q, DBuf<double> &Bc, hipStream_t st) {
+    const int64_t na = (int64_t)off.size() - 1;
+    if (na <= 0) return false;
+    int64_t mmax = 0;
+    for (int64_t x = 0; x < na; ++x) mmax = std::max<int64_t>(mmax, (off[x + 1] - off[x]) * bs);
+    if (mmax > kTentMaxRows || mmax < kTentK) return false;
+    const int ld = (int)mmax;
+    DBuf<int64_t> doff;
+    DBuf<int32_t> dmem, bad(1);
+    upload(doff, off, st);
+    upload(dmem, mem, st);
+    Q.alloc(std::max<int64_t>(n * bs * kTentK, 1));
+    Bc.alloc(na * kTentK * kTentK);
+    TE_CHECK_HIP(hipMemsetAsync(Q.p, 0, Q.bytes(), st));
+    TE_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), st));
+    const size_t lds = (size_t)2 * kTentK * ld * sizeof(double);
+    hipLaunchKernelGGL(k_tent_qr, dim3((unsigned)na), dim3(64), lds, st, doff.p, dmem.p, B.p, bs, ld, rank_rtol, Q.p,
+                       Bc.p, bad.p);
+    TE_CHECK_HIP(hipGetLastError());
+    return read_flag(bad, st) == 0;
+}
 
 uint64_t dev_pattern_hash(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st) {
     DBuf<unsigned long long> d(1);
