@@ -131,6 +131,32 @@ def test_imposed_aggregates_reproduce_hierarchy(disc_case):
         assert np.array_equal(h2.aggregates(l), levels[l].agg)
 
 
+def test_rank_deficient_aggregate_takes_the_host_path(disc_case):
+    """A one-node aggregate (3 rows for 6 modes) cannot be factored on the
+    device: the level goes back to the host QR, which merges it into the
+    neighbour aggregate of largest summed strength, as the oracle does; the
+    resulting hierarchy matches the oracle's."""
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob, A, b, B, levels, h = disc_case
+    agg0 = levels[0].agg.copy()
+    i = int(np.flatnonzero(agg0 >= 0)[len(agg0) // 2])
+    agg0[i] = agg0.max() + 1
+    opt = amg.AMGOptions(coarse_max=400)
+    lv2 = amg.setup(A, B, opt, aggregates=[agg0])
+    assert lv2[0].agg.max() + 1 == levels[0].agg.max() + 1      # the lone node was merged back
+    h2 = te.AMG(oracle_bsr_to_device(A), dev(prob.mesh.coords, torch.float64), dev(prob.mask), aggregates=[agg0],
+                coarse_max=400)
+    info = h2.info()
+    assert info["n_levels"] == len(lv2)
+    assert np.array_equal(h2.aggregates(0), lv2[0].agg)
+    for l, lv in enumerate(lv2):
+        rp, col, val = h2.level_matrix(l)
+        G = sp.bsr_matrix((val, col, rp), shape=lv.A.shape).tocsr()
+        D = G - lv.A.tocsr()
+        assert (abs(D).max() if D.nnz else 0.0) <= OP_TOL * np.abs(lv.A.data).max(), f"A_{l} differs"
+
+
 def test_coarse_symmetric_storage_matches_full(disc_case):
     """Coarse operators stored by their blocks on/above the diagonal
     (coarse_sym = 1, the default) against the full storage of the same
