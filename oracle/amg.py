@@ -36,6 +36,11 @@ is silent the following readings are taken (each is a parameter):
 * eigenvalue: largest Ritz value of 20 Lanczos steps on D^-1/2 A D^-1/2, start
               vector from splitmix64 with seed 0x5EED + level.
 * smoothing:  P = (I - omega D^-1 A) P_tent, omega = 4 / (3 lambda_hat).
+              Option smooth_filtered: A replaced by A^F, the strong blocks
+              (the symmetric strong graph of the MIS-2 rule) and the diagonal
+              of each block row, every dropped block added to the row's
+              diagonal block (so A^F acts on the translations as A does);
+              D and lambda_hat stay those of A.
 * Galerkin:   A_c = P^T A P, coarse block size = near-nullspace size (6).
 * stop:       coarse DOF <= coarse_max (3000) or 10 levels or a coarsening
               ratio above 0.8; the coarsest level is solved by a dense
@@ -71,6 +76,7 @@ class AMGOptions:
     cheb_safety: float = 1.1     # b = cheb_safety * lambda_hat
     max_coarse_ratio: float = 0.8
     aggregation: str = "mis2"  # or "greedy"
+    smooth_filtered: bool = False
 
 
 class RankError(RuntimeError):
@@ -349,6 +355,25 @@ def lanczos_max(A, D, steps, seed):
     return float(ev.max())
 
 
+def filtered_operator(A: sp.bsr_matrix, theta: float):
+    """A^F: per block row the diagonal block plus the dropped blocks (summed
+    in stored order), and the strong off-diagonal blocks unchanged."""
+    flag, (rows, cols, _) = symmetric_strong(A, theta)
+    diag = rows == cols
+    keep = flag | diag
+    data = A.data.copy()
+    n = A.shape[0] // A.blocksize[0]
+    dpos = np.full(n, -1, np.int64)
+    dpos[rows[diag]] = np.flatnonzero(diag)
+    assert np.all(dpos >= 0), "a block row without its diagonal block"
+    dropped = np.flatnonzero(~keep)
+    for k in dropped.tolist():            # stored order within each row
+        data[dpos[rows[k]]] += A.data[k]
+    counts = np.bincount(rows[keep], minlength=n)
+    indptr = np.concatenate([[0], np.cumsum(counts)])
+    return sp.bsr_matrix((data[keep], cols[keep], indptr), shape=A.shape)
+
+
 def smooth_prolongator(A, D, P_tent, lam_hat):
     omega = 4.0 / (3.0 * lam_hat)
     return (P_tent - omega * sp.diags(1.0 / D) @ (A.tocsr() @ P_tent)).tocsr()
@@ -401,7 +426,7 @@ def setup(A: sp.bsr_matrix, B: np.ndarray, opt: AMGOptions = AMGOptions(), aggre
         if n_agg == 0:
             break
         P_tent, Bc, agg = tentative_prolongator(agg, n_agg, Bl, bs, sinfo)
-        P = smooth_prolongator(Al, D, P_tent, lev.lam)
+        P = smooth_prolongator(filtered_operator(Al, theta) if opt.smooth_filtered else Al, D, P_tent, lev.lam)
         Ac = galerkin(Al, P, Bc.shape[1])
         if Ac.shape[0] > opt.max_coarse_ratio * ndof:
             break

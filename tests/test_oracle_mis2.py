@@ -164,3 +164,31 @@ def test_amg_with_parallel_aggregation_converges(deg, cm):
         assert res.converged and np.linalg.norm(b - A @ res.u) <= 1e-8 * np.linalg.norm(b)
         its[mode] = res.iters
     assert its["mis2"] <= 1.3 * its["greedy"] + 2
+
+
+def test_filtered_operator_keeps_strong_blocks_and_translations():
+    """A^F (prolongator smoothing option): strong and diagonal blocks only,
+    the dropped blocks lumped into the diagonal, so A^F t = A t for the three
+    translations t; the smoothed prolongator gets fewer blocks and the
+    hierarchy still preconditions CG to the tolerance."""
+    prob = mg.disc_problem(8, 34, 2, 2, seed=5)
+    A, b, _, _ = fem.assemble_problem(prob)
+    n = A.shape[0] // 3
+    Af = amg.filtered_operator(A, 0.08)
+    flag, (rows, cols, s) = amg.symmetric_strong(A, 0.08)
+    assert Af.nnz // 9 == int(flag.sum()) + n
+    for q in range(3):
+        t = np.zeros(3 * n)
+        t[q::3] = 1.0
+        assert np.abs(Af @ t - A @ t).max() <= 1e-12 * np.abs(A.data).max()
+    # a rotation is not preserved in general (only the block row sums are)
+    x = prob.mesh.coords
+    rot = np.stack([-x[:, 1], x[:, 0], np.zeros(n)], axis=1).reshape(-1)
+    assert np.abs(Af @ rot - A @ rot).max() > 1e-6 * np.abs(A @ rot).max()
+    B = fem.rigid_body_modes(prob.mesh.coords, prob.mask)
+    full = amg.setup(A, B, amg.AMGOptions(coarse_max=400))
+    filt = amg.setup(A, B, amg.AMGOptions(coarse_max=400, smooth_filtered=True))
+    assert filt[0].P.nnz < full[0].P.nnz and filt[1].A.nnz < full[1].A.nnz
+    opt = amg.AMGOptions(coarse_max=400, smooth_filtered=True)
+    res = krylov.pcg(A, b, lambda r: amg.vcycle(filt, r, opt=opt))
+    assert res.converged and np.linalg.norm(b - A @ res.u) <= 1e-8 * np.linalg.norm(b)
