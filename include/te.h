@@ -192,6 +192,10 @@ typedef struct {
                                 transposed from their mirror (symmetric pattern only;
                                 float32 copies keep full storage) (1)                   */
     int32_t aggregation;     /* TE_AGG_MIS2 (default) or TE_AGG_GREEDY                   */
+    int32_t smooth_filtered; /* 1: smooth the prolongator with the filtered operator:
+                                per block row the strong blocks (s_IJ or s_JI >= theta_l)
+                                and the diagonal block plus the dropped blocks; D and
+                                lambda_hat stay those of A (0)                          */
 } amg_options;
 
 /* Fills the defaults listed above. */

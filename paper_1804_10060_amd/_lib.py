@@ -56,7 +56,7 @@ class AmgOptions(C.Structure):
                 ("lanczos_steps", C.c_int32), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("cheb_safety", C.c_double), ("max_coarse_ratio", C.c_double), ("build_fp32", C.c_int32),
                 ("host_threads", C.c_int32), ("max_nrhs", C.c_int32), ("coarse_sym", C.c_int32),
-                ("aggregation", C.c_int32)]
+                ("aggregation", C.c_int32), ("smooth_filtered", C.c_int32)]
 
 
 class AmgInfo(C.Structure):

@@ -773,13 +773,16 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                     upload(dQ, T.Q, s);
                     upload(dBc, T.Bc, s);
                 }
+                DBsr Af;  // filtered operator of the prolongator smoothing (option)
+                if (o.smooth_filtered) dev_filtered(*cur, ds, theta, Af, s);
                 S = Strength();
                 ds.release();
                 note(on_device ? "tentative prolongator (device)" : "tentative prolongator (host)", l, T.nc, 0);
                 DBuf<int32_t> dagg;
                 upload(dagg, T.agg, s);
                 DBsr P, AP, R, Ac;
-                dev_smoothed_p(*cur, dagg, T.nc, dQ, dnat, 4.0 / (3.0 * L.lam), P, s);
+                dev_smoothed_p(o.smooth_filtered ? Af : *cur, dagg, T.nc, dQ, dnat, 4.0 / (3.0 * L.lam), P, s);
+                Af.release();
                 note("smoothed P", l, P.nr, P.nnzb);
                 dev_mult(*cur, P, AP, s);
                 note("A P", l, AP.nr, AP.nnzb);
@@ -924,6 +927,7 @@ extern "C" void amg_options_default(amg_options *o) {
     o->max_nrhs = 1;
     o->coarse_sym = 1;
     o->aggregation = TE_AGG_MIS2;
+    o->smooth_filtered = 0;
 }
 
 extern "C" int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,

@@ -82,6 +82,11 @@ void dev_dense_inverse_spd(const std::vector<double> &M, int n, DBuf<double> &in
 int64_t dev_aggregate_mis2(const DBsr &A, const DBuf<double> &s, double theta, uint64_t seed, double tie_rtol,
                            std::vector<int32_t> &agg, hipStream_t st);
 
+// Filtered operator for the prolongator smoothing: per block row the diagonal
+// block plus every dropped block (summed in stored order) and the strong
+// off-diagonal blocks unchanged; strong = s_ij or s_ji >= theta (i != j).
+void dev_filtered(const DBsr &A, const DBuf<double> &s, double theta, DBsr &F, hipStream_t st);
+
 // Level-0 near-nullspace on the device: the six rigid-body modes about the
 // point c, B [n][3][6] (translations x, y, z, then rotations about z, x, y),
 // rows of constrained DOFs (mask, may be NULL) zero.

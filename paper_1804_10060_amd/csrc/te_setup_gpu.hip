@@ -1192,6 +1192,85 @@ __global__ void k_pattern_hash(const int64_t *__restrict__ ptr, const int32_t *_
 }
 }  // namespace
 
+namespace {
+__global__ void k_filter_count(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                               const uint8_t *__restrict__ flag, int64_t *__restrict__ cnt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        bool diag = false;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            diag = diag || col[k] == i;
+            c += (flag[k] || col[k] == i) ? 1 : 0;
+        }
+        cnt[i] = diag ? c : -1;
+    }
+}
+
+template <int BB>
+__global__ void k_filter_copy(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                              const double *__restrict__ val, const uint8_t *__restrict__ flag,
+                              const int64_t *__restrict__ fptr, int32_t *__restrict__ fcol, double *__restrict__ fval) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double d[BB];
+        int64_t kd = -1;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+            if (col[k] == i) kd = k;
+        if (kd < 0) continue;  // rejected on the host before the launch
+        for (int e = 0; e < BB; ++e) d[e] = val[kd * BB + e];
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+            if (!flag[k] && col[k] != i)
+                for (int e = 0; e < BB; ++e) d[e] += val[k * BB + e];
+        int64_t o = fptr[i];
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            if (col[k] == i) {
+                fcol[o] = (int32_t)i;
+                for (int e = 0; e < BB; ++e) fval[o * BB + e] = d[e];
+                ++o;
+            } else if (flag[k]) {
+                fcol[o] = col[k];
+                for (int e = 0; e < BB; ++e) fval[o * BB + e] = val[k * BB + e];
+                ++o;
+            }
+        }
+    }
+}
+}  // namespace
+
+void dev_filtered(const DBsr &A, const DBuf<double> &s, double theta, DBsr &F, hipStream_t st) {
+    TE_REQUIRE(A.nr == A.nc && A.br == A.bc && (A.br == 3 || A.br == 6), TE_EINVAL, "filtered operator: block %dx%d",
+               A.br, A.bc);
+    const int64_t n = A.nr;
+    DBuf<uint8_t> flag(std::max<int64_t>(A.nnzb, 1));
+    TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, std::max<int64_t>(A.nnzb, 1), st));
+    hipLaunchKernelGGL(k_strong_sym, dim3(grid_for(n)), dim3(256), 0, st, n, A.ptr, A.col, s.p, theta, flag.p);
+    DBuf<int64_t> cnt(std::max<int64_t>(n, 1));
+    hipLaunchKernelGGL(k_filter_count, dim3(grid_for(n)), dim3(256), 0, st, n, A.ptr, A.col, flag.p, cnt.p);
+    TE_CHECK_HIP(hipGetLastError());
+    std::vector<int64_t> c;
+    download(c, cnt.p, (size_t)n, st);
+    std::vector<int64_t> fp(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        TE_REQUIRE(c[i] >= 1, TE_EINVAL, "filtered operator: block row %lld has no diagonal block", (long long)i);
+        fp[i + 1] = fp[i] + c[i];
+    }
+    F.release();
+    F.br = F.bc = A.br;
+    F.nr = F.nc = n;
+    F.nnzb = fp[n];
+    upload(F.ptr_own, fp, st);
+    F.col_own.alloc(std::max<int64_t>(F.nnzb, 1));
+    F.val_own.alloc(std::max<int64_t>(F.nnzb * A.br * A.bc, 1));
+    F.bind();
+    if (A.br == 3)
+        hipLaunchKernelGGL(k_filter_copy<9>, dim3(grid_for(n)), dim3(256), 0, st, n, A.ptr, A.col, A.val, flag.p,
+                           F.ptr, F.col_own.p, F.val_own.p);
+    else
+        hipLaunchKernelGGL(k_filter_copy<36>, dim3(grid_for(n)), dim3(256), 0, st, n, A.ptr, A.col, A.val, flag.p,
+                           F.ptr, F.col_own.p, F.val_own.p);
+    TE_CHECK_HIP(hipGetLastError());
+    TE_CHECK_HIP(hipStreamSynchronize(st));
+}
+
 void dev_rigid_body_modes(const double *coords, const uint8_t *mask, int64_t n, const double c[3], DBuf<double> &B,
                           hipStream_t st) {
     B.alloc(std::max<int64_t>(n * 18, 1));

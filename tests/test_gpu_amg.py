@@ -157,6 +157,36 @@ def test_rank_deficient_aggregate_takes_the_host_path(disc_case):
         assert (abs(D).max() if D.nnz else 0.0) <= OP_TOL * np.abs(lv.A.data).max(), f"A_{l} differs"
 
 
+def test_filtered_smoothing_matches_oracle():
+    """amg_options.smooth_filtered: the prolongators smoothed with the
+    filtered operator, level by level against the oracle's, and the solve."""
+    from oracle import krylov
+    prob = mg.disc_problem(8, 34, 2, 2, seed=5)
+    A, b, B = _oracle_system(prob)
+    opt = amg.AMGOptions(coarse_max=400, smooth_filtered=True)
+    levels = amg.setup(A, B, opt)
+    h = _gpu_amg_from_oracle_matrix(prob, A, coarse_max=400, smooth_filtered=1)
+    info = h.info()
+    assert info["n_levels"] == len(levels)
+    for l, lv in enumerate(levels):
+        if l + 1 < len(levels):
+            assert np.array_equal(h.aggregates(l), lv.agg), f"aggregates differ at level {l}"
+            assert info["p_nnzb"][l] * lv.bs * 6 >= lv.P.nnz  # block pattern holds the scalar nonzeros
+        rp, col, val = h.level_matrix(l)
+        G = sp.bsr_matrix((val, col, rp), shape=lv.A.shape).tocsr()
+        D = G - lv.A.tocsr()
+        assert (abs(D).max() if D.nnz else 0.0) <= OP_TOL * np.abs(lv.A.data).max(), f"A_{l} differs"
+    full = amg.setup(A, B, amg.AMGOptions(coarse_max=400))
+    assert levels[1].A.nnz < full[1].A.nnz
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    u, rep = h.solve(dev(b, torch.float64))
+    res = krylov.pcg(A, b, lambda r: amg.vcycle(levels, r, opt=opt))
+    say(f"filtered smoothing: iters gpu {rep.iters[0]} oracle {res.iters}")
+    assert rep.converged == [1] and abs(rep.iters[0] - res.iters) <= 1
+    assert np.linalg.norm(u.cpu().numpy() - res.u) <= 1e-8 * np.linalg.norm(res.u)
+
+
 def test_coarse_symmetric_storage_matches_full(disc_case):
     """Coarse operators stored by their blocks on/above the diagonal
     (coarse_sym = 1, the default) against the full storage of the same
