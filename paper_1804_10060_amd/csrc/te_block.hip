@@ -152,11 +152,7 @@ __global__ void __launch_bounds__(UBLK) k_block_xr(int64_t rows, int m, const do
     const int nk = (m + 3) / 4, nc = (m + 15) / 16;
     double rr[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t r0 = ((int64_t)blockIdx.x * nw + w) * 16; r0 < rows; r0 += (int64_t)gridDim.x * nw * 16) {
-        d4 dx[4], dr[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) dx[c] = dr[c] = d4{0.0, 0.0, 0.0, 0.0};
-        // all fragments of the 16 rows first (loads in flight together), then
-        // the matrix-core steps
+        // all fragments of the 16 rows first (loads in flight together)
         const int64_t ra = r0 + kc;
         double pa[GM / 4], qa[GM / 4];
 #pragma unroll
@@ -166,30 +162,37 @@ __global__ void __launch_bounds__(UBLK) k_block_xr(int64_t rows, int m, const do
             pa[s] = ok ? P[ra * m + k] : 0.0;
             qa[s] = ok ? Q[ra * m + k] : 0.0;
         }
-#pragma unroll
-        for (int s = 0; s < GM / 4; ++s) {
-            if (s >= nk) break;
-            const int k = 4 * s + kr;
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (c < nc) {
-                    const double bv = s_a[k * GM + c * 16 + kc];
-                    dx[c] = mfma(pa[s], bv, dx[c]);
-                    dr[c] = mfma(qa[s], bv, dr[c]);
-                }
-        }
+        // one 16-column tile at a time: its X and R entries are loaded before
+        // its matrix-core steps, which then cover their latency
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
+            if (c >= nc) break;
             const int col = c * 16 + kc;
-            if (c >= nc || col >= m) continue;
+            double xo[4], ro[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t row = r0 + kr + 4 * q;
-                if (row >= rows) continue;
-                X[row * m + col] += dx[c][q];
-                const double r = R[row * m + col] - dr[c][q];
-                R[row * m + col] = r;
-                rr[c] += r * r;
+                const bool ok = row < rows && col < m;
+                xo[q] = ok ? X[row * m + col] : 0.0;
+                ro[q] = ok ? R[row * m + col] : 0.0;
+            }
+            d4 dx = d4{0.0, 0.0, 0.0, 0.0}, dr = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < GM / 4; ++s) {
+                if (s >= nk) break;
+                const double bv = s_a[(4 * s + kr) * GM + col];
+                dx = mfma(pa[s], bv, dx);
+                dr = mfma(qa[s], bv, dr);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = r0 + kr + 4 * q;
+                if (col < m && row < rows) {
+                    X[row * m + col] = xo[q] + dx[q];
+                    const double r = ro[q] - dr[q];
+                    R[row * m + col] = r;
+                    rr[c] += r * r;
+                }
             }
         }
     }
