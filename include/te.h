@@ -206,11 +206,15 @@ void amg_options_default(amg_options *opt);
  *   dir_mask: device [N][3] or NULL: near-nullspace rows of constrained DOFs
  *             are zeroed;
  *   out: receives a library-owned handle (release with amg_destroy).
- * Strength of connection, prolongator smoothing, the products A P and
- * P^T (A P) and the packing into the solver layouts run on the device; the
- * greedy aggregation, the per-aggregate QR and the coarsest factor on the
- * host (host_threads threads).  Only the pattern, the strength values and the
- * tentative prolongator cross to the host and back.
+ * The rigid-body modes, strength of connection, the MIS-2 aggregation, the
+ * per-aggregate QR of the tentative prolongator, prolongator smoothing, the
+ * products A P and P^T (A P), the packing into the solver layouts and the
+ * coarsest inverse run on the device.  On the host (host_threads threads):
+ * the greedy aggregation when chosen, the merge of a rank-deficient
+ * aggregate into a neighbour (the level's QR then runs on the host), the
+ * storage orders and the aggregate ids of the MIS-2 roots.  Only the pattern
+ * and the aggregate maps cross to the host (the strengths too under the
+ * greedy rule or a merge).
  * The matrix values are copied; A may be freed afterwards.  Synchronises
  * `stream`.  Errors: TE_EINVAL, TE_ENOMEM, TE_EHIP, TE_ERANK, TE_ECHOL. */
 int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask,

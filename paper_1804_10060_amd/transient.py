@@ -47,7 +47,6 @@ class ElasticTransient:
         self.coords, self.mask = coords, mask
         self.reuse, self.rtol, self.amg_opts = reuse, rtol, amg_opts
         self.h = None
-        self.A_setup = None   # the matrix the hierarchy was built from
         self.u = None
 
     def _sync(self):
@@ -67,7 +66,6 @@ class ElasticTransient:
             if self.h is not None:
                 self.h.close()
             self.h = AMG(A, self.coords, self.mask, **self.amg_opts)
-            self.A_setup = A
         else:
             self.h.set_operator(A)
         self._sync()
