@@ -165,3 +165,32 @@ def test_driver_follows_the_oracle_step_sequence():
     for r, u in zip(recs, us):
         A, b = _oracle_system(prob, mat, faces, p, T_np(r.t))
         assert np.linalg.norm(b - A @ u) <= 1.0000001e-8 * np.linalg.norm(b), f"step at t = {r.t}"
+
+
+def test_reused_hierarchy_with_mixed_precision_and_block_cg():
+    """After amg_set_operator the float32 V-cycle (the setup matrix's copies)
+    inside float64 flexible CG, and block CG over three columns, both solve
+    the new system to the true residual on the oracle's own assembly."""
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob = mg.disc_problem(6, 26, 2, 2, seed=2)
+    m = prob.mesh
+    mat, faces, p = _materials_setup(prob)
+    Ta, Tb = (293.0 + (prob.T - 293.0) * s for s in (0.5, 0.6))
+    Aa, ba = _gpu_system(prob, mat, faces, p, Ta)
+    Ab, bb = _gpu_system(prob, mat, faces, p, Tb)
+    Abo, bbo = _oracle_system(prob, mat, faces, p, Tb)
+    h = te.AMG(Aa, dev(m.coords, torch.float64), dev(prob.mask), coarse_max=400, max_nrhs=4)
+    h.set_operator(Ab)
+    u, rep = h.solve(bb, precision="mixed")
+    assert rep.converged == [1]
+    uh = u.cpu().numpy()
+    assert np.linalg.norm(bbo - Abo @ uh) <= 1.0000001e-8 * np.linalg.norm(bbo)
+    B3 = torch.stack([bb.reshape(-1, 3), 0.5 * bb.reshape(-1, 3), ba.reshape(-1, 3)], dim=2).contiguous()
+    U, repb = h.solve(B3, block=True)
+    assert all(repb.converged)
+    Uh = U.cpu().numpy().reshape(-1, 3)
+    Bh = B3.cpu().numpy().reshape(-1, 3)
+    for j in range(3):
+        assert np.linalg.norm(Bh[:, j] - Abo @ Uh[:, j]) <= 1.0000001e-8 * np.linalg.norm(Bh[:, j]) + \
+            1e-12 * np.linalg.norm(Bh[:, j]), f"column {j}"
