@@ -477,7 +477,9 @@ static double lanczos_estimate(const Level &L, int steps, uint64_t seed, hipStre
     const int64_t n = L.n * L.bs;
     DBuf<double> v(n), vp(n), w(n), t(n), dh(n), part(dot_nblocks(n) + 1), res(1);
     std::vector<double> dhh(n);
-    for (int64_t i = 0; i < n; ++i) dhh[i] = 1.0 / std::sqrt(L.dstore[i]);
+    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i) dhh[i] = 1.0 / std::sqrt(L.dstore[i]);
+    });
     TE_CHECK_HIP(hipMemcpyAsync(dh.p, dhh.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
     lanczos_start(v.p, L.perm.p, L.n, L.bs, seed, s);
     double nv = std::sqrt(dev_dot(v.p, v.p, n, part, res, s));
