@@ -212,9 +212,9 @@ void amg_options_default(amg_options *opt);
  * coarsest inverse run on the device.  On the host (host_threads threads):
  * the greedy aggregation when chosen, the merge of a rank-deficient
  * aggregate into a neighbour (the level's QR then runs on the host), the
- * storage orders and the aggregate ids of the MIS-2 roots.  Only the pattern
- * and the aggregate maps cross to the host (the strengths too under the
- * greedy rule or a merge).
+ * storage orders and the aggregate ids of the MIS-2 roots.  Only the row
+ * pointers, the coarse patterns and the aggregate maps cross to the host (the
+ * mesh level's columns and strengths too under the greedy rule or a merge).
  * The matrix values are copied; A may be freed afterwards.  Synchronises
  * `stream`.  Errors: TE_EINVAL, TE_ENOMEM, TE_EHIP, TE_ERANK, TE_ECHOL. */
 int amg_setup(const te_bsr *A, const double *coords, const uint8_t *dir_mask,

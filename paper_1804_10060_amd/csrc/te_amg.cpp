@@ -511,6 +511,37 @@ static double lanczos_estimate(const Level &L, int steps, uint64_t seed, hipStre
 // the setup
 // ---------------------------------------------------------------------------
 
+// The level's columns on the host (level 0 keeps them on the device unless a
+// host step needs them; the coarse levels always have them).
+static void host_cols(Level &L, const DBsr &D, hipStream_t s) {
+    const int64_t nnzb = L.Ah.ptr.empty() ? 0 : L.Ah.ptr.back();
+    if ((int64_t)L.Ah.col.size() != nnzb) download(L.Ah.col, D.col, (size_t)nnzb, s);
+}
+
+static int64_t host_nnzb(const HBsr &H) { return H.ptr.empty() ? 0 : H.ptr.back(); }
+
+// Columns of a level in natural numbering: the host copy, or for a mesh level
+// without one, read back from the packed lane-per-row operator (storage row r
+// holds natural row perm[r], its entries in their original order, columns
+// stored in the storage numbering).
+static std::vector<int32_t> level_cols(const Level &L) {
+    if ((int64_t)L.Ah.col.size() == host_nnzb(L.Ah)) return L.Ah.col;
+    const Sell &S = L.A;
+    TE_REQUIRE(S.format == FMT_SELL, TE_EINVAL, "level %d has no host pattern", L.index);
+    hipStream_t s = nullptr;
+    std::vector<int32_t> sc, off, rl;
+    download(sc, S.col.p, S.col.n, s);
+    download(off, S.slice_off.p, (size_t)S.nslices + 1, s);
+    download(rl, S.rowlen.p, S.rowlen.n, s);
+    std::vector<int32_t> col((size_t)host_nnzb(L.Ah));
+    for (int64_t r = 0; r < S.nrows; ++r) {
+        const int64_t o = L.perm_h[r], d0 = L.Ah.ptr[o], sl = r / SELL_C, ln = r % SELL_C;
+        TE_REQUIRE(rl[r] == L.Ah.ptr[o + 1] - d0, TE_EHIP, "packed row %lld has the wrong length", (long long)r);
+        for (int64_t k = 0; k < rl[r]; ++k) col[d0 + k] = L.perm_h[sc[(size_t)(off[sl] + k) * SELL_C + ln]];
+    }
+    return col;
+}
+
 // Lane-per-row SELL for operators with 3-row blocks (many short rows); one
 // wave per row for 6-row blocks (coarse operators, restrictions).
 static int fmt_for(int br) { return br >= 6 ? FMT_ROWWAVE : FMT_SELL; }
@@ -646,29 +677,14 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     TE_REQUIRE(L0.Ah.ptr[0] == 0 && L0.Ah.ptr[n] == A->nnzb, TE_EINVAL, "row_ptr inconsistent with nnzb");
     for (int64_t i = 0; i < n; ++i)
         TE_REQUIRE(L0.Ah.ptr[i + 1] >= L0.Ah.ptr[i], TE_EINVAL, "row_ptr decreases at row %lld", (long long)i);
-    download(L0.Ah.col, A->col_idx, (size_t)A->nnzb, s);
+    note("row pointers checked", 0, n, A->nnzb);
+    // the columns stay on the device: the host needs them only for the greedy
+    // rule or a rank-deficient merge (host_cols below)
     {
-        std::atomic<int64_t> bad{INT64_MAX};
-        parallel_for(n, [&](int64_t lo, int64_t hi, int) {
-            for (int64_t i = lo; i < hi; ++i) {
-                bool diag = false, ok = true;
-                for (int64_t k = L0.Ah.ptr[i]; k < L0.Ah.ptr[i + 1]; ++k) {
-                    const int32_t c = L0.Ah.col[k];
-                    ok = ok && c >= 0 && c < n;
-                    diag = diag || c == i;
-                }
-                if (!ok || !diag) {
-                    int64_t cur = bad.load();
-                    while (i < cur && !bad.compare_exchange_weak(cur, i)) {
-                    }
-                    break;
-                }
-            }
-        });
-        const int64_t i = bad.load();
-        TE_REQUIRE(i == INT64_MAX, TE_EINVAL, "row %lld has a column index out of range or no diagonal block",
-                   (long long)i);
+        const int64_t i = dev_check_pattern(A->row_ptr, A->col_idx, n, s);
+        TE_REQUIRE(i < 0, TE_EINVAL, "row %lld has a column index out of range or no diagonal block", (long long)i);
     }
+    note("columns checked", 0, n, A->nnzb);
     h->pattern_hash = dev_pattern_hash(A->row_ptr, A->col_idx, n, s);
     DBsr D0;  // view of the caller's matrix
     D0.br = D0.bc = 3;
@@ -690,6 +706,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
         for (int q = 0; q < 3; ++q) c[q] /= (double)n;
         dev_rigid_body_modes(coords, dir_mask, n, c, dB, s);
     }
+    note("near-nullspace", 0, n, 0);
     std::vector<double> B;
     const int k = 6;
     h->L.push_back(std::move(L0));
@@ -700,10 +717,10 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     bool pending = false;
     for (int l = 0;; ++l) {
         Level &L = h->L[l];
-        note("pack operator", l, L.n, L.Ah.nnzb());
+        note("pack operator", l, L.n, host_nnzb(L.Ah));
         DBuf<double> dnat;
         finish_level(L, *cur, o, dnat, s);
-        note("operator packed", l, L.n, L.Ah.nnzb());
+        note("operator packed", l, L.n, host_nnzb(L.Ah));
         if (pending) {
             Level &U = h->L[l - 1];
             const auto pord = window_sorted_order(Pn_ptr, 4096);
@@ -745,6 +762,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
             } else if (par) {
                 na = dev_aggregate_mis2(*cur, ds, theta, kMisSeed + (uint64_t)l, kTieRtol, agg, s);
             } else {
+                host_cols(L, *cur, s);
                 na = greedy_aggregate(L.Ah, S, theta, agg);
             }
             coarsest = na == 0;
@@ -771,6 +789,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                     T.agg = std::move(agg);
                 } else {
                     if (B.empty()) download(B, dB.p, (size_t)L.n * L.bs * k, s);
+                    host_cols(L, *cur, s);
                     T = tentative(L.Ah, strength, agg, na, B, L.bs, k);
                     upload(dQ, T.Q, s);
                     upload(dBc, T.Bc, s);
@@ -859,7 +878,7 @@ static void unpack_values(const Level &L, std::vector<double> &val) {
     hipStream_t s = nullptr;
     std::vector<double> sv;
     download(sv, S.val.p, S.val.n, s);
-    val.assign((size_t)L.Ah.nnzb() * bb, 0.0);
+    val.assign((size_t)host_nnzb(L.Ah) * bb, 0.0);
     if (S.format == FMT_ROWWAVE && S.sym()) {
         // blocks on/above the diagonal in the row's natural order, the others
         // as the transposes of their mirrors, in the same order
@@ -958,9 +977,9 @@ static int set_operator_impl(amg_handle *h, const te_bsr *A, hipStream_t s) {
     }
     Level &L0 = h->L[0];
     TE_REQUIRE(A->row_ptr && A->col_idx && A->val, TE_EINVAL, "NULL matrix array");
-    TE_REQUIRE(A->n_brows == L0.n && A->nnzb == L0.Ah.nnzb(), TE_EINVAL,
+    TE_REQUIRE(A->n_brows == L0.n && A->nnzb == host_nnzb(L0.Ah), TE_EINVAL,
                "operator has %lld block rows and %lld blocks, the setup matrix %lld and %lld", (long long)A->n_brows,
-               (long long)A->nnzb, (long long)L0.n, (long long)L0.Ah.nnzb());
+               (long long)A->nnzb, (long long)L0.n, (long long)host_nnzb(L0.Ah));
     TE_REQUIRE(dev_pattern_hash(A->row_ptr, A->col_idx, A->n_brows, s) == h->pattern_hash, TE_EINVAL,
                "operator pattern differs from the setup matrix's");
     DBsr D;
@@ -996,7 +1015,7 @@ extern "C" int amg_get_info(const amg_handle *h, amg_info *info) {
         for (size_t l = 0; l < h->L.size() && l < 16; ++l) {
             const Level &L = h->L[l];
             info->n_dof[l] = L.n * L.bs;
-            info->nnzb[l] = L.Ah.nnzb();
+            info->nnzb[l] = host_nnzb(L.Ah);
             info->bs[l] = L.bs;
             info->lambda_hat[l] = L.lam;
             info->p_nnzb[l] = L.p_nnzb;
@@ -1026,9 +1045,12 @@ extern "C" int amg_get_level_matrix(const amg_handle *h, int32_t level, int64_t 
         const Level &L = h->L[level];
         const HBsr &M = L.Ah;
         *n_rows_out = M.nr;
-        *nnzb_out = M.nnzb();
+        *nnzb_out = host_nnzb(M);
         if (row_ptr) std::copy(M.ptr.begin(), M.ptr.end(), row_ptr);
-        if (col) std::copy(M.col.begin(), M.col.end(), col);
+        if (col) {
+            const std::vector<int32_t> c = level_cols(L);
+            std::copy(c.begin(), c.end(), col);
+        }
         if (val) {
             std::vector<double> v;
             unpack_values(L, v);

@@ -102,6 +102,10 @@ void dev_rigid_body_modes(const double *coords, const uint8_t *mask, int64_t n, 
 bool dev_tentative(const std::vector<int64_t> &off, const std::vector<int32_t> &mem, const DBuf<double> &B,
                    int64_t n, int bs, double rank_rtol, DBuf<double> &Q, DBuf<double> &Bc, hipStream_t st);
 
+// First block row (ascending) with a column index outside [0, n) or without
+// its diagonal block, or -1.
+int64_t dev_check_pattern(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st);
+
 // Order-independent 64-bit hash of a block pattern (row pointers and columns).
 uint64_t dev_pattern_hash(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st);
 

@@ -1301,6 +1301,32 @@ bool dev_tentative(const std::vector<int64_t> &off, const std::vector<int32_t> &
     return read_flag(bad, st) == 0;
 }
 
+namespace {
+__global__ void k_check_pattern(const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, int64_t n,
+                                unsigned long long *__restrict__ bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        bool ok = true, diag = false;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t c = col[k];
+            ok = ok && c >= 0 && c < n;
+            diag = diag || c == i;
+        }
+        if (!ok || !diag) atomicMin(bad, (unsigned long long)i);
+    }
+}
+}  // namespace
+
+int64_t dev_check_pattern(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st) {
+    DBuf<unsigned long long> d(1);
+    TE_CHECK_HIP(hipMemsetAsync(d.p, 0xFF, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_check_pattern, dim3(grid_for(n)), dim3(256), 0, st, ptr, col, n, d.p);
+    TE_CHECK_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    TE_CHECK_HIP(hipMemcpyAsync(&h, d.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    TE_CHECK_HIP(hipStreamSynchronize(st));
+    return h == ~0ull ? -1 : (int64_t)h;
+}
+
 uint64_t dev_pattern_hash(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st) {
     DBuf<unsigned long long> d(1);
     TE_CHECK_HIP(hipMemsetAsync(d.p, 0, sizeof(unsigned long long), st));
