@@ -476,11 +476,7 @@ static double dev_dot(const double *x, const double *y, int64_t n, DBuf<double> 
 static double lanczos_estimate(const Level &L, int steps, uint64_t seed, hipStream_t s) {
     const int64_t n = L.n * L.bs;
     DBuf<double> v(n), vp(n), w(n), t(n), dh(n), part(dot_nblocks(n) + 1), res(1);
-    std::vector<double> dhh(n);
-    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t i = lo; i < hi; ++i) dhh[i] = 1.0 / std::sqrt(L.dstore[i]);
-    });
-    TE_CHECK_HIP(hipMemcpyAsync(dh.p, dhh.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+    dev_rsqrt(L.dstore.p, dh.p, n, s);
     lanczos_start(v.p, L.perm.p, L.n, L.bs, seed, s);
     double nv = std::sqrt(dev_dot(v.p, v.p, n, part, res, s));
     scal(v.p, 1.0 / nv, n, s);
@@ -563,27 +559,14 @@ static void finish_level(Level &L, const DBsr &D, const amg_options &o, DBuf<dou
     }
     upload(L.perm, L.perm_h, s);
     dev_diag(D, dnat, s);
-    std::vector<double> dh;
-    download(dh, dnat.p, (size_t)L.n * L.bs, s);
-    for (int64_t i = 0; i < L.n; ++i)
-        for (int p = 0; p < L.bs; ++p)
-            TE_REQUIRE(dh[(size_t)i * L.bs + p] > 0, TE_EINVAL, "non-positive diagonal entry %g at level %d row %lld",
-                       dh[(size_t)i * L.bs + p], L.index, (long long)i);
-    L.dstore.assign((size_t)L.n * L.bs, 0.0);
-    std::vector<double> dinv((size_t)L.n * L.bs);
-    std::vector<float> dinv32((size_t)L.n * L.bs);
-    parallel_for(L.n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t i = lo; i < hi; ++i)
-            for (int p = 0; p < L.bs; ++p) {
-                const double d = dh[(size_t)L.perm_h[i] * L.bs + p];
-                L.dstore[i * L.bs + p] = d;
-                dinv[i * L.bs + p] = 1.0 / d;
-                dinv32[i * L.bs + p] = (float)(1.0 / d);
-            }
-    });
-    upload(L.dinv, dinv, s);
-    if (o.build_fp32) upload(L.dinv32, dinv32, s);
-    TE_CHECK_HIP(hipStreamSynchronize(s));
+    // diagonal, its reciprocals and the positivity check in storage order on the device
+    const int64_t nd = std::max<int64_t>(L.n * L.bs, 1);
+    L.dstore.alloc(nd);
+    L.dinv.alloc(nd);
+    if (o.build_fp32) L.dinv32.alloc(nd);
+    const int64_t bad = dev_diag_store(dnat.p, L.perm.p, L.n, L.bs, L.dstore.p, L.dinv.p,
+                                       o.build_fp32 ? L.dinv32.p : nullptr, s);
+    TE_REQUIRE(bad < 0, TE_EINVAL, "non-positive diagonal entry at level %d row %lld", L.index, (long long)bad);
 }
 
 static void set_cheb(Level &L, const amg_options &o) {
@@ -736,6 +719,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
         bool coarsest = ndof <= o.coarse_max || l == o.max_levels - 1;
         if (!coarsest) {
             L.lam = lanczos_estimate(L, o.lanczos_steps, 0x5EEDull + (uint64_t)l, s);
+            L.dstore.release();
             set_cheb(L, o);
             note("eigenvalue estimate", l, L.n, 0);
             const double theta = o.theta0 * std::ldexp(1.0, -l);
@@ -838,6 +822,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
         TE_REQUIRE(ndof <= 12000, TE_EINVAL, "coarsest level has %lld DOF, too many for the dense factor",
                    (long long)ndof);
         dev_to_host(*cur, L.Ah, s);
+        L.dstore.release();
         break;
     }
     owned.release();

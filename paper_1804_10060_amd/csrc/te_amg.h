@@ -22,7 +22,7 @@ struct Level {
     std::vector<int32_t> agg;      // aggregate of each node (natural), -1 isolated
     std::vector<int32_t> perm_h;   // storage position -> natural index
     std::vector<int32_t> iperm_h;  // natural index -> storage position
-    std::vector<double> dstore;    // point diagonal in storage order
+    DBuf<double> dstore;           // point diagonal in storage order (setup only)
     Sell A, P, R;                  // device operators, storage numbering
     Sell A32;                      // float32 operator in full storage when A keeps only its upper blocks
     DBuf<int32_t> perm;

@@ -106,6 +106,14 @@ bool dev_tentative(const std::vector<int64_t> &off, const std::vector<int32_t> &
 // its diagonal block, or -1.
 int64_t dev_check_pattern(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st);
 
+// Point diagonal in the storage order of a level: d[i*bs+p] = dnat[perm[i]*bs+p]
+// and its reciprocals in float64 and (if dinv32) float32.  Returns the first
+// natural block row with a diagonal entry that is not positive, or -1.
+int64_t dev_diag_store(const double *dnat, const int32_t *perm, int64_t n, int bs, double *d, double *dinv,
+                       float *dinv32, hipStream_t st);
+// y = 1 / sqrt(x), n entries.
+void dev_rsqrt(const double *x, double *y, int64_t n, hipStream_t st);
+
 // Order-independent 64-bit hash of a block pattern (row pointers and columns).
 uint64_t dev_pattern_hash(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st);
 

@@ -1316,6 +1316,44 @@ __global__ void k_check_pattern(const int64_t *__restrict__ ptr, const int32_t *
 }
 }  // namespace
 
+namespace {
+__global__ void k_diag_store(const double *__restrict__ dnat, const int32_t *__restrict__ perm, int64_t n, int bs,
+                             double *__restrict__ d, double *__restrict__ dinv, float *__restrict__ dinv32,
+                             unsigned long long *__restrict__ bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = perm[i];
+        for (int p = 0; p < bs; ++p) {
+            const double v = dnat[o * bs + p];
+            if (!(v > 0)) atomicMin(bad, (unsigned long long)o);
+            d[i * bs + p] = v;
+            dinv[i * bs + p] = 1.0 / v;
+            if (dinv32) dinv32[i * bs + p] = (float)(1.0 / v);
+        }
+    }
+}
+__global__ void k_rsqrt(const double *__restrict__ x, double *__restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = 1.0 / sqrt(x[i]);
+}
+}  // namespace
+
+int64_t dev_diag_store(const double *dnat, const int32_t *perm, int64_t n, int bs, double *d, double *dinv,
+                       float *dinv32, hipStream_t st) {
+    DBuf<unsigned long long> b(1);
+    TE_CHECK_HIP(hipMemsetAsync(b.p, 0xFF, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_diag_store, dim3(grid_for(n)), dim3(256), 0, st, dnat, perm, n, bs, d, dinv, dinv32, b.p);
+    TE_CHECK_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    TE_CHECK_HIP(hipMemcpyAsync(&h, b.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    TE_CHECK_HIP(hipStreamSynchronize(st));
+    return h == ~0ull ? -1 : (int64_t)h;
+}
+
+void dev_rsqrt(const double *x, double *y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_rsqrt, dim3(grid_for(n)), dim3(256), 0, st, x, y, n);
+    TE_CHECK_HIP(hipGetLastError());
+}
+
 int64_t dev_check_pattern(const int64_t *ptr, const int32_t *col, int64_t n, hipStream_t st) {
     DBuf<unsigned long long> d(1);
     TE_CHECK_HIP(hipMemsetAsync(d.p, 0xFF, sizeof(unsigned long long), st));
