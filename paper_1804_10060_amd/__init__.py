@@ -207,7 +207,7 @@ class AMG:
         h, lib = getattr(self, "_h", None), getattr(self, "_cd", None)
         if h is not None and h.value and lib is not None:
             lib.amg_destroy(h)
-            self._h = C.c_void_p(0)
+            h.value = None  # in place: module globals may be gone at interpreter exit
 
     def close(self):
         self.__del__()
@@ -364,7 +364,7 @@ class MPNN:
         h, lib = getattr(self, "_h", None), getattr(self, "_cd", None)
         if h is not None and h.value and lib is not None:
             lib.mpnn_destroy(h)
-            self._h = C.c_void_p(0)
+            h.value = None  # in place: module globals may be gone at interpreter exit
 
     def features(self, T, T_ref, mask, f=None):
         torch = _torch()
