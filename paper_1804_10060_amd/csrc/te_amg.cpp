@@ -549,7 +549,7 @@ static void finish_level(Level &L, const DBsr &D, const amg_options &o, DBuf<dou
     L.iperm_h.assign(L.n, 0);
     for (int64_t i = 0; i < L.n; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
     dev_pack(L.A, D, L.Ah.ptr, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.bs),
-             (o.coarse_sym && L.bs == 6) ? &L.Ah.col : nullptr);
+             o.coarse_sym && L.bs == 6);
     if (L.A.sym() && o.build_fp32) {
         // the float32 V-cycle keeps full storage: its halved value stream does
         // not pay for the gathered mirror blocks

@@ -58,12 +58,12 @@ void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s);
 //   col_map[c]   = column index stored for column c of M
 //   out_map      = if non-null, position i writes output row (*out_map)[row_order[i]];
 //                  otherwise position i writes output row i
-//   sym_cols     = if non-null (the host columns of M), a square M in the
-//                  one-wave-per-row format keeps only its blocks on and above
-//                  the diagonal when its pattern is symmetric
+//   sym          = a square M in the one-wave-per-row format keeps only its
+//                  blocks on and above the diagonal when its pattern is
+//                  symmetric (columns ascending within each row)
 void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &row_order,
               const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32, hipStream_t s,
-              int format, const std::vector<int32_t> *sym_cols = nullptr);
+              int format, bool sym = false);
 
 // inv = M^-1 for a symmetric positive definite n x n matrix M (host,
 // row-major), computed on the device by n symmetric sweeps; TE_ECHOL if a

@@ -753,70 +753,126 @@ void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s) {
 // row_order[r], storage column cs = col_map[c]): blocks with cs >= r stay,
 // each block with cs < r becomes a reference to its mirror.  Returns false
 // (and leaves S alone) when the pattern is not symmetric.
-static bool pack_rows_sym(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &hcol,
+// ---- upper-triangle storage of a symmetric block operator --------------------
+// Storage row r holds natural row o = order[r]; its entry (o, j) is an upper
+// entry when the storage column map[j] is >= r, otherwise a lower one, which
+// the products read transposed from its mirror (j, o).  One thread per row;
+// an entry whose column is out of range is skipped by both fill passes (the
+// row then writes fewer entries than counted) and flags the pattern as bad.
+__global__ void k_sym_count(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                            const int32_t *__restrict__ order, const int32_t *__restrict__ map,
+                            int32_t *__restrict__ ucnt, int32_t *__restrict__ lcnt, int32_t *__restrict__ bad) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = order[r];
+        int32_t u = 0;
+        for (int64_t k = ptr[o]; k < ptr[o + 1]; ++k) {
+            const int32_t j = col[k];
+            if (j < 0 || j >= n) {
+                *bad = 1;
+                continue;
+            }
+            u += map[j] >= r ? 1 : 0;
+        }
+        ucnt[r] = u;
+        lcnt[r] = (int32_t)(ptr[o + 1] - ptr[o]) - u;
+    }
+}
+
+// upper entries: storage column, source entry, and each source entry's
+// position in the upper list (upos stays -1 for the lower ones)
+__global__ void k_sym_upper(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                            const int32_t *__restrict__ order, const int32_t *__restrict__ map,
+                            const int64_t *__restrict__ rptr, int32_t *__restrict__ ucol, int64_t *__restrict__ usrc,
+                            int32_t *__restrict__ upos) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = order[r];
+        int64_t u = rptr[r];
+        for (int64_t k = ptr[o]; k < ptr[o + 1]; ++k) {
+            const int32_t j = col[k];
+            if (j < 0 || j >= n) continue;
+            const int32_t cs = map[j];
+            if (cs >= r) {
+                upos[k] = (int32_t)u;
+                usrc[u] = k;
+                ucol[u] = cs;
+                ++u;
+            }
+        }
+    }
+}
+
+// lower entries: storage column and the upper-list position of the mirror
+// block, found by bisection in the mirror's row (columns ascending)
+__global__ void k_sym_lower(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                            const int32_t *__restrict__ order, const int32_t *__restrict__ map,
+                            const int64_t *__restrict__ lptr, const int32_t *__restrict__ upos,
+                            int32_t *__restrict__ lcol, int32_t *__restrict__ lidx, int32_t *__restrict__ bad) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t o = order[r];
+        int64_t l = lptr[r];
+        for (int64_t k = ptr[o]; k < ptr[o + 1]; ++k) {
+            const int32_t j = col[k];
+            if (j < 0 || j >= n) continue;
+            const int32_t cs = map[j];
+            if (cs >= r) continue;
+            int64_t lo = ptr[j], hi = ptr[j + 1];
+            const int64_t end = hi;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < o) lo = mid + 1;
+                else hi = mid;
+            }
+            int32_t up = (lo < end && col[lo] == o) ? upos[lo] : -1;
+            if (up < 0) {
+                *bad = 1;
+                up = 0;
+            }
+            lcol[l] = cs;
+            lidx[l] = up;
+            ++l;
+        }
+    }
+}
+
+// Upper-triangle packing on the device; false (nothing kept) when M is not
+// square in one numbering, a mirror block is missing (an unsymmetric pattern,
+// or columns not ascending within a row) or the upper part has 2^31 blocks.
+static bool pack_rows_sym(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr,
                           const std::vector<int32_t> &row_order, const std::vector<int32_t> &col_map, bool fp32,
                           hipStream_t s) {
     const int64_t n = M.nr;
-    if (M.nr != M.nc || M.br != M.bc || (int64_t)hcol.size() != M.nnzb) return false;
-    for (int64_t r = 0; r < n; ++r)
-        if (col_map[row_order[r]] != r) return false;  // rows and columns in the same numbering
-    std::vector<int64_t> ucnt(n), lcnt(n);
-    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t r = lo; r < hi; ++r) {
-            const int64_t o = row_order[r];
-            int64_t u = 0;
-            for (int64_t k = hptr[o]; k < hptr[o + 1]; ++k) u += col_map[hcol[k]] >= r ? 1 : 0;
-            ucnt[r] = u;
-            lcnt[r] = hptr[o + 1] - hptr[o] - u;
-        }
-    });
-    std::vector<int64_t> rptr(n + 1, 0), lptr(n + 1, 0);
+    if (M.nr != M.nc || M.br != M.bc || (int64_t)hptr.size() != n + 1 || hptr[n] != M.nnzb ||
+        (int64_t)row_order.size() != n || (int64_t)col_map.size() != n)
+        return false;
     for (int64_t r = 0; r < n; ++r) {
-        rptr[r + 1] = rptr[r] + ucnt[r];
-        lptr[r + 1] = lptr[r] + lcnt[r];
+        const int32_t o = row_order[r];
+        if (o < 0 || o >= n || col_map[o] != r) return false;  // rows and columns in the same numbering
     }
-    const int64_t nup = rptr[n], nlow = lptr[n];
+    DBuf<int32_t> dorder, dmap, ucnt(std::max<int64_t>(n, 1)), lcnt(std::max<int64_t>(n, 1)), bad(1);
+    upload(dorder, row_order, s);
+    upload(dmap, col_map, s);
+    TE_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    const unsigned g = grid_for(n);
+    hipLaunchKernelGGL(k_sym_count, dim3(g), dim3(256), 0, s, n, M.ptr, M.col, dorder.p, dmap.p, ucnt.p, lcnt.p,
+                       bad.p);
+    TE_CHECK_HIP(hipGetLastError());
+    if (read_flag(bad, s) != 0) return false;
+    DBuf<int64_t> rptr, lptr;
+    int64_t nup = 0, nlow = 0;
+    counts_to_ptr(ucnt, n, rptr, nup, s);
+    counts_to_ptr(lcnt, n, lptr, nlow, s);
     if (nup >= INT32_MAX) return false;
-    std::vector<int64_t> upos(M.nnzb, -1), usrc(nup);
-    std::vector<int32_t> ucol(nup), lcol(nlow), lidx(nlow);
-    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t r = lo; r < hi; ++r) {
-            const int64_t o = row_order[r];
-            int64_t u = rptr[r];
-            for (int64_t k = hptr[o]; k < hptr[o + 1]; ++k) {
-                const int32_t cs = col_map[hcol[k]];
-                if (cs >= r) {
-                    upos[k] = u;
-                    usrc[u] = k;
-                    ucol[u] = cs;
-                    ++u;
-                }
-            }
-        }
-    });
-    std::atomic<bool> bad{false};
-    parallel_for(n, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t r = lo; r < hi; ++r) {
-            const int64_t o = row_order[r];
-            int64_t l = lptr[r];
-            for (int64_t k = hptr[o]; k < hptr[o + 1]; ++k) {
-                const int32_t cs = col_map[hcol[k]];
-                if (cs >= r) continue;
-                // the mirror block (row hcol[k], column o) in its sorted row
-                const int64_t j = hcol[k];
-                const auto b0 = hcol.begin() + hptr[j], b1 = hcol.begin() + hptr[j + 1];
-                const auto it = std::lower_bound(b0, b1, (int32_t)o);
-                if (it == b1 || *it != (int32_t)o || upos[it - hcol.begin()] < 0) {
-                    bad = true;
-                    return;
-                }
-                lcol[l] = cs;
-                lidx[l] = (int32_t)upos[it - hcol.begin()];
-                ++l;
-            }
-        }
-    });
-    if (bad) return false;
+    DBuf<int32_t> ucol(std::max<int64_t>(nup, 1)), upos(std::max<int64_t>(M.nnzb, 1));
+    DBuf<int32_t> lcol(std::max<int64_t>(nlow, 1)), lidx(std::max<int64_t>(nlow, 1));
+    DBuf<int64_t> usrc(std::max<int64_t>(nup, 1));
+    TE_CHECK_HIP(hipMemsetAsync(upos.p, 0xFF, (size_t)std::max<int64_t>(M.nnzb, 1) * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_sym_upper, dim3(g), dim3(256), 0, s, n, M.ptr, M.col, dorder.p, dmap.p, rptr.p, ucol.p,
+                       usrc.p, upos.p);
+    TE_CHECK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sym_lower, dim3(g), dim3(256), 0, s, n, M.ptr, M.col, dorder.p, dmap.p, lptr.p, upos.p,
+                       lcol.p, lidx.p, bad.p);
+    TE_CHECK_HIP(hipGetLastError());
+    if (read_flag(bad, s) != 0) return false;
     const int bb = M.br * M.bc;
     S.format = FMT_ROWWAVE;
     S.br = M.br;
@@ -826,21 +882,15 @@ static bool pack_rows_sym(Sell &S, const DBsr &M, const std::vector<int64_t> &hp
     S.nnzb = nup;
     S.nslices = 0;
     S.padded = nup;
-    upload(S.rptr, rptr, s);
-    upload(S.col, ucol, s);
-    upload(S.lptr, lptr, s);
-    upload(S.lcol, lcol, s);
-    upload(S.lidx, lidx, s);
-    if (nlow == 0) {  // keep the symmetric marker valid for an operator without lower blocks
-        S.lcol.alloc(1);
-        S.lidx.alloc(1);
-    }
-    DBuf<int64_t> dsrc;
-    upload(dsrc, usrc, s);
+    S.rptr = std::move(rptr);
+    S.col = std::move(ucol);
+    S.lptr = std::move(lptr);
+    S.lcol = std::move(lcol);  // one entry at least, also without lower blocks
+    S.lidx = std::move(lidx);
     S.val.alloc(std::max<int64_t>(nup * bb, 1));
     if (fp32) S.val32.alloc(std::max<int64_t>(nup * bb, 1));
     else S.val32.release();
-    hipLaunchKernelGGL(k_pack_upper, dim3(grid_for(nup * bb)), dim3(256), 0, s, nup, bb, dsrc.p, M.val, S.val.p,
+    hipLaunchKernelGGL(k_pack_upper, dim3(grid_for(nup * bb)), dim3(256), 0, s, nup, bb, usrc.p, M.val, S.val.p,
                        fp32 ? S.val32.p : nullptr);
     TE_CHECK_HIP(hipGetLastError());
     S.slice_off.release();
@@ -852,12 +902,11 @@ static bool pack_rows_sym(Sell &S, const DBsr &M, const std::vector<int64_t> &hp
 
 void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const std::vector<int32_t> &row_order,
               const std::vector<int32_t> &col_map, const std::vector<int32_t> *out_map, bool fp32, hipStream_t s,
-              int format, const std::vector<int32_t> *sym_cols) {
+              int format, bool sym) {
     S.lptr.release();
     S.lcol.release();
     S.lidx.release();
-    if (sym_cols && format == FMT_ROWWAVE && !out_map &&
-        pack_rows_sym(S, M, hptr, *sym_cols, row_order, col_map, fp32, s))
+    if (sym && format == FMT_ROWWAVE && !out_map && pack_rows_sym(S, M, hptr, row_order, col_map, fp32, s))
         return;
     TE_REQUIRE((int64_t)hptr.size() == M.nr + 1 && (int64_t)row_order.size() == M.nr &&
                    (int64_t)col_map.size() == M.nc && hptr[M.nr] == M.nnzb,
