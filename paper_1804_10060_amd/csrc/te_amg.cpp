@@ -547,7 +547,9 @@ static int fmt_for(int br) { return br >= 6 ? FMT_ROWWAVE : FMT_SELL; }
 static void finish_level(Level &L, const DBsr &D, const amg_options &o, DBuf<double> &dnat, hipStream_t s) {
     L.perm_h = window_sorted_order(L.Ah.ptr, 4096);
     L.iperm_h.assign(L.n, 0);
-    for (int64_t i = 0; i < L.n; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
+    parallel_for(L.n, [&](int64_t lo, int64_t hi, int) {
+        for (int64_t i = lo; i < hi; ++i) L.iperm_h[L.perm_h[i]] = (int32_t)i;
+    });
     dev_pack(L.A, D, L.Ah.ptr, L.perm_h, L.iperm_h, nullptr, o.build_fp32 != 0, s, fmt_for(L.bs),
              o.coarse_sym && L.bs == 6);
     if (L.A.sym() && o.build_fp32) {

@@ -442,11 +442,15 @@ __global__ void k_t_fill(int64_t tn, const int64_t *__restrict__ src, const int3
 
 // ---- packing into the solver layouts ----------------------------------------------------
 // SELL-64: storage position r (slice r/64, lane r%64) holds row order[r]
-__global__ void k_pack_sell(int64_t nr, int bb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+// BB > 0: the block size fixed at compile time, so a block's loads are all
+// issued before its stores; BB = 0 takes it from bb
+template <int BB>
+__global__ void k_pack_sell(int64_t nr, int bb_rt, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
                             const double *__restrict__ val, const int32_t *__restrict__ order,
                             const int32_t *__restrict__ colmap, const int32_t *__restrict__ slice_off,
                             int64_t nslices, int32_t *__restrict__ scol, double *__restrict__ sval,
                             float *__restrict__ sval32) {
+    const int bb = BB > 0 ? BB : bb_rt;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nslices * 64;
          r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t sl = r / 64, l = r % 64;
@@ -459,11 +463,22 @@ __global__ void k_pack_sell(int64_t nr, int bb, const int64_t *__restrict__ ptr,
         for (int64_t k = 0; k < w; ++k) {
             if (k < len) last = colmap[col[s0 + k]];
             scol[(o0 + k) * 64 + l] = last;
-            for (int x = 0; x < bb; ++x) {
-                const double v = k < len ? val[(s0 + k) * bb + x] : 0.0;
-                const int64_t e0 = (o0 + k) * bb * 64;
-                sval[e0 + sell_val_off<sell_vw<double>()>(x, bb, (int)l)] = v;
-                if (sval32) sval32[e0 + sell_val_off<sell_vw<float>()>(x, bb, (int)l)] = (float)v;
+            const int64_t e0 = (o0 + k) * bb * 64;
+            if constexpr (BB > 0) {
+                double v[BB];
+#pragma unroll
+                for (int x = 0; x < BB; ++x) v[x] = k < len ? val[(s0 + k) * BB + x] : 0.0;
+#pragma unroll
+                for (int x = 0; x < BB; ++x) {
+                    sval[e0 + sell_val_off<sell_vw<double>()>(x, BB, (int)l)] = v[x];
+                    if (sval32) sval32[e0 + sell_val_off<sell_vw<float>()>(x, BB, (int)l)] = (float)v[x];
+                }
+            } else {
+                for (int x = 0; x < bb; ++x) {
+                    const double v = k < len ? val[(s0 + k) * bb + x] : 0.0;
+                    sval[e0 + sell_val_off<sell_vw<double>()>(x, bb, (int)l)] = v;
+                    if (sval32) sval32[e0 + sell_val_off<sell_vw<float>()>(x, bb, (int)l)] = (float)v;
+                }
             }
         }
     }
@@ -939,17 +954,23 @@ void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const st
         S.rptr.release();
         S.nslices = (M.nr + SELL_C - 1) / SELL_C;
         std::vector<int32_t> off(S.nslices + 1, 0), rowlen(S.nslices * SELL_C, 0);
-        for (int64_t sl = 0; sl < S.nslices; ++sl) {
-            int64_t w = 0;
-            for (int l = 0; l < SELL_C; ++l) {
-                const int64_t r = sl * SELL_C + l;
-                if (r >= M.nr) break;
-                const int64_t len = hptr[row_order[r] + 1] - hptr[row_order[r]];
-                rowlen[r] = (int32_t)len;
-                w = std::max(w, len);
+        std::vector<int64_t> width(S.nslices);
+        parallel_for(S.nslices, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t sl = lo; sl < hi; ++sl) {
+                int64_t w = 0;
+                for (int l = 0; l < SELL_C; ++l) {
+                    const int64_t r = sl * SELL_C + l;
+                    if (r >= M.nr) break;
+                    const int64_t len = hptr[row_order[r] + 1] - hptr[row_order[r]];
+                    rowlen[r] = (int32_t)len;
+                    w = std::max(w, len);
+                }
+                width[sl] = w;
             }
-            TE_REQUIRE((int64_t)off[sl] + w < INT32_MAX, TE_EINVAL, "matrix too large for the SELL offsets");
-            off[sl + 1] = off[sl] + (int32_t)w;
+        });
+        for (int64_t sl = 0; sl < S.nslices; ++sl) {
+            TE_REQUIRE((int64_t)off[sl] + width[sl] < INT32_MAX, TE_EINVAL, "matrix too large for the SELL offsets");
+            off[sl + 1] = off[sl] + (int32_t)width[sl];
         }
         S.padded = (int64_t)off[S.nslices] * SELL_C;
         upload(S.slice_off, off, s);
@@ -958,14 +979,16 @@ void dev_pack(Sell &S, const DBsr &M, const std::vector<int64_t> &hptr, const st
         S.val.alloc(std::max<int64_t>(S.padded * bb, 1));
         if (fp32) S.val32.alloc(std::max<int64_t>(S.padded * bb, 1));
         else S.val32.release();
-        hipLaunchKernelGGL(k_pack_sell, dim3(grid_for(S.nslices * 64)), dim3(256), 0, s, M.nr, bb, M.ptr, M.col,
-                           M.val, dorder.p, dmap.p, S.slice_off.p, S.nslices, S.col.p, S.val.p,
-                           fp32 ? S.val32.p : nullptr);
+        auto kern = bb == 9 ? k_pack_sell<9> : bb == 18 ? k_pack_sell<18> : k_pack_sell<0>;
+        hipLaunchKernelGGL(kern, dim3(grid_for(S.nslices * 64)), dim3(256), 0, s, M.nr, bb, M.ptr, M.col, M.val,
+                           dorder.p, dmap.p, S.slice_off.p, S.nslices, S.col.p, S.val.p, fp32 ? S.val32.p : nullptr);
     }
     TE_CHECK_HIP(hipGetLastError());
     if (out_map) {
         std::vector<int32_t> rm(format == FMT_ROWWAVE ? M.nr : S.nslices * SELL_C, -1);
-        for (int64_t r = 0; r < M.nr; ++r) rm[r] = (*out_map)[row_order[r]];
+        parallel_for(M.nr, [&](int64_t lo, int64_t hi, int) {
+            for (int64_t r = lo; r < hi; ++r) rm[r] = (*out_map)[row_order[r]];
+        });
         upload(S.rowmap, rm, s);
     } else {
         S.rowmap.release();
