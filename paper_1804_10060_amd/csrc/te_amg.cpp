@@ -118,8 +118,8 @@ static int n_threads() {
     unsigned h = std::thread::hardware_concurrency();
     return h ? (int)std::min(h, 64u) : 4;
 }
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &fn) {
-    int nt = (int)std::min<int64_t>(n_threads(), std::max<int64_t>(1, n / 256));
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &fn, int64_t grain) {
+    int nt = (int)std::min<int64_t>(n_threads(), std::max<int64_t>(1, n / std::max<int64_t>(grain, 1)));
     if (nt <= 1) {
         fn(0, n, 0);
         return;
@@ -419,15 +419,19 @@ std::vector<int32_t> window_sorted_order(const std::vector<int64_t> &ptr, int64_
     std::vector<int32_t> ord(n);
     for (int64_t i = 0; i < n; ++i) ord[i] = (int32_t)i;
     const int64_t nw = (n + window - 1) / window;
-    parallel_for(nw, [&](int64_t lo, int64_t hi, int) {
-        for (int64_t wi = lo; wi < hi; ++wi) {
-            const int64_t w0 = wi * window, w1 = std::min(n, w0 + window);
-            std::sort(ord.begin() + w0, ord.begin() + w1, [&](int32_t a, int32_t b) {
-                const int64_t la = ptr[a + 1] - ptr[a], lb = ptr[b + 1] - ptr[b];
-                return la != lb ? la > lb : a < b;
-            });
-        }
-    });
+    // one window is a few thousand rows of work: every thread takes windows
+    parallel_for(
+        nw,
+        [&](int64_t lo, int64_t hi, int) {
+            for (int64_t wi = lo; wi < hi; ++wi) {
+                const int64_t w0 = wi * window, w1 = std::min(n, w0 + window);
+                std::sort(ord.begin() + w0, ord.begin() + w1, [&](int32_t a, int32_t b) {
+                    const int64_t la = ptr[a + 1] - ptr[a], lb = ptr[b + 1] - ptr[b];
+                    return la != lb ? la > lb : a < b;
+                });
+            }
+        },
+        1);
     return ord;
 }
 
@@ -683,12 +687,8 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     // tentative prolongator has to take the host path
     DBuf<double> dB;
     {
-        std::vector<double> X;
-        download(X, coords, (size_t)n * 3, s);
-        double c[3] = {0, 0, 0};
-        for (int64_t i = 0; i < n; ++i)
-            for (int q = 0; q < 3; ++q) c[q] += X[i * 3 + q];
-        for (int q = 0; q < 3; ++q) c[q] /= (double)n;
+        double c[3];
+        dev_centroid(coords, n, c, s);
         dev_rigid_body_modes(coords, dir_mask, n, c, dB, s);
     }
     note("near-nullspace", 0, n, 0);

@@ -87,6 +87,10 @@ int64_t dev_aggregate_mis2(const DBsr &A, const DBuf<double> &s, double theta, u
 // off-diagonal blocks unchanged; strong = s_ij or s_ji >= theta (i != j).
 void dev_filtered(const DBsr &A, const DBuf<double> &s, double theta, DBsr &F, hipStream_t st);
 
+// c = mean of the n node coordinates (device [n][3]); partial sums per
+// workgroup on the device, added on the host in workgroup order
+void dev_centroid(const double *coords, int64_t n, double c[3], hipStream_t st);
+
 // Level-0 near-nullspace on the device: the six rigid-body modes about the
 // point c, B [n][3][6] (translations x, y, z, then rotations about z, x, y),
 // rows of constrained DOFs (mask, may be NULL) zero.

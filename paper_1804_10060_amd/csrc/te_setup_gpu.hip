@@ -1343,6 +1343,39 @@ void dev_filtered(const DBsr &A, const DBuf<double> &s, double theta, DBsr &F, h
     TE_CHECK_HIP(hipStreamSynchronize(st));
 }
 
+namespace {
+// per workgroup: the sums of the three coordinates over a grid-stride share
+// of the nodes
+__global__ void __launch_bounds__(256) k_coord_sum(const double *__restrict__ X, int64_t n, double *__restrict__ part) {
+    __shared__ double sh[3][256];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int q = 0; q < 3; ++q) a[q] += X[i * 3 + q];
+    for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = a[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[blockIdx.x * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+}  // namespace
+
+void dev_centroid(const double *coords, int64_t n, double c[3], hipStream_t st) {
+    c[0] = c[1] = c[2] = 0.0;
+    if (n <= 0) return;
+    const int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    DBuf<double> part((size_t)nb * 3);
+    hipLaunchKernelGGL(k_coord_sum, dim3(nb), dim3(256), 0, st, coords, n, part.p);
+    TE_CHECK_HIP(hipGetLastError());
+    std::vector<double> h;
+    download(h, part.p, (size_t)nb * 3, st);
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < 3; ++q) c[q] += h[(size_t)b * 3 + q];
+    for (int q = 0; q < 3; ++q) c[q] /= (double)n;
+}
+
 void dev_rigid_body_modes(const double *coords, const uint8_t *mask, int64_t n, const double c[3], DBuf<double> &B,
                           hipStream_t st) {
     B.alloc(std::max<int64_t>(n * 18, 1));
