@@ -43,7 +43,9 @@ inline Sell &level_op(Level &L) {
     else return L.A;
 }
 
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &fn);
+// fn(lo, hi, thread) over [0, n) on the host threads, one thread per `grain`
+// items at most
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t, int)> &fn, int64_t grain = 256);
 int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt,
                const int32_t *const *agg_given, int n_given, amg_handle **out, hipStream_t s);
 
