@@ -3,8 +3,9 @@
  * AMG library.
  *
  * The library solves the linear thermoelastic problem of the paper's Sec. 3
- * (eqs. elasticity_bvp, u-dbc and the weak form wf_elastic, without boundary
- * pressure):  -div(C:(eps(u) - alpha (T - T_ref) I)) = f  on a tetrahedral
+ * (eqs. elasticity_bvp, u-dbc and the weak form wf_elastic, the boundary
+ * pressure term included in fe_assemble_thermoelastic_materials):
+ *   -div(C:(eps(u) - alpha (T - T_ref) I)) = f  on a tetrahedral
  * mesh with Lagrange P1 or P2 elements (Sec. 3.1), by conjugate gradients
  * preconditioned with smoothed-aggregation AMG using the rigid-body modes as
  * near-nullspace and a Chebyshev smoother (Sec. 2.1.2, 2.1.3 and 5.1).
@@ -107,7 +108,7 @@ int fe_assemble_thermoelastic(const te_mesh *mesh, const te_material *mat, const
                               te_bsr *A, double *b, hipStream_t stream);
 
 /* Temperature-dependent isotropic materials (Sec. 3: C and alpha_L depend on
- * T; Sec. 4.1 shows such tables for several materials).  Material m gives E,
+ * T; Sec. 4.2 shows such tables for several materials).  Material m gives E,
  * nu and alpha_L at n_points temperatures T[m][k] (strictly ascending); values
  * between samples are linear in T, beyond the first and last sample constant.
  * All arrays are host arrays [n_materials][n_points], read during the call. */
@@ -360,7 +361,7 @@ int amg_energy_scale(amg_handle *h, const double *b, double *u0, double *gamma, 
 int te_autotune(amg_handle *h, const char *cache_path, int32_t use_cache, char *report, int64_t report_len,
                 hipStream_t stream);
 
-/* ---- transient runs (Sec. 3.4, Sec. 5.3) -------------------------------- */
+/* ---- transient runs (Sec. 3.3, Sec. 5.3) -------------------------------- */
 
 /* Preconditioner reuse across time steps (Sec. 5.3: the elastic
  * preconditioner of the first step serves the later ones).  From this call

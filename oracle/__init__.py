@@ -22,6 +22,6 @@ paper and the textbook methods it names, in float64:
 * ``mpnn``    -- message-passing network forward/backward for the learned
                  initial guess.
 * ``transient`` -- the time-step control of eq. dt_spec around the elastic
-                 solve of a transient run (Sec. 3.4, Sec. 5.3).
+                 solve of a transient run (Sec. 3.3, Sec. 5.3).
 * ``rng``     -- splitmix64 counter generator (Steele, Lea & Flood 2014).
 """

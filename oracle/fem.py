@@ -254,7 +254,7 @@ def assemble_rows(coords, cells, degree, E, nu, alpha, T_ref, T, rows, f=None):
 # ---------------------------------------------------------------------------
 # Sec. 3 lets the stiffness tensor C and alpha_L depend on temperature and
 # the weak form wf_elastic carries the boundary term - int p_bc n . v ds on
-# Gamma_N (traction sigma n = p_bc n); Sec. 4.1 shows normalised
+# Gamma_N (traction sigma n = p_bc n); Sec. 4.2 shows normalised
 # temperature tables for several materials.  Readings: each material gives
 # E, nu and alpha_L as piecewise-linear tables in T, constant beyond their
 # ends; a cell takes the values of its material at the mean of T_h over the

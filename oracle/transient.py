@@ -1,7 +1,7 @@
 """Oracle: the time-step control around the elastic solve of a transient run
 (test infrastructure only; see the package docstring).
 
-What the paper fixes (Sec. 3.4, eq. dt_spec, and Sec. 5.3):
+What the paper fixes (Sec. 3.3, eq. dt_spec, and Sec. 5.3):
 
 * the next step is the current one scaled so that the largest temperature
   change over it would be the target eps * dT_max:

@@ -671,7 +671,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
     // rule or a rank-deficient merge (host_cols below)
     {
         const int64_t i = dev_check_pattern(A->row_ptr, A->col_idx, n, s);
-        TE_REQUIRE(i < 0, TE_EINVAL, "row %lld has a column index out of range or no diagonal block", (long long)i);
+        TE_REQUIRE(i < 0, TE_EINVAL, "row %lld has a column index out of range or out of ascending order, or no diagonal block", (long long)i);
     }
     note("columns checked", 0, n, A->nnzb);
     h->pattern_hash = dev_pattern_hash(A->row_ptr, A->col_idx, n, s);

@@ -2,8 +2,10 @@
 // strength of connection, the smoothed prolongator P = (I - w D^-1 A) P_tent,
 // the product A P, the transpose R = P^T and the Galerkin product R (A P),
 // all on block compressed rows, and the packing of an operator into the
-// solver layouts.  The greedy aggregation and the per-aggregate QR stay on
-// the host: both are sequential by definition.
+// solver layouts, the MIS-2 aggregation and the per-aggregate QR of the
+// tentative prolongator.  Only the greedy aggregation (an option, sequential
+// by definition) and the merge of a rank-deficient aggregate into a
+// neighbour stay on the host.
 //
 // Sparse products take two passes.  Symbolic: one wave per output row puts
 // the candidate columns into an open-addressing hash set in LDS, counts them,
@@ -1410,10 +1412,12 @@ namespace {
 __global__ void k_check_pattern(const int64_t *__restrict__ ptr, const int32_t *__restrict__ col, int64_t n,
                                 unsigned long long *__restrict__ bad) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        // columns in range, strictly ascending (the strength symmetrisation
+        // binary-searches mirror rows), and a diagonal block present
         bool ok = true, diag = false;
         for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
             const int32_t c = col[k];
-            ok = ok && c >= 0 && c < n;
+            ok = ok && c >= 0 && c < n && (k == ptr[i] || c > col[k - 1]);
             diag = diag || c == i;
         }
         if (!ok || !diag) atomicMin(bad, (unsigned long long)i);

@@ -1,4 +1,4 @@
-// Time-step control of a transient run (Sec. 3.4, eq. dt_spec): the largest
+// Time-step control of a transient run (Sec. 3.3, eq. dt_spec): the largest
 // temperature change over a step, reduced on the device, and the rule that
 // turns it into the next step or a rejection.
 #include <hip/hip_runtime.h>

@@ -1,5 +1,5 @@
 """Elastic solves along a temperature history: the loop around the solve in
-a transient run (Sec. 3.4 and Sec. 5.3).
+a transient run (Sec. 3.3 and Sec. 5.3).
 
 Each accepted time step assembles the system at the new temperature (with
 temperature-dependent materials the matrix changes), solves it starting from

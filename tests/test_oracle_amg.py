@@ -81,6 +81,55 @@ def test_aggregation_brute_force_random_graphs():
         assert np.array_equal(agg, ref)
 
 
+def test_phase2_tie_rule_hand_worked():
+    """Phase 2's choice among aggregated strong neighbours (the reading of the
+    aggregation step of Sec. 5.1: strongest neighbour wins; strengths within
+    a relative 1e-9 are equal and the smaller aggregate id wins), worked by
+    hand on one free node per case.  Catches a larger-id winner, a missing or
+    an oversized tolerance and an unaggregated neighbour being taken."""
+    s = 0.5
+    cases = [
+        # (neighbour aggregate ids, strengths, expected aggregate)
+        ([5, 3], [s, s], 3),                                  # exact tie: smaller id
+        ([3, 5], [s, s], 3),                                  # same, other visiting order
+        ([4, 2], [s, s * (1.0 - 5e-10)], 2),                  # within 1e-9: a tie
+        ([2, 4], [s * (1.0 - 5e-10), s], 2),
+        ([4, 2], [s, s * (1.0 - 1e-8)], 4),                   # 1e-8 apart: strongest wins
+        ([2, 4], [s * (1.0 - 1e-8), s], 4),
+        ([7, -1, 6], [0.3, 0.9, 0.2], 7),                     # unaggregated neighbour ignored
+        ([1, 0, 2], [0.2, 0.2 * (1 + 2e-10), 0.25], 2),
+    ]
+    nodes = []
+    agg0 = []
+    nbrs = []
+    nid = 0
+    for ids, sv, _ in cases:
+        free = nid
+        agg0.append(-1)
+        nbrs_free = []
+        nid += 1
+        for a in ids:
+            agg0.append(a)        # a neighbour node carrying aggregate a (or -1)
+            nbrs_free.append(nid)
+            nid += 1
+        nodes.append((free, nbrs_free, sv))
+    n = nid
+    lists = [(np.zeros(0, np.int64), np.zeros(0)) for _ in range(n)]
+    for free, nb, sv in nodes:
+        lists[free] = (np.array(nb, np.int64), np.array(sv, float))
+    # an unaggregated neighbour (-1) is itself a free node of phase 2: give it
+    # one aggregated strong neighbour (the first of its case)
+    agg0 = np.array(agg0, np.int64)
+    for free, nb, sv in nodes:
+        for j in nb:
+            if agg0[j] < 0:
+                lists[j] = (np.array([nb[0]], np.int64), np.array([0.9]))
+    out = amg._attach_rest(agg0, lists)
+    for (free, _, _), (_, _, want) in zip(nodes, cases):
+        assert out[free] == want, (free, out[free], want)
+
+
+
 @pytest.mark.parametrize("deg,n", [(1, 6), (2, 3)])
 def test_aggregation_invariants(deg, n):
     prob, A, b, B = _cube_system(n, deg)
