@@ -388,6 +388,20 @@ int amg_set_operator(amg_handle *h, const te_bsr *A, hipStream_t stream);
 int te_timestep(const double *T_new, const double *T_old, int64_t n, double dt, double dT_max, double eps,
                 double *dt_next, int32_t *accept, double *max_change, hipStream_t stream);
 
+/* te_timestep for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, checks, results and errors, but the partial maxima
+ * live in a file-scope device array of the library (1088 doubles, 8.5 KB per
+ * GPU, held until the process ends) instead of a buffer allocated per call,
+ * and the call makes no device or host allocation.  Any n >= 0 fits: the
+ * reduction folds n entries into at most 1024 partials.  Every call on one
+ * GPU shares that GPU's array, so calls that overlap on one GPU (several
+ * threads or streams at once) race; the array is fully rewritten by each
+ * call before it is read.  The first call on a device looks up the array's
+ * device address on the current device. */
+int te_timestep_noalloc(const double *T_new, const double *T_old, int64_t n, double dt, double dT_max,
+                        double eps, double *dt_next, int32_t *accept, double *max_change, hipStream_t stream);
+
 /* Releases everything the handle owns.  NULL is accepted. */
 int amg_destroy(amg_handle *h);
 

@@ -308,15 +308,17 @@ class AMG:
                               list(rep.kernel_ms), list(rep.kernel_launches))
 
 
-def timestep(T_new, T_old, dt, dT_max=10.0, eps=0.9):
+def timestep(T_new, T_old, dt, dT_max=10.0, eps=0.9, noalloc=False):
     """te_timestep (eq. dt_spec): returns (accept, dt_next, max_change) for a
-    step of length dt from T_old to T_new (float64 device tensors, same size)."""
+    step of length dt from T_old to T_new (float64 device tensors, same size).
+    noalloc=True calls te_timestep_noalloc (library scratch, no allocation)."""
     torch = _torch()
     _dev(T_new, torch.float64, None, "T_new")
     _dev(T_old, torch.float64, tuple(T_new.shape), "T_old")
     dn, acc, mc = C.c_double(0.0), C.c_int32(0), C.c_double(0.0)
-    check(load().te_timestep(_ptr(T_new), _ptr(T_old), T_new.numel(), float(dt), float(dT_max), float(eps),
-                             C.byref(dn), C.byref(acc), C.byref(mc), _stream()))
+    fn = load().te_timestep_noalloc if noalloc else load().te_timestep
+    check(fn(_ptr(T_new), _ptr(T_old), T_new.numel(), float(dt), float(dT_max), float(eps), C.byref(dn),
+             C.byref(acc), C.byref(mc), _stream()))
     return bool(acc.value), dn.value, mc.value
 
 

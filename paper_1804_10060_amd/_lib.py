@@ -23,7 +23,7 @@ EXPORTS = ["te_version", "te_last_error", "fe_assemble_pattern", "fe_assemble_th
            "fe_assemble_thermoelastic_materials",
            "amg_options_default", "amg_setup", "amg_setup_with_aggregates", "amg_get_info", "amg_get_aggregates",
            "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_pcg_solve_multi", "amg_energy_scale", "te_autotune", "amg_destroy",
-           "amg_set_operator", "te_timestep",
+           "amg_set_operator", "te_timestep", "te_timestep_noalloc",
            "mpnn_param_count", "mpnn_create", "mpnn_destroy", "mpnn_features", "mpnn_forward", "mpnn_backward", "mpnn_backward_from", "mpnn_energy_grad",
            "mpnn_adam_step", "mpnn_guess"]
 
@@ -115,6 +115,8 @@ def load():
         "amg_set_operator": ([vp, C.POINTER(TeBsr), vp], C.c_int),
         "te_timestep": ([vp, vp, i64, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
                          C.POINTER(C.c_int32), C.POINTER(C.c_double), vp], C.c_int),
+        "te_timestep_noalloc": ([vp, vp, i64, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_double), vp], C.c_int),
         "mpnn_param_count": ([], i64),
         "mpnn_create": ([i64, vp, vp, vp, C.POINTER(vp), vp], C.c_int),
         "mpnn_destroy": ([vp], C.c_int),
