@@ -3,20 +3,23 @@
 // solve's [rows][m] arrays (right-hand sides fastest, m <= 64); small matrices
 // are 64 x 64 row-major with zero padding.
 //
-// All three are tall-skinny dense contractions and run on the float64 matrix
-// cores (v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16); lane i holds
-// A[i%16][i/16] and B[i/16][i%16], and D[i/16 + 4q][i%16] in register q).
+// The three kernels are tall-skinny dense contractions done with plain
+// float64 vector FMAs (no matrix cores), register-tiled like a GEMM:
 //
 //   k_gram      C_t = L_t^T R_t for up to three pairs of block vectors in one
-//               pass over the rows.  A = 16 columns of L over 4 rows and
-//               B = 16 columns of R over the same 4 rows are both plain
-//               4-row x 16-column loads; two waves per pair each hold 8 of the
-//               16 output tiles.  One partial per workgroup, summed in
-//               workgroup order (k_gram_sum1/2: deterministic).
-//   k_block_xr  X += P alpha, R -= Q alpha; one wave per 16 rows, alpha in
-//               LDS, plus per-column partial sums of R^2.
-//   k_block_p   P <- Z T1 + P T2 in place (a wave reads all of its 16 rows
-//               before it writes them); T1, T2 in LDS.
+//               pass over the rows, one wave per pair.  The workgroup stages
+//               32 block rows of each distinct block vector in LDS (coalesced
+//               loads); lane (a, b) accumulates the 8 x 8 tile
+//               C[8a..8a+7][8b..8b+7] from them (64 FMAs per 16 LDS values).
+//               One partial per workgroup, summed in workgroup order
+//               (k_gram_sum1/2: deterministic).
+//   k_block_xr  X += P alpha, R -= Q alpha, plus per-column partial sums of
+//               R^2.  A wave computes 32 block rows x 64 columns: lane (a, b)
+//               the 4 x 8 tile of rows 4a.. and columns 8b..; the row entries
+//               come from global memory four at a time (the next four loaded
+//               while the current ones are used), alpha from LDS.
+//   k_block_p   P <- Z T1 + P T2 in place, organised as k_block_xr (a wave
+//               reads its 32 rows of Z and P whole before it writes them).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,17 +29,13 @@
 namespace te {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
 constexpr int GM = 64;      // largest block size
-constexpr int GBLKS = 512;  // workgroups of the Gram pass
+constexpr int GBLKS = 1024; // workgroups of the Gram pass
 constexpr int GSPLIT = 16;  // first-stage slices of the Gram partial sum
-constexpr int GU = 4;       // 4-row steps per load batch in the Gram pass
-constexpr int UBLK = 512;   // threads of the update kernels (8 waves)
-
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+constexpr int GT = 32;      // block rows per LDS stage of the Gram pass
+constexpr int UBLK = 256;   // threads of the update kernels (4 waves)
+constexpr int TRW = 32;     // block rows per wave in the updates
+constexpr int KB = 4;       // row entries per load batch in the updates
 
 struct GramArgs {
     const double *mat[3];   // distinct block vectors [rows][m]
@@ -48,70 +47,51 @@ struct GramArgs {
     double *partials;       // [GBLKS][npair][GM][GM]
 };
 
-// blockDim = 128 * npair: wave w takes pair w / 2 and output row tiles
-// 2 (w % 2), 2 (w % 2) + 1 against all four column tiles.
-__global__ void __launch_bounds__(384) k_gram(GramArgs g) {
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-    const int p = w >> 1, jt0 = (w & 1) * 2;
-    const int kr = lane >> 4, kc = lane & 15;
-    const int m = g.m;
-    const double *__restrict__ L = g.mat[g.li[p]];
-    const double *__restrict__ R = g.mat[g.ri[p]];
-    const bool tj[2] = {jt0 * 16 < m, (jt0 + 1) * 16 < m};
-    d4 acc[2][4];
+// blockDim = 64 * npair: wave p computes pair p over the workgroup's rows.
+__global__ void __launch_bounds__(192) k_gram(GramArgs g) {
+    __shared__ double tile[3][GT][GM];
+    const int lane = threadIdx.x & (WAVE - 1), p = threadIdx.x / WAVE;
+    const int ta = (lane >> 3) * 8, tb = (lane & 7) * 8;
+    const int m = g.m, nmat = g.nmat;
+    const int lm = g.li[p], rm = g.ri[p];
+    double acc[8][8];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int q = 0; q < 8; ++q)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[t][c] = d4{0.0, 0.0, 0.0, 0.0};
-    const int64_t step = 4 * GU;
-    const int64_t chunk = ((g.rows + gridDim.x - 1) / gridDim.x + step - 1) / step * step;
+        for (int t = 0; t < 8; ++t) acc[q][t] = 0.0;
+    const int64_t chunk = (g.rows + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(g.rows, lo + chunk);
-    // fragments of one batch of GU 4-row steps; the next batch is loaded
-    // while the current one goes through the matrix cores
-    double a[GU][2], b[GU][4];
-    auto load = [&](int64_t r0) {
-#pragma unroll
-        for (int u = 0; u < GU; ++u) {
-            const int64_t row = r0 + 4 * u + kr;
-            const bool ok = row < hi;
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int col = (jt0 + t) * 16 + kc;
-                a[u][t] = (ok && col < m) ? L[row * m + col] : 0.0;
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int col = c * 16 + kc;
-                b[u][c] = (ok && col < m) ? R[row * m + col] : 0.0;
+    for (int64_t r0 = lo; r0 < hi; r0 += GT) {
+        const int nr = (int)min<int64_t>(GT, hi - r0);
+        // stage rows r0 .. r0+nr-1 of every distinct block vector (zero beyond
+        // m and nr); the rows are contiguous in memory
+        for (int t = 0; t < nmat; ++t) {
+            const double *__restrict__ src = g.mat[t] + r0 * m;
+            for (int e = threadIdx.x; e < GT * GM; e += blockDim.x) {
+                const int rr = e / GM, c = e % GM;
+                tile[t][rr][c] = (rr < nr && c < m) ? src[rr * m + c] : 0.0;
             }
         }
-    };
-    if (lo < hi) load(lo);
-    for (int64_t r0 = lo; r0 < hi; r0 += step) {
-        double ca[GU][2], cb[GU][4];
+        __syncthreads();
+        for (int rr = 0; rr < nr; ++rr) {
+            double l[8], r[8];
 #pragma unroll
-        for (int u = 0; u < GU; ++u) {
+            for (int q = 0; q < 8; ++q) {
+                l[q] = tile[lm][rr][ta + q];
+                r[q] = tile[rm][rr][tb + q];
+            }
 #pragma unroll
-            for (int t = 0; t < 2; ++t) ca[u][t] = a[u][t];
+            for (int q = 0; q < 8; ++q)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cb[u][c] = b[u][c];
+                for (int t = 0; t < 8; ++t) acc[q][t] = fma(l[q], r[t], acc[q][t]);
         }
-        if (r0 + step < hi) load(r0 + step);
-#pragma unroll
-        for (int u = 0; u < GU; ++u)
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (tj[t] && c * 16 < m) acc[t][c] = mfma(ca[u][t], cb[u][c], acc[t][c]);
+        __syncthreads();
     }
     double *out = g.partials + ((int64_t)blockIdx.x * g.npair + p) * GM * GM;
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int q = 0; q < 8; ++q)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) out[((jt0 + t) * 16 + kr + 4 * q) * GM + c * 16 + kc] = acc[t][c][q];
+        for (int t = 0; t < 8; ++t) out[(ta + q) * GM + tb + t] = acc[q][t];
 }
 
 // Partial sums over the GBLKS workgroups in a fixed order: slice y of the
@@ -136,79 +116,99 @@ __global__ void __launch_bounds__(256) k_gram_sum2(const double *__restrict__ ou
     out[e] = s;
 }
 
-// X += P alpha, R -= Q alpha.  Wave tile: 16 rows x m columns; A fragments
-// are P (or Q) at rows r0 + i%16, columns 4s + i/16; B fragments alpha rows
-// 4s + i/16, columns 16c + i%16 from LDS.
+// acc[u][t] (+)= sum_k A[row0 + ra + u][k] C[k][cb + t] for the lane's 4 x 8
+// tile; A's entries four at a time with the next four in flight.
+__device__ __forceinline__ void tile_times(const double *__restrict__ A, int64_t row0, int ra, int cb, int64_t rows,
+                                           int m, const double *C, double (&acc)[4][8]) {
+    double cur[4][KB], nxt[4][KB];
+    auto load = [&](double (&dst)[4][KB], int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t row = row0 + ra + u;
+#pragma unroll
+            for (int q = 0; q < KB; ++q) dst[u][q] = (row < rows && k0 + q < m) ? A[row * m + k0 + q] : 0.0;
+        }
+    };
+    load(cur, 0);
+    for (int k0 = 0; k0 < m; k0 += KB) {
+        if (k0 + KB < m) load(nxt, k0 + KB);
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            double c[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) c[t] = C[(k0 + q) * GM + cb + t];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) acc[u][t] = fma(cur[u][q], c[t], acc[u][t]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < KB; ++q) cur[u][q] = nxt[u][q];
+    }
+}
+
+// X += P alpha, R -= Q alpha; a wave takes TRW rows, lane (a, b) rows
+// 4a..4a+3 and columns 8b..8b+7 of them.
 __global__ void __launch_bounds__(UBLK) k_block_xr(int64_t rows, int m, const double *__restrict__ alpha,
                                                    const double *__restrict__ P, const double *__restrict__ Q,
                                                    double *__restrict__ X, double *__restrict__ R,
                                                    double *__restrict__ partials) {
     __shared__ double s_a[GM * GM];
-    __shared__ double s_col[UBLK / WAVE][4][GM];
+    __shared__ double s_col[UBLK / WAVE][8][GM];
     for (int e = threadIdx.x; e < GM * GM; e += blockDim.x) s_a[e] = alpha[e];
     __syncthreads();
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    const int kr = lane >> 4, kc = lane & 15;
-    const int nk = (m + 3) / 4, nc = (m + 15) / 16;
-    double rr[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t r0 = ((int64_t)blockIdx.x * nw + w) * 16; r0 < rows; r0 += (int64_t)gridDim.x * nw * 16) {
-        // all fragments of the 16 rows first (loads in flight together)
-        const int64_t ra = r0 + kc;
-        double pa[GM / 4], qa[GM / 4];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int ra = (lane >> 3) * 4, cb = (lane & 7) * 8;
+    double rr[8];
 #pragma unroll
-        for (int s = 0; s < GM / 4; ++s) {
-            const int k = 4 * s + kr;
-            const bool ok = ra < rows && k < m;
-            pa[s] = ok ? P[ra * m + k] : 0.0;
-            qa[s] = ok ? Q[ra * m + k] : 0.0;
+    for (int t = 0; t < 8; ++t) rr[t] = 0.0;
+    const int64_t step = (int64_t)gridDim.x * (UBLK / WAVE) * TRW;
+    for (int64_t row0 = ((int64_t)blockIdx.x * (UBLK / WAVE) + w) * TRW; row0 < rows; row0 += step) {
+        double acc[4][8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[u][t] = 0.0;
+        tile_times(P, row0, ra, cb, rows, m, s_a, acc);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t row = row0 + ra + u;
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (row < rows && cb + t < m) X[row * m + cb + t] += acc[u][t];
         }
-        // one 16-column tile at a time: its X and R entries are loaded before
-        // its matrix-core steps, which then cover their latency
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (c >= nc) break;
-            const int col = c * 16 + kc;
-            double xo[4], ro[4];
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t row = r0 + kr + 4 * q;
-                const bool ok = row < rows && col < m;
-                xo[q] = ok ? X[row * m + col] : 0.0;
-                ro[q] = ok ? R[row * m + col] : 0.0;
-            }
-            d4 dx = d4{0.0, 0.0, 0.0, 0.0}, dr = d4{0.0, 0.0, 0.0, 0.0};
+            for (int t = 0; t < 8; ++t) acc[u][t] = 0.0;
+        tile_times(Q, row0, ra, cb, rows, m, s_a, acc);
 #pragma unroll
-            for (int s = 0; s < GM / 4; ++s) {
-                if (s >= nk) break;
-                const double bv = s_a[(4 * s + kr) * GM + col];
-                dx = mfma(pa[s], bv, dx);
-                dr = mfma(qa[s], bv, dr);
-            }
+        for (int u = 0; u < 4; ++u) {
+            const int64_t row = row0 + ra + u;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t row = r0 + kr + 4 * q;
-                if (col < m && row < rows) {
-                    X[row * m + col] = xo[q] + dx[q];
-                    const double r = ro[q] - dr[q];
-                    R[row * m + col] = r;
-                    rr[c] += r * r;
+            for (int t = 0; t < 8; ++t)
+                if (row < rows && cb + t < m) {
+                    const double r = R[row * m + cb + t] - acc[u][t];
+                    R[row * m + cb + t] = r;
+                    rr[t] += r * r;
                 }
-            }
         }
     }
     // per-column partial of this workgroup: (wave, row group) in order
 #pragma unroll
-    for (int c = 0; c < 4; ++c) s_col[w][kr][c * 16 + kc] = rr[c];
+    for (int t = 0; t < 8; ++t) s_col[w][lane >> 3][cb + t] = rr[t];
     __syncthreads();
     if ((int)threadIdx.x < m) {
-        double t = 0.0;
-        for (int v = 0; v < nw; ++v)
-            for (int g = 0; g < 4; ++g) t += s_col[v][g][threadIdx.x];
-        partials[(int64_t)blockIdx.x * m + threadIdx.x] = t;
+        double tot = 0.0;
+        for (int v = 0; v < UBLK / WAVE; ++v)
+            for (int gq = 0; gq < 8; ++gq) tot += s_col[v][gq][threadIdx.x];
+        partials[(int64_t)blockIdx.x * m + threadIdx.x] = tot;
     }
 }
 
-// P <- Z T1 + P T2 in place.
+// P <- Z T1 + P T2 in place; tiles as in k_block_xr.
 __global__ void __launch_bounds__(UBLK) k_block_p(int64_t rows, int m, const double *__restrict__ T1,
                                                   const double *__restrict__ T2, const double *__restrict__ Z,
                                                   double *P) {
@@ -218,49 +218,33 @@ __global__ void __launch_bounds__(UBLK) k_block_p(int64_t rows, int m, const dou
         s_2[e] = T2[e];
     }
     __syncthreads();
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    const int kr = lane >> 4, kc = lane & 15;
-    const int nk = (m + 3) / 4, nc = (m + 15) / 16;
-    for (int64_t r0 = ((int64_t)blockIdx.x * nw + w) * 16; r0 < rows; r0 += (int64_t)gridDim.x * nw * 16) {
-        d4 acc[4];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int ra = (lane >> 3) * 4, cb = (lane & 7) * 8;
+    const int64_t step = (int64_t)gridDim.x * (UBLK / WAVE) * TRW;
+    for (int64_t row0 = ((int64_t)blockIdx.x * (UBLK / WAVE) + w) * TRW; row0 < rows; row0 += step) {
+        double acc[4][8];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
-        const int64_t ra = r0 + kc;
-        double za[GM / 4], pa[GM / 4];
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int s = 0; s < GM / 4; ++s) {
-            const int k = 4 * s + kr;
-            const bool ok = ra < rows && k < m;
-            za[s] = ok ? Z[ra * m + k] : 0.0;
-            pa[s] = ok ? P[ra * m + k] : 0.0;
-        }
+            for (int t = 0; t < 8; ++t) acc[u][t] = 0.0;
+        tile_times(Z, row0, ra, cb, rows, m, s_1, acc);
+        tile_times(P, row0, ra, cb, rows, m, s_2, acc);
+        // the wave's rows of P are read whole by every lane before any lane
+        // writes: wait for the whole wave here
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int s = 0; s < GM / 4; ++s) {
-            if (s >= nk) break;
-            const int k = 4 * s + kr;
+        for (int u = 0; u < 4; ++u) {
+            const int64_t row = row0 + ra + u;
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (c < nc) {
-                    acc[c] = mfma(za[s], s_1[k * GM + c * 16 + kc], acc[c]);
-                    acc[c] = mfma(pa[s], s_2[k * GM + c * 16 + kc], acc[c]);
-                }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int col = c * 16 + kc;
-            if (c >= nc || col >= m) continue;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t row = r0 + kr + 4 * q;
-                if (row < rows) P[row * m + col] = acc[c][q];
-            }
+            for (int t = 0; t < 8; ++t)
+                if (row < rows && cb + t < m) P[row * m + cb + t] = acc[u][t];
         }
     }
 }
 
 inline unsigned update_grid(int64_t rows) {
-    const int64_t per = 16 * (UBLK / WAVE);
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + per - 1) / per, 768));
+    const int64_t per = (int64_t)(UBLK / WAVE) * TRW;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + per - 1) / per, 2048));
 }
 
 }  // namespace
@@ -285,7 +269,7 @@ void block_gram(const double *const *mats, int nmat, const int *li, const int *r
     g.rows = rows;
     g.m = m;
     g.partials = partials;
-    hipLaunchKernelGGL(k_gram, dim3(GBLKS), dim3(128 * npair), 0, s, g);
+    hipLaunchKernelGGL(k_gram, dim3(GBLKS), dim3(64 * npair), 0, s, g);
     const int64_t n = (int64_t)npair * GM * GM;
     double *out2 = partials + (int64_t)GBLKS * n;
     const unsigned gx = (unsigned)((n + 255) / 256);
