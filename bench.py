@@ -56,31 +56,169 @@ def algorithmic_bytes(info, n_rows, nnzb0, vt=8):
     return out
 
 
-def cpu_baseline(sample_grid=(24, 104, 3, 2)):
-    """The oracle (numpy/scipy float64, one thread) on a smaller disc of the
-    same family: the solve phase of the same algorithm to the same rtol."""
-    from threadpoolctl import threadpool_limits
-
+def cpu_baseline(sample_grid=(48, 208, 6, 2)):
+    """The oracle in its C++17/OpenMP form (float64, the same algorithm and
+    rtol) on all host cores the process may use, on a bounded sample of the
+    workload: the P2 disc of the same recipe with half the cells per
+    direction (1,573,728 DOF, an eighth of the headline disc)."""
     import meshgen as mg
-    from oracle import amg, fem, krylov
+    from oracle import native
     nr, nth, nz, deg = sample_grid
     prob = mg.disc_problem(nr, nth, nz, deg, seed=0)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        A, b, _, _ = fem.assemble_problem(prob)
-        B = fem.rigid_body_modes(prob.mesh.coords, prob.mask)
-        t1 = time.perf_counter()
-        levels = amg.setup(A, B)
-        t2 = time.perf_counter()
-        res = krylov.pcg(A, b, lambda r: amg.vcycle(levels, r), rtol=1e-8)
-        t3 = time.perf_counter()
+    threads = native.max_threads()
+    S = native.System.from_problem(prob)
+    H = native.Hierarchy(S)
+    r = H.pcg(S.b(), rtol=1e-8)
     n = prob.mesh.n_dof
-    log(f"cpu oracle: {n} DOF, assembly {t1 - t0:.1f}s setup {t2 - t1:.1f}s solve {t3 - t2:.1f}s, {res.iters} it")
-    return {"value": n / (t3 - t2), "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle solve phase (PCG + SA-AMG, float64, rtol 1e-8, {res.iters} iterations) on the "
-                      f"disc P2 {nr}x{nth}x{nz} ({n} DOF), same material/field recipe; oracle assembly "
-                      f"{t1 - t0:.1f}s and setup {t2 - t1:.1f}s not in the value",
-            "solve_s": t3 - t2, "iters": res.iters}
+    log(f"cpu oracle ({threads} threads): {n} DOF, assembly {S.time_assemble:.1f}s setup {H.time_setup:.1f}s "
+        f"solve {r.time_solve:.1f}s, {r.iters} it")
+    return {"value": n / r.time_solve, "unit": "DOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"C++17/OpenMP oracle solve phase (PCG + SA-AMG, float64, rtol 1e-8, {r.iters} iterations) "
+                      f"on the disc P2 {nr}x{nth}x{nz} ({n} DOF, 1/8 of the headline disc), same material and "
+                      f"field recipe, {threads} OpenMP threads; its assembly {S.time_assemble:.2f}s and setup "
+                      f"{H.time_setup:.2f}s are reported beside the value",
+            "solve_s": r.time_solve, "setup_s": H.time_setup, "assembly_s": S.time_assemble, "iters": r.iters,
+            "dof_per_s_setup_plus_solve": n / (H.time_setup + r.time_solve), "host_cpus": os.cpu_count()}
+
+
+def cpu_baseline_full(grid=(96, 416, 12, 2), repeats=3, one_thread_grid=(48, 208, 6, 2)):
+    """The protocol of a full CPU comparison: the C++ oracle on the headline
+    disc with all host cores (assembly, setup and solve, median of `repeats`),
+    and with one thread on the 1/8 disc (one run each; a one-thread run of the
+    headline disc takes tens of minutes)."""
+    import statistics
+
+    import meshgen as mg
+    from oracle import native
+    out = {"threads": native.max_threads(), "host_cpus": os.cpu_count()}
+    for key, g, th, rep in (("all_cores", grid, 0, repeats), ("one_thread", one_thread_grid, 1, 1)):
+        prob = mg.disc_problem(*g, seed=0)
+        runs = []
+        for k in range(rep):
+            S = native.System.from_problem(prob, threads=th)
+            H = native.Hierarchy(S, threads=th)
+            r = H.pcg(S.b(), rtol=1e-8)
+            runs.append((S.time_assemble, H.time_setup, r.time_solve, r.iters))
+            log(f"cpu oracle {key} run {k}: {prob.mesh.n_dof} DOF, assembly {runs[-1][0]:.1f}s setup "
+                f"{runs[-1][1]:.1f}s solve {runs[-1][2]:.1f}s, {r.iters} it")
+            H.free()
+            S.free()
+        med = [statistics.median(x[i] for x in runs) for i in range(3)]
+        n = prob.mesh.n_dof
+        out[key] = {"grid": list(g), "n_dof": n, "runs": len(runs), "assembly_s": med[0], "setup_s": med[1],
+                    "solve_s": med[2], "iters": runs[0][3], "dof_per_s_solve": n / med[2],
+                    "dof_per_s_setup_plus_solve": n / (med[1] + med[2]),
+                    "threads": native.max_threads() if th == 0 else th}
+    return out
+
+
+def block_rhs_form(te, torch, dev):
+    """64 thermal load cases on the 1,993,320-DOF P1 disc as one multi-RHS
+    solve (and as block CG), against 64 single float64 solves on the same GPU;
+    columns 0 and 63 against the stored oracle solutions of their cases."""
+    import numpy as np
+
+    import meshgen as mg
+    from tests import golden_c2
+    prob = mg.disc_problem(*mg.DISC_P1_2M, seed=0)
+    m = prob.mesh
+    coords, cells = torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.cells).to(dev)
+    mask = torch.from_numpy(prob.mask).to(dev)
+    A, _ = te.assemble(coords, cells, 1, prob.E, prob.nu, prob.alpha, prob.T_ref, torch.from_numpy(prob.T).to(dev),
+                       mask=mask)
+    h = te.AMG(A, coords, mask, max_nrhs=64, aggregation="greedy")
+    h.autotune()
+    seeds = list(range(1000, 1064))
+    Ts = torch.from_numpy(np.stack([mg.disc_temperature_bumps(m, s) for s in seeds])).to(dev)
+    B = te.assemble_load(coords, cells, 1, prob.E, prob.nu, prob.alpha, prob.T_ref, Ts, mask=mask)
+    h.solve(B[:, :, :2].contiguous())
+    h.solve(B[:, :, :2].contiguous(), block=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, rep = h.solve(B)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ub, repb = h.solve(B, block=True)
+    torch.cuda.synchronize()
+    t_bcg = time.perf_counter() - t0
+    t_single, its = 0.0, []
+    for j in range(len(seeds)):
+        bj = B[:, :, j].reshape(-1).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rj = h.solve(bj)
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t0
+        its.append(rj.iters[0])
+    err = {}
+    for j, seed in ((0, 1000), (63, 1063)):
+        g = golden_c2.load(golden_c2.load_case_path(seed))
+        es, ep = golden_c2.errors(U[:, :, j].reshape(-1).cpu().numpy(), g)
+        eb, _ = golden_c2.errors(Ub[:, :, j].reshape(-1).cpu().numpy(), g)
+        err[f"case{seed}"] = {"sampled": es, "projected": ep, "block_cg_sampled": eb, "iters": rep.iters[j],
+                              "oracle_iters": g["iters"]}
+    n = m.n_dof
+    out = {"workload": f"P1 disc 104x452x13, {n} DOF, 64 bump load cases (seeds 1000-1063), greedy aggregation",
+           "ms": round(t_multi * 1e3, 2), "singles_ms": round(t_single * 1e3, 2),
+           "speedup_vs_fp64_singles": round(t_single / t_multi, 3), "iters_max": max(rep.iters),
+           "single_iters_mean": float(np.mean(its)), "all_converged": bool(all(rep.converged)),
+           "max_relres_true": max(rep.relres_true), "block_cg_ms": round(t_bcg * 1e3, 2),
+           "block_cg_iters": repb.iters[0], "block_cg_speedup_vs_fp64_singles": round(t_single / t_bcg, 3),
+           "dof_rhs_per_s": n * len(seeds) / t_multi, "err_vs_oracle": err}
+    log(f"block rhs: 64 columns {t_multi * 1e3:.1f} ms, block CG {t_bcg * 1e3:.1f} ms, singles "
+        f"{t_single * 1e3:.1f} ms; errors {err}")
+    return out
+
+
+def multi_mesh_form(te, torch, dev):
+    """32 P1 discs (DOF log-uniform in [1e4, 5e5], bump fields of seeds
+    2000-2031) in one persistent graph-replayed launch sequence against 32
+    single float64 solves; the smallest and the largest mesh against the
+    stored oracle solutions of those meshes."""
+    import numpy as np
+
+    import meshgen as mg
+    from tests import golden_c2
+    sizes = mg.multi_mesh_sizes(32, lo=1e4, hi=5e5)
+    hs, bs, probs = [], [], []
+    for (nr, nth, nz, seed) in sizes:
+        prob = mg.disc_problem(nr, nth, nz, 1, seed=0)
+        prob.T = mg.disc_temperature_bumps(prob.mesh, seed)
+        m = prob.mesh
+        c = torch.from_numpy(m.coords).to(dev)
+        mk = torch.from_numpy(prob.mask).to(dev)
+        A, b = te.assemble(c, torch.from_numpy(m.cells).to(dev), 1, prob.E, prob.nu, prob.alpha, prob.T_ref,
+                           torch.from_numpy(prob.T).to(dev), mask=mk)
+        hs.append(te.AMG(A, c, mk, aggregation="greedy"))
+        bs.append(b)
+        probs.append(prob)
+    te.solve_multi(hs[:2], bs[:2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, reps = te.solve_multi(hs, bs)
+    torch.cuda.synchronize()
+    t_multi = time.perf_counter() - t0
+    t_seq = 0.0
+    for h, b in zip(hs, bs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.solve(b)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+    dofs = [p.mesh.n_dof for p in probs]
+    err = {}
+    for i in golden_c2.MULTI_MESH_INDICES:
+        g = golden_c2.load(golden_c2.multi_mesh_path(i))
+        es, ep = golden_c2.errors(us[i].cpu().numpy(), g)
+        err[f"mesh{i}_{dofs[i]}dof"] = {"sampled": es, "projected": ep, "iters": reps["iters"][i],
+                                         "oracle_iters": g["iters"]}
+    out = {"workload": f"32 P1 discs, {sum(dofs)} DOF in total ({min(dofs)}-{max(dofs)} each), bump fields, "
+                       f"greedy aggregation", "ms": round(t_multi * 1e3, 2), "singles_ms": round(t_seq * 1e3, 2),
+           "speedup_vs_fp64_singles": round(t_seq / t_multi, 3),
+           "all_converged": bool(all(reps["converged"])), "err_vs_oracle": err}
+    log(f"multi-mesh: {t_multi * 1e3:.1f} ms vs {t_seq * 1e3:.1f} ms sequential; errors {err}")
+    return out
 
 
 def main():
@@ -90,7 +228,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", default="96,416,12,2", help="disc nr,ntheta,nz,degree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the mixed-precision solve")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only the full CPU protocol: the oracle on the headline disc with all cores (median of 3) "
+                         "and with one thread on the 1/8 disc; prints one JSON line")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision, 64-load-case and 32-mesh forms")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configurations")
     ap.add_argument("--coarse-sym", type=int, default=1, choices=(0, 1),
                     help="store the coarse operators by their upper triangle (amg_options.coarse_sym)")
@@ -99,6 +241,9 @@ def main():
         print(f"bench.py measures one GPU only (the build targets a single MI355X); --gpus {args.gpus} is not "
               f"supported", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_full:
+        print(json.dumps({"cpu_baseline_full": cpu_baseline_full()}), flush=True)
+        return
     os.environ.setdefault("TE_VERBOSE", "1")
     ensure_built()
     import numpy as np
@@ -216,6 +361,20 @@ def main():
             roofline["traffic"] = t["per_launch"][dom]["traffic_bytes"]
             roofline["traffic_source"] = "profiles/disc_p2_12M_fp64_hbm_counters.md"
 
+    # error against the stored float64 oracle solution of this disc
+    err_vs_oracle = None
+    golden = None
+    if (nr, nth, nz, deg) == (96, 416, 12, 2):
+        from tests import golden_c2
+        golden = golden_c2.load()
+        es, ep = golden_c2.errors(u.cpu().numpy(), golden)
+        err_vs_oracle = {"sampled": es, "projected": ep, "oracle_iters": golden["iters"],
+                         "aggregates_equal": all(golden_c2.agg_digest(h.aggregates(l)) == dg
+                                                 for l, (_, dg) in golden["agg"].items()),
+                         "source": "tests/golden/disc_p2_12m_oracle.txt (C++ oracle, 4096 sampled DOFs and 8 "
+                                   "Gaussian projections)"}
+        log(f"vs oracle: sampled {es:.2e}, projected {ep:.2e}")
+
     forms = {}
     if not args.no_forms:
         u64 = u.clone()
@@ -224,7 +383,12 @@ def main():
         forms["mixed_fp32_vcycle"] = {"ms": round(repm.time_ms, 2), "iters": repm.iters[0],
                                       "relres_true": repm.relres_true[0], "rel_diff_vs_fp64": diff,
                                       "speedup_vs_fp64": round(reps[-1].time_ms / repm.time_ms, 3)}
+        if golden is not None:
+            es, ep = golden_c2.errors(um.cpu().numpy(), golden)
+            forms["mixed_fp32_vcycle"]["err_vs_oracle"] = {"sampled": es, "projected": ep}
         log(f"mixed: {repm.iters[0]} it, {repm.time_ms:.1f} ms, diff vs fp64 {diff:.2e}")
+        forms["block_rhs_64"] = block_rhs_form(te, torch, dev)
+        forms["multi_mesh_32"] = multi_mesh_form(te, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -245,6 +409,7 @@ def main():
         "time_setup_ms": round(t_setup * 1e3, 1),
         "time_autotune_ms": round(t_tune * 1e3, 1),
         "dof_per_s_with_setup": m.n_dof / (t_asm + t_setup + ms_per_step * 1e-3),
+        "err_vs_oracle": err_vs_oracle,
         "roofline": roofline,
         "kernels": kernels,
         "autotune": [ln for ln in tune_report.splitlines() if ln.strip()],

@@ -1,7 +1,10 @@
-"""The stored float64 oracle solution of the 12,043,200-DOF P2 disc
-(tests/golden/disc_p2_12m_oracle.txt, written by
-tests/golden/make_disc_p2_12m.py from the C++ oracle) and the error of a
-solution against it.  Holds no arithmetic of the method: sampling rules and
+"""Stored float64 oracle solutions of the benchmark workloads and the error
+of a solution against them: the 12,043,200-DOF P2 disc
+(tests/golden/disc_p2_12m_oracle.txt) and two load cases of the 64-case
+1,993,320-DOF P1 disc (tests/golden/disc_p1_2m_case*_oracle.txt), written by
+tests/golden/make_disc_p2_12m.py and make_disc_p1_2m_cases.py from the C++
+oracle, and two meshes of the 32-mesh form (tests/golden/multi_mesh*_oracle.txt,
+make_multi_mesh_cases.py).  Holds no arithmetic of the method: sampling rules and
 the file format only."""
 from __future__ import annotations
 
@@ -10,14 +13,29 @@ import os
 
 import numpy as np
 
-PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "disc_p2_12m_oracle.txt")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+PATH = os.path.join(GOLDEN, "disc_p2_12m_oracle.txt")
+# the 64-load-case form: P1 disc 104 x 452 x 13, bump fields of seeds 1000..1063
+LOAD_CASE_SEEDS = (1000, 1063)
+
+
+def load_case_path(seed):
+    return os.path.join(GOLDEN, f"disc_p1_2m_case{seed}_oracle.txt")
+
+
+# the 32-mesh form: the smallest and the largest of meshgen.multi_mesh_sizes(32)
+MULTI_MESH_INDICES = (27, 25)
+
+
+def multi_mesh_path(index):
+    return os.path.join(GOLDEN, f"multi_mesh{index}_oracle.txt")
 N_SAMPLES = 4096
 SAMPLE_SEED = 12_043_200
 PROJ_SEEDS = list(range(1000, 1008))
 
 
 def sample_indices(n_dof):
-    return np.sort(np.random.default_rng(SAMPLE_SEED).choice(n_dof, N_SAMPLES, replace=False))
+    return np.sort(np.random.default_rng(SAMPLE_SEED).choice(n_dof, min(N_SAMPLES, n_dof), replace=False))
 
 
 def projection_vector(seed, n_dof):
