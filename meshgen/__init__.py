@@ -340,6 +340,62 @@ def disc_pressure_faces(mesh: Mesh, p_rim: float = 4.0e7, p_top: float = -5.0e6,
     return np.ascontiguousarray(faces[keep]), np.ascontiguousarray(p.astype(np.float64))
 
 
+@dataclasses.dataclass
+class ThermalMaterials:
+    """Temperature tables [n_materials][n_points] (T ascending) of the thermal
+    conductivity kappa (W/(m K)) and specific heat c_v (J/(kg K)), the density
+    rho [n_materials] (kg/m^3), and the material of every cell."""
+    T: np.ndarray
+    kappa: np.ndarray
+    cv: np.ndarray
+    rho: np.ndarray
+    cell_material: np.ndarray
+
+
+def turbine_thermal_tables():
+    """Three illustrative metals sampled at 250..1000 K (the paper shows
+    normalised conductivity and specific-heat curves only): conductivity
+    falling for the first, rising for the other two, specific heat rising."""
+    Tp = np.linspace(250.0, 1000.0, 6)
+    s = (Tp - 250.0) / 750.0
+    kappa = np.array([26.0 * (1.0 - 0.25 * s), 14.0 * (1.0 + 0.6 * s), 21.0 * (1.0 + 0.35 * s * (1.0 - 0.3 * s))])
+    cv = np.array([450.0 * (1.0 + 0.35 * s), 430.0 * (1.0 + 0.45 * s), 470.0 * (1.0 + 0.3 * s)])
+    rho = np.array([7850.0, 8190.0, 7750.0])
+    return np.tile(Tp, (3, 1)), kappa, cv, rho
+
+
+def disc_thermal_materials(mesh: Mesh, geom: DiscGeom = DiscGeom()) -> ThermalMaterials:
+    """Hub, web and rim (radial thirds of the cell centroid, as
+    disc_materials) with the thermal tables above."""
+    cm = disc_materials(mesh, geom).cell_material
+    Tp, kappa, cv, rho = turbine_thermal_tables()
+    return ThermalMaterials(Tp, kappa, cv, rho, cm)
+
+
+@dataclasses.dataclass
+class RobinFaces:
+    """Heat-transfer boundary faces (the triangles of boundary_faces), with a
+    heat-transfer coefficient h >= 0 (W/(m^2 K)) and an exterior temperature
+    T_bc (K) per face."""
+    faces: np.ndarray
+    h: np.ndarray
+    T_bc: np.ndarray
+
+
+def disc_robin_faces(mesh: Mesh, geom: DiscGeom = DiscGeom(), T_rim=900.0, T_bore=350.0, T_side=600.0,
+                     h_rim=1500.0, h_bore=800.0, h_side=150.0) -> RobinFaces:
+    """Every boundary face of the disc exchanges heat: hot gas at the rim,
+    cooling air in the bore, and a moderate exchange on the two flat faces."""
+    faces = boundary_faces(mesh)
+    x = mesh.coords[faces[:, :3].astype(np.int64)]
+    r = np.hypot(x[..., 0], x[..., 1])
+    rim = np.all(r > geom.r_out * (1 - 1e-6), axis=1)
+    bore = np.all(r < geom.r_in * (1 + 1e-6), axis=1)
+    h = np.where(rim, h_rim, np.where(bore, h_bore, h_side))
+    Tb = np.where(rim, T_rim, np.where(bore, T_bore, T_side))
+    return RobinFaces(faces, np.ascontiguousarray(h, dtype=np.float64), np.ascontiguousarray(Tb, dtype=np.float64))
+
+
 # ---------------------------------------------------------------------------
 # Named workloads
 # ---------------------------------------------------------------------------

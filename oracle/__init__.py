@@ -23,5 +23,14 @@ paper and the textbook methods it names, in float64:
                  initial guess.
 * ``transient`` -- the time-step control of eq. dt_spec around the elastic
                  solve of a transient run (Sec. 3.3, Sec. 5.3).
+* ``thermal`` -- the nonlinear heat equation of eq. wf_thermal (steady, or
+                 one backward-Euler step) with its Newton Jacobian and
+                 Newton's method (Sec. 3, 3.2, 5.2, 5.3).
+* ``camg``    -- classical AMG for the scalar thermal corrections: strength,
+                 PMIS coarsening, direct interpolation, Galerkin product, l1
+                 hybrid Gauss-Seidel smoother, V-cycle (Sec. 5.1).
+* ``native``  -- the assembly, smoothed-aggregation setup, V-cycle and PCG
+                 restated in plain C++17/OpenMP (``native/te_oracle.cpp``),
+                 for the sizes the NumPy oracle cannot reach.
 * ``rng``     -- splitmix64 counter generator (Steele, Lea & Flood 2014).
 """
