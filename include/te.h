@@ -405,6 +405,188 @@ int te_timestep_noalloc(const double *T_new, const double *T_old, int64_t n, dou
 /* Releases everything the handle owns.  NULL is accepted. */
 int amg_destroy(amg_handle *h);
 
+/* ---- thermal solve (Sec. 3, eq. wf_thermal; Sec. 3.2; Sec. 5.1-5.3) ------
+ * The temperature of a step solves F_T(T; s) = 0 for all s in V_h:
+ *   F_T = int rho c_v (T - T_old)/dt s + int kappa grad T . grad s
+ *         + int_Gamma h (T - T_bc) s ds
+ * (backward Euler, theta = 1, Sec. 5.3; without the first term for a steady
+ * solve, Sec. 5.2), kappa and c_v temperature dependent (so F_T is
+ * nonlinear), by Newton's method (Sec. 3.2) with each correction solved by
+ * CG preconditioned with classical AMG and an l1 hybrid Gauss-Seidel
+ * smoother (Sec. 5.1).  The paper's Robin coefficient beta is -h here, h >= 0
+ * the heat-transfer coefficient, so the boundary term draws T toward T_bc.
+ * Coefficients: each material gives kappa and c_v as piecewise-linear tables
+ * in T (constant beyond the ends) and a density; a cell takes its material's
+ * values at the exact mean of T_h over the cell, so every integral is exact
+ * (P1 and P2).  The Newton Jacobian includes the derivatives of the tables
+ * (the slope of the segment [T_k, T_k+1) holding the cell mean), so it is not
+ * symmetric. */
+
+/* Scalar compressed sparse rows. */
+typedef struct {
+    int64_t n_rows;
+    int64_t nnz;
+    int64_t *row_ptr;       /* device [n_rows+1]                              */
+    int32_t *col_idx;       /* device [nnz], ascending within a row, diagonal
+                               present                                        */
+    double *val;            /* device [nnz]                                   */
+} te_csr;
+
+/* Host arrays, read during the call: T, kappa, cv [n_materials][n_points]
+ * (T strictly ascending, kappa and cv > 0), rho [n_materials] (> 0). */
+typedef struct {
+    int32_t n_materials;
+    int32_t n_points;
+    const double *T;
+    const double *kappa;    /* thermal conductivity                           */
+    const double *cv;       /* specific heat                                  */
+    const double *rho;      /* density                                        */
+} te_thermal_tables;
+
+/* Heat-transfer boundary: faces device [n_faces][3] (P1) or [n_faces][6] (P2:
+ * vertices, then the edge nodes 01, 02, 12), h and T_bc device [n_faces]
+ * (h >= 0).  n_faces = 0: insulated everywhere. */
+typedef struct {
+    int64_t n_faces;
+    const int32_t *faces;
+    const double *h;
+    const double *T_bc;
+} te_robin;
+
+/* Residual F (device [N]) and Jacobian J = dF/dT of F_T at T (device [N]),
+ * all integrals exact.  T_old (device [N]) with dt > 0: one backward-Euler
+ * step from T_old; T_old = NULL: steady.  cell_material: device [C].
+ * J: row_ptr from fe_assemble_pattern (the node coupling), col_idx and val
+ * caller-allocated with J->nnz entries, overwritten.  Deterministic (rows
+ * gathered over their cells and faces in ascending order).  Errors:
+ * TE_EINVAL (bad mesh, tables or faces, a material id out of range),
+ * TE_ENOMEM, TE_EHIP. */
+int fe_assemble_thermal(const te_mesh *mesh, const te_thermal_tables *tab, const int32_t *cell_material,
+                        const te_robin *robin, const double *T, const double *T_old, double dt, te_csr *J,
+                        double *F, hipStream_t stream);
+
+/* Classical AMG (the paper's thermal preconditioner is a classical AMG with a
+ * hybrid Gauss-Seidel smoother, Sec. 5.1): per level
+ *   strength: row i strongly depends on j != i when
+ *             -a_ij >= theta max_k (-a_ik) > 0;
+ *   splitting: PMIS with the fixed keys (|S_i^T|, splitmix64((0xC1A5 + level)
+ *             ^ i) >> 24, i), C points numbered ascending;
+ *   interpolation: direct (negative and positive couplings scaled apart);
+ *   A_c = P^T A P; stop at <= coarse_max rows, max_levels, or a coarse level
+ *   keeping more than max_coarse_ratio of the rows; the coarsest level is
+ *   applied as its explicit inverse;
+ *   smoother: l1 hybrid Gauss-Seidel over blocks of `block` consecutive rows
+ *   (Gauss-Seidel inside a block, Jacobi across, diagonal a_ii + the
+ *   absolute entries outside the block): one forward sweep before the coarse
+ *   correction (from zero), one backward sweep after it. */
+typedef struct {
+    double theta;            /* (0.25)                                          */
+    int32_t coarse_max;      /* (500)                                           */
+    int32_t max_levels;      /* (10)                                            */
+    double max_coarse_ratio; /* (0.9)                                           */
+    int32_t block;           /* rows per Gauss-Seidel block, 1..1024 (128)      */
+} camg_options;
+void camg_options_default(camg_options *opt);
+
+typedef struct camg_handle camg_handle;
+
+/* Builds the hierarchy of A (square, scalar); the values are copied (the
+ * hierarchy keeps them).  Synchronises `stream`.  Errors: TE_EINVAL,
+ * TE_ENOMEM, TE_EHIP, TE_ECHOL (singular coarsest level). */
+int camg_setup(const te_csr *A, const camg_options *opt, camg_handle **out, hipStream_t stream);
+int camg_destroy(camg_handle *h);
+
+typedef struct {
+    int32_t n_levels;
+    int64_t n_rows[16];
+    int64_t nnz[16];
+    int64_t p_nnz[16];
+    double setup_ms;
+} camg_info;
+int camg_get_info(const camg_handle *h, camg_info *info);
+/* Host copy of level l's C/F splitting: state[i] = 2 (C) or 0 (F). */
+int camg_get_splitting(const camg_handle *h, int32_t level, int8_t *state_host);
+/* Host copy of A_l (which = 0), P_l (1) or R_l = P_l^T (2); NULL arrays
+ * query the sizes through *n_rows_out / *nnz_out. */
+int camg_get_level_matrix(const camg_handle *h, int32_t level, int32_t which, int64_t *n_rows_out,
+                          int64_t *nnz_out, int64_t *row_ptr, int32_t *col, double *val);
+
+/* Component access (device vectors, level numbering = natural):
+ *   TE_CAMG_A          y = A_l x
+ *   TE_CAMG_P          y = P_l x       (x on level l+1)
+ *   TE_CAMG_R          y = P_l^T x     (y on level l+1)
+ *   TE_CAMG_VCYCLE     y = V-cycle from level l applied to x
+ *   TE_CAMG_SWEEP_FWD  y <- one forward hybrid Gauss-Seidel sweep for
+ *                      A_l z = x from z = y (y in: start, out: result)
+ *   TE_CAMG_SWEEP_BWD  the same, backward */
+#define TE_CAMG_A          0
+#define TE_CAMG_P          1
+#define TE_CAMG_R          2
+#define TE_CAMG_VCYCLE     3
+#define TE_CAMG_SWEEP_FWD  4
+#define TE_CAMG_SWEEP_BWD  5
+int camg_apply(camg_handle *h, int32_t level, int32_t op, const double *x, double *y, hipStream_t stream);
+
+/* Preconditioned CG (Sec. 2.1.2) on A (any matrix with the level-0 size,
+ * e.g. a newer Jacobian than the one the hierarchy was built from) with the
+ * V-cycle as preconditioner, from the guess in x, stopping as amg_pcg_solve
+ * (true |b - A x| <= rtol |b|, at most 3 residual replacements).  iters,
+ * relres: host, may be NULL.  Returns TE_OK, TE_ENOTCONV, TE_EINDEF, TE_ENAN,
+ * TE_EINVAL, TE_EHIP. */
+int camg_pcg_solve(camg_handle *h, const te_csr *A, const double *b, double *x, double rtol, int32_t maxit,
+                   int32_t *iters, double *relres, hipStream_t stream);
+
+/* Newton's method for F_T = 0 (Sec. 3.2): T <- T + d with J(T) d = -F(T),
+ * stopping at |F(T)|_2 <= rtol |F(T_0)|_2 (rtol 1e-9 and T_0 = 400 K in the
+ * paper's steady runs, Sec. 5.2).  The classical-AMG preconditioner is built
+ * from the Jacobian of the first Newton step and kept across Newton steps
+ * and calls (time steps); it is rebuilt before the next correction when a
+ * correction needed more than rebuild_factor times the CG iterations of the
+ * first correction after the last build (the paper rebuilds the thermal
+ * preconditioner at the steps with rapid temperature change, Sec. 5.3). */
+typedef struct {
+    double rtol;             /* Newton stop (1e-9)                              */
+    double lin_rtol;         /* CG stop for each correction (1e-8)              */
+    int32_t maxit;           /* Newton steps (25)                               */
+    int32_t lin_maxit;       /* CG iterations per correction (500)              */
+    double rebuild_factor;   /* (1.5)                                           */
+    camg_options amg;
+} newton_options;
+void newton_options_default(newton_options *opt);
+
+typedef struct {
+    int32_t iters;           /* Newton corrections                              */
+    int32_t converged;
+    int32_t rebuilds;        /* preconditioner builds in this call              */
+    int32_t lin_iters_total;
+    double res0, res;        /* |F(T_0)|_2, |F(T)|_2 at the end                 */
+    double res_hist[33];     /* |F| before each correction and at the end       */
+    int32_t lin_iters[32];   /* CG iterations of each correction                */
+    double time_ms;          /* host wall time of the call                      */
+    double assembly_ms, setup_ms, solve_ms;  /* device event time per phase     */
+} newton_report;
+
+typedef struct thermal_solver thermal_solver;
+
+/* A thermal solver for one mesh: copies the mesh, the tables, the cell
+ * materials and the heat-transfer faces (device arrays may be freed
+ * afterwards).  Synchronises.  Errors: TE_EINVAL, TE_ENOMEM, TE_EHIP. */
+int thermal_create(const te_mesh *mesh, const te_thermal_tables *tab, const int32_t *cell_material,
+                   const te_robin *robin, thermal_solver **out, hipStream_t stream);
+/* New exterior temperatures of the faces (device [n_faces], copied), for
+ * time-dependent boundary data. */
+int thermal_set_exterior(thermal_solver *s, const double *T_bc, hipStream_t stream);
+/* Newton solve of one step: T device [N] (in: initial guess, out: solution);
+ * T_old device [N] with dt > 0 (backward Euler) or NULL (steady).  rep: host,
+ * may be NULL.  Synchronises.  Returns TE_OK, TE_ENOTCONV (Newton or a CG
+ * solve hit its limit; T holds the last iterate), TE_EINDEF, TE_ENAN,
+ * TE_EINVAL, TE_EHIP, TE_ECHOL. */
+int thermal_newton(thermal_solver *s, double *T, const double *T_old, double dt, const newton_options *opt,
+                   newton_report *rep, hipStream_t stream);
+/* Drops the kept preconditioner (the next correction builds a new one). */
+int thermal_reset_preconditioner(thermal_solver *s);
+int thermal_destroy(thermal_solver *s);
+
 /* ---- learned initial guess (message-passing network, float32) ---------
  * The paper starts each transient elastic solve from the previous step's
  * displacement (Sec. 5.3).  This network maps the load instead:

@@ -29,7 +29,7 @@ parameter:
   levels, or a coarse level keeping more than 0.9 of the rows; the coarsest
   level is solved exactly (dense LU).
 * smoother: the l1 hybrid Gauss-Seidel of the cited work: the rows are cut
-  into blocks of `block` consecutive rows (256); inside a block Gauss-Seidel,
+  into blocks of `block` consecutive rows (128); inside a block Gauss-Seidel,
   across blocks Jacobi (values from before the sweep), with the diagonal
   a_ii + sum over columns outside the block of |a_ij| (convergent for any
   SPD matrix).  Pre-smoothing one forward sweep from zero, post-smoothing
@@ -56,7 +56,7 @@ class CAMGOptions:
     coarse_max: int = 500
     max_levels: int = 10
     max_coarse_ratio: float = 0.9
-    block: int = 256
+    block: int = 128
 
 
 def strength(A: sp.csr_matrix, theta=THETA):

@@ -208,3 +208,37 @@ def newton(P: ThermalProblem, T0, linear_solve, T_old=None, dt=None, rtol=1e-9, 
         F, J = assemble(P, T, T_old, dt)
         hist.append(float(np.linalg.norm(F)))
     return NewtonResult(T, maxit, hist[-1] <= rtol * f0, hist, lin)
+
+
+class ReusedPreconditioner:
+    """The linear solves of Newton's method with a kept classical-AMG
+    preconditioner (a reading of Sec. 5.3, where the thermal preconditioner is
+    rebuilt only at steps of rapid change): built from the Jacobian of the
+    first correction and kept across Newton steps and time steps; rebuilt
+    before the next correction when a correction needed more than
+    rebuild_factor times the CG iterations of the first correction after the
+    last build.  Each correction: PCG from zero to lin_rtol."""
+
+    def __init__(self, amg_options=None, lin_rtol=1e-8, lin_maxit=500, rebuild_factor=1.5):
+        from . import camg
+        self.camg = camg
+        self.opt = amg_options or camg.CAMGOptions()
+        self.lin_rtol, self.lin_maxit, self.factor = lin_rtol, lin_maxit, rebuild_factor
+        self.levels = None
+        self.base = -1
+        self.stale = True
+        self.builds = 0
+
+    def __call__(self, J, rhs, k):
+        from . import krylov
+        if self.levels is None or self.stale:
+            self.levels = self.camg.setup(J, self.opt)
+            self.base, self.stale = -1, False
+            self.builds += 1
+        r = krylov.pcg(J, rhs, lambda v: self.camg.vcycle(self.levels, v, opt=self.opt), rtol=self.lin_rtol,
+                       maxit=self.lin_maxit)
+        if self.base < 0:
+            self.base = r.iters
+        elif r.iters > self.factor * self.base:
+            self.stale = True
+        return r.u, r.iters

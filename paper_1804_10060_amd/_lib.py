@@ -25,7 +25,12 @@ EXPORTS = ["te_version", "te_last_error", "fe_assemble_pattern", "fe_assemble_th
            "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_pcg_solve_multi", "amg_energy_scale", "te_autotune", "amg_destroy",
            "amg_set_operator", "te_timestep", "te_timestep_noalloc",
            "mpnn_param_count", "mpnn_create", "mpnn_destroy", "mpnn_features", "mpnn_forward", "mpnn_backward", "mpnn_backward_from", "mpnn_energy_grad",
-           "mpnn_adam_step", "mpnn_guess"]
+           "mpnn_adam_step", "mpnn_guess",
+           "fe_assemble_thermal", "camg_options_default", "camg_setup", "camg_destroy", "camg_get_info",
+           "camg_get_splitting", "camg_get_level_matrix", "camg_apply", "camg_pcg_solve", "newton_options_default",
+           "thermal_create", "thermal_set_exterior", "thermal_newton", "thermal_reset_preconditioner",
+           "thermal_destroy"]
+TE_CAMG_A, TE_CAMG_P, TE_CAMG_R, TE_CAMG_VCYCLE, TE_CAMG_SWEEP_FWD, TE_CAMG_SWEEP_BWD = 0, 1, 2, 3, 4, 5
 
 
 class TeMesh(C.Structure):
@@ -49,6 +54,42 @@ class TePressure(C.Structure):
 class TeBsr(C.Structure):
     _fields_ = [("n_brows", C.c_int64), ("nnzb", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
                 ("val", C.c_void_p)]
+
+
+class TeCsr(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class TeThermalTables(C.Structure):
+    _fields_ = [("n_materials", C.c_int32), ("n_points", C.c_int32), ("T", C.c_void_p), ("kappa", C.c_void_p),
+                ("cv", C.c_void_p), ("rho", C.c_void_p)]
+
+
+class TeRobin(C.Structure):
+    _fields_ = [("n_faces", C.c_int64), ("faces", C.c_void_p), ("h", C.c_void_p), ("T_bc", C.c_void_p)]
+
+
+class CamgOptions(C.Structure):
+    _fields_ = [("theta", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+                ("max_coarse_ratio", C.c_double), ("block", C.c_int32)]
+
+
+class CamgInfo(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_rows", C.c_int64 * 16), ("nnz", C.c_int64 * 16),
+                ("p_nnz", C.c_int64 * 16), ("setup_ms", C.c_double)]
+
+
+class NewtonOptions(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("lin_rtol", C.c_double), ("maxit", C.c_int32), ("lin_maxit", C.c_int32),
+                ("rebuild_factor", C.c_double), ("amg", CamgOptions)]
+
+
+class NewtonReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("rebuilds", C.c_int32),
+                ("lin_iters_total", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
+                ("res_hist", C.c_double * 33), ("lin_iters", C.c_int32 * 32), ("time_ms", C.c_double),
+                ("assembly_ms", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
 
 
 class AmgOptions(C.Structure):
@@ -127,6 +168,25 @@ def load():
         "mpnn_energy_grad": ([vp, vp, vp, vp, C.POINTER(C.c_double), vp], C.c_int),
         "mpnn_adam_step": ([i64, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp], C.c_int),
         "mpnn_guess": ([vp, vp, vp], C.c_int),
+        "fe_assemble_thermal": ([C.POINTER(TeMesh), C.POINTER(TeThermalTables), vp, C.POINTER(TeRobin), vp, vp,
+                                 C.c_double, C.POINTER(TeCsr), vp, vp], C.c_int),
+        "camg_options_default": ([C.POINTER(CamgOptions)], None),
+        "camg_setup": ([C.POINTER(TeCsr), C.POINTER(CamgOptions), C.POINTER(vp), vp], C.c_int),
+        "camg_destroy": ([vp], C.c_int),
+        "camg_get_info": ([vp, C.POINTER(CamgInfo)], C.c_int),
+        "camg_get_splitting": ([vp, i32, vp], C.c_int),
+        "camg_get_level_matrix": ([vp, i32, i32, C.POINTER(i64), C.POINTER(i64), vp, vp, vp], C.c_int),
+        "camg_apply": ([vp, i32, i32, vp, vp, vp], C.c_int),
+        "camg_pcg_solve": ([vp, C.POINTER(TeCsr), vp, vp, C.c_double, i32, C.POINTER(C.c_int32),
+                            C.POINTER(C.c_double), vp], C.c_int),
+        "newton_options_default": ([C.POINTER(NewtonOptions)], None),
+        "thermal_create": ([C.POINTER(TeMesh), C.POINTER(TeThermalTables), vp, C.POINTER(TeRobin), C.POINTER(vp),
+                            vp], C.c_int),
+        "thermal_set_exterior": ([vp, vp, vp], C.c_int),
+        "thermal_newton": ([vp, vp, vp, C.c_double, C.POINTER(NewtonOptions), C.POINTER(NewtonReport), vp],
+                           C.c_int),
+        "thermal_reset_preconditioner": ([vp], C.c_int),
+        "thermal_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

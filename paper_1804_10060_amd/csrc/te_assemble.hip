@@ -1,5 +1,7 @@
 // Finite-element assembly of the thermoelastic system (weak form wf_elastic,
-// Sec. 3.1) into 3x3-block compressed rows, and Dirichlet elimination.
+// Sec. 3.1) into 3x3-block compressed rows, and Dirichlet elimination; and
+// the residual and Newton Jacobian of the heat equation (weak form
+// wf_thermal) in scalar compressed rows.
 //
 // Gather formulation, nothing is scattered: the stiffness rows of a node are
 // built by one wave that walks the cells containing the node (ascending cell
@@ -23,6 +25,7 @@
 #include <numeric>
 
 #include "te_internal.h"
+#include "te_thermal.h"
 
 namespace te {
 
@@ -117,11 +120,6 @@ static void scan_counts(const int32_t *cnt, int64_t *out, int64_t n, hipStream_t
     }
     TE_CHECK_HIP(hipStreamSynchronize(s));
 }
-
-struct Incidence {
-    DBuf<int64_t> start;  // [N+1]
-    DBuf<int64_t> inc;    // [C*npe] entries cell*npe + local, ascending per node
-};
 
 static void build_incidence(const te_mesh *m, int npe, Incidence &I, hipStream_t s) {
     const int64_t n = m->n_nodes, ne = m->n_cells * (int64_t)npe;
@@ -576,6 +574,259 @@ __global__ void k_pressure(int64_t n, const int64_t *__restrict__ ptr, const int
         }
         for (int k = 0; k < 3; ++k) b[i * 3 + k] += acc[k];
     }
+}
+
+// ---------------------------------------------------------------------------
+// heat equation (eq. wf_thermal): residual and Newton Jacobian
+// ---------------------------------------------------------------------------
+// F_i = sum over cells of kappa_c (K_c T)_i + rho c_c / dt (M_c (T - T_old))_i
+//     + sum over heat-transfer faces of h_f ((M_f T)_i - T_bc,f int_f phi_i),
+// kappa_c and c_c the cell's material tables at the cell mean Tbar_c of T_h
+// (weights w: P1 1/4; P2 -1/20 vertices, 1/5 edges); J = dF/dT adds the
+// rank-one terms kappa'(Tbar) (K_c T) w^T and rho c'(Tbar)/dt (M_c dT) w^T.
+struct ThArgs {
+    const double *X;
+    const int32_t *cells;
+    int64_t n;
+    const int64_t *start, *inc;
+    const int32_t *cmat;
+    const double *tab;  // [3][nm][np]
+    int nm, np;
+    const double *rho;
+    const int64_t *fptr, *fent;
+    const int32_t *faces;
+    const double *h, *Tbc;
+    const double *T, *Told;
+    double inv_dt;      // 0: steady
+    const int64_t *ptr;
+    const int32_t *col;
+    double *J, *F;
+};
+
+// piecewise-linear table, constant beyond its ends: value at x and the slope
+// of the segment [T_k, T_k+1) holding x (0 outside)
+__device__ __forceinline__ void table_eval(const double *Tt, const double *v, int np, double x, double &val,
+                                           double &slope) {
+    int k = -1;
+    for (int j = 0; j < np; ++j)
+        if (Tt[j] <= x) k = j;
+    if (k < 0) {
+        val = v[0];
+        slope = 0.0;
+    } else if (k >= np - 1) {
+        val = v[np - 1];
+        slope = 0.0;
+    } else {
+        slope = (v[k + 1] - v[k]) / (Tt[k + 1] - Tt[k]);
+        val = slope * (x - Tt[k]) + v[k];
+    }
+}
+
+__device__ __forceinline__ int64_t row_pos(const int32_t *__restrict__ col, int64_t r0, int64_t r1, int32_t c) {
+    int64_t lo = r0, hi = r1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// P2 triangle mass matrix times 180/|F| (vertices, then edges 01, 02, 12)
+__device__ __forceinline__ double p2_face_mass180(int a, int b) {
+    if (a < 3 && b < 3) return a == b ? 6.0 : -1.0;
+    if (a >= 3 && b >= 3) return a == b ? 32.0 : 16.0;
+    const int v = a < 3 ? a : b, e = a < 3 ? b : a;
+    // edge 3 = (0,1), 4 = (0,2), 5 = (1,2): the vertex opposite is 2, 1, 0
+    return (5 - e) == v ? -4.0 : 0.0;
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(ABLK) k_thermal(ThArgs A) {
+    const int64_t i = (int64_t)blockIdx.x * ABLK + threadIdx.x;
+    if (i >= A.n) return;
+    constexpr int NPE = DEG == 1 ? 4 : 10;
+    constexpr int NPF = DEG == 1 ? 3 : 6;
+    __shared__ double s_g[ABLK][12];
+    double *G = s_g[threadIdx.x];
+    const int64_t r0 = A.ptr[i], r1 = A.ptr[i + 1];
+    for (int64_t k = r0; k < r1; ++k) A.J[k] = 0.0;
+    double Fi = 0.0;
+    for (int64_t e = A.start[i]; e < A.start[i + 1]; ++e) {
+        const int64_t cell = A.inc[e] / NPE;
+        const int a = (int)(A.inc[e] % NPE);
+        const int32_t *cv = A.cells + cell * NPE;
+        const Geo g = cell_geo(A.X, cv);
+        for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) G[k * 3 + c] = g.G[k][c];
+        double Tc[NPE], w[NPE];
+        double Tbar = 0.0;
+        for (int c = 0; c < NPE; ++c) {
+            Tc[c] = A.T[cv[c]];
+            w[c] = DEG == 1 ? 0.25 : (c < 4 ? -0.05 : 0.2);
+            Tbar += w[c] * Tc[c];
+        }
+        const int m = A.cmat[cell];
+        double kap, dkap, cvv = 0.0, dcv = 0.0;
+        table_eval(A.tab + (int64_t)m * A.np, A.tab + (int64_t)(A.nm + m) * A.np, A.np, Tbar, kap, dkap);
+        if (A.inv_dt > 0.0)
+            table_eval(A.tab + (int64_t)m * A.np, A.tab + (int64_t)(2 * A.nm + m) * A.np, A.np, Tbar, cvv, dcv);
+        // row a of the reference stiffness int grad phi_a . grad phi_b and mass
+        double Kab[NPE], Mab[NPE];
+        if (DEG == 1) {
+            for (int b = 0; b < NPE; ++b) {
+                Kab[b] = g.vol * (G[a * 3] * G[b * 3] + G[a * 3 + 1] * G[b * 3 + 1] + G[a * 3 + 2] * G[b * 3 + 2]);
+                Mab[b] = g.vol * (a == b ? 2.0 : 1.0) / 20.0;
+            }
+        } else {
+            for (int b = 0; b < NPE; ++b) Kab[b] = 0.0;
+            const double qa = 0.5854101966249685, qb = 0.1381966011250105;
+            for (int q = 0; q < 4; ++q) {
+                const double l0 = q == 0 ? qa : qb, l1 = q == 1 ? qa : qb, l2 = q == 2 ? qa : qb,
+                             l3 = q == 3 ? qa : qb;
+                double ga[3];
+                p2_grad(a, l0, l1, l2, l3, G, ga);
+                for (int b = 0; b < NPE; ++b) {
+                    double gb[3];
+                    p2_grad(b, l0, l1, l2, l3, G, gb);
+                    Kab[b] += 0.25 * g.vol * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]);
+                }
+            }
+            for (int b = 0; b < NPE; ++b) Mab[b] = g.vol * p2_mass420(a, b) / 420.0;
+        }
+        double KT = 0.0, MdT = 0.0;
+        for (int b = 0; b < NPE; ++b) KT += Kab[b] * Tc[b];
+        Fi += kap * KT;
+        const double rc = A.inv_dt > 0.0 ? A.rho[m] * A.inv_dt : 0.0;
+        if (A.inv_dt > 0.0) {
+            for (int b = 0; b < NPE; ++b) MdT += Mab[b] * (Tc[b] - A.Told[cv[b]]);
+            Fi += rc * cvv * MdT;
+        }
+        for (int b = 0; b < NPE; ++b) {
+            double v = kap * Kab[b] + dkap * w[b] * KT;
+            if (A.inv_dt > 0.0) v += rc * (cvv * Mab[b] + dcv * w[b] * MdT);
+            A.J[row_pos(A.col, r0, r1, cv[b])] += v;
+        }
+    }
+    if (A.fptr) {
+        for (int64_t e = A.fptr[i]; e < A.fptr[i + 1]; ++e) {
+            const int64_t f = A.fent[e] / NPF;
+            const int a = (int)(A.fent[e] % NPF);
+            const int32_t *fv = A.faces + f * NPF;
+            double d1[3], d2[3];
+            for (int k = 0; k < 3; ++k) {
+                const double x0 = A.X[(int64_t)fv[0] * 3 + k];
+                d1[k] = A.X[(int64_t)fv[1] * 3 + k] - x0;
+                d2[k] = A.X[(int64_t)fv[2] * 3 + k] - x0;
+            }
+            const double nx = d1[1] * d2[2] - d1[2] * d2[1], ny = d1[2] * d2[0] - d1[0] * d2[2],
+                         nz = d1[0] * d2[1] - d1[1] * d2[0];
+            const double area = 0.5 * sqrt(nx * nx + ny * ny + nz * nz);
+            const double hf = A.h[f];
+            double MT = 0.0;
+            for (int b = 0; b < NPF; ++b) {
+                const double mf = DEG == 1 ? area * (a == b ? 2.0 : 1.0) / 12.0 : area * p2_face_mass180(a, b) / 180.0;
+                MT += mf * A.T[fv[b]];
+                A.J[row_pos(A.col, r0, r1, fv[b])] += hf * mf;
+            }
+            const double fint = DEG == 1 ? area / 3.0 : (a < 3 ? 0.0 : area / 3.0);
+            Fi += hf * (MT - A.Tbc[f] * fint);
+        }
+    }
+    A.F[i] = Fi;
+}
+
+static void pattern_impl(const te_mesh *m, Incidence &I, int64_t *row_ptr, int32_t *col, hipStream_t s);
+
+void thermal_asm_init(ThermalAsm &ta, const te_mesh *m, const te_thermal_tables *tab, const int32_t *cell_material,
+                      const te_robin *robin, hipStream_t s) {
+    TE_REQUIRE(m && tab && cell_material, TE_EINVAL, "NULL argument");
+    TE_REQUIRE(m->degree == 1 || m->degree == 2, TE_EINVAL, "degree must be 1 or 2 (got %d)", m->degree);
+    TE_REQUIRE(m->n_nodes > 0 && m->n_cells > 0 && m->coords && m->cells, TE_EINVAL, "empty mesh");
+    TE_REQUIRE(m->n_nodes < (int64_t)INT32_MAX, TE_EINVAL, "too many nodes for 32-bit indices");
+    const int nm = tab->n_materials, np = tab->n_points;
+    TE_REQUIRE(nm >= 1 && np >= 1 && tab->T && tab->kappa && tab->cv && tab->rho, TE_EINVAL,
+               "thermal tables are empty or NULL");
+    std::vector<double> h((size_t)3 * nm * np);
+    const size_t so = (size_t)nm * np;
+    for (int mm = 0; mm < nm; ++mm) {
+        TE_REQUIRE(tab->rho[mm] > 0.0, TE_EINVAL, "material %d: density must be positive", mm);
+        for (int k = 0; k < np; ++k) {
+            const size_t q = (size_t)mm * np + k;
+            TE_REQUIRE(k == 0 || tab->T[q] > tab->T[q - 1], TE_EINVAL, "material %d: temperatures not ascending", mm);
+            TE_REQUIRE(tab->kappa[q] > 0.0 && tab->cv[q] > 0.0, TE_EINVAL,
+                       "material %d: conductivity and specific heat must be positive", mm);
+            h[q] = tab->T[q];
+            h[so + q] = tab->kappa[q];
+            h[2 * so + q] = tab->cv[q];
+        }
+    }
+    ta.n = m->n_nodes;
+    ta.nc = m->n_cells;
+    ta.degree = m->degree;
+    ta.npe = m->degree == 1 ? 4 : 10;
+    ta.npf = m->degree == 1 ? 3 : 6;
+    ta.nm = nm;
+    ta.np = np;
+    upload(ta.tab, h, s);
+    upload(ta.rho, std::vector<double>(tab->rho, tab->rho + nm), s);
+    ta.coords.alloc(ta.n * 3);
+    ta.cells.alloc(ta.nc * ta.npe);
+    ta.cell_material.alloc(ta.nc);
+    TE_CHECK_HIP(hipMemcpyAsync(ta.coords.p, m->coords, ta.n * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TE_CHECK_HIP(hipMemcpyAsync(ta.cells.p, m->cells, ta.nc * ta.npe * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    TE_CHECK_HIP(hipMemcpyAsync(ta.cell_material.p, cell_material, ta.nc * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    te_mesh mc{ta.n, ta.nc, ta.degree, ta.coords.p, ta.cells.p};
+    build_incidence(&mc, ta.npe, ta.I, s);  // rejects node ids outside the mesh
+    {
+        std::vector<int32_t> cm;
+        download(cm, ta.cell_material.p, (size_t)ta.nc, s);
+        for (int32_t v : cm) TE_REQUIRE(v >= 0 && v < nm, TE_EINVAL, "a cell material id is outside 0..%d", nm - 1);
+    }
+    ta.n_faces = robin ? robin->n_faces : 0;
+    TE_REQUIRE(ta.n_faces >= 0, TE_EINVAL, "negative face count");
+    if (ta.n_faces > 0) {
+        TE_REQUIRE(robin->faces && robin->h && robin->T_bc, TE_EINVAL, "heat-transfer face arrays are NULL");
+        const int npf = ta.npf;
+        std::vector<int32_t> fh;
+        download(fh, robin->faces, (size_t)ta.n_faces * npf, s);
+        std::vector<double> hh, tb;
+        download(hh, robin->h, (size_t)ta.n_faces, s);
+        download(tb, robin->T_bc, (size_t)ta.n_faces, s);
+        for (double v : hh) TE_REQUIRE(v >= 0.0, TE_EINVAL, "heat-transfer coefficients must be >= 0");
+        std::vector<int64_t> cnt(ta.n + 1, 0);
+        for (int64_t q = 0; q < (int64_t)fh.size(); ++q) {
+            TE_REQUIRE(fh[q] >= 0 && fh[q] < ta.n, TE_EINVAL, "face %lld has a node outside the mesh",
+                       (long long)(q / npf));
+            ++cnt[fh[q] + 1];
+        }
+        for (int64_t i = 0; i < ta.n; ++i) cnt[i + 1] += cnt[i];
+        std::vector<int64_t> ent(cnt[ta.n]), fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t q = 0; q < (int64_t)fh.size(); ++q) ent[fill[fh[q]]++] = q;
+        upload(ta.fptr, cnt, s);
+        upload(ta.fent, ent, s);
+        upload(ta.faces, fh, s);
+        upload(ta.h, hh, s);
+        upload(ta.T_bc, tb, s);
+    }
+    ta.ptr.alloc(ta.n + 1);
+    pattern_impl(&mc, ta.I, ta.ptr.p, nullptr, s);
+    TE_CHECK_HIP(hipMemcpyAsync(&ta.nnz, ta.ptr.p + ta.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TE_CHECK_HIP(hipStreamSynchronize(s));
+    ta.col.alloc(std::max<int64_t>(ta.nnz, 1));
+    pattern_impl(&mc, ta.I, ta.ptr.p, ta.col.p, s);
+}
+
+void thermal_asm_run(const ThermalAsm &ta, const double *T, const double *T_old, double dt, double *Jval, double *F,
+                     hipStream_t s) {
+    const bool transient = T_old != nullptr && dt > 0.0;
+    ThArgs a{ta.coords.p, ta.cells.p, ta.n, ta.I.start.p, ta.I.inc.p, ta.cell_material.p, ta.tab.p, ta.nm, ta.np,
+             ta.rho.p, ta.n_faces > 0 ? ta.fptr.p : nullptr, ta.fent.p, ta.faces.p, ta.h.p, ta.T_bc.p, T,
+             transient ? T_old : nullptr, transient ? 1.0 / dt : 0.0, ta.ptr.p, ta.col.p, Jval, F};
+    const unsigned g = (unsigned)((ta.n + ABLK - 1) / ABLK);
+    if (ta.degree == 1) hipLaunchKernelGGL(k_thermal<1>, dim3(g), dim3(ABLK), 0, s, a);
+    else hipLaunchKernelGGL(k_thermal<2>, dim3(g), dim3(ABLK), 0, s, a);
+    TE_CHECK_HIP(hipGetLastError());
 }
 
 static void check_mesh(const te_mesh *m) {

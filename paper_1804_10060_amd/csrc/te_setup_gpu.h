@@ -46,10 +46,12 @@ void dev_diag(const DBsr &A, DBuf<double> &d, hipStream_t st);
 void dev_smoothed_p(const DBsr &A, const DBuf<int32_t> &agg, int64_t nagg, const DBuf<double> &Q,
                     const DBuf<double> &d, double omega, DBsr &P, hipStream_t s);
 
-// C = A B with the blocks summed in the order of A's row, then B's row.
+// C = A B with the blocks summed in the order of A's row, then B's row
+// (block shapes 1x1 * 1x1, 3x3 * 3x6, 6x3 * 3x6, 6x6 * 6x6).
 void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s);
 
-// T = A^T (blocks transposed; rows of each column in ascending order).
+// T = A^T (blocks transposed; rows of each column in ascending order;
+// block shapes 1x1, 3x6, 6x6).
 void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s);
 
 // Pack M into a solver layout (SELL-64 or one wave per row).  hptr is M's

@@ -725,7 +725,8 @@ void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s) {
     DBuf<int32_t> flag(1);
     TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
     const int key = A.br * 100 + A.bc * 10 + B.bc;
-    if (key == 336) launch_num<3, 3, 6>(tb, mx, A, B, C, flag.p, s);
+    if (key == 111) launch_num<1, 1, 1>(tb, mx, A, B, C, flag.p, s);
+    else if (key == 336) launch_num<3, 3, 6>(tb, mx, A, B, C, flag.p, s);
     else if (key == 636) launch_num<6, 3, 6>(tb, mx, A, B, C, flag.p, s);
     else if (key == 666) launch_num<6, 6, 6>(tb, mx, A, B, C, flag.p, s);
     else TE_REQUIRE(false, TE_EINVAL, "unsupported product block shapes %dx%d * %dx%d", A.br, A.bc, B.br, B.bc);
@@ -754,7 +755,10 @@ void dev_transpose(const DBsr &A, DBsr &T, hipStream_t s) {
                        row.p);
     DBuf<int64_t> srt(std::max<int64_t>(A.nnzb, 1));
     hipLaunchKernelGGL(k_t_rank, dim3(wave_grid(T.nr)), dim3(64), 0, s, T.nr, T.ptr, src.p, srt.p);
-    if (A.br == 3 && A.bc == 6)
+    if (A.br == 1 && A.bc == 1)
+        hipLaunchKernelGGL((k_t_fill<1, 1>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, srt.p, row.p, A.val,
+                           T.col_own.p, T.val_own.p);
+    else if (A.br == 3 && A.bc == 6)
         hipLaunchKernelGGL((k_t_fill<3, 6>), dim3(grid_for(T.nnzb)), dim3(256), 0, s, T.nnzb, srt.p, row.p, A.val,
                            T.col_own.p, T.val_own.p);
     else if (A.br == 6 && A.bc == 6)

@@ -45,7 +45,9 @@ def test_library_exports_every_declared_symbol():
 
 STRUCTS = {"te_mesh": "TeMesh", "te_material": "TeMaterial", "te_material_tables": "TeMaterialTables",
            "te_pressure": "TePressure", "te_bsr": "TeBsr", "amg_options": "AmgOptions",
-           "amg_info": "AmgInfo", "pcg_options": "PcgOptions", "pcg_report": "PcgReport"}
+           "amg_info": "AmgInfo", "pcg_options": "PcgOptions", "pcg_report": "PcgReport", "te_csr": "TeCsr",
+           "te_thermal_tables": "TeThermalTables", "te_robin": "TeRobin", "camg_options": "CamgOptions",
+           "camg_info": "CamgInfo", "newton_options": "NewtonOptions", "newton_report": "NewtonReport"}
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,143 @@
+"""The thermal solve on the GPU against the oracle: the residual and Newton
+Jacobian of eq. wf_thermal (steady and backward Euler, P1 and P2), the
+classical AMG hierarchy (C/F splitting exactly, interpolation, coarse
+operators, smoother sweeps, V-cycle), preconditioned CG, and whole Newton
+solves with the kept preconditioner (Sec. 3.2, 5.1, 5.2)."""
+import numpy as np
+import pytest
+
+import meshgen as mg
+from tests.gpu_util import dev, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(dims, deg):
+    from oracle import thermal
+    from paper_1804_10060_amd import heat
+    torch = torch_cuda()
+    m = mg.disc_mesh(*dims, deg)
+    mats = mg.disc_thermal_materials(m)
+    rb = mg.disc_robin_faces(m)
+    P = thermal.problem_from_meshgen(m, mats, rb)
+    d = dict(coords=dev(m.coords, torch.float64), cells=dev(m.cells.astype(np.int32)),
+             cm=dev(mats.cell_material.astype(np.int32)), faces=dev(rb.faces.astype(np.int32)),
+             h=dev(rb.h, torch.float64), Tbc=dev(rb.T_bc, torch.float64), tab=heat.Tables.of(mats))
+    return m, P, d
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_assembly_matches_oracle(deg):
+    from oracle import thermal
+    from paper_1804_10060_amd import heat
+    torch = torch_cuda()
+    m, P, d = _setup((6, 24, 2), deg)
+    rng = np.random.default_rng(5)
+    T = rng.uniform(300.0, 950.0, m.n_nodes)
+    T_old = T - rng.uniform(0.0, 40.0, m.n_nodes)
+    for transient in (False, True):
+        say("thermal assembly P%d transient=%s" % (deg, transient))
+        J, F = heat.assemble(d["coords"], d["cells"], deg, d["tab"], d["cm"], dev(T, torch.float64), d["faces"],
+                             d["h"], d["Tbc"], dev(T_old, torch.float64) if transient else None,
+                             3.5 if transient else 0.0)
+        Fo, Jo = thermal.assemble(P, T, T_old if transient else None, 3.5 if transient else None)
+        Jg = J.to_scipy()
+        assert np.array_equal(Jg.indptr, Jo.indptr) and np.array_equal(Jg.indices, Jo.indices)
+        assert _rel(Jg.data, Jo.data) <= 1e-12
+        assert np.abs(F.cpu().numpy() - Fo).max() <= 1e-12 * np.abs(Fo).max()
+
+
+def test_classical_amg_hierarchy_matches_oracle():
+    from oracle import camg, thermal
+    from paper_1804_10060_amd import heat
+    from paper_1804_10060_amd import _lib
+    torch = torch_cuda()
+    m, P, d = _setup((10, 40, 2), 2)
+    T = 350.0 + 500.0 * np.hypot(m.coords[:, 0], m.coords[:, 1])
+    J, _ = heat.assemble(d["coords"], d["cells"], 2, d["tab"], d["cm"], dev(T, torch.float64), d["faces"], d["h"],
+                         d["Tbc"])
+    _, Jo = thermal.assemble(P, T)
+    opt = camg.CAMGOptions(coarse_max=200, block=64)
+    h = heat.CAMG(J, coarse_max=200, block=64)
+    lev = camg.setup(Jo, opt)
+    info = h.info()
+    say("levels", info["n_rows"], "oracle", [lv.A.shape[0] for lv in lev])
+    assert info["n_levels"] == len(lev) >= 3
+    for l in range(len(lev) - 1):
+        st = h.splitting(l)
+        assert np.array_equal(st == 2, lev[l].state == camg.C_PT), f"C/F splitting differs at level {l}"
+        assert _rel(h.level_matrix(l, 1).toarray(), lev[l].P.toarray()) <= 1e-12
+    for l in range(len(lev)):
+        assert _rel(h.level_matrix(l, 0).toarray(), lev[l].A.toarray()) <= 1e-11
+    rng = np.random.default_rng(3)
+    for l in range(len(lev) - 1):
+        n = lev[l].A.shape[0]
+        g, x0 = rng.standard_normal(n), rng.standard_normal(n)
+        for op, fwd in ((_lib.TE_CAMG_SWEEP_FWD, True), (_lib.TE_CAMG_SWEEP_BWD, False)):
+            y = h.apply(l, op, dev(g, torch.float64), dev(x0, torch.float64)).cpu().numpy()
+            ref = camg.hybrid_gs(lev[l], g, x0, 64, forward=fwd)
+            assert _rel(y, ref) <= 1e-12, (l, op)
+    g = rng.standard_normal(m.n_nodes)
+    z = h.apply(0, _lib.TE_CAMG_VCYCLE, dev(g, torch.float64)).cpu().numpy()
+    assert _rel(z, camg.vcycle(lev, g, opt=opt)) <= 1e-10
+    # CG on the (non-symmetric) Jacobian with the V-cycle, against the oracle's
+    from oracle import krylov
+    b = rng.standard_normal(m.n_nodes)
+    x, it, rel = h.pcg(J, dev(b, torch.float64), rtol=1e-10)
+    ro = krylov.pcg(Jo, b, lambda v: camg.vcycle(lev, v, opt=opt), rtol=1e-10)
+    say(f"pcg iters {it} oracle {ro.iters}")
+    assert abs(it - ro.iters) <= 1 and rel <= 1e-10
+    assert np.linalg.norm(x.cpu().numpy() - ro.u) <= 1e-8 * np.linalg.norm(ro.u)
+
+
+@pytest.mark.parametrize("deg", [1, 2])
+def test_steady_newton_matches_oracle(deg):
+    """Steady solve from 400 K to relative residual 1e-9 (Sec. 5.2)."""
+    from oracle import camg, thermal
+    from paper_1804_10060_amd import heat
+    torch = torch_cuda()
+    m, P, d = _setup((12, 48, 3), deg)
+    ts = heat.ThermalSolver(d["coords"], d["cells"], deg, d["tab"], d["cm"], d["faces"], d["h"], d["Tbc"])
+    T0 = np.full(m.n_nodes, 400.0)
+    T, rep = ts.newton(dev(T0, torch.float64), coarse_max=200, block=64)
+    pre = thermal.ReusedPreconditioner(camg.CAMGOptions(coarse_max=200, block=64))
+    ro = thermal.newton(P, T0, pre)
+    say(f"P{deg} newton {rep.iters} (oracle {ro.iters}), lin {rep.lin_iters} (oracle {ro.lin_iters}), "
+        f"builds {rep.rebuilds} ({pre.builds}), {rep.time_ms:.1f} ms")
+    assert rep.converged and ro.converged and rep.iters == ro.iters
+    assert all(abs(a - b) <= 1 for a, b in zip(rep.lin_iters, ro.lin_iters))
+    assert np.abs(T.cpu().numpy() - ro.T).max() <= 1e-8 * np.abs(ro.T).max()
+    Fo, _ = thermal.assemble(P, T.cpu().numpy())
+    assert np.linalg.norm(Fo) <= 1.01e-9 * ro.res_history[0]
+
+
+def test_backward_euler_steps_with_kept_preconditioner_match_oracle():
+    """Three backward-Euler steps from 293 K (Sec. 5.3) with the exterior
+    temperatures rising between steps; the preconditioner of the first step is
+    kept (rebuilt by the same rule on both sides)."""
+    from oracle import camg, thermal
+    from paper_1804_10060_amd import heat
+    torch = torch_cuda()
+    m, P, d = _setup((10, 40, 2), 2)
+    rb = mg.disc_robin_faces(m)
+    ts = heat.ThermalSolver(d["coords"], d["cells"], 2, d["tab"], d["cm"], d["faces"], d["h"], d["Tbc"])
+    pre = thermal.ReusedPreconditioner(camg.CAMGOptions(coarse_max=200, block=64))
+    Tg = np.full(m.n_nodes, 293.0)
+    To = Tg.copy()
+    Tgd = dev(Tg, torch.float64)
+    for step, dt in enumerate((20.0, 40.0, 80.0)):
+        Tbc = 293.0 + (rb.T_bc - 293.0) * (step + 1) / 3.0
+        P.T_bc = Tbc
+        ts.set_exterior(dev(Tbc, torch.float64))
+        Tn, rep = ts.newton(Tgd, T_old=Tgd, dt=dt, coarse_max=200, block=64)
+        ro = thermal.newton(P, To, pre, T_old=To, dt=dt)
+        say(f"step {step}: newton {rep.iters} ({ro.iters}) lin {rep.lin_iters} ({ro.lin_iters}) "
+            f"builds {rep.rebuilds}")
+        assert rep.converged and ro.converged and rep.iters == ro.iters
+        assert np.abs(Tn.cpu().numpy() - ro.T).max() <= 1e-8 * np.abs(ro.T).max()
+        Tgd, To = Tn, ro.T
+    assert pre.builds >= 1
