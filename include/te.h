@@ -537,8 +537,9 @@ int camg_pcg_solve(camg_handle *h, const te_csr *A, const double *b, double *x, 
                    int32_t *iters, double *relres, hipStream_t stream);
 
 /* Newton's method for F_T = 0 (Sec. 3.2): T <- T + d with J(T) d = -F(T),
- * stopping at |F(T)|_2 <= rtol |F(T_0)|_2 (rtol 1e-9 and T_0 = 400 K in the
- * paper's steady runs, Sec. 5.2).  The classical-AMG preconditioner is built
+ * stopping at |F(T)|_2 <= max(rtol |F(T_0)|_2, atol) (rtol 1e-9 and T_0 =
+ * 400 K in the paper's steady runs, Sec. 5.2; the absolute floor atol, in
+ * the units of F, ends a time step that starts near a steady state).  The classical-AMG preconditioner is built
  * from the Jacobian of the first Newton step and kept across Newton steps
  * and calls (time steps); it is rebuilt before the next correction when a
  * correction needed more than rebuild_factor times the CG iterations of the
@@ -546,6 +547,7 @@ int camg_pcg_solve(camg_handle *h, const te_csr *A, const double *b, double *x, 
  * preconditioner at the steps with rapid temperature change, Sec. 5.3). */
 typedef struct {
     double rtol;             /* Newton stop (1e-9)                              */
+    double atol;             /* absolute floor of the Newton stop (1e-8)        */
     double lin_rtol;         /* CG stop for each correction (1e-8)              */
     int32_t maxit;           /* Newton steps (25)                               */
     int32_t lin_maxit;       /* CG iterations per correction (500)              */

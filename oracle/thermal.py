@@ -29,8 +29,10 @@ Readings (the paper is silent or its sign is ambiguous):
   mass integrands).  The table slope used in the Jacobian is that of the
   segment [T_k, T_{k+1}) holding the mean (0 beyond the ends).
 * Newton: T <- T + d with J(T) d = -F(T); stop when |F(T)|_2 <= rtol |F(T_0)|_2
-  (rtol 1e-9); the correction solved by preconditioned CG to a relative
-  residual of 1e-8 (lin_rtol).
+  (rtol 1e-9) or |F(T)|_2 <= atol (1e-8, in the units of F: watts), the
+  absolute floor that ends a step starting near a steady state, where 1e-9
+  of the initial residual lies below rounding; the correction solved by
+  preconditioned CG to a relative residual of 1e-8 (lin_rtol).
 """
 from __future__ import annotations
 
@@ -189,7 +191,7 @@ class NewtonResult:
     lin_iters: list
 
 
-def newton(P: ThermalProblem, T0, linear_solve, T_old=None, dt=None, rtol=1e-9, maxit=25):
+def newton(P: ThermalProblem, T0, linear_solve, T_old=None, dt=None, rtol=1e-9, maxit=25, atol=1e-8):
     """Newton's method on F_T = 0 (Sec. 3.2): linear_solve(J, rhs, k) returns
     (d, lin_iters) with J d = rhs for Newton iteration k."""
     T = np.array(T0, dtype=np.float64, copy=True)
@@ -197,17 +199,16 @@ def newton(P: ThermalProblem, T0, linear_solve, T_old=None, dt=None, rtol=1e-9, 
     f0 = float(np.linalg.norm(F))
     hist = [f0]
     lin = []
-    if f0 == 0.0:
-        return NewtonResult(T, 0, True, hist, lin)
+    stop = max(rtol * f0, atol)
     for k in range(maxit):
-        if hist[-1] <= rtol * f0:
+        if hist[-1] <= stop:
             return NewtonResult(T, k, True, hist, lin)
         d, li = linear_solve(J, -F, k)
         lin.append(li)
         T = T + d
         F, J = assemble(P, T, T_old, dt)
         hist.append(float(np.linalg.norm(F)))
-    return NewtonResult(T, maxit, hist[-1] <= rtol * f0, hist, lin)
+    return NewtonResult(T, maxit, hist[-1] <= stop, hist, lin)
 
 
 class ReusedPreconditioner:

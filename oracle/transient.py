@@ -16,6 +16,10 @@ Preconditioner reuse (Sec. 5.3: the elastic preconditioner built at the first
 step is reused for the later steps, and the previous solution is the initial
 guess) needs nothing beyond krylov.pcg: the new step's matrix with the old
 hierarchy's V-cycle as M and the previous displacement as u0.
+
+The temperature of each step comes from one backward-Euler step (theta = 1,
+Sec. 5.3) of the heat equation solved by Newton (oracle.thermal), the
+exterior temperatures taken at the step's end time (coupled_step_sequence).
 """
 from __future__ import annotations
 
@@ -64,5 +68,47 @@ def step_sequence(T_of_t, t0, t_end, dt0, dT_max=10.0, eps=0.9, max_steps=10000)
         t += h
         steps.append(Step(t, h, dT, rejected))
         T_old = T_new
+        dt = dt_next
+    return steps
+
+
+@dataclasses.dataclass
+class CoupledStep:
+    t: float              # time at the end of the accepted step
+    dt: float             # its length
+    dT: float             # its largest temperature change
+    rejected: int         # attempts rejected before it
+    T: np.ndarray         # temperature at t
+    newton_iters: int     # Newton corrections of the accepted attempt
+    lin_iters: list       # CG iterations of each correction
+
+
+def coupled_step_sequence(P, T0, T_bc_of_t, linear_solve, t0, t_end, dt0, dT_max=10.0, eps=0.9, max_steps=10000,
+                          newton_kw=None):
+    """The thermal half of a transient run (Sec. 3.2, 3.3, 5.3): each attempt
+    solves one backward-Euler step of eq. wf_thermal by Newton from the
+    previous temperature, with the exterior temperatures of the step's end
+    time (P.T_bc is set to T_bc_of_t(t + h)); eq. dt_spec then accepts it or
+    halves it (next_step).  linear_solve is the Newton correction solver
+    (e.g. thermal.ReusedPreconditioner, kept across attempts and steps)."""
+    from . import thermal
+    steps = []
+    t, dt = float(t0), float(dt0)
+    T_old = np.asarray(T0, np.float64).copy()
+    while t < t_end and len(steps) < max_steps:
+        h = min(dt, t_end - t)
+        rejected = 0
+        while True:
+            P.T_bc = np.asarray(T_bc_of_t(t + h), np.float64)
+            res = thermal.newton(P, T_old, linear_solve, T_old=T_old, dt=h, **(newton_kw or {}))
+            assert res.converged, "thermal Newton did not converge"
+            ok, dt_next, dT = next_step(res.T, T_old, h, dT_max, eps)
+            if ok:
+                break
+            rejected += 1
+            h = dt_next
+        t += h
+        steps.append(CoupledStep(t, h, dT, rejected, res.T, res.iters, res.lin_iters))
+        T_old = res.T
         dt = dt_next
     return steps

@@ -81,7 +81,7 @@ class CamgInfo(C.Structure):
 
 
 class NewtonOptions(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("lin_rtol", C.c_double), ("maxit", C.c_int32), ("lin_maxit", C.c_int32),
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("lin_rtol", C.c_double), ("maxit", C.c_int32),
                 ("rebuild_factor", C.c_double), ("amg", CamgOptions)]
 
 

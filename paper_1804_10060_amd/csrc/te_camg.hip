@@ -648,6 +648,7 @@ extern "C" void camg_options_default(camg_options *o) {
 extern "C" void newton_options_default(newton_options *o) {
     if (!o) return;
     o->rtol = 1e-9;
+    o->atol = 1e-8;
     o->lin_rtol = 1e-8;
     o->maxit = 25;
     o->lin_maxit = 500;
@@ -817,7 +818,7 @@ extern "C" int thermal_newton(thermal_solver *ts, double *T, const double *T_old
         newton_options o;
         newton_options_default(&o);
         if (opt) o = *opt;
-        TE_REQUIRE(o.rtol > 0.0 && o.lin_rtol > 0.0 && o.maxit >= 0 && o.maxit <= 32 && o.lin_maxit >= 1 &&
+        TE_REQUIRE(o.rtol > 0.0 && o.atol >= 0.0 && o.lin_rtol > 0.0 && o.maxit >= 0 && o.maxit <= 32 && o.lin_maxit >= 1 &&
                        o.rebuild_factor >= 1.0,
                    TE_EINVAL, "bad Newton options");
         auto t0 = std::chrono::steady_clock::now();
@@ -858,7 +859,7 @@ extern "C" int thermal_newton(thermal_solver *ts, double *T, const double *T_old
             if (k == 0) f0 = f;
             r.res_hist[k] = f;
             r.res = f;
-            if (f <= o.rtol * f0 || f0 == 0.0) {
+            if (f <= std::max(o.rtol * f0, o.atol) || f0 == 0.0) {
                 r.converged = 1;
                 break;
             }

@@ -244,7 +244,7 @@ class ThermalSolver:
     def reset_preconditioner(self):
         check(load().thermal_reset_preconditioner(self._h))
 
-    def newton(self, T0, T_old=None, dt=0.0, rtol=1e-9, lin_rtol=1e-8, maxit=25, lin_maxit=500,
+    def newton(self, T0, T_old=None, dt=0.0, rtol=1e-9, atol=1e-8, lin_rtol=1e-8, maxit=25, lin_maxit=500,
                rebuild_factor=1.5, allow_notconv=False, **amg_opts):
         """Newton solve of one (steady or backward-Euler) step from T0.
         Returns (T, NewtonReport)."""
@@ -254,7 +254,8 @@ class ThermalSolver:
         T = T0.clone()
         o = _lib.NewtonOptions()
         load().newton_options_default(C.byref(o))
-        o.rtol, o.lin_rtol, o.maxit, o.lin_maxit, o.rebuild_factor = rtol, lin_rtol, maxit, lin_maxit, rebuild_factor
+        o.rtol, o.atol, o.lin_rtol, o.maxit, o.lin_maxit = rtol, atol, lin_rtol, maxit, lin_maxit
+        o.rebuild_factor = rebuild_factor
         for k, v in amg_opts.items():
             if not hasattr(o.amg, k):
                 raise TypeError(f"unknown classical AMG option {k}")

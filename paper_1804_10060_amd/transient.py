@@ -1,5 +1,6 @@
-"""Elastic solves along a temperature history: the loop around the solve in
-a transient run (Sec. 3.3 and Sec. 5.3).
+"""The loop of a transient run (Sec. 3.2, 3.3 and Sec. 5.3): backward-Euler
+heat steps (ThermoelasticTransient) driving elastic solves along the
+temperature history (ElasticTransient).
 
 Each accepted time step assembles the system at the new temperature (with
 temperature-dependent materials the matrix changes), solves it starting from
@@ -9,10 +10,14 @@ stays) or builds a new one.  Steps follow eq. dt_spec through te_timestep:
 the next step targets a largest temperature change of eps * dT_max, and a
 step whose change exceeds dT_max is repeated with half the length.
 
-The temperature at each time comes from the caller (`T_of_t`), since the
-thermal solve that produces it in the paper is not part of this package.
-Every step of the computation runs in the library; this module only orders
-the calls.
+ElasticTransient takes the temperature at each time from the caller
+(`T_of_t`); ThermoelasticTransient computes it: every attempted step is one
+backward-Euler step of the heat equation (eq. wf_thermal, theta = 1) solved
+by Newton from the previous temperature with the exterior temperatures of
+the step's end time, the thermal preconditioner kept across steps and
+rebuilt by the library when a step's corrections need clearly more CG
+iterations (the steps of rapid change, Sec. 5.3).  Every step of the
+computation runs in the library; this module only orders the calls.
 """
 from __future__ import annotations
 
@@ -105,3 +110,69 @@ class ElasticTransient:
         if self.h is not None:
             self.h.close()
             self.h = None
+
+
+@dataclasses.dataclass
+class CoupledRecord:
+    t: float
+    dt: float
+    max_change: float
+    rejected: int
+    newton_iters: int       # Newton corrections of the accepted attempt
+    lin_iters: list         # its CG iterations per correction
+    thermal_rebuilds: int   # thermal preconditioner builds in this step (all attempts)
+    thermal_ms: float       # wall time of the step's thermal solves (all attempts)
+    iters: int              # elastic CG iterations
+    relres_true: float
+    setup: bool
+    assemble_ms: float
+    operator_ms: float
+    solve_ms: float
+
+
+class ThermoelasticTransient:
+    """Heat steps driving the elastic solves of one mesh (Sec. 3.2: the
+    thermal problem first, then the mechanical one at the new temperature).
+    thermal: heat.ThermalSolver; elastic: ElasticTransient on the same mesh
+    and node numbering; T_bc_of_t(t) -> device [n_faces] exterior
+    temperatures; face_p_of_t(t) -> device [n_pressure_faces] or None (fixed
+    pressure)."""
+
+    def __init__(self, thermal, elastic: ElasticTransient, T_bc_of_t, face_p_of_t=None, **newton_kw):
+        self.thermal, self.elastic = thermal, elastic
+        self.T_bc_of_t, self.face_p_of_t = T_bc_of_t, face_p_of_t
+        self.newton_kw = newton_kw
+
+    def _elastic(self, t, T):
+        if self.face_p_of_t is not None:
+            self.elastic.kw["face_p"] = self.face_p_of_t(t)
+        return self.elastic.solve_at(T)
+
+    def run(self, T0, t0, t_end, dt0, dT_max=10.0, eps=0.9, max_steps=None):
+        """The elastic state at t0 (temperature T0), then accepted steps to
+        t_end (the last one cut to end there) or max_steps of them.  Returns
+        (records, T) with the first record for t0."""
+        t, dt = float(t0), float(dt0)
+        T_old = T0.clone()
+        u, rep, built, ta, to, ts = self._elastic(t, T_old)
+        recs = [CoupledRecord(t, 0.0, 0.0, 0, 0, [], 0, 0.0, rep.iters[0], rep.relres_true[0], built, ta, to, ts)]
+        while t < t_end and (max_steps is None or len(recs) <= max_steps):
+            h = min(dt, t_end - t)
+            rejected, rebuilds, th_ms = 0, 0, 0.0
+            while True:
+                self.thermal.set_exterior(self.T_bc_of_t(t + h))
+                T_new, nrep = self.thermal.newton(T_old, T_old=T_old, dt=h, **self.newton_kw)
+                rebuilds += nrep.rebuilds
+                th_ms += nrep.time_ms
+                ok, dt_next, dT = timestep(T_new, T_old, h, dT_max, eps)
+                if ok:
+                    break
+                rejected += 1
+                h = dt_next
+            t += h
+            u, rep, built, ta, to, ts = self._elastic(t, T_new)
+            recs.append(CoupledRecord(t, h, dT, rejected, nrep.iters, nrep.lin_iters, rebuilds, th_ms, rep.iters[0],
+                                      rep.relres_true[0], built, ta, to, ts))
+            T_old = T_new
+            dt = dt_next
+        return recs, T_old

@@ -194,3 +194,69 @@ def test_reused_hierarchy_with_mixed_precision_and_block_cg():
     for j in range(3):
         assert np.linalg.norm(Bh[:, j] - Abo @ Uh[:, j]) <= 1.0000001e-8 * np.linalg.norm(Bh[:, j]) + \
             1e-12 * np.linalg.norm(Bh[:, j]), f"column {j}"
+
+
+def test_coupled_heat_and_elastic_steps_match_oracle():
+    """Backward-Euler heat steps from 293 K (Sec. 5.3) with exterior
+    temperatures and pressures ramping in time, each followed by the elastic
+    solve at the new temperature on the reused hierarchy: the step times,
+    lengths and rejections of eq. dt_spec, the temperatures and the
+    displacements against the oracle running the same sequence (the
+    thermal preconditioner kept and rebuilt by the same rule)."""
+    from oracle import camg, thermal
+    from paper_1804_10060_amd import heat
+    from paper_1804_10060_amd import transient as gt
+    torch = torch_cuda()
+    prob = mg.disc_problem(6, 26, 2, 2, seed=2)
+    prob.T_ref = 293.0
+    m = prob.mesh
+    mat, faces, p = _materials_setup(prob)
+    tm = mg.disc_thermal_materials(m)
+    rb = mg.disc_robin_faces(m)
+    P = thermal.problem_from_meshgen(m, tm, rb)
+    ramp = lambda t: min(1.0, t / 600.0)  # noqa: E731
+    Tbc_np = lambda t: 293.0 + (rb.T_bc - 293.0) * ramp(t)  # noqa: E731
+    p_np = lambda t: p * ramp(t)  # noqa: E731
+    d_coords, d_cells = dev(m.coords, torch.float64), dev(m.cells.astype(np.int32))
+    ts = heat.ThermalSolver(d_coords, d_cells, 2, heat.Tables.of(tm), dev(tm.cell_material.astype(np.int32)),
+                            dev(rb.faces.astype(np.int32)), dev(rb.h, torch.float64), dev(rb.T_bc, torch.float64))
+    el = gt.ElasticTransient(d_coords, d_cells, 2, (mat.T, mat.E, mat.nu, mat.alpha),
+                             dev(mat.cell_material.astype(np.int32)), prob.T_ref, dev(prob.mask),
+                             faces=dev(faces.astype(np.int32)), face_p=dev(p_np(0.0), torch.float64), coarse_max=400)
+    us = []
+    orig = el.solve_at
+
+    def keep(T):
+        out = orig(T)
+        us.append(out[0].cpu().numpy())
+        return out
+
+    el.solve_at = keep
+    run = gt.ThermoelasticTransient(ts, el, lambda t: dev(Tbc_np(t), torch.float64),
+                                    lambda t: dev(p_np(t), torch.float64), coarse_max=200, block=64)
+    recs, _ = run.run(dev(np.full(m.n_nodes, 293.0), torch.float64), 0.0, 1e9, 200.0, max_steps=4)
+    el.close()
+    pre = thermal.ReusedPreconditioner(camg.CAMGOptions(coarse_max=200, block=64))
+    ref = transient.coupled_step_sequence(P, np.full(m.n_nodes, 293.0), Tbc_np, pre, 0.0, 1e9, 200.0, max_steps=4)
+    say("coupled", [(round(r.t, 3), round(r.dt, 3), r.rejected, r.newton_iters, r.iters) for r in recs[1:]])
+    say("oracle ", [(round(o.t, 3), round(o.dt, 3), o.rejected, o.newton_iters) for o in ref])
+    assert len(recs) == 5 and recs[1].rejected >= 1
+    # the same decisions; the times agree to the rounding of the largest change
+    for r, o in zip(recs[1:], ref):
+        assert r.rejected == o.rejected and r.newton_iters == o.newton_iters
+        assert abs(r.t - o.t) <= 1e-9 * o.t and abs(r.max_change - o.dT) <= 1e-9 * o.dT
+    # displacements: the oracle's elastic solve on its own assembly at its
+    # own temperature, on the hierarchy of the first step, from the previous
+    # displacement
+    opt = amg.AMGOptions(coarse_max=400)
+    A0, b0 = _oracle_system(prob, mat, faces, p_np(0.0), np.full(m.n_nodes, 293.0))
+    lv = amg.setup(A0, fem.rigid_body_modes(m.coords, prob.mask), opt)
+    M = lambda r: amg.vcycle(lv, r, opt=opt)  # noqa: E731
+    u_prev = np.zeros(3 * m.n_nodes)
+    assert np.abs(us[0]).max() == 0.0       # stress-free start: T = T_ref, no pressure
+    for k, o in enumerate(ref):
+        A, b = _oracle_system(prob, mat, faces, p_np(o.t), o.T)
+        res = krylov.pcg(A, b, M, u0=u_prev)
+        assert abs(recs[k + 1].iters - res.iters) <= 1
+        assert np.linalg.norm(us[k + 1] - res.u) <= 1e-7 * np.linalg.norm(res.u), f"step {k}"
+        u_prev = res.u

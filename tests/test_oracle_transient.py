@@ -90,3 +90,35 @@ def test_reused_hierarchy_solves_the_changed_system():
     assert res.converged and np.linalg.norm(bb - Ab @ res.u) <= 1e-8 * np.linalg.norm(bb)
     assert np.linalg.norm(res.u - direct) <= 1e-6 * np.linalg.norm(direct)
     assert np.linalg.norm(bb - Ab @ ua) < np.linalg.norm(bb)
+
+
+def test_coupled_heat_steps_respect_the_limit_and_reach_the_steady_state():
+    """Backward-Euler heat steps from 293 K with fixed exterior temperatures:
+    every accepted step changes T by at most dT_max, the decisions follow
+    next_step, a too-long first attempt is halved, and the temperature
+    tends to the steady Newton solution of the same problem (the fixed point
+    of the backward-Euler map is the steady solution)."""
+    import scipy.sparse.linalg as spla
+
+    from oracle import thermal
+    m = mg.disc_mesh(3, 12, 2, 1)
+    P = thermal.problem_from_meshgen(m, mg.disc_thermal_materials(m), mg.disc_robin_faces(m))
+    Tbc = P.T_bc.copy()
+    direct = lambda J, r, k: (spla.spsolve(J.tocsc(), r), 1)  # noqa: E731
+    steps = transient.coupled_step_sequence(P, np.full(m.n_nodes, 293.0), lambda t: Tbc, direct, 0.0, 1e7, 50.0,
+                                            dT_max=10.0, eps=0.9, max_steps=400)
+    assert steps[0].rejected >= 1
+    T_prev = np.full(m.n_nodes, 293.0)
+    for s in steps:
+        assert s.dT <= 10.0 and s.dT == float(np.abs(s.T - T_prev).max())
+        T_prev = s.T
+    # each step's length: the previous step's next length (eq. dt_spec), cut to
+    # t_end, halved once per rejected attempt
+    dt_next, t = 50.0, 0.0
+    for s_ in steps:
+        assert s_.dt == min(dt_next, 1e7 - t) / 2 ** s_.rejected
+        dt_next = 2.0 * s_.dt if s_.dT == 0.0 else 0.9 * 10.0 / s_.dT * s_.dt
+        t = s_.t
+    P.T_bc = Tbc
+    steady = thermal.newton(P, np.full(m.n_nodes, 400.0), direct)
+    assert np.abs(steps[-1].T - steady.T).max() <= 1e-6 * np.abs(steady.T).max()
