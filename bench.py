@@ -171,6 +171,47 @@ def block_rhs_form(te, torch, dev):
     return out
 
 
+def thermal_form(torch, dev, elastic_ms):
+    """The steady thermal solve of the same disc (P2, 4,014,400 nodes; hub,
+    web and rim thermal tables; heat exchange on every boundary face): Newton
+    from 400 K to relative residual 1e-9 with CG and classical AMG (Sec. 5.1,
+    5.2), timed beside the elastic solve, against the stored oracle
+    temperature."""
+    import numpy as np
+
+    import meshgen as mg
+    from paper_1804_10060_amd import heat
+    from tests import golden_c2
+    m = mg.disc_mesh(*mg.DISC_P2_12M)
+    tm = mg.disc_thermal_materials(m)
+    rb = mg.disc_robin_faces(m)
+    ts = heat.ThermalSolver(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.cells).to(dev), 2,
+                            heat.Tables.of(tm), torch.from_numpy(tm.cell_material.astype(np.int32)).to(dev),
+                            torch.from_numpy(rb.faces).to(dev), torch.from_numpy(rb.h).to(dev),
+                            torch.from_numpy(rb.T_bc).to(dev))
+    T0 = torch.full((m.n_nodes,), 400.0, dtype=torch.float64, device=dev)
+    ts.newton(T0)                      # warm-up (builds its preconditioner)
+    ts.reset_preconditioner()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T, rep = ts.newton(T0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"workload": f"steady heat equation on the P2 disc 96x416x12, {m.n_nodes} thermal DOF, 3 materials, "
+                       f"{rb.faces.shape[0]} heat-exchange faces; Newton from 400 K to relres 1e-9, CG + classical "
+                       f"AMG", "ms": round(wall * 1e3, 2), "newton_iters": rep.iters, "lin_iters": rep.lin_iters,
+           "assembly_ms": round(rep.assembly_ms, 2), "amg_setup_ms": round(rep.setup_ms, 2),
+           "cg_ms": round(rep.solve_ms, 2), "dof_per_s": m.n_nodes / wall,
+           "share_of_thermal_plus_elastic": round(wall * 1e3 / (wall * 1e3 + elastic_ms), 3)}
+    if os.path.exists(golden_c2.THERMAL_PATH):
+        g = golden_c2.load(golden_c2.THERMAL_PATH)
+        es, ep = golden_c2.errors(T.cpu().numpy(), g)
+        out["err_vs_oracle"] = {"sampled": es, "projected": ep, "newton_iters": rep.iters,
+                                "oracle_newton_iters": g["iters"], "oracle_lin_iters": g["lin_iters"]}
+    log(f"thermal: {wall * 1e3:.1f} ms, Newton {rep.iters}, CG {rep.lin_iters}; {out.get('err_vs_oracle')}")
+    return out
+
+
 def multi_mesh_form(te, torch, dev):
     """32 P1 discs (DOF log-uniform in [1e4, 5e5], bump fields of seeds
     2000-2031) in one persistent graph-replayed launch sequence against 32
@@ -232,7 +273,7 @@ def main():
                     help="only the full CPU protocol: the oracle on the headline disc with all cores (median of 3) "
                          "and with one thread on the 1/8 disc; prints one JSON line")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the mixed-precision, 64-load-case and 32-mesh forms")
+                    help="skip the mixed-precision, thermal, 64-load-case and 32-mesh forms")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch configurations")
     ap.add_argument("--coarse-sym", type=int, default=1, choices=(0, 1),
                     help="store the coarse operators by their upper triangle (amg_options.coarse_sym)")
@@ -387,6 +428,7 @@ def main():
             es, ep = golden_c2.errors(um.cpu().numpy(), golden)
             forms["mixed_fp32_vcycle"]["err_vs_oracle"] = {"sampled": es, "projected": ep}
         log(f"mixed: {repm.iters[0]} it, {repm.time_ms:.1f} ms, diff vs fp64 {diff:.2e}")
+        forms["thermal_steady"] = thermal_form(torch, dev, ms_per_step)
         forms["block_rhs_64"] = block_rhs_form(te, torch, dev)
         forms["multi_mesh_32"] = multi_mesh_form(te, torch, dev)
 

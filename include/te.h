@@ -484,7 +484,7 @@ typedef struct {
     int32_t coarse_max;      /* (500)                                           */
     int32_t max_levels;      /* (10)                                            */
     double max_coarse_ratio; /* (0.9)                                           */
-    int32_t block;           /* rows per Gauss-Seidel block, 1..1024 (128)      */
+    int32_t block;           /* rows per Gauss-Seidel block, 1..256 (128)       */
 } camg_options;
 void camg_options_default(camg_options *opt);
 

@@ -17,9 +17,10 @@
 //   A_c = R (A P) with the device sparse products of the smoothed-aggregation
 //   setup (1x1 blocks), R = P^T; the coarsest level as an explicit inverse.
 // Solve: the l1 hybrid Gauss-Seidel sweep is two kernels, the out-of-block
-// part of every row in parallel (k_hgs_out, Jacobi across blocks) and one wave
-// per block running its rows in order from an LDS copy of the block's values
-// (k_hgs_seq, Gauss-Seidel inside).  Products one thread per row.
+// part of every row in parallel (k_csr mode 3, Jacobi across blocks) and one
+// wave per block running its rows in order from LDS, the block's entries
+// streamed through two LDS buffers (k_hgs_seq, Gauss-Seidel inside).
+// Products RG lanes per row.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,7 +35,7 @@ namespace te {
 namespace {
 
 constexpr int TB = 256;
-constexpr int MAX_BLOCK = 1024;
+constexpr int MAX_BLOCK = 256;
 constexpr int8_t PT_F = 0, PT_U = 1, PT_C = 2;
 
 unsigned grid1(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + TB - 1) / TB, 1 << 20)); }
@@ -47,16 +48,31 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
-// y = A x (mode 0), y = g - A x (mode 1), y += A x (mode 2)
+// Scalar products, RG lanes per row (coalesced loads of the row's entries,
+// the partial sums of a row's lanes added by a fixed shuffle tree):
+//   mode 0: y = A x; 1: y = g - A x; 2: y += A x;
+//   3: y = g - (sum over columns outside row i's block of B rows of a_ij x_j)
+//      (the Jacobi part of the hybrid Gauss-Seidel sweep)
+constexpr int RG = 8;
+
 __global__ void __launch_bounds__(TB) k_csr(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                             const double *__restrict__ val, const double *__restrict__ x, double *y,
-                                            const double *g, int mode) {
-    for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+                                            const double *g, int mode, int B) {
+    const int sub = threadIdx.x % RG;
+    const int64_t stride = (int64_t)gridDim.x * (TB / RG);
+    for (int64_t i = blockIdx.x * (int64_t)(TB / RG) + threadIdx.x / RG; i < n; i += stride) {
         double t = 0.0;
-        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) t += val[k] * x[col[k]];
-        if (mode == 0) y[i] = t;
-        else if (mode == 1) y[i] = g[i] - t;
-        else y[i] += t;
+        const int64_t bi = mode == 3 ? i / B : 0;
+        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += RG) {
+            const int32_t c = col[k];
+            if (mode != 3 || c / B != bi) t += val[k] * x[c];
+        }
+        for (int o = RG / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, RG);
+        if (sub == 0) {
+            if (mode == 0) y[i] = t;
+            else if (mode == 2) y[i] += t;
+            else y[i] = g[i] - t;
+        }
     }
 }
 
@@ -219,44 +235,104 @@ __global__ void __launch_bounds__(TB) k_dl1(int64_t n, const int64_t *__restrict
     }
 }
 
-// o_i = g_i - sum over columns outside row i's block of a_ij x_j
-__global__ void __launch_bounds__(TB) k_hgs_out(int64_t n, const int64_t *__restrict__ ptr,
-                                                const int32_t *__restrict__ col, const double *__restrict__ val, int B,
-                                                const double *__restrict__ g, const double *__restrict__ x,
-                                                double *__restrict__ o) {
-    for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
-        double t = 0.0;
-        const int64_t bi = i / B;
-        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
-            if (col[k] / B != bi) t += val[k] * x[col[k]];
-        o[i] = g[i] - t;
-    }
-}
-
 // one wave per block of B rows: Gauss-Seidel over the block's rows in order
-// (ascending or descending) on an LDS copy of its values; entries outside the
-// block are in o
+// (ascending or descending); entries outside the block are in o.  The
+// block's x, o and l1 diagonal sit in LDS; its entries (contiguous in the
+// arrays) stream through two LDS buffers in groups of GRP rows: while the
+// rows of one group run (LDS reads and a wave reduction per row, the
+// sequential part), the loads of the next group are in flight.  A group with
+// more than GCAP entries reads global memory.
+constexpr int GRP = 16;
+constexpr int GCAP = 768;
+constexpr int GPL = GCAP / 64;   // entries per lane of one group
+
 __global__ void __launch_bounds__(64) k_hgs_seq(int64_t n, const int64_t *__restrict__ ptr,
                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
                                                 const double *__restrict__ dl1, const double *__restrict__ o,
                                                 const double *__restrict__ x_in, double *__restrict__ x_out, int B,
                                                 int forward) {
-    __shared__ double xb[MAX_BLOCK];
+    __shared__ double xb[MAX_BLOCK], ob[MAX_BLOCK], db[MAX_BLOCK];
+    __shared__ int32_t rp[MAX_BLOCK + 1];
+    __shared__ double bv[2][GCAP];
+    __shared__ int16_t bc[2][GCAP];
     const int lane = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * B;
     const int nb = (int)min<int64_t>(B, n - b0);
-    for (int r = lane; r < nb; r += 64) xb[r] = x_in ? x_in[b0 + r] : 0.0;
+    const int64_t e0 = ptr[b0];
+    for (int r = lane; r < nb; r += 64) {
+        xb[r] = x_in ? x_in[b0 + r] : 0.0;
+        ob[r] = o[b0 + r];
+        db[r] = dl1[b0 + r];
+    }
+    for (int r = lane; r <= nb; r += 64) rp[r] = (int32_t)(ptr[b0 + r] - e0);
     __syncthreads();
-    for (int t = 0; t < nb; ++t) {
-        const int r = forward ? t : nb - 1 - t;
-        const int64_t i = b0 + r;
-        double sum = 0.0;
-        for (int64_t k = ptr[i] + lane; k < ptr[i + 1]; k += 64) {
-            const int64_t j = col[k] - b0;
-            if (j >= 0 && j < nb) sum += val[k] * xb[j];
+    const int ng = (nb + GRP - 1) / GRP;
+    // group q (in processing order) covers rows [lo, hi)
+    auto rows_of = [&](int q, int &lo, int &hi) {
+        const int g = forward ? q : ng - 1 - q;
+        lo = g * GRP;
+        hi = min(nb, lo + GRP);
+    };
+    double pv[GPL];
+    int16_t pc[GPL];
+    auto fetch = [&](int q) {
+        int lo, hi;
+        rows_of(q, lo, hi);
+        const int k0 = rp[lo], ne = rp[hi] - k0;
+#pragma unroll
+        for (int u = 0; u < GPL; ++u) {
+            const int k = u * 64 + lane;
+            if (ne <= GCAP && k < ne) {
+                const int64_t j = col[e0 + k0 + k] - b0;
+                pc[u] = (j >= 0 && j < nb) ? (int16_t)j : (int16_t)-1;
+                pv[u] = val[e0 + k0 + k];
+            }
         }
-        sum = wave_sum(sum);
-        if (lane == 0) xb[r] += (o[i] - sum) / dl1[i];
+    };
+    auto store = [&](int q, int buf) {
+        int lo, hi;
+        rows_of(q, lo, hi);
+        const int ne = rp[hi] - rp[lo];
+#pragma unroll
+        for (int u = 0; u < GPL; ++u) {
+            const int k = u * 64 + lane;
+            if (ne <= GCAP && k < ne) {
+                bc[buf][k] = pc[u];
+                bv[buf][k] = pv[u];
+            }
+        }
+    };
+    if (ng > 0) {
+        fetch(0);
+        store(0, 0);
+    }
+    __syncthreads();
+    for (int q = 0; q < ng; ++q) {
+        const int buf = q & 1;
+        if (q + 1 < ng) fetch(q + 1);
+        int lo, hi;
+        rows_of(q, lo, hi);
+        const int k0 = rp[lo];
+        const bool staged = rp[hi] - k0 <= GCAP;
+        for (int t = 0; t < hi - lo; ++t) {
+            const int r = forward ? lo + t : hi - 1 - t;
+            double sum = 0.0;
+            if (staged) {
+                for (int k = rp[r] - k0 + lane; k < rp[r + 1] - k0; k += 64) {
+                    const int j = bc[buf][k];
+                    if (j >= 0) sum += bv[buf][k] * xb[j];
+                }
+            } else {
+                for (int64_t k = e0 + rp[r] + lane; k < e0 + rp[r + 1]; k += 64) {
+                    const int64_t j = col[k] - b0;
+                    if (j >= 0 && j < nb) sum += val[k] * xb[j];
+                }
+            }
+            sum = wave_sum(sum);
+            if (lane == 0) xb[r] += (ob[r] - sum) / db[r];
+            __syncthreads();
+        }
+        if (q + 1 < ng) store(q + 1, buf ^ 1);
         __syncthreads();
     }
     for (int r = lane; r < nb; r += 64) x_out[b0 + r] = xb[r];
@@ -299,9 +375,13 @@ struct camg_handle {
 namespace te {
 namespace {
 
-void csr_apply(const DBsr &A, const double *x, double *y, const double *g, int mode, hipStream_t s) {
+unsigned grid_rows(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + TB / RG - 1) / (TB / RG), 1 << 20));
+}
+
+void csr_apply(const DBsr &A, const double *x, double *y, const double *g, int mode, hipStream_t s, int B = 1) {
     if (A.nr == 0) return;
-    hipLaunchKernelGGL(k_csr, dim3(grid1(A.nr)), dim3(TB), 0, s, A.nr, A.ptr, A.col, A.val, x, y, g, mode);
+    hipLaunchKernelGGL(k_csr, dim3(grid_rows(A.nr)), dim3(TB), 0, s, A.nr, A.ptr, A.col, A.val, x, y, g, mode, B);
     TE_CHECK_HIP(hipGetLastError());
 }
 
@@ -326,14 +406,12 @@ void sweep(camg_handle *h, CLv &L, const double *g, const double *x_in, double *
     const int B = h->opt.block;
     const double *o = g;
     if (x_in) {
-        hipLaunchKernelGGL(k_hgs_out, dim3(grid1(L.n)), dim3(TB), 0, s, L.n, L.A.ptr, L.A.col, L.A.val, B, g, x_in,
-                           L.o.p);
-        TE_CHECK_HIP(hipGetLastError());
+        csr_apply(L.A, x_in, L.o.p, g, 3, s, B);
         o = L.o.p;
     }
     const unsigned nb = (unsigned)((L.n + B - 1) / B);
-    hipLaunchKernelGGL(k_hgs_seq, dim3(nb), dim3(64), 0, s, L.n, L.A.ptr, L.A.col, L.A.val, L.dl1.p, o, x_in, x_out, B,
-                       forward ? 1 : 0);
+    hipLaunchKernelGGL(k_hgs_seq, dim3(nb), dim3(64), 0, s, L.n, L.A.ptr, L.A.col, L.A.val, L.dl1.p, o, x_in, x_out,
+                       B, forward ? 1 : 0);
     TE_CHECK_HIP(hipGetLastError());
 }
 

@@ -23,6 +23,9 @@ def load_case_path(seed):
     return os.path.join(GOLDEN, f"disc_p1_2m_case{seed}_oracle.txt")
 
 
+# the steady thermal solve of the P2 disc 96 x 416 x 12 (4,014,400 nodes)
+THERMAL_PATH = os.path.join(GOLDEN, "thermal_disc_p2_4m_oracle.txt")
+
 # the 32-mesh form: the smallest and the largest of meshgen.multi_mesh_sizes(32)
 MULTI_MESH_INDICES = (27, 25)
 
@@ -55,6 +58,10 @@ def load(path=PATH):
                 continue
             if t[0] == "iters":
                 g["iters"] = int(t[1])
+            elif t[0] == "lin_iters":
+                g["lin_iters"] = [int(x) for x in t[1:]]
+            elif t[0] == "res_history":
+                g["res_history"] = [float(x) for x in t[1:]]
             elif t[0] in ("relres", "norm2"):
                 g[t[0]] = float(t[1])
             elif t[0] == "level_dof":
