@@ -626,6 +626,7 @@ static void alloc_work(amg_handle *h, hipStream_t) {
     h->partials.alloc((size_t)np * m * 2 + 64);
     h->sums.alloc(4 * 64);
     h->scal.alloc(cg_scalars_bytes());
+    h->colsel.alloc(64);
 }
 
 int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, const amg_options *opt_in,

@@ -128,6 +128,10 @@ struct amg_handle {
     te::DBuf<double> u, r, r_old, z, p, q, t, b;
     te::DBuf<double> partials, sums;
     te::DBuf<char> scal;
+    te::DBuf<int32_t> colsel;      // [64] column selector of copy_cols
+    // block-CG workspace, allocated by the first block solve and kept:
+    // Gram partials and results, the two small coefficient matrices, X/R partials
+    te::DBuf<double> bgpart, bgout, bsmall, bxpart;
 };
 
 namespace te {

@@ -305,9 +305,15 @@ static int block_solve_impl(amg_handle *h, const double *b_nat, double *u_nat, i
     double *X = h->u.p, *R = h->r.p, *Z = h->z.p, *P = h->p.p, *Q = h->q.p, *B = h->b.p, *Tt = h->t.p;
     permute_gather(b_nat, B, L0.perm.p, n, 3, m, s);
     permute_gather(u_nat, X, L0.perm.p, n, 3, m, s);
-    DBuf<double> gpart((size_t)block_gram_nblocks() * 3 * BM * BM), gout(3 * BM * BM), smalls(2 * BM * BM);
     const int nxr = block_xr_nblocks(rows);
-    DBuf<double> xpart((size_t)(nxr + 1024) * m);
+    {  // kept in the handle: the sizes depend on the level-0 rows and max_nrhs only
+        const size_t mm = (size_t)h->opt.max_nrhs;
+        if (!h->bgpart.p) h->bgpart.alloc((size_t)block_gram_nblocks() * 3 * BM * BM);
+        if (!h->bgout.p) h->bgout.alloc(3 * BM * BM);
+        if (!h->bsmall.p) h->bsmall.alloc(2 * BM * BM);
+        if (!h->bxpart.p) h->bxpart.alloc((size_t)(nxr + 1024) * mm);
+    }
+    DBuf<double> &gpart = h->bgpart, &gout = h->bgout, &smalls = h->bsmall, &xpart = h->bxpart;
     std::vector<double> bb, rr, tr;
     dot_partials(B, B, nv, m, part, s);
     reduce_partials(part, dot_nblocks(rows), m, sums, s);
@@ -519,10 +525,9 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
         }
     }
     if (any_zero) {  // b = 0 has the solution u = 0 whatever the guess
-        DBuf<int32_t> dsel(64);
-        TE_CHECK_HIP(hipMemcpyAsync(dsel.p, zero_cols.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        TE_CHECK_HIP(hipMemcpyAsync(h->colsel.p, zero_cols.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
         TE_CHECK_HIP(hipMemsetAsync(h->t.p, 0, nv * sizeof(double), s));
-        copy_cols(h->u.p, h->t.p, dsel.p, nv, m, s);
+        copy_cols(h->u.p, h->t.p, h->colsel.p, nv, m, s);
         TE_CHECK_HIP(hipStreamSynchronize(s));
     }
     if (n_active) {
@@ -595,9 +600,8 @@ static int solve_impl(amg_handle *h, const double *b_nat, double *u_nat, int m, 
                 }
             }
             if (any_repl) {
-                DBuf<int32_t> dsel(64);
-                TE_CHECK_HIP(hipMemcpyAsync(dsel.p, repl.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-                copy_cols(h->r.p, h->t.p, dsel.p, nv, m, s);
+                TE_CHECK_HIP(hipMemcpyAsync(h->colsel.p, repl.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+                copy_cols(h->r.p, h->t.p, h->colsel.p, nv, m, s);
                 TE_CHECK_HIP(hipStreamSynchronize(s));
             }
             if (changed)

@@ -1,7 +1,7 @@
 """Measurements of the batched and learned forms against plain float64 PCG-AMG
 on the same GPU, at the same true relative residual 1e-8.
 
-    python -m paper_1804_10060_amd.forms [block|multi|learned|materials|aggregation|transient|all] [--quick]
+    python -m paper_1804_10060_amd.forms [block|multi|learned|materials|aggregation|thermal|transient|all] [--quick]
 
 Prints one JSON object.  Workloads (seeded, synthetic):
   block   : 64 thermal load cases (4-16 Gaussian bumps, U[0,500] K) on the
@@ -19,11 +19,17 @@ Prints one JSON object.  Workloads (seeded, synthetic):
   aggregation: P2 disc 96x416x12: AMG setup and solve with the device MIS-2
             aggregation against the host greedy aggregation, and with the
             prolongator smoothed by the filtered operator;
-  transient: P2 disc 96x416x12 with the three materials and pressure, heated
-            from 293 K toward its operating field (time constant 600 s), 16
-            steps of eq. dt_spec (dT_max 10 K, eps 0.9): the hierarchy of the
-            first step reused with the previous displacement as guess,
-            against a new hierarchy and a zero guess at sampled steps.
+  thermal : P2 disc 96x416x12 (4,014,400 temperature DOF) with the hub, web
+            and rim thermal tables and heat exchange on every boundary face:
+            the steady Newton solve from 400 K (CG + classical AMG);
+  transient: the same disc with the three materials and pressure, starting
+            stress-free at 293 K while the exterior temperatures and the
+            pressures ramp to their operating values over 600 s: 16 accepted
+            steps of eq. dt_spec (dT_max 10 K, eps 0.9), each attempt one
+            backward-Euler heat step by Newton, each accepted step an elastic
+            solve on the first step's hierarchy from the previous
+            displacement; against a new hierarchy and a zero guess at
+            sampled steps.
 """
 from __future__ import annotations
 
@@ -251,17 +257,52 @@ def aggregation_form(quick=False):
     return out
 
 
+def _thermal_solver(torch, dev, m, degree):
+    from paper_1804_10060_amd import heat
+    tm = mg.disc_thermal_materials(m)
+    rb = mg.disc_robin_faces(m)
+    ts = heat.ThermalSolver(torch.from_numpy(m.coords).to(dev), torch.from_numpy(m.cells.astype(np.int32)).to(dev),
+                            degree, heat.Tables.of(tm), torch.from_numpy(tm.cell_material.astype(np.int32)).to(dev),
+                            torch.from_numpy(rb.faces.astype(np.int32)).to(dev), torch.from_numpy(rb.h).to(dev),
+                            torch.from_numpy(rb.T_bc).to(dev))
+    return ts, rb
+
+
+def thermal_form(quick=False):
+    """The steady heat equation of the disc by Newton from 400 K (Sec. 5.2):
+    a warm-up solve, then the timed solve with a fresh preconditioner."""
+    torch = _torch()
+    grid = (24, 104, 3, 2) if quick else mg.DISC_P2_12M
+    m = mg.disc_mesh(*grid)
+    dev = torch.device("cuda:0")
+    ts, rb = _thermal_solver(torch, dev, m, grid[3])
+    T0 = torch.full((m.n_nodes,), 400.0, dtype=torch.float64, device=dev)
+    ts.newton(T0)
+    ts.reset_preconditioner()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T, rep = ts.newton(T0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"workload": f"steady heat equation, P2 disc {grid[0]}x{grid[1]}x{grid[2]}, {m.n_nodes} DOF, "
+                       f"{rb.faces.shape[0]} exchange faces", "ms": wall * 1e3, "newton_iters": rep.iters,
+           "lin_iters": rep.lin_iters, "assembly_ms": rep.assembly_ms, "setup_ms": rep.setup_ms,
+           "cg_ms": rep.solve_ms, "res_history": rep.res_history, "T_min": float(T.min()), "T_max": float(T.max())}
+    log(json.dumps(out))
+    return out
+
+
 def transient_form(quick=False):
-    """Elastic steps along a heating history with the first step's hierarchy
-    reused (amg_set_operator, previous displacement as guess), against a new
-    hierarchy per step from a zero guess at sampled steps."""
-    import math
-    import paper_1804_10060_amd as te
+    """Backward-Euler heat steps driving the elastic solves (the loop of a
+    transient run, Sec. 3.3 and 5.3), the elastic hierarchy of the first step
+    reused with the previous displacement as guess, against a new hierarchy
+    per step from a zero guess at sampled steps."""
     from paper_1804_10060_amd import transient
     torch = _torch()
     grid = (24, 104, 3, 2) if quick else mg.DISC_P2_12M
     nsteps = 6 if quick else 16
     prob = mg.disc_problem(*grid, seed=0)
+    prob.T_ref = 293.0
     m = prob.mesh
     dev = torch.device("cuda:0")
     mat = mg.disc_materials(m)
@@ -271,35 +312,63 @@ def transient_form(quick=False):
     mask = torch.from_numpy(prob.mask).to(dev)
     cm = torch.from_numpy(mat.cell_material).to(dev)
     tables = (mat.T, mat.E, mat.nu, mat.alpha)
-    Top = torch.from_numpy(prob.T).to(dev)
-    tau, T0 = 600.0, 293.0
+    ts, rb = _thermal_solver(torch, dev, m, grid[3])
+    T_bc = torch.from_numpy(rb.T_bc).to(dev)
+    p_d = torch.from_numpy(p).to(dev)
+    ramp_s, T0 = 600.0, 293.0
 
-    def T_of_t(t):
-        return (T0 + (Top - T0) * (1.0 - math.exp(-t / tau))).contiguous()
+    def ramp(t):
+        return min(1.0, t / ramp_s)
 
-    run = transient.ElasticTransient(c, cl, grid[3], tables, cm, prob.T_ref, mask,
-                                     faces=torch.from_numpy(faces).to(dev), face_p=torch.from_numpy(p).to(dev))
-    recs = run.run(T_of_t, 0.0, 1e9, 1.0, dT_max=10.0, eps=0.9, max_steps=nsteps)
-    run.close()
-    # sampled steps again with a new hierarchy each and a zero guess
+    def T_bc_of_t(t):
+        return (T0 + (T_bc - T0) * ramp(t)).contiguous()
+
+    def p_of_t(t):
+        return (p_d * ramp(t)).contiguous()
+
+    def elastic():
+        return transient.ElasticTransient(c, cl, grid[3], tables, cm, prob.T_ref, mask,
+                                          faces=torch.from_numpy(faces).to(dev), face_p=p_of_t(0.0))
+
+    el = elastic()
+    # the temperatures of sampled steps, kept for the comparison below
+    keep_at = sorted({1, nsteps // 2, nsteps})
+    temps, count, orig = {}, [0], el.solve_at
+
+    def capture(T):
+        if count[0] in keep_at:
+            temps[count[0]] = T.clone()
+        count[0] += 1
+        return orig(T)
+
+    el.solve_at = capture
+    run = transient.ThermoelasticTransient(ts, el, T_bc_of_t, p_of_t)
+    Tstart = torch.full((m.n_nodes,), T0, dtype=torch.float64, device=dev)
+    recs, _ = run.run(Tstart, 0.0, 1e9, 10.0, dT_max=10.0, eps=0.9, max_steps=nsteps)
+    el.close()
     fresh = {}
-    for k in sorted({1, nsteps // 2, nsteps}):
-        r = transient.ElasticTransient(c, cl, grid[3], tables, cm, prob.T_ref, mask,
-                                       faces=torch.from_numpy(faces).to(dev), face_p=torch.from_numpy(p).to(dev))
-        u, rep, built, ta, to, ts = r.solve_at(T_of_t(recs[k].t))
-        fresh[k] = {"iters": rep.iters[0], "assemble_ms": ta, "setup_ms": to, "solve_ms": ts}
+    for k, T in temps.items():
+        r = elastic()
+        r.kw["face_p"] = p_of_t(recs[k].t)
+        u, rep, built, ta, to, tsol = r.solve_at(T)
+        fresh[k] = {"iters": rep.iters[0], "assemble_ms": ta, "setup_ms": to, "solve_ms": tsol}
         r.close()
     steps = [dataclasses.asdict(s) for s in recs]
     later = recs[1:]
-    reuse_ms = [s.assemble_ms + s.operator_ms + s.solve_ms for s in later]
+    elastic_ms = [s.assemble_ms + s.operator_ms + s.solve_ms for s in later]
+    thermal_ms = [s.thermal_ms for s in later]
     fresh_ms = [v["assemble_ms"] + v["setup_ms"] + v["solve_ms"] for v in fresh.values()]
-    out = {"workload": f"P2 disc {grid[0]}x{grid[1]}x{grid[2]}, {m.n_dof} DOF, 3 materials + pressure, heating "
-                       f"293 K -> operating field (tau {tau:.0f} s), dT_max 10 K, eps 0.9",
-           "n_dof": m.n_dof, "steps": steps,
-           "reuse_step_ms_mean": float(np.mean(reuse_ms)), "reuse_iters_mean": float(np.mean([s.iters for s in later])),
-           "fresh_sampled": fresh, "fresh_step_ms_mean": float(np.mean(fresh_ms)),
-           "all_converged": bool(all(s.relres_true <= 1e-8 for s in recs)),
-           "rejected_total": int(sum(s.rejected for s in recs))}
+    out = {"workload": f"P2 disc {grid[0]}x{grid[1]}x{grid[2]}, {m.n_dof} elastic + {m.n_nodes} thermal DOF, 3 "
+                       f"materials, exterior temperatures and pressures ramped over {ramp_s:.0f} s from a "
+                       f"stress-free 293 K, dT_max 10 K, eps 0.9",
+           "steps": steps, "t_end": recs[-1].t,
+           "thermal_step_ms_mean": float(np.mean(thermal_ms)), "elastic_step_ms_mean": float(np.mean(elastic_ms)),
+           "thermal_share": float(np.sum(thermal_ms) / (np.sum(thermal_ms) + np.sum(elastic_ms))),
+           "elastic_iters_mean": float(np.mean([s.iters for s in later])),
+           "thermal_rebuilds": int(sum(s.thermal_rebuilds for s in later)),
+           "rejected_total": int(sum(s.rejected for s in later)),
+           "fresh_sampled": fresh, "fresh_elastic_step_ms_mean": float(np.mean(fresh_ms)),
+           "all_converged": bool(all(s.relres_true <= 1e-8 for s in recs))}
     log(json.dumps({k: v for k, v in out.items() if k != "steps"}))
     return out
 
@@ -307,7 +376,7 @@ def transient_form(quick=False):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", nargs="?", default="all", choices=["block", "multi", "learned", "materials", "aggregation",
-                                                               "transient", "all"])
+                                                               "thermal", "transient", "all"])
     ap.add_argument("--quick", action="store_true")
     a = ap.parse_args()
     out = {}
@@ -321,6 +390,8 @@ def main():
         out["materials"] = materials_form(a.quick)
     if a.which in ("aggregation", "all"):
         out["aggregation"] = aggregation_form(a.quick)
+    if a.which in ("thermal", "all"):
+        out["thermal"] = thermal_form(a.quick)
     if a.which in ("transient", "all"):
         out["transient"] = transient_form(a.quick)
     print(json.dumps(out), flush=True)
