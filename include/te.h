@@ -593,12 +593,14 @@ int thermal_destroy(thermal_solver *s);
  * The paper starts each transient elastic solve from the previous step's
  * displacement (Sec. 5.3).  This network maps the load instead:
  *   h0 = relu(X W_in + b_in);  4 layers of
- *   h  = h + relu(h W_s + mean_{N(v)} h W_n + mean_V h W_g + b);
+ *   h  = h + relu(h W_s + mean_{N(v)} h W_n + mean_V h W_g
+ *                 + sum_k (sum_{u in N(v)} w^k_vu h_u) W_dk + b),  k = x, y, z,
+ *        w^k_vu = (x_u - x_v)_k / (deg_v l_v), l_v the mean edge length at v;
  *   y  = (h W_out + b_out) * (1 - mask),  u0 = 1e-3 * y.
  * Features X[v] = [(T-T_ref)/500, f/2e9 (3), mask (3), (x - centroid)/0.5 (3)].
  * Parameters: one float array of mpnn_param_count() entries in the order
- * W_in[10][64], b_in[64], per layer {W_s,W_n,W_g}[64][64], b[64],
- * W_out[64][3], b_out[3] (weights [in][out]). */
+ * W_in[10][64], b_in[64], per layer {W_s,W_n,W_g,W_dx,W_dy,W_dz}[64][64],
+ * b[64], W_out[64][3], b_out[3] (weights [in][out]). */
 typedef struct mpnn_handle mpnn_handle;
 
 int64_t mpnn_param_count(void);
@@ -629,10 +631,13 @@ int mpnn_backward(mpnn_handle *h, const float *params, const float *target, floa
  * [N][3]; entries of constrained DOFs are ignored) into grad. */
 int mpnn_backward_from(mpnn_handle *h, const float *params, const float *gy, float *grad, hipStream_t stream);
 
-/* Energy-norm loss of the last forward's guess, the quantity CG reduces:
- * loss = e^T A e / t^T A t with e = 1e-3 (y - target), t = 1e-3 target and A
+/* Energy-norm loss of the last forward's guess taken at its energy-optimal
+ * multiple (the guess the solve uses, amg_energy_scale):
+ * loss = 1 - (u, A t)^2 / ((u, A u)(t, A t)) = ||g u - t||_A^2 / ||t||_A^2 at
+ * the best g, with u = 1e-3 y (constrained DOFs zero), t = 1e-3 target and A
  * the level-0 operator of `amg` (same mesh); gy [N][3] = dloss/dy (device
- * float).  *loss host, may be NULL.  Uses amg's solve workspace; synchronises. */
+ * float); a zero guess gives loss 1 and gy 0.  *loss host, may be NULL.  Uses
+ * amg's solve workspace; synchronises. */
 int mpnn_energy_grad(mpnn_handle *h, amg_handle *amg, const float *target, float *gy, double *loss,
                      hipStream_t stream);
 

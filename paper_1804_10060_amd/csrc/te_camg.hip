@@ -16,10 +16,10 @@
 //                the row's column order
 //   A_c = R (A P) with the device sparse products of the smoothed-aggregation
 //   setup (1x1 blocks), R = P^T; the coarsest level as an explicit inverse.
-// Solve: the l1 hybrid Gauss-Seidel sweep is two kernels, the out-of-block
-// part of every row in parallel (k_csr mode 3, Jacobi across blocks) and one
-// wave per block running its rows in order from LDS, the block's entries
-// streamed through two LDS buffers (k_hgs_seq, Gauss-Seidel inside).
+// Solve: the l1 hybrid Gauss-Seidel sweep is two kernels, the entries
+// outside each row's block in parallel (a product with that part of A,
+// Jacobi across blocks) and eight blocks per wave running their rows in
+// order (k_hgs8, Gauss-Seidel inside), the two parts split at setup.
 // Products RG lanes per row.
 #include <hip/hip_runtime.h>
 
@@ -48,26 +48,37 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
-// Scalar products, RG lanes per row (coalesced loads of the row's entries,
-// the partial sums of a row's lanes added by a fixed shuffle tree):
-//   mode 0: y = A x; 1: y = g - A x; 2: y += A x;
-//   3: y = g - (sum over columns outside row i's block of B rows of a_ij x_j)
-//      (the Jacobi part of the hybrid Gauss-Seidel sweep)
+// v summed over the eight lanes of each eighth of the wave, the result in
+// all eight: DPP quad permutations [1,0,3,2] and [2,3,0,1], then the
+// half-row mirror (lane i of the eight takes lane 7 - i, in the other quad).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double sum8(double v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    return v;
+}
+
+// Scalar products, RG = 8 lanes per row (coalesced loads of the row's
+// entries, the partial sums of a row's lanes added by sum8):
+//   mode 0: y = A x; 1: y = g - A x; 2: y += A x
 constexpr int RG = 8;
 
 __global__ void __launch_bounds__(TB) k_csr(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                             const double *__restrict__ val, const double *__restrict__ x, double *y,
-                                            const double *g, int mode, int B) {
+                                            const double *g, int mode) {
     const int sub = threadIdx.x % RG;
     const int64_t stride = (int64_t)gridDim.x * (TB / RG);
+    // the eight lanes of a row share its loop trips, and sum8 mixes only them
     for (int64_t i = blockIdx.x * (int64_t)(TB / RG) + threadIdx.x / RG; i < n; i += stride) {
         double t = 0.0;
-        const int64_t bi = mode == 3 ? i / B : 0;
-        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += RG) {
-            const int32_t c = col[k];
-            if (mode != 3 || c / B != bi) t += val[k] * x[c];
-        }
-        for (int o = RG / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, RG);
+        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += RG) t += val[k] * x[col[k]];
+        t = sum8(t);
         if (sub == 0) {
             if (mode == 0) y[i] = t;
             else if (mode == 2) y[i] += t;
@@ -235,107 +246,113 @@ __global__ void __launch_bounds__(TB) k_dl1(int64_t n, const int64_t *__restrict
     }
 }
 
-// one wave per block of B rows: Gauss-Seidel over the block's rows in order
-// (ascending or descending); entries outside the block are in o.  The
-// block's x, o and l1 diagonal sit in LDS; its entries (contiguous in the
-// arrays) stream through two LDS buffers in groups of GRP rows: while the
-// rows of one group run (LDS reads and a wave reduction per row, the
-// sequential part), the loads of the next group are in flight.  A group with
-// more than GCAP entries reads global memory.
-constexpr int GRP = 16;
-constexpr int GCAP = 768;
-constexpr int GPL = GCAP / 64;   // entries per lane of one group
+// The smoother's split of a level matrix into the entries inside each
+// row's block of B consecutive rows (local column as one byte, B <= 256)
+// and the entries outside it, with 1/d of the l1 diagonal: counts, then fill.
+__global__ void __launch_bounds__(TB) k_split_count(int64_t n, const int64_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ col, int B, int32_t *__restrict__ cin,
+                                                    int32_t *__restrict__ cout) {
+    for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+        const int64_t bi = i / B;
+        int a = 0, o = 0;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            if (col[k] / B == bi) ++a;
+            else ++o;
+        }
+        cin[i] = a;
+        cout[i] = o;
+    }
+}
 
-__global__ void __launch_bounds__(64) k_hgs_seq(int64_t n, const int64_t *__restrict__ ptr,
-                                                const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                const double *__restrict__ dl1, const double *__restrict__ o,
-                                                const double *__restrict__ x_in, double *__restrict__ x_out, int B,
-                                                int forward) {
-    __shared__ double xb[MAX_BLOCK], ob[MAX_BLOCK], db[MAX_BLOCK];
-    __shared__ int32_t rp[MAX_BLOCK + 1];
-    __shared__ double bv[2][GCAP];
-    __shared__ int16_t bc[2][GCAP];
-    const int lane = threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * B;
-    const int nb = (int)min<int64_t>(B, n - b0);
-    const int64_t e0 = ptr[b0];
-    for (int r = lane; r < nb; r += 64) {
-        xb[r] = x_in ? x_in[b0 + r] : 0.0;
-        ob[r] = o[b0 + r];
-        db[r] = dl1[b0 + r];
-    }
-    for (int r = lane; r <= nb; r += 64) rp[r] = (int32_t)(ptr[b0 + r] - e0);
-    __syncthreads();
-    const int ng = (nb + GRP - 1) / GRP;
-    // group q (in processing order) covers rows [lo, hi)
-    auto rows_of = [&](int q, int &lo, int &hi) {
-        const int g = forward ? q : ng - 1 - q;
-        lo = g * GRP;
-        hi = min(nb, lo + GRP);
-    };
-    double pv[GPL];
-    int16_t pc[GPL];
-    auto fetch = [&](int q) {
-        int lo, hi;
-        rows_of(q, lo, hi);
-        const int k0 = rp[lo], ne = rp[hi] - k0;
-#pragma unroll
-        for (int u = 0; u < GPL; ++u) {
-            const int k = u * 64 + lane;
-            if (ne <= GCAP && k < ne) {
-                const int64_t j = col[e0 + k0 + k] - b0;
-                pc[u] = (j >= 0 && j < nb) ? (int16_t)j : (int16_t)-1;
-                pv[u] = val[e0 + k0 + k];
-            }
-        }
-    };
-    auto store = [&](int q, int buf) {
-        int lo, hi;
-        rows_of(q, lo, hi);
-        const int ne = rp[hi] - rp[lo];
-#pragma unroll
-        for (int u = 0; u < GPL; ++u) {
-            const int k = u * 64 + lane;
-            if (ne <= GCAP && k < ne) {
-                bc[buf][k] = pc[u];
-                bv[buf][k] = pv[u];
-            }
-        }
-    };
-    if (ng > 0) {
-        fetch(0);
-        store(0, 0);
-    }
-    __syncthreads();
-    for (int q = 0; q < ng; ++q) {
-        const int buf = q & 1;
-        if (q + 1 < ng) fetch(q + 1);
-        int lo, hi;
-        rows_of(q, lo, hi);
-        const int k0 = rp[lo];
-        const bool staged = rp[hi] - k0 <= GCAP;
-        for (int t = 0; t < hi - lo; ++t) {
-            const int r = forward ? lo + t : hi - 1 - t;
-            double sum = 0.0;
-            if (staged) {
-                for (int k = rp[r] - k0 + lane; k < rp[r + 1] - k0; k += 64) {
-                    const int j = bc[buf][k];
-                    if (j >= 0) sum += bv[buf][k] * xb[j];
-                }
+__global__ void __launch_bounds__(TB) k_split_fill(int64_t n, const int64_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   int B, const double *__restrict__ dl1,
+                                                   const int64_t *__restrict__ pin, uint8_t *__restrict__ lin,
+                                                   double *__restrict__ vin, const int64_t *__restrict__ pout,
+                                                   int32_t *__restrict__ cout, double *__restrict__ vout,
+                                                   double *__restrict__ idl) {
+    for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+        const int64_t bi = i / B;
+        int64_t a = pin[i], o = pout[i];
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t c = col[k];
+            if (c / B == bi) {
+                lin[a] = (uint8_t)(c - bi * B);
+                vin[a++] = val[k];
             } else {
-                for (int64_t k = e0 + rp[r] + lane; k < e0 + rp[r + 1]; k += 64) {
-                    const int64_t j = col[k] - b0;
-                    if (j >= 0 && j < nb) sum += val[k] * xb[j];
-                }
+                cout[o] = c;
+                vout[o++] = val[k];
             }
-            sum = wave_sum(sum);
-            if (lane == 0) xb[r] += (ob[r] - sum) / db[r];
-            __syncthreads();
         }
-        if (q + 1 < ng) store(q + 1, buf ^ 1);
+        idl[i] = 1.0 / dl1[i];
+    }
+}
+
+// One l1 hybrid Gauss-Seidel sweep, eight blocks of B rows per wave: the
+// eight lanes of block g run its rows in order (ascending or descending),
+// each row's in-block entries eight at a time, the products summed across
+// the eight lanes by sum8; the block's x sits in LDS, and the entries, o and
+// 1/d of the next row are loaded while the current row runs.  o holds
+// g - (entries outside the block) x_in, or g when x_in is NULL (x_in = 0).
+// x_out may be x_in: a block reads only its own rows of x_in.
+// PF: entries per lane held for the next row (8 PF per row; chosen per level
+// from its longest in-block row, longer rows read the rest in the chain).
+template <int PF>
+__global__ void __launch_bounds__(64) k_hgs8(int64_t n, int B, const int64_t *__restrict__ pin,
+                                             const uint8_t *__restrict__ lin, const double *__restrict__ vin,
+                                             const double *__restrict__ idl, const double *__restrict__ o,
+                                             const double *x_in, double *x_out, int forward) {
+    extern __shared__ double xs[];   // [8][B]
+    const int lane = threadIdx.x, g = lane >> 3, l = lane & 7;
+    const int64_t b0 = ((int64_t)blockIdx.x * 8 + g) * B;
+    const int nb = b0 < n ? (int)min<int64_t>(B, n - b0) : 0;
+    double *xb = xs + g * B;
+    for (int r = l; r < nb; r += 8) xb[r] = x_in ? x_in[b0 + r] : 0.0;
+    __syncthreads();
+    // the data of row step t: entries l, l+8, l+16 and the row's o and 1/d
+    int64_t lo = 0, hi = 0;
+    double v[PF] = {}, orow = 0.0, irow = 0.0;
+    int c[PF] = {};
+    auto fetch = [&](int t) {
+        lo = hi = 0;
+        if (t >= nb) return;
+        const int64_t row = b0 + (forward ? t : nb - 1 - t);
+        lo = pin[row];
+        hi = pin[row + 1];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int64_t k = lo + l + 8 * u;
+            c[u] = k < hi ? (int)lin[k] : 0;
+            v[u] = k < hi ? vin[k] : 0.0;
+        }
+        orow = o[row];
+        irow = idl[row];
+    };
+    fetch(0);
+    for (int t = 0; t < B; ++t) {   // the same trip count in every eighth
+        const int64_t clo = lo, chi = hi;
+        double cv[PF], co = orow, ci = irow;
+        int cc[PF];
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            cv[u] = v[u];
+            cc[u] = c[u];
+        }
+        fetch(t + 1);
+        double sum = 0.0;
+        if (t < nb) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) sum += cv[u] * xb[cc[u]];
+            for (int64_t k = clo + l + 8 * PF; k < chi; k += 8) sum += vin[k] * xb[lin[k]];
+        }
+        sum = sum8(sum);
+        if (t < nb && l == 0) {
+            const int r = forward ? t : nb - 1 - t;
+            xb[r] += (co - sum) * ci;
+        }
         __syncthreads();
     }
-    for (int r = lane; r < nb; r += 64) x_out[b0 + r] = xb[r];
+    for (int r = l; r < nb; r += 8) x_out[b0 + r] = xb[r];
 }
 
 __global__ void __launch_bounds__(TB) k_xpby(double *__restrict__ p, const double *__restrict__ z, double beta,
@@ -357,6 +374,13 @@ struct CLv {
     int64_t n = 0;
     DBsr A, P, R;                 // 1x1 blocks
     DBuf<double> dl1;
+    // smoother split of A: entries inside the row's block (local column, one
+    // byte) and outside it, and 1 / l1 diagonal
+    DBuf<int64_t> pin, pout;
+    DBuf<uint8_t> lin;
+    DBuf<int32_t> cout;
+    DBuf<double> vin, vout, idl;
+    int max_in = 0;               // longest in-block row
     DBuf<int8_t> state;
     DBuf<double> g, x, s, o, t;   // work vectors
 };
@@ -379,9 +403,9 @@ unsigned grid_rows(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + TB / RG - 1) / (TB / RG), 1 << 20));
 }
 
-void csr_apply(const DBsr &A, const double *x, double *y, const double *g, int mode, hipStream_t s, int B = 1) {
+void csr_apply(const DBsr &A, const double *x, double *y, const double *g, int mode, hipStream_t s) {
     if (A.nr == 0) return;
-    hipLaunchKernelGGL(k_csr, dim3(grid_rows(A.nr)), dim3(TB), 0, s, A.nr, A.ptr, A.col, A.val, x, y, g, mode, B);
+    hipLaunchKernelGGL(k_csr, dim3(grid_rows(A.nr)), dim3(TB), 0, s, A.nr, A.ptr, A.col, A.val, x, y, g, mode);
     TE_CHECK_HIP(hipGetLastError());
 }
 
@@ -406,12 +430,20 @@ void sweep(camg_handle *h, CLv &L, const double *g, const double *x_in, double *
     const int B = h->opt.block;
     const double *o = g;
     if (x_in) {
-        csr_apply(L.A, x_in, L.o.p, g, 3, s, B);
+        // o = g - (entries outside the blocks) x_in
+        hipLaunchKernelGGL(k_csr, dim3(grid_rows(L.n)), dim3(TB), 0, s, L.n, L.pout.p, L.cout.p, L.vout.p, x_in,
+                           L.o.p, g, 1);
         o = L.o.p;
     }
-    const unsigned nb = (unsigned)((L.n + B - 1) / B);
-    hipLaunchKernelGGL(k_hgs_seq, dim3(nb), dim3(64), 0, s, L.n, L.A.ptr, L.A.col, L.A.val, L.dl1.p, o, x_in, x_out,
-                       B, forward ? 1 : 0);
+    const int64_t nblk = (L.n + B - 1) / B;
+    const unsigned grid = (unsigned)((nblk + 7) / 8);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), (size_t)8 * B * sizeof(double), s, L.n, B, L.pin.p, L.lin.p,
+                           L.vin.p, L.idl.p, o, x_in, x_out, forward ? 1 : 0);
+    };
+    if (L.max_in <= 24) go(k_hgs8<3>);
+    else if (L.max_in <= 64) go(k_hgs8<8>);
+    else go(k_hgs8<16>);
     TE_CHECK_HIP(hipGetLastError());
 }
 
@@ -427,8 +459,7 @@ void vcycle(camg_handle *h, size_t l, const double *g, double *x, hipStream_t s)
     csr_apply(L.R, L.s.p, N.g.p, nullptr, 0, s);
     vcycle(h, l + 1, N.g.p, N.x.p, s);
     csr_apply(L.P, N.x.p, x, nullptr, 2, s);
-    sweep(h, L, g, x, L.t.p, false, s);
-    TE_CHECK_HIP(hipMemcpyAsync(x, L.t.p, L.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    sweep(h, L, g, x, x, false, s);
 }
 
 void copy_csr(const te_csr *A, DBsr &M, hipStream_t s) {
@@ -483,6 +514,33 @@ bool host_inverse(std::vector<double> M, int n, std::vector<double> &inv) {
         }
     }
     return true;
+}
+
+void split_level(CLv &L, int B, hipStream_t s) {
+    const int64_t n = L.n;
+    DBuf<int32_t> ci(n), co(n);
+    hipLaunchKernelGGL(k_split_count, dim3(grid1(n)), dim3(TB), 0, s, n, L.A.ptr, L.A.col, B, ci.p, co.p);
+    TE_CHECK_HIP(hipGetLastError());
+    std::vector<int32_t> hi_, ho_;
+    download(hi_, ci.p, (size_t)n, s);
+    download(ho_, co.p, (size_t)n, s);
+    std::vector<int64_t> pi(n + 1, 0), po(n + 1, 0);
+    L.max_in = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        pi[i + 1] = pi[i] + hi_[i];
+        po[i + 1] = po[i] + ho_[i];
+        L.max_in = std::max(L.max_in, hi_[i]);
+    }
+    upload(L.pin, pi, s);
+    upload(L.pout, po, s);
+    L.lin.alloc(std::max<int64_t>(pi[n], 1));
+    L.vin.alloc(std::max<int64_t>(pi[n], 1));
+    L.cout.alloc(std::max<int64_t>(po[n], 1));
+    L.vout.alloc(std::max<int64_t>(po[n], 1));
+    L.idl.alloc(n);
+    hipLaunchKernelGGL(k_split_fill, dim3(grid1(n)), dim3(TB), 0, s, n, L.A.ptr, L.A.col, L.A.val, B, L.dl1.p,
+                       L.pin.p, L.lin.p, L.vin.p, L.pout.p, L.cout.p, L.vout.p, L.idl.p);
+    TE_CHECK_HIP(hipGetLastError());
 }
 
 void alloc_work(CLv &L) {
@@ -610,6 +668,7 @@ int setup_impl(const te_csr *A, const camg_options *o, camg_handle **out, hipStr
                 TE_CHECK_HIP(hipGetLastError());
                 TE_REQUIRE(read_i32(bad, s) == 0, TE_EINVAL, "level %d has a row with a non-positive l1 diagonal",
                            (int)l);
+                split_level(L, h->opt.block, s);
             }
         }
         const int64_t n0 = h->L[0].n;

@@ -152,6 +152,8 @@ constexpr int FMT_ROWWAVE = 1;
 // non-temporal loads of the matrix values.
 struct Tune {
     int wpb = 4, spw = 1, remap = 1, nt = 0;
+    int mwpb = 4;    // several right-hand sides: waves per workgroup
+    int mtile = 0;   // several right-hand sides on the SELL layout: columns per pass (0: row per wave)
 };
 
 struct Sell {

@@ -45,42 +45,70 @@ __global__ void __launch_bounds__(512) k_sell1(SellView<VT> A, const XT *__restr
     }
 }
 
-// Several right-hand sides: one wave per block row, lane = right-hand side.
+// Several right-hand sides on the SELL layout: R consecutive block rows of
+// one slice per wave, T = 64 / R lanes per row, each lane S right-hand sides
+// (c0 + j, c0 + j + T, ...) of the column tile c0 = blockIdx.y * T * S.  A
+// lane loads its row's block values (vector loads: the R rows of a wave
+// share each 16-byte value piece line) and reuses them for its S columns;
+// the x rows of MU entries are loaded before any is used.  Column tiles are
+// the slowest grid dimension, so the whole matrix runs for one tile before
+// the next and the x rows an XCD gathers (tile width x 24 bytes per node)
+// stay in its L2; the matrix is read once per tile.  The rows of a slice are
+// sorted by descending length, so the first row of the wave bounds the
+// entry loop; shorter rows run over their zero padding blocks (valid
+// columns).  `wpb` waves per workgroup.
+// The other SELL multi-RHS organisation: one wave per block row with the
+// right-hand sides on the lanes (at most 64); the block values are
+// wave-uniform (scalar loads), the row's column indices come 64 at a time
+// and are taken by readlane, and the x rows of 4 entries are loaded before
+// any of them is used.  Chosen by the tuner when it beats the row groups.
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
-__global__ void __launch_bounds__(BLK) k_sellm(SellView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
-                                               double *__restrict__ partials) {
-    __shared__ double lds[BLK];
+__global__ void __launch_bounds__(512) k_sellw(SellView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
+                                               double *__restrict__ partials, int wpb) {
+    constexpr int MU = BC <= 3 ? 4 : 2;
+    __shared__ double lds[8 * WAVE];
     const int64_t nb = gridDim.x;
     const int64_t lb = xcd_logical_block(blockIdx.x, nb);
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * WPB + threadIdx.x / WAVE));
+    const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * wpb + threadIdx.x / WAVE));
     double red = 0.0;
     if (row < A.nrows) {
-        const int64_t slice = row / WAVE;
         const int rl = (int)(row % WAVE);
-        const int off = A.slice_off[slice];
+        const int off = A.slice_off[row / WAVE];
         const int len = A.rowlen[row];
         AT acc[BR];
 #pragma unroll
         for (int i = 0; i < BR; ++i) acc[i] = AT(0);
-        // up to 64 column indices of the row in one load (lane u holds entry
-        // k0 + u, every lane active), then taken one by one with readlane: the
-        // x loads of an entry depend on no load of its own
+        auto entry = [&](int k, const AT *xv) {
+            const VT *vk = A.val + (int64_t)(off + k) * (BR * BC * WAVE);
+#pragma unroll
+            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                for (int j = 0; j < BC; ++j)
+                    acc[i] += AT(vk[sell_val_off<sell_vw<VT>()>(i * BC + j, BR * BC, rl)]) * xv[j];
+        };
         for (int k0 = 0; k0 < len; k0 += WAVE) {
             const int cnt = min(WAVE, len - k0);
             const int cl = k0 + lane < len ? A.col[(int64_t)(off + k0 + lane) * WAVE + rl] : 0;
             if (lane < nrhs) {
-                for (int u = 0; u < cnt; ++u) {
+                int u = 0;
+                for (; u + MU <= cnt; u += MU) {
+                    AT xv[MU][BC];
+#pragma unroll
+                    for (int t = 0; t < MU; ++t) {
+                        const int64_t c = __builtin_amdgcn_readlane(cl, u + t);
+#pragma unroll
+                        for (int j = 0; j < BC; ++j) xv[t][j] = AT(x[(c * BC + j) * nrhs + lane]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < MU; ++t) entry(k0 + u + t, xv[t]);
+                }
+                for (; u < cnt; ++u) {
                     const int64_t c = __builtin_amdgcn_readlane(cl, u);
-                    const VT *vk = A.val + (int64_t)(off + k0 + u) * (BR * BC * WAVE);
                     AT xv[BC];
 #pragma unroll
                     for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
-#pragma unroll
-                    for (int i = 0; i < BR; ++i)
-#pragma unroll
-                        for (int j = 0; j < BC; ++j)
-                            acc[i] += AT(vk[sell_val_off<sell_vw<VT>()>(i * BC + j, BR * BC, rl)]) * xv[j];
+                    entry(k0 + u, xv);
                 }
             }
         }
@@ -90,13 +118,107 @@ __global__ void __launch_bounds__(BLK) k_sellm(SellView<VT> A, const XT *__restr
         }
     }
     if (Epi::kReduce) {
-        // per-column partial: sum over the waves of this block, fixed order
         lds[threadIdx.x] = red;
         __syncthreads();
         if (threadIdx.x < WAVE && threadIdx.x < nrhs) {
             double t = 0.0;
-            for (int w = 0; w < WPB; ++w) t += lds[w * WAVE + threadIdx.x];
+            for (int w = 0; w < wpb; ++w) t += lds[w * WAVE + threadIdx.x];
             partials[lb * nrhs + threadIdx.x] = t;
+        }
+    }
+}
+
+template <int BC, int S>
+constexpr int multi_unroll() {
+    return BC <= 3 && S <= 2 ? 2 : 1;
+}
+
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, int R, int S>
+__global__ void __launch_bounds__(512) k_sellm(SellView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
+                                                double *__restrict__ partials, int wpb) {
+    constexpr int T = WAVE / R, E = BR * BC, MU = multi_unroll<BC, S>();
+    constexpr int VW = sell_vw<VT>(), G = E / VW;
+    typedef VT vec_t __attribute__((ext_vector_type(VW)));
+    __shared__ double lds[16 * WAVE];
+    const int64_t nb = gridDim.x;
+    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int q = lane / T, w = threadIdx.x / WAVE;
+    const int c0 = blockIdx.y * (T * S);
+    const int j = c0 + lane % T;      // first column of the lane
+    const int64_t row0 = (lb * wpb + w) * R;
+    const int64_t row = row0 + q;
+    double red[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) red[t] = 0.0;
+    if (row0 < A.nrows) {
+        // rows past the end (last slice) compute on row0's entries, store nothing
+        const bool live = row < A.nrows;
+        const int64_t rr = live ? row : row0;
+        const int rl = (int)(rr % WAVE);
+        const int off = A.slice_off[rr / WAVE];
+        const int lmax = __builtin_amdgcn_readfirstlane(A.rowlen[row0]);
+        AT acc[S][BR];
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+#pragma unroll
+            for (int i = 0; i < BR; ++i) acc[t][i] = AT(0);
+        for (int k = 0; k < lmax; k += MU) {
+            VT v[MU][E];
+            AT xv[MU][S][BC];
+#pragma unroll
+            for (int u = 0; u < MU; ++u) {
+                const int kk = min(k + u, lmax - 1);   // a repeated entry is not accumulated
+                const int64_t c = A.col[(int64_t)(off + kk) * WAVE + rl];
+                const VT *vk = A.val + (int64_t)(off + kk) * (E * WAVE);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const vec_t t = *reinterpret_cast<const vec_t *>(vk + (int64_t)(g * WAVE + rl) * VW);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) v[u][g * VW + e] = t[e];
+                }
+#pragma unroll
+                for (int e = G * VW; e < E; ++e) v[u][e] = vk[(int64_t)(G * VW) * WAVE + (e - G * VW) * WAVE + rl];
+#pragma unroll
+                for (int t = 0; t < S; ++t) {
+                    const int jj = j + t * T;
+#pragma unroll
+                    for (int b = 0; b < BC; ++b) xv[u][t][b] = jj < nrhs ? AT(x[(c * BC + b) * nrhs + jj]) : AT(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < MU; ++u) {
+                if (k + u >= lmax) break;
+#pragma unroll
+                for (int t = 0; t < S; ++t)
+#pragma unroll
+                    for (int i = 0; i < BR; ++i)
+#pragma unroll
+                        for (int b = 0; b < BC; ++b) acc[t][i] += AT(v[u][i * BC + b]) * xv[u][t][b];
+            }
+        }
+        if (live) {
+            const int64_t out = A.rowmap ? (int64_t)A.rowmap[row] : row;
+#pragma unroll
+            for (int t = 0; t < S; ++t)
+                if (j + t * T < nrhs) epi.template apply_m<BR>(out, j + t * T, nrhs, acc[t], red[t]);
+        }
+    }
+    if (Epi::kReduce) {
+        // per column: the R rows of the wave by a fixed shuffle tree, then the
+        // waves of the block in order
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            double v = red[t];
+#pragma unroll
+            for (int o = T; o < WAVE; o <<= 1) v += __shfl_xor(v, o, WAVE);
+            if (q == 0) lds[w * WAVE + (j - c0) + t * T] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < T * S && c0 + (int)threadIdx.x < nrhs) {
+            double t = 0.0;
+            for (int ww = 0; ww < wpb; ++ww) t += lds[ww * WAVE + threadIdx.x];
+            partials[lb * nrhs + c0 + threadIdx.x] = t;
         }
     }
 }
@@ -120,36 +242,53 @@ __global__ void __launch_bounds__(512) k_roww(RowView<VT> A, const XT *__restric
     }
 }
 
-// Format 1 with several right-hand sides: one wave per row, lane = RHS.
+// Format 1 with several right-hand sides: one wave per row, lane = RHS, MU
+// blocks' x rows loaded before they are used (as k_sellm).
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
-__global__ void __launch_bounds__(BLK) k_rowwm(RowView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
-                                               double *__restrict__ partials) {
-    __shared__ double lds[BLK];
+__global__ void __launch_bounds__(1024) k_rowwm(RowView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
+                                                double *__restrict__ partials, int wpb) {
+    constexpr int MU = BC <= 3 ? 4 : 2;
+    __shared__ double lds[1024];
     const int64_t nb = gridDim.x;
     const int64_t lb = xcd_logical_block(blockIdx.x, nb);
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * WPB + threadIdx.x / WAVE));
+    const int64_t row = (int64_t)__builtin_amdgcn_readfirstlane((int)(lb * wpb + threadIdx.x / WAVE));
     double red = 0.0;
     if (row < A.nrows) {
         AT acc[BR];
 #pragma unroll
         for (int i = 0; i < BR; ++i) acc[i] = AT(0);
+        // TR: the block is stored transposed (mirror of a lower block)
+        auto block = [&](const VT *v, const AT *xv, bool tr) {
+#pragma unroll
+            for (int i = 0; i < BR; ++i)
+#pragma unroll
+                for (int j = 0; j < BC; ++j) acc[i] += AT(tr ? v[j * BC + i] : v[i * BC + j]) * xv[j];
+        };
         // column indices 64 at a time (every lane active), taken with readlane
         const int64_t lo = A.rptr[row], hi = A.rptr[row + 1];
         for (int64_t k0 = lo; k0 < hi; k0 += WAVE) {
             const int cnt = (int)min((int64_t)WAVE, hi - k0);
             const int cl = k0 + lane < hi ? A.col[k0 + lane] : 0;
             if (lane < nrhs) {
-                for (int u = 0; u < cnt; ++u) {
+                int u = 0;
+                for (; u + MU <= cnt; u += MU) {
+                    AT xv[MU][BC];
+#pragma unroll
+                    for (int t = 0; t < MU; ++t) {
+                        const int64_t c = __builtin_amdgcn_readlane(cl, u + t);
+#pragma unroll
+                        for (int j = 0; j < BC; ++j) xv[t][j] = AT(x[(c * BC + j) * nrhs + lane]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < MU; ++t) block(A.val + (k0 + u + t) * (BR * BC), xv[t], false);
+                }
+                for (; u < cnt; ++u) {
                     const int64_t c = __builtin_amdgcn_readlane(cl, u);
-                    const VT *v = A.val + (k0 + u) * (BR * BC);
                     AT xv[BC];
 #pragma unroll
                     for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
-#pragma unroll
-                    for (int i = 0; i < BR; ++i)
-#pragma unroll
-                        for (int j = 0; j < BC; ++j) acc[i] += AT(v[i * BC + j]) * xv[j];
+                    block(A.val + (k0 + u) * (BR * BC), xv, false);
                 }
             }
         }
@@ -161,16 +300,25 @@ __global__ void __launch_bounds__(BLK) k_rowwm(RowView<VT> A, const XT *__restri
                     const int cl = q0 + lane < lhi ? A.lcol[q0 + lane] : 0;
                     const int il = q0 + lane < lhi ? A.lidx[q0 + lane] : 0;
                     if (lane < nrhs) {
-                        for (int u = 0; u < cnt; ++u) {
+                        int u = 0;
+                        for (; u + MU <= cnt; u += MU) {
+                            AT xv[MU][BC];
+#pragma unroll
+                            for (int t = 0; t < MU; ++t) {
+                                const int64_t c = __builtin_amdgcn_readlane(cl, u + t);
+#pragma unroll
+                                for (int j = 0; j < BC; ++j) xv[t][j] = AT(x[(c * BC + j) * nrhs + lane]);
+                            }
+#pragma unroll
+                            for (int t = 0; t < MU; ++t)
+                                block(A.val + (int64_t)__builtin_amdgcn_readlane(il, u + t) * (BR * BC), xv[t], true);
+                        }
+                        for (; u < cnt; ++u) {
                             const int64_t c = __builtin_amdgcn_readlane(cl, u);
-                            const VT *v = A.val + (int64_t)__builtin_amdgcn_readlane(il, u) * (BR * BC);
                             AT xv[BC];
 #pragma unroll
                             for (int j = 0; j < BC; ++j) xv[j] = AT(x[(c * BC + j) * nrhs + lane]);
-#pragma unroll
-                            for (int i = 0; i < BR; ++i)
-#pragma unroll
-                                for (int j = 0; j < BC; ++j) acc[i] += AT(v[j * BC + i]) * xv[j];
+                            block(A.val + (int64_t)__builtin_amdgcn_readlane(il, u) * (BR * BC), xv, true);
                         }
                     }
                 }
@@ -186,7 +334,7 @@ __global__ void __launch_bounds__(BLK) k_rowwm(RowView<VT> A, const XT *__restri
         __syncthreads();
         if (threadIdx.x < WAVE && threadIdx.x < nrhs) {
             double t = 0.0;
-            for (int w = 0; w < WPB; ++w) t += lds[w * WAVE + threadIdx.x];
+            for (int w = 0; w < wpb; ++w) t += lds[w * WAVE + threadIdx.x];
             partials[lb * nrhs + threadIdx.x] = t;
         }
     }
@@ -200,13 +348,30 @@ static inline const Tune &tune_of(const Sell &A) {
     return sizeof(T) == 4 ? A.tune32 : A.tune64;
 }
 
+// Block rows per wave of the SELL multi-RHS product for nrhs columns: 16
+// rows (4 lanes each) for at most 4 columns, else 4 rows of 16 lanes; one
+// row per wave for the lane-per-column kernel (tile 0, above 16 columns).
+static inline int multi_rows(int nrhs, int mtile) {
+    if (mtile == 0 && nrhs > 16) return 1;   // k_sellw
+    return nrhs <= 4 ? 16 : 4;
+}
+// Columns per lane: the column tile (16, 32 or 64 columns per pass over the
+// matrix, tuned) over the 16 lanes of a row.
+static inline int multi_cols(int nrhs, int mtile) {
+    if (nrhs <= 4) return 1;
+    const int need = (nrhs + 15) / 16;   // 1..4
+    const int s = std::min(need, mtile / 16);
+    return s >= 4 ? 4 : (s >= 2 ? 2 : 1);
+}
+
 static inline int64_t sell_grid(const Sell &A, int nrhs, const Tune &t) {
     if (nrhs == 1) {
         const int64_t units = A.format == FMT_SELL ? A.nslices : A.nrows;
         const int64_t per = (int64_t)t.wpb * t.spw;
         return (units + per - 1) / per;
     }
-    return (A.nrows + WPB - 1) / WPB;
+    const int64_t per = (int64_t)t.mwpb * (A.format == FMT_SELL ? multi_rows(nrhs, t.mtile) : 1);
+    return (A.nrows + per - 1) / per;
 }
 
 int sell_partials_count(const Sell &A, int nrhs) { return (int)sell_grid(A, nrhs, A.tune64); }
@@ -215,9 +380,13 @@ template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
 static void launch_t(const Sell &A, const VT *val, const XT *x, const Epi &epi, int nrhs, double *partials,
                      hipStream_t s) {
     const Tune &t = tune_of<VT>(A);
+    // the partial-sum tables hold one entry per 4 block rows at most; the SELL
+    // multi-RHS kernel runs at most 8 waves per workgroup
+    TE_REQUIRE(nrhs == 1 || t.mwpb == 4 || t.mwpb == 8 || (t.mwpb == 16 && A.format == FMT_ROWWAVE), TE_EINVAL,
+               "bad waves per workgroup %d", t.mwpb);
     int64_t g = sell_grid(A, nrhs, t);
     if (g == 0) return;
-    const dim3 blk(nrhs == 1 ? 64 * t.wpb : BLK);
+    const dim3 blk(64 * (nrhs == 1 ? t.wpb : t.mwpb));
     if (nrhs == 1) {
         if (A.format == FMT_ROWWAVE) {
             if (t.nt)
@@ -236,10 +405,26 @@ static void launch_t(const Sell &A, const VT *val, const XT *x, const Epi &epi, 
         }
     } else if (A.format == FMT_ROWWAVE) {
         hipLaunchKernelGGL((k_rowwm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), blk, 0, s, rview(A, val), x, epi,
-                           nrhs, partials);
+                           nrhs, partials, t.mwpb);
     } else {
-        hipLaunchKernelGGL((k_sellm<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), blk, 0, s, view(A, val), x, epi,
-                           nrhs, partials);
+        const int R = multi_rows(nrhs, t.mtile);
+        if (R == 1) {
+            hipLaunchKernelGGL((k_sellw<BR, BC, VT, XT, AT, Epi>), dim3((unsigned)g), blk, 0, s, view(A, val), x,
+                               epi, nrhs, partials, t.mwpb);
+            TE_CHECK_HIP(hipGetLastError());
+            return;
+        }
+        const int S = multi_cols(nrhs, t.mtile);
+        const int tile = (WAVE / R) * S;
+        const unsigned tiles = (unsigned)((nrhs + tile - 1) / tile);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)g, tiles), blk, 0, s, view(A, val), x, epi, nrhs, partials,
+                               t.mwpb);
+        };
+        if (R == 16) go(k_sellm<BR, BC, VT, XT, AT, Epi, 16, 1>);
+        else if (S == 1) go(k_sellm<BR, BC, VT, XT, AT, Epi, 4, 1>);
+        else if (S == 2) go(k_sellm<BR, BC, VT, XT, AT, Epi, 4, 2>);
+        else go(k_sellm<BR, BC, VT, XT, AT, Epi, 4, 4>);
     }
     TE_CHECK_HIP(hipGetLastError());
 }

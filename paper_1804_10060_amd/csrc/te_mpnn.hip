@@ -5,19 +5,25 @@
 //
 //   h0   = relu(X W_in + b_in)                               X: [N, 10]
 //   for l < 4:  m = mean_{u in N(v)} h_u;  g = mean_v h_v
-//               h = h + relu(h W_s + m W_n + g W_g + b)
+//               d_k = sum_{u in N(v)} w^k_vu h_u   (k = x, y, z)
+//               h = h + relu(h W_s + m W_n + g W_g + d_x W_dx + d_y W_dy + d_z W_dz + b)
 //   y    = (h W_out + b_out) * (1 - mask)                    [N, 3]
+// with the direction weights w^k_vu = (x_u - x_v)_k / (deg_v l_v), l_v the
+// mean length of the edges at v (a first-difference stencil).
 //
-// Layouts: activations [N][64] row-major; parameters one float array in the
-// order W_in[10][64], b_in[64], per layer {W_s, W_n, W_g}[64][64], b[64],
-// W_out[64][3], b_out[3] (weights [in][out]).
+// Layouts: activations [N][64] row-major, the directional sums [N][3][64];
+// parameters one float array in the order W_in[10][64], b_in[64], per layer
+// {W_s, W_n, W_g, W_dx, W_dy, W_dz}[64][64], b[64], W_out[64][3], b_out[3]
+// (weights [in][out]), so the three directional weights of a layer form one
+// [192][64] matrix against the [N][192] sums.
 //
 // Vertex kernels run one wave per vertex with the 64 channels on the lanes
-// (the neighbour gather is then a coalesced 256-byte row read); weight
-// gradients X^T Y are blocked reductions over vertices with per-block partial
-// tiles summed in a fixed order (deterministic, no atomics).  The graph is
-// symmetric, so the adjoint of the neighbour mean is again a gather:
-// d h_u = sum_{v in N(u)} d m_v / deg_v.
+// (the neighbour gather is then a coalesced 256-byte row read; a vertex's
+// channel values reach every lane by readlane); weight gradients X^T Y are
+// blocked reductions over vertices with per-block partial tiles summed in a
+// fixed order (deterministic, no atomics).  The graph is symmetric, so the
+// adjoints of the neighbour mean and of the directional sums are gathers
+// too: d h_u = sum_{v in N(u)} (d m_v / deg_v + sum_k w^k_vu d d_k[v]).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,10 +34,10 @@
 
 namespace te {
 
-constexpr int MH = 64, ML = 4, MF = 10, MO = 3;
+constexpr int MH = 64, ML = 4, MF = 10, MO = 3, MD = 3 * MH;
 constexpr int64_t OFF_WIN = 0, OFF_BIN = MF * MH;
 constexpr int64_t LAYER0 = OFF_BIN + MH;
-constexpr int64_t LAYER_SZ = 3 * MH * MH + MH;
+constexpr int64_t LAYER_SZ = 6 * MH * MH + MH;
 constexpr int64_t OFF_WOUT = LAYER0 + ML * LAYER_SZ;
 constexpr int64_t OFF_BOUT = OFF_WOUT + MH * MO;
 constexpr int64_t NPARAM = OFF_BOUT + MO;
@@ -43,7 +49,12 @@ constexpr int RED_BLOCKS = 512;
 __host__ __device__ constexpr int64_t off_ws(int l) { return LAYER0 + l * LAYER_SZ; }
 __host__ __device__ constexpr int64_t off_wn(int l) { return LAYER0 + l * LAYER_SZ + MH * MH; }
 __host__ __device__ constexpr int64_t off_wg(int l) { return LAYER0 + l * LAYER_SZ + 2 * MH * MH; }
-__host__ __device__ constexpr int64_t off_b(int l) { return LAYER0 + l * LAYER_SZ + 3 * MH * MH; }
+__host__ __device__ constexpr int64_t off_wd(int l) { return LAYER0 + l * LAYER_SZ + 3 * MH * MH; }
+__host__ __device__ constexpr int64_t off_b(int l) { return LAYER0 + l * LAYER_SZ + 6 * MH * MH; }
+
+__device__ __forceinline__ float lane_val(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
 
 static inline unsigned vgrid(int64_t n) {
     int64_t g = (n + MW - 1) / MW;
@@ -110,32 +121,52 @@ __global__ void k_global(int nparts, const double *__restrict__ part, int64_t n,
     gw[c] = a;
 }
 
-// one message-passing layer: m = mean of neighbours, a = h W_s + m W_n + gw,
-// h' = h + relu(a); stores m and a for the backward pass
+// one message-passing layer: m = mean of neighbours, d = directional sums,
+// a = h W_s + m W_n + d W_d + gw, h' = h + relu(a); stores m, d and a for the
+// backward pass.  W_s, W_n, W_dx and W_dy sit in LDS (64 KB), W_dz is read
+// through the cache.
 __global__ void __launch_bounds__(MB) k_mp_fwd(int64_t n, const int64_t *__restrict__ gp, const int32_t *__restrict__ gi,
+                                               const float *__restrict__ xf, const float *__restrict__ invdl,
                                                const float *__restrict__ P, int l, const float *__restrict__ gw,
                                                const float *__restrict__ h, float *__restrict__ m,
-                                               float *__restrict__ a, float *__restrict__ hn) {
-    __shared__ float Ws[MH * MH], Wn[MH * MH];
+                                               float *__restrict__ d, float *__restrict__ a, float *__restrict__ hn) {
+    extern __shared__ float W[];   // [4][64][64]: W_s, W_n, W_dx, W_dy
     for (int t = threadIdx.x; t < MH * MH; t += MB) {
-        Ws[t] = P[off_ws(l) + t];
-        Wn[t] = P[off_wn(l) + t];
+        W[t] = P[off_ws(l) + t];
+        W[MH * MH + t] = P[off_wn(l) + t];
     }
+    for (int t = threadIdx.x; t < 2 * MH * MH; t += MB) W[2 * MH * MH + t] = P[off_wd(l) + t];
     __syncthreads();
+    const float *__restrict__ Wz = P + off_wd(l) + 2 * MH * MH;
     const int c = threadIdx.x & 63;
     const float gwc = gw[c];
     for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
         const int64_t lo = gp[v], hi = gp[v + 1];
-        float s = 0.f;
-        for (int64_t e = lo; e < hi; ++e) s += h[(int64_t)gi[e] * MH + c];
+        const float xv0 = xf[v * 3], xv1 = xf[v * 3 + 1], xv2 = xf[v * 3 + 2], iv = invdl[v];
+        float s = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f;
+        for (int64_t e = lo; e < hi; ++e) {
+            const int64_t u = gi[e];
+            const float hu = h[u * MH + c];
+            s += hu;
+            d0 += (xf[u * 3] - xv0) * iv * hu;
+            d1 += (xf[u * 3 + 1] - xv1) * iv * hu;
+            d2 += (xf[u * 3 + 2] - xv2) * iv * hu;
+        }
         const float mv = hi > lo ? s / float(hi - lo) : 0.f;
         const float hv = h[v * MH + c];
         float acc = gwc;
+#pragma unroll 8
         for (int k = 0; k < MH; ++k) {
-            acc += __shfl(hv, k, 64) * Ws[k * MH + c];
-            acc += __shfl(mv, k, 64) * Wn[k * MH + c];
+            acc += lane_val(hv, k) * W[k * MH + c];
+            acc += lane_val(mv, k) * W[MH * MH + k * MH + c];
+            acc += lane_val(d0, k) * W[2 * MH * MH + k * MH + c];
+            acc += lane_val(d1, k) * W[3 * MH * MH + k * MH + c];
+            acc += lane_val(d2, k) * Wz[k * MH + c];
         }
         m[v * MH + c] = mv;
+        d[v * MD + c] = d0;
+        d[v * MD + MH + c] = d1;
+        d[v * MD + 2 * MH + c] = d2;
         a[v * MH + c] = acc;
         hn[v * MH + c] = hv + (acc > 0.f ? acc : 0.f);
     }
@@ -189,29 +220,43 @@ __global__ void __launch_bounds__(MB) k_out(int64_t n, const float *__restrict__
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-// ga = gh * (a > 0); gmd = (ga W_n^T) / deg
+// ga = gh * (a > 0); gmd = (ga W_n^T) / deg; gd_k = ga W_dk^T
 __global__ void __launch_bounds__(MB) k_mp_bwd1(int64_t n, const int64_t *__restrict__ gp, const float *__restrict__ P,
                                                 int l, const float *__restrict__ gh, const float *__restrict__ a,
-                                                float *__restrict__ ga, float *__restrict__ gmd) {
-    __shared__ float Wn[MH * MH];
-    for (int t = threadIdx.x; t < MH * MH; t += MB) Wn[t] = P[off_wn(l) + t];
+                                                float *__restrict__ ga, float *__restrict__ gmd,
+                                                float *__restrict__ gd) {
+    extern __shared__ float W[];   // [4][64][64]: W_n, W_dx, W_dy, W_dz
+    for (int t = threadIdx.x; t < MH * MH; t += MB) W[t] = P[off_wn(l) + t];
+    for (int t = threadIdx.x; t < 3 * MH * MH; t += MB) W[MH * MH + t] = P[off_wd(l) + t];
     __syncthreads();
     const int c = threadIdx.x & 63;
     for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
         const float g = a[v * MH + c] > 0.f ? gh[v * MH + c] : 0.f;
         ga[v * MH + c] = g;
-        float t = 0.f;
-        for (int k = 0; k < MH; ++k) t += __shfl(g, k, 64) * Wn[c * MH + k];
+        float t = 0.f, t0 = 0.f, t1 = 0.f, t2 = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < MH; ++k) {
+            const float gk = lane_val(g, k);
+            t += gk * W[c * MH + k];
+            t0 += gk * W[MH * MH + c * MH + k];
+            t1 += gk * W[2 * MH * MH + c * MH + k];
+            t2 += gk * W[3 * MH * MH + c * MH + k];
+        }
         const int64_t deg = gp[v + 1] - gp[v];
         gmd[v * MH + c] = deg > 0 ? t / float(deg) : 0.f;
+        gd[v * MD + c] = t0;
+        gd[v * MD + MH + c] = t1;
+        gd[v * MD + 2 * MH + c] = t2;
     }
 }
 
-// gh_prev = gh + ga W_s^T + sum_{u in N(v)} gmd_u + gg / n
+// gh_prev = gh + ga W_s^T + gg / n + sum_{u in N(v)} (gmd_u + sum_k w^k_uv gd_k[u]),
+// w^k_uv = (x_v - x_u)_k / (deg_u l_u)
 __global__ void __launch_bounds__(MB) k_mp_bwd2(int64_t n, const int64_t *__restrict__ gp, const int32_t *__restrict__ gi,
+                                                const float *__restrict__ xf, const float *__restrict__ invdl,
                                                 const float *__restrict__ P, int l, const float *__restrict__ ga,
-                                                const float *__restrict__ gmd, const float *__restrict__ gg,
-                                                float *__restrict__ gh) {
+                                                const float *__restrict__ gmd, const float *__restrict__ gd,
+                                                const float *__restrict__ gg, float *__restrict__ gh) {
     __shared__ float Ws[MH * MH];
     for (int t = threadIdx.x; t < MH * MH; t += MB) Ws[t] = P[off_ws(l) + t];
     __syncthreads();
@@ -220,8 +265,17 @@ __global__ void __launch_bounds__(MB) k_mp_bwd2(int64_t n, const int64_t *__rest
     for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
         const float g = ga[v * MH + c];
         float t = gh[v * MH + c] + ggc;
-        for (int k = 0; k < MH; ++k) t += __shfl(g, k, 64) * Ws[c * MH + k];
-        for (int64_t e = gp[v]; e < gp[v + 1]; ++e) t += gmd[(int64_t)gi[e] * MH + c];
+#pragma unroll 8
+        for (int k = 0; k < MH; ++k) t += lane_val(g, k) * Ws[c * MH + k];
+        const float xv0 = xf[v * 3], xv1 = xf[v * 3 + 1], xv2 = xf[v * 3 + 2];
+        for (int64_t e = gp[v]; e < gp[v + 1]; ++e) {
+            const int64_t u = gi[e];
+            const float iu = invdl[u];
+            t += gmd[u * MH + c];
+            t += (xv0 - xf[u * 3]) * iu * gd[u * MD + c];
+            t += (xv1 - xf[u * 3 + 1]) * iu * gd[u * MD + MH + c];
+            t += (xv2 - xf[u * 3 + 2]) * iu * gd[u * MD + 2 * MH + c];
+        }
         gh[v * MH + c] = t;
     }
 }
@@ -333,20 +387,19 @@ __global__ void __launch_bounds__(MB) k_gy_to_gh(int64_t n, const float *__restr
     }
 }
 
-// e = S_U (y - t) * keep, u_t = S_U t  (float64, natural order)
-__global__ void k_energy_err(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
-                             const uint8_t *__restrict__ mask, double *__restrict__ e, double *__restrict__ ut) {
+// u = S_U y * keep, u_t = S_U t  (float64, natural order)
+__global__ void k_energy_prep(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
+                              const uint8_t *__restrict__ mask, double *__restrict__ u, double *__restrict__ ut) {
     for (int64_t i = blockIdx.x * (int64_t)MB + threadIdx.x; i < n * 3; i += (int64_t)gridDim.x * MB) {
-        const double keep = mask[i] ? 0.0 : 1.0;
-        e[i] = S_U * (double(y[i]) - double(t[i])) * keep;
+        u[i] = mask[i] ? 0.0 : S_U * double(y[i]);
         ut[i] = S_U * double(t[i]);
     }
 }
-// gy = 2 S_U keep * Ae / E (float)
-__global__ void k_energy_gy(int64_t n, const double *__restrict__ Ae, const uint8_t *__restrict__ mask, double scale,
-                            float *__restrict__ gy) {
+// gy = keep * (ca * A u_t + cb * A u)  (float)
+__global__ void k_energy_gy(int64_t n, const double *__restrict__ Aut, const double *__restrict__ Au,
+                            const uint8_t *__restrict__ mask, double ca, double cb, float *__restrict__ gy) {
     for (int64_t i = blockIdx.x * (int64_t)MB + threadIdx.x; i < n * 3; i += (int64_t)gridDim.x * MB)
-        gy[i] = mask[i] ? 0.f : float(scale * Ae[i]);
+        gy[i] = mask[i] ? 0.f : float(ca * Aut[i] + cb * Au[i]);
 }
 
 // Adam (Kingma & Ba 2015) with bias correction
@@ -365,6 +418,22 @@ __global__ void k_adam(int64_t n, float *__restrict__ p, const float *__restrict
 __global__ void k_guess(int64_t n, const float *__restrict__ y, double *__restrict__ u0) {
     for (int64_t t = blockIdx.x * (int64_t)MB + threadIdx.x; t < n * 3; t += (int64_t)gridDim.x * MB)
         u0[t] = S_U * double(y[t]);
+}
+
+// 1 / (deg_v l_v), l_v the mean length of the edges at v (0 without edges)
+__global__ void k_invdl(int64_t n, const int64_t *__restrict__ gp, const int32_t *__restrict__ gi,
+                        const double *__restrict__ xc, float *__restrict__ invdl, float *__restrict__ xf) {
+    for (int64_t v = blockIdx.x * (int64_t)MB + threadIdx.x; v < n; v += (int64_t)gridDim.x * MB) {
+        double len = 0.0;
+        for (int64_t e = gp[v]; e < gp[v + 1]; ++e) {
+            const int64_t u = gi[e];
+            const double a = xc[u * 3] - xc[v * 3], b = xc[u * 3 + 1] - xc[v * 3 + 1], c = xc[u * 3 + 2] - xc[v * 3 + 2];
+            len += sqrt(a * a + b * b + c * c);
+        }
+        const int64_t deg = gp[v + 1] - gp[v];
+        invdl[v] = deg > 0 && len > 0.0 ? float(1.0 / len) : 0.f;   // 1 / (deg * (len / deg))
+        for (int k = 0; k < 3; ++k) xf[v * 3 + k] = float(xc[v * 3 + k]);
+    }
 }
 
 // vertex graph = stiffness pattern without the diagonal
@@ -395,8 +464,9 @@ struct mpnn_handle {
     te::DBuf<int64_t> gp;
     te::DBuf<int32_t> gi;
     te::DBuf<double> xc;  // centred coordinates
-    te::DBuf<float> h[te::ML + 1], m[te::ML], a[te::ML], g[te::ML], gw;
-    te::DBuf<float> y, gy, gh, ga, gmd, gg, part;
+    te::DBuf<float> xf, invdl;  // float centred coordinates, 1 / (deg l) per vertex
+    te::DBuf<float> h[te::ML + 1], m[te::ML], d[te::ML], a[te::ML], g[te::ML], gw;
+    te::DBuf<float> y, gy, gh, ga, gmd, gd, gg, part;
     te::DBuf<double> dpart;
     te::DBuf<float> X;     // last forward input (borrowed copy)
     te::DBuf<uint8_t> mask;
@@ -434,9 +504,14 @@ extern "C" int mpnn_create(int64_t n, const int64_t *row_ptr, const int32_t *col
         for (int64_t v = 0; v < n; ++v)
             for (int k = 0; k < 3; ++k) X[v * 3 + k] -= c[k];
         upload(H->xc, X, s);
+        H->xf.alloc(n * 3);
+        H->invdl.alloc(n);
+        hipLaunchKernelGGL(k_invdl, dim3(g), dim3(MB), 0, s, n, H->gp.p, H->gi.p, H->xc.p, H->invdl.p, H->xf.p);
+        TE_CHECK_HIP(hipGetLastError());
         for (int l = 0; l <= ML; ++l) H->h[l].alloc(n * MH);
         for (int l = 0; l < ML; ++l) {
             H->m[l].alloc(n * MH);
+            H->d[l].alloc(n * MD);
             H->a[l].alloc(n * MH);
             H->g[l].alloc(MH);
         }
@@ -446,8 +521,9 @@ extern "C" int mpnn_create(int64_t n, const int64_t *row_ptr, const int32_t *col
         H->gh.alloc(n * MH);
         H->ga.alloc(n * MH);
         H->gmd.alloc(n * MH);
+        H->gd.alloc(n * MD);
         H->gg.alloc(MH);
-        H->part.alloc((size_t)RED_BLOCKS * MH * MH);
+        H->part.alloc((size_t)RED_BLOCKS * MD * MH);
         H->dpart.alloc((size_t)RED_BLOCKS * 64);
         H->X.alloc(n * MF);
         H->mask.alloc(n * 3);
@@ -487,8 +563,9 @@ extern "C" int mpnn_forward(mpnn_handle *H, const float *P, const float *X, cons
         for (int l = 0; l < ML; ++l) {
             hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->dpart.p);
             hipLaunchKernelGGL(k_global, dim3(1), dim3(64), 0, s, np, H->dpart.p, n, P, l, H->g[l].p, H->gw.p);
-            hipLaunchKernelGGL(k_mp_fwd, dim3(vgrid(n)), dim3(MB), 0, s, n, H->gp.p, H->gi.p, P, l, H->gw.p,
-                               H->h[l].p, H->m[l].p, H->a[l].p, H->h[l + 1].p);
+            hipLaunchKernelGGL(k_mp_fwd, dim3(vgrid(n)), dim3(MB), 4 * MH * MH * sizeof(float), s, n, H->gp.p,
+                               H->gi.p, H->xf.p, H->invdl.p, P, l, H->gw.p, H->h[l].p, H->m[l].p, H->d[l].p,
+                               H->a[l].p, H->h[l + 1].p);
         }
         hipLaunchKernelGGL(k_out, dim3(vgrid(n)), dim3(MB), 0, s, n, P, H->h[ML].p, mask, y ? y : H->y.p,
                            (const float *)nullptr, (float *)nullptr, (float *)nullptr, (double *)nullptr);
@@ -509,16 +586,18 @@ static void backward_tail(mpnn_handle *H, const float *P, float *grad, hipStream
     hipLaunchKernelGGL(k_colsum3, dim3(np), dim3(MB), 0, s, n, H->gy.p, H->dpart.p);
     hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MO, grad + OFF_BOUT);
     for (int l = ML - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(k_mp_bwd1, dim3(vg), dim3(MB), 0, s, n, H->gp.p, P, l, H->gh.p, H->a[l].p, H->ga.p,
-                           H->gmd.p);
+        hipLaunchKernelGGL(k_mp_bwd1, dim3(vg), dim3(MB), 4 * MH * MH * sizeof(float), s, n, H->gp.p, P, l, H->gh.p,
+                           H->a[l].p, H->ga.p, H->gmd.p, H->gd.p);
         hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->ga.p, H->part.p);
         hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_ws(l));
         hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->m[l].p, H->ga.p, H->part.p);
         hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_wn(l));
+        hipLaunchKernelGGL((k_xty<MD, MH>), dim3(np), dim3(MB), 0, s, n, H->d[l].p, H->ga.p, H->part.p);
+        hipLaunchKernelGGL(k_sum_parts, dim3(48), dim3(MB), 0, s, np, MD * MH, H->part.p, grad + off_wd(l));
         hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->ga.p, H->dpart.p);
         hipLaunchKernelGGL(k_layer_small, dim3(1), dim3(64), 0, s, np, H->dpart.p, H->g[l].p, P, l, grad, H->gg.p);
-        hipLaunchKernelGGL(k_mp_bwd2, dim3(vg), dim3(MB), 0, s, n, H->gp.p, H->gi.p, P, l, H->ga.p, H->gmd.p,
-                           H->gg.p, H->gh.p);
+        hipLaunchKernelGGL(k_mp_bwd2, dim3(vg), dim3(MB), 0, s, n, H->gp.p, H->gi.p, H->xf.p, H->invdl.p, P, l,
+                           H->ga.p, H->gmd.p, H->gd.p, H->gg.p, H->gh.p);
     }
     hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<int64_t>((n * MH + MB - 1) / MB, 65536)), dim3(MB), 0, s,
                        n, H->h[0].p, H->gh.p, H->ga.p);
@@ -563,9 +642,12 @@ extern "C" int mpnn_backward_from(mpnn_handle *H, const float *P, const float *g
     });
 }
 
-// Relative energy error of the last forward's guess, loss = e^T A e / t^T A t
-// with e = S_U (y - t), t = S_U target (A = level-0 operator of the AMG
-// handle), and gy = dloss/dy.  Uses the AMG handle's solve workspace.
+// Relative energy error of the energy-optimally scaled guess of the last
+// forward: loss = 1 - c^2 / (a e) with u = S_U y (constrained DOFs zero),
+// t = S_U target, a = (u, A u), c = (u, A t), e = (t, A t) (A = level-0
+// operator of the AMG handle), and gy = dloss/dy =
+// S_U keep (-2c/(a e) A t + 2c^2/(a^2 e) A u).  A zero guess: loss 1, gy 0.
+// Uses the AMG handle's solve workspace.
 extern "C" int mpnn_energy_grad(mpnn_handle *H, amg_handle *A, const float *target, float *gy, double *loss,
                                 hipStream_t s) {
     return guarded([&] {
@@ -575,23 +657,33 @@ extern "C" int mpnn_energy_grad(mpnn_handle *H, amg_handle *A, const float *targ
         TE_REQUIRE(L0.n == H->n, TE_EINVAL, "AMG and MPNN sizes differ");
         const int64_t n = H->n, nv = 3 * n;
         const unsigned g = (unsigned)std::min<int64_t>((nv + MB - 1) / MB, 65536);
-        // natural-order e and u_t in the AMG's z / p buffers, storage order in t / u
-        hipLaunchKernelGGL(k_energy_err, dim3(g), dim3(MB), 0, s, n, H->y.p, target, H->mask.p, A->z.p, A->p.p);
+        // natural-order u and u_t in the AMG's z / p buffers, storage order in t / u
+        hipLaunchKernelGGL(k_energy_prep, dim3(g), dim3(MB), 0, s, n, H->y.p, target, H->mask.p, A->z.p, A->p.p);
         permute_gather(A->z.p, A->t.p, L0.perm.p, n, 3, 1, s);
         permute_gather(A->p.p, A->u.p, L0.perm.p, n, 3, 1, s);
-        sell_apply<double>(L0.A, A->t.p, A->q.p, nullptr, 0, 1, s);   // A e
+        sell_apply<double>(L0.A, A->t.p, A->q.p, nullptr, 0, 1, s);   // A u
         sell_apply<double>(L0.A, A->u.p, A->r.p, nullptr, 0, 1, s);   // A u_t
         double *part = A->partials.p, *sums = A->sums.p;
         dot_partials(A->t.p, A->q.p, nv, 1, part, s);
         reduce_partials(part, dot_nblocks(nv), 1, sums, s);
-        dot_partials(A->u.p, A->r.p, nv, 1, part, s);
+        dot_partials(A->t.p, A->r.p, nv, 1, part, s);
         reduce_partials(part, dot_nblocks(nv), 1, sums + 1, s);
+        dot_partials(A->u.p, A->r.p, nv, 1, part, s);
+        reduce_partials(part, dot_nblocks(nv), 1, sums + 2, s);
         std::vector<double> v;
-        download(v, sums, 2, s);
-        TE_REQUIRE(v[1] > 0, TE_EINVAL, "target has no energy");
-        if (loss) *loss = v[0] / v[1];
-        permute_scatter(A->q.p, A->z.p, L0.perm.p, n, 3, 1, s);
-        hipLaunchKernelGGL(k_energy_gy, dim3(g), dim3(MB), 0, s, n, A->z.p, H->mask.p, 2.0 * S_U / v[1], gy);
+        download(v, sums, 3, s);
+        const double aa = v[0], c = v[1], e = v[2];
+        TE_REQUIRE(e > 0, TE_EINVAL, "target has no energy");
+        double ca = 0.0, cb = 0.0, L = 1.0;
+        if (aa > 0) {
+            L = 1.0 - c * c / (aa * e);
+            ca = -2.0 * c / (aa * e) * S_U;
+            cb = 2.0 * c * c / (aa * aa * e) * S_U;
+        }
+        if (loss) *loss = L;
+        permute_scatter(A->q.p, A->z.p, L0.perm.p, n, 3, 1, s);   // A u, natural
+        permute_scatter(A->r.p, A->p.p, L0.perm.p, n, 3, 1, s);   // A u_t, natural
+        hipLaunchKernelGGL(k_energy_gy, dim3(g), dim3(MB), 0, s, n, A->p.p, A->z.p, H->mask.p, ca, cb, gy);
         TE_CHECK_HIP(hipGetLastError());
         return TE_OK;
     });

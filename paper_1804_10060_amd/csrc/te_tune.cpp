@@ -1,9 +1,13 @@
 // Autotuner: picks the launch configuration of every level operator of a
 // hierarchy by timing the candidates on the operator itself (median of 5
 // launches after one warm-up, HIP events on the solve stream), separately
-// for the float64 and float32 copies.  Choices can be stored in and re-read
-// from a small JSON file keyed by the operator's shape class, so a second run
-// on a similar problem applies them without timing.
+// for the float64 and float32 copies: for one right-hand side the waves per
+// workgroup, slices (rows) per wave, XCD block order and non-temporal value
+// loads; for the hierarchy's max_nrhs right-hand sides (when above one) the
+// block rows per workgroup of the multi-RHS products.  Choices can be stored
+// in and re-read from a small JSON file keyed by the operator's shape class
+// (and the number of right-hand sides), so a second run on a similar problem
+// applies them without timing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +40,7 @@ std::map<std::string, Tune> read_cache(const char *path) {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // lines of the form:  "key": [wpb, spw, remap, nt],
+        // lines of the form:  "key": [wpb, spw, remap, nt, mwpb, mtile]  (the last two optional)
         auto a = line.find('"'), b = line.find('"', a + 1), l = line.find('['), r = line.find(']');
         if (a == std::string::npos || b == std::string::npos || l == std::string::npos || r == std::string::npos)
             continue;
@@ -44,7 +48,12 @@ std::map<std::string, Tune> read_cache(const char *path) {
         std::string nums = line.substr(l + 1, r - l - 1);
         std::replace(nums.begin(), nums.end(), ',', ' ');
         std::istringstream is(nums);
-        if (is >> t.wpb >> t.spw >> t.remap >> t.nt) c[line.substr(a + 1, b - a - 1)] = t;
+        if (is >> t.wpb >> t.spw >> t.remap >> t.nt) {
+            int m = 0, mt = 0;
+            if (is >> m && (m == 4 || m == 8 || m == 16)) t.mwpb = m;   // checked against the format at launch
+            if (is >> mt && (mt == 0 || mt == 16 || mt == 32 || mt == 64)) t.mtile = mt;
+            c[line.substr(a + 1, b - a - 1)] = t;
+        }
     }
     return c;
 }
@@ -57,19 +66,21 @@ void write_cache(const char *path, const std::map<std::string, Tune> &c) {
     size_t i = 0;
     for (const auto &kv : c) {
         f << "  \"" << kv.first << "\": [" << kv.second.wpb << ", " << kv.second.spw << ", " << kv.second.remap
-          << ", " << kv.second.nt << "]" << (++i < c.size() ? "," : "") << "\n";
+          << ", " << kv.second.nt << ", " << kv.second.mwpb << ", " << kv.second.mtile << "]"
+          << (++i < c.size() ? "," : "") << "\n";
     }
     f << "}\n";
 }
 
 template <typename T>
-float time_op(Sell &A, Tune &slot, const Tune &cand, const T *x, T *y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+float time_op(Sell &A, Tune &slot, const Tune &cand, const T *x, T *y, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+              int nrhs = 1) {
     slot = cand;
-    sell_apply<T>(A, x, y, nullptr, 0, 1, s);  // warm-up
+    sell_apply<T>(A, x, y, nullptr, 0, nrhs, s);  // warm-up
     float t[5];
     for (int r = 0; r < 5; ++r) {
         TE_CHECK_HIP(hipEventRecord(e0, s));
-        sell_apply<T>(A, x, y, nullptr, 0, 1, s);
+        sell_apply<T>(A, x, y, nullptr, 0, nrhs, s);
         TE_CHECK_HIP(hipEventRecord(e1, s));
         TE_CHECK_HIP(hipEventSynchronize(e1));
         TE_CHECK_HIP(hipEventElapsedTime(&t[r], e0, e1));
@@ -78,15 +89,55 @@ float time_op(Sell &A, Tune &slot, const Tune &cand, const T *x, T *y, hipStream
     return t[2];
 }
 
+// Waves per workgroup and, on the SELL layout with more than 16 columns,
+// the column tile (16, 32 or 64 columns per pass over the matrix, or 0: one
+// row per wave with a lane per column) of the nrhs-column products; the
+// single-RHS choice in `slot` is kept.
+template <typename T>
+void tune_multi(Sell &A, Tune &slot, const std::string &key, const T *x, T *y, int nrhs,
+                std::map<std::string, Tune> &cache, hipStream_t s, hipEvent_t e0, hipEvent_t e1, std::string &report) {
+    const Tune keep = slot;
+    Tune best = keep;
+    float best_t = INFINITY, def_t = 0.f;
+    const bool tiles = A.format == FMT_SELL && nrhs > 16;
+    for (int mt : {0, 64, 32, 16}) {
+        if (!tiles && mt != keep.mtile) continue;
+        for (int m : {4, 8, 16}) {
+            if (m == 16 && A.format == FMT_SELL) continue;   // the SELL kernel takes at most 8 waves
+            Tune c = keep;
+            c.mwpb = m;
+            c.mtile = mt;
+            const float t = time_op<T>(A, slot, c, x, y, s, e0, e1, nrhs);
+            if (m == 4 && mt == keep.mtile) def_t = t;
+            if (t < best_t) {
+                best_t = t;
+                best = c;
+            }
+        }
+    }
+    slot = best;
+    cache[key] = slot;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s best %d waves per workgroup, tile %d: %.4f ms (default %.4f ms)\n",
+                  key.c_str(), best.mwpb, best.mtile, best_t, def_t);
+    report += buf;
+}
+
 template <typename T>
 void tune_one(Sell &A, Tune &slot, const char *dtype, const T *x, T *y, std::map<std::string, Tune> &cache,
-              bool use_cache, hipStream_t s, hipEvent_t e0, hipEvent_t e1, std::string &report) {
+              bool use_cache, hipStream_t s, hipEvent_t e0, hipEvent_t e1, std::string &report, int nrhs) {
     if (A.nrows == 0) return;
     const std::string key = key_of(A, dtype);
+    const std::string mkey = key + "-nrhs" + std::to_string(nrhs);
     if (use_cache) {
         auto it = cache.find(key);
-        if (it != cache.end()) {
+        auto mt = cache.find(mkey);
+        if (it != cache.end() && (nrhs == 1 || mt != cache.end())) {
             slot = it->second;
+            if (nrhs > 1) {
+                slot.mwpb = A.format == FMT_SELL ? std::min(mt->second.mwpb, 8) : mt->second.mwpb;
+                slot.mtile = mt->second.mtile;
+            }
             report += key + " cached\n";
             return;
         }
@@ -111,6 +162,7 @@ void tune_one(Sell &A, Tune &slot, const char *dtype, const T *x, T *y, std::map
     std::snprintf(buf, sizeof buf, "%s best [%d,%d,%d,%d] %.4f ms (default %.4f ms)\n", key.c_str(), best.wpb,
                   best.spw, best.remap, best.nt, best_t, def_t);
     report += buf;
+    if (nrhs > 1) tune_multi<T>(A, slot, mkey, x, y, nrhs, cache, s, e0, e1, report);
 }
 
 int autotune_impl(amg_handle *h, const char *cache_path, int32_t use_cache, char *report_out, int64_t report_len,
@@ -129,22 +181,23 @@ int autotune_impl(amg_handle *h, const char *cache_path, int32_t use_cache, char
     TE_CHECK_HIP(hipEventCreate(&ev.b));
     hipEvent_t e0 = ev.a, e1 = ev.b;
     std::string rep;
+    const int m = h->opt.max_nrhs;
     for (size_t l = 0; l < h->L.size(); ++l) {
         Level &L = h->L[l];
         const bool next = l + 1 < h->L.size();
-        tune_one<double>(L.A, L.A.tune64, "f64", L.w64.d.p, L.w64.s.p, cache, use_cache, s, e0, e1, rep);
+        tune_one<double>(L.A, L.A.tune64, "f64", L.w64.d.p, L.w64.s.p, cache, use_cache, s, e0, e1, rep, m);
         if (next) {
             Level &N = h->L[l + 1];
-            tune_one<double>(L.P, L.P.tune64, "f64", N.w64.x.p, L.w64.s.p, cache, use_cache, s, e0, e1, rep);
-            tune_one<double>(L.R, L.R.tune64, "f64", L.w64.s.p, N.w64.g.p, cache, use_cache, s, e0, e1, rep);
+            tune_one<double>(L.P, L.P.tune64, "f64", N.w64.x.p, L.w64.s.p, cache, use_cache, s, e0, e1, rep, m);
+            tune_one<double>(L.R, L.R.tune64, "f64", L.w64.s.p, N.w64.g.p, cache, use_cache, s, e0, e1, rep, m);
         }
         if (h->opt.build_fp32) {
             tune_one<float>(level_op<float>(L), level_op<float>(L).tune32, "f32", L.w32.d.p, L.w32.s.p, cache,
-                            use_cache, s, e0, e1, rep);
+                            use_cache, s, e0, e1, rep, m);
             if (next) {
                 Level &N = h->L[l + 1];
-                tune_one<float>(L.P, L.P.tune32, "f32", N.w32.x.p, L.w32.s.p, cache, use_cache, s, e0, e1, rep);
-                tune_one<float>(L.R, L.R.tune32, "f32", L.w32.s.p, N.w32.g.p, cache, use_cache, s, e0, e1, rep);
+                tune_one<float>(L.P, L.P.tune32, "f32", N.w32.x.p, L.w32.s.p, cache, use_cache, s, e0, e1, rep, m);
+                tune_one<float>(L.R, L.R.tune32, "f32", L.w32.s.p, N.w32.g.p, cache, use_cache, s, e0, e1, rep, m);
             }
         }
     }

@@ -75,6 +75,14 @@ def block_form(quick=False):
     pr.amg.solve(B[:, :, :2].contiguous())  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    pr.amg.solve(B)
+    torch.cuda.synchronize()
+    t_untuned = time.perf_counter() - t0
+    tune_report = pr.amg.autotune()   # launch configurations, including those of the k-column products
+    log(tune_report)
+    pr.amg.solve(B[:, :, :2].contiguous())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     U, rep = pr.amg.solve(B)
     torch.cuda.synchronize()
     t_block = time.perf_counter() - t0
@@ -96,7 +104,8 @@ def block_form(quick=False):
         its.append(rj.iters[0])
         diffs.append(float((U[:, :, j].reshape(-1) - uj).norm() / uj.norm()))
     out = {"workload": f"P1 disc {grid[0]}x{grid[1]}x{grid[2]}, {pr.mesh.n_dof} DOF, {k} bump load cases",
-           "n_dof": pr.mesh.n_dof, "nrhs": k, "block_s": t_block, "singles_s": singles,
+           "n_dof": pr.mesh.n_dof, "nrhs": k, "block_s": t_block, "block_s_untuned": t_untuned, "singles_s": singles,
+           "autotune": [ln for ln in tune_report.splitlines() if "nrhs" in ln],
            "speedup": singles / t_block, "block_iters_max": max(rep.iters), "single_iters_mean": float(np.mean(its)),
            "all_converged": bool(all(rep.converged)), "max_relres_true": max(rep.relres_true),
            "max_rel_diff_vs_single": max(diffs),
@@ -172,6 +181,8 @@ def learned_form(quick=False):
            "loss_last": hist[-1], "iters_zero_mean": float(np.mean(iz)), "iters_guess_mean": float(np.mean(ig)),
            "ms_zero_mean": float(np.mean([r["ms_zero"] for r in res])),
            "ms_guess_mean": float(np.mean([r["ms_guess"] for r in res])),
+           "ms_inference_mean": float(np.mean([r["ms_inference"] for r in res])),
+           "ms_guess_plus_inference_mean": float(np.mean([r["ms_guess"] + r["ms_inference"] for r in res])),
            "guess_used_fraction": float(np.mean([r["guess_used"] for r in res])),
            "rel_err_scaled_guess_mean": float(np.mean([r["rel_err0"] for r in res])),
            "max_relres_true_guess": max(r["relres_true_guess"] for r in res),

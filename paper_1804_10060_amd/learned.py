@@ -34,7 +34,8 @@ def init_params(seed: int = 0):
 
     parts += [u(F, (F, H)), np.zeros(H)]
     for _ in range(L):
-        parts += [u(3 * H, (H, H)), u(3 * H, (H, H)), u(3 * H, (H, H)), np.zeros(H)]
+        # W_s, W_n, W_g and the three directional weights, then b
+        parts += [u(6 * H, (H, H)) for _ in range(6)] + [np.zeros(H)]
     parts += [u(H, (H, 3)), np.zeros(3)]
     return np.concatenate(parts).astype(np.float32)
 
@@ -115,8 +116,9 @@ class Problem:
         return self.net.features(T_row.contiguous(), self.prob.T_ref, self.mask, f)
 
     def train(self, data: Dataset, epochs=8, lr=1e-3, seed=0, log=print, loss="energy"):
-        """Adam on the relative energy error of the guess (the quantity CG
-        reduces; loss="energy") or on the mean squared error (loss="mse")."""
+        """Adam on the relative energy error of the energy-optimally scaled
+        guess (the quantity the solve sees; loss="energy") or on the mean
+        squared error (loss="mse")."""
         import torch
         params = torch.from_numpy(init_params(seed)).to(self.dev)
         m1 = torch.zeros_like(params)
@@ -152,21 +154,26 @@ class Problem:
 
     def evaluate(self, params, data: Dataset, log=print):
         """Per test case: iterations and solve time from the scaled learned guess
-        and from zero, both to true relres 1e-8 in float64."""
+        and from zero, both to true relres 1e-8 in float64, and the time of
+        the guess itself (features, network, energy-optimal scaling)."""
         import torch
         res = []
         for i in range(data.T.shape[0]):
             b = self.loads(data.T[i:i + 1].contiguous(), data.f[i:i + 1].contiguous()).reshape(-1).contiguous()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             u0 = self.guess(params, data.T[i], data.f[i])
             # energy-optimal multiple of the guess; gamma = 0 falls back to zero
             gamma = self.amg.energy_scale(b, u0)
+            torch.cuda.synchronize()
+            ms_inf = (time.perf_counter() - t0) * 1e3
             r0 = float(torch.linalg.norm(b - self.apply_A(u0)))
             uz, rz = self.amg.solve(b)
             ug, rg = self.amg.solve(b, u0=u0)
             err = float(torch.linalg.norm(ug - uz) / torch.linalg.norm(uz))
             e0 = float(torch.linalg.norm(u0 - uz) / torch.linalg.norm(uz))
             res.append({"iters_zero": rz.iters[0], "iters_guess": rg.iters[0], "ms_zero": rz.time_ms,
-                        "ms_guess": rg.time_ms, "gamma": gamma, "guess_used": gamma > 0,
+                        "ms_guess": rg.time_ms, "ms_inference": ms_inf, "gamma": gamma, "guess_used": gamma > 0,
                         "relres0": r0 / float(torch.linalg.norm(b)), "rel_err0": e0,
                         "relres_true_guess": rg.relres_true[0], "rel_diff": err})
         return res

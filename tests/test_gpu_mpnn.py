@@ -44,6 +44,7 @@ def small():
     X = net.features(dev(T, torch.float64), prob.T_ref, d["mask"], dev(f, torch.float64))
     Xo = om.features(m.coords, T, prob.T_ref, f, prob.mask)
     ptr, nbr = om.vertex_graph(m.cells, m.n_nodes)
+    w = om.direction_weights(m.coords, ptr, nbr)
     p32 = _flatten(om.init_params(1)).astype(np.float32)
     rng2 = np.random.default_rng(4)
     # non-zero biases so both ReLU branches occur
@@ -54,7 +55,7 @@ def small():
     p32 = _flatten(po).astype(np.float32)
     po = _unflatten(p32)
     target = (rng.normal(size=(m.n_nodes, 3)) * (1 - prob.mask)).astype(np.float32)
-    return dict(prob=prob, net=net, X=X, Xo=Xo, ptr=ptr, nbr=nbr, p32=p32, po=po, target=target, d=d)
+    return dict(prob=prob, net=net, X=X, Xo=Xo, ptr=ptr, nbr=nbr, w=w, p32=p32, po=po, target=target, d=d)
 
 
 def test_features_match_oracle(small):
@@ -66,7 +67,8 @@ def test_forward_matches_oracle(small):
     torch = torch_cuda()
     s = small
     y = s["net"].forward(dev(s["p32"]), s["X"], s["d"]["mask"]).cpu().numpy()
-    yo, _ = om.forward(s["po"], s["X"].cpu().numpy().astype(np.float64), s["ptr"], s["nbr"], s["prob"].mask)
+    yo, _ = om.forward(s["po"], s["X"].cpu().numpy().astype(np.float64), s["ptr"], s["nbr"], s["prob"].mask,
+                       s["w"])
     err = np.linalg.norm(y - yo) / np.linalg.norm(yo)
     say(f"mpnn forward rel err {err:.2e}")
     assert err <= 1e-4
@@ -79,8 +81,8 @@ def test_gradients_match_oracle(small):
     g, loss = s["net"].backward(P, dev(s["target"]))
     g = g.cpu().numpy()
     Xo = s["X"].cpu().numpy().astype(np.float64)
-    yo, cache = om.forward(s["po"], Xo, s["ptr"], s["nbr"], s["prob"].mask)
-    go = om.backward(s["po"], Xo, s["ptr"], s["nbr"], cache, yo, s["target"].astype(np.float64))
+    yo, cache = om.forward(s["po"], Xo, s["ptr"], s["nbr"], s["prob"].mask, s["w"])
+    go = om.backward(s["po"], Xo, s["ptr"], s["nbr"], s["w"], cache, yo, s["target"].astype(np.float64))
     lo = om.loss(yo, s["target"].astype(np.float64))
     assert abs(loss - lo) <= 1e-5 * lo
     gg = _unflatten(g)
@@ -100,22 +102,29 @@ def test_backward_from_gradient_and_energy_loss_match_oracle(small):
     gy = rng.normal(size=(s["prob"].mesh.n_nodes, 3)).astype(np.float32)
     g = s["net"].backward_from(P, dev(gy)).cpu().numpy()
     Xo = s["X"].cpu().numpy().astype(np.float64)
-    yo, cache = om.forward(s["po"], Xo, s["ptr"], s["nbr"], s["prob"].mask)
-    go = om.backward_from(s["po"], Xo, s["ptr"], s["nbr"], cache, gy.astype(np.float64))
+    yo, cache = om.forward(s["po"], Xo, s["ptr"], s["nbr"], s["prob"].mask, s["w"])
+    go = om.backward_from(s["po"], Xo, s["ptr"], s["nbr"], s["w"], cache, gy.astype(np.float64))
     gg = _unflatten(g)
     for k in om.PARAM_ORDER:
         e = np.linalg.norm(gg[k] - go[k]) / max(np.linalg.norm(go[k]), 1e-30)
         assert e <= 1e-4, f"{k}: {e:.2e}"
-    # energy loss and its gradient, with the library operator vs the oracle's
+    # energy loss and its gradient at the GPU's own output y, with the library
+    # operator vs the oracle's: float64 arithmetic on the same y, so the loss
+    # agrees to rounding (the operators agree to 1e-13) and the float32
+    # gradient to its rounding
     prob = s["prob"]
     A, b, d = gpu_assemble(prob)
     h = te.AMG(A, d["coords"], d["mask"])
-    s["net"].forward(P, s["X"], s["d"]["mask"])
+    y32 = s["net"].forward(P, s["X"], s["d"]["mask"]).cpu().numpy().astype(np.float64)
     gy_e, L = s["net"].energy_grad(h, dev(s["target"]))
     Ao, _, _, _ = fem.assemble_problem(prob)
-    Lo, gyo = om.energy_loss(yo, s["target"].astype(np.float64), Ao, 1.0 - prob.mask)
-    assert abs(L - Lo) <= 1e-5 * Lo
-    assert np.linalg.norm(gy_e.cpu().numpy() - gyo) <= 1e-5 * np.linalg.norm(gyo)
+    Lo, gyo = om.energy_loss(y32, s["target"].astype(np.float64), Ao, 1.0 - prob.mask)
+    say(f"energy loss {L:.6e} vs oracle {Lo:.6e}")
+    assert abs(L - Lo) <= 1e-10
+    assert np.linalg.norm(gy_e.cpu().numpy() - gyo) <= 1e-6 * np.linalg.norm(gyo)
+    # and the oracle's loss at its own float64 output is close (forward error 1e-5)
+    Lf, _ = om.energy_loss(yo, s["target"].astype(np.float64), Ao, 1.0 - prob.mask)
+    assert abs(L - Lf) <= 1e-4 * max(Lf, 1e-3)
 
 
 def test_adam_step_matches_oracle(small):
@@ -137,12 +146,12 @@ def test_adam_step_matches_oracle(small):
     assert np.abs(P.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
-def test_trained_guess_never_hurts_and_reports_gain():
+def test_trained_guess_reduces_iterations():
     """Train on 192 method-generated solves of a small disc, test on 16
-    held-out fields.  Guaranteed by construction: the energy-scaled guess is
-    never worse than zero in the energy norm, and the solve from it reaches
-    the same true residual and solution.  The iteration gain is measured and
-    reported (a 4-hop network sees little of the global elastic response)."""
+    held-out fields: the energy-scaled guess takes strictly fewer iterations
+    on average than the zero guess.  Guaranteed by construction besides: the
+    scaled guess is never worse than zero in the energy norm, and the solve
+    from it reaches the same true residual and solution."""
     from paper_1804_10060_amd import learned
     torch = torch_cuda()
     pr = learned.Problem(16, 68, 3, max_nrhs=64)
@@ -166,4 +175,9 @@ def test_trained_guess_never_hurts_and_reports_gain():
         pr.amg.energy_scale(b, u0)
         J = 0.5 * float(u0 @ pr.apply_A(u0)) - float(b @ u0)
         assert J <= 1e-12 * float(b.norm()) * float(u0.norm() + 1e-300)
-    assert ig <= iz + 1.0
+    # the gain on the held-out fields: strictly fewer iterations on average
+    # than from zero (the time, inference included, is measured at the full
+    # size by forms.py learned)
+    say(f"solve ms from the guess {np.mean([r['ms_guess'] for r in res]):.3f} + inference "
+        f"{np.mean([r['ms_inference'] for r in res]):.3f} vs from zero {np.mean([r['ms_zero'] for r in res]):.3f}")
+    assert ig < iz
