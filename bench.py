@@ -56,6 +56,15 @@ def algorithmic_bytes(info, n_rows, nnzb0, vt=8):
     return out
 
 
+def algorithmic_bytes_multi(n_rows, nnzb0, m, vt=8):
+    """The mesh-level classes of an m-column solve: the matrix once, every
+    per-column vector m times, D^-1 (one per row) once."""
+    mat = nnzb0 * (9 * vt + 4) + n_rows * 4
+    v = 3 * vt * n_rows
+    return {"Ap": mat + 2 * v * m, "pre_smooth": mat + 3 * v * m + v, "residual": mat + 3 * v * m,
+            "post_init": mat + 4 * v * m + v, "post_smooth": mat + 4 * v * m + v}
+
+
 def cpu_baseline(sample_grid=(48, 208, 6, 2)):
     """The oracle in its C++17/OpenMP form (float64, the same algorithm and
     rtol) on all host cores the process may use, on a bounded sample of the
@@ -119,6 +128,7 @@ def block_rhs_form(te, torch, dev):
     import numpy as np
 
     import meshgen as mg
+    from paper_1804_10060_amd._lib import KERNEL_CLASSES
     from tests import golden_c2
     prob = mg.disc_problem(*mg.DISC_P1_2M, seed=0)
     m = prob.mesh
@@ -138,6 +148,19 @@ def block_rhs_form(te, torch, dev):
     U, rep = h.solve(B)
     torch.cuda.synchronize()
     t_multi = time.perf_counter() - t0
+    # per-class times of the 64-column mesh-level products (HIP events)
+    _, prep = h.solve(B, profile=True)
+    algo = algorithmic_bytes_multi(m.n_nodes, A.nnzb, B.shape[2])
+    spmm = {}
+    for i, name in enumerate(KERNEL_CLASSES):
+        if name in algo and prep.kernel_launches[i]:
+            avg = prep.kernel_ms[i] / prep.kernel_launches[i]
+            spmm[name] = {"avg_ms": round(avg, 4), "algo_bytes": int(algo[name]),
+                          "GBps": round(algo[name] / (avg * 1e-3) / 1e9, 1)}
+    dom = max(spmm, key=lambda k: spmm[k]["avg_ms"] * prep.kernel_launches[KERNEL_CLASSES.index(k)])
+    spmm_roofline = {"bound": "hbm", "kernel": dom, "achieved": spmm[dom]["GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(spmm[dom]["GBps"] / HBM_PEAK_GBS, 4),
+                     "algo_bytes_per_launch": spmm[dom]["algo_bytes"]}
     t0 = time.perf_counter()
     Ub, repb = h.solve(B, block=True)
     torch.cuda.synchronize()
@@ -165,7 +188,8 @@ def block_rhs_form(te, torch, dev):
            "single_iters_mean": float(np.mean(its)), "all_converged": bool(all(rep.converged)),
            "max_relres_true": max(rep.relres_true), "block_cg_ms": round(t_bcg * 1e3, 2),
            "block_cg_iters": repb.iters[0], "block_cg_speedup_vs_fp64_singles": round(t_single / t_bcg, 3),
-           "dof_rhs_per_s": n * len(seeds) / t_multi, "err_vs_oracle": err}
+           "dof_rhs_per_s": n * len(seeds) / t_multi, "err_vs_oracle": err,
+           "spmm_kernels": spmm, "spmm_roofline": spmm_roofline}
     log(f"block rhs: 64 columns {t_multi * 1e3:.1f} ms, block CG {t_bcg * 1e3:.1f} ms, singles "
         f"{t_single * 1e3:.1f} ms; errors {err}")
     return out
@@ -209,6 +233,32 @@ def thermal_form(torch, dev, elastic_ms):
         out["err_vs_oracle"] = {"sampled": es, "projected": ep, "newton_iters": rep.iters,
                                 "oracle_newton_iters": g["iters"], "oracle_lin_iters": g["lin_iters"]}
     log(f"thermal: {wall * 1e3:.1f} ms, Newton {rep.iters}, CG {rep.lin_iters}; {out.get('err_vs_oracle')}")
+    return out
+
+
+def learned_form_small(torch):
+    """The learned initial guess at a size the bench can afford: a P1 disc of
+    13,872 DOF, the network trained by the library's kernels on 192 solves the
+    library generates, then 16 held-out load fields solved from the scaled
+    guess and from zero (the 1M-DOF protocol is forms.py learned)."""
+    import numpy as np
+
+    from paper_1804_10060_amd import learned
+    pr = learned.Problem(16, 68, 3, max_nrhs=64, aggregation="greedy")
+    train = pr.generate(list(range(10000, 10192)), log=lambda *a: None)
+    test = pr.generate(list(range(20000, 20016)), log=lambda *a: None)
+    params, hist, t_train = pr.train(train, epochs=24, lr=2e-3, log=lambda *a: None)
+    res = pr.evaluate(params, test)
+    out = {"workload": f"P1 disc 16x68x3, {pr.mesh.n_dof} DOF; 192 train / 16 held-out load fields",
+           "training_s": round(t_train, 2), "loss_first": hist[0], "loss_last": hist[-1],
+           "iters_zero_mean": float(np.mean([r["iters_zero"] for r in res])),
+           "iters_guess_mean": float(np.mean([r["iters_guess"] for r in res])),
+           "ms_zero_mean": float(np.mean([r["ms_zero"] for r in res])),
+           "ms_guess_mean": float(np.mean([r["ms_guess"] for r in res])),
+           "ms_inference_mean": float(np.mean([r["ms_inference"] for r in res])),
+           "max_relres_true_guess": max(r["relres_true_guess"] for r in res),
+           "max_rel_diff_vs_zero_start": max(r["rel_diff"] for r in res)}
+    log(f"learned (small): {out['iters_guess_mean']:.2f} vs {out['iters_zero_mean']:.2f} iterations")
     return out
 
 
@@ -431,6 +481,7 @@ def main():
         forms["thermal_steady"] = thermal_form(torch, dev, ms_per_step)
         forms["block_rhs_64"] = block_rhs_form(te, torch, dev)
         forms["multi_mesh_32"] = multi_mesh_form(te, torch, dev)
+        forms["learned_guess_small"] = learned_form_small(torch)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -291,66 +291,85 @@ __global__ void __launch_bounds__(TB) k_split_fill(int64_t n, const int64_t *__r
 // One l1 hybrid Gauss-Seidel sweep, eight blocks of B rows per wave: the
 // eight lanes of block g run its rows in order (ascending or descending),
 // each row's in-block entries eight at a time, the products summed across
-// the eight lanes by sum8; the block's x sits in LDS, and the entries, o and
-// 1/d of the next row are loaded while the current row runs.  o holds
-// g - (entries outside the block) x_in, or g when x_in is NULL (x_in = 0).
-// x_out may be x_in: a block reads only its own rows of x_in.
-// PF: entries per lane held for the next row (8 PF per row; chosen per level
-// from its longest in-block row, longer rows read the rest in the chain).
-template <int PF>
+// the eight lanes by sum8; the block's x and row offsets sit in LDS.  The row chain (LDS
+// read, FMA, three DPP steps, LDS write) is far shorter than a memory
+// latency, so the entries, o and 1/d of the next D rows are kept in flight
+// in a ring of registers: row t's slot is refilled with row t + D as soon
+// as row t starts.  o holds g - (entries outside the block) x_in, or g when
+// x_in is NULL (x_in = 0).  x_out may be x_in: a block reads only its own
+// rows of x_in.  PF: entries per lane held per row (8 PF per row; chosen per
+// level from its longest in-block row, longer rows read the rest in the
+// chain).
+template <int PF, int D>
 __global__ void __launch_bounds__(64) k_hgs8(int64_t n, int B, const int64_t *__restrict__ pin,
                                              const uint8_t *__restrict__ lin, const double *__restrict__ vin,
                                              const double *__restrict__ idl, const double *__restrict__ o,
                                              const double *x_in, double *x_out, int forward) {
-    extern __shared__ double xs[];   // [8][B]
+    extern __shared__ double xs[];   // [8][B] x, then [8][B + 1] int row offsets
     const int lane = threadIdx.x, g = lane >> 3, l = lane & 7;
     const int64_t b0 = ((int64_t)blockIdx.x * 8 + g) * B;
     const int nb = b0 < n ? (int)min<int64_t>(B, n - b0) : 0;
     double *xb = xs + g * B;
+    // the block's row pointers, relative to its first entry, in LDS: a row's
+    // entry range is then an LDS read, not a load the entry loads wait for
+    int *pb = reinterpret_cast<int *>(xs + 8 * B) + g * (B + 1);
+    const int64_t e0 = nb > 0 ? pin[b0] : 0;
     for (int r = l; r < nb; r += 8) xb[r] = x_in ? x_in[b0 + r] : 0.0;
+    for (int r = l; r <= nb; r += 8) pb[r] = (int)(pin[b0 + r] - e0);
     __syncthreads();
-    // the data of row step t: entries l, l+8, l+16 and the row's o and 1/d
-    int64_t lo = 0, hi = 0;
-    double v[PF] = {}, orow = 0.0, irow = 0.0;
-    int c[PF] = {};
-    auto fetch = [&](int t) {
-        lo = hi = 0;
-        if (t >= nb) return;
-        const int64_t row = b0 + (forward ? t : nb - 1 - t);
-        lo = pin[row];
-        hi = pin[row + 1];
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const int64_t k = lo + l + 8 * u;
-            c[u] = k < hi ? (int)lin[k] : 0;
-            v[u] = k < hi ? vin[k] : 0.0;
-        }
-        orow = o[row];
-        irow = idl[row];
+    struct Slot {
+        int64_t lo, hi;   // the row's in-block entries
+        double v[PF], o, id;
+        int c[PF];
     };
-    fetch(0);
-    for (int t = 0; t < B; ++t) {   // the same trip count in every eighth
-        const int64_t clo = lo, chi = hi;
-        double cv[PF], co = orow, ci = irow;
-        int cc[PF];
+    Slot sl[D];
+    auto fetch = [&](Slot &q, int t) {
+        q.lo = q.hi = 0;
+        q.o = q.id = 0.0;
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
-            cv[u] = v[u];
-            cc[u] = c[u];
+            q.v[u] = 0.0;
+            q.c[u] = 0;
         }
-        fetch(t + 1);
-        double sum = 0.0;
-        if (t < nb) {
+        if (t >= nb) return;
+        const int r = forward ? t : nb - 1 - t;
+        const int64_t row = b0 + r;
+        q.lo = e0 + pb[r];
+        q.hi = e0 + pb[r + 1];
 #pragma unroll
-            for (int u = 0; u < PF; ++u) sum += cv[u] * xb[cc[u]];
-            for (int64_t k = clo + l + 8 * PF; k < chi; k += 8) sum += vin[k] * xb[lin[k]];
+        for (int u = 0; u < PF; ++u) {
+            const int64_t k = q.lo + l + 8 * u;
+            if (k < q.hi) {
+                q.c[u] = (int)lin[k];
+                q.v[u] = vin[k];
+            }
         }
-        sum = sum8(sum);
-        if (t < nb && l == 0) {
-            const int r = forward ? t : nb - 1 - t;
-            xb[r] += (co - sum) * ci;
+        q.o = o[row];
+        q.id = idl[row];
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) fetch(sl[d], d);
+    for (int t0 = 0; t0 < B; t0 += D) {   // the same trip count in every eighth
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const int t = t0 + d;
+            const Slot cur = sl[d];
+            fetch(sl[d], t + D);
+            if (t < B) {   // uniform
+                double sum = 0.0;
+                if (t < nb) {
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) sum += cur.v[u] * xb[cur.c[u]];
+                    for (int64_t k = cur.lo + l + 8 * PF; k < cur.hi; k += 8) sum += vin[k] * xb[lin[k]];
+                }
+                sum = sum8(sum);
+                if (t < nb && l == 0) {
+                    const int r = forward ? t : nb - 1 - t;
+                    xb[r] += (cur.o - sum) * cur.id;
+                }
+                __syncthreads();
+            }
         }
-        __syncthreads();
     }
     for (int r = l; r < nb; r += 8) x_out[b0 + r] = xb[r];
 }
@@ -438,12 +457,13 @@ void sweep(camg_handle *h, CLv &L, const double *g, const double *x_in, double *
     const int64_t nblk = (L.n + B - 1) / B;
     const unsigned grid = (unsigned)((nblk + 7) / 8);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), (size_t)8 * B * sizeof(double), s, L.n, B, L.pin.p, L.lin.p,
-                           L.vin.p, L.idl.p, o, x_in, x_out, forward ? 1 : 0);
+        const size_t lds = (size_t)8 * B * sizeof(double) + (size_t)8 * (B + 1) * sizeof(int);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, L.n, B, L.pin.p, L.lin.p, L.vin.p, L.idl.p, o, x_in,
+                           x_out, forward ? 1 : 0);
     };
-    if (L.max_in <= 24) go(k_hgs8<3>);
-    else if (L.max_in <= 64) go(k_hgs8<8>);
-    else go(k_hgs8<16>);
+    if (L.max_in <= 24) go(k_hgs8<3, 4>);
+    else if (L.max_in <= 64) go(k_hgs8<8, 4>);
+    else go(k_hgs8<16, 2>);
     TE_CHECK_HIP(hipGetLastError());
 }
 

@@ -154,6 +154,7 @@ struct Tune {
     int wpb = 4, spw = 1, remap = 1, nt = 0;
     int mwpb = 4;    // several right-hand sides: waves per workgroup
     int mtile = 0;   // several right-hand sides on the SELL layout: columns per pass (0: row per wave)
+    int msplit = 0;  // ... and the column tiles on different XCDs instead of passes
 };
 
 struct Sell {

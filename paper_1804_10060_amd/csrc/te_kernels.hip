@@ -45,23 +45,12 @@ __global__ void __launch_bounds__(512) k_sell1(SellView<VT> A, const XT *__restr
     }
 }
 
-// Several right-hand sides on the SELL layout: R consecutive block rows of
-// one slice per wave, T = 64 / R lanes per row, each lane S right-hand sides
-// (c0 + j, c0 + j + T, ...) of the column tile c0 = blockIdx.y * T * S.  A
-// lane loads its row's block values (vector loads: the R rows of a wave
-// share each 16-byte value piece line) and reuses them for its S columns;
-// the x rows of MU entries are loaded before any is used.  Column tiles are
-// the slowest grid dimension, so the whole matrix runs for one tile before
-// the next and the x rows an XCD gathers (tile width x 24 bytes per node)
-// stay in its L2; the matrix is read once per tile.  The rows of a slice are
-// sorted by descending length, so the first row of the wave bounds the
-// entry loop; shorter rows run over their zero padding blocks (valid
-// columns).  `wpb` waves per workgroup.
-// The other SELL multi-RHS organisation: one wave per block row with the
-// right-hand sides on the lanes (at most 64); the block values are
+// Several right-hand sides on the SELL layout, one wave per block row with
+// the right-hand sides on the lanes (at most 64); the block values are
 // wave-uniform (scalar loads), the row's column indices come 64 at a time
 // and are taken by readlane, and the x rows of 4 entries are loaded before
-// any of them is used.  Chosen by the tuner when it beats the row groups.
+// any of them is used.  The default above 16 columns; the tuner may pick
+// the row groups below instead.
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi>
 __global__ void __launch_bounds__(512) k_sellw(SellView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
                                                double *__restrict__ partials, int wpb) {
@@ -128,6 +117,20 @@ __global__ void __launch_bounds__(512) k_sellw(SellView<VT> A, const XT *__restr
     }
 }
 
+// Several right-hand sides on the SELL layout in row groups: R consecutive
+// block rows of one slice per wave, T = 64 / R lanes per row, each lane S
+// right-hand sides
+// (c0 + j, c0 + j + T, ...) of the column tile c0 = blockIdx.y * T * S.  A
+// lane loads its row's block values (vector loads: the R rows of a wave
+// share each 16-byte value piece line) and reuses them for its S columns;
+// the x rows of MU entries are loaded before any is used.  Column tiles are
+// the slowest grid dimension, so the whole matrix runs for one tile before
+// the next and the x rows an XCD gathers (tile width x 24 bytes per node)
+// stay in its L2; the matrix is read once per tile.  The rows of a slice are
+// sorted by descending length, so the first row of the wave bounds the
+// entry loop; shorter rows run over their zero padding blocks (valid
+// columns).  `wpb` waves per workgroup.  With split_tiles > 0 the column
+// tiles are spread over the XCDs instead (see the kernel).
 template <int BC, int S>
 constexpr int multi_unroll() {
     return BC <= 3 && S <= 2 ? 2 : 1;
@@ -135,16 +138,29 @@ constexpr int multi_unroll() {
 
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, int R, int S>
 __global__ void __launch_bounds__(512) k_sellm(SellView<VT> A, const XT *__restrict__ x, Epi epi, int nrhs,
-                                                double *__restrict__ partials, int wpb) {
+                                                double *__restrict__ partials, int wpb, int split_tiles,
+                                                int64_t split_chunk, int64_t nrb) {
     constexpr int T = WAVE / R, E = BR * BC, MU = multi_unroll<BC, S>();
     constexpr int VW = sell_vw<VT>(), G = E / VW;
     typedef VT vec_t __attribute__((ext_vector_type(VW)));
     __shared__ double lds[16 * WAVE];
-    const int64_t nb = gridDim.x;
-    const int64_t lb = xcd_logical_block(blockIdx.x, nb);
+    int64_t lb;
+    int c0;
+    if (split_tiles) {
+        // workgroup b runs on XCD b % 8: the XCDs are split_tiles column tiles
+        // times 8 / split_tiles row ranges, so the XCDs of one range stream the
+        // same rows (and value lines) at the same time, each for its tile
+        const int xcd = (int)(blockIdx.x & 7);
+        const int64_t i = blockIdx.x >> 3;
+        lb = (int64_t)(xcd / split_tiles) * split_chunk + i;
+        if (i >= split_chunk || lb >= nrb) return;   // the whole workgroup
+        c0 = (xcd % split_tiles) * (T * S);
+    } else {
+        lb = xcd_logical_block(blockIdx.x, gridDim.x);
+        c0 = blockIdx.y * (T * S);
+    }
     const int lane = threadIdx.x & (WAVE - 1);
     const int q = lane / T, w = threadIdx.x / WAVE;
-    const int c0 = blockIdx.y * (T * S);
     const int j = c0 + lane % T;      // first column of the lane
     const int64_t row0 = (lb * wpb + w) * R;
     const int64_t row = row0 + q;
@@ -417,9 +433,17 @@ static void launch_t(const Sell &A, const VT *val, const XT *x, const Epi &epi, 
         const int S = multi_cols(nrhs, t.mtile);
         const int tile = (WAVE / R) * S;
         const unsigned tiles = (unsigned)((nrhs + tile - 1) / tile);
+        dim3 grid((unsigned)g, tiles);
+        int split = 0;
+        int64_t chunk = 0;
+        if (t.msplit && (tiles == 2 || tiles == 4 || tiles == 8)) {
+            split = (int)tiles;
+            chunk = (g + 8 / split - 1) / (8 / split);
+            grid = dim3((unsigned)(8 * chunk), 1);
+        }
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)g, tiles), blk, 0, s, view(A, val), x, epi, nrhs, partials,
-                               t.mwpb);
+            hipLaunchKernelGGL(kern, grid, blk, 0, s, view(A, val), x, epi, nrhs, partials, t.mwpb, split, chunk,
+                               g);
         };
         if (R == 16) go(k_sellm<BR, BC, VT, XT, AT, Epi, 16, 1>);
         else if (S == 1) go(k_sellm<BR, BC, VT, XT, AT, Epi, 4, 1>);

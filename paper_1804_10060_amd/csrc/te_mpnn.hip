@@ -44,6 +44,7 @@ constexpr int64_t NPARAM = OFF_BOUT + MO;
 constexpr float S_T = 500.f, S_F = 2.0e9f, S_X = 0.5f;
 constexpr double S_U = 1.0e-3;
 constexpr int MB = 256, MW = MB / 64;
+constexpr int VB = 4;   // vertices per wave step of the dense layer transforms
 constexpr int RED_BLOCKS = 512;
 
 __host__ __device__ constexpr int64_t off_ws(int l) { return LAYER0 + l * LAYER_SZ; }
@@ -124,7 +125,8 @@ __global__ void k_global(int nparts, const double *__restrict__ part, int64_t n,
 // one message-passing layer: m = mean of neighbours, d = directional sums,
 // a = h W_s + m W_n + d W_d + gw, h' = h + relu(a); stores m, d and a for the
 // backward pass.  W_s, W_n, W_dx and W_dy sit in LDS (64 KB), W_dz is read
-// through the cache.
+// through the cache; a wave takes VB vertices at a time, each weight value
+// serving all of them.
 __global__ void __launch_bounds__(MB) k_mp_fwd(int64_t n, const int64_t *__restrict__ gp, const int32_t *__restrict__ gi,
                                                const float *__restrict__ xf, const float *__restrict__ invdl,
                                                const float *__restrict__ P, int l, const float *__restrict__ gw,
@@ -140,35 +142,53 @@ __global__ void __launch_bounds__(MB) k_mp_fwd(int64_t n, const int64_t *__restr
     const float *__restrict__ Wz = P + off_wd(l) + 2 * MH * MH;
     const int c = threadIdx.x & 63;
     const float gwc = gw[c];
-    for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
-        const int64_t lo = gp[v], hi = gp[v + 1];
-        const float xv0 = xf[v * 3], xv1 = xf[v * 3 + 1], xv2 = xf[v * 3 + 2], iv = invdl[v];
-        float s = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f;
-        for (int64_t e = lo; e < hi; ++e) {
-            const int64_t u = gi[e];
-            const float hu = h[u * MH + c];
-            s += hu;
-            d0 += (xf[u * 3] - xv0) * iv * hu;
-            d1 += (xf[u * 3 + 1] - xv1) * iv * hu;
-            d2 += (xf[u * 3 + 2] - xv2) * iv * hu;
+    const int64_t step = (int64_t)gridDim.x * MW * VB;
+    for (int64_t v0 = (blockIdx.x * (int64_t)MW + threadIdx.x / 64) * VB; v0 < n; v0 += step) {
+        float hv[VB], mv[VB], d0[VB], d1[VB], d2[VB], acc[VB];
+#pragma unroll
+        for (int i = 0; i < VB; ++i) {
+            const int64_t v = v0 + i;
+            hv[i] = mv[i] = d0[i] = d1[i] = d2[i] = 0.f;
+            acc[i] = gwc;
+            if (v >= n) continue;
+            const int64_t lo = gp[v], hi = gp[v + 1];
+            const float xv0 = xf[v * 3], xv1 = xf[v * 3 + 1], xv2 = xf[v * 3 + 2], iv = invdl[v];
+            float s = 0.f;
+            for (int64_t e = lo; e < hi; ++e) {
+                const int64_t u = gi[e];
+                const float hu = h[u * MH + c];
+                s += hu;
+                d0[i] += (xf[u * 3] - xv0) * iv * hu;
+                d1[i] += (xf[u * 3 + 1] - xv1) * iv * hu;
+                d2[i] += (xf[u * 3 + 2] - xv2) * iv * hu;
+            }
+            mv[i] = hi > lo ? s / float(hi - lo) : 0.f;
+            hv[i] = h[v * MH + c];
         }
-        const float mv = hi > lo ? s / float(hi - lo) : 0.f;
-        const float hv = h[v * MH + c];
-        float acc = gwc;
-#pragma unroll 8
+#pragma unroll 4
         for (int k = 0; k < MH; ++k) {
-            acc += lane_val(hv, k) * W[k * MH + c];
-            acc += lane_val(mv, k) * W[MH * MH + k * MH + c];
-            acc += lane_val(d0, k) * W[2 * MH * MH + k * MH + c];
-            acc += lane_val(d1, k) * W[3 * MH * MH + k * MH + c];
-            acc += lane_val(d2, k) * Wz[k * MH + c];
+            const float ws = W[k * MH + c], wn = W[MH * MH + k * MH + c], wx = W[2 * MH * MH + k * MH + c],
+                        wy = W[3 * MH * MH + k * MH + c], wz = Wz[k * MH + c];
+#pragma unroll
+            for (int i = 0; i < VB; ++i) {
+                acc[i] += lane_val(hv[i], k) * ws;
+                acc[i] += lane_val(mv[i], k) * wn;
+                acc[i] += lane_val(d0[i], k) * wx;
+                acc[i] += lane_val(d1[i], k) * wy;
+                acc[i] += lane_val(d2[i], k) * wz;
+            }
         }
-        m[v * MH + c] = mv;
-        d[v * MD + c] = d0;
-        d[v * MD + MH + c] = d1;
-        d[v * MD + 2 * MH + c] = d2;
-        a[v * MH + c] = acc;
-        hn[v * MH + c] = hv + (acc > 0.f ? acc : 0.f);
+#pragma unroll
+        for (int i = 0; i < VB; ++i) {
+            const int64_t v = v0 + i;
+            if (v >= n) break;
+            m[v * MH + c] = mv[i];
+            d[v * MD + c] = d0[i];
+            d[v * MD + MH + c] = d1[i];
+            d[v * MD + 2 * MH + c] = d2[i];
+            a[v * MH + c] = acc[i];
+            hn[v * MH + c] = hv[i] + (acc[i] > 0.f ? acc[i] : 0.f);
+        }
     }
 }
 
@@ -220,33 +240,60 @@ __global__ void __launch_bounds__(MB) k_out(int64_t n, const float *__restrict__
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-// ga = gh * (a > 0); gmd = (ga W_n^T) / deg; gd_k = ga W_dk^T
+// ga = gh * (a > 0); gmd = (ga W_n^T) / deg; gd_k = ga W_dk^T.  The four
+// matrices sit transposed in LDS (64 KB), so lane c reads W[c][k] of row k
+// of the copy: consecutive lanes, consecutive banks.  A wave takes VB
+// vertices at a time, each LDS value serving all of them.
+
 __global__ void __launch_bounds__(MB) k_mp_bwd1(int64_t n, const int64_t *__restrict__ gp, const float *__restrict__ P,
                                                 int l, const float *__restrict__ gh, const float *__restrict__ a,
                                                 float *__restrict__ ga, float *__restrict__ gmd,
                                                 float *__restrict__ gd) {
-    extern __shared__ float W[];   // [4][64][64]: W_n, W_dx, W_dy, W_dz
-    for (int t = threadIdx.x; t < MH * MH; t += MB) W[t] = P[off_wn(l) + t];
-    for (int t = threadIdx.x; t < 3 * MH * MH; t += MB) W[MH * MH + t] = P[off_wd(l) + t];
+    extern __shared__ float W[];   // [4][64][64] transposed: W_n, W_dx, W_dy, W_dz
+    for (int t = threadIdx.x; t < MH * MH; t += MB) {
+        const int r = t / MH, q = t % MH;   // W[r][q] -> copy[q][r]
+        W[q * MH + r] = P[off_wn(l) + t];
+        W[MH * MH + q * MH + r] = P[off_wd(l) + t];
+        W[2 * MH * MH + q * MH + r] = P[off_wd(l) + MH * MH + t];
+        W[3 * MH * MH + q * MH + r] = P[off_wd(l) + 2 * MH * MH + t];
+    }
     __syncthreads();
     const int c = threadIdx.x & 63;
-    for (int64_t v = blockIdx.x * (int64_t)MW + threadIdx.x / 64; v < n; v += (int64_t)gridDim.x * MW) {
-        const float g = a[v * MH + c] > 0.f ? gh[v * MH + c] : 0.f;
-        ga[v * MH + c] = g;
-        float t = 0.f, t0 = 0.f, t1 = 0.f, t2 = 0.f;
-#pragma unroll 8
-        for (int k = 0; k < MH; ++k) {
-            const float gk = lane_val(g, k);
-            t += gk * W[c * MH + k];
-            t0 += gk * W[MH * MH + c * MH + k];
-            t1 += gk * W[2 * MH * MH + c * MH + k];
-            t2 += gk * W[3 * MH * MH + c * MH + k];
+    const int64_t step = (int64_t)gridDim.x * MW * VB;
+    for (int64_t v0 = (blockIdx.x * (int64_t)MW + threadIdx.x / 64) * VB; v0 < n; v0 += step) {
+        float g[VB], t[VB][4];
+#pragma unroll
+        for (int i = 0; i < VB; ++i) {
+            const int64_t v = v0 + i;
+            g[i] = v < n && a[v * MH + c] > 0.f ? gh[v * MH + c] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t[i][j] = 0.f;
         }
-        const int64_t deg = gp[v + 1] - gp[v];
-        gmd[v * MH + c] = deg > 0 ? t / float(deg) : 0.f;
-        gd[v * MD + c] = t0;
-        gd[v * MD + MH + c] = t1;
-        gd[v * MD + 2 * MH + c] = t2;
+#pragma unroll 4
+        for (int k = 0; k < MH; ++k) {
+            // W^T[k][c] of each matrix: W[c][k] (row c of the weight, column k)
+            const float w0 = W[k * MH + c], w1 = W[MH * MH + k * MH + c], w2 = W[2 * MH * MH + k * MH + c],
+                        w3 = W[3 * MH * MH + k * MH + c];
+#pragma unroll
+            for (int i = 0; i < VB; ++i) {
+                const float gk = lane_val(g[i], k);
+                t[i][0] += gk * w0;
+                t[i][1] += gk * w1;
+                t[i][2] += gk * w2;
+                t[i][3] += gk * w3;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < VB; ++i) {
+            const int64_t v = v0 + i;
+            if (v >= n) break;
+            ga[v * MH + c] = g[i];
+            const int64_t deg = gp[v + 1] - gp[v];
+            gmd[v * MH + c] = deg > 0 ? t[i][0] / float(deg) : 0.f;
+            gd[v * MD + c] = t[i][1];
+            gd[v * MD + MH + c] = t[i][2];
+            gd[v * MD + 2 * MH + c] = t[i][3];
+        }
     }
 }
 
@@ -257,8 +304,8 @@ __global__ void __launch_bounds__(MB) k_mp_bwd2(int64_t n, const int64_t *__rest
                                                 const float *__restrict__ P, int l, const float *__restrict__ ga,
                                                 const float *__restrict__ gmd, const float *__restrict__ gd,
                                                 const float *__restrict__ gg, float *__restrict__ gh) {
-    __shared__ float Ws[MH * MH];
-    for (int t = threadIdx.x; t < MH * MH; t += MB) Ws[t] = P[off_ws(l) + t];
+    __shared__ float Ws[MH * MH];   // W_s transposed (conflict-free reads, as k_mp_bwd1)
+    for (int t = threadIdx.x; t < MH * MH; t += MB) Ws[(t % MH) * MH + t / MH] = P[off_ws(l) + t];
     __syncthreads();
     const int c = threadIdx.x & 63;
     const float ggc = gg[c] / float(n);
@@ -266,7 +313,7 @@ __global__ void __launch_bounds__(MB) k_mp_bwd2(int64_t n, const int64_t *__rest
         const float g = ga[v * MH + c];
         float t = gh[v * MH + c] + ggc;
 #pragma unroll 8
-        for (int k = 0; k < MH; ++k) t += lane_val(g, k) * Ws[c * MH + k];
+        for (int k = 0; k < MH; ++k) t += lane_val(g, k) * Ws[k * MH + c];
         const float xv0 = xf[v * 3], xv1 = xf[v * 3 + 1], xv2 = xf[v * 3 + 2];
         for (int64_t e = gp[v]; e < gp[v + 1]; ++e) {
             const int64_t u = gi[e];
@@ -563,7 +610,8 @@ extern "C" int mpnn_forward(mpnn_handle *H, const float *P, const float *X, cons
         for (int l = 0; l < ML; ++l) {
             hipLaunchKernelGGL(k_colsum, dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->dpart.p);
             hipLaunchKernelGGL(k_global, dim3(1), dim3(64), 0, s, np, H->dpart.p, n, P, l, H->g[l].p, H->gw.p);
-            hipLaunchKernelGGL(k_mp_fwd, dim3(vgrid(n)), dim3(MB), 4 * MH * MH * sizeof(float), s, n, H->gp.p,
+            hipLaunchKernelGGL(k_mp_fwd, dim3(vgrid((n + VB - 1) / VB)), dim3(MB), 4 * MH * MH * sizeof(float), s, n,
+                               H->gp.p,
                                H->gi.p, H->xf.p, H->invdl.p, P, l, H->gw.p, H->h[l].p, H->m[l].p, H->d[l].p,
                                H->a[l].p, H->h[l + 1].p);
         }
@@ -586,7 +634,8 @@ static void backward_tail(mpnn_handle *H, const float *P, float *grad, hipStream
     hipLaunchKernelGGL(k_colsum3, dim3(np), dim3(MB), 0, s, n, H->gy.p, H->dpart.p);
     hipLaunchKernelGGL(k_colsum_out, dim3(1), dim3(64), 0, s, np, H->dpart.p, MO, grad + OFF_BOUT);
     for (int l = ML - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(k_mp_bwd1, dim3(vg), dim3(MB), 4 * MH * MH * sizeof(float), s, n, H->gp.p, P, l, H->gh.p,
+        hipLaunchKernelGGL(k_mp_bwd1, dim3(vgrid((n + VB - 1) / VB)), dim3(MB), 4 * MH * MH * sizeof(float), s, n,
+                           H->gp.p, P, l, H->gh.p,
                            H->a[l].p, H->ga.p, H->gmd.p, H->gd.p);
         hipLaunchKernelGGL((k_xty<MH, MH>), dim3(np), dim3(MB), 0, s, n, H->h[l].p, H->ga.p, H->part.p);
         hipLaunchKernelGGL(k_sum_parts, dim3(16), dim3(MB), 0, s, np, MH * MH, H->part.p, grad + off_ws(l));

@@ -17,6 +17,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <utility>
 
 #include "te_amg.h"
 
@@ -40,7 +41,7 @@ std::map<std::string, Tune> read_cache(const char *path) {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // lines of the form:  "key": [wpb, spw, remap, nt, mwpb, mtile]  (the last two optional)
+        // lines of the form:  "key": [wpb, spw, remap, nt, mwpb, mtile, msplit]  (the last three optional)
         auto a = line.find('"'), b = line.find('"', a + 1), l = line.find('['), r = line.find(']');
         if (a == std::string::npos || b == std::string::npos || l == std::string::npos || r == std::string::npos)
             continue;
@@ -49,9 +50,10 @@ std::map<std::string, Tune> read_cache(const char *path) {
         std::replace(nums.begin(), nums.end(), ',', ' ');
         std::istringstream is(nums);
         if (is >> t.wpb >> t.spw >> t.remap >> t.nt) {
-            int m = 0, mt = 0;
+            int m = 0, mt = 0, sp = 0;
             if (is >> m && (m == 4 || m == 8 || m == 16)) t.mwpb = m;   // checked against the format at launch
             if (is >> mt && (mt == 0 || mt == 16 || mt == 32 || mt == 64)) t.mtile = mt;
+            if (is >> sp) t.msplit = sp ? 1 : 0;
             c[line.substr(a + 1, b - a - 1)] = t;
         }
     }
@@ -66,7 +68,8 @@ void write_cache(const char *path, const std::map<std::string, Tune> &c) {
     size_t i = 0;
     for (const auto &kv : c) {
         f << "  \"" << kv.first << "\": [" << kv.second.wpb << ", " << kv.second.spw << ", " << kv.second.remap
-          << ", " << kv.second.nt << ", " << kv.second.mwpb << ", " << kv.second.mtile << "]"
+          << ", " << kv.second.nt << ", " << kv.second.mwpb << ", " << kv.second.mtile << ", " << kv.second.msplit
+          << "]"
           << (++i < c.size() ? "," : "") << "\n";
     }
     f << "}\n";
@@ -100,15 +103,18 @@ void tune_multi(Sell &A, Tune &slot, const std::string &key, const T *x, T *y, i
     Tune best = keep;
     float best_t = INFINITY, def_t = 0.f;
     const bool tiles = A.format == FMT_SELL && nrhs > 16;
-    for (int mt : {0, 64, 32, 16}) {
-        if (!tiles && mt != keep.mtile) continue;
+    const std::pair<int, int> shapes[] = {{0, 0}, {64, 0}, {32, 0}, {16, 0}, {32, 1}, {16, 1}};
+    for (const auto &sh : shapes) {
+        const int mt = sh.first;
+        if (!tiles && (mt != keep.mtile || sh.second)) continue;
         for (int m : {4, 8, 16}) {
             if (m == 16 && A.format == FMT_SELL) continue;   // the SELL kernel takes at most 8 waves
             Tune c = keep;
             c.mwpb = m;
             c.mtile = mt;
+            c.msplit = sh.second;
             const float t = time_op<T>(A, slot, c, x, y, s, e0, e1, nrhs);
-            if (m == 4 && mt == keep.mtile) def_t = t;
+            if (m == 4 && mt == keep.mtile && !sh.second) def_t = t;
             if (t < best_t) {
                 best_t = t;
                 best = c;
@@ -118,8 +124,8 @@ void tune_multi(Sell &A, Tune &slot, const std::string &key, const T *x, T *y, i
     slot = best;
     cache[key] = slot;
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s best %d waves per workgroup, tile %d: %.4f ms (default %.4f ms)\n",
-                  key.c_str(), best.mwpb, best.mtile, best_t, def_t);
+    std::snprintf(buf, sizeof buf, "%s best %d waves per workgroup, tile %d%s: %.4f ms (default %.4f ms)\n",
+                  key.c_str(), best.mwpb, best.mtile, best.msplit ? " over the XCDs" : "", best_t, def_t);
     report += buf;
 }
 
@@ -137,6 +143,7 @@ void tune_one(Sell &A, Tune &slot, const char *dtype, const T *x, T *y, std::map
             if (nrhs > 1) {
                 slot.mwpb = A.format == FMT_SELL ? std::min(mt->second.mwpb, 8) : mt->second.mwpb;
                 slot.mtile = mt->second.mtile;
+                slot.msplit = mt->second.msplit;
             }
             report += key + " cached\n";
             return;

@@ -145,3 +145,53 @@ def test_every_tuner_candidate_matches_oracle_operators():
                         n_cand += 1
     say(f"{n_cand} candidate configurations x {len(ops)} operators checked")
     assert n_cand == 48
+
+
+def test_every_multi_rhs_candidate_matches_oracle_pcg_multi():
+    """The multi-RHS launch shapes the autotuner times (row per wave with a
+    lane per column; row groups with column tiles of 64, 32 or 16 per pass;
+    tiles of 32 or 16 spread over the XCDs; 4 or 8 waves per workgroup), each
+    imposed through the tuning cache on a 40-column solve (ragged tiles):
+    every column equals the oracle's krylov.pcg_multi to 1e-8 with the
+    iteration count within one."""
+    import paper_1804_10060_amd as te
+    from oracle import amg, fem, krylov
+    torch = torch_cuda()
+    prob = mg.disc_problem(8, 34, 2, 2, seed=6)
+    A, _, d = gpu_assemble(prob)
+    m = 40
+    h = te.AMG(A, d["coords"], d["mask"], max_nrhs=m)
+    Ao, _, _, _ = fem.assemble_problem(prob)
+    lev = amg.setup(Ao, fem.rigid_body_modes(prob.mesh.coords, prob.mask))
+    rng = np.random.default_rng(21)
+    keep = (1.0 - prob.mask.reshape(-1))[:, None]
+    Uo = rng.standard_normal((Ao.shape[0], m)) * keep
+    Bo = Ao @ Uo
+    ref = krylov.pcg_multi(Ao, Bo, lambda v: amg.vcycle(lev, v), rtol=1e-8)
+    n = prob.mesh.n_nodes
+    B = dev(np.ascontiguousarray(Bo.reshape(n, 3, m)), torch.float64)
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "tune.json")
+        h.autotune(path, use_cache=False)
+        with open(path) as fh:
+            tuned = json.load(fh)
+        multi = [k for k in tuned if k.endswith(f"-nrhs{m}")]
+        assert multi
+        n_cand = 0
+        for mwpb in (4, 8):
+            for mtile, msplit in ((0, 0), (64, 0), (32, 0), (16, 0), (32, 1), (16, 1)):
+                cache = dict(tuned)
+                for k in multi:
+                    cache[k] = tuned[k][:4] + [mwpb, mtile, msplit]
+                with open(path, "w") as fh:
+                    json.dump(cache, fh)
+                h.autotune(path, use_cache=True)
+                U, rep = h.solve(B)
+                U = U.cpu().numpy().reshape(-1, m)
+                for j in range(m):
+                    r = ref[j]
+                    assert rep.converged[j] and abs(rep.iters[j] - r.iters) <= 1, (mwpb, mtile, msplit, j)
+                    e = np.linalg.norm(U[:, j] - r.u) / np.linalg.norm(r.u)
+                    assert e <= 1e-8, (mwpb, mtile, msplit, j, e)
+                n_cand += 1
+    say(f"{n_cand} multi-RHS launch shapes x {m} columns checked against the oracle")
