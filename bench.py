@@ -285,6 +285,8 @@ def multi_mesh_form(te, torch, dev):
         bs.append(b)
         probs.append(prob)
     te.solve_multi(hs[:2], bs[:2])
+    tune_multi = te.autotune_multi(hs)
+    log(tune_multi.strip())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     us, reps = te.solve_multi(hs, bs)
@@ -306,6 +308,7 @@ def multi_mesh_form(te, torch, dev):
                                          "oracle_iters": g["iters"]}
     out = {"workload": f"32 P1 discs, {sum(dofs)} DOF in total ({min(dofs)}-{max(dofs)} each), bump fields, "
                        f"greedy aggregation", "ms": round(t_multi * 1e3, 2), "singles_ms": round(t_seq * 1e3, 2),
+           "autotune": tune_multi.strip(),
            "speedup_vs_fp64_singles": round(t_seq / t_multi, 3),
            "all_converged": bool(all(reps["converged"])), "err_vs_oracle": err}
     log(f"multi-mesh: {t_multi * 1e3:.1f} ms vs {t_seq * 1e3:.1f} ms sequential; errors {err}")
@@ -427,6 +430,13 @@ def main():
             ent["algo_bytes"] = int(algo[name])
             ent["GBps"] = round(algo[name] / (avg * 1e-3) / 1e9, 1)
         kernels[name] = ent
+    # CG vector work per iteration (float64): u += a p, r -= a q with the (r, r) partials (read u, r, p, q;
+    # write u, r), (r, z) (read r, z), p = z + b p (read z, p; write p): 11 nodal vectors
+    if "vector" in kernels and "Ap" in kernels:
+        iters = kn[KERNEL_CLASSES.index("Ap")] / args.steps
+        vb = 11 * 3 * 8 * m.n_nodes * iters
+        kernels["vector"]["algo_bytes_per_step"] = int(vb)
+        kernels["vector"]["GBps"] = round(vb / (kernels["vector"]["total_ms"] * 1e-3) / 1e9, 1)
     single = [k for k in ("Ap", "pre_smooth", "residual", "post_init", "post_smooth") if k in kernels]
     dom = max(single, key=lambda k: kernels[k]["total_ms"])
     achieved = kernels[dom]["GBps"]
@@ -474,6 +484,17 @@ def main():
         forms["mixed_fp32_vcycle"] = {"ms": round(repm.time_ms, 2), "iters": repm.iters[0],
                                       "relres_true": repm.relres_true[0], "rel_diff_vs_fp64": diff,
                                       "speedup_vs_fp64": round(reps[-1].time_ms / repm.time_ms, 3)}
+        # the float32 V-cycle kernels (values and vectors 4 bytes; the outer product stays float64)
+        _, repp = h.solve(b, precision="mixed", profile=True)
+        algo32 = algorithmic_bytes(info, m.n_nodes, A.nnzb, vt=4)
+        k32 = {}
+        for i, name in enumerate(KERNEL_CLASSES):
+            if name in algo32 and name != "Ap" and repp.kernel_launches[i]:
+                avg = repp.kernel_ms[i] / repp.kernel_launches[i]
+                k32[name] = {"avg_ms": round(avg, 4), "algo_bytes": int(algo32[name]),
+                             "GBps": round(algo32[name] / (avg * 1e-3) / 1e9, 1),
+                             "frac": round(algo32[name] / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        forms["mixed_fp32_vcycle"]["fp32_kernels"] = k32
         if golden is not None:
             es, ep = golden_c2.errors(um.cpu().numpy(), golden)
             forms["mixed_fp32_vcycle"]["err_vs_oracle"] = {"sampled": es, "projected": ep}

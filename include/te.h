@@ -342,6 +342,16 @@ int amg_pcg_solve(amg_handle *h, const double *b, double *u, int32_t nrhs,
 int amg_pcg_solve_multi(amg_handle **h, int32_t n, const double *const *b, double *const *u,
                         const pcg_options *opt, pcg_report *rep, hipStream_t stream);
 
+/* Autotuner of amg_pcg_solve_multi for the set h[0..n-1]: times the grouped
+ * launches (one V-cycle of every system plus the level-0 product, median of
+ * 5 after a warm-up) for a persistent grid of 1, 2 or 4 times the workgroups
+ * the device holds at once and for the work items in the order given or
+ * largest system first, and keeps the fastest in every handle (later
+ * amg_pcg_solve_multi calls on them use it).  report (host, may be NULL):
+ * text of the choice.  Overwrites the handles' solve workspaces; synchronises.
+ * Returns TE_OK, TE_EINVAL, TE_EHIP. */
+int te_autotune_multi(amg_handle **h, int32_t n, char *report, int64_t report_len, hipStream_t stream);
+
 /* Initial-guess scaling for CG: u0 <- gamma u0 with
  * gamma = (b, u0) / (u0, A u0), the multiple of the guess of least energy
  * (smallest A-norm error along u0); gamma = 0, i.e. the zero guess, when

@@ -322,6 +322,16 @@ def timestep(T_new, T_old, dt, dT_max=10.0, eps=0.9, noalloc=False):
     return bool(acc.value), dn.value, mc.value
 
 
+def autotune_multi(amgs):
+    """te_autotune_multi: the grouped launch shape of solve_multi for this set
+    of AMG handles (kept in them); returns the text report."""
+    n = len(amgs)
+    H = (C.c_void_p * n)(*[a._h.value for a in amgs])
+    buf = C.create_string_buffer(1 << 12)
+    check(load().te_autotune_multi(H, n, buf, len(buf), _stream()))
+    return buf.value.decode()
+
+
 def solve_multi(amgs, bs, u0s=None, rtol=1e-8, maxit=500, max_replace=3):
     """amg_pcg_solve_multi over several AMG handles.  Returns (us, reports)."""
     import numpy as np

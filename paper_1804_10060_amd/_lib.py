@@ -22,7 +22,8 @@ CODE_NAMES = {TE_ENOTCONV: "TE_ENOTCONV", TE_EINVAL: "TE_EINVAL", TE_ENOMEM: "TE
 EXPORTS = ["te_version", "te_last_error", "fe_assemble_pattern", "fe_assemble_thermoelastic", "fe_assemble_load",
            "fe_assemble_thermoelastic_materials",
            "amg_options_default", "amg_setup", "amg_setup_with_aggregates", "amg_get_info", "amg_get_aggregates",
-           "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_pcg_solve_multi", "amg_energy_scale", "te_autotune", "amg_destroy",
+           "amg_get_level_matrix", "amg_apply", "pcg_options_default", "amg_pcg_solve", "amg_pcg_solve_multi", "te_autotune_multi", "amg_energy_scale",
+           "te_autotune", "amg_destroy",
            "amg_set_operator", "te_timestep", "te_timestep_noalloc",
            "mpnn_param_count", "mpnn_create", "mpnn_destroy", "mpnn_features", "mpnn_forward", "mpnn_backward", "mpnn_backward_from", "mpnn_energy_grad",
            "mpnn_adam_step", "mpnn_guess",
@@ -150,6 +151,7 @@ def load():
         "amg_pcg_solve": ([vp, vp, vp, i32, C.POINTER(PcgOptions), C.POINTER(PcgReport), vp], C.c_int),
         "amg_pcg_solve_multi": ([C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(PcgOptions),
                                  C.POINTER(PcgReport), vp], C.c_int),
+        "te_autotune_multi": ([C.POINTER(vp), i32, C.c_char_p, i64, vp], C.c_int),
         "amg_energy_scale": ([vp, vp, vp, C.POINTER(C.c_double), vp], C.c_int),
         "te_autotune": ([vp, C.c_char_p, i32, C.c_char_p, i64, vp], C.c_int),
         "amg_destroy": ([vp], C.c_int),

@@ -129,6 +129,9 @@ struct amg_handle {
     te::DBuf<double> partials, sums;
     te::DBuf<char> scal;
     te::DBuf<int32_t> colsel;      // [64] column selector of copy_cols
+    // launch shape of amg_pcg_solve_multi over a set of handles (te_autotune_multi):
+    // persistent grid multiplier and work-item order (0: as given, 1: largest first)
+    int multi_grid = 1, multi_order = 0;
     // block-CG workspace, allocated by the first block solve and kept:
     // Gram partials and results, the two small coefficient matrices, X/R partials
     te::DBuf<double> bgpart, bgout, bsmall, bxpart;

@@ -291,60 +291,61 @@ __global__ void __launch_bounds__(TB) k_split_fill(int64_t n, const int64_t *__r
 // One l1 hybrid Gauss-Seidel sweep, eight blocks of B rows per wave: the
 // eight lanes of block g run its rows in order (ascending or descending),
 // each row's in-block entries eight at a time, the products summed across
-// the eight lanes by sum8; the block's x and row offsets sit in LDS.  The row chain (LDS
-// read, FMA, three DPP steps, LDS write) is far shorter than a memory
-// latency, so the entries, o and 1/d of the next D rows are kept in flight
-// in a ring of registers: row t's slot is refilled with row t + D as soon
-// as row t starts.  o holds g - (entries outside the block) x_in, or g when
-// x_in is NULL (x_in = 0).  x_out may be x_in: a block reads only its own
-// rows of x_in.  PF: entries per lane held per row (8 PF per row; chosen per
-// level from its longest in-block row, longer rows read the rest in the
-// chain).
-template <int PF, int D>
+// the eight lanes by sum8; the block's x and row offsets sit in LDS.  The
+// row chain (LDS read, FMA, three DPP steps, LDS write) is far shorter than
+// a memory latency, so the entries, o and 1/d of the next D rows are kept in
+// flight in a ring of registers: row t's slot is refilled with row t + D as
+// soon as row t starts.  Everything in the row loop is predicated rather
+// than branched (loads of an absent entry read entry 0 and are zeroed, rows
+// past the block write a spare LDS slot), so the compiler can leave the
+// ring's loads outstanding across rows.  o holds g - (entries outside the
+// block) x_in, or g when x_in is NULL (x_in = 0).  x_out may be x_in: a
+// block reads only its own rows of x_in.  PF: entries per lane held per row
+// (8 PF per row, chosen per level from its longest in-block row; TAIL: rows
+// may be longer, the rest is read in the chain).
+template <int PF, int D, bool TAIL>
 __global__ void __launch_bounds__(64) k_hgs8(int64_t n, int B, const int64_t *__restrict__ pin,
                                              const uint8_t *__restrict__ lin, const double *__restrict__ vin,
                                              const double *__restrict__ idl, const double *__restrict__ o,
                                              const double *x_in, double *x_out, int forward) {
-    extern __shared__ double xs[];   // [8][B] x, then [8][B + 1] int row offsets
+    extern __shared__ double xs[];   // [8][B + 1] x (spare last slot), then [8][B + 1] int row offsets
     const int lane = threadIdx.x, g = lane >> 3, l = lane & 7;
     const int64_t b0 = ((int64_t)blockIdx.x * 8 + g) * B;
     const int nb = b0 < n ? (int)min<int64_t>(B, n - b0) : 0;
-    double *xb = xs + g * B;
-    // the block's row pointers, relative to its first entry, in LDS: a row's
-    // entry range is then an LDS read, not a load the entry loads wait for
-    int *pb = reinterpret_cast<int *>(xs + 8 * B) + g * (B + 1);
+    double *xb = xs + g * (B + 1);
+    // the block's row pointers, relative to its first entry
+    int *pb = reinterpret_cast<int *>(xs + 8 * (B + 1)) + g * (B + 1);
     const int64_t e0 = nb > 0 ? pin[b0] : 0;
     for (int r = l; r < nb; r += 8) xb[r] = x_in ? x_in[b0 + r] : 0.0;
     for (int r = l; r <= nb; r += 8) pb[r] = (int)(pin[b0 + r] - e0);
     __syncthreads();
+    // a slot holds the raw loads of one row and the mask of its present
+    // entries; nothing is computed from the loaded values until the row runs
     struct Slot {
-        int64_t lo, hi;   // the row's in-block entries
+        int64_t lo, hi;
         double v[PF], o, id;
         int c[PF];
+        unsigned msk;
     };
     Slot sl[D];
     auto fetch = [&](Slot &q, int t) {
-        q.lo = q.hi = 0;
-        q.o = q.id = 0.0;
+        const bool ok = t < nb;
+        const int r = ok ? (forward ? t : nb - 1 - t) : 0;
+        const int64_t row = ok ? b0 + r : 0;
+        const int64_t lo = e0 + pb[r], hi1 = e0 + pb[r + 1];   // r + 1 <= B: inside the LDS table
+        q.lo = lo;
+        q.hi = ok ? hi1 : lo;
+        q.msk = 0u;
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
-            q.v[u] = 0.0;
-            q.c[u] = 0;
+            const int64_t k = lo + l + 8 * u;
+            const bool in = k < q.hi;
+            const int64_t kk = in ? k : 0;   // an absent entry reads entry 0, masked at use
+            q.c[u] = (int)lin[kk];
+            q.v[u] = vin[kk];
+            q.msk |= (in ? 1u : 0u) << u;
         }
-        if (t >= nb) return;
-        const int r = forward ? t : nb - 1 - t;
-        const int64_t row = b0 + r;
-        q.lo = e0 + pb[r];
-        q.hi = e0 + pb[r + 1];
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const int64_t k = q.lo + l + 8 * u;
-            if (k < q.hi) {
-                q.c[u] = (int)lin[k];
-                q.v[u] = vin[k];
-            }
-        }
-        q.o = o[row];
+        q.o = o[row];   // rows past the block update the spare slot only
         q.id = idl[row];
     };
 #pragma unroll
@@ -357,16 +358,18 @@ __global__ void __launch_bounds__(64) k_hgs8(int64_t n, int B, const int64_t *__
             fetch(sl[d], t + D);
             if (t < B) {   // uniform
                 double sum = 0.0;
-                if (t < nb) {
 #pragma unroll
-                    for (int u = 0; u < PF; ++u) sum += cur.v[u] * xb[cur.c[u]];
+                for (int u = 0; u < PF; ++u) {
+                    const double p = cur.v[u] * xb[cur.c[u]];
+                    sum += (cur.msk >> u) & 1u ? p : 0.0;
+                }
+                if (TAIL)
                     for (int64_t k = cur.lo + l + 8 * PF; k < cur.hi; k += 8) sum += vin[k] * xb[lin[k]];
-                }
                 sum = sum8(sum);
-                if (t < nb && l == 0) {
-                    const int r = forward ? t : nb - 1 - t;
-                    xb[r] += (cur.o - sum) * cur.id;
-                }
+                // every lane of the eighth holds the same sum: all write the
+                // row's new value; steps past the block write the spare slot
+                const int r = t < nb ? (forward ? t : nb - 1 - t) : B;
+                xb[r] = xb[r] + (cur.o - sum) * cur.id;
                 __syncthreads();
             }
         }
@@ -457,13 +460,14 @@ void sweep(camg_handle *h, CLv &L, const double *g, const double *x_in, double *
     const int64_t nblk = (L.n + B - 1) / B;
     const unsigned grid = (unsigned)((nblk + 7) / 8);
     auto go = [&](auto kern) {
-        const size_t lds = (size_t)8 * B * sizeof(double) + (size_t)8 * (B + 1) * sizeof(int);
+        const size_t lds = (size_t)8 * (B + 1) * (sizeof(double) + sizeof(int));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, L.n, B, L.pin.p, L.lin.p, L.vin.p, L.idl.p, o, x_in,
                            x_out, forward ? 1 : 0);
     };
-    if (L.max_in <= 24) go(k_hgs8<3, 4>);
-    else if (L.max_in <= 64) go(k_hgs8<8, 4>);
-    else go(k_hgs8<16, 2>);
+    if (L.max_in <= 24) go(k_hgs8<3, 4, false>);
+    else if (L.max_in <= 64) go(k_hgs8<8, 4, false>);
+    else if (L.max_in <= 128) go(k_hgs8<16, 2, false>);
+    else go(k_hgs8<16, 2, true>);
     TE_CHECK_HIP(hipGetLastError());
 }
 

@@ -13,6 +13,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <string>
+#include <vector>
 
 #include "te_amg.h"
 #include "te_multi_kernels.h"
@@ -32,6 +34,7 @@ struct Phase {
     int nitems = 0;
     int64_t ntiles = 0;
     const double *coef = nullptr;  // per-mesh scalar for vector ops
+    int gmult = 1;                 // persistent grid: gmult x the resident workgroups
 };
 
 enum Epis { E_DOT, E_RESID, E_RESIDN, E_SET, E_ADD, E_INIT, E_STEP_LZ, E_STEP_L, E_STEP_Z, E_STEP };
@@ -73,6 +76,8 @@ struct MultiState {
     bool flexible = false;
     int deg = 2;
     int Lmax = 1;
+    int gmult = 1;            // grid multiplier of every grouped launch
+    std::vector<int> order;   // mesh order of the work items
     // device scalars
     DBuf<double> rz, pq, alpha, beta, rr, bb, tol2, sums;
     DBuf<int32_t> active, cand, flag, iters, tailmask;
@@ -90,37 +95,43 @@ double *level_x(amg_handle *h, int l) { return l == 0 ? h->z.p : h->L[l].w64.x.p
 template <int BR, int BC>
 void launch_sparse(const Phase &P, const int32_t *active, double *partials, hipStream_t s) {
     switch (P.epi) {
-        case E_DOT: group_launch<BR, BC, EpiDot>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active, partials, s); break;
+        case E_DOT: group_launch<BR, BC, EpiDot>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
+                                                 partials, s, P.gmult); break;
         case E_RESID:
-            group_launch<BR, BC, EpiResid<double, false>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active, partials, s);
+            group_launch<BR, BC, EpiResid<double, false>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
+                                                          partials, s, P.gmult);
             break;
         case E_RESIDN:
-            group_launch<BR, BC, EpiResid<double, true>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active, partials, s);
+            group_launch<BR, BC, EpiResid<double, true>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
+                                                         partials, s, P.gmult);
             break;
         case E_SET:
-            group_launch<BR, BC, EpiSet<double>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active, partials, s);
+            group_launch<BR, BC, EpiSet<double>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
+                                                 partials, s, P.gmult);
             break;
         case E_ADD:
-            group_launch<BR, BC, EpiAdd<double>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active, partials, s);
+            group_launch<BR, BC, EpiAdd<double>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
+                                                 partials, s, P.gmult);
             break;
         case E_INIT:
-            group_launch<BR, BC, EpiChebInit<double>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active, partials, s);
+            group_launch<BR, BC, EpiChebInit<double>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
+                                                      partials, s, P.gmult);
             break;
         case E_STEP_LZ:
             group_launch<BR, BC, EpiChebStep<double, true, true>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
-                                                                  partials, s);
+                                                                  partials, s, P.gmult);
             break;
         case E_STEP_L:
             group_launch<BR, BC, EpiChebStep<double, true, false>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
-                                                                   partials, s);
+                                                                   partials, s, P.gmult);
             break;
         case E_STEP_Z:
             group_launch<BR, BC, EpiChebStep<double, false, true>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
-                                                                   partials, s);
+                                                                   partials, s, P.gmult);
             break;
         default:
             group_launch<BR, BC, EpiChebStep<double, false, false>>(P.items.p, P.tile0.p, P.nitems, P.ntiles, active,
-                                                                    partials, s);
+                                                                    partials, s, P.gmult);
     }
 }
 
@@ -136,14 +147,19 @@ void run(const Phase &P, const int32_t *active, double *partials, hipStream_t s)
     } else if (P.kind == 1) {
         const VItem *it = (const VItem *)P.items.p;
         switch (P.vop) {
-            case VOP_UPDATE: group_vec_launch<VOP_UPDATE>(it, P.tile0.p, P.nitems, P.ntiles, active, P.coef, partials, s); break;
-            case VOP_DOTRZ: group_vec_launch<VOP_DOTRZ>(it, P.tile0.p, P.nitems, P.ntiles, active, P.coef, partials, s); break;
-            case VOP_PUPDATE: group_vec_launch<VOP_PUPDATE>(it, P.tile0.p, P.nitems, P.ntiles, active, P.coef, partials, s); break;
-            case VOP_JACOBI: group_vec_launch<VOP_JACOBI>(it, P.tile0.p, P.nitems, P.ntiles, active, P.coef, partials, s); break;
-            default: group_vec_launch<VOP_DOTSELF>(it, P.tile0.p, P.nitems, P.ntiles, active, P.coef, partials, s);
+            case VOP_UPDATE: group_vec_launch<VOP_UPDATE>(it, P.tile0.p, P.nitems, P.ntiles, active,
+                                                          P.coef, partials, s, P.gmult); break;
+            case VOP_DOTRZ: group_vec_launch<VOP_DOTRZ>(it, P.tile0.p, P.nitems, P.ntiles, active,
+                                                        P.coef, partials, s, P.gmult); break;
+            case VOP_PUPDATE: group_vec_launch<VOP_PUPDATE>(it, P.tile0.p, P.nitems, P.ntiles, active,
+                                                            P.coef, partials, s, P.gmult); break;
+            case VOP_JACOBI: group_vec_launch<VOP_JACOBI>(it, P.tile0.p, P.nitems, P.ntiles, active,
+                                                          P.coef, partials, s, P.gmult); break;
+            default: group_vec_launch<VOP_DOTSELF>(it, P.tile0.p, P.nitems, P.ntiles, active,
+                                                   P.coef, partials, s, P.gmult);
         }
     } else {
-        const unsigned g = (unsigned)std::min<int64_t>(P.ntiles, GROUP_GRID);
+        const unsigned g = (unsigned)std::min<int64_t>(P.ntiles, (int64_t)GROUP_GRID * P.gmult);
         hipLaunchKernelGGL(k_group_dense, dim3(g), dim3(BLK), 0, s, (const DItem *)P.items.p, P.tile0.p, P.nitems,
                            active);
         TE_CHECK_HIP(hipGetLastError());
@@ -167,7 +183,7 @@ void build_phases(MultiState &M, hipStream_t s) {
         std::vector<GItem<double, EpiResid<double, true>>> it2;
         std::vector<VItem> up, rz, pu;
         std::vector<int64_t> tv;
-        for (int m = 0; m < n; ++m) {
+        for (int m : M.order) {
             amg_handle *h = M.H[m];
             const Sell &A = h->L[0].A;
             it.push_back(gitem(A, h->p.p, EpiDot{h->p.p, h->q.p}, m));
@@ -212,7 +228,7 @@ void build_phases(MultiState &M, hipStream_t s) {
         std::vector<std::vector<GItem<double, EpiChebStep<double, false, true>>>> s_z(steps);
         std::vector<std::vector<GItem<double, EpiChebStep<double, false, false>>>> s_n(steps);
         int bs = 0, rbr = 0, rbc = 0, pbr = 0, pbc = 0;
-        for (int m = 0; m < M.n; ++m) {
+        for (int m : M.order) {
             amg_handle *h = M.H[m];
             if (l + 1 >= (int)h->L.size()) continue;
             Level &L = h->L[l];
@@ -270,7 +286,7 @@ void build_phases(MultiState &M, hipStream_t s) {
             // post-smoothing: same operators, rin = r after the init, never x = 0
             std::vector<GItem<double, EpiChebStep<double, true, false>>> q_l;
             std::vector<GItem<double, EpiChebStep<double, false, false>>> q_n;
-            for (int m = 0; m < M.n; ++m) {
+            for (int m : M.order) {
                 amg_handle *h = M.H[m];
                 if (l + 1 >= (int)h->L.size()) continue;
                 Level &L = h->L[l];
@@ -292,7 +308,7 @@ void build_phases(MultiState &M, hipStream_t s) {
         std::vector<DItem> di;
         std::vector<int64_t> dt;
         std::vector<int32_t> mo;
-        for (int m = 0; m < M.n; ++m) {
+        for (int m : M.order) {
             amg_handle *h = M.H[m];
             const int c = (int)h->L.size() - 1;
             di.push_back(DItem{h->Ainv.p, level_g(h, c), level_x(h, c), (int64_t)h->nc, m});
@@ -302,6 +318,22 @@ void build_phases(MultiState &M, hipStream_t s) {
         M.dense.kind = 2;
         upload_items(M.dense, di, dt, mo, s);
     }
+    for (Phase *P : {&M.ap, &M.update, &M.dotrz, &M.pupdate, &M.tres, &M.dense}) P->gmult = M.gmult;
+    for (auto *V : {&M.jac, &M.resid, &M.restrict_, &M.prolong, &M.postinit})
+        for (Phase &P : *V) P.gmult = M.gmult;
+    for (auto *V : {&M.pre_steps, &M.post_steps})
+        for (auto &row : *V)
+            for (Phase &P : row) P.gmult = M.gmult;
+}
+
+// The work-item order of the grouped phases: the meshes as given (0), or
+// largest first (1: ties by index), so the largest tiles start first.
+std::vector<int> mesh_order(amg_handle *const *hs, int n, int how) {
+    std::vector<int> o(n);
+    for (int m = 0; m < n; ++m) o[m] = m;
+    if (how == 1)
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return hs[a]->L[0].n > hs[b]->L[0].n; });
+    return o;
 }
 
 // z = M^-1 r for every mesh whose flag in `mask` is set
@@ -372,6 +404,9 @@ int multi_impl(amg_handle **hs, int n, const double *const *b, double *const *u,
     M.n = n;
     M.H.assign(hs, hs + n);
     M.deg = hs[0]->opt.cheb_degree;
+    // launch shape chosen by te_autotune_multi for this set (kept in the handles)
+    M.gmult = std::max(1, hs[0]->multi_grid);
+    M.order = mesh_order(hs, n, hs[0]->multi_order);
     for (int m = 0; m < n; ++m) {
         TE_REQUIRE(hs[m] && b[m] && u[m], TE_EINVAL, "NULL handle or vector %d", m);
         TE_REQUIRE(!hs[m]->has_op, TE_EINVAL, "handle %d has an operator set by amg_set_operator, which the "
@@ -581,6 +616,87 @@ int multi_impl(amg_handle **hs, int n, const double *const *b, double *const *u,
 
 }  // namespace
 }  // namespace te
+
+namespace te {
+namespace {
+// Launch shape of the grouped phases for one set of hierarchies: the
+// persistent grid (1, 2 or 4 times the resident workgroups) and the work-item
+// order (meshes as given, or largest first), timed on one V-cycle of every
+// mesh plus the level-0 product (median of 5 after a warm-up, HIP events),
+// the best kept in every handle.  Overwrites the handles' solve workspace.
+int autotune_multi_impl(amg_handle **hs, int n, char *report, int64_t len, hipStream_t s) {
+    TE_REQUIRE(hs && n >= 1, TE_EINVAL, "bad argument");
+    MultiState M;
+    M.n = n;
+    M.H.assign(hs, hs + n);
+    M.deg = hs[0]->opt.cheb_degree;
+    for (int m = 0; m < n; ++m) {
+        TE_REQUIRE(hs[m], TE_EINVAL, "NULL handle %d", m);
+        TE_REQUIRE(hs[m]->opt.cheb_degree == M.deg && M.deg >= 2, TE_EINVAL,
+                   "all meshes need the same Chebyshev degree >= 2");
+        M.Lmax = std::max<int>(M.Lmax, (int)hs[m]->L.size());
+        for (size_t l = 1; l < hs[m]->L.size(); ++l)
+            TE_REQUIRE(hs[m]->L[l].bs == 6, TE_EINVAL, "unexpected coarse block size");
+    }
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    TE_CHECK_HIP(hipEventCreate(&ev.a));
+    TE_CHECK_HIP(hipEventCreate(&ev.b));
+    DBuf<int32_t> ones;
+    upload(ones, std::vector<int32_t>(n, 1), s);
+    std::string rep;
+    float best_t = INFINITY, def_t = 0.f;
+    int best_g = 1, best_o = 0;
+    for (int how : {0, 1}) {
+        for (int gm : {1, 2, 4}) {
+            M.order = mesh_order(hs, n, how);
+            M.gmult = gm;
+            build_phases(M, s);
+            DBuf<double> part(2 * M.ap.ntiles + 2);
+            auto once = [&] {
+                vcycle_all(M, ones.p, s);
+                run(M.ap, ones.p, part.p, s);
+            };
+            once();
+            float t[5];
+            for (int r = 0; r < 5; ++r) {
+                TE_CHECK_HIP(hipEventRecord(ev.a, s));
+                once();
+                TE_CHECK_HIP(hipEventRecord(ev.b, s));
+                TE_CHECK_HIP(hipEventSynchronize(ev.b));
+                TE_CHECK_HIP(hipEventElapsedTime(&t[r], ev.a, ev.b));
+            }
+            std::sort(t, t + 5);
+            if (how == 0 && gm == 1) def_t = t[2];
+            if (t[2] < best_t) {
+                best_t = t[2];
+                best_g = gm;
+                best_o = how;
+            }
+        }
+    }
+    for (int m = 0; m < n; ++m) {
+        hs[m]->multi_grid = best_g;
+        hs[m]->multi_order = best_o;
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "multi-mesh %d systems: grid %dx resident, %s order: %.4f ms per V-cycle + "
+                  "product (default %.4f ms)\n", n, best_g, best_o ? "largest-first" : "given", best_t, def_t);
+    rep += buf;
+    if (report && len > 0) std::snprintf(report, (size_t)len, "%s", rep.c_str());
+    return TE_OK;
+}
+}  // namespace
+}  // namespace te
+
+extern "C" int te_autotune_multi(amg_handle **h, int32_t n, char *report, int64_t report_len, hipStream_t stream) {
+    return te::guarded([&] { return te::autotune_multi_impl(h, n, report, report_len, stream); });
+}
 
 extern "C" int amg_pcg_solve_multi(amg_handle **h, int32_t n, const double *const *b, double *const *u,
                                    const pcg_options *opt, pcg_report *rep, hipStream_t stream) {

@@ -254,10 +254,10 @@ int64_t resident_groups(K kernel, int threads) {
 
 template <int BR, int BC, class Epi>
 void group_launch(const void *items, const int64_t *tile0, int nitems, int64_t ntiles, const int32_t *active,
-                  double *partials, hipStream_t s) {
+                  double *partials, hipStream_t s, int gmult = 1) {
     if (nitems == 0 || ntiles == 0) return;
     static const int64_t cap = resident_groups(k_group<BR, BC, double, Epi>, GBLK);
-    const unsigned g = (unsigned)std::min<int64_t>(ntiles, cap);
+    const unsigned g = (unsigned)std::min<int64_t>(ntiles, cap * gmult);
     hipLaunchKernelGGL((k_group<BR, BC, double, Epi>), dim3(g), dim3(GBLK), 0, s,
                        (const GItem<double, Epi> *)items, tile0, nitems, active, partials);
     TE_CHECK_HIP(hipGetLastError());
@@ -265,9 +265,9 @@ void group_launch(const void *items, const int64_t *tile0, int nitems, int64_t n
 
 template <int OP>
 void group_vec_launch(const VItem *items, const int64_t *tile0, int nitems, int64_t ntiles, const int32_t *active,
-                      const double *coef, double *partials, hipStream_t s) {
+                      const double *coef, double *partials, hipStream_t s, int gmult = 1) {
     if (nitems == 0 || ntiles == 0) return;
-    const unsigned g = (unsigned)std::min<int64_t>(ntiles, GROUP_GRID);
+    const unsigned g = (unsigned)std::min<int64_t>(ntiles, (int64_t)GROUP_GRID * gmult);
     hipLaunchKernelGGL(k_group_vec<OP>, dim3(g), dim3(BLK), 0, s, items, tile0, nitems, active, coef, partials);
     TE_CHECK_HIP(hipGetLastError());
 }

@@ -140,6 +140,13 @@ def multi_form(quick=False):
     te.solve_multi(hs[:2], bs[:2])  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    te.solve_multi(hs, bs)
+    torch.cuda.synchronize()
+    t_untuned = time.perf_counter() - t0
+    tune_multi = te.autotune_multi(hs)   # persistent grid and work order of the grouped launches
+    log(tune_multi.strip())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     us, rep = te.solve_multi(hs, bs)
     torch.cuda.synchronize()
     t_multi = time.perf_counter() - t0
@@ -153,6 +160,7 @@ def multi_form(quick=False):
         its.append(r1.iters[0])
         diffs.append(float((u - u1).norm() / u1.norm()))
     out = {"workload": f"{len(hs)} P1 discs, DOF log-uniform, {ndof} DOF total",
+           "multi_s_untuned": t_untuned, "autotune": tune_multi.strip(),
            "meshes": len(hs), "total_dof": ndof, "dof_per_mesh": [3 * int(h.info()['n_dof'][0] // 3) for h in hs],
            "multi_s": t_multi, "sequential_s": seq, "speedup": seq / t_multi,
            "iters_multi": rep["iters"], "iters_single": its, "all_converged": bool(all(rep["converged"])),

@@ -47,6 +47,16 @@ def test_multi_mesh_equals_standalone_solves():
         say(f"mesh {i}: iters multi {rep['iters'][i]} single {r1.iters[0]} diff {err:.1e}")
         assert err <= tol
         assert rep["relres_true"][i] <= 1e-8
+    # the multi-mesh autotuner (persistent grid, work-item order): the per-tile
+    # partial sums and the per-mesh reductions over them keep their order, so
+    # the tuned launches give the same iterates bit for bit
+    report = te.autotune_multi(hs)
+    say(report.strip())
+    assert "grid" in report
+    ut, rept = te.solve_multi(hs, bs)
+    assert rept["iters"] == rep["iters"]
+    for i in range(len(hs)):
+        assert torch_cuda().equal(ut[i], us[i]), i
 
 
 def test_multi_mesh_matches_oracle_and_zero_rhs():
