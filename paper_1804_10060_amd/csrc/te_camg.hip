@@ -464,7 +464,13 @@ void sweep(camg_handle *h, CLv &L, const double *g, const double *x_in, double *
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, L.n, B, L.pin.p, L.lin.p, L.vin.p, L.idl.p, o, x_in,
                            x_out, forward ? 1 : 0);
     };
-    if (L.max_in <= 24) go(k_hgs8<3, 4, false>);
+    // a level of fewer waves than compute units has no other waves to hide
+    // the loads behind: a deeper ring there (more registers, one wave per
+    // SIMD anyway).  The ring's depth is capped by the hardware's count of
+    // outstanding loads (63): a row of PF = 8 issues 18 loads per lane, so
+    // deeper than four rows gains nothing there.
+    const bool deep = grid < 256;
+    if (L.max_in <= 24) deep ? go(k_hgs8<3, 8, false>) : go(k_hgs8<3, 4, false>);
     else if (L.max_in <= 64) go(k_hgs8<8, 4, false>);
     else if (L.max_in <= 128) go(k_hgs8<16, 2, false>);
     else go(k_hgs8<16, 2, true>);
