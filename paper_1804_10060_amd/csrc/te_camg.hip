@@ -64,21 +64,48 @@ __device__ __forceinline__ double sum8(double v) {
     return v;
 }
 
-// Scalar products, RG = 8 lanes per row (coalesced loads of the row's
-// entries, the partial sums of a row's lanes added by sum8):
+// Scalar products, RG lanes per row (coalesced loads of the row's entries,
+// the partial sums of a row's lanes added by DPP steps inside the group):
 //   mode 0: y = A x; 1: y = g - A x; 2: y += A x
-constexpr int RG = 8;
+// A lane takes its entries CU at a time: the columns and values of all CU
+// are loaded, then their x, then the products are added in entry order, so
+// a row of up to RG * CU entries costs two dependent loads instead of two
+// per entry (absent entries read the row's first entry and add zero).
+constexpr int RG = 8, CU = 4;
+
+__device__ __forceinline__ double sum_rg(double v) {
+    static_assert(RG == 4 || RG == 8, "row group of 4 or 8 lanes");
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    if (RG == 8) v += dpp_mov<0x141>(v);
+    return v;
+}
 
 __global__ void __launch_bounds__(TB) k_csr(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                             const double *__restrict__ val, const double *__restrict__ x, double *y,
                                             const double *g, int mode) {
     const int sub = threadIdx.x % RG;
     const int64_t stride = (int64_t)gridDim.x * (TB / RG);
-    // the eight lanes of a row share its loop trips, and sum8 mixes only them
+    // the lanes of a row share its loop trips, and sum_rg mixes only them
     for (int64_t i = blockIdx.x * (int64_t)(TB / RG) + threadIdx.x / RG; i < n; i += stride) {
+        const int64_t lo = ptr[i], hi = ptr[i + 1];
         double t = 0.0;
-        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += RG) t += val[k] * x[col[k]];
-        t = sum8(t);
+        for (int64_t k0 = lo + sub; k0 < hi; k0 += RG * CU) {
+            int c[CU];
+            double v[CU], xv[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const int64_t k = k0 + u * RG;
+                const int64_t kk = k < hi ? k : lo;
+                c[u] = col[kk];
+                v[u] = k < hi ? val[kk] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) t += v[u] * xv[u];
+        }
+        t = sum_rg(t);
         if (sub == 0) {
             if (mode == 0) y[i] = t;
             else if (mode == 2) y[i] += t;
