@@ -180,6 +180,16 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                         if (lane == 0) atomicOr(flag, 8);
                         continue;
                     }
+                    if (BB == 1 && LACC) {
+                        // scalar blocks: every lane updates its own entry's slot
+                        // (the slots of one B row are distinct), each slot still
+                        // receiving its updates in A-row order
+                        if (lane < nb) {
+                            const double t1 = __dmul_rn(aval[ka], bval[kb0 + lane]);
+                            acc[my] = __dadd_rn(acc[my], t1);
+                        }
+                        continue;
+                    }
                     // the slots of one B row are distinct: batches of UB updates
                     // load their accumulators together, then store them
                     constexpr int UB = 8;
