@@ -180,13 +180,50 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                         if (lane == 0) atomicOr(flag, 8);
                         continue;
                     }
-                    if (BB == 1 && LACC) {
+                    if constexpr (LACC && BB == 1) {
                         // scalar blocks: every lane updates its own entry's slot
                         // (the slots of one B row are distinct), each slot still
                         // receiving its updates in A-row order
                         if (lane < nb) {
                             const double t1 = __dmul_rn(aval[ka], bval[kb0 + lane]);
                             acc[my] = __dadd_rn(acc[my], t1);
+                        }
+                        continue;
+                    } else if constexpr (LACC && 2 * BB <= 64) {
+                        // G groups of BB lanes take G entries of the B row at once
+                        // (distinct slots); per output element the products and
+                        // the accumulation run in the same order as with one group
+                        constexpr int G = 64 / BB, UG = (8 + G - 1) / G;
+                        const int g = lane / BB, e = lane - (lane / BB) * BB;
+                        const bool gon = g < G;
+                        const int gp = gon ? e / BC : 0, gq = gon ? e % BC : 0;
+                        double ag[BK];
+                        const double *a2 = aval + ka * (BR * BK) + gp * BK;
+#pragma unroll
+                        for (int r = 0; r < BK; ++r) ag[r] = gon ? a2[r] : 0.0;
+                        for (int u0 = 0; u0 < nb; u0 += G * UG) {
+                            int sl[UG];
+                            double t[UG], old[UG];
+                            bool ok[UG];
+#pragma unroll
+                            for (int uu = 0; uu < UG; ++uu) {
+                                const int u = u0 + uu * G + g;
+                                ok[uu] = gon && u < nb;
+                                const int uc = u < nb ? u : nb - 1;
+                                sl[uu] = __shfl(my, uc);
+                                t[uu] = 0.0;
+                                if (ok[uu]) {
+                                    const double *b = bval + (kb0 + uc) * (BK * BC) + gq;
+#pragma unroll
+                                    for (int r = 0; r < BK; ++r) t[uu] += ag[r] * b[r * BC];
+                                }
+                            }
+#pragma unroll
+                            for (int uu = 0; uu < UG; ++uu)
+                                if (ok[uu]) old[uu] = acc[sl[uu] * BB + e];
+#pragma unroll
+                            for (int uu = 0; uu < UG; ++uu)
+                                if (ok[uu]) acc[sl[uu] * BB + e] = old[uu] + t[uu];
                         }
                         continue;
                     }
