@@ -329,12 +329,16 @@ __global__ void __launch_bounds__(TB) k_split_fill(int64_t n, const int64_t *__r
 // block) x_in, or g when x_in is NULL (x_in = 0).  x_out may be x_in: a
 // block reads only its own rows of x_in.  PF: entries per lane held per row
 // (8 PF per row, chosen per level from its longest in-block row; TAIL: rows
-// may be longer, the rest is read in the chain).
-template <int PF, int D, bool TAIL>
+// may be longer, the rest is read in the chain).  REC: each in-block entry
+// comes as one 16-byte record (value, local column), one load instead of
+// two, so that a ring of several long rows stays within the hardware's count
+// of outstanding loads per wave (63).
+template <int PF, int D, bool TAIL, bool REC>
 __global__ void __launch_bounds__(64) k_hgs8(int64_t n, int B, const int64_t *__restrict__ pin,
                                              const uint8_t *__restrict__ lin, const double *__restrict__ vin,
-                                             const double *__restrict__ idl, const double *__restrict__ o,
-                                             const double *x_in, double *x_out, int forward) {
+                                             const int4 *__restrict__ rin, const double *__restrict__ idl,
+                                             const double *__restrict__ o, const double *x_in, double *x_out,
+                                             int forward) {
     extern __shared__ double xs[];   // [8][B + 1] x (spare last slot), then [8][B + 1] int row offsets
     const int lane = threadIdx.x, g = lane >> 3, l = lane & 7;
     const int64_t b0 = ((int64_t)blockIdx.x * 8 + g) * B;
@@ -368,8 +372,14 @@ __global__ void __launch_bounds__(64) k_hgs8(int64_t n, int B, const int64_t *__
             const int64_t k = lo + l + 8 * u;
             const bool in = k < q.hi;
             const int64_t kk = in ? k : 0;   // an absent entry reads entry 0, masked at use
-            q.c[u] = (int)lin[kk];
-            q.v[u] = vin[kk];
+            if (REC) {
+                const int4 rec = rin[kk];
+                q.c[u] = rec.z;
+                q.v[u] = __hiloint2double(rec.y, rec.x);
+            } else {
+                q.c[u] = (int)lin[kk];
+                q.v[u] = vin[kk];
+            }
             q.msk |= (in ? 1u : 0u) << u;
         }
         q.o = o[row];   // rows past the block update the spare slot only
@@ -429,6 +439,7 @@ struct CLv {
     DBuf<uint8_t> lin;
     DBuf<int32_t> cout;
     DBuf<double> vin, vout, idl;
+    DBuf<int4> rin;               // in-block entries as 16-byte records (levels with long rows)
     int max_in = 0;               // longest in-block row
     DBuf<int8_t> state;
     DBuf<double> g, x, s, o, t;   // work vectors
@@ -488,19 +499,19 @@ void sweep(camg_handle *h, CLv &L, const double *g, const double *x_in, double *
     const unsigned grid = (unsigned)((nblk + 7) / 8);
     auto go = [&](auto kern) {
         const size_t lds = (size_t)8 * (B + 1) * (sizeof(double) + sizeof(int));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, L.n, B, L.pin.p, L.lin.p, L.vin.p, L.idl.p, o, x_in,
-                           x_out, forward ? 1 : 0);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, s, L.n, B, L.pin.p, L.lin.p, L.vin.p, L.rin.p, L.idl.p, o,
+                           x_in, x_out, forward ? 1 : 0);
     };
-    // a level of fewer waves than compute units has no other waves to hide
-    // the loads behind: a deeper ring there (more registers, one wave per
-    // SIMD anyway).  The ring's depth is capped by the hardware's count of
-    // outstanding loads (63): a row of PF = 8 issues 18 loads per lane, so
-    // deeper than four rows gains nothing there.
-    const bool deep = grid < 256;
-    if (L.max_in <= 24) deep ? go(k_hgs8<3, 8, false>) : go(k_hgs8<3, 4, false>);
-    else if (L.max_in <= 64) go(k_hgs8<8, 4, false>);
-    else if (L.max_in <= 128) go(k_hgs8<16, 2, false>);
-    else go(k_hgs8<16, 2, true>);
+    // a level of fewer waves than SIMDs has no other waves to hide the loads
+    // behind: a deeper ring there (more registers, one wave per SIMD anyway).  The ring's depth is capped by the hardware's count of
+    // outstanding loads per wave (63): a row issues PF + 2 loads per lane
+    // with records (levels whose rows exceed 24 in-block entries), 2 PF + 2
+    // with the byte columns and values apart.
+    const bool deep = grid < 1024;
+    if (L.max_in <= 24) deep ? go(k_hgs8<3, 8, false, false>) : go(k_hgs8<3, 4, false, false>);
+    else if (L.max_in <= 64) deep ? go(k_hgs8<8, 6, false, true>) : go(k_hgs8<8, 4, false, true>);
+    else if (L.max_in <= 128) go(k_hgs8<16, 3, false, true>);
+    else go(k_hgs8<16, 3, true, true>);
     TE_CHECK_HIP(hipGetLastError());
 }
 
@@ -573,6 +584,13 @@ bool host_inverse(std::vector<double> M, int n, std::vector<double> &inv) {
     return true;
 }
 
+// the records of the in-block entries: {value low word, value high word, local column, 0}
+__global__ void __launch_bounds__(TB) k_split_rec(int64_t m, const uint8_t *__restrict__ lin,
+                                                  const double *__restrict__ vin, int4 *__restrict__ rin) {
+    for (int64_t a = blockIdx.x * (int64_t)TB + threadIdx.x; a < m; a += (int64_t)gridDim.x * TB)
+        rin[a] = make_int4(__double2loint(vin[a]), __double2hiint(vin[a]), (int)lin[a], 0);
+}
+
 void split_level(CLv &L, int B, hipStream_t s) {
     const int64_t n = L.n;
     DBuf<int32_t> ci(n), co(n);
@@ -598,6 +616,11 @@ void split_level(CLv &L, int B, hipStream_t s) {
     hipLaunchKernelGGL(k_split_fill, dim3(grid1(n)), dim3(TB), 0, s, n, L.A.ptr, L.A.col, L.A.val, B, L.dl1.p,
                        L.pin.p, L.lin.p, L.vin.p, L.pout.p, L.cout.p, L.vout.p, L.idl.p);
     TE_CHECK_HIP(hipGetLastError());
+    if (L.max_in > 24 && pi[n] > 0) {   // the sweeps of this level read records
+        L.rin.alloc(pi[n]);
+        hipLaunchKernelGGL(k_split_rec, dim3(grid1(pi[n])), dim3(TB), 0, s, pi[n], L.lin.p, L.vin.p, L.rin.p);
+        TE_CHECK_HIP(hipGetLastError());
+    }
 }
 
 void alloc_work(CLv &L) {
