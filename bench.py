@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import statistics
 import math
 import os
 import sys
@@ -318,7 +319,7 @@ def multi_mesh_form(te, torch, dev):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--grid", default="96,416,12,2", help="disc nr,ntheta,nz,degree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -522,6 +523,8 @@ def main():
                    "n_dof": m.n_dof, "nnzb": A.nnzb, "levels_dof": info["n_dof"],
                    "iterations": reps[-1].iters[0], "parallelism": "single GPU"},
         "time_solve_ms": round(ms_per_step, 2),
+        "time_solve_ms_median": round(statistics.median(r.time_ms for r in reps), 2),
+        "time_solve_ms_min": round(min(r.time_ms for r in reps), 2),
         "time_assembly_ms": round(t_asm * 1e3, 2),
         "time_setup_ms": round(t_setup * 1e3, 1),
         "time_autotune_ms": round(t_tune * 1e3, 1),
