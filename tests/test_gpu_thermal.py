@@ -141,3 +141,31 @@ def test_backward_euler_steps_with_kept_preconditioner_match_oracle():
         assert np.abs(Tn.cpu().numpy() - ro.T).max() <= 1e-8 * np.abs(ro.T).max()
         Tgd, To = Tn, ro.T
     assert pre.builds >= 1
+
+
+def test_full_size_disc_matches_stored_oracle_temperature():
+    """The steady solve of the P2 disc 96 x 416 x 12 (4,014,400 nodes, the
+    size the benchmark times, so every sweep variant of the hierarchy runs:
+    byte columns on the levels of short rows, 16-byte records on the levels of
+    long ones) against the stored float64 oracle temperature
+    (tests/golden/thermal_disc_p2_4m_oracle.txt, written by the oracle alone):
+    the same Newton step count, every correction's CG count within one, and a
+    relative error below 1e-9 (the Newton tolerance) over the 4096 stored nodes
+    and from the stored Gaussian projections."""
+    from paper_1804_10060_amd import heat
+    from tests import golden_c2
+    torch = torch_cuda()
+    m = mg.disc_mesh(*mg.DISC_P2_12M)
+    tm = mg.disc_thermal_materials(m)
+    rb = mg.disc_robin_faces(m)
+    ts = heat.ThermalSolver(dev(m.coords, torch.float64), dev(m.cells.astype(np.int32)), 2, heat.Tables.of(tm),
+                            dev(tm.cell_material.astype(np.int32)), dev(rb.faces.astype(np.int32)),
+                            dev(rb.h, torch.float64), dev(rb.T_bc, torch.float64))
+    T, rep = ts.newton(torch.full((m.n_nodes,), 400.0, dtype=torch.float64, device="cuda"))
+    g = golden_c2.load(golden_c2.THERMAL_PATH)
+    es, ep = golden_c2.errors(T.cpu().numpy(), g)
+    say(f"newton {rep.iters} (oracle {g['iters']}), CG {rep.lin_iters} (oracle {g['lin_iters']}); "
+        f"sampled {es:.2e}, projected {ep:.2e}")
+    assert rep.converged and rep.iters == g["iters"]
+    assert all(abs(a - b) <= 1 for a, b in zip(rep.lin_iters, g["lin_iters"]))
+    assert es <= 1e-9 and ep <= 1e-9
