@@ -320,7 +320,8 @@ typedef struct {
  * the same number of iterations, usually fewer than its own CG, and the stop
  * test waits for all of them; iters[j] is that common count, history is NaN,
  * the per-kernel profile is not kept, and the setup's solve workspace for
- * nrhs columns plus small buffers allocated per call are used.  Block CG
+ * nrhs columns is used, plus Gram and update buffers that the first block
+ * solve adds to the handle (kept for later calls).  Block CG
  * with MIXED is TE_EINVAL; a block P^T A P that is not positive definite is
  * TE_EINDEF.  Synchronises `stream`.
  * Returns TE_OK, TE_ENOTCONV (some column hit maxit), TE_EINDEF, TE_ENAN,
