@@ -795,7 +795,7 @@ int setup_impl(const te_bsr *A, const double *coords, const uint8_t *dir_mask, c
                 dev_mult(*cur, P, AP, s);
                 note("A P", l, AP.nr, AP.nnzb);
                 dev_transpose(P, R, s);
-                dev_mult(R, AP, Ac, s);
+                dev_mult(R, AP, Ac, s, true);
                 note("Galerkin", l, Ac.nr, Ac.nnzb);
                 AP.release();
                 coarsest = (double)Ac.nr * k > o.max_coarse_ratio * (double)ndof;

@@ -47,8 +47,11 @@ void dev_smoothed_p(const DBsr &A, const DBuf<int32_t> &agg, int64_t nagg, const
                     const DBuf<double> &d, double omega, DBsr &P, hipStream_t s);
 
 // C = A B with the blocks summed in the order of A's row, then B's row
-// (block shapes 1x1 * 1x1, 3x3 * 3x6, 6x3 * 3x6, 6x6 * 6x6).
-void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s);
+// (block shapes 1x1 * 1x1, 3x3 * 3x6, 6x3 * 3x6, 6x6 * 6x6).  symmetric: C is
+// known to be symmetric (a Galerkin product P^T (A P) of a symmetric A) and
+// has 6x6 blocks: the blocks on and above the diagonal are formed, those below
+// are their transposes (other shapes ignore the flag).
+void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s, bool symmetric = false);
 
 // T = A^T (blocks transposed; rows of each column in ascending order;
 // block shapes 1x1, 3x6, 6x6).

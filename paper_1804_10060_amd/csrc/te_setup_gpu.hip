@@ -103,11 +103,25 @@ __global__ void __launch_bounds__(64) k_sym(int64_t n, const int64_t *__restrict
     }
 }
 
+// first position in the sorted columns col[0, m) that is >= c
+__device__ __forceinline__ int lower_bound_col(const int32_t *__restrict__ col, int m, int64_t c) {
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)col[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Numeric pass.  For each block k_a of A's row, the lanes first look up the
 // output slots of the whole B row k_a points to (lane l: entry l), then walk
 // that B row in order, the slot passed by a lane shuffle.  LACC: the row's
 // output blocks are accumulated in dynamic LDS (mcap blocks), else in place.
-template <int BR, int BK, int BC, int TB, bool LACC>
+// UP (a product known to be symmetric): only the blocks on and above the
+// diagonal are formed (contributions to columns left of the row are
+// skipped); k_mirror_lower fills the others from them afterwards.
+template <int BR, int BK, int BC, int TB, bool LACC, bool UP = false>
 __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict__ aptr,
                                             const int32_t *__restrict__ acol, const double *__restrict__ aval,
                                             const int64_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
@@ -124,8 +138,12 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
     const bool on = lane < BB;
     const int p = on ? lane / BC : 0, q = on ? lane % BC : 0;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const int64_t c0 = cptr[i];
-        const int m = (int)(cptr[i + 1] - c0);
+        const int64_t cs = cptr[i];
+        const int mf = (int)(cptr[i + 1] - cs);
+        // UP: the row's slots are its columns >= i, a suffix of the sorted row
+        const int u0 = UP ? lower_bound_col(ccol + cs, mf, i) : 0;
+        const int64_t c0 = cs + u0;
+        const int m = mf - u0;
         if (2 * m > TB || (LACC && m > mcap)) {  // uniform over the block
             if (lane == 0) atomicOr(flag, 4);
             continue;
@@ -168,15 +186,19 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                     int my = -1;
                     if (lane < nb) {
                         const int32_t c = bcol[kb0 + lane];
-                        uint32_t h = hslot<TB>(c);
-                        int probe = 0;
-                        while (probe < TB && key[h] != c) {
-                            h = (h + 1) & (TB - 1);
-                            ++probe;
+                        if (UP && (int64_t)c < i) {
+                            my = -2;   // left of the diagonal: not formed
+                        } else {
+                            uint32_t h = hslot<TB>(c);
+                            int probe = 0;
+                            while (probe < TB && key[h] != c) {
+                                h = (h + 1) & (TB - 1);
+                                ++probe;
+                            }
+                            my = probe < TB ? slot[h] : -1;
                         }
-                        my = probe < TB ? slot[h] : -1;
                     }
-                    if (__any(lane < nb && my < 0)) {
+                    if (__any(lane < nb && my == -1)) {
                         if (lane == 0) atomicOr(flag, 8);
                         continue;
                     }
@@ -184,7 +206,7 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                         // scalar blocks: every lane updates its own entry's slot
                         // (the slots of one B row are distinct), each slot still
                         // receiving its updates in A-row order
-                        if (lane < nb) {
+                        if (lane < nb && my >= 0) {
                             const double t1 = __dmul_rn(aval[ka], bval[kb0 + lane]);
                             acc[my] = __dadd_rn(acc[my], t1);
                         }
@@ -201,16 +223,16 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                         const double *a2 = aval + ka * (BR * BK) + gp * BK;
 #pragma unroll
                         for (int r = 0; r < BK; ++r) ag[r] = gon ? a2[r] : 0.0;
-                        for (int u0 = 0; u0 < nb; u0 += G * UG) {
+                        for (int ub = 0; ub < nb; ub += G * UG) {
                             int sl[UG];
                             double t[UG], old[UG];
                             bool ok[UG];
 #pragma unroll
                             for (int uu = 0; uu < UG; ++uu) {
-                                const int u = u0 + uu * G + g;
-                                ok[uu] = gon && u < nb;
+                                const int u = ub + uu * G + g;
                                 const int uc = u < nb ? u : nb - 1;
                                 sl[uu] = __shfl(my, uc);
+                                ok[uu] = gon && u < nb && sl[uu] >= 0;
                                 t[uu] = 0.0;
                                 if (ok[uu]) {
                                     const double *b = bval + (kb0 + uc) * (BK * BC) + gq;
@@ -230,15 +252,15 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                     // the slots of one B row are distinct: batches of UB updates
                     // load their accumulators together, then store them
                     constexpr int UB = 8;
-                    for (int u0 = 0; u0 < nb; u0 += UB) {
+                    for (int ub = 0; ub < nb; ub += UB) {
                         int sl[UB];
                         double t[UB], old[UB];
 #pragma unroll
                         for (int uu = 0; uu < UB; ++uu) {
-                            const int u = u0 + uu < nb ? u0 + uu : nb - 1;
+                            const int u = ub + uu < nb ? ub + uu : nb - 1;
                             sl[uu] = __shfl(my, u);
                             t[uu] = 0.0;
-                            if (on && u0 + uu < nb) {
+                            if (on && ub + uu < nb && sl[uu] >= 0) {
                                 const double *b = bval + (kb0 + u) * (BK * BC) + q;
 #pragma unroll
                                 for (int r = 0; r < BK; ++r) t[uu] += ar[r] * b[r * BC];
@@ -247,10 +269,10 @@ __global__ void __launch_bounds__(64) k_num(int64_t n, const int64_t *__restrict
                         if (on) {
 #pragma unroll
                             for (int uu = 0; uu < UB; ++uu)
-                                if (u0 + uu < nb) old[uu] = acc[sl[uu] * BB + lane];
+                                if (ub + uu < nb && sl[uu] >= 0) old[uu] = acc[sl[uu] * BB + lane];
 #pragma unroll
                             for (int uu = 0; uu < UB; ++uu)
-                                if (u0 + uu < nb) acc[sl[uu] * BB + lane] = old[uu] + t[uu];
+                                if (ub + uu < nb && sl[uu] >= 0) acc[sl[uu] * BB + lane] = old[uu] + t[uu];
                         }
                     }
                 }
@@ -620,6 +642,48 @@ int64_t counts_to_ptr(const DBuf<int32_t> &cnt, int64_t n, DBuf<int64_t> &ptr, i
     return mx;
 }
 
+// The blocks left of the diagonal of a symmetric product, from their mirrors
+// formed by the numeric pass with UP: C_ij = C_ji^T, C_ji found by bisection
+// in row j (columns ascending).  One wave per row; flag bit 16 if a mirror is
+// missing (the pattern is not symmetric).
+template <int BS>
+__global__ void __launch_bounds__(64) k_mirror_lower(int64_t n, const int64_t *__restrict__ cptr,
+                                                     const int32_t *__restrict__ ccol, double *__restrict__ cval,
+                                                     int32_t *__restrict__ flag) {
+    constexpr int BB = BS * BS;
+    const int lane = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t c0 = cptr[i];
+        const int u0 = lower_bound_col(ccol + c0, (int)(cptr[i + 1] - c0), i);
+        for (int x = lane; x < u0; x += 64) {
+            const int64_t j = ccol[c0 + x];
+            const int64_t r0 = cptr[j];
+            const int mj = (int)(cptr[j + 1] - r0);
+            const int y = lower_bound_col(ccol + r0, mj, i);
+            if (y >= mj || ccol[r0 + y] != i) {
+                atomicOr(flag, 16);
+                continue;
+            }
+            const double *src = cval + (r0 + y) * BB;
+            double *dst = cval + (c0 + x) * BB;
+#pragma unroll
+            for (int a = 0; a < BS; ++a)
+#pragma unroll
+                for (int b = 0; b < BS; ++b) dst[a * BS + b] = src[b * BS + a];
+        }
+    }
+}
+
+// the longest row part on and right of the diagonal (atomic maximum)
+__global__ void k_upper_max(int64_t n, const int64_t *__restrict__ cptr, const int32_t *__restrict__ ccol,
+                            int32_t *__restrict__ mx) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c0 = cptr[i];
+        const int m = (int)(cptr[i + 1] - c0);
+        atomicMax(mx, m - lower_bound_col(ccol + c0, m, i));
+    }
+}
+
 template <bool AGG>
 void launch_sym(int tb, const DBsr &A, const int64_t *bptr, const int32_t *bcol, const int32_t *agg, int32_t *cnt,
                 const int64_t *cptr, int32_t *ccol, int32_t *flag, hipStream_t s) {
@@ -672,7 +736,7 @@ int64_t symbolic(const DBsr &A, const int64_t *bptr, const int32_t *bcol, const 
     return mx;
 }
 
-template <int BR, int BK, int BC>
+template <int BR, int BK, int BC, bool UP = false>
 void launch_num(int tb, int64_t mx, const DBsr &A, const DBsr &B, DBsr &C, int32_t *flag, hipStream_t s) {
     const dim3 g(wave_grid(A.nr)), b(64);
     // LDS accumulation while a row's blocks fit in 32 KB (several waves per CU)
@@ -682,10 +746,10 @@ void launch_num(int tb, int64_t mx, const DBsr &A, const DBsr &B, DBsr &C, int32
 #define TE_NUM(TBV)                                                                                                \
     case TBV:                                                                                                      \
         if (lacc)                                                                                                  \
-            hipLaunchKernelGGL((k_num<BR, BK, BC, TBV, true>), g, b, lds, s, A.nr, A.ptr, A.col, A.val, B.ptr,     \
+            hipLaunchKernelGGL((k_num<BR, BK, BC, TBV, true, UP>), g, b, lds, s, A.nr, A.ptr, A.col, A.val, B.ptr, \
                                B.col, B.val, C.ptr, C.col, C.val_own.p, flag, mcap);                               \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_num<BR, BK, BC, TBV, false>), g, b, 0, s, A.nr, A.ptr, A.col, A.val, B.ptr,      \
+            hipLaunchKernelGGL((k_num<BR, BK, BC, TBV, false, UP>), g, b, 0, s, A.nr, A.ptr, A.col, A.val, B.ptr,  \
                                B.col, B.val, C.ptr, C.col, C.val_own.p, flag, mcap);                               \
         break;
     switch (tb) {
@@ -757,14 +821,14 @@ void dev_smoothed_p(const DBsr &A, const DBuf<int32_t> &agg, int64_t nagg, const
     TE_REQUIRE(read_flag(flag, s) == 0, TE_EHIP, "prolongator pattern misses a column");
 }
 
-void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s) {
+void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s, bool symmetric) {
     TE_REQUIRE(A.bc == B.br && A.nc == B.nr, TE_EINVAL, "product shape mismatch");
     C.release();
     C.br = A.br;
     C.bc = B.bc;
     C.nr = A.nr;
     C.nc = B.nc;
-    const int64_t mx = symbolic<false>(A, B.ptr, B.col, nullptr, C.br == 3 ? 128 : 512, C, s);
+    int64_t mx = symbolic<false>(A, B.ptr, B.col, nullptr, C.br == 3 ? 128 : 512, C, s);
     C.val_own.alloc(std::max<int64_t>(C.nnzb * C.br * C.bc, 1));
     C.bind();
     const int tb = table_for(mx);
@@ -772,11 +836,27 @@ void dev_mult(const DBsr &A, const DBsr &B, DBsr &C, hipStream_t s) {
     DBuf<int32_t> flag(1);
     TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
     const int key = A.br * 100 + A.bc * 10 + B.bc;
+    // a symmetric product of 6x6 blocks: the upper blocks, then their mirrors
+    const bool up = symmetric && C.br == C.bc && C.nr == C.nc && (key == 636 || key == 666);
+    if (up) {
+        TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_upper_max, dim3(grid_for(C.nr)), dim3(256), 0, s, C.nr, C.ptr, C.col, flag.p);
+        TE_CHECK_HIP(hipGetLastError());
+        mx = std::max<int32_t>(read_flag(flag, s), 1);   // the longest upper row part
+        TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    }
     if (key == 111) launch_num<1, 1, 1>(tb, mx, A, B, C, flag.p, s);
     else if (key == 336) launch_num<3, 3, 6>(tb, mx, A, B, C, flag.p, s);
-    else if (key == 636) launch_num<6, 3, 6>(tb, mx, A, B, C, flag.p, s);
-    else if (key == 666) launch_num<6, 6, 6>(tb, mx, A, B, C, flag.p, s);
+    else if (key == 636) up ? launch_num<6, 3, 6, true>(tb, mx, A, B, C, flag.p, s)
+                            : launch_num<6, 3, 6>(tb, mx, A, B, C, flag.p, s);
+    else if (key == 666) up ? launch_num<6, 6, 6, true>(tb, mx, A, B, C, flag.p, s)
+                            : launch_num<6, 6, 6>(tb, mx, A, B, C, flag.p, s);
     else TE_REQUIRE(false, TE_EINVAL, "unsupported product block shapes %dx%d * %dx%d", A.br, A.bc, B.br, B.bc);
+    if (up) {
+        hipLaunchKernelGGL((k_mirror_lower<6>), dim3(wave_grid(C.nr)), dim3(64), 0, s, C.nr, C.ptr, C.col,
+                           C.val_own.p, flag.p);
+        TE_CHECK_HIP(hipGetLastError());
+    }
     TE_REQUIRE(read_flag(flag, s) == 0, TE_EHIP, "sparse product numeric pass found an inconsistent pattern");
 }
 
