@@ -62,6 +62,8 @@ __global__ void __launch_bounds__(64) k_sym(int64_t n, const int64_t *__restrict
     __shared__ int32_t tab[TB];
     __shared__ int32_t lst[TB];
     __shared__ int32_t num;
+    __shared__ int64_t s_b0[64];
+    __shared__ int32_t s_pre[64];
     const int lane = threadIdx.x;
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         for (int t = lane; t < TB; t += 64) tab[t] = -1;
@@ -75,10 +77,39 @@ __global__ void __launch_bounds__(64) k_sym(int64_t n, const int64_t *__restrict
                 if (c >= 0) ok = set_insert<TB>(tab, lst, &num, c) && ok;
             }
         } else {
-            for (int64_t ka = aptr[i]; ka < aptr[i + 1]; ++ka) {
-                const int32_t j = acol[ka];
-                for (int64_t kb = bptr[j] + lane; kb < bptr[j + 1]; kb += 64)
-                    ok = set_insert<TB>(tab, lst, &num, bcol[kb]) && ok;
+            // the B rows of (up to) 64 entries of A's row at a time, taken as
+            // one concatenated list: their starts and the prefix sums of their
+            // lengths in LDS, every lane one entry of the list
+            const int64_t a1 = aptr[i + 1];
+            for (int64_t kc = aptr[i]; kc < a1; kc += 64) {
+                const int na = (int)((a1 - kc) < 64 ? (a1 - kc) : 64);
+                int64_t b0 = 0;
+                int len = 0;
+                if (lane < na) {
+                    const int32_t j = acol[kc + lane];
+                    b0 = bptr[j];
+                    len = (int)(bptr[j + 1] - b0);
+                }
+                int pre = len;   // inclusive prefix sum over the lanes
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(pre, o, 64);
+                    if (lane >= o) pre += t;
+                }
+                const int total = __shfl(pre, 63, 64);
+                s_b0[lane] = b0;
+                s_pre[lane] = pre;
+                __syncthreads();
+                for (int f = lane; f < total; f += 64) {
+                    int lo = 0, hi = na - 1;   // the entry whose list part holds f
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_pre[mid] <= f) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    const int start = lo > 0 ? s_pre[lo - 1] : 0;
+                    ok = set_insert<TB>(tab, lst, &num, bcol[s_b0[lo] + (f - start)]) && ok;
+                }
+                __syncthreads();   // s_b0 / s_pre are refilled for the next entries
             }
         }
         if (!ok) atomicOr(flag, 1);
