@@ -116,14 +116,28 @@ __global__ void __launch_bounds__(TB) k_csr(int64_t n, const int64_t *__restrict
     }
 }
 
+// the largest value over a row group of RG lanes (exact in any order)
+__device__ __forceinline__ double max_rg(double v) {
+    v = fmax(v, dpp_mov<0xB1>(v));
+    v = fmax(v, dpp_mov<0x4E>(v));
+    if (RG >= 8) v = fmax(v, dpp_mov<0x141>(v));
+    if (RG == 16) v = fmax(v, dpp_mov<0x140>(v));
+    return v;
+}
+
+// Ruge-Stueben strength, RG lanes per row (coalesced entry loads)
 __global__ void __launch_bounds__(TB) k_strength(int64_t n, const int64_t *__restrict__ ptr,
                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
                                                  double theta, uint8_t *__restrict__ S) {
-    for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+    const int sub = threadIdx.x % RG;
+    const int64_t stride = (int64_t)gridDim.x * (TB / RG);
+    for (int64_t i = blockIdx.x * (int64_t)(TB / RG) + threadIdx.x / RG; i < n; i += stride) {
+        const int64_t lo = ptr[i], hi = ptr[i + 1];
         double m = -INFINITY;
-        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+        for (int64_t k = lo + sub; k < hi; k += RG)
             if (col[k] != i) m = fmax(m, -val[k]);
-        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) S[k] = (col[k] != i && m > 0.0 && -val[k] >= theta * m) ? 1 : 0;
+        m = max_rg(m);
+        for (int64_t k = lo + sub; k < hi; k += RG) S[k] = (col[k] != i && m > 0.0 && -val[k] >= theta * m) ? 1 : 0;
     }
 }
 
@@ -136,12 +150,14 @@ __global__ void __launch_bounds__(TB) k_infl(int64_t n, const int64_t *__restric
 }
 
 // Gs[k] = S[k] or S[mirror of k]; a missing mirror (pattern not symmetric)
-// raises flag
+// raises flag.  RG lanes per row.
 __global__ void __launch_bounds__(TB) k_sym(int64_t n, const int64_t *__restrict__ ptr,
                                             const int32_t *__restrict__ col, const uint8_t *__restrict__ S,
                                             uint8_t *__restrict__ Gs, int32_t *__restrict__ flag) {
-    for (int64_t i = blockIdx.x * (int64_t)TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB)
-        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+    const int sub = threadIdx.x % RG;
+    const int64_t stride = (int64_t)gridDim.x * (TB / RG);
+    for (int64_t i = blockIdx.x * (int64_t)(TB / RG) + threadIdx.x / RG; i < n; i += stride)
+        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += RG) {
             const int32_t j = col[k];
             int64_t lo = ptr[j], hi = ptr[j + 1];
             while (lo < hi) {
@@ -643,11 +659,11 @@ bool coarsen(camg_handle *h, size_t l, hipStream_t s) {
     DBuf<int32_t> cnt(n), flag(1), left(1);
     DBuf<uint64_t> key(n);
     L.state.alloc(n);
-    hipLaunchKernelGGL(k_strength, dim3(g), dim3(TB), 0, s, n, A.ptr, A.col, A.val, h->opt.theta, S.p);
+    hipLaunchKernelGGL(k_strength, dim3(grid_rows(n)), dim3(TB), 0, s, n, A.ptr, A.col, A.val, h->opt.theta, S.p);
     TE_CHECK_HIP(hipMemsetAsync(cnt.p, 0, n * sizeof(int32_t), s));
     TE_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(k_infl, dim3(g), dim3(TB), 0, s, n, A.ptr, A.col, S.p, cnt.p);
-    hipLaunchKernelGGL(k_sym, dim3(g), dim3(TB), 0, s, n, A.ptr, A.col, S.p, Gs.p, flag.p);
+    hipLaunchKernelGGL(k_sym, dim3(grid_rows(n)), dim3(TB), 0, s, n, A.ptr, A.col, S.p, Gs.p, flag.p);
     hipLaunchKernelGGL(k_keys, dim3(g), dim3(TB), 0, s, n, cnt.p, (uint64_t)(0xC1A5 + l), key.p, L.state.p);
     TE_CHECK_HIP(hipGetLastError());
     TE_REQUIRE(read_i32(flag, s) == 0, TE_EINVAL, "classical AMG needs a symmetric pattern (level %d)", (int)l);
