@@ -451,25 +451,52 @@ __global__ void __launch_bounds__(64) k_p_wave(int64_t n, const int64_t *__restr
             return (lo < m && s_pc[lo] == a) ? lo : -1;
         };
         const double f = on ? omega / d[i * BS + p] : 0.0;
-        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
-            const int32_t j = col[k];
-            const int32_t a = agg[j];
-            if (a < 0) continue;
-            const int at = find(a);
-            if (at < 0) {
-                if (lane == 0) atomicOr(flag, 8);
-                continue;
-            }
-            if (on) {
-                const double *av = val + k * BS * BS + p * BS;
-                const double *qv = Q + (int64_t)j * BS * K + c;
-                double o = s_acc[at * BB + lane];
-                for (int r = 0; r < BS; ++r) {
-                    const double ar = av[r];
-                    if (ar == 0.0) continue;
-                    o -= f * ar * qv[r * K];
+        // the row's entries 64 at a time: every lane looks up one entry's
+        // column, aggregate and output slot at once; then the entries are
+        // applied in order, the block values and Q rows of U entries loaded
+        // before any of them is added (the updates of one slot keep their order)
+        const int64_t k1 = ptr[i + 1];
+        for (int64_t kc = ptr[i]; kc < k1; kc += 64) {
+            const int cnt = (int)((k1 - kc) < 64 ? (k1 - kc) : 64);
+            int jl = 0, atl = -1;
+            if (lane < cnt) {
+                jl = col[kc + lane];
+                const int32_t a = agg[jl];
+                if (a >= 0) {
+                    atl = find(a);
+                    if (atl < 0) {
+                        atomicOr(flag, 8);
+                        atl = -2;
+                    }
                 }
-                s_acc[at * BB + lane] = o;
+            }
+            constexpr int U = 4;
+            for (int u0 = 0; u0 < cnt; u0 += U) {
+                double ar[U][BS], qr[U][BS];
+                int at[U];
+#pragma unroll
+                for (int t = 0; t < U; ++t) {
+                    const int u = u0 + t < cnt ? u0 + t : cnt - 1;
+                    at[t] = u0 + t < cnt ? __shfl(atl, u) : -1;
+                    const int32_t j = __shfl(jl, u);
+                    const double *av = val + (kc + u) * BS * BS + p * BS;
+                    const double *qv = Q + (int64_t)j * BS * K + c;
+#pragma unroll
+                    for (int r = 0; r < BS; ++r) {
+                        ar[t][r] = on ? av[r] : 0.0;
+                        qr[t][r] = on ? qv[r * K] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < U; ++t) {
+                    if (at[t] < 0 || !on) continue;
+                    double o = s_acc[at[t] * BB + lane];
+                    for (int r = 0; r < BS; ++r) {
+                        if (ar[t][r] == 0.0) continue;
+                        o -= f * ar[t][r] * qr[t][r];
+                    }
+                    s_acc[at[t] * BB + lane] = o;
+                }
             }
         }
         const int32_t ai = agg[i];
