@@ -182,9 +182,25 @@ constexpr int roww_batch() {
     return BC <= 3 ? 2 : 1;
 }
 
-template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT = false>
+// Lane `src`'s value of v (cross-lane permute through the LDS crossbar; no
+// memory access, no barrier).
+__device__ __forceinline__ double lane_bperm(int src, double v) {
+    const int a = src << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_bperm(int src, float v) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+// XB (square blocks only): a slot's BC lanes load one x entry each of the
+// block column and pass them round by lane_bperm, instead of every lane
+// loading all BC (the same values, so the same result bit for bit).
+template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT = false, bool XB = false>
 __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__restrict__ x, const Epi &epi, int64_t row,
                                           int lane, double &red, AT *__restrict__ wbuf) {
+    static_assert(!XB || BR == BC, "x exchange needs square blocks");
     constexpr int NB = WAVE / BR, U = roww_batch<BC>();
     const int slot = lane / BR, i = lane % BR;
     AT acc = AT(0);
@@ -212,9 +228,14 @@ __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__rest
                 const int64_t ku = k + u * NB;
                 const VT *v = A.val + (ku < hi ? ku : k) * (BR * BC) + i * BC;
 #pragma unroll
-                for (int j = 0; j < BC; ++j) {
-                    vv[u][j] = ld_val<NT>(&v[j]);
-                    xx[u][j] = x[cc[u] * BC + j];
+                for (int j = 0; j < BC; ++j) vv[u][j] = ld_val<NT>(&v[j]);
+                if constexpr (XB) {
+                    const XT xi = x[cc[u] * BC + i];
+#pragma unroll
+                    for (int j = 0; j < BC; ++j) xx[u][j] = lane_bperm(slot * BR + j, xi);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < BC; ++j) xx[u][j] = x[cc[u] * BC + j];
                 }
             }
 #pragma unroll
@@ -253,9 +274,14 @@ __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__rest
                     for (int u = 0; u < U; ++u) {
                         const VT *v = A.val + li[u] * (BR * BC) + i;
 #pragma unroll
-                        for (int j = 0; j < BC; ++j) {
-                            vv[u][j] = v[j * BC];
-                            xx[u][j] = x[lc[u] * BC + j];
+                        for (int j = 0; j < BC; ++j) vv[u][j] = v[j * BC];
+                        if constexpr (XB) {
+                            const XT xi = x[lc[u] * BC + i];
+#pragma unroll
+                            for (int j = 0; j < BC; ++j) xx[u][j] = lane_bperm(slot * BR + j, xi);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < BC; ++j) xx[u][j] = x[lc[u] * BC + j];
                         }
                     }
 #pragma unroll

@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(512) k_sellm(SellView<VT> A, const XT *__restr
 
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT>
 __global__ void __launch_bounds__(512) k_roww(RowView<VT> A, const XT *__restrict__ x, Epi epi,
-                                              double *__restrict__ partials, int spw, int remap) {
+                                              double *__restrict__ partials, int spw, int remap, int xb) {
     __shared__ double rlds[16];
     __shared__ AT wb[512];
     const int64_t nb = gridDim.x;
@@ -250,8 +250,19 @@ __global__ void __launch_bounds__(512) k_roww(RowView<VT> A, const XT *__restric
     const int64_t w0 = (lb * (blockDim.x / WAVE) + threadIdx.x / WAVE) * spw;
     AT *wbuf = wb + (threadIdx.x / WAVE) * WAVE;
     double red = 0.0;
-    for (int u = 0; u < spw; ++u)
-        if (w0 + u < A.nrows) roww_body<BR, BC, VT, XT, AT, Epi, NT>(A, x, epi, w0 + u, lane, red, wbuf);
+    if constexpr (BR == BC) {
+        if (xb) {
+            for (int u = 0; u < spw; ++u)
+                if (w0 + u < A.nrows)
+                    roww_body<BR, BC, VT, XT, AT, Epi, NT, true>(A, x, epi, w0 + u, lane, red, wbuf);
+        } else {
+            for (int u = 0; u < spw; ++u)
+                if (w0 + u < A.nrows) roww_body<BR, BC, VT, XT, AT, Epi, NT>(A, x, epi, w0 + u, lane, red, wbuf);
+        }
+    } else {
+        for (int u = 0; u < spw; ++u)
+            if (w0 + u < A.nrows) roww_body<BR, BC, VT, XT, AT, Epi, NT>(A, x, epi, w0 + u, lane, red, wbuf);
+    }
     if (Epi::kReduce) {
         double t = block_sum(red, rlds);
         if (threadIdx.x == 0) partials[lb] = t;
@@ -407,10 +418,10 @@ static void launch_t(const Sell &A, const VT *val, const XT *x, const Epi &epi, 
         if (A.format == FMT_ROWWAVE) {
             if (t.nt)
                 hipLaunchKernelGGL((k_roww<BR, BC, VT, XT, AT, Epi, true>), dim3((unsigned)g), blk, 0, s,
-                                   rview(A, val), x, epi, partials, t.spw, t.remap);
+                                   rview(A, val), x, epi, partials, t.spw, t.remap, t.xb);
             else
                 hipLaunchKernelGGL((k_roww<BR, BC, VT, XT, AT, Epi, false>), dim3((unsigned)g), blk, 0, s,
-                                   rview(A, val), x, epi, partials, t.spw, t.remap);
+                                   rview(A, val), x, epi, partials, t.spw, t.remap, t.xb);
         } else {
             if (t.nt)
                 hipLaunchKernelGGL((k_sell1<BR, BC, VT, XT, AT, Epi, true>), dim3((unsigned)g), blk, 0, s,

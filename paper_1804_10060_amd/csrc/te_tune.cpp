@@ -3,7 +3,8 @@
 // launches after one warm-up, HIP events on the solve stream), separately
 // for the float64 and float32 copies: for one right-hand side the waves per
 // workgroup, slices (rows) per wave, XCD block order and non-temporal value
-// loads; for the hierarchy's max_nrhs right-hand sides (when above one) the
+// loads, and for square-block operators stored one wave per row whether a
+// slot's lanes share the x entries by lane permutes; for the hierarchy's max_nrhs right-hand sides (when above one) the
 // block rows per workgroup of the multi-RHS products.  Choices can be stored
 // in and re-read from a small JSON file keyed by the operator's shape class
 // (and the number of right-hand sides), so a second run on a similar problem
@@ -41,7 +42,7 @@ std::map<std::string, Tune> read_cache(const char *path) {
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
-        // lines of the form:  "key": [wpb, spw, remap, nt, mwpb, mtile, msplit]  (the last three optional)
+        // lines of the form:  "key": [wpb, spw, remap, nt, mwpb, mtile, msplit, xb]  (the last four optional)
         auto a = line.find('"'), b = line.find('"', a + 1), l = line.find('['), r = line.find(']');
         if (a == std::string::npos || b == std::string::npos || l == std::string::npos || r == std::string::npos)
             continue;
@@ -54,6 +55,8 @@ std::map<std::string, Tune> read_cache(const char *path) {
             if (is >> m && (m == 4 || m == 8 || m == 16)) t.mwpb = m;   // checked against the format at launch
             if (is >> mt && (mt == 0 || mt == 16 || mt == 32 || mt == 64)) t.mtile = mt;
             if (is >> sp) t.msplit = sp ? 1 : 0;
+            int xb = 0;
+            if (is >> xb) t.xb = xb ? 1 : 0;   // used by square-block row-wave operators only
             c[line.substr(a + 1, b - a - 1)] = t;
         }
     }
@@ -69,7 +72,7 @@ void write_cache(const char *path, const std::map<std::string, Tune> &c) {
     for (const auto &kv : c) {
         f << "  \"" << kv.first << "\": [" << kv.second.wpb << ", " << kv.second.spw << ", " << kv.second.remap
           << ", " << kv.second.nt << ", " << kv.second.mwpb << ", " << kv.second.mtile << ", " << kv.second.msplit
-          << "]"
+          << ", " << kv.second.xb << "]"
           << (++i < c.size() ? "," : "") << "\n";
     }
     f << "}\n";
@@ -151,23 +154,27 @@ void tune_one(Sell &A, Tune &slot, const char *dtype, const T *x, T *y, std::map
     }
     Tune best;
     float best_t = INFINITY, def_t = 0.f;
-    for (int wpb : {1, 2, 4, 8})
-        for (int spw : {1, 2, 4})
-            for (int remap : {0, 1})
-                for (int nt : {0, 1}) {
-                    Tune c{wpb, spw, remap, nt};
-                    const float t = time_op<T>(A, slot, c, x, y, s, e0, e1);
-                    if (wpb == 4 && spw == 1 && remap == 1 && nt == 0) def_t = t;
-                    if (t < best_t) {
-                        best_t = t;
-                        best = c;
+    // the shared x entries exist for one wave per row with square blocks
+    const int nxb = A.format == FMT_ROWWAVE && A.br == A.bc ? 2 : 1;
+    for (int xb = 0; xb < nxb; ++xb)
+        for (int wpb : {1, 2, 4, 8})
+            for (int spw : {1, 2, 4})
+                for (int remap : {0, 1})
+                    for (int nt : {0, 1}) {
+                        Tune c{wpb, spw, remap, nt};
+                        c.xb = xb;
+                        const float t = time_op<T>(A, slot, c, x, y, s, e0, e1);
+                        if (wpb == 4 && spw == 1 && remap == 1 && nt == 0 && xb == 0) def_t = t;
+                        if (t < best_t) {
+                            best_t = t;
+                            best = c;
+                        }
                     }
-                }
     slot = best;
     cache[key] = best;
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s best [%d,%d,%d,%d] %.4f ms (default %.4f ms)\n", key.c_str(), best.wpb,
-                  best.spw, best.remap, best.nt, best_t, def_t);
+    std::snprintf(buf, sizeof buf, "%s best [%d,%d,%d,%d%s] %.4f ms (default %.4f ms)\n", key.c_str(), best.wpb,
+                  best.spw, best.remap, best.nt, best.xb ? ",shared-x" : "", best_t, def_t);
     report += buf;
     if (nrhs > 1) tune_multi<T>(A, slot, mkey, x, y, nrhs, cache, s, e0, e1, report);
 }

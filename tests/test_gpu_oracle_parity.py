@@ -102,7 +102,8 @@ def test_multi_rhs_columns_match_oracle_pcg_multi():
 def test_every_tuner_candidate_matches_oracle_operators():
     """The autotuner picks among 48 launch configurations per operator
     (waves per workgroup 1/2/4/8, slices or rows per wave 1/2/4, XCD order,
-    non-temporal loads).  Each one, imposed on every operator through the
+    non-temporal loads), for the square-block row-wave operators each also
+    with the x entries shared by lane permutes.  Each one, imposed on every operator through the
     tuning cache, computes A_l x, P_l x and R_l x equal to the oracle's
     operators (float64 within the summation-order bound, float32 within its
     rounding)."""
@@ -130,21 +131,23 @@ def test_every_tuner_candidate_matches_oracle_operators():
             keys = list(json.load(fh))
         assert keys
         n_cand = 0
-        for wpb in (1, 2, 4, 8):
-            for spw in (1, 2, 4):
-                for remap in (0, 1):
-                    for nt in (0, 1):
-                        with open(path, "w") as fh:
-                            json.dump({k: [wpb, spw, remap, nt] for k in keys}, fh)
-                        h.autotune(path, use_cache=True)
-                        for l, op, x, y_ref, scale in ops:
-                            for prec, tol in ((te.TE_PREC_FP64, 1e-13), (te.TE_PREC_MIXED, 1e-5)):
-                                y = h.apply(l, op, dev(x, torch.float64), precision=prec).cpu().numpy()
-                                bad = np.abs(y - y_ref) > tol * scale + 1e-300
-                                assert not bad.any(), (wpb, spw, remap, nt, l, op, prec)
-                        n_cand += 1
+        # xb: the square-block row-wave operators' shared x entries (ignored elsewhere)
+        for xb in (0, 1):
+            for wpb in (1, 2, 4, 8):
+                for spw in (1, 2, 4):
+                    for remap in (0, 1):
+                        for nt in (0, 1):
+                            with open(path, "w") as fh:
+                                json.dump({k: [wpb, spw, remap, nt, 4, 0, 0, xb] for k in keys}, fh)
+                            h.autotune(path, use_cache=True)
+                            for l, op, x, y_ref, scale in ops:
+                                for prec, tol in ((te.TE_PREC_FP64, 1e-13), (te.TE_PREC_MIXED, 1e-5)):
+                                    y = h.apply(l, op, dev(x, torch.float64), precision=prec).cpu().numpy()
+                                    bad = np.abs(y - y_ref) > tol * scale + 1e-300
+                                    assert not bad.any(), (xb, wpb, spw, remap, nt, l, op, prec)
+                            n_cand += 1
     say(f"{n_cand} candidate configurations x {len(ops)} operators checked")
-    assert n_cand == 48
+    assert n_cand == 96
 
 
 def test_every_multi_rhs_candidate_matches_oracle_pcg_multi():

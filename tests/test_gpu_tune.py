@@ -1,6 +1,8 @@
 """Autotuner: every candidate launch configuration computes the same rows,
 so tuned operators reproduce the untuned products bit for bit, the tuned
 solve matches, and the choices survive a round trip through the cache file."""
+import json
+
 import numpy as np
 import pytest
 
@@ -39,3 +41,44 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     u2, r2 = h2.solve(b)
     assert r2.iters[0] == r1.iters[0]
     assert float(((u2 - u1).norm() / u1.norm()).cpu()) == 0.0
+
+
+def test_shared_x_entries_equal_own_loads(tmp_path):
+    """The row-wave products of the 6x6-block coarse operators (symmetric
+    float64 storage and the full float32 copies) with the x entries of a
+    block column loaded once per slot and passed round by lane permutes use
+    the same values in the same order as with every lane loading them: each
+    level operator's product, for several launch shapes and both precisions,
+    and the float64 and mixed solves agree bit for bit."""
+    import paper_1804_10060_amd as te
+    torch = torch_cuda()
+    prob = mg.disc_problem(10, 40, 3, 2, seed=5)
+    A, b, d = gpu_assemble(prob)
+    h = te.AMG(A, d["coords"], d["mask"], coarse_max=400)
+    info = h.info()
+    assert h.opts.coarse_sym == 1 and info["n_levels"] >= 3
+    rng = np.random.default_rng(1)
+    xs = [dev(rng.normal(size=n), torch.float64) for n in info["n_dof"]]
+    path = str(tmp_path / "tune.json")
+    h.autotune(path, use_cache=False)
+    with open(path) as fh:
+        keys = list(json.load(fh))
+
+    def run(shape, xb):
+        with open(path, "w") as fh:
+            json.dump({k: [*shape, 4, 0, 0, xb] for k in keys}, fh)
+        h.autotune(path, use_cache=True)
+        nl = info["n_levels"]
+        ys = [h.apply(l, te.TE_OP_A, xs[l]).cpu().numpy() for l in range(nl)]
+        ys += [h.apply(l, te.TE_OP_A, xs[l], precision=te.TE_PREC_MIXED).cpu().numpy() for l in range(nl - 1)]
+        u, rep = h.solve(b)
+        um, repm = h.solve(b, precision="mixed")
+        return ys, (u, um), (rep.iters[0], repm.iters[0])
+
+    for shape in ([4, 1, 1, 0], [8, 2, 0, 1], [1, 4, 1, 0]):
+        ya, ua, ia = run(shape, 0)
+        yb, ub, ib = run(shape, 1)
+        for q, (a, c) in enumerate(zip(ya, yb)):
+            assert np.array_equal(a, c), (shape, q)
+        assert ia == ib and all(torch.equal(p, q) for p, q in zip(ua, ub)), shape
+        say(f"launch shape {shape}: level products and both solves ({ia} iterations) equal")
