@@ -363,8 +363,8 @@ int amg_energy_scale(amg_handle *h, const double *b, double *u0, double *gamma, 
 /* Autotuner: for every level operator (A_l, P_l, R_l; float64 and, if built,
  * float32) times the launch configurations (waves per workgroup 1/2/4/8,
  * slices or rows per wave 1/2/4, XCD-contiguous block order on/off,
- * non-temporal matrix loads on/off; for the square-block operators stored
- * one wave per row, each also with the x entries of a block column loaded
+ * non-temporal matrix loads on/off; for the operators stored one wave per
+ * row (6-row blocks), each also with the x entries of a block column loaded
  * once per block slot and shared by lane permutes, the same values in the
  * same order; median of 5 launches) and keeps the fastest in the handle.  cache_path (host string, may be NULL): if
  * use_cache, choices already stored there for the same operator class

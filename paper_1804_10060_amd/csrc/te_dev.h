@@ -194,13 +194,13 @@ __device__ __forceinline__ float lane_bperm(int src, float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
 }
 
-// XB (square blocks only): a slot's BC lanes load one x entry each of the
+// XB (BC <= BR): the first BC lanes of a slot load one x entry each of the
 // block column and pass them round by lane_bperm, instead of every lane
 // loading all BC (the same values, so the same result bit for bit).
 template <int BR, int BC, typename VT, typename XT, typename AT, class Epi, bool NT = false, bool XB = false>
 __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__restrict__ x, const Epi &epi, int64_t row,
                                           int lane, double &red, AT *__restrict__ wbuf) {
-    static_assert(!XB || BR == BC, "x exchange needs square blocks");
+    static_assert(!XB || BC <= BR, "x exchange needs BC <= BR");
     constexpr int NB = WAVE / BR, U = roww_batch<BC>();
     const int slot = lane / BR, i = lane % BR;
     AT acc = AT(0);
@@ -230,7 +230,7 @@ __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__rest
 #pragma unroll
                 for (int j = 0; j < BC; ++j) vv[u][j] = ld_val<NT>(&v[j]);
                 if constexpr (XB) {
-                    const XT xi = x[cc[u] * BC + i];
+                    const XT xi = i < BC ? x[cc[u] * BC + i] : XT(0);
 #pragma unroll
                     for (int j = 0; j < BC; ++j) xx[u][j] = lane_bperm(slot * BR + j, xi);
                 } else {
@@ -276,7 +276,7 @@ __device__ __forceinline__ void roww_body(const RowView<VT> &A, const XT *__rest
 #pragma unroll
                         for (int j = 0; j < BC; ++j) vv[u][j] = v[j * BC];
                         if constexpr (XB) {
-                            const XT xi = x[lc[u] * BC + i];
+                            const XT xi = i < BC ? x[lc[u] * BC + i] : XT(0);
 #pragma unroll
                             for (int j = 0; j < BC; ++j) xx[u][j] = lane_bperm(slot * BR + j, xi);
                         } else {

@@ -155,7 +155,7 @@ struct Tune {
     int mwpb = 4;    // several right-hand sides: waves per workgroup
     int mtile = 0;   // several right-hand sides on the SELL layout: columns per pass (0: row per wave)
     int msplit = 0;  // ... and the column tiles on different XCDs instead of passes
-    int xb = 0;      // one wave per row, square blocks: a slot's lanes share the x entries by lane permutes
+    int xb = 0;      // one wave per row: a slot's lanes share the block column's x entries by lane permutes
 };
 
 struct Sell {

@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(512) k_roww(RowView<VT> A, const XT *__restric
     const int64_t w0 = (lb * (blockDim.x / WAVE) + threadIdx.x / WAVE) * spw;
     AT *wbuf = wb + (threadIdx.x / WAVE) * WAVE;
     double red = 0.0;
-    if constexpr (BR == BC) {
+    if constexpr (BC <= BR) {
         if (xb) {
             for (int u = 0; u < spw; ++u)
                 if (w0 + u < A.nrows)

@@ -3,8 +3,8 @@
 // launches after one warm-up, HIP events on the solve stream), separately
 // for the float64 and float32 copies: for one right-hand side the waves per
 // workgroup, slices (rows) per wave, XCD block order and non-temporal value
-// loads, and for square-block operators stored one wave per row whether a
-// slot's lanes share the x entries by lane permutes; for the hierarchy's max_nrhs right-hand sides (when above one) the
+// loads, and for the operators stored one wave per row whether a slot's
+// lanes share the x entries by lane permutes; for the hierarchy's max_nrhs right-hand sides (when above one) the
 // block rows per workgroup of the multi-RHS products.  Choices can be stored
 // in and re-read from a small JSON file keyed by the operator's shape class
 // (and the number of right-hand sides), so a second run on a similar problem
@@ -56,7 +56,7 @@ std::map<std::string, Tune> read_cache(const char *path) {
             if (is >> mt && (mt == 0 || mt == 16 || mt == 32 || mt == 64)) t.mtile = mt;
             if (is >> sp) t.msplit = sp ? 1 : 0;
             int xb = 0;
-            if (is >> xb) t.xb = xb ? 1 : 0;   // used by square-block row-wave operators only
+            if (is >> xb) t.xb = xb ? 1 : 0;   // used by the row-wave operators only
             c[line.substr(a + 1, b - a - 1)] = t;
         }
     }
@@ -154,8 +154,8 @@ void tune_one(Sell &A, Tune &slot, const char *dtype, const T *x, T *y, std::map
     }
     Tune best;
     float best_t = INFINITY, def_t = 0.f;
-    // the shared x entries exist for one wave per row with square blocks
-    const int nxb = A.format == FMT_ROWWAVE && A.br == A.bc ? 2 : 1;
+    // the shared x entries exist for one wave per row (blocks no wider than tall)
+    const int nxb = A.format == FMT_ROWWAVE && A.bc <= A.br ? 2 : 1;
     for (int xb = 0; xb < nxb; ++xb)
         for (int wpb : {1, 2, 4, 8})
             for (int spw : {1, 2, 4})

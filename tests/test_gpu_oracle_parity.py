@@ -102,7 +102,7 @@ def test_multi_rhs_columns_match_oracle_pcg_multi():
 def test_every_tuner_candidate_matches_oracle_operators():
     """The autotuner picks among 48 launch configurations per operator
     (waves per workgroup 1/2/4/8, slices or rows per wave 1/2/4, XCD order,
-    non-temporal loads), for the square-block row-wave operators each also
+    non-temporal loads), for the row-wave operators (6-row blocks) each also
     with the x entries shared by lane permutes.  Each one, imposed on every operator through the
     tuning cache, computes A_l x, P_l x and R_l x equal to the oracle's
     operators (float64 within the summation-order bound, float32 within its
@@ -131,7 +131,7 @@ def test_every_tuner_candidate_matches_oracle_operators():
             keys = list(json.load(fh))
         assert keys
         n_cand = 0
-        # xb: the square-block row-wave operators' shared x entries (ignored elsewhere)
+        # xb: the row-wave operators' shared x entries (ignored by the SELL ones)
         for xb in (0, 1):
             for wpb in (1, 2, 4, 8):
                 for spw in (1, 2, 4):

@@ -44,12 +44,13 @@ def test_autotune_keeps_results_and_caches(tmp_path):
 
 
 def test_shared_x_entries_equal_own_loads(tmp_path):
-    """The row-wave products of the 6x6-block coarse operators (symmetric
-    float64 storage and the full float32 copies) with the x entries of a
-    block column loaded once per slot and passed round by lane permutes use
-    the same values in the same order as with every lane loading them: each
-    level operator's product, for several launch shapes and both precisions,
-    and the float64 and mixed solves agree bit for bit."""
+    """The row-wave products (the 6x6-block coarse operators in symmetric
+    float64 storage and full float32 copies, and the 6x3-block restrictions)
+    with the x entries of a block column loaded once per slot and passed
+    round by lane permutes use the same values in the same order as with
+    every lane loading them: each level operator's and restriction's
+    product, for several launch shapes and both precisions, and the float64
+    and mixed solves agree bit for bit."""
     import paper_1804_10060_amd as te
     torch = torch_cuda()
     prob = mg.disc_problem(10, 40, 3, 2, seed=5)
@@ -71,6 +72,8 @@ def test_shared_x_entries_equal_own_loads(tmp_path):
         nl = info["n_levels"]
         ys = [h.apply(l, te.TE_OP_A, xs[l]).cpu().numpy() for l in range(nl)]
         ys += [h.apply(l, te.TE_OP_A, xs[l], precision=te.TE_PREC_MIXED).cpu().numpy() for l in range(nl - 1)]
+        ys += [h.apply(l, te.TE_OP_R, xs[l], precision=p).cpu().numpy()
+               for l in range(nl - 1) for p in (te.TE_PREC_FP64, te.TE_PREC_MIXED)]
         u, rep = h.solve(b)
         um, repm = h.solve(b, precision="mixed")
         return ys, (u, um), (rep.iters[0], repm.iters[0])
