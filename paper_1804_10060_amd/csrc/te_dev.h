@@ -49,10 +49,12 @@ __device__ __forceinline__ T ld_val(const T *p) {
     else return *p;
 }
 
-// Stores of the single-RHS epilogue outputs: non-temporal.  Measured on the
-// 12M-DOF disc against plain stores: A p 1.652 -> 1.633 ms, pre-smoothing
-// 1.738 -> 1.719, residual 1.599 -> 1.569, post-smoothing step 1.659 -> 1.637
-// (the Chebyshev start keeps plain stores, see EpiChebInit).
+// Stores of the epilogue outputs: non-temporal.  Measured on the 12M-DOF disc
+// against plain stores: A p 1.652 -> 1.633 ms, pre-smoothing 1.738 -> 1.719,
+// residual 1.599 -> 1.569, post-smoothing step 1.659 -> 1.637 (the
+// single-RHS Chebyshev start keeps plain stores, see EpiChebInit); on the
+// 64-column products of the 2M-DOF disc 1-3 % faster (Chebyshev start
+// included).  The multi-RHS outputs of y = A x (EpiSet) stay plain.
 template <typename T>
 __device__ __forceinline__ void st_out(T *p, T v) {
     __builtin_nontemporal_store(v, p);
@@ -379,7 +381,7 @@ struct EpiAdd {  // y += A x
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             int64_t q = (r * BR + i) * m + j;
-            y[q] = T(AT(y[q]) + acc[i]);
+            st_out(&y[q], T(AT(y[q]) + acc[i]));
         }
     }
 };
@@ -419,7 +421,7 @@ struct EpiResid {  // y = g - A x  (optionally red += y^2)
         for (int i = 0; i < BR; ++i) {
             int64_t q = (r * BR + i) * m + j;
             AT v = AT(g[q]) - acc[i];
-            y[q] = T(v);
+            st_out(&y[q], T(v));
             if (NORM) red += double(v) * double(v);
         }
     }
@@ -457,7 +459,7 @@ struct EpiDot {  // q = A p, red += p.q   (float64 outer CG)
 #pragma unroll
         for (int i = 0; i < BR; ++i) {
             int64_t k = (r * BR + i) * m + j;
-            q[k] = acc[i];
+            st_out(&q[k], double(acc[i]));
             red += p[k] * double(acc[i]);
         }
     }
@@ -508,8 +510,8 @@ struct EpiChebInit {
         for (int i = 0; i < BR; ++i) {
             int64_t q = (row * BR + i) * m + j;
             T rv = T(AT(g[q]) - acc[i]);
-            r[q] = rv;
-            d[q] = dinv[row * BR + i] * rv * inv_theta;
+            st_out(&r[q], rv);
+            st_out(&d[q], T(dinv[row * BR + i] * rv * inv_theta));
         }
     }
 };
@@ -577,11 +579,11 @@ struct EpiChebStep {
             T dn = c1 * dv + c2 * (dinv[row * BR + i] * rn);
             T xv = XZERO ? T(0) : x[q];
             if (LAST) {
-                x[q] = xv + dv + dn;
+                st_out(&x[q], T(xv + dv + dn));
             } else {
-                rout[q] = rn;
-                dout[q] = dn;
-                x[q] = xv + dv;
+                st_out(&rout[q], rn);
+                st_out(&dout[q], dn);
+                st_out(&x[q], T(xv + dv));
             }
         }
     }
